@@ -1,0 +1,196 @@
+/*
+ * tsim.h -- C ABI of the MI355X (gfx950) microscopic traffic stepper.
+ *
+ * The library implements the data-parallel per-timestep vehicle update of
+ * arXiv 2406.10661 ("A GPU-accelerated Large-scale Simulator for
+ * Transportation System Optimization Benchmarking"):
+ *   - two-phase step with a read-only snapshot and a private next state
+ *     (Section 3.1, "Two-phase Parallel Process for Read/Write Separation";
+ *     Appendix B.2 execution process);
+ *   - per-lane ordered vehicle index with own-lane and side-lane neighbours
+ *     (Section 3.1, "Linked-list based Vehicle Sensing Indexes");
+ *   - IDM car following, randomized MOBIL lane changing, signal stop rule
+ *     (Appendix B.3, vehicle model implementation);
+ *   - signal policies NONE / FIXED_TIME / MANUAL (Section 3.2, traffic signal);
+ *   - metrics of Section 3.3 (lane queue length, road speed, average
+ *     travelling time, throughput).
+ *
+ * Conventions
+ *   - Every function returns TSIM_OK (0) or a negative TSIM_E* status; no C++
+ *     exception crosses this boundary.  tsim_last_error() returns a message for
+ *     the last failure on a handle (or the last global failure for NULL).
+ *   - "host" pointers are plain CPU memory owned by the caller and only read
+ *     (or written, for getters) during the call.  "device" pointers are GPU
+ *     memory.  Nothing is retained after a call returns except where stated.
+ *   - A handle is used by one host thread at a time.
+ *   - Lane ids: road lanes are numbered road by road (road r owns
+ *     road_lane_begin[r] .. road_lane_begin[r+1]-1, index 0 within a road is
+ *     the leftmost lane); junction lanes follow, junction lane q having lane
+ *     id n_road_lanes + q.
+ *   - Time: step t covers [t*dt, (t+1)*dt).
+ */
+#ifndef TSIM_H
+#define TSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TSIM_OK 0
+#define TSIM_EINVAL (-1)   /* invalid argument or malformed network / trips */
+#define TSIM_ENOMEM (-2)   /* device arena smaller than tsim_footprint() */
+#define TSIM_EDEVICE (-3)  /* a HIP call failed; message in tsim_last_error */
+#define TSIM_ESTATE (-4)   /* the device detected a violated invariant (see metrics.errors) */
+
+/* signal policies (Section 3.2) */
+#define TSIM_POLICY_NONE 0       /* every junction lane always green */
+#define TSIM_POLICY_FIXED_TIME 1 /* phases in order with their durations, phase 0 at t = 0 */
+#define TSIM_POLICY_MANUAL 2     /* phase set through tsim_set_signal_phases */
+
+/* vehicle status */
+#define TSIM_WAITING 0
+#define TSIM_ACTIVE 1
+#define TSIM_FINISHED 2
+
+/*
+ * Road network (all host arrays, read during tsim_footprint/tsim_create).
+ * Limits: <= 32 lanes per road, <= 32 phases per junction, lane and junction
+ * lane lengths >= v_max*dt + a_max*dt^2/2 (one lane-end crossing per step),
+ * every road lane length shared by the lanes of its road.
+ */
+typedef struct tsim_network {
+    int32_t n_junctions;
+    int32_t n_roads;
+    const int32_t *road_from;        /* [n_roads] junction the road leaves */
+    const int32_t *road_to;          /* [n_roads] junction the road enters */
+    const int32_t *road_lane_begin;  /* [n_roads+1] road lanes of road r */
+    const float *road_length;        /* [n_roads] metres */
+    const float *road_limit;         /* [n_roads] m/s */
+    int32_t n_jlanes;
+    const int32_t *jl_in_lane;       /* [n_jlanes] road lane the junction lane leaves */
+    const int32_t *jl_out_lane;      /* [n_jlanes] road lane it enters (next road) */
+    const float *jl_length;          /* [n_jlanes] metres */
+    const float *jl_limit;           /* [n_jlanes] m/s */
+    const int32_t *junc_phase_begin; /* [n_junctions+1] phases of junction j */
+    const float *phase_duration;     /* [n_phases] seconds (FIXED_TIME) */
+    const int32_t *phase_green_begin;/* [n_phases+1] green junction lanes of phase p */
+    const int32_t *phase_green_jl;   /* junction-lane indices 0..n_jlanes-1 */
+    const int32_t *junc_policy;      /* [n_junctions] TSIM_POLICY_* */
+} tsim_network;
+
+/* Trip table (host arrays).  Route = consecutive road ids, origin first,
+ * destination last; consecutive roads must be joined by a junction lane. */
+typedef struct tsim_trips {
+    int32_t n_vehicles;
+    const float *depart_time;        /* [n] seconds */
+    const int32_t *route_begin;      /* [n+1] CSR into route_roads */
+    const int32_t *route_roads;      /* road ids */
+    const float *v0_factor;          /* [n] desired speed = v0_factor * lane limit */
+    const float *length;             /* [n] vehicle length, metres, > 0 */
+} tsim_trips;
+
+/* Model parameters (Appendix B.3; the MOBIL threshold, safe deceleration,
+ * probability cap/floor and braking floor are this library's parameters). */
+typedef struct tsim_params {
+    double dt;          /* step, seconds */
+    double T;           /* IDM safe time headway */
+    double a_max;       /* IDM maximum acceleration */
+    double b_comf;      /* IDM comfortable deceleration */
+    double s0;          /* IDM minimum gap */
+    double delta;       /* IDM free-road exponent (4 in the paper) */
+    double politeness;  /* MOBIL politeness p (0.1 in the paper) */
+    double a_th;        /* MOBIL switching threshold */
+    double b_safe;      /* MOBIL safe deceleration of the new follower */
+    double p_max;       /* lane-change probability cap (0.9 in the paper) */
+    double p_min;       /* lane-change probability floor (2e-8 in the paper) */
+    double a_emerg;     /* braking floor */
+    uint64_t seed;      /* Philox4x32-10 key */
+} tsim_params;
+
+/* Aggregates (Section 3.3).  Totals since create / set_state. */
+typedef struct tsim_metrics {
+    int64_t step;             /* steps taken: the next step to run */
+    int64_t n_waiting;
+    int64_t n_active;
+    int64_t n_finished;       /* throughput (get_finished_vehicle_count) */
+    double sum_travel_time;   /* seconds, over finished vehicles */
+    double att;               /* average travelling time of finished vehicles */
+    double mean_speed_last;   /* road-lane mean speed of the last step */
+    double mean_speed_avg;    /* time average of mean_speed_last */
+    int64_t vehicle_steps;    /* sum over steps of active vehicles */
+    int64_t lane_changes;
+    int64_t transfers;        /* lane-end crossings into the next lane */
+    int64_t clamps;           /* position bounded by a snapshot obstacle */
+    int64_t feeder_blocks;    /* merge entries refused by feeder priority */
+    int64_t departures;
+    int64_t speed_steps;      /* steps with at least one road-lane vehicle */
+    int64_t errors;           /* device-detected capacity/ordering violations */
+} tsim_metrics;
+
+/* Vehicle state for checkpoint/resume and tests (host arrays of n_vehicles,
+ * n_junctions entries, filled by get_state and read by set_state). */
+typedef struct tsim_state_host {
+    int64_t step;
+    int32_t *status;          /* TSIM_WAITING / ACTIVE / FINISHED */
+    int32_t *lane;            /* lane id when ACTIVE, else -1 */
+    int32_t *route_pos;       /* index of the current road within the route */
+    float *x;                 /* front-bumper coordinate along the lane, metres */
+    float *v;                 /* speed, m/s */
+    int32_t *finish_step;     /* step during which the trip ended, else -1 */
+    int32_t *junc_policy;     /* [n_junctions] */
+    int32_t *junc_phase;      /* [n_junctions] MANUAL phase index */
+} tsim_state_host;
+
+typedef struct tsim_handle tsim_handle;
+
+/* Device bytes tsim_create needs for this input (arena size). */
+int tsim_footprint(const tsim_network *net, const tsim_trips *trips, const tsim_params *params,
+                   size_t *bytes_out);
+
+/* Builds the device state inside the caller's arena (device pointer, at
+ * least tsim_footprint bytes, 256-byte aligned, alive until tsim_destroy).
+ * hip_stream (a hipStream_t, or NULL for the null stream) carries every later
+ * launch and copy.  Validates the input (TSIM_EINVAL with a message). */
+int tsim_create(const tsim_network *net, const tsim_trips *trips, const tsim_params *params,
+                void *hip_stream, void *device_arena, size_t arena_bytes, tsim_handle **out);
+
+/* Enqueues n_steps steps on the stream and returns without waiting. */
+int tsim_step(tsim_handle *h, int32_t n_steps);
+
+/* Junctions junction_ids[c] switch to MANUAL with phase phase_index[c] from
+ * the next step on (Section 3.2 set_tl_phase and its batch form). */
+int tsim_set_signal_phases(tsim_handle *h, const int32_t *junction_ids, const int32_t *phase_index,
+                           int32_t n);
+
+/* Synchronises the stream, then fills *out. */
+int tsim_get_metrics(tsim_handle *h, tsim_metrics *out);
+
+/* Mean speed of the vehicles on each road's lanes during the last step
+ * (end-of-step speeds), -1 for a road without vehicles.  out[n_roads]. */
+int tsim_get_road_mean_speed(tsim_handle *h, float *out, int32_t n_roads);
+
+/* Vehicles slower than 0.1 m/s at the end of the last step, per lane they
+ * occupied during it.  out[n_lanes] (road lanes then junction lanes). */
+int tsim_get_lane_waiting_counts(tsim_handle *h, int32_t *out, int32_t n_lanes);
+
+/* Vehicle ids of every lane, front first (the sensing index): offsets
+ * [n_lanes+1] and ids [n_active]. */
+int tsim_get_lane_order(tsim_handle *h, int32_t *offsets, int32_t *vehicle_ids, int32_t n_lanes,
+                        int32_t max_ids);
+
+int tsim_get_state(tsim_handle *h, tsim_state_host *out);
+/* Replaces the state.  Finished-trip totals are recomputed from finish_step;
+ * the running averages and event counters restart from zero. */
+int tsim_set_state(tsim_handle *h, const tsim_state_host *in);
+
+int tsim_destroy(tsim_handle *h);
+const char *tsim_last_error(const tsim_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSIM_H */

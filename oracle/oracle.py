@@ -1,0 +1,190 @@
+"""ctypes binding of the FP64 CPU oracle (``tsim_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  It takes the
+same plain generator arrays as the HIP library and nothing else.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tsim_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+WAITING, ACTIVE, FINISHED = 0, 1, 2
+EV_TRANSFER, EV_FINISH, EV_FEEDER_BLOCK, EV_CLAMP, EV_DEPART = 1, 2, 4, 8, 16
+NMARGIN = 6
+METRIC_NAMES = ["t", "waiting", "active", "finished", "sum_tt", "att", "mean_speed_last",
+                "mean_speed_avg", "vehicle_steps", "lane_changes", "transfers", "clamps",
+                "feeder_blocks", "departures", "speed_steps", "_"]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain C, -O2, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        L.osim_create.restype = C.c_void_p
+        L.osim_create.argtypes = ([C.c_int, C.c_int] + [C.c_void_p] * 5 + [C.c_int] + [C.c_void_p] * 9
+                                  + [C.c_int] + [C.c_void_p] * 5 + [C.c_void_p, C.c_uint64])
+        L.osim_destroy.argtypes = [C.c_void_p]
+        L.osim_step.argtypes = [C.c_void_p, C.c_int]
+        L.osim_get_state.argtypes = [C.c_void_p] + [C.c_void_p] * 7
+        L.osim_set_state.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 6
+        L.osim_set_signal_phases.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.osim_set_policy.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.osim_get_metrics.argtypes = [C.c_void_p, C.c_void_p]
+        L.osim_get_road_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.osim_get_lane_waiting.argtypes = [C.c_void_p, C.c_void_p]
+        L.osim_get_green.argtypes = [C.c_void_p, C.c_void_p]
+        L.osim_eval_signals.argtypes = [C.c_void_p, C.c_void_p]
+        L.osim_last_diag.argtypes = [C.c_void_p] + [C.c_void_p] * 4
+        L.osim_idm.restype = C.c_double
+        L.osim_idm.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.osim_philox.argtypes = [C.c_uint64, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def params_array(params):
+    return np.array([params.dt, params.T, params.a_max, params.b_comf, params.s0, params.delta,
+                     params.politeness, params.a_th, params.b_safe, params.p_max, params.p_min,
+                     params.a_emerg], np.float64)
+
+
+def idm(params, v, v0, s, dv):
+    pa = params_array(params)
+    return lib().osim_idm(_p(pa), float(v), float(v0), float(s), float(dv))
+
+
+def philox(seed, ctr):
+    c = np.ascontiguousarray(np.asarray(ctr, np.uint32))
+    out = np.zeros(4, np.uint32)
+    lib().osim_philox(C.c_uint64(seed), _p(c), _p(out))
+    return out
+
+
+class OracleSim:
+    """One oracle simulation instance over a generator network and trip table."""
+
+    def __init__(self, net, trips, params):
+        L = lib()
+        self.net, self.trips, self.params = net, trips, params
+        i32 = lambda a: np.ascontiguousarray(a, np.int32)
+        f32 = lambda a: np.ascontiguousarray(a, np.float32)
+        self._keep = [i32(net.road_from), i32(net.road_to), i32(net.road_lane_begin), f32(net.road_length),
+                      f32(net.road_limit), i32(net.jl_in_lane), i32(net.jl_out_lane), f32(net.jl_length),
+                      f32(net.jl_limit), i32(net.junc_phase_begin), f32(net.phase_duration),
+                      i32(net.phase_green_begin), i32(net.phase_green_jl), i32(net.junc_policy),
+                      f32(trips.depart_time), i32(trips.route_begin), i32(trips.route_roads),
+                      f32(trips.v0_factor), f32(trips.length), params_array(params)]
+        k = self._keep
+        self.N = trips.n_vehicles
+        self.R = net.n_roads
+        self.NL = net.n_lanes
+        self.NJL = net.n_jlanes
+        self.h = L.osim_create(net.n_junctions, net.n_roads, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]),
+                               net.n_jlanes, _p(k[5]), _p(k[6]), _p(k[7]), _p(k[8]), _p(k[9]), _p(k[10]),
+                               _p(k[11]), _p(k[12]), _p(k[13]),
+                               self.N, _p(k[14]), _p(k[15]), _p(k[16]), _p(k[17]), _p(k[18]),
+                               _p(k[19]), C.c_uint64(params.seed))
+        if not self.h:
+            raise MemoryError("oracle create failed")
+
+    def close(self):
+        if self.h:
+            lib().osim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        lib().osim_step(self.h, int(n))
+
+    def get_state(self):
+        N = self.N
+        t = np.zeros(1, np.int64)
+        st = dict(status=np.zeros(N, np.int32), lane=np.zeros(N, np.int32), route_pos=np.zeros(N, np.int32),
+                  x=np.zeros(N, np.float64), v=np.zeros(N, np.float64), finish_step=np.zeros(N, np.int32))
+        lib().osim_get_state(self.h, _p(t), _p(st["status"]), _p(st["lane"]), _p(st["route_pos"]),
+                             _p(st["x"]), _p(st["v"]), _p(st["finish_step"]))
+        st["step"] = int(t[0])
+        return st
+
+    def set_state(self, st):
+        a = {k: np.ascontiguousarray(st[k], np.int32) for k in ("status", "lane", "route_pos", "finish_step")}
+        x = np.ascontiguousarray(st["x"], np.float64)
+        v = np.ascontiguousarray(st["v"], np.float64)
+        lib().osim_set_state(self.h, C.c_int64(int(st["step"])), _p(a["status"]), _p(a["lane"]),
+                             _p(a["route_pos"]), _p(x), _p(v), _p(a["finish_step"]))
+
+    def set_signal_phases(self, junctions, phases):
+        j = np.ascontiguousarray(junctions, np.int32)
+        p = np.ascontiguousarray(phases, np.int32)
+        lib().osim_set_signal_phases(self.h, int(j.size), _p(j), _p(p))
+
+    def set_policy(self, junctions, policies):
+        j = np.ascontiguousarray(junctions, np.int32)
+        p = np.ascontiguousarray(policies, np.int32)
+        lib().osim_set_policy(self.h, int(j.size), _p(j), _p(p))
+
+    def metrics(self):
+        out = np.zeros(16, np.float64)
+        lib().osim_get_metrics(self.h, _p(out))
+        return dict(zip(METRIC_NAMES, out.tolist()))
+
+    def road_stats(self):
+        sv = np.zeros(self.R, np.float64)
+        c = np.zeros(self.R, np.int32)
+        lib().osim_get_road_stats(self.h, _p(sv), _p(c))
+        return sv, c
+
+    def lane_waiting(self):
+        out = np.zeros(self.NL, np.int32)
+        lib().osim_get_lane_waiting(self.h, _p(out))
+        return out
+
+    def green(self):
+        out = np.zeros(self.NJL, np.uint8)
+        lib().osim_get_green(self.h, _p(out))
+        return out
+
+    def eval_signals(self):
+        out = np.zeros(self.NJL, np.uint8)
+        lib().osim_eval_signals(self.h, _p(out))
+        return out
+
+    def diag(self):
+        N = self.N
+        m = np.zeros((N, NMARGIN), np.float64)
+        mob = np.zeros((N, 4), np.float64)
+        dec = np.zeros(N, np.int32)
+        ev = np.zeros(N, np.int32)
+        lib().osim_last_diag(self.h, _p(m), _p(mob), _p(dec), _p(ev))
+        return dict(margin=m, mobil=mob, decision=dec, event=ev)

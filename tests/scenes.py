@@ -1,0 +1,43 @@
+"""Tiny hand-built networks and scenes for the oracle pins."""
+
+import numpy as np
+
+from paper_2406_10661_amd import workloads as W
+
+
+def line_network(lanes=1, length=300.0, limit=13.9, policy=W.POLICY_FIXED_TIME):
+    """J0 -- J1 -- J2 on a straight line: roads 0 (J0->J1), 1 (J1->J0),
+    2 (J1->J2), 3 (J2->J1).  Road 0 continues straight into road 2."""
+    xy = np.array([[0.0, 0.0], [length + 50, 0.0], [2 * length + 100, 0.0]])
+    net = W._build_network(xy, np.array([[0, 1], [1, 2]]), [length, length], [lanes, lanes],
+                           [limit, limit], policy=policy)
+    return net
+
+
+def left_turn_network(lanes=2, length=300.0, limit=13.9, policy=W.POLICY_NONE):
+    """J0 (0,0) -> J1 (L,0) -> J2 (L,L): road 0 turns left into road 2, so only
+    lane 0 of road 0 connects (lane group {0})."""
+    xy = np.array([[0.0, 0.0], [length, 0.0], [length, length]])
+    return W._build_network(xy, np.array([[0, 1], [1, 2]]), [length, length], [lanes, lanes],
+                            [limit, limit], policy=policy)
+
+
+def trips_for(routes, depart=None, v0_factor=None, length=5.0):
+    n = len(routes)
+    rb = np.zeros(n + 1, np.int32)
+    rb[1:] = np.cumsum([len(r) for r in routes])
+    return W.Trips(
+        depart_time=np.zeros(n, np.float32) if depart is None else np.asarray(depart, np.float32),
+        route_begin=rb,
+        route_roads=np.concatenate([np.asarray(r, np.int32) for r in routes]),
+        v0_factor=np.ones(n, np.float32) if v0_factor is None else np.asarray(v0_factor, np.float32),
+        length=np.full(n, length, np.float32),
+    )
+
+
+def state_from(n, lanes, xs, vs, route_pos=None, step=0, status=None):
+    st = dict(status=np.full(n, 1, np.int32) if status is None else np.asarray(status, np.int32),
+              lane=np.asarray(lanes, np.int32), x=np.asarray(xs, np.float64), v=np.asarray(vs, np.float64),
+              route_pos=np.zeros(n, np.int32) if route_pos is None else np.asarray(route_pos, np.int32),
+              finish_step=np.full(n, -1, np.int32), step=step)
+    return st
