@@ -695,7 +695,7 @@ static double mobil_dir(osim *s, int i, int dir, double *m_pos, double *m_acc, i
         g = s->x[i] - s->L[i] - s->x[tf] - (s->v[tf] * P->dt + reach_extra); /* F4 */
         if (!(g >= 0.0)) { feasible = 0; if (-g > worst_fail) worst_fail = -g; }
         if (fabs(g) < min_pass) min_pass = fabs(g);
-    } else {
+    } else if (tf < 0) {
         for (int e = s->feed_begin[kk]; e < s->feed_begin[kk + 1]; ++e) {
             int fl = s->feed_jl[e];
             int h = lane_front(s, fl);
@@ -808,8 +808,10 @@ static void step_once(osim *s)
         double m_r = INFINITY;
         if (uT > 0.0) {
             double bL = pLC * uLp / uT;
-            if (rr < bL) dec = 1;
-            else if (rr < pLC) dec = 2;
+            /* a side with zero utility owns an empty interval (guarded, since
+             * the rounded boundary may sit a hair below p_LC) */
+            if (uLp > 0.0 && rr < bL) dec = 1;
+            else if (uRp > 0.0 && rr >= bL && rr < pLC) dec = 2;
             m_r = fmin(fabs(rr - bL), fabs(rr - pLC));
         } else {
             int fL = uL > -INFINITY, fR = uR > -INFINITY;

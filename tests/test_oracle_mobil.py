@@ -40,10 +40,11 @@ def idm(v, v0, s, dv):
     return max(a, -P.a_emerg)
 
 
-def bf_utility(veh, i, d, n_lanes, group, road_len):
+def bf_utility(veh, i, d, n_lanes, group, road_len, feeders=None):
     """veh: list of dicts (id, lane, x, v, L, f) on one road whose successor
-    lanes are empty and green; group: set of lanes connected to the next road.
-    Returns u (or -inf when the change is infeasible)."""
+    lanes are empty and green; group: set of lanes connected to the next road;
+    feeders: {lane: [(x, v, length of the feeder lane)]} front vehicles of the
+    junction lanes entering each lane.  Returns u (or -inf when infeasible)."""
     me = veh[i]
     lane0 = me["lane"]
     k = lane0 + d
@@ -104,6 +105,11 @@ def bf_utility(veh, i, d, n_lanes, group, road_len):
             return -math.inf
     if nf_a is not None and not yields and acc(after, nf_a) < -P.b_safe:
         return -math.inf
+    # no new follower: no vehicle leaving a feeder junction lane may reach the rear
+    if nf_a is None:
+        for (xh, vh, lf) in (feeders or {}).get(k, []):
+            if not ((ego_a["x"] - ego_a["L"]) - (xh + vh * P.dt + 0.5 * P.a_max * P.dt ** 2 - lf) >= 0):
+                return -math.inf
     # same gap, rightward only: a vehicle of lane k+1 between the same k-neighbours
     if d > 0 and k + 1 < n_lanes:
         def gap_of(conf, j):
@@ -251,6 +257,59 @@ def test_mobil_bruteforce_lane_group(oracle_lib, seed):
     for i in range(n_veh):
         for col, dd in ((0, -1), (1, +1)):
             want = bf_utility(veh, i, dd, n_lanes, {0}, float(net.road_length[0]))
+            got = d["mobil"][i, col]
+            if math.isinf(want):
+                assert math.isinf(got) and got < 0, (seed, i, dd, got)
+            else:
+                assert got == pytest.approx(want, abs=1e-9), (seed, i, dd)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_mobil_bruteforce_with_feeder(oracle_lib, seed):
+    """Two-lane road whose lane 0 is also entered from a junction lane (the
+    U-turn at the dead end): a vehicle there can veto a change into lane 0
+    that would leave nobody behind the changer."""
+    rng = np.random.default_rng(5000 + seed)
+    L = 300.0
+    n_road = int(rng.integers(1, 5))
+    lanes, xs, vs, fs = random_scene(rng, 2, n_road, L)
+    xs = xs * 0.2  # near the lane start, where feeder entrants land
+    merging = seed % 2 == 1
+    if merging:
+        # a merging vehicle on lane 1 close to the start, a follower on lane 0
+        # behind its rear (that follower yields), and maybe one more ahead
+        xi = float(rng.uniform(8.0, 18.0))
+        lanes = np.array([1, 0] + ([0] if seed % 4 == 3 else []))
+        xs = np.array([xi, float(rng.uniform(0.0, xi - 5.5))] + ([xi + float(rng.uniform(2.0, 30.0))] if seed % 4 == 3 else []))
+        n_road = len(lanes)
+        vs = rng.uniform(0.0, 14.0, n_road)
+        fs = rng.uniform(0.8, 1.2, n_road).astype(np.float32).astype(np.float64)
+    if merging:
+        # left turn at the end: lane group {0}, vehicles on lane 1 must merge
+        from tests.scenes import left_turn_network
+        net = left_turn_network(lanes=2, length=L, policy=W.POLICY_NONE)
+    else:
+        net = line_network(lanes=2, policy=W.POLICY_NONE)
+    NRL = net.n_road_lanes
+    fq = [q for q in range(net.n_jlanes) if net.jl_out_lane[q] == 0][0]
+    xf = float(rng.uniform(15.0, 24.9))
+    vf = float(rng.uniform(0.0, 14.0))
+    routes = [[0, 2]] * n_road + [[1, 0, 2]]
+    assert net.road_from[1] == net.road_to[0] and net.road_to[1] == net.road_from[0]
+    trips = trips_for(routes, v0_factor=list(fs) + [1.0])
+    o = oracle_lib.OracleSim(net, trips, P)
+    st = state_from(n_road + 1, list(lanes) + [NRL + fq], list(xs) + [xf], list(vs) + [vf],
+                    route_pos=[0] * (n_road + 1))
+    o.set_state(st)
+    o.step(1)
+    d = o.diag()
+    veh = [dict(id=j, id_idx=j, lane=int(lanes[j]), x=float(xs[j]), v=float(vs[j]), L=5.0, f=float(fs[j]))
+           for j in range(n_road)]
+    feeders = {0: [(xf, vf, float(net.jl_length[fq]))]}
+    group = {0} if merging else {0, 1}
+    for i in range(n_road):
+        for col, dd in ((0, -1), (1, +1)):
+            want = bf_utility(veh, i, dd, 2, group, float(net.road_length[0]), feeders)
             got = d["mobil"][i, col]
             if math.isinf(want):
                 assert math.isinf(got) and got < 0, (seed, i, dd, got)
