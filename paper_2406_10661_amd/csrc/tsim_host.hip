@@ -1,0 +1,804 @@
+// Host side of the C ABI (include/tsim.h): input validation, internal lane
+// numbering by road tile, device arena layout, state import/export and the
+// step driver.  All device memory is carved from the caller's arena; the
+// library itself never allocates device memory.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/tsim.h"
+#include "tsim_internal.h"
+
+namespace tsim {
+hipError_t launch_prepare(const DevNet& D, hipStream_t s);
+hipError_t launch_update(const DevNet& D, hipStream_t s);
+hipError_t launch_set_phases(const DevNet& D, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
+hipError_t launch_export(const DevNet& D, const int32_t* lane_ext, int32_t* o_lane, float* o_x, float* o_v,
+                         int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
+hipError_t launch_import(const DevNet& D, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
+}  // namespace tsim
+
+using namespace tsim;
+
+namespace {
+
+thread_local std::string g_error;
+
+struct Build {
+    int R = 0, NJ = 0, NRL = 0, NJL = 0, NL = 0, N = 0;
+    std::vector<int32_t> tile_lane_begin, tile_n_road, tile_order;
+    std::vector<float> lane_len, lane_lim;
+    std::vector<uint32_t> lane_base;
+    std::vector<int32_t> lane_cap, lane_tile, lane_local, jl_out, jl_junc, jl_ext, jl_in_local, jl_out_road;
+    std::vector<uint32_t> jl_green_mask;
+    std::vector<int32_t> out_begin, out_jl, feed_begin, feed_jl;
+    std::vector<int32_t> int_of_ext, ext_of_int;
+    std::vector<int32_t> junc_phase_begin, junc_policy;
+    std::vector<float> phase_dur;
+    std::vector<double> junc_cycle;
+    std::vector<float> tau, vf, vlen;
+    std::vector<int32_t> route_begin, route, q_begin, q_veh;
+    uint64_t slots = 0;
+    int G = 0;
+};
+
+struct Region {
+    void** ptr;
+    size_t bytes;
+};
+
+int fail(std::string* err, int code, const std::string& msg)
+{
+    if (err) *err = msg;
+    g_error = msg;
+    return code;
+}
+
+int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_params* prm, Build& B, std::string* err)
+{
+    if (!net || !tr || !prm) return fail(err, TSIM_EINVAL, "null network, trips or params");
+    const int R = net->n_roads, NJ = net->n_junctions, NJL = net->n_jlanes, N = tr->n_vehicles;
+    if (R <= 0 || NJ <= 0 || NJL < 0 || N < 0) return fail(err, TSIM_EINVAL, "bad sizes");
+    if (!net->road_from || !net->road_to || !net->road_lane_begin || !net->road_length || !net->road_limit ||
+        (NJL && (!net->jl_in_lane || !net->jl_out_lane || !net->jl_length || !net->jl_limit)) ||
+        !net->junc_phase_begin || !net->junc_policy || !tr->route_begin || (N && (!tr->depart_time || !tr->route_roads ||
+        !tr->v0_factor || !tr->length)))
+        return fail(err, TSIM_EINVAL, "null array in network or trips");
+    if (!(prm->dt > 0 && prm->a_max > 0 && prm->b_comf > 0 && prm->s0 >= 0 && prm->delta > 0 && prm->a_emerg > 0 &&
+          prm->p_max >= prm->p_min && prm->p_min >= 0 && prm->p_max <= 1))
+        return fail(err, TSIM_EINVAL, "invalid model parameters");
+    B.R = R;
+    B.NJ = NJ;
+    B.NJL = NJL;
+    B.N = N;
+    if (net->road_lane_begin[0] != 0) return fail(err, TSIM_EINVAL, "road_lane_begin[0] must be 0");
+    for (int r = 0; r < R; ++r) {
+        const int nl = net->road_lane_begin[r + 1] - net->road_lane_begin[r];
+        if (nl <= 0 || nl > kMaxRoadLanes) return fail(err, TSIM_EINVAL, "road " + std::to_string(r) + ": 1..32 lanes");
+        if (net->road_from[r] < 0 || net->road_from[r] >= NJ || net->road_to[r] < 0 || net->road_to[r] >= NJ)
+            return fail(err, TSIM_EINVAL, "road junction id out of range");
+        if (!(net->road_length[r] > 0) || !(net->road_limit[r] > 0)) return fail(err, TSIM_EINVAL, "road length/limit");
+    }
+    const int NRL = net->road_lane_begin[R];
+    B.NRL = NRL;
+    B.NL = NRL + NJL;
+    std::vector<int32_t> road_of(NRL);
+    for (int r = 0; r < R; ++r)
+        for (int l = net->road_lane_begin[r]; l < net->road_lane_begin[r + 1]; ++l) road_of[l] = r;
+    std::unordered_set<long long> movement;    // (in road, out road)
+    std::unordered_set<long long> lane_target; // (in lane, out road), must be unique
+    for (int q = 0; q < NJL; ++q) {
+        const int a = net->jl_in_lane[q], b = net->jl_out_lane[q];
+        if (a < 0 || a >= NRL || b < 0 || b >= NRL) return fail(err, TSIM_EINVAL, "junction lane endpoints");
+        if (net->road_to[road_of[a]] != net->road_from[road_of[b]])
+            return fail(err, TSIM_EINVAL, "junction lane " + std::to_string(q) + " does not join its roads at a junction");
+        if (!(net->jl_length[q] > 0) || !(net->jl_limit[q] > 0)) return fail(err, TSIM_EINVAL, "junction lane length/limit");
+        movement.insert((long long)road_of[a] * R + road_of[b]);
+        if (!lane_target.insert((long long)a * R + road_of[b]).second)
+            return fail(err, TSIM_EINVAL, "two junction lanes from one lane into one road");
+    }
+    // trips
+    float Lmin = 1e30f, fmax_ = 0.0f;
+    if (tr->route_begin[0] != 0) return fail(err, TSIM_EINVAL, "route_begin[0] must be 0");
+    for (int i = 0; i < N; ++i) {
+        const int b = tr->route_begin[i], e = tr->route_begin[i + 1];
+        if (e <= b) return fail(err, TSIM_EINVAL, "empty route of vehicle " + std::to_string(i));
+        for (int k = b; k < e; ++k) {
+            const int r = tr->route_roads[k];
+            if (r < 0 || r >= R) return fail(err, TSIM_EINVAL, "route road out of range");
+            if (k + 1 < e && !movement.count((long long)r * R + tr->route_roads[k + 1]))
+                return fail(err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": consecutive route roads not connected");
+        }
+        if (!(tr->length[i] > 0) || !(tr->v0_factor[i] > 0) || !(tr->depart_time[i] >= 0))
+            return fail(err, TSIM_EINVAL, "vehicle length/factor/departure");
+        Lmin = std::min(Lmin, tr->length[i]);
+        fmax_ = std::max(fmax_, tr->v0_factor[i]);
+    }
+    if (N == 0) Lmin = 1.0f;
+    // one lane-end crossing per step: every lane longer than the farthest one-step move
+    const double reach = 0.5 * prm->a_max * prm->dt * prm->dt;
+    for (int r = 0; r < R; ++r)
+        if (net->road_length[r] <= fmax_ * net->road_limit[r] * prm->dt + reach)
+            return fail(err, TSIM_EINVAL, "road " + std::to_string(r) + " shorter than one step of travel");
+    for (int q = 0; q < NJL; ++q)
+        if (net->jl_length[q] <= fmax_ * net->jl_limit[q] * prm->dt + reach)
+            return fail(err, TSIM_EINVAL, "junction lane " + std::to_string(q) + " shorter than one step of travel");
+    // junctions and phases
+    if (net->junc_phase_begin[0] != 0) return fail(err, TSIM_EINVAL, "junc_phase_begin[0] must be 0");
+    const int NP = net->junc_phase_begin[NJ];
+    if (NP && (!net->phase_duration || !net->phase_green_begin || !net->phase_green_jl))
+        return fail(err, TSIM_EINVAL, "null phase arrays");
+    std::vector<int32_t> jl_junc_ext(NJL);
+    for (int q = 0; q < NJL; ++q) jl_junc_ext[q] = net->road_to[road_of[net->jl_in_lane[q]]];
+    std::vector<uint32_t> mask_ext(NJL, 0u);
+    B.junc_cycle.assign(NJ, 0.0);
+    for (int j = 0; j < NJ; ++j) {
+        const int b = net->junc_phase_begin[j], e = net->junc_phase_begin[j + 1];
+        if (e < b || e - b > kMaxPhases) return fail(err, TSIM_EINVAL, "junction " + std::to_string(j) + ": 0..32 phases");
+        const int pol = net->junc_policy[j];
+        if (pol < 0 || pol > 2) return fail(err, TSIM_EINVAL, "bad policy");
+        double cyc = 0.0;
+        for (int p = b; p < e; ++p) {
+            if (pol == TSIM_POLICY_FIXED_TIME && !(net->phase_duration[p] > 0))
+                return fail(err, TSIM_EINVAL, "non-positive phase duration");
+            cyc += net->phase_duration[p];
+            for (int g = net->phase_green_begin[p]; g < net->phase_green_begin[p + 1]; ++g) {
+                const int q = net->phase_green_jl[g];
+                if (q < 0 || q >= NJL || jl_junc_ext[q] != j)
+                    return fail(err, TSIM_EINVAL, "phase lists a junction lane of another junction");
+                mask_ext[q] |= 1u << (p - b);
+            }
+        }
+        B.junc_cycle[j] = cyc;
+    }
+    B.junc_phase_begin.assign(net->junc_phase_begin, net->junc_phase_begin + NJ + 1);
+    B.phase_dur.assign(NP, 0.0f);
+    for (int p = 0; p < NP; ++p) B.phase_dur[p] = net->phase_duration[p];
+    B.junc_policy.assign(net->junc_policy, net->junc_policy + NJ);
+
+    // internal lane numbering: tile r = road lanes of r, then junction lanes
+    // leaving r in external order
+    std::vector<std::vector<int>> jl_of_road(R);
+    for (int q = 0; q < NJL; ++q) jl_of_road[road_of[net->jl_in_lane[q]]].push_back(q);
+    B.tile_lane_begin.assign(R + 1, 0);
+    B.tile_n_road.assign(R, 0);
+    B.int_of_ext.assign(B.NL, -1);
+    B.ext_of_int.assign(B.NL, -1);
+    int nxt = 0;
+    for (int r = 0; r < R; ++r) {
+        B.tile_lane_begin[r] = nxt;
+        const int nl = net->road_lane_begin[r + 1] - net->road_lane_begin[r];
+        B.tile_n_road[r] = nl;
+        if (nl + (int)jl_of_road[r].size() > kMaxTileLanes)
+            return fail(err, TSIM_EINVAL, "road " + std::to_string(r) + ": more than 64 lanes with its junction lanes");
+        for (int l = net->road_lane_begin[r]; l < net->road_lane_begin[r + 1]; ++l) {
+            B.int_of_ext[l] = nxt;
+            B.ext_of_int[nxt] = l;
+            nxt++;
+        }
+        for (int q : jl_of_road[r]) {
+            B.int_of_ext[NRL + q] = nxt;
+            B.ext_of_int[nxt] = NRL + q;
+            nxt++;
+        }
+    }
+    B.tile_lane_begin[R] = nxt;
+    const int NL = B.NL;
+    B.lane_len.assign(NL, 0.f);
+    B.lane_lim.assign(NL, 0.f);
+    B.lane_cap.assign(NL, 0);
+    B.lane_base.assign(NL, 0u);
+    B.lane_tile.assign(NL, 0);
+    B.lane_local.assign(NL, 0);
+    B.jl_out.assign(NL, -1);
+    B.jl_junc.assign(NL, 0);
+    B.jl_ext.assign(NL, -1);
+    B.jl_in_local.assign(NL, -1);
+    B.jl_out_road.assign(NL, -1);
+    B.jl_green_mask.assign(NL, 0u);
+    uint64_t slots = 0;
+    for (int r = 0; r < R; ++r) {
+        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) {
+            const int e = B.ext_of_int[m];
+            B.lane_tile[m] = r;
+            B.lane_local[m] = m - B.tile_lane_begin[r];
+            if (e < NRL) {
+                B.lane_len[m] = net->road_length[r];
+                B.lane_lim[m] = net->road_limit[r];
+            } else {
+                const int q = e - NRL;
+                B.lane_len[m] = net->jl_length[q];
+                B.lane_lim[m] = net->jl_limit[q];
+                B.jl_out[m] = B.int_of_ext[net->jl_out_lane[q]];
+                B.jl_junc[m] = jl_junc_ext[q];
+                B.jl_ext[m] = q;
+                B.jl_in_local[m] = net->jl_in_lane[q] - net->road_lane_begin[r];
+                B.jl_out_road[m] = road_of[net->jl_out_lane[q]];
+                B.jl_green_mask[m] = mask_ext[q];
+            }
+            const int cap = (int)std::floor(B.lane_len[m] / Lmin) + 2;
+            B.lane_cap[m] = cap;
+            B.lane_base[m] = (uint32_t)slots;
+            slots += (uint64_t)cap;
+        }
+    }
+    if (slots >= (1ull << 31)) return fail(err, TSIM_EINVAL, "network too large for 32-bit slot indices");
+    B.slots = slots;
+    // connections per internal road lane
+    B.out_begin.assign(NL + 1, 0);
+    B.feed_begin.assign(NL + 1, 0);
+    for (int q = 0; q < NJL; ++q) {
+        B.out_begin[B.int_of_ext[net->jl_in_lane[q]] + 1]++;
+        B.feed_begin[B.int_of_ext[net->jl_out_lane[q]] + 1]++;
+    }
+    for (int m = 0; m < NL; ++m) {
+        B.out_begin[m + 1] += B.out_begin[m];
+        B.feed_begin[m + 1] += B.feed_begin[m];
+    }
+    B.out_jl.assign(NJL, 0);
+    B.feed_jl.assign(NJL, 0);
+    {
+        std::vector<int> fo(NL, 0), ff(NL, 0);
+        for (int q = 0; q < NJL; ++q) {  // external order = feeder priority order
+            const int a = B.int_of_ext[net->jl_in_lane[q]], b = B.int_of_ext[net->jl_out_lane[q]];
+            B.out_jl[B.out_begin[a] + fo[a]++] = B.int_of_ext[NRL + q];
+            B.feed_jl[B.feed_begin[b] + ff[b]++] = B.int_of_ext[NRL + q];
+        }
+    }
+    // vehicles and departure queues (tau, id) per origin road
+    B.tau.assign(tr->depart_time, tr->depart_time + N);
+    B.vf.assign(tr->v0_factor, tr->v0_factor + N);
+    B.vlen.assign(tr->length, tr->length + N);
+    B.route_begin.assign(tr->route_begin, tr->route_begin + N + 1);
+    B.route.assign(tr->route_roads, tr->route_roads + tr->route_begin[N]);
+    B.q_begin.assign(R + 1, 0);
+    for (int i = 0; i < N; ++i) B.q_begin[B.route[B.route_begin[i]] + 1]++;
+    for (int r = 0; r < R; ++r) B.q_begin[r + 1] += B.q_begin[r];
+    B.q_veh.assign(N, 0);
+    {
+        std::vector<int> fill(R, 0);
+        for (int i = 0; i < N; ++i) {
+            const int r = B.route[B.route_begin[i]];
+            B.q_veh[B.q_begin[r] + fill[r]++] = i;
+        }
+        for (int r = 0; r < R; ++r)
+            std::sort(B.q_veh.begin() + B.q_begin[r], B.q_veh.begin() + B.q_begin[r + 1], [&](int a, int b) {
+                return B.tau[a] < B.tau[b] || (B.tau[a] == B.tau[b] && a < b);
+            });
+    }
+    // tiles in decreasing capacity, so long roads start first
+    std::vector<long long> tcap(R, 0);
+    for (int r = 0; r < R; ++r)
+        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) tcap[r] += B.lane_cap[m];
+    B.tile_order.resize(R);
+    std::iota(B.tile_order.begin(), B.tile_order.end(), 0);
+    std::stable_sort(B.tile_order.begin(), B.tile_order.end(), [&](int a, int b) { return tcap[a] > tcap[b]; });
+    B.G = std::max(1, std::min(R, 8192));
+    return TSIM_OK;
+}
+
+}  // namespace
+
+struct tsim_handle {
+    hipStream_t stream = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    DevNet D{};
+    Build B;
+    int32_t* d_lane_ext = nullptr;   // internal -> external lane id
+    int32_t* d_io_i0 = nullptr;      // staging: export lane / import slots
+    int32_t* d_io_i1 = nullptr;      // staging: export route pos
+    int32_t* d_io_i2 = nullptr;      // staging: export rank
+    float* d_io_f0 = nullptr;
+    float* d_io_f1 = nullptr;
+    VehRec* d_io_rec = nullptr;      // staging: import records
+    int32_t* d_io_ph = nullptr;      // staging: phase updates (2 x NJ)
+    std::string err;
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// every device array of a handle, in arena order
+std::vector<Region> regions(tsim_handle* h, bool assign)
+{
+    Build& B = h->B;
+    DevNet& D = h->D;
+    const size_t NL = B.NL, R = B.R, NJ = B.NJ, N = B.N, S = B.slots, NJL = B.NJL;
+    std::vector<Region> v;
+    auto add = [&](void* field, size_t bytes) { v.push_back({(void**)field, bytes}); };
+    (void)assign;
+    add(&D.tile_lane_begin, (R + 1) * 4);
+    add(&D.tile_n_road, R * 4);
+    add(&D.tile_order, R * 4);
+    add(&D.lane_len, NL * 4);
+    add(&D.lane_lim, NL * 4);
+    add(&D.lane_base, NL * 4);
+    add(&D.lane_cap, NL * 4);
+    add(&D.lane_tile, NL * 4);
+    add(&D.lane_local, NL * 4);
+    add(&D.jl_out, NL * 4);
+    add(&D.jl_junc, NL * 4);
+    add(&D.jl_green_mask, NL * 4);
+    add(&D.jl_ext, NL * 4);
+    add(&D.jl_in_local, NL * 4);
+    add(&D.jl_out_road, NL * 4);
+    add(&D.out_begin, (NL + 1) * 4);
+    add(&D.out_jl, std::max<size_t>(NJL, 1) * 4);
+    add(&D.feed_begin, (NL + 1) * 4);
+    add(&D.feed_jl, std::max<size_t>(NJL, 1) * 4);
+    add(&D.junc_phase_begin, (NJ + 1) * 4);
+    add(&D.phase_dur, std::max<size_t>(B.phase_dur.size(), 1) * 4);
+    add(&D.junc_cycle, NJ * 8);
+    add(&D.junc_policy, NJ * 4);
+    add(&D.junc_manual, NJ * 4);
+    add(&D.junc_cur, NJ * 4);
+    add(&D.tau, std::max<size_t>(N, 1) * 4);
+    add(&D.route_begin, (N + 1) * 4);
+    add(&D.route, std::max<size_t>(B.route.size(), 1) * 4);
+    add(&D.vf, std::max<size_t>(N, 1) * 4);
+    add(&D.vlen, std::max<size_t>(N, 1) * 4);
+    add(&D.status, std::max<size_t>(N, 1) * 4);
+    add(&D.finish_step, std::max<size_t>(N, 1) * 4);
+    add(&D.q_begin, (R + 1) * 4);
+    add(&D.q_veh, std::max<size_t>(N, 1) * 4);
+    add(&D.q_head, R * 4);
+    add(&D.slab0, S * sizeof(VehRec));
+    add(&D.slab1, S * sizeof(VehRec));
+    add(&D.cnt0, NL * 4);
+    add(&D.cnt1, NL * 4);
+    add(&D.inbox, NL * sizeof(VehRec));
+    add(&D.inbox_flag, NL * 4);
+    add(&D.sh_gmask, S * 4);
+    add(&D.sh_aown, S * 4);
+    add(&D.sh_merge, S * 4);
+    add(&D.sh_lrear, S * 4);
+    add(&D.sh_lv, S * 4);
+    add(&D.sh_nx, S * 4);
+    add(&D.sh_nv, S * 4);
+    add(&D.sh_kind, S * 4);
+    add(&D.sh_nlane, S * 4);
+    add(&D.sh_pref, S * 4);
+    add(&D.road_speed, R * 4);
+    add(&D.lane_wait, NL * 4);
+    add(&D.part, (size_t)B.G * sizeof(WGPartial));
+    add(&D.done_ctr, 4);
+    add(&D.met, sizeof(DevMetrics));
+    add(&h->d_lane_ext, NL * 4);
+    add(&h->d_io_i0, std::max<size_t>(N, 1) * 4);
+    add(&h->d_io_i1, std::max<size_t>(N, 1) * 4);
+    add(&h->d_io_i2, std::max<size_t>(N, 1) * 4);
+    add(&h->d_io_f0, std::max<size_t>(N, 1) * 4);
+    add(&h->d_io_f1, std::max<size_t>(N, 1) * 4);
+    add(&h->d_io_rec, std::max<size_t>(N, 1) * sizeof(VehRec));
+    add(&h->d_io_ph, 2 * NJ * 4);
+    return v;
+}
+
+size_t arena_size(tsim_handle* h)
+{
+    size_t s = 0;
+    for (auto& r : regions(h, false)) s += align_up(r.bytes);
+    return s;
+}
+
+int hip_fail(tsim_handle* h, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (h) h->err = m;
+    g_error = m;
+    return TSIM_EDEVICE;
+}
+
+#define HIPCHK(h, call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+    } while (0)
+
+template <class T>
+hipError_t up(tsim_handle* h, T* dst, const std::vector<T>& src)
+{
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync((void*)dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, h->stream);
+}
+
+void fill_params(KParams& P, const tsim_params* p)
+{
+    P.dt = (float)p->dt;
+    P.T = (float)p->T;
+    P.a_max = (float)p->a_max;
+    P.s0 = (float)p->s0;
+    P.delta = (float)p->delta;
+    P.p = (float)p->politeness;
+    P.a_th = (float)p->a_th;
+    P.b_safe = (float)p->b_safe;
+    P.p_max = (float)p->p_max;
+    P.p_min = (float)p->p_min;
+    P.a_emerg = (float)p->a_emerg;
+    P.inv_2sqrt_ab = (float)(1.0 / (2.0 * std::sqrt(p->a_max * p->b_comf)));
+    P.reach = (float)(0.5 * p->a_max * p->dt * p->dt);
+    P.dt_d = p->dt;
+    P.key0 = (uint32_t)p->seed;
+    P.key1 = (uint32_t)(p->seed >> 32);
+    P.delta_is_4 = p->delta == 4.0 ? 1 : 0;
+}
+
+// uploads a full state: per-lane orders are rebuilt on the host
+int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int32_t* lane_ext, const int32_t* route_pos,
+                 const float* x, const float* v, const int32_t* finish_step, const int32_t* pol, const int32_t* ph)
+{
+    Build& B = h->B;
+    DevNet& D = h->D;
+    const int N = B.N;
+    std::vector<std::vector<int>> per_lane(B.NL);
+    long long departed = 0, finished = 0;
+    long long sum_tt = 0;
+    for (int i = 0; i < N; ++i) {
+        const int s = status[i];
+        if (s < 0 || s > 2) return fail(&h->err, TSIM_EINVAL, "bad status");
+        if (s == TSIM_ACTIVE) {
+            const int e = lane_ext[i];
+            if (e < 0 || e >= B.NL) return fail(&h->err, TSIM_EINVAL, "active vehicle without a valid lane");
+            const int rl = B.route_begin[i + 1] - B.route_begin[i];
+            const int k = route_pos[i];
+            if (k < 0 || k >= rl) return fail(&h->err, TSIM_EINVAL, "route position out of range");
+            const int m = B.int_of_ext[e];
+            const int r = B.lane_tile[m];
+            if (B.route[B.route_begin[i] + k] != r) return fail(&h->err, TSIM_EINVAL, "lane not on the current road");
+            if (B.jl_out[m] >= 0 && (k + 1 >= rl || B.jl_out_road[m] != B.route[B.route_begin[i] + k + 1]))
+                return fail(&h->err, TSIM_EINVAL, "junction lane not toward the next road");
+            if (!(x[i] >= 0.0f && x[i] <= B.lane_len[m]) || !(v[i] >= 0.0f))
+                return fail(&h->err, TSIM_EINVAL, "position or speed out of range");
+            per_lane[m].push_back(i);
+        }
+        if (s != TSIM_WAITING) departed++;
+        if (s == TSIM_FINISHED) {
+            finished++;
+            const double tt = (double)(finish_step[i] + 1) * h->D.P.dt_d - (double)B.tau[i];
+            sum_tt += llrint(tt * kTimeFx);
+        }
+    }
+    std::vector<uint32_t> slots;
+    std::vector<VehRec> recs;
+    std::vector<int32_t> cnt(B.NL, 0);
+    slots.reserve(departed);
+    recs.reserve(departed);
+    for (int m = 0; m < B.NL; ++m) {
+        auto& L = per_lane[m];
+        std::sort(L.begin(), L.end(), [&](int a, int b) { return x[a] > x[b] || (x[a] == x[b] && a < b); });
+        if ((int)L.size() > B.lane_cap[m]) return fail(&h->err, TSIM_EINVAL, "lane over capacity (overlapping vehicles)");
+        cnt[m] = (int)L.size();
+        for (size_t c = 0; c < L.size(); ++c) {
+            const int i = L[c];
+            VehRec o;
+            o.x = x[i];
+            o.v = v[i];
+            o.vid = i;
+            o.len = B.vlen[i];
+            o.f = B.vf[i];
+            o.rp = B.route_begin[i] + route_pos[i];
+            o.rem = B.route_begin[i + 1] - o.rp - 1;
+            o.nr = o.rem > 0 ? B.route[o.rp + 1] : -1;
+            slots.push_back(B.lane_base[m] + (uint32_t)c);
+            recs.push_back(o);
+        }
+    }
+    std::vector<int32_t> qhead(B.R);
+    for (int r = 0; r < B.R; ++r) {
+        int hd = B.q_begin[r];
+        while (hd < B.q_begin[r + 1] && status[B.q_veh[hd]] != TSIM_WAITING) hd++;
+        qhead[r] = hd;
+    }
+    DevMetrics M{};
+    M.step = step;
+    M.departed = departed;
+    M.finished = finished;
+    M.sum_tt_fx = sum_tt;
+    std::vector<int32_t> st(status, status + N), fs(finish_step, finish_step + N);
+    std::vector<int32_t> jp(pol, pol + B.NJ), jm(ph, ph + B.NJ);
+    int32_t* cnt_rd = (step & 1) ? D.cnt1 : D.cnt0;
+    HIPCHK(h, up(h, D.status, st));
+    HIPCHK(h, up(h, D.finish_step, fs));
+    HIPCHK(h, up(h, D.junc_policy, jp));
+    HIPCHK(h, up(h, D.junc_manual, jm));
+    HIPCHK(h, up(h, D.q_head, qhead));
+    HIPCHK(h, up(h, cnt_rd, cnt));
+    HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
+    HIPCHK(h, hipMemcpyAsync(D.met, &M, sizeof(M), hipMemcpyHostToDevice, h->stream));
+    if (!slots.empty()) {
+        HIPCHK(h, hipMemcpyAsync(h->d_io_i0, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->d_io_rec, recs.data(), recs.size() * sizeof(VehRec), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, launch_import(D, (const uint32_t*)h->d_io_i0, h->d_io_rec, (int)slots.size(), h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsim_footprint(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, size_t* bytes_out)
+{
+    if (!bytes_out) return fail(nullptr, TSIM_EINVAL, "null bytes_out");
+    tsim_handle tmp;
+    int rc = build_tables(net, trips, params, tmp.B, nullptr);
+    if (rc) return rc;
+    *bytes_out = arena_size(&tmp) + 256;
+    return TSIM_OK;
+}
+
+int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,
+                void* device_arena, size_t arena_bytes, tsim_handle** out)
+{
+    if (!out) return fail(nullptr, TSIM_EINVAL, "null out");
+    *out = nullptr;
+    if (!device_arena) return fail(nullptr, TSIM_EINVAL, "null arena");
+    tsim_handle* h = new (std::nothrow) tsim_handle();
+    if (!h) return fail(nullptr, TSIM_ENOMEM, "host allocation failed");
+    int rc = build_tables(net, trips, params, h->B, &h->err);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    const size_t need = arena_size(h);
+    char* base = (char*)(((uintptr_t)device_arena + 255) & ~(uintptr_t)255);
+    const size_t lost = (size_t)(base - (char*)device_arena);
+    if (arena_bytes < need + lost) {
+        g_error = "arena too small: need " + std::to_string(need + lost) + " bytes";
+        delete h;
+        return TSIM_ENOMEM;
+    }
+    h->stream = (hipStream_t)hip_stream;
+    h->arena = (char*)device_arena;
+    h->arena_bytes = arena_bytes;
+    size_t off = 0;
+    for (auto& r : regions(h, true)) {
+        *r.ptr = base + off;
+        off += align_up(r.bytes);
+    }
+    Build& B = h->B;
+    DevNet& D = h->D;
+    D.R = B.R;
+    D.NJ = B.NJ;
+    D.NL = B.NL;
+    D.N = B.N;
+    D.G = B.G;
+    fill_params(D.P, params);
+    auto chk = [&](hipError_t e, const char* what) -> int { return e == hipSuccess ? 0 : hip_fail(h, e, what); };
+    int e = 0;
+    e = e ? e : chk(up(h, (int32_t*)D.tile_lane_begin, B.tile_lane_begin), "tiles");
+    e = e ? e : chk(up(h, (int32_t*)D.tile_n_road, B.tile_n_road), "tiles");
+    e = e ? e : chk(up(h, (int32_t*)D.tile_order, B.tile_order), "tiles");
+    e = e ? e : chk(up(h, (float*)D.lane_len, B.lane_len), "lanes");
+    e = e ? e : chk(up(h, (float*)D.lane_lim, B.lane_lim), "lanes");
+    e = e ? e : chk(up(h, (uint32_t*)D.lane_base, B.lane_base), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.lane_cap, B.lane_cap), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.lane_tile, B.lane_tile), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.lane_local, B.lane_local), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.jl_out, B.jl_out), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.jl_junc, B.jl_junc), "lanes");
+    e = e ? e : chk(up(h, (uint32_t*)D.jl_green_mask, B.jl_green_mask), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.jl_ext, B.jl_ext), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.jl_in_local, B.jl_in_local), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.jl_out_road, B.jl_out_road), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.out_begin, B.out_begin), "conn");
+    e = e ? e : chk(up(h, (int32_t*)D.out_jl, B.out_jl), "conn");
+    e = e ? e : chk(up(h, (int32_t*)D.feed_begin, B.feed_begin), "conn");
+    e = e ? e : chk(up(h, (int32_t*)D.feed_jl, B.feed_jl), "conn");
+    e = e ? e : chk(up(h, (int32_t*)D.junc_phase_begin, B.junc_phase_begin), "junctions");
+    e = e ? e : chk(up(h, (float*)D.phase_dur, B.phase_dur), "junctions");
+    e = e ? e : chk(up(h, (double*)D.junc_cycle, B.junc_cycle), "junctions");
+    e = e ? e : chk(up(h, (float*)D.tau, B.tau), "trips");
+    e = e ? e : chk(up(h, (int32_t*)D.route_begin, B.route_begin), "trips");
+    e = e ? e : chk(up(h, (int32_t*)D.route, B.route), "trips");
+    e = e ? e : chk(up(h, (float*)D.vf, B.vf), "trips");
+    e = e ? e : chk(up(h, (float*)D.vlen, B.vlen), "trips");
+    e = e ? e : chk(up(h, (int32_t*)D.q_begin, B.q_begin), "queues");
+    e = e ? e : chk(up(h, (int32_t*)D.q_veh, B.q_veh), "queues");
+    e = e ? e : chk(up(h, h->d_lane_ext, B.ext_of_int), "lanes");
+    if (e) {
+        delete h;
+        return e;
+    }
+    // initial state: every vehicle waiting at t = 0
+    std::vector<int32_t> st(B.N, TSIM_WAITING), lane(B.N, -1), rpos(B.N, 0), fs(B.N, -1);
+    std::vector<float> xz(B.N, 0.f), vz(B.N, 0.f);
+    std::vector<int32_t> zero_nj(B.NJ, 0);
+    rc = upload_state(h, 0, st.data(), lane.data(), rpos.data(), xz.data(), vz.data(), fs.data(), B.junc_policy.data(),
+                      zero_nj.data());
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return TSIM_OK;
+}
+
+int tsim_step(tsim_handle* h, int32_t n_steps)
+{
+    if (!h || n_steps < 0) return fail(nullptr, TSIM_EINVAL, "bad handle or step count");
+    for (int s = 0; s < n_steps; ++s) {
+        HIPCHK(h, launch_prepare(h->D, h->stream));
+        HIPCHK(h, launch_update(h->D, h->stream));
+    }
+    return TSIM_OK;
+}
+
+int tsim_set_signal_phases(tsim_handle* h, const int32_t* junction_ids, const int32_t* phase_index, int32_t n)
+{
+    if (!h || n < 0 || (n && (!junction_ids || !phase_index))) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    if (n == 0) return TSIM_OK;
+    Build& B = h->B;
+    if (n > B.NJ) return fail(&h->err, TSIM_EINVAL, "more updates than junctions");
+    for (int c = 0; c < n; ++c) {
+        const int j = junction_ids[c];
+        if (j < 0 || j >= B.NJ) return fail(&h->err, TSIM_EINVAL, "junction id out of range");
+        const int np = B.junc_phase_begin[j + 1] - B.junc_phase_begin[j];
+        if (phase_index[c] < 0 || phase_index[c] >= np) return fail(&h->err, TSIM_EINVAL, "phase index out of range");
+    }
+    HIPCHK(h, hipMemcpyAsync(h->d_io_ph, junction_ids, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_io_ph + B.NJ, phase_index, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_set_phases(h->D, h->d_io_ph, h->d_io_ph + B.NJ, n, h->stream));
+    // the host arrays may be reused as soon as the copies have been consumed
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_get_metrics(tsim_handle* h, tsim_metrics* out)
+{
+    if (!h || !out) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    DevMetrics M;
+    HIPCHK(h, hipMemcpyAsync(&M, h->D.met, sizeof(M), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->step = M.step;
+    out->n_waiting = h->B.N - M.departed;
+    out->n_active = M.departed - M.finished;
+    out->n_finished = M.finished;
+    out->sum_travel_time = (double)M.sum_tt_fx / kTimeFx;
+    out->att = M.finished > 0 ? out->sum_travel_time / (double)M.finished : 0.0;
+    out->mean_speed_last = M.mean_speed_last;
+    out->mean_speed_avg = M.speed_steps > 0 ? M.speed_acc / (double)M.speed_steps : 0.0;
+    out->vehicle_steps = M.vehicle_steps;
+    out->lane_changes = M.lane_changes;
+    out->transfers = M.transfers;
+    out->clamps = M.clamps;
+    out->feeder_blocks = M.feeder_blocks;
+    out->departures = M.dep_events;
+    out->speed_steps = M.speed_steps;
+    out->errors = M.errors;
+    return M.errors ? TSIM_ESTATE : TSIM_OK;
+}
+
+int tsim_get_road_mean_speed(tsim_handle* h, float* out, int32_t n_roads)
+{
+    if (!h || !out || n_roads != h->B.R) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    HIPCHK(h, hipMemcpyAsync(out, h->D.road_speed, (size_t)n_roads * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_get_lane_waiting_counts(tsim_handle* h, int32_t* out, int32_t n_lanes)
+{
+    if (!h || !out || n_lanes != h->B.NL) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    std::vector<int32_t> tmp(n_lanes);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->D.lane_wait, (size_t)n_lanes * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int m = 0; m < n_lanes; ++m) out[h->B.ext_of_int[m]] = tmp[m];
+    return TSIM_OK;
+}
+
+static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<float>& x, std::vector<float>& v,
+                        std::vector<int32_t>& rpos, std::vector<int32_t>& rank)
+{
+    const int N = h->B.N;
+    if (N == 0) return TSIM_OK;
+    HIPCHK(h, hipMemsetAsync(h->d_io_i0, 0xFF, (size_t)N * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->d_io_f0, 0, (size_t)N * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->d_io_f1, 0, (size_t)N * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->d_io_i1, 0, (size_t)N * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->d_io_i2, 0, (size_t)N * 4, h->stream));
+    HIPCHK(h, launch_export(h->D, h->d_lane_ext, h->d_io_i0, h->d_io_f0, h->d_io_f1, h->d_io_i1, h->d_io_i2, h->stream));
+    lane.resize(N);
+    x.resize(N);
+    v.resize(N);
+    rpos.resize(N);
+    rank.resize(N);
+    HIPCHK(h, hipMemcpyAsync(lane.data(), h->d_io_i0, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(x.data(), h->d_io_f0, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(v.data(), h->d_io_f1, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(rpos.data(), h->d_io_i1, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(rank.data(), h->d_io_i2, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_get_lane_order(tsim_handle* h, int32_t* offsets, int32_t* vehicle_ids, int32_t n_lanes, int32_t max_ids)
+{
+    if (!h || !offsets || !vehicle_ids || n_lanes != h->B.NL) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    std::vector<int32_t> lane, rpos, rank;
+    std::vector<float> x, v;
+    int rc = export_state(h, lane, x, v, rpos, rank);
+    if (rc) return rc;
+    std::vector<int32_t> cnt(n_lanes + 1, 0);
+    for (int i = 0; i < h->B.N; ++i)
+        if (lane[i] >= 0) cnt[lane[i] + 1]++;
+    for (int m = 0; m < n_lanes; ++m) cnt[m + 1] += cnt[m];
+    if (cnt[n_lanes] > max_ids) return fail(&h->err, TSIM_EINVAL, "vehicle_ids too small");
+    for (int m = 0; m <= n_lanes; ++m) offsets[m] = cnt[m];
+    for (int i = 0; i < h->B.N; ++i)
+        if (lane[i] >= 0) {
+            const int pos = cnt[lane[i]] + rank[i];
+            if (pos >= cnt[lane[i] + 1]) return fail(&h->err, TSIM_ESTATE, "inconsistent lane order");
+            vehicle_ids[pos] = i;
+        }
+    return TSIM_OK;
+}
+
+int tsim_get_state(tsim_handle* h, tsim_state_host* out)
+{
+    if (!h || !out || !out->status || !out->lane || !out->route_pos || !out->x || !out->v || !out->finish_step ||
+        !out->junc_policy || !out->junc_phase)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const int N = h->B.N;
+    std::vector<int32_t> lane, rpos, rank;
+    std::vector<float> x, v;
+    int rc = export_state(h, lane, x, v, rpos, rank);
+    if (rc) return rc;
+    DevMetrics M;
+    HIPCHK(h, hipMemcpyAsync(out->status, h->D.status, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out->finish_step, h->D.finish_step, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out->junc_policy, h->D.junc_policy, (size_t)h->B.NJ * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out->junc_phase, h->D.junc_manual, (size_t)h->B.NJ * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&M, h->D.met, sizeof(M), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    out->step = M.step;
+    for (int i = 0; i < N; ++i) {
+        const bool act = out->status[i] == TSIM_ACTIVE;
+        out->lane[i] = act ? lane[i] : -1;
+        out->x[i] = act ? x[i] : 0.0f;
+        out->v[i] = act ? v[i] : 0.0f;
+        out->route_pos[i] = act ? rpos[i] : (out->status[i] == TSIM_WAITING ? 0 : h->B.route_begin[i + 1] - h->B.route_begin[i] - 1);
+    }
+    return TSIM_OK;
+}
+
+int tsim_set_state(tsim_handle* h, const tsim_state_host* in)
+{
+    if (!h || !in || !in->status || !in->lane || !in->route_pos || !in->x || !in->v || !in->finish_step ||
+        !in->junc_policy || !in->junc_phase || in->step < 0)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    for (int j = 0; j < h->B.NJ; ++j) {
+        if (in->junc_policy[j] < 0 || in->junc_policy[j] > 2) return fail(&h->err, TSIM_EINVAL, "bad policy");
+        const int np = h->B.junc_phase_begin[j + 1] - h->B.junc_phase_begin[j];
+        if (in->junc_policy[j] == TSIM_POLICY_MANUAL && (in->junc_phase[j] < 0 || in->junc_phase[j] >= np))
+            return fail(&h->err, TSIM_EINVAL, "manual phase out of range");
+    }
+    return upload_state(h, in->step, in->status, in->lane, in->route_pos, in->x, in->v, in->finish_step, in->junc_policy,
+                        in->junc_phase);
+}
+
+int tsim_destroy(tsim_handle* h)
+{
+    if (!h) return fail(nullptr, TSIM_EINVAL, "null handle");
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return TSIM_OK;
+}
+
+const char* tsim_last_error(const tsim_handle* h)
+{
+    if (h && !h->err.empty()) return h->err.c_str();
+    return g_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal device layout of the gfx950 stepper (not part of the C ABI).
+//
+// Vehicles live in lane slabs: every lane owns a fixed-capacity run of
+// 32-byte records, front vehicle first.  Two slab buffers alternate by step
+// parity: step t reads buffer t&1 (the snapshot of Section 3.1's two-phase
+// process) and writes buffer (t+1)&1, so no vehicle ever reads a value written
+// in the same step.  A lane's capacity follows from the no-overlap invariant:
+// floor(length / shortest vehicle) + 2.
+//
+// Work is organised by road tiles: tile r holds the road lanes of road r
+// followed by the junction lanes that leave it, so every lane change and every
+// road-to-junction transfer stays inside one tile; only junction-to-road
+// transfers cross tiles, through a one-record inbox per road lane that the
+// next prepare kernel appends at the lane rear.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsim {
+
+constexpr int kMaxTileLanes = 64;    // road lanes + junction lanes of one road
+constexpr int kMaxRoadLanes = 32;
+constexpr int kMaxPhases = 32;
+constexpr int kWave = 64;
+constexpr int kChangerCap = 128;     // lane changers per tile kept in LDS
+constexpr int kMergeCap = 128;       // merging vehicles per tile kept in LDS
+constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
+constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
+constexpr int kWaitSpeedFlag = 0;
+
+struct __align__(16) VehRec {
+    float x;      // front-bumper coordinate along the lane
+    float v;      // speed
+    int32_t vid;  // vehicle id
+    float len;    // vehicle length
+    float f;      // desired-speed factor (v0 = f * lane limit)
+    int32_t rp;   // index into the route array of the current road
+    int32_t rem;  // roads of the route after the current one
+    int32_t nr;   // next road of the route, -1 on the last road
+};
+
+struct KParams {
+    float dt, T, a_max, s0, delta, p, a_th, b_safe, p_max, p_min, a_emerg;
+    float inv_2sqrt_ab;  // 1 / (2 sqrt(a_max b_comf))
+    float reach;         // a_max dt^2 / 2
+    double dt_d;
+    uint32_t key0, key1; // Philox key
+    int delta_is_4;
+};
+
+// cumulative metrics, folded once per step by the last workgroup of the
+// update kernel
+struct DevMetrics {
+    long long step;
+    long long departed;
+    long long finished;
+    long long sum_tt_fx;
+    long long vehicle_steps;
+    long long lane_changes;
+    long long transfers;
+    long long clamps;
+    long long feeder_blocks;
+    long long errors;
+    long long speed_steps;
+    long long dep_events;    // departures since create / set_state
+    double speed_acc;
+    double mean_speed_last;
+};
+
+// per-workgroup partial sums of one step
+struct WGPartial {
+    long long sumv_fx, cnt, active, changes, transfers, clamps, feeder_blocks, finished, sum_tt_fx, errors;
+};
+
+struct DevNet {
+    int32_t R, NJ, NL, N, G;     // roads, junctions, lanes, vehicles, update grid size
+    // tiles
+    const int32_t* tile_lane_begin;  // [R+1]
+    const int32_t* tile_n_road;      // [R]
+    const int32_t* tile_order;       // [R]
+    // lanes (internal ids)
+    const float* lane_len;
+    const float* lane_lim;
+    const uint32_t* lane_base;
+    const int32_t* lane_cap;
+    const int32_t* lane_tile;        // tile (road) owning the lane
+    const int32_t* lane_local;       // index within its tile
+    const int32_t* jl_out;           // out lane (internal) of a junction lane, -1 for road lanes
+    const int32_t* jl_junc;          // junction of a junction lane
+    const uint32_t* jl_green_mask;   // phases (bit index) in which it is green
+    const int32_t* jl_ext;           // external junction-lane index (feeder priority)
+    const int32_t* jl_in_local;      // local index of its in lane within the tile
+    const int32_t* jl_out_road;      // road of its out lane
+    const int32_t* out_begin;        // [NL+1] junction lanes leaving a road lane
+    const int32_t* out_jl;
+    const int32_t* feed_begin;       // [NL+1] junction lanes entering a road lane, by external id
+    const int32_t* feed_jl;
+    // junctions
+    const int32_t* junc_phase_begin; // [NJ+1]
+    const float* phase_dur;
+    const double* junc_cycle;
+    int32_t* junc_policy;
+    int32_t* junc_manual;
+    int32_t* junc_cur;               // phase index of the current step, -1 = all green
+    // vehicles
+    const float* tau;
+    const int32_t* route_begin;
+    const int32_t* route;
+    const float* vf;
+    const float* vlen;
+    int32_t* status;
+    int32_t* finish_step;
+    const int32_t* q_begin;          // [R+1] departure queue of each origin road
+    const int32_t* q_veh;
+    int32_t* q_head;
+    // slabs
+    VehRec* slab0;
+    VehRec* slab1;
+    int32_t* cnt0;
+    int32_t* cnt1;
+    VehRec* inbox;                   // [NL]
+    int32_t* inbox_flag;             // [NL]
+    // per-slot scratch of the update kernel (indexed like the read slab)
+    uint32_t* sh_gmask;
+    float* sh_aown;
+    int32_t* sh_merge;               // local index of the merge target lane, -1 none
+    float* sh_lrear;                 // own leader's rear (lane coordinate), +inf none
+    float* sh_lv;
+    float* sh_nx;
+    float* sh_nv;
+    int32_t* sh_kind;                // 0 stay, 1 change, 2 enter junction lane, 3 leave tile, 4 finished
+    int32_t* sh_nlane;               // local index of the new lane
+    int32_t* sh_pref;                // stayer prefix count within the tile enumeration
+    // metrics
+    float* road_speed;               // [R] mean speed of the last step, -1 empty
+    int32_t* lane_wait;              // [NL] (internal ids)
+    WGPartial* part;                 // [G]
+    unsigned int* done_ctr;
+    DevMetrics* met;
+    KParams P;
+};
+
+}  // namespace tsim

@@ -1,0 +1,229 @@
+"""Python binding of the C ABI in ``include/tsim.h`` (argument marshalling only).
+
+Every step of the simulation runs in the HIP library ``libtsim.so``; torch only
+provides the device arena (one uint8 tensor) and the HIP stream.  Importing
+this module never falls back to any other implementation: when the library is
+missing or no GPU is present, the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsim.so")
+
+TSIM_OK, TSIM_EINVAL, TSIM_ENOMEM, TSIM_EDEVICE, TSIM_ESTATE = 0, -1, -2, -3, -4
+WAITING, ACTIVE, FINISHED = 0, 1, 2
+
+
+class TsimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tsim error {code}: {msg}")
+        self.code = code
+
+
+class tsim_network(C.Structure):
+    _fields_ = [("n_junctions", C.c_int32), ("n_roads", C.c_int32),
+                ("road_from", C.c_void_p), ("road_to", C.c_void_p), ("road_lane_begin", C.c_void_p),
+                ("road_length", C.c_void_p), ("road_limit", C.c_void_p),
+                ("n_jlanes", C.c_int32),
+                ("jl_in_lane", C.c_void_p), ("jl_out_lane", C.c_void_p), ("jl_length", C.c_void_p),
+                ("jl_limit", C.c_void_p), ("junc_phase_begin", C.c_void_p), ("phase_duration", C.c_void_p),
+                ("phase_green_begin", C.c_void_p), ("phase_green_jl", C.c_void_p), ("junc_policy", C.c_void_p)]
+
+
+class tsim_trips(C.Structure):
+    _fields_ = [("n_vehicles", C.c_int32), ("depart_time", C.c_void_p), ("route_begin", C.c_void_p),
+                ("route_roads", C.c_void_p), ("v0_factor", C.c_void_p), ("length", C.c_void_p)]
+
+
+class tsim_params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("dt", "T", "a_max", "b_comf", "s0", "delta", "politeness", "a_th",
+                                           "b_safe", "p_max", "p_min", "a_emerg")] + [("seed", C.c_uint64)]
+
+
+class tsim_metrics(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_waiting", C.c_int64), ("n_active", C.c_int64), ("n_finished", C.c_int64),
+                ("sum_travel_time", C.c_double), ("att", C.c_double), ("mean_speed_last", C.c_double),
+                ("mean_speed_avg", C.c_double), ("vehicle_steps", C.c_int64), ("lane_changes", C.c_int64),
+                ("transfers", C.c_int64), ("clamps", C.c_int64), ("feeder_blocks", C.c_int64),
+                ("departures", C.c_int64), ("speed_steps", C.c_int64), ("errors", C.c_int64)]
+
+
+class tsim_state_host(C.Structure):
+    _fields_ = [("step", C.c_int64), ("status", C.c_void_p), ("lane", C.c_void_p), ("route_pos", C.c_void_p),
+                ("x", C.c_void_p), ("v", C.c_void_p), ("finish_step", C.c_void_p), ("junc_policy", C.c_void_p),
+                ("junc_phase", C.c_void_p)]
+
+
+_lib = None
+
+EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases", "tsim_get_metrics",
+           "tsim_get_road_mean_speed", "tsim_get_lane_waiting_counts", "tsim_get_lane_order", "tsim_get_state",
+           "tsim_set_state", "tsim_destroy", "tsim_last_error"]
+
+
+def lib():
+    """Loads libtsim.so (built by ``paper_2406_10661_amd.build``); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2406_10661_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.tsim_footprint.argtypes = [P, P, P, C.POINTER(C.c_size_t)]
+        L.tsim_create.argtypes = [P, P, P, P, P, C.c_size_t, C.POINTER(C.c_void_p)]
+        L.tsim_step.argtypes = [P, C.c_int32]
+        L.tsim_set_signal_phases.argtypes = [P, P, P, C.c_int32]
+        L.tsim_get_metrics.argtypes = [P, P]
+        L.tsim_get_road_mean_speed.argtypes = [P, P, C.c_int32]
+        L.tsim_get_lane_waiting_counts.argtypes = [P, P, C.c_int32]
+        L.tsim_get_lane_order.argtypes = [P, P, P, C.c_int32, C.c_int32]
+        L.tsim_get_state.argtypes = [P, P]
+        L.tsim_set_state.argtypes = [P, P]
+        L.tsim_destroy.argtypes = [P]
+        L.tsim_last_error.argtypes = [P]
+        L.tsim_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            getattr(L, name).restype = C.c_int if name != "tsim_last_error" else C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _Inputs:
+    """Keeps the contiguous host arrays alive while a C structure points at them."""
+
+    def __init__(self, net, trips, params):
+        i32 = lambda a: np.ascontiguousarray(a, np.int32)
+        f32 = lambda a: np.ascontiguousarray(a, np.float32)
+        self.arrays = dict(
+            road_from=i32(net.road_from), road_to=i32(net.road_to), road_lane_begin=i32(net.road_lane_begin),
+            road_length=f32(net.road_length), road_limit=f32(net.road_limit), jl_in_lane=i32(net.jl_in_lane),
+            jl_out_lane=i32(net.jl_out_lane), jl_length=f32(net.jl_length), jl_limit=f32(net.jl_limit),
+            junc_phase_begin=i32(net.junc_phase_begin), phase_duration=f32(net.phase_duration),
+            phase_green_begin=i32(net.phase_green_begin), phase_green_jl=i32(net.phase_green_jl),
+            junc_policy=i32(net.junc_policy), depart_time=f32(trips.depart_time),
+            route_begin=i32(trips.route_begin), route_roads=i32(trips.route_roads),
+            v0_factor=f32(trips.v0_factor), length=f32(trips.length))
+        a = self.arrays
+        self.net = tsim_network(net.n_junctions, net.n_roads, *[_p(a[k]) for k in (
+            "road_from", "road_to", "road_lane_begin", "road_length", "road_limit")], net.n_jlanes,
+            *[_p(a[k]) for k in ("jl_in_lane", "jl_out_lane", "jl_length", "jl_limit", "junc_phase_begin",
+                                 "phase_duration", "phase_green_begin", "phase_green_jl", "junc_policy")])
+        self.trips = tsim_trips(trips.n_vehicles, *[_p(a[k]) for k in (
+            "depart_time", "route_begin", "route_roads", "v0_factor", "length")])
+        self.params = tsim_params(params.dt, params.T, params.a_max, params.b_comf, params.s0, params.delta,
+                                  params.politeness, params.a_th, params.b_safe, params.p_max, params.p_min,
+                                  params.a_emerg, int(params.seed))
+
+
+def _check(rc, h=None):
+    if rc != TSIM_OK:
+        msg = lib().tsim_last_error(h)
+        raise TsimError(rc, msg.decode() if msg else "")
+
+
+def footprint(net, trips, params):
+    ins = _Inputs(net, trips, params)
+    n = C.c_size_t(0)
+    _check(lib().tsim_footprint(C.byref(ins.net), C.byref(ins.trips), C.byref(ins.params), C.byref(n)))
+    return int(n.value)
+
+
+class Sim:
+    """One simulation instance resident in GPU memory."""
+
+    def __init__(self, net, trips, params, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("tsim needs a GPU: torch.cuda.is_available() is False")
+        self.net, self.trips, self.params = net, trips, params
+        self.N = trips.n_vehicles
+        self.R = net.n_roads
+        self.NL = net.n_lanes
+        self.NJ = net.n_junctions
+        ins = _Inputs(net, trips, params)
+        nbytes = C.c_size_t(0)
+        _check(lib().tsim_footprint(C.byref(ins.net), C.byref(ins.trips), C.byref(ins.params), C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().tsim_create(C.byref(ins.net), C.byref(ins.trips), C.byref(ins.params),
+                                 C.c_void_p(self.stream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
+                                 C.c_size_t(self.arena.numel()), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tsim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(lib().tsim_step(self.h, int(n)), self.h)
+
+    def set_signal_phases(self, junctions, phases):
+        j = np.ascontiguousarray(junctions, np.int32)
+        p = np.ascontiguousarray(phases, np.int32)
+        _check(lib().tsim_set_signal_phases(self.h, _p(j), _p(p), int(j.size)), self.h)
+
+    def metrics(self, check=True):
+        m = tsim_metrics()
+        rc = lib().tsim_get_metrics(self.h, C.byref(m))
+        if check:
+            _check(rc, self.h)
+        return {k: getattr(m, k) for k, _ in tsim_metrics._fields_}
+
+    def road_mean_speed(self):
+        out = np.zeros(self.R, np.float32)
+        _check(lib().tsim_get_road_mean_speed(self.h, _p(out), self.R), self.h)
+        return out
+
+    def lane_waiting_counts(self):
+        out = np.zeros(self.NL, np.int32)
+        _check(lib().tsim_get_lane_waiting_counts(self.h, _p(out), self.NL), self.h)
+        return out
+
+    def lane_order(self):
+        off = np.zeros(self.NL + 1, np.int32)
+        ids = np.zeros(max(self.N, 1), np.int32)
+        _check(lib().tsim_get_lane_order(self.h, _p(off), _p(ids), self.NL, ids.size), self.h)
+        return off, ids[:off[-1]]
+
+    def get_state(self):
+        N, NJ = self.N, self.NJ
+        st = dict(status=np.zeros(N, np.int32), lane=np.zeros(N, np.int32), route_pos=np.zeros(N, np.int32),
+                  x=np.zeros(N, np.float32), v=np.zeros(N, np.float32), finish_step=np.zeros(N, np.int32),
+                  junc_policy=np.zeros(NJ, np.int32), junc_phase=np.zeros(NJ, np.int32))
+        s = tsim_state_host(0, *[_p(st[k]) for k in ("status", "lane", "route_pos", "x", "v", "finish_step",
+                                                       "junc_policy", "junc_phase")])
+        _check(lib().tsim_get_state(self.h, C.byref(s)), self.h)
+        st["step"] = int(s.step)
+        return st
+
+    def set_state(self, st):
+        N, NJ = self.N, self.NJ
+        a = dict(status=np.ascontiguousarray(st["status"], np.int32),
+                 lane=np.ascontiguousarray(st["lane"], np.int32),
+                 route_pos=np.ascontiguousarray(st["route_pos"], np.int32),
+                 x=np.ascontiguousarray(st["x"], np.float32), v=np.ascontiguousarray(st["v"], np.float32),
+                 finish_step=np.ascontiguousarray(st["finish_step"], np.int32),
+                 junc_policy=np.ascontiguousarray(st.get("junc_policy", self.net.junc_policy), np.int32),
+                 junc_phase=np.ascontiguousarray(st.get("junc_phase", np.zeros(NJ, np.int32)), np.int32))
+        s = tsim_state_host(int(st["step"]), *[_p(a[k]) for k in ("status", "lane", "route_pos", "x", "v",
+                                                                   "finish_step", "junc_policy", "junc_phase")])
+        _check(lib().tsim_set_state(self.h, C.byref(s)), self.h)

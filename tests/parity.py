@@ -1,0 +1,146 @@
+"""One-step GPU-vs-oracle comparison used by the parity tests.
+
+Both sides start from the same state (positions and speeds as float32), take
+one step, and are compared vehicle by vehicle:
+  * decisions (status, lane, route position, departure) must be identical,
+    except where the oracle reports a near-threshold margin for that vehicle
+    (|Delta a - a_th|, |a~_new + b_safe|, gap margins, |r - boundary|,
+    |x' - bound| or |x' - lane end|, departure room) -- such cases are counted
+    and returned;
+  * where the decision matches, x' and v' agree within
+    |d| <= 1e-5 * max(|ref|, scale), scale = lane length for x and the
+    desired speed for v;
+  * per-lane vehicle order (the sensing index) identical on lanes without a
+    near-threshold vehicle;
+  * lane waiting counts and road mean speeds identical / within tolerance
+    away from near cases.
+"""
+
+import numpy as np
+
+REL = 1e-5
+EPS_ACC = 1e-4       # m/s^2
+EPS_POS_ABS = 1e-4   # m
+
+
+def pos_eps(lane_len):
+    # float32 positions carry about 8e-8 relative error per operation
+    return np.maximum(EPS_POS_ABS, 2e-6 * lane_len)
+
+
+def oracle_one_step(O, net, trips, params, st):
+    o = O.OracleSim(net, trips, params)
+    s64 = dict(st)
+    s64["x"] = np.asarray(st["x"], np.float32).astype(np.float64)
+    s64["v"] = np.asarray(st["v"], np.float32).astype(np.float64)
+    o.set_state(s64)
+    if "junc_policy" in st:
+        man = np.nonzero(st["junc_policy"] == 2)[0]
+        if man.size:
+            o.set_signal_phases(man, st["junc_phase"][man])
+        none = np.nonzero(st["junc_policy"] == 0)[0]
+        if none.size:
+            o.set_policy(none, np.zeros(none.size, np.int32))
+    o.step(1)
+    return o
+
+
+def compare_one_step(O, sim_cls, net, trips, params, st, sim=None):
+    """Returns a report dict; raises AssertionError on a parity failure."""
+    o = oracle_one_step(O, net, trips, params, st)
+    ost = o.get_state()
+    od = o.diag()
+    om = o.metrics()
+    g = sim if sim is not None else sim_cls(net, trips, params)
+    g.set_state(st)
+    g.step(1)
+    gst = g.get_state()
+    gm = g.metrics()
+    N = trips.n_vehicles
+    lane_len = np.concatenate([np.repeat(net.road_length, np.diff(net.road_lane_begin)),
+                               net.jl_length]).astype(np.float64)
+    lim = np.concatenate([np.repeat(net.road_limit, np.diff(net.road_lane_begin)), net.jl_limit]).astype(np.float64)
+    m = od["margin"]
+    st_lane = np.asarray(st["lane"])
+    ref_len = np.where(st_lane >= 0, lane_len[np.maximum(st_lane, 0)], 1.0)
+    pe = pos_eps(ref_len)
+    near = ((m[:, 0] < EPS_ACC) | (m[:, 2] < EPS_ACC) | (m[:, 1] < pe) | (m[:, 4] < pe) | (m[:, 5] < pe)
+            | (m[:, 3] < 1e-4 * (params.p_max - params.p_min)))
+    # departures cascade into their lane: a near departure marks its lane's road
+    same = ((gst["status"] == ost["status"]) & (gst["lane"] == ost["lane"]) & (gst["route_pos"] == ost["route_pos"]))
+    bad = ~same & ~near
+    rep = dict(n=N, active=int((ost["status"] == 1).sum()), mismatched=int((~same).sum()),
+               near=int(near.sum()), near_mismatch=int((~same & near).sum()),
+               changes=int(om["lane_changes"]), transfers=int(om["transfers"]),
+               departures=int(om["departures"]))
+    if bad.any():
+        idx = np.nonzero(bad)[0][:10]
+        detail = [(int(i), int(st["status"][i]), int(st_lane[i]), float(st["x"][i]), float(st["v"][i]),
+                   "gpu", int(gst["status"][i]), int(gst["lane"][i]), float(gst["x"][i]),
+                   "ora", int(ost["status"][i]), int(ost["lane"][i]), float(ost["x"][i]),
+                   "dec", int(od["decision"][i]), int(od["event"][i]), m[i].tolist()) for i in idx]
+        raise AssertionError(f"decision mismatch on {int(bad.sum())} vehicles: {detail}")
+    ok = same & (ost["status"] == 1)
+    xl = lane_len[np.maximum(ost["lane"], 0)]
+    vscale = trips.v0_factor.astype(np.float64) * lim[np.maximum(ost["lane"], 0)]
+    dx = np.abs(gst["x"].astype(np.float64) - ost["x"])
+    dv = np.abs(gst["v"].astype(np.float64) - ost["v"])
+    tx = REL * np.maximum(np.abs(ost["x"]), xl)
+    tv = REL * np.maximum(np.abs(ost["v"]), vscale)
+    badx = ok & (dx > tx)
+    badv = ok & (dv > tv)
+    if badx.any() or badv.any():
+        i = int(np.nonzero(badx | badv)[0][0])
+        raise AssertionError(f"value mismatch: {int(badx.sum())} x, {int(badv.sum())} v; e.g. vehicle {i} "
+                             f"x {gst['x'][i]} vs {ost['x'][i]}, v {gst['v'][i]} vs {ost['v'][i]}, "
+                             f"start lane {st_lane[i]} x {st['x'][i]} v {st['v'][i]}")
+    rep["max_rel_dx"] = float(np.max(dx[ok] / np.maximum(np.abs(ost["x"][ok]), xl[ok]), initial=0.0))
+    rep["max_rel_dv"] = float(np.max(dv[ok] / np.maximum(np.abs(ost["v"][ok]), vscale[ok]), initial=0.0))
+    # sensing index: per-lane order
+    off, ids = g.lane_order()
+    act = np.nonzero(ost["status"] == 1)[0]
+    order = act[np.lexsort((act, -ost["x"][act], ost["lane"][act]))]
+    o_lane = ost["lane"][order]
+    NL = net.n_lanes
+    o_off = np.searchsorted(o_lane, np.arange(NL + 1))
+    tainted = np.zeros(NL, bool)
+    nm = np.nonzero(~same | near)[0]
+    for i in nm:
+        for l in (st_lane[i], ost["lane"][i], gst["lane"][i]):
+            if l >= 0:
+                tainted[l] = True
+    diff_lanes = 0
+    for l in np.nonzero(~tainted)[0]:
+        a = ids[off[l]:off[l + 1]]
+        b = order[o_off[l]:o_off[l + 1]]
+        if not np.array_equal(a, b):
+            diff_lanes += 1
+    assert diff_lanes == 0, f"lane order differs on {diff_lanes} lanes"
+    # metrics
+    gw = g.lane_waiting_counts()
+    ow = o.lane_waiting()
+    vnear = np.zeros(NL, bool)
+    vv = np.abs(ost["v"] - 0.1) < 1e-4
+    for i in np.nonzero(vv)[0]:
+        vnear[st_lane[i]] = True
+    wl = ~tainted & ~vnear
+    assert np.array_equal(gw[wl], ow[wl]), "lane waiting counts differ"
+    rs = g.road_mean_speed()
+    osv, oc = o.road_stats()
+    road_t = np.zeros(net.n_roads, bool)
+    rol = net.road_of_lane()
+    for l in np.nonzero(tainted[:net.n_road_lanes])[0]:
+        road_t[rol[l]] = True
+    has = (oc > 0) & ~road_t
+    ors = np.where(oc > 0, osv / np.maximum(oc, 1), -1.0)
+    assert np.all((rs[oc == 0] == -1.0)), "empty roads must report -1"
+    np.testing.assert_allclose(rs[has], ors[has], rtol=1e-5, atol=1e-5 * 20)
+    if rep["near_mismatch"] == 0:
+        for k in ("lane_changes", "transfers", "departures", "feeder_blocks"):
+            assert int(gm[k]) == int(om[k]), (k, gm[k], om[k])
+        assert int(gm["n_finished"]) == int(om["finished"])
+        assert abs(gm["mean_speed_last"] - om["mean_speed_last"]) <= 1e-5 * max(1.0, om["mean_speed_last"])
+    assert gm["errors"] == 0
+    rep["gpu_metrics"] = gm
+    rep["oracle_metrics"] = om
+    return rep

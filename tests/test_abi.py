@@ -1,0 +1,74 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+function the header declares, and rejects malformed inputs in
+tsim_footprint (host-only validation)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2406_10661_amd import workloads as W
+from paper_2406_10661_amd import tsim as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "tsim.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(tsim_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(T.LIB_PATH):
+        from paper_2406_10661_amd import build
+        build.build()
+    return T.lib()
+
+
+def test_header_declarations_exported(L):
+    names = declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(T.EXPORTS)
+
+
+def test_footprint_valid_config1(L):
+    w = W.config1()
+    nb = T.footprint(w.network, w.trips, w.params)
+    assert nb > 0
+
+
+def _broken(mut):
+    w = W.config1()
+    net, trips, params = w.network, w.trips, w.params
+    mut(net, trips, params)
+    return net, trips, params
+
+
+@pytest.mark.parametrize("name,mut", [
+    ("unconnected route", lambda n, t, p: t.route_roads.__setitem__(1, (t.route_roads[0] + 7) % 48)),
+    ("bad road id", lambda n, t, p: t.route_roads.__setitem__(0, 10_000)),
+    ("zero length", lambda n, t, p: t.length.__setitem__(3, 0.0)),
+    ("short lane", lambda n, t, p: n.road_length.__setitem__(5, 10.0)),
+    ("bad policy", lambda n, t, p: n.junc_policy.__setitem__(0, 7)),
+    ("bad dt", lambda n, t, p: setattr(p, "dt", 0.0)),
+    ("foreign phase lane", lambda n, t, p: n.phase_green_jl.__setitem__(0, n.n_jlanes - 1)),
+])
+def test_footprint_rejects(L, name, mut):
+    net, trips, params = _broken(mut)
+    with pytest.raises(T.TsimError) as e:
+        T.footprint(net, trips, params)
+    assert e.value.code == T.TSIM_EINVAL, name
+
+
+def test_no_gpu_fails_loudly(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    w = W.config1()
+    with pytest.raises(RuntimeError):
+        T.Sim(w.network, w.trips, w.params)
