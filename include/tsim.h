@@ -187,6 +187,14 @@ int tsim_get_state(tsim_handle *h, tsim_state_host *out);
  * the running averages and event counters restart from zero. */
 int tsim_set_state(tsim_handle *h, const tsim_state_host *in);
 
+/* Kernel timing for measurement tools.  While enabled, tsim_step brackets
+ * every launch with HIP events on the handle's stream (a small overhead);
+ * tsim_get_kernel_times synchronises and returns, per kernel, the summed
+ * milliseconds and the number of launches since profiling was enabled.
+ * Kernel 0 is the update kernel, kernel 1 the prepare kernel; n_kernels <= 2. */
+int tsim_set_profiling(tsim_handle *h, int32_t enable);
+int tsim_get_kernel_times(tsim_handle *h, double *ms, int64_t *launches, int32_t n_kernels);
+
 int tsim_destroy(tsim_handle *h);
 const char *tsim_last_error(const tsim_handle *h);
 

@@ -298,6 +298,12 @@ struct tsim_handle {
     float* d_io_f1 = nullptr;
     VehRec* d_io_rec = nullptr;      // staging: import records
     int32_t* d_io_ph = nullptr;      // staging: phase updates (2 x NJ)
+    // kernel timing (tsim_set_profiling)
+    bool prof = false;
+    std::vector<hipEvent_t> ev[2];   // start/stop pairs per kernel
+    int ev_used[2] = {0, 0};
+    double ms[2] = {0.0, 0.0};
+    long long launches[2] = {0, 0};
     std::string err;
 };
 
@@ -623,12 +629,78 @@ int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_par
     return TSIM_OK;
 }
 
+namespace {
+constexpr int kEventPairs = 4096;
+
+// sums the recorded event pairs of kernel k into h->ms[k]
+int flush_events(tsim_handle* h, int k)
+{
+    if (h->ev_used[k] == 0) return TSIM_OK;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->ev_used[k]; ++i) {
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, h->ev[k][2 * i], h->ev[k][2 * i + 1]));
+        h->ms[k] += t;
+    }
+    h->launches[k] += h->ev_used[k];
+    h->ev_used[k] = 0;
+    return TSIM_OK;
+}
+
+int timed_launch(tsim_handle* h, int k)
+{
+    if (!h->prof) return (k == 0 ? launch_update(h->D, h->stream) : launch_prepare(h->D, h->stream)) == hipSuccess
+                             ? TSIM_OK
+                             : hip_fail(h, hipGetLastError(), "kernel launch");
+    if (h->ev_used[k] == kEventPairs) {
+        int rc = flush_events(h, k);
+        if (rc) return rc;
+    }
+    if (h->ev[k].empty()) {
+        h->ev[k].resize(2 * kEventPairs);
+        for (auto& e : h->ev[k]) HIPCHK(h, hipEventCreate(&e));
+    }
+    const int i = h->ev_used[k]++;
+    HIPCHK(h, hipEventRecord(h->ev[k][2 * i], h->stream));
+    HIPCHK(h, k == 0 ? launch_update(h->D, h->stream) : launch_prepare(h->D, h->stream));
+    HIPCHK(h, hipEventRecord(h->ev[k][2 * i + 1], h->stream));
+    return TSIM_OK;
+}
+}  // namespace
+
 int tsim_step(tsim_handle* h, int32_t n_steps)
 {
     if (!h || n_steps < 0) return fail(nullptr, TSIM_EINVAL, "bad handle or step count");
     for (int s = 0; s < n_steps; ++s) {
-        HIPCHK(h, launch_prepare(h->D, h->stream));
-        HIPCHK(h, launch_update(h->D, h->stream));
+        int rc = timed_launch(h, 1);
+        if (rc) return rc;
+        rc = timed_launch(h, 0);
+        if (rc) return rc;
+    }
+    return TSIM_OK;
+}
+
+int tsim_set_profiling(tsim_handle* h, int32_t enable)
+{
+    if (!h) return fail(nullptr, TSIM_EINVAL, "null handle");
+    for (int k = 0; k < 2; ++k) {
+        int rc = flush_events(h, k);
+        if (rc) return rc;
+        h->ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    h->prof = enable != 0;
+    return TSIM_OK;
+}
+
+int tsim_get_kernel_times(tsim_handle* h, double* ms, int64_t* launches, int32_t n_kernels)
+{
+    if (!h || !ms || !launches || n_kernels < 1 || n_kernels > 2) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    for (int k = 0; k < n_kernels; ++k) {
+        int rc = flush_events(h, k);
+        if (rc) return rc;
+        ms[k] = h->ms[k];
+        launches[k] = h->launches[k];
     }
     return TSIM_OK;
 }
@@ -791,6 +863,8 @@ int tsim_destroy(tsim_handle* h)
 {
     if (!h) return fail(nullptr, TSIM_EINVAL, "null handle");
     (void)hipStreamSynchronize(h->stream);
+    for (int k = 0; k < 2; ++k)
+        for (auto& e : h->ev[k]) (void)hipEventDestroy(e);
     delete h;
     return TSIM_OK;
 }

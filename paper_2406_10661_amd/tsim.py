@@ -64,7 +64,7 @@ _lib = None
 
 EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases", "tsim_get_metrics",
            "tsim_get_road_mean_speed", "tsim_get_lane_waiting_counts", "tsim_get_lane_order", "tsim_get_state",
-           "tsim_set_state", "tsim_destroy", "tsim_last_error"]
+           "tsim_set_state", "tsim_set_profiling", "tsim_get_kernel_times", "tsim_destroy", "tsim_last_error"]
 
 
 def lib():
@@ -85,6 +85,8 @@ def lib():
         L.tsim_get_lane_order.argtypes = [P, P, P, C.c_int32, C.c_int32]
         L.tsim_get_state.argtypes = [P, P]
         L.tsim_set_state.argtypes = [P, P]
+        L.tsim_set_profiling.argtypes = [P, C.c_int32]
+        L.tsim_get_kernel_times.argtypes = [P, P, P, C.c_int32]
         L.tsim_destroy.argtypes = [P]
         L.tsim_last_error.argtypes = [P]
         L.tsim_last_error.restype = C.c_char_p
@@ -203,6 +205,16 @@ class Sim:
         ids = np.zeros(max(self.N, 1), np.int32)
         _check(lib().tsim_get_lane_order(self.h, _p(off), _p(ids), self.NL, ids.size), self.h)
         return off, ids[:off[-1]]
+
+    def set_profiling(self, enable=True):
+        _check(lib().tsim_set_profiling(self.h, 1 if enable else 0), self.h)
+
+    def kernel_times(self):
+        """{'update': (ms, launches), 'prepare': (ms, launches)} since profiling was enabled."""
+        ms = np.zeros(2, np.float64)
+        n = np.zeros(2, np.int64)
+        _check(lib().tsim_get_kernel_times(self.h, _p(ms), _p(n), 2), self.h)
+        return {"update": (float(ms[0]), int(n[0])), "prepare": (float(ms[1]), int(n[1]))}
 
     def get_state(self):
         N, NJ = self.N, self.NJ

@@ -581,4 +581,84 @@ def ring_road(circumference_road=300.0, n_vehicles=10, laps=50, v0_factor=1.0):
     return net, trips
 
 
+def synthetic_state(net, trips, step, seed, p_active=0.5, p_finished=0.1, p_junction=0.08, min_gap=0.3,
+                    p_standing=0.15):
+    """Seeded mid-simulation state: a fraction of the vehicles sits somewhere
+    along its own route (a road lane of the current road, lane group or not,
+    or a junction lane toward the next road) with uniformly drawn position and
+    speed up to the desired speed; vehicles overlapping the one ahead on their
+    lane are put back to waiting; others wait (some already due) or have
+    finished.  Evaluates nothing of the vehicle model."""
+    rng = np.random.default_rng(seed)
+    N = trips.n_vehicles
+    NRL = net.n_road_lanes
+    rol = net.road_of_lane().astype(np.int64)
+    rb = trips.route_begin.astype(np.int64)
+    rr = trips.route_roads.astype(np.int64)
+    R = net.n_roads
+    lane_len = np.concatenate([np.repeat(net.road_length, np.diff(net.road_lane_begin)),
+                               net.jl_length]).astype(np.float64)
+    lim = np.concatenate([np.repeat(net.road_limit, np.diff(net.road_lane_begin)),
+                          net.jl_limit]).astype(np.float64)
+    # junction lanes grouped by (in road, out road)
+    jkey = rol[net.jl_in_lane] * R + rol[net.jl_out_lane]
+    jorder = np.argsort(jkey, kind="stable")
+    jsorted = jkey[jorder]
+    u = rng.random(N)
+    status = np.zeros(N, np.int32)
+    status[u < p_active] = 1
+    status[(u >= p_active) & (u < p_active + p_finished)] = 2
+    act = np.nonzero(status == 1)[0]
+    rl = rb[act + 1] - rb[act]
+    k = np.minimum((rng.random(act.size) * rl).astype(np.int64), rl - 1)
+    r = rr[rb[act] + k]
+    lane = np.full(N, -1, np.int64)
+    lb = net.road_lane_begin[r].astype(np.int64)
+    nl = net.road_lane_begin[r + 1].astype(np.int64) - lb
+    lane_a = lb + np.minimum((rng.random(act.size) * nl).astype(np.int64), nl - 1)
+    to_jl = (k + 1 < rl) & (rng.random(act.size) < p_junction)
+    if to_jl.any():
+        ji = np.nonzero(to_jl)[0]
+        key = r[ji] * R + rr[rb[act[ji]] + k[ji] + 1]
+        lo = np.searchsorted(jsorted, key, "left")
+        hi = np.searchsorted(jsorted, key, "right")
+        pick = lo + np.minimum((rng.random(ji.size) * (hi - lo)).astype(np.int64), hi - lo - 1)
+        lane_a[ji] = NRL + jorder[pick]
+    lane[act] = lane_a
+    route_pos = np.zeros(N, np.int64)
+    route_pos[act] = k
+    x = np.zeros(N, np.float64)
+    x[act] = rng.random(act.size) * lane_len[lane_a]
+    gap = min_gap * (1.0 + rng.random(N))
+    L = trips.length.astype(np.float64)
+    # drop vehicles that overlap the vehicle ahead on their lane until none do
+    alive = act.copy()
+    while alive.size:
+        o = alive[np.lexsort((alive, -x[alive], lane[alive]))]
+        same = np.zeros(o.size, bool)
+        same[1:] = lane[o[1:]] == lane[o[:-1]]
+        prev_rear = np.full(o.size, np.inf)
+        prev_rear[1:] = x[o[:-1]] - L[o[:-1]]
+        bad = same & (x[o] > prev_rear - gap[o])
+        if not bad.any():
+            break
+        # drop every vehicle that overlaps its current predecessor
+        drop = o[bad]
+        status[drop] = 0
+        alive = np.setdiff1d(alive, drop)
+    lane[status != 1] = -1
+    route_pos[status != 1] = 0
+    x[status != 1] = 0.0
+    v = np.zeros(N, np.float64)
+    a2 = np.nonzero(status == 1)[0]
+    v[a2] = rng.random(a2.size) * trips.v0_factor[a2] * lim[lane[a2]]
+    v[a2[rng.random(a2.size) < p_standing]] = 0.0
+    finish = np.full(N, -1, np.int64)
+    fin = np.nonzero(status == 2)[0]
+    finish[fin] = rng.integers(0, max(step, 1), fin.size)
+    route_pos[fin] = rb[fin + 1] - rb[fin] - 1
+    return dict(step=int(step), status=status, lane=lane.astype(np.int32), route_pos=route_pos.astype(np.int32),
+                x=x.astype(np.float32), v=v.astype(np.float32), finish_step=finish.astype(np.int32))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3}
