@@ -583,8 +583,8 @@ def ring_road(circumference_road=300.0, n_vehicles=10, laps=50, v0_factor=1.0):
 
 def synthetic_state(net, trips, step, seed, p_active=0.5, p_finished=0.1, p_junction=0.08, min_gap=0.3,
                     p_standing=0.15):
-    """Seeded mid-simulation state: a fraction of the vehicles sits somewhere
-    along its own route (a road lane of the current road, lane group or not,
+    """Seeded mid-simulation state at time step*dt (dt = 1 s): among vehicles
+    already due to depart, a fraction sits somewhere along its own route (a road lane of the current road, lane group or not,
     or a junction lane toward the next road) with uniformly drawn position and
     speed up to the desired speed; vehicles overlapping the one ahead on their
     lane are put back to waiting; others wait (some already due) or have
@@ -606,8 +606,9 @@ def synthetic_state(net, trips, step, seed, p_active=0.5, p_finished=0.1, p_junc
     jsorted = jkey[jorder]
     u = rng.random(N)
     status = np.zeros(N, np.int32)
-    status[u < p_active] = 1
-    status[(u >= p_active) & (u < p_active + p_finished)] = 2
+    due = trips.depart_time.astype(np.float64) <= step * 1.0
+    status[(u < p_active) & due] = 1
+    status[(u >= p_active) & (u < p_active + p_finished) & due] = 2
     act = np.nonzero(status == 1)[0]
     rl = rb[act + 1] - rb[act]
     k = np.minimum((rng.random(act.size) * rl).astype(np.int64), rl - 1)
@@ -655,7 +656,8 @@ def synthetic_state(net, trips, step, seed, p_active=0.5, p_finished=0.1, p_junc
     v[a2[rng.random(a2.size) < p_standing]] = 0.0
     finish = np.full(N, -1, np.int64)
     fin = np.nonzero(status == 2)[0]
-    finish[fin] = rng.integers(0, max(step, 1), fin.size)
+    lo = np.ceil(trips.depart_time[fin].astype(np.float64)).astype(np.int64)
+    finish[fin] = lo + (rng.random(fin.size) * np.maximum(step - lo, 1)).astype(np.int64)
     route_pos[fin] = rb[fin + 1] - rb[fin] - 1
     return dict(step=int(step), status=status, lane=lane.astype(np.int32), route_pos=route_pos.astype(np.int32),
                 x=x.astype(np.float32), v=v.astype(np.float32), finish_step=finish.astype(np.int32))

@@ -109,13 +109,15 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None):
         for l in (st_lane[i], ost["lane"][i], gst["lane"][i]):
             if l >= 0:
                 tainted[l] = True
-    diff_lanes = 0
-    for l in np.nonzero(~tainted)[0]:
-        a = ids[off[l]:off[l + 1]]
-        b = order[o_off[l]:o_off[l + 1]]
-        if not np.array_equal(a, b):
-            diff_lanes += 1
-    assert diff_lanes == 0, f"lane order differs on {diff_lanes} lanes"
+    g_cnt = np.diff(off)
+    o_cnt = np.diff(o_off)
+    clean = ~tainted
+    assert np.array_equal(g_cnt[clean], o_cnt[clean]), "lane occupancy differs"
+    g_lane_of = np.repeat(np.arange(NL), g_cnt)
+    o_lane_of = np.repeat(np.arange(NL), o_cnt)
+    ga = ids[clean[g_lane_of]]
+    ob = order[clean[o_lane_of]]
+    assert np.array_equal(ga, ob), f"lane order differs on {int((ga != ob).sum())} positions"
     # metrics
     gw = g.lane_waiting_counts()
     ow = o.lane_waiting()

@@ -126,3 +126,46 @@ def test_determinism_and_invariants(Sim):
     sb = b.get_state()
     for k in ("status", "lane", "route_pos", "x", "v", "finish_step"):
         assert np.array_equal(prev[k], sb[k]), k
+
+
+@pytest.fixture(scope="module")
+def city():
+    return W.config3()
+
+
+@pytest.mark.timeout(900)
+def test_c2_full_size_one_step(O, Sim):
+    w = W.config2()
+    st = W.synthetic_state(w.network, w.trips, 1200, seed=21, p_active=0.6)
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st)
+    _log("c2_full_synth_t1200", rep)
+    assert rep["active"] > 30000
+
+
+@pytest.mark.timeout(900)
+def test_c3_full_size_one_step(O, Sim, city):
+    """The paper-scale city (2,464,950 vehicles) in the bench's launch
+    configuration: one step from a synthetic state with ~1M active vehicles."""
+    st = W.synthetic_state(city.network, city.trips, 3600, seed=31, p_active=0.5)
+    rep = compare_one_step(O, Sim, city.network, city.trips, city.params, st)
+    _log("c3_full_synth_t3600", rep)
+    assert rep["active"] > 500000
+
+
+@pytest.mark.timeout(900)
+def test_c3_invariants_over_steps(Sim, city):
+    """Properties at full size: I1-I7 after each of 20 GPU steps from a
+    synthetic mid-horizon state."""
+    st = W.synthetic_state(city.network, city.trips, 3600, seed=32, p_active=0.5)
+    g = Sim(city.network, city.trips, city.params)
+    g.set_state(st)
+    info = S.NetInfo(city.network, city.trips)
+    prev = g.get_state()
+    for t in range(3600, 3620):
+        green = S.green_set(city.network, t, 1.0)
+        g.step(1)
+        cur = g.get_state()
+        errs = S.check_state(info, cur) + S.check_transition(info, prev, cur, green)
+        assert not errs, (t, errs)
+        prev = cur
+    assert g.metrics()["errors"] == 0
