@@ -15,6 +15,17 @@ MI355X HBM peak (algorithmic bytes from the state layout: each active
 vehicle's 32-byte record read and written once, plus each lane's count read
 and written), and the CPU oracle's throughput on a bounded sample.
 
+--workload batch: 256 uneven jittered-grid instances (1k-150k vehicles each,
+about 15M in total) stepped together through captured 15-step HIP graphs for
+1,800 steps, with every junction's phase set from a seeded random policy every
+15 steps; the same instances stepped one at a time by the plain stepper on the
+same schedule are the baseline (ratio in "vs_plain_loop").
+
+--workload serve: a Poisson stream (20 jobs/s) of pre-generated jobs (signal
+timing plans or road prices; 10k-500k vehicles; 300-3,600 steps) run by the
+continuous-batching loop of ``paper_2406_10661_amd.serve`` under an HBM
+budget; reports jobs/s, p50/p99 latency and the plain one-job-at-a-time loop.
+
 Prints one JSON line on stdout.
 """
 
@@ -86,19 +97,189 @@ def cpu_baseline(w, seconds=12.0):
             "hz": steps / el}
 
 
+METRIC = "vehicle-steps/s + sim Hz at 2.46M veh; batched jobs/s, p50/p99 job latency"
+
+
+def roofline(alg_bytes, upd_ms, upd_n, traffic):
+    achieved = alg_bytes / (upd_ms / 1e3) / 1e9 if upd_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update",
+            "us_per_launch": upd_ms / max(upd_n, 1) * 1e3, "bytes_per_launch": alg_bytes / max(upd_n, 1)}
+
+
+def run_batch(args):
+    """Batched RL-style stepping of many uneven instances versus the plain
+    per-instance loop on the same phase schedule."""
+    import numpy as np
+    import torch
+    from paper_2406_10661_amd import workloads as W
+    from paper_2406_10661_amd.tsim import Batch, Sim
+    every = 15
+    t0 = time.time()
+    ws = W.batch_workload(args.instances, steps=args.steps)
+    n_chunks = args.steps // every
+    scheds = [W.random_phase_schedule(w.network, w.extra["policy_seed"], n_chunks) for w in ws]
+    allph = [np.concatenate([sc[c] for sc in scheds]) for c in range(n_chunks)]
+    nets, trips, pars = [w.network for w in ws], [w.trips for w in ws], [w.params for w in ws]
+    nveh = sum(w.trips.n_vehicles for w in ws)
+    lanes = sum(w.network.n_lanes for w in ws)
+    log(f"[bench] batch of {len(ws)} instances, {nveh} vehicles, {lanes} lanes, generated in "
+        f"{time.time() - t0:.1f} s")
+
+    def batched(profile):
+        b = Batch(nets, trips, pars)
+        if profile:
+            b.set_profiling(True)
+        else:
+            b.set_graph_steps(every)
+            b.step(0)                      # captures the graph outside the timed region
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        for c in range(n_chunks):
+            b.set_all_phases(allph[c])
+            b.step(every)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kt = b.kernel_times() if profile else None
+        ms_inst = [b.metrics(k) for k in range(len(ws))]
+        log(f"[bench] batched{' (profiled)' if profile else ''}: {n_chunks * every} steps in {ms:.1f} ms")
+        b.close()
+        del b
+        torch.cuda.synchronize()
+        return ms, kt, ms_inst
+
+    _, kt, _ = batched(True)
+    ms_b, _, met_b = batched(False)
+    vs_b = sum(m["vehicle_steps"] for m in met_b)
+
+    # plain loop: one instance at a time, direct launches, same schedule
+    plain_ms = 0.0
+    same = True
+    for k, w in enumerate(ws):
+        sim = Sim(w.network, w.trips, w.params)
+        js = np.arange(w.network.n_junctions, dtype=np.int32)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        for c in range(n_chunks):
+            sim.set_signal_phases(js, scheds[k][c])
+            sim.step(every)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        plain_ms += e0.elapsed_time(e1)
+        m = sim.metrics()
+        same &= (m["vehicle_steps"] == met_b[k]["vehicle_steps"] and m["n_finished"] == met_b[k]["n_finished"]
+                 and m["mean_speed_avg"] == met_b[k]["mean_speed_avg"])
+        sim.close()
+        del sim
+    log(f"[bench] plain loop: {plain_ms:.1f} ms; identical per-instance results: {same}")
+    upd_ms, upd_n = kt["update"]
+    alg = BYTES_PER_ACTIVE * vs_b + BYTES_PER_LANE * lanes * upd_n
+    steps = n_chunks * every
+    out = {
+        "metric": METRIC, "value": vs_b / (ms_b / 1e3), "unit": "vehicle-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "ms_per_step": ms_b / steps, "sim_hz": steps / (ms_b / 1e3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch{len(ws)}_jittered_grids", "instances": len(ws), "vehicles": nveh,
+                   "lanes": lanes, "steps_per_phase_update": every, "launch": "captured 15-step HIP graphs"},
+        "vs_plain_loop": plain_ms / ms_b,
+        "plain_loop": {"value": vs_b / (plain_ms / 1e3), "ms": plain_ms, "identical_results": bool(same)},
+        "roofline": roofline(alg, upd_ms, upd_n, traffic_from_profiles(f"batch{len(ws)}")),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Continuous batching of a Poisson job stream versus the plain loop."""
+    import numpy as np
+    import torch
+    from paper_2406_10661_amd import workloads as W
+    from paper_2406_10661_amd import serve as SV
+    from paper_2406_10661_amd.tsim import Sim
+    t0 = time.time()
+    ws = W.served_jobs(args.jobs)
+    arr = W.poisson_arrivals(args.jobs, rate=args.rate)
+    log(f"[bench] {len(ws)} jobs generated in {time.time() - t0:.1f} s; "
+        f"{sum(w.trips.n_vehicles for w in ws)} vehicles in total")
+    jobs = [SV.Job(jid=k, arrival=float(arr[k]), network=w.network, trips=w.trips, params=w.params,
+                   horizon=w.n_steps) for k, w in enumerate(ws)]
+    fac = SV.GpuFactory(n_streams=args.streams, graph_steps=args.tick)
+    loop = SV.ServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick)
+    res = loop.run(jobs)
+    summ = SV.summarize(res, skip=args.skip)
+    log(f"[bench] served: {json.dumps(summ)}")
+    # plain loop over the measured jobs: one job at a time, direct launches
+    sel = sorted(res["jobs"], key=lambda j: j.arrival)[args.skip:]
+    plain_ms = 0.0
+    vs = 0
+    same = True
+    for j in sel:
+        sim = Sim(j.network, j.trips, j.params)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(j.horizon)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        plain_ms += e0.elapsed_time(e1)
+        m = sim.metrics()
+        vs += m["vehicle_steps"]
+        same &= (m["vehicle_steps"] == j.metrics["vehicle_steps"] and m["n_finished"] == j.metrics["n_finished"])
+        sim.close()
+    plain = vs / (plain_ms / 1e3)
+    log(f"[bench] plain loop over {len(sel)} jobs: {plain_ms:.1f} ms of steps, {plain:.3e} vehicle-steps/s, "
+        f"identical results {same}")
+    offered = sum(j.horizon * j.trips.n_vehicles for j in sel)
+    out = {
+        "metric": METRIC, "value": summ["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
+        "steps": int(sum(j.horizon for j in sel)), "warmup": args.skip,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served_poisson", "jobs": len(jobs), "measured_after": args.skip,
+                   "rate_jobs_per_s": args.rate, "hbm_budget_gib": args.budget_gib, "steps_per_tick": args.tick,
+                   "streams": args.streams},
+        "latency_p50_s": summ["latency_p50_s"], "latency_p99_s": summ["latency_p99_s"],
+        "queue_wait_p99_s": summ["queue_wait_p99_s"],
+        "vehicle_steps_per_s": summ["vehicle_steps_per_s"],
+        "vs_plain_loop": summ["vehicle_steps_per_s"] / plain,
+        "plain_loop": {"vehicle_steps_per_s": plain, "ms": plain_ms, "identical_results": bool(same)},
+        "offered_vehicle_trip_steps": offered,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=7200)
+    ap.add_argument("--workload", choices=["city", "batch", "serve"], default="city")
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--jobs", type=int, default=400)
+    ap.add_argument("--skip", type=int, default=50)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--tick", type=int, default=30)
+    ap.add_argument("--streams", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
               f"build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        args.steps = args.steps or 1800
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
+    args.steps = args.steps or 7200
 
     from paper_2406_10661_amd import workloads as W
     t0 = time.time()

@@ -162,7 +162,8 @@ int tsim_create(const tsim_network *net, const tsim_trips *trips, const tsim_par
 int tsim_step(tsim_handle *h, int32_t n_steps);
 
 /* Junctions junction_ids[c] switch to MANUAL with phase phase_index[c] from
- * the next step on (Section 3.2 set_tl_phase and its batch form). */
+ * the next step on (Section 3.2 set_tl_phase and its batch form).  Enqueued on
+ * the stream without waiting; the host arrays may be reused on return. */
 int tsim_set_signal_phases(tsim_handle *h, const int32_t *junction_ids, const int32_t *phase_index,
                            int32_t n);
 
@@ -195,8 +196,50 @@ int tsim_set_state(tsim_handle *h, const tsim_state_host *in);
 int tsim_set_profiling(tsim_handle *h, int32_t enable);
 int tsim_get_kernel_times(tsim_handle *h, double *ms, int64_t *launches, int32_t n_kernels);
 
+/* Launch mode.  chunk > 0: tsim_step captures `chunk` steps (both kernels of
+ * each) into one HIP graph on its first call and replays that graph for every
+ * whole chunk of a call; the remaining steps are launched one by one.  chunk
+ * = 0 (default) launches every kernel directly.  Graphs are not used while
+ * profiling is on.  Changing the chunk synchronises the stream.  chunk in
+ * [0, 4096]; TSIM_EDEVICE if capture fails. */
+int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
+
 int tsim_destroy(tsim_handle *h);
 const char *tsim_last_error(const tsim_handle *h);
+
+/*
+ * Batched instances: many independent simulations (networks, trip tables and
+ * seeds of their own) resident together and advanced by the same kernel
+ * launches, one launch per kernel per step for the whole batch.  Every
+ * instance draws its random numbers from its own seed, vehicle ids and step
+ * count, so its trajectory is bit-identical to the same instance created alone
+ * with tsim_create.  All instances share the model parameters except the seed
+ * (params[i].seed).  Arrays nets/trips/params have n entries (host).
+ * Instance-indexed calls take local ids (junction ids, roads, lanes, vehicles
+ * of that instance).
+ */
+typedef struct tsim_handle tsim_batch;
+
+int tsim_batch_footprint(const tsim_network *nets, const tsim_trips *trips, const tsim_params *params, int32_t n,
+                         size_t *bytes_out);
+int tsim_batch_create(const tsim_network *nets, const tsim_trips *trips, const tsim_params *params, int32_t n,
+                      void *hip_stream, void *device_arena, size_t arena_bytes, tsim_batch **out);
+/* Enqueues n_steps steps of every instance (async on the stream). */
+int tsim_batch_step(tsim_batch *b, int32_t n_steps);
+/* As tsim_set_graph_steps, for the whole batch. */
+int tsim_batch_set_graph_steps(tsim_batch *b, int32_t chunk);
+int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
+                                 const int32_t *phase_index, int32_t n);
+/* Every junction of every instance at once: phase_index[k] for the k-th
+ * junction of the batch in instance order (instance 0's junctions first), a
+ * negative entry leaves that junction unchanged; non-negative entries switch
+ * it to MANUAL from the next step.  n_total = total junctions of the batch. */
+int tsim_batch_set_all_phases(tsim_batch *b, const int32_t *phase_index, int32_t n_total);
+/* Synchronises the stream, then fills *out for one instance. */
+int tsim_batch_get_metrics(tsim_batch *b, int32_t instance, tsim_metrics *out);
+/* State of one instance (arrays sized for that instance). */
+int tsim_batch_get_state(tsim_batch *b, int32_t instance, tsim_state_host *out);
+int tsim_batch_destroy(tsim_batch *b);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,7 @@
 // library itself never allocates device memory.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -15,12 +16,13 @@
 #include "tsim_internal.h"
 
 namespace tsim {
-hipError_t launch_prepare(const DevNet& D, hipStream_t s);
-hipError_t launch_update(const DevNet& D, hipStream_t s);
-hipError_t launch_set_phases(const DevNet& D, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
-hipError_t launch_export(const DevNet& D, const int32_t* lane_ext, int32_t* o_lane, float* o_x, float* o_v,
-                         int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
-hipError_t launch_import(const DevNet& D, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
+hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s);
+hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s);
+hipError_t launch_set_phases(const DevNet* Dd, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
+hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
+                         float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
+hipError_t launch_import(const DevNet* Dd, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
+hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s);
 }  // namespace tsim
 
 using namespace tsim;
@@ -45,6 +47,15 @@ struct Build {
     std::vector<int32_t> route_begin, route, q_begin, q_veh;
     uint64_t slots = 0;
     int G = 0;
+    // instances of a batch (one for tsim_create)
+    int n_inst = 1;
+    bool blocked = false;
+    std::vector<int32_t> tile_inst, junc_inst, inst_vbase;
+    std::vector<uint32_t> inst_key;
+    std::vector<long long> inst_t0;
+    // per-instance offsets into the union: roads, junctions, road lanes,
+    // junction lanes, vehicles (n_inst + 1 entries each)
+    std::vector<int> road_off, junc_off, rl_off, jl_off, veh_off;
 };
 
 struct Region {
@@ -282,13 +293,168 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
     return TSIM_OK;
 }
 
+// instance metadata for a single network
+void single_instance(Build& B, const tsim_params* prm)
+{
+    B.n_inst = 1;
+    B.blocked = false;
+    B.tile_inst.assign(B.R, 0);
+    B.junc_inst.assign(B.NJ, 0);
+    B.inst_vbase.assign(1, 0);
+    B.inst_key = {(uint32_t)prm->seed, (uint32_t)(prm->seed >> 32)};
+    B.inst_t0.assign(1, 0);
+    B.road_off = {0, B.R};
+    B.junc_off = {0, B.NJ};
+    B.rl_off = {0, B.NRL};
+    B.jl_off = {0, B.NJL};
+    B.veh_off = {0, B.N};
+}
+
+// the disjoint union of several instances as one network and trip table
+struct Union {
+    std::vector<int32_t> road_from, road_to, road_lane_begin, jl_in, jl_out, junc_phase_begin, phase_green_begin,
+        phase_green_jl, junc_policy, route_begin, route_roads;
+    std::vector<float> road_length, road_limit, jl_length, jl_limit, phase_duration, depart, v0f, vlen;
+    tsim_network net{};
+    tsim_trips trips{};
+    std::vector<int> road_off, junc_off, rl_off, jl_off, veh_off;
+};
+
+int make_union(const tsim_network* nets, const tsim_trips* trips, const tsim_params* prm, int n, Union& U,
+               std::string* err)
+{
+    if (!nets || !trips || !prm || n <= 0) return fail(err, TSIM_EINVAL, "null or empty batch");
+    U.road_off.assign(1, 0);
+    U.junc_off.assign(1, 0);
+    U.rl_off.assign(1, 0);
+    U.jl_off.assign(1, 0);
+    U.veh_off.assign(1, 0);
+    U.road_lane_begin.assign(1, 0);
+    U.junc_phase_begin.assign(1, 0);
+    U.phase_green_begin.assign(1, 0);
+    U.route_begin.assign(1, 0);
+    for (int k = 0; k < n; ++k) {
+        const tsim_network& N = nets[k];
+        const tsim_trips& T = trips[k];
+        const tsim_params& P = prm[k];
+        const tsim_params& P0 = prm[0];
+        if (P.dt != P0.dt || P.T != P0.T || P.a_max != P0.a_max || P.b_comf != P0.b_comf || P.s0 != P0.s0 ||
+            P.delta != P0.delta || P.politeness != P0.politeness || P.a_th != P0.a_th || P.b_safe != P0.b_safe ||
+            P.p_max != P0.p_max || P.p_min != P0.p_min || P.a_emerg != P0.a_emerg)
+            return fail(err, TSIM_EINVAL, "batch instances must share every parameter but the seed");
+        if (N.n_roads <= 0 || N.n_junctions <= 0 || !N.road_lane_begin || !N.junc_phase_begin || !T.route_begin ||
+            T.n_vehicles < 0 || N.n_jlanes < 0)
+            return fail(err, TSIM_EINVAL, "instance " + std::to_string(k) + ": bad sizes");
+        const int ro = U.road_off.back(), jo = U.junc_off.back(), lo = U.rl_off.back(), qo = U.jl_off.back(),
+                  vo = U.veh_off.back();
+        const int nrl = N.road_lane_begin[N.n_roads];
+        const int np = N.junc_phase_begin[N.n_junctions];
+        const int pgo = (int)U.phase_duration.size();
+        const int go = U.phase_green_begin.back();
+        for (int r = 0; r < N.n_roads; ++r) {
+            U.road_from.push_back(N.road_from[r] + jo);
+            U.road_to.push_back(N.road_to[r] + jo);
+            U.road_lane_begin.push_back(N.road_lane_begin[r + 1] + lo);
+            U.road_length.push_back(N.road_length[r]);
+            U.road_limit.push_back(N.road_limit[r]);
+        }
+        for (int q = 0; q < N.n_jlanes; ++q) {
+            U.jl_in.push_back(N.jl_in_lane[q] + lo);
+            U.jl_out.push_back(N.jl_out_lane[q] + lo);
+            U.jl_length.push_back(N.jl_length[q]);
+            U.jl_limit.push_back(N.jl_limit[q]);
+        }
+        for (int j = 0; j < N.n_junctions; ++j) {
+            U.junc_phase_begin.push_back(N.junc_phase_begin[j + 1] + pgo);
+            U.junc_policy.push_back(N.junc_policy[j]);
+        }
+        for (int p = 0; p < np; ++p) {
+            U.phase_duration.push_back(N.phase_duration[p]);
+            U.phase_green_begin.push_back(N.phase_green_begin[p + 1] + go);
+        }
+        for (int g = 0; g < (np ? N.phase_green_begin[np] : 0); ++g) U.phase_green_jl.push_back(N.phase_green_jl[g] + qo);
+        const int rbo = U.route_begin.back();
+        for (int i = 0; i < T.n_vehicles; ++i) {
+            U.route_begin.push_back(T.route_begin[i + 1] + rbo);
+            U.depart.push_back(T.depart_time[i]);
+            U.v0f.push_back(T.v0_factor[i]);
+            U.vlen.push_back(T.length[i]);
+        }
+        for (int e = 0; e < T.route_begin[T.n_vehicles]; ++e) U.route_roads.push_back(T.route_roads[e] + ro);
+        U.road_off.push_back(ro + N.n_roads);
+        U.junc_off.push_back(jo + N.n_junctions);
+        U.rl_off.push_back(lo + nrl);
+        U.jl_off.push_back(qo + N.n_jlanes);
+        U.veh_off.push_back(vo + T.n_vehicles);
+    }
+    tsim_network& N = U.net;
+    N.n_junctions = U.junc_off.back();
+    N.n_roads = U.road_off.back();
+    N.road_from = U.road_from.data();
+    N.road_to = U.road_to.data();
+    N.road_lane_begin = U.road_lane_begin.data();
+    N.road_length = U.road_length.data();
+    N.road_limit = U.road_limit.data();
+    N.n_jlanes = U.jl_off.back();
+    N.jl_in_lane = U.jl_in.data();
+    N.jl_out_lane = U.jl_out.data();
+    N.jl_length = U.jl_length.data();
+    N.jl_limit = U.jl_limit.data();
+    N.junc_phase_begin = U.junc_phase_begin.data();
+    N.phase_duration = U.phase_duration.data();
+    N.phase_green_begin = U.phase_green_begin.data();
+    N.phase_green_jl = U.phase_green_jl.data();
+    N.junc_policy = U.junc_policy.data();
+    tsim_trips& T = U.trips;
+    T.n_vehicles = U.veh_off.back();
+    T.depart_time = U.depart.data();
+    T.route_begin = U.route_begin.data();
+    T.route_roads = U.route_roads.data();
+    T.v0_factor = U.v0f.data();
+    T.length = U.vlen.data();
+    return TSIM_OK;
+}
+
+// instance metadata of a batch built from a union
+void batch_instances(Build& B, const Union& U, const tsim_params* prm, int n)
+{
+    B.n_inst = n;
+    B.blocked = n > 1;
+    B.road_off = U.road_off;
+    B.junc_off = U.junc_off;
+    B.rl_off = U.rl_off;
+    B.jl_off = U.jl_off;
+    B.veh_off = U.veh_off;
+    B.tile_inst.assign(B.R, 0);
+    B.junc_inst.assign(B.NJ, 0);
+    B.inst_vbase.assign(n, 0);
+    B.inst_key.assign(2 * n, 0u);
+    B.inst_t0.assign(n, 0);
+    for (int k = 0; k < n; ++k) {
+        for (int r = U.road_off[k]; r < U.road_off[k + 1]; ++r) B.tile_inst[r] = k;
+        for (int j = U.junc_off[k]; j < U.junc_off[k + 1]; ++j) B.junc_inst[j] = k;
+        B.inst_vbase[k] = U.veh_off[k];
+        B.inst_key[2 * k] = (uint32_t)prm[k].seed;
+        B.inst_key[2 * k + 1] = (uint32_t)(prm[k].seed >> 32);
+    }
+    // tiles grouped by instance (each workgroup takes a contiguous run),
+    // larger tiles first within an instance
+    std::vector<long long> tcap(B.R, 0);
+    for (int r = 0; r < B.R; ++r)
+        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) tcap[r] += B.lane_cap[m];
+    std::stable_sort(B.tile_order.begin(), B.tile_order.end(), [&](int a, int b) {
+        return B.tile_inst[a] < B.tile_inst[b] || (B.tile_inst[a] == B.tile_inst[b] && tcap[a] > tcap[b]);
+    });
+}
+
 }  // namespace
 
 struct tsim_handle {
     hipStream_t stream = nullptr;
     char* arena = nullptr;
     size_t arena_bytes = 0;
-    DevNet D{};
+    DevNet D{};                      // host copy of the device view
+    DevNet* d_net = nullptr;         // device copy (kernel argument)
     Build B;
     int32_t* d_lane_ext = nullptr;   // internal -> external lane id
     int32_t* d_io_i0 = nullptr;      // staging: export lane / import slots
@@ -297,13 +463,22 @@ struct tsim_handle {
     float* d_io_f0 = nullptr;
     float* d_io_f1 = nullptr;
     VehRec* d_io_rec = nullptr;      // staging: import records
-    int32_t* d_io_ph = nullptr;      // staging: phase updates (2 x NJ)
+    int32_t* d_io_ph = nullptr;      // staging: phase updates (2 slots of 2 x NJ)
+    int32_t* h_pin[2] = {nullptr, nullptr};   // pinned host staging of the two slots
+    hipEvent_t pin_ev[2] = {nullptr, nullptr};
+    bool pin_used[2] = {false, false};
+    int pin_slot = 0;
     // kernel timing (tsim_set_profiling)
     bool prof = false;
     std::vector<hipEvent_t> ev[2];   // start/stop pairs per kernel
     int ev_used[2] = {0, 0};
     double ms[2] = {0.0, 0.0};
     long long launches[2] = {0, 0};
+    // captured step chunks (tsim_set_graph_steps): one graph of `graph_chunk`
+    // steps, replayed; the remainder of a call is launched directly
+    int graph_chunk = 0;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
     std::string err;
 };
 
@@ -357,8 +532,10 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.q_head, R * 4);
     add(&D.slab0, S * sizeof(VehRec));
     add(&D.slab1, S * sizeof(VehRec));
-    add(&D.cnt0, NL * 4);
-    add(&D.cnt1, NL * 4);
+    add(&D.sum0, NL * sizeof(LaneSum));
+    add(&D.sum1, NL * sizeof(LaneSum));
+    add(&D.tile_n0, R * 4);
+    add(&D.tile_n1, R * 4);
     add(&D.inbox, NL * sizeof(VehRec));
     add(&D.inbox_flag, NL * 4);
     add(&D.sh_gmask, S * 4);
@@ -375,7 +552,14 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.lane_wait, NL * 4);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.done_ctr, 4);
-    add(&D.met, sizeof(DevMetrics));
+    add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
+    add(&D.tile_inst, R * 4);
+    add(&D.junc_inst, NJ * 4);
+    add(&D.inst_vbase, (size_t)B.n_inst * 4);
+    add(&D.inst_key, (size_t)B.n_inst * 8);
+    add(&D.inst_t0, (size_t)B.n_inst * 8);
+    add(&D.inst_acc, (size_t)B.n_inst * sizeof(WGPartial));
+    add(&D.gstep, 8);
     add(&h->d_lane_ext, NL * 4);
     add(&h->d_io_i0, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_i1, std::max<size_t>(N, 1) * 4);
@@ -383,7 +567,8 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&h->d_io_f0, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_f1, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_rec, std::max<size_t>(N, 1) * sizeof(VehRec));
-    add(&h->d_io_ph, 2 * NJ * 4);
+    add(&h->d_io_ph, 4 * NJ * 4);
+    add(&h->d_net, sizeof(DevNet));
     return v;
 }
 
@@ -473,14 +658,32 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     }
     std::vector<uint32_t> slots;
     std::vector<VehRec> recs;
-    std::vector<int32_t> cnt(B.NL, 0);
+    const float INF = std::numeric_limits<float>::infinity();
+    LaneSum empty;
+    empty.cnt = 0;
+    empty.rear = INF;
+    empty.rear_v = 0.0f;
+    empty.front_reach = -INF;
+    std::vector<LaneSum> sum(B.NL, empty), sum_other(B.NL, empty);
+    std::vector<int32_t> tile_n(B.R, 0), tile_zero(B.R, 0);
+    std::vector<float> road_speed(B.R, -1.0f);
+    std::vector<int32_t> lane_wait(B.NL, 0);
     slots.reserve(departed);
     recs.reserve(departed);
+    const float dtf = (float)h->D.P.dt, reachf = h->D.P.reach;
     for (int m = 0; m < B.NL; ++m) {
         auto& L = per_lane[m];
         std::sort(L.begin(), L.end(), [&](int a, int b) { return x[a] > x[b] || (x[a] == x[b] && a < b); });
         if ((int)L.size() > B.lane_cap[m]) return fail(&h->err, TSIM_EINVAL, "lane over capacity (overlapping vehicles)");
-        cnt[m] = (int)L.size();
+        if (!L.empty()) {
+            LaneSum& su = sum[m];
+            su.cnt = (int)L.size();
+            const int f = L.front(), b = L.back();
+            su.front_reach = x[f] + v[f] * dtf + reachf - B.lane_len[m];
+            su.rear = x[b] - B.vlen[b];
+            su.rear_v = v[b];
+            tile_n[B.lane_tile[m]] += su.cnt;
+        }
         for (size_t c = 0; c < L.size(); ++c) {
             const int i = L[c];
             VehRec o;
@@ -502,27 +705,49 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
         while (hd < B.q_begin[r + 1] && status[B.q_veh[hd]] != TSIM_WAITING) hd++;
         qhead[r] = hd;
     }
-    DevMetrics M{};
-    M.step = step;
-    M.departed = departed;
-    M.finished = finished;
-    M.sum_tt_fx = sum_tt;
+    std::vector<DevMetrics> Ms(B.n_inst);
+    for (int k = 0; k < B.n_inst; ++k) {
+        DevMetrics& M = Ms[k];
+        std::memset(&M, 0, sizeof(M));
+        M.step = step - B.inst_t0[k];
+        for (int i = B.veh_off[k]; i < B.veh_off[k + 1]; ++i) {
+            if (status[i] != TSIM_WAITING) M.departed++;
+            if (status[i] == TSIM_FINISHED) {
+                M.finished++;
+                const double tt = (double)(finish_step[i] + 1) * h->D.P.dt_d - (double)B.tau[i];
+                M.sum_tt_fx += llrint(tt * kTimeFx);
+            }
+        }
+    }
+    (void)departed;
+    (void)finished;
+    (void)sum_tt;
+    std::vector<WGPartial> zacc(B.n_inst);
+    std::memset(zacc.data(), 0, zacc.size() * sizeof(WGPartial));
+    const long long gstep = step;
     std::vector<int32_t> st(status, status + N), fs(finish_step, finish_step + N);
     std::vector<int32_t> jp(pol, pol + B.NJ), jm(ph, ph + B.NJ);
-    int32_t* cnt_rd = (step & 1) ? D.cnt1 : D.cnt0;
+    const bool odd = (step & 1) != 0;
+    HIPCHK(h, up(h, odd ? D.sum1 : D.sum0, sum));
+    HIPCHK(h, up(h, odd ? D.sum0 : D.sum1, sum_other));
+    HIPCHK(h, up(h, odd ? D.tile_n1 : D.tile_n0, tile_n));
+    HIPCHK(h, up(h, odd ? D.tile_n0 : D.tile_n1, tile_zero));
+    HIPCHK(h, up(h, D.road_speed, road_speed));
+    HIPCHK(h, up(h, D.lane_wait, lane_wait));
     HIPCHK(h, up(h, D.status, st));
     HIPCHK(h, up(h, D.finish_step, fs));
     HIPCHK(h, up(h, D.junc_policy, jp));
     HIPCHK(h, up(h, D.junc_manual, jm));
     HIPCHK(h, up(h, D.q_head, qhead));
-    HIPCHK(h, up(h, cnt_rd, cnt));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
-    HIPCHK(h, hipMemcpyAsync(D.met, &M, sizeof(M), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, up(h, D.met, Ms));
+    HIPCHK(h, up(h, D.inst_acc, zacc));
+    HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
     if (!slots.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_io_i0, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_io_rec, recs.data(), recs.size() * sizeof(VehRec), hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, launch_import(D, (const uint32_t*)h->d_io_i0, h->d_io_rec, (int)slots.size(), h->stream));
+        HIPCHK(h, launch_import(h->d_net, (const uint32_t*)h->d_io_i0, h->d_io_rec, (int)slots.size(), h->stream));
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
@@ -542,6 +767,9 @@ int tsim_footprint(const tsim_network* net, const tsim_trips* trips, const tsim_
     return TSIM_OK;
 }
 
+static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stream, void* device_arena,
+                       size_t arena_bytes, tsim_handle** out);
+
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,
                 void* device_arena, size_t arena_bytes, tsim_handle** out)
 {
@@ -555,6 +783,49 @@ int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_par
         delete h;
         return rc;
     }
+    single_instance(h->B, params);
+    return create_impl(h, params, hip_stream, device_arena, arena_bytes, out);
+}
+
+int tsim_batch_footprint(const tsim_network* nets, const tsim_trips* trips, const tsim_params* params, int32_t n,
+                         size_t* bytes_out)
+{
+    if (!bytes_out) return fail(nullptr, TSIM_EINVAL, "null bytes_out");
+    Union U;
+    int rc = make_union(nets, trips, params, n, U, nullptr);
+    if (rc) return rc;
+    tsim_handle tmp;
+    rc = build_tables(&U.net, &U.trips, params, tmp.B, nullptr);
+    if (rc) return rc;
+    batch_instances(tmp.B, U, params, n);
+    *bytes_out = arena_size(&tmp) + 256;
+    return TSIM_OK;
+}
+
+int tsim_batch_create(const tsim_network* nets, const tsim_trips* trips, const tsim_params* params, int32_t n,
+                      void* hip_stream, void* device_arena, size_t arena_bytes, tsim_batch** out)
+{
+    if (!out) return fail(nullptr, TSIM_EINVAL, "null out");
+    *out = nullptr;
+    if (!device_arena) return fail(nullptr, TSIM_EINVAL, "null arena");
+    Union U;
+    int rc = make_union(nets, trips, params, n, U, nullptr);
+    if (rc) return rc;
+    tsim_handle* h = new (std::nothrow) tsim_handle();
+    if (!h) return fail(nullptr, TSIM_ENOMEM, "host allocation failed");
+    rc = build_tables(&U.net, &U.trips, params, h->B, &h->err);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    batch_instances(h->B, U, params, n);
+    return create_impl(h, params, hip_stream, device_arena, arena_bytes, out);
+}
+
+static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stream, void* device_arena,
+                       size_t arena_bytes, tsim_handle** out)
+{
+    int rc = 0;
     const size_t need = arena_size(h);
     char* base = (char*)(((uintptr_t)device_arena + 255) & ~(uintptr_t)255);
     const size_t lost = (size_t)(base - (char*)device_arena);
@@ -578,6 +849,8 @@ int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_par
     D.NL = B.NL;
     D.N = B.N;
     D.G = B.G;
+    D.n_inst = B.n_inst;
+    D.blocked = B.blocked ? 1 : 0;
     fill_params(D.P, params);
     auto chk = [&](hipError_t e, const char* what) -> int { return e == hipSuccess ? 0 : hip_fail(h, e, what); };
     int e = 0;
@@ -611,6 +884,12 @@ int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_par
     e = e ? e : chk(up(h, (int32_t*)D.q_begin, B.q_begin), "queues");
     e = e ? e : chk(up(h, (int32_t*)D.q_veh, B.q_veh), "queues");
     e = e ? e : chk(up(h, h->d_lane_ext, B.ext_of_int), "lanes");
+    e = e ? e : chk(up(h, (int32_t*)D.tile_inst, B.tile_inst), "instances");
+    e = e ? e : chk(up(h, (int32_t*)D.junc_inst, B.junc_inst), "instances");
+    e = e ? e : chk(up(h, (int32_t*)D.inst_vbase, B.inst_vbase), "instances");
+    e = e ? e : chk(up(h, (uint32_t*)D.inst_key, B.inst_key), "instances");
+    e = e ? e : chk(up(h, (long long*)D.inst_t0, B.inst_t0), "instances");
+    e = e ? e : chk(hipMemcpyAsync(h->d_net, &h->D, sizeof(DevNet), hipMemcpyHostToDevice, h->stream), "view");
     if (e) {
         delete h;
         return e;
@@ -649,7 +928,7 @@ int flush_events(tsim_handle* h, int k)
 
 int timed_launch(tsim_handle* h, int k)
 {
-    if (!h->prof) return (k == 0 ? launch_update(h->D, h->stream) : launch_prepare(h->D, h->stream)) == hipSuccess
+    if (!h->prof) return (k == 0 ? launch_update(h->d_net, h->D, h->stream) : launch_prepare(h->d_net, h->D, h->stream)) == hipSuccess
                              ? TSIM_OK
                              : hip_fail(h, hipGetLastError(), "kernel launch");
     if (h->ev_used[k] == kEventPairs) {
@@ -662,15 +941,61 @@ int timed_launch(tsim_handle* h, int k)
     }
     const int i = h->ev_used[k]++;
     HIPCHK(h, hipEventRecord(h->ev[k][2 * i], h->stream));
-    HIPCHK(h, k == 0 ? launch_update(h->D, h->stream) : launch_prepare(h->D, h->stream));
+    HIPCHK(h, k == 0 ? launch_update(h->d_net, h->D, h->stream) : launch_prepare(h->d_net, h->D, h->stream));
     HIPCHK(h, hipEventRecord(h->ev[k][2 * i + 1], h->stream));
     return TSIM_OK;
 }
 }  // namespace
 
+static int capture_chunk(tsim_handle* h)
+{
+    hipGraph_t g = nullptr;
+    if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < h->graph_chunk && e == hipSuccess; ++s) {
+        e = launch_prepare(h->d_net, h->D, h->cap_stream);
+        if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->cap_stream);
+    }
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(&h->err, TSIM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph = nullptr;
+        return fail(&h->err, TSIM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return TSIM_OK;
+}
+
+int tsim_set_graph_steps(tsim_handle* h, int32_t chunk)
+{
+    if (!h || chunk < 0 || chunk > 4096) return fail(nullptr, TSIM_EINVAL, "bad handle or chunk");
+    if (h->graph) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    h->graph_chunk = chunk;
+    return TSIM_OK;
+}
+
 int tsim_step(tsim_handle* h, int32_t n_steps)
 {
     if (!h || n_steps < 0) return fail(nullptr, TSIM_EINVAL, "bad handle or step count");
+    if (h->graph_chunk > 0 && !h->prof) {
+        if (!h->graph) {
+            int rc = capture_chunk(h);
+            if (rc) return rc;
+        }
+        while (n_steps >= h->graph_chunk) {
+            HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
+            n_steps -= h->graph_chunk;
+        }
+    }
     for (int s = 0; s < n_steps; ++s) {
         int rc = timed_launch(h, 1);
         if (rc) return rc;
@@ -705,35 +1030,95 @@ int tsim_get_kernel_times(tsim_handle* h, double* ms, int64_t* launches, int32_t
     return TSIM_OK;
 }
 
-int tsim_set_signal_phases(tsim_handle* h, const int32_t* junction_ids, const int32_t* phase_index, int32_t n)
+// next pinned/device staging slot for phase updates; waits only for the copy
+// that last used the same slot
+static int stage_slot(tsim_handle* h, int32_t** hp, int32_t** dp)
 {
-    if (!h || n < 0 || (n && (!junction_ids || !phase_index))) return fail(nullptr, TSIM_EINVAL, "bad arguments");
-    if (n == 0) return TSIM_OK;
-    Build& B = h->B;
-    if (n > B.NJ) return fail(&h->err, TSIM_EINVAL, "more updates than junctions");
-    for (int c = 0; c < n; ++c) {
-        const int j = junction_ids[c];
-        if (j < 0 || j >= B.NJ) return fail(&h->err, TSIM_EINVAL, "junction id out of range");
-        const int np = B.junc_phase_begin[j + 1] - B.junc_phase_begin[j];
-        if (phase_index[c] < 0 || phase_index[c] >= np) return fail(&h->err, TSIM_EINVAL, "phase index out of range");
+    const int s = h->pin_slot;
+    const size_t bytes = (size_t)2 * h->B.NJ * 4;
+    if (!h->h_pin[s]) {
+        HIPCHK(h, hipHostMalloc((void**)&h->h_pin[s], bytes, hipHostMallocDefault));
+        HIPCHK(h, hipEventCreateWithFlags(&h->pin_ev[s], hipEventDisableTiming));
     }
-    HIPCHK(h, hipMemcpyAsync(h->d_io_ph, junction_ids, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->d_io_ph + B.NJ, phase_index, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, launch_set_phases(h->D, h->d_io_ph, h->d_io_ph + B.NJ, n, h->stream));
-    // the host arrays may be reused as soon as the copies have been consumed
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->pin_used[s]) HIPCHK(h, hipEventSynchronize(h->pin_ev[s]));
+    h->pin_used[s] = true;
+    *hp = h->h_pin[s];
+    *dp = h->d_io_ph + (size_t)s * 2 * h->B.NJ;
+    h->pin_slot = s ^ 1;
     return TSIM_OK;
 }
 
-int tsim_get_metrics(tsim_handle* h, tsim_metrics* out)
+static int set_phases_impl(tsim_handle* h, int inst, const int32_t* junction_ids, const int32_t* phase_index,
+                           int32_t n)
+{
+    if (!h || n < 0 || (n && (!junction_ids || !phase_index))) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = h->B;
+    if (inst < 0 || inst >= B.n_inst) return fail(&h->err, TSIM_EINVAL, "instance out of range");
+    if (n == 0) return TSIM_OK;
+    const int jo = B.junc_off[inst], nj = B.junc_off[inst + 1] - jo;
+    if (n > nj) return fail(&h->err, TSIM_EINVAL, "more updates than junctions");
+    std::vector<int32_t> ids(n), ph(n);
+    for (int c = 0; c < n; ++c) {
+        const int j = junction_ids[c];
+        if (j < 0 || j >= nj) return fail(&h->err, TSIM_EINVAL, "junction id out of range");
+        const int np = B.junc_phase_begin[jo + j + 1] - B.junc_phase_begin[jo + j];
+        if (phase_index[c] < 0 || phase_index[c] >= np) return fail(&h->err, TSIM_EINVAL, "phase index out of range");
+        ids[c] = jo + j;
+        ph[c] = phase_index[c];
+    }
+    int32_t* hp = nullptr;
+    int32_t* dp = nullptr;
+    int rc = stage_slot(h, &hp, &dp);
+    if (rc) return rc;
+    std::memcpy(hp, ids.data(), (size_t)n * 4);
+    std::memcpy(hp + B.NJ, ph.data(), (size_t)n * 4);
+    HIPCHK(h, hipMemcpyAsync(dp, hp, (size_t)2 * B.NJ * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_set_phases(h->d_net, dp, dp + B.NJ, n, h->stream));
+    HIPCHK(h, hipEventRecord(h->pin_ev[h->pin_slot ^ 1], h->stream));
+    return TSIM_OK;
+}
+
+int tsim_set_signal_phases(tsim_handle* h, const int32_t* junction_ids, const int32_t* phase_index, int32_t n)
+{
+    return set_phases_impl(h, 0, junction_ids, phase_index, n);
+}
+
+int tsim_batch_set_signal_phases(tsim_batch* b, int32_t instance, const int32_t* junction_ids,
+                                 const int32_t* phase_index, int32_t n)
+{
+    return set_phases_impl(b, instance, junction_ids, phase_index, n);
+}
+
+int tsim_batch_set_all_phases(tsim_batch* b, const int32_t* phase_index, int32_t n_total)
+{
+    if (!b || !phase_index || n_total != b->B.NJ) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = b->B;
+    for (int j = 0; j < B.NJ; ++j) {
+        const int np = B.junc_phase_begin[j + 1] - B.junc_phase_begin[j];
+        if (phase_index[j] >= np) return fail(&b->err, TSIM_EINVAL, "phase index out of range");
+    }
+    int32_t* hp = nullptr;
+    int32_t* dp = nullptr;
+    int rc = stage_slot(b, &hp, &dp);
+    if (rc) return rc;
+    std::memcpy(hp, phase_index, (size_t)B.NJ * 4);
+    HIPCHK(b, hipMemcpyAsync(dp, hp, (size_t)B.NJ * 4, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, launch_set_all_phases(b->d_net, b->D, dp, b->stream));
+    HIPCHK(b, hipEventRecord(b->pin_ev[b->pin_slot ^ 1], b->stream));
+    return TSIM_OK;
+}
+
+static int metrics_impl(tsim_handle* h, int inst, tsim_metrics* out)
 {
     if (!h || !out) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    if (inst < 0 || inst >= h->B.n_inst) return fail(&h->err, TSIM_EINVAL, "instance out of range");
     DevMetrics M;
-    HIPCHK(h, hipMemcpyAsync(&M, h->D.met, sizeof(M), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&M, h->D.met + inst, sizeof(M), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    const long long n_veh = h->B.veh_off[inst + 1] - h->B.veh_off[inst];
     std::memset(out, 0, sizeof(*out));
     out->step = M.step;
-    out->n_waiting = h->B.N - M.departed;
+    out->n_waiting = n_veh - M.departed;
     out->n_active = M.departed - M.finished;
     out->n_finished = M.finished;
     out->sum_travel_time = (double)M.sum_tt_fx / kTimeFx;
@@ -751,9 +1136,16 @@ int tsim_get_metrics(tsim_handle* h, tsim_metrics* out)
     return M.errors ? TSIM_ESTATE : TSIM_OK;
 }
 
+int tsim_get_metrics(tsim_handle* h, tsim_metrics* out) { return metrics_impl(h, 0, out); }
+
+int tsim_batch_get_metrics(tsim_batch* b, int32_t instance, tsim_metrics* out)
+{
+    return metrics_impl(b, instance, out);
+}
+
 int tsim_get_road_mean_speed(tsim_handle* h, float* out, int32_t n_roads)
 {
-    if (!h || !out || n_roads != h->B.R) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    if (!h || !out || n_roads != h->B.R || h->B.n_inst != 1) return fail(nullptr, TSIM_EINVAL, "bad arguments");
     HIPCHK(h, hipMemcpyAsync(out, h->D.road_speed, (size_t)n_roads * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
@@ -761,7 +1153,7 @@ int tsim_get_road_mean_speed(tsim_handle* h, float* out, int32_t n_roads)
 
 int tsim_get_lane_waiting_counts(tsim_handle* h, int32_t* out, int32_t n_lanes)
 {
-    if (!h || !out || n_lanes != h->B.NL) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    if (!h || !out || n_lanes != h->B.NL || h->B.n_inst != 1) return fail(nullptr, TSIM_EINVAL, "bad arguments");
     std::vector<int32_t> tmp(n_lanes);
     HIPCHK(h, hipMemcpyAsync(tmp.data(), h->D.lane_wait, (size_t)n_lanes * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -779,7 +1171,8 @@ static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<
     HIPCHK(h, hipMemsetAsync(h->d_io_f1, 0, (size_t)N * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(h->d_io_i1, 0, (size_t)N * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(h->d_io_i2, 0, (size_t)N * 4, h->stream));
-    HIPCHK(h, launch_export(h->D, h->d_lane_ext, h->d_io_i0, h->d_io_f0, h->d_io_f1, h->d_io_i1, h->d_io_i2, h->stream));
+    HIPCHK(h, launch_export(h->d_net, h->D, h->d_lane_ext, h->d_io_i0, h->d_io_f0, h->d_io_f1, h->d_io_i1, h->d_io_i2,
+                            h->stream));
     lane.resize(N);
     x.resize(N);
     v.resize(N);
@@ -796,7 +1189,8 @@ static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<
 
 int tsim_get_lane_order(tsim_handle* h, int32_t* offsets, int32_t* vehicle_ids, int32_t n_lanes, int32_t max_ids)
 {
-    if (!h || !offsets || !vehicle_ids || n_lanes != h->B.NL) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    if (!h || !offsets || !vehicle_ids || n_lanes != h->B.NL || h->B.n_inst != 1)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
     std::vector<int32_t> lane, rpos, rank;
     std::vector<float> x, v;
     int rc = export_state(h, lane, x, v, rpos, rank);
@@ -816,38 +1210,60 @@ int tsim_get_lane_order(tsim_handle* h, int32_t* offsets, int32_t* vehicle_ids, 
     return TSIM_OK;
 }
 
-int tsim_get_state(tsim_handle* h, tsim_state_host* out)
+static int get_state_impl(tsim_handle* h, int inst, tsim_state_host* out)
 {
     if (!h || !out || !out->status || !out->lane || !out->route_pos || !out->x || !out->v || !out->finish_step ||
         !out->junc_policy || !out->junc_phase)
         return fail(nullptr, TSIM_EINVAL, "bad arguments");
-    const int N = h->B.N;
+    Build& B = h->B;
+    if (inst < 0 || inst >= B.n_inst) return fail(&h->err, TSIM_EINVAL, "instance out of range");
+    const int N = B.N;
     std::vector<int32_t> lane, rpos, rank;
     std::vector<float> x, v;
     int rc = export_state(h, lane, x, v, rpos, rank);
     if (rc) return rc;
+    std::vector<int32_t> status(N), finish(N), pol(B.NJ), man(B.NJ);
     DevMetrics M;
-    HIPCHK(h, hipMemcpyAsync(out->status, h->D.status, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(out->finish_step, h->D.finish_step, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(out->junc_policy, h->D.junc_policy, (size_t)h->B.NJ * 4, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(out->junc_phase, h->D.junc_manual, (size_t)h->B.NJ * 4, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(&M, h->D.met, sizeof(M), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(status.data(), h->D.status, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(finish.data(), h->D.finish_step, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(pol.data(), h->D.junc_policy, (size_t)B.NJ * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(man.data(), h->D.junc_manual, (size_t)B.NJ * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&M, h->D.met + inst, sizeof(M), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     out->step = M.step;
-    for (int i = 0; i < N; ++i) {
-        const bool act = out->status[i] == TSIM_ACTIVE;
-        out->lane[i] = act ? lane[i] : -1;
-        out->x[i] = act ? x[i] : 0.0f;
-        out->v[i] = act ? v[i] : 0.0f;
-        out->route_pos[i] = act ? rpos[i] : (out->status[i] == TSIM_WAITING ? 0 : h->B.route_begin[i + 1] - h->B.route_begin[i] - 1);
+    const int vo = B.veh_off[inst], nv = B.veh_off[inst + 1] - vo;
+    const int lo = B.rl_off[inst], nrl_i = B.rl_off[inst + 1] - lo, qo = B.jl_off[inst];
+    for (int k = 0; k < nv; ++k) {
+        const int i = vo + k;
+        const bool act = status[i] == TSIM_ACTIVE;
+        int l = -1;
+        if (act) l = lane[i] < B.NRL ? lane[i] - lo : (lane[i] - B.NRL - qo) + nrl_i;
+        out->status[k] = status[i];
+        out->finish_step[k] = finish[i];
+        out->lane[k] = l;
+        out->x[k] = act ? x[i] : 0.0f;
+        out->v[k] = act ? v[i] : 0.0f;
+        out->route_pos[k] = act ? rpos[i] : (status[i] == TSIM_WAITING ? 0 : B.route_begin[i + 1] - B.route_begin[i] - 1);
+    }
+    const int jo = B.junc_off[inst], nj = B.junc_off[inst + 1] - jo;
+    for (int j = 0; j < nj; ++j) {
+        out->junc_policy[j] = pol[jo + j];
+        out->junc_phase[j] = man[jo + j];
     }
     return TSIM_OK;
+}
+
+int tsim_get_state(tsim_handle* h, tsim_state_host* out) { return get_state_impl(h, 0, out); }
+
+int tsim_batch_get_state(tsim_batch* b, int32_t instance, tsim_state_host* out)
+{
+    return get_state_impl(b, instance, out);
 }
 
 int tsim_set_state(tsim_handle* h, const tsim_state_host* in)
 {
     if (!h || !in || !in->status || !in->lane || !in->route_pos || !in->x || !in->v || !in->finish_step ||
-        !in->junc_policy || !in->junc_phase || in->step < 0)
+        !in->junc_policy || !in->junc_phase || in->step < 0 || h->B.n_inst != 1)
         return fail(nullptr, TSIM_EINVAL, "bad arguments");
     for (int j = 0; j < h->B.NJ; ++j) {
         if (in->junc_policy[j] < 0 || in->junc_policy[j] > 2) return fail(&h->err, TSIM_EINVAL, "bad policy");
@@ -865,9 +1281,21 @@ int tsim_destroy(tsim_handle* h)
     (void)hipStreamSynchronize(h->stream);
     for (int k = 0; k < 2; ++k)
         for (auto& e : h->ev[k]) (void)hipEventDestroy(e);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (int k = 0; k < 2; ++k) {
+        if (h->pin_ev[k]) (void)hipEventDestroy(h->pin_ev[k]);
+        if (h->h_pin[k]) (void)hipHostFree(h->h_pin[k]);
+    }
     delete h;
     return TSIM_OK;
 }
+
+int tsim_batch_step(tsim_batch* b, int32_t n_steps) { return tsim_step(b, n_steps); }
+
+int tsim_batch_set_graph_steps(tsim_batch* b, int32_t chunk) { return tsim_set_graph_steps(b, chunk); }
+
+int tsim_batch_destroy(tsim_batch* b) { return tsim_destroy(b); }
 
 const char* tsim_last_error(const tsim_handle* h)
 {

@@ -22,8 +22,9 @@ constexpr int kMaxTileLanes = 64;    // road lanes + junction lanes of one road
 constexpr int kMaxRoadLanes = 32;
 constexpr int kMaxPhases = 32;
 constexpr int kWave = 64;
-constexpr int kChangerCap = 128;     // lane changers per tile kept in LDS
-constexpr int kMergeCap = 128;       // merging vehicles per tile kept in LDS
+constexpr int kChangerCap = 64;      // lane changers per tile kept in LDS
+constexpr int kMergeCap = 64;        // merging vehicles per tile kept in LDS
+constexpr int kTileCap = 128;        // vehicles of a tile staged in LDS
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
 constexpr int kWaitSpeedFlag = 0;
@@ -37,6 +38,15 @@ struct __align__(16) VehRec {
     int32_t rp;   // index into the route array of the current road
     int32_t rem;  // roads of the route after the current one
     int32_t nr;   // next road of the route, -1 on the last road
+};
+
+// per-lane summary of one step's state, read by other tiles (lookahead,
+// merge priority, departure safety) so that they need a single load
+struct __align__(16) LaneSum {
+    int32_t cnt;        // vehicles in the lane
+    float rear;         // rearmost vehicle's rear bumper (x - length)
+    float rear_v;       // its speed
+    float front_reach;  // front vehicle's x + v dt + a_max dt^2/2 - lane length
 };
 
 struct KParams {
@@ -74,6 +84,16 @@ struct WGPartial {
 
 struct DevNet {
     int32_t R, NJ, NL, N, G;     // roads, junctions, lanes, vehicles, update grid size
+    // instances (a batch is the disjoint union of several networks)
+    int32_t n_inst;
+    int32_t blocked;                 // 1: each workgroup takes a contiguous run of tiles
+    const int32_t* tile_inst;        // [R] instance of each road tile
+    const int32_t* junc_inst;        // [NJ]
+    const int32_t* inst_vbase;       // [n_inst] first vehicle id of each instance
+    const uint32_t* inst_key;        // [2 n_inst] Philox key of each instance
+    const long long* inst_t0;        // [n_inst] global step at which the instance starts
+    WGPartial* inst_acc;             // [n_inst] sums of the current step (batches)
+    long long* gstep;                // global step counter
     // tiles
     const int32_t* tile_lane_begin;  // [R+1]
     const int32_t* tile_n_road;      // [R]
@@ -86,6 +106,7 @@ struct DevNet {
     const int32_t* lane_tile;        // tile (road) owning the lane
     const int32_t* lane_local;       // index within its tile
     const int32_t* jl_out;           // out lane (internal) of a junction lane, -1 for road lanes
+    const int32_t* jl_out_local;     // local index of that out lane within its own tile
     const int32_t* jl_junc;          // junction of a junction lane
     const uint32_t* jl_green_mask;   // phases (bit index) in which it is green
     const int32_t* jl_ext;           // external junction-lane index (feeder priority)
@@ -116,8 +137,10 @@ struct DevNet {
     // slabs
     VehRec* slab0;
     VehRec* slab1;
-    int32_t* cnt0;
-    int32_t* cnt1;
+    LaneSum* sum0;                   // lane summaries read at even steps
+    LaneSum* sum1;                   // lane summaries read at odd steps
+    int32_t* tile_n0;                // vehicles of each tile, read at even steps
+    int32_t* tile_n1;
     VehRec* inbox;                   // [NL]
     int32_t* inbox_flag;             // [NL]
     // per-slot scratch of the update kernel (indexed like the read slab)
@@ -136,7 +159,7 @@ struct DevNet {
     int32_t* lane_wait;              // [NL] (internal ids)
     WGPartial* part;                 // [G]
     unsigned int* done_ctr;
-    DevMetrics* met;
+    DevMetrics* met;                 // [n_inst]
     KParams P;
 };
 

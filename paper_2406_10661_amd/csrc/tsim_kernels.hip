@@ -5,16 +5,19 @@
 //              FIXED_TIME / MANUAL / NONE); one thread per road: append the
 //              junction-to-road entrant held in each road lane's inbox, then
 //              release due departures into the origin road's lanes when safe.
-//   k_update   one wavefront per road tile, grid-stride over tiles.  Pass 1:
-//              own leader (or two-lane lookahead), lane group, stop obstacle,
-//              own IDM acceleration, merge target.  Pass 2: randomized MOBIL
-//              (Appendix B.3), Philox draw, ballistic integration with snapshot
-//              bounds, lane-end transfer.  Pass 3: new per-lane order (stayers
-//              keep theirs, changers merge by position) written to the other
-//              slab buffer.  The last workgroup folds the step's metrics.
-// Reads of the step come only from slab buffer t&1 and its counts; writes go
-// to buffer (t+1)&1, the inboxes and per-vehicle status, so the update is free
-// of read/write races without any lock.
+//   k_update   one wavefront per road tile, grid-stride over tiles.  A tile of
+//              up to kTileCap vehicles is staged in LDS (records and per-vehicle
+//              scratch); larger tiles run the same code on global scratch.
+//              Pass 1: own leader (or two-lane lookahead), lane group, stop
+//              obstacle, own IDM acceleration, merge target.  Pass 2: randomized
+//              MOBIL (Appendix B.3), Philox draw, ballistic integration with
+//              snapshot bounds, lane-end transfer.  Pass 3: new per-lane order
+//              (stayers keep theirs, changers merge by position) written to the
+//              other slab buffer with the lane summaries other tiles read next
+//              step.  The last workgroup folds the step's metrics.
+// Reads of the step come only from slab buffer t&1 and its lane summaries;
+// writes go to buffer (t+1)&1, the inboxes and per-vehicle status, so the update
+// is free of read/write races without any lock.
 #include "tsim_internal.h"
 
 namespace tsim {
@@ -90,7 +93,7 @@ __device__ __forceinline__ bool jl_green(const DevNet& D, int g)
     return cur < 0 || ((D.jl_green_mask[g] >> cur) & 1u);
 }
 
-// junction lane leaving road lane m toward road nr, or -1
+// junction lane leaving road lane m toward road nr (global tables), or -1
 __device__ __forceinline__ int out_toward(const DevNet& D, int m, int nr)
 {
     if (nr < 0) return -1;
@@ -101,64 +104,27 @@ __device__ __forceinline__ int out_toward(const DevNet& D, int m, int nr)
     return -1;
 }
 
-// leader substitution when lane m has nobody ahead: rearmost vehicle of the
-// next lane of the route, else of the lane after it
-__device__ Lead lookahead(const DevNet& D, const VehRec* slab, const int32_t* cnt, int m, bool m_is_jl, int nr,
-                          int rp, int rem)
+__device__ __forceinline__ float front_reach(float x, float v, float len, const KParams& P)
 {
-    Lead L{TS_INF, 0.0f, false};
-    const int g1 = m_is_jl ? D.jl_out[m] : out_toward(D, m, nr);
-    if (g1 < 0) return L;
-    const float off = D.lane_len[m];
-    const int c1 = cnt[g1];
-    if (c1 > 0) {
-        const VehRec z = slab[D.lane_base[g1] + c1 - 1];
-        L.ex = true;
-        L.rear = off + (z.x - z.len);
-        L.v = z.v;
-        return L;
-    }
-    int g2;
-    if (m_is_jl) {
-        if (rem < 2) return L;
-        g2 = out_toward(D, g1, D.route[rp + 2]);
-    } else {
-        g2 = D.jl_out[g1];
-    }
-    if (g2 < 0) return L;
-    const int c2 = cnt[g2];
-    if (c2 > 0) {
-        const VehRec z = slab[D.lane_base[g2] + c2 - 1];
-        L.ex = true;
-        L.rear = (off + D.lane_len[g1]) + (z.x - z.len);
-        L.v = z.v;
-    }
-    return L;
-}
-
-// stop obstacle at the end of road lane m: red next junction lane, or (with
-// with_wrong) no connection to the next road
-__device__ __forceinline__ bool stop_end(const DevNet& D, int m, bool m_is_jl, int nr, bool with_wrong)
-{
-    if (m_is_jl || nr < 0) return false;
-    const int g = out_toward(D, m, nr);
-    if (g < 0) return with_wrong;
-    return !jl_green(D, g);
+    return x + v * P.dt + P.reach - len;
 }
 
 // ---------------------------------------------------------------------------
 // prepare
 // ---------------------------------------------------------------------------
-__global__ void k_prepare(DevNet D)
+__global__ void k_prepare(const DevNet* __restrict__ Dp)
 {
-    const long long t = D.met->step;
-    const int p = (int)(t & 1);
+    const DevNet& D = *Dp;
+    const long long tg = *D.gstep;
+    const int p = (int)(tg & 1);
     VehRec* slab = p ? D.slab1 : D.slab0;
-    int32_t* cnt = p ? D.cnt1 : D.cnt0;
+    LaneSum* sum = p ? D.sum1 : D.sum0;
+    int32_t* tile_n = p ? D.tile_n1 : D.tile_n0;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const KParams& P = D.P;
 
     if (i < D.NJ) {
+        const long long t = tg - D.inst_t0[D.junc_inst[i]];
         const int b = D.junc_phase_begin[i], e = D.junc_phase_begin[i + 1];
         int cur = -1;
         const int pol = D.junc_policy[i];
@@ -183,16 +149,25 @@ __global__ void k_prepare(DevNet D)
     }
     if (i >= D.R) return;
     const int r = i;
+    const int inst = D.tile_inst[r];
+    const long long t = tg - D.inst_t0[inst];
     const int lb = D.tile_lane_begin[r];
     const int nrl = D.tile_n_road[r];
     long long errors = 0;
+    int appended = 0;
     for (int li = 0; li < nrl; ++li) {
         const int m = lb + li;
         if (D.inbox_flag[m]) {
-            const int c = cnt[m];
-            if (c < D.lane_cap[m]) {
-                slab[D.lane_base[m] + c] = D.inbox[m];
-                cnt[m] = c + 1;
+            LaneSum s = sum[m];
+            const VehRec z = D.inbox[m];
+            if (s.cnt < D.lane_cap[m]) {
+                slab[D.lane_base[m] + s.cnt] = z;
+                if (s.cnt == 0) s.front_reach = front_reach(z.x, z.v, D.lane_len[m], P);
+                s.cnt += 1;
+                s.rear = z.x - z.len;
+                s.rear_v = z.v;
+                sum[m] = s;
+                appended++;
             } else {
                 errors++;
             }
@@ -224,20 +199,14 @@ __global__ void k_prepare(DevNet D)
             if (nr >= 0 && out_toward(D, m, nr) < 0) continue;
             bool safe = true;
             for (int e = D.feed_begin[m]; e < D.feed_begin[m + 1]; ++e) {
-                const int fl = D.feed_jl[e];
-                const int cf = cnt[fl];
-                if (cf == 0) continue;
-                const VehRec h = slab[D.lane_base[fl]];
-                const float mg = -Lv - (h.x + h.v * P.dt + P.reach - D.lane_len[fl]);
+                const LaneSum f = sum[D.feed_jl[e]];
+                if (f.cnt == 0) continue;
+                const float mg = -Lv - f.front_reach;
                 if (!(mg >= 0.0f)) safe = false;
             }
             if (!safe) continue;
-            const int c = cnt[m];
-            float room = TS_INF;
-            if (c > 0) {
-                const VehRec z = slab[D.lane_base[m] + c - 1];
-                room = z.x - z.len;
-            }
+            const LaneSum s = sum[m];
+            const float room = s.cnt > 0 ? s.rear : TS_INF;
             if (room > best_room) {
                 best_room = room;
                 best = li;
@@ -245,8 +214,8 @@ __global__ void k_prepare(DevNet D)
         }
         if (best < 0 || !(best_room >= P.s0)) break;
         const int m = lb + best;
-        const int c = cnt[m];
-        if (c >= D.lane_cap[m]) {
+        LaneSum s = sum[m];
+        if (s.cnt >= D.lane_cap[m]) {
             errors++;
             break;
         }
@@ -259,19 +228,24 @@ __global__ void k_prepare(DevNet D)
         nrec.rp = rb;
         nrec.rem = rl - 1;
         nrec.nr = nr;
-        slab[D.lane_base[m] + c] = nrec;
-        cnt[m] = c + 1;
+        slab[D.lane_base[m] + s.cnt] = nrec;
+        if (s.cnt == 0) s.front_reach = front_reach(0.0f, 0.0f, D.lane_len[m], P);
+        s.cnt += 1;
+        s.rear = 0.0f - Lv;
+        s.rear_v = 0.0f;
+        sum[m] = s;
         D.status[v] = 1;
         used |= 1u << best;
         departed++;
         head++;
     }
     D.q_head[r] = head;
+    if (appended + departed) tile_n[r] += appended + departed;
     if (departed) {
-        atomicAdd((unsigned long long*)&D.met->departed, (unsigned long long)departed);
-        atomicAdd((unsigned long long*)&D.met->dep_events, (unsigned long long)departed);
+        atomicAdd((unsigned long long*)&D.met[inst].departed, (unsigned long long)departed);
+        atomicAdd((unsigned long long*)&D.met[inst].dep_events, (unsigned long long)departed);
     }
-    if (errors) atomicAdd((unsigned long long*)&D.met->errors, (unsigned long long)errors);
+    if (errors) atomicAdd((unsigned long long*)&D.met[inst].errors, (unsigned long long)errors);
 }
 
 // ---------------------------------------------------------------------------
@@ -290,13 +264,15 @@ struct TileShared {
     uint32_t base[kMaxTileLanes];
     float len[kMaxTileLanes];
     float lim[kMaxTileLanes];
+    int jl_out[kMaxTileLanes];
     int jl_out_road[kMaxTileLanes];
     int jl_in_local[kMaxTileLanes];
+    int green[kMaxTileLanes];
     int nstay[kMaxTileLanes];
     int nin[kMaxTileLanes];
     int nenter[kMaxTileLanes];
     int wait[kMaxTileLanes];
-    int nlanes, nroad, n;
+    int nlanes, nroad, n, skip;
     int nchg, nmerge;
     float chg_x[kChangerCap];
     int chg_vid[kChangerCap];
@@ -306,9 +282,21 @@ struct TileShared {
     float mrg_v[kMergeCap];
     int mrg_vid[kMergeCap];
     unsigned long long sumv;
+    unsigned long long sum_tt;
     int cntv;
     int changes, transfers, clamps, fblocks, finished, errors;
-    unsigned long long sum_tt;
+    // staged tile (n <= kTileCap)
+    VehRec rec[kTileCap];
+    float aown[kTileCap];
+    float lrear[kTileCap];
+    float lv[kTileCap];
+    float nx[kTileCap];
+    float nv[kTileCap];
+    uint32_t gmask[kTileCap];
+    int pref[kTileCap];
+    signed char merge[kTileCap];
+    signed char kind[kTileCap];
+    signed char nlane[kTileCap];
 };
 
 __device__ __forceinline__ int lane_of(const TileShared& S, int j)
@@ -318,7 +306,81 @@ __device__ __forceinline__ int lane_of(const TileShared& S, int j)
     return li;
 }
 
-// nearest lane of the group (bit set) to local lane li; ties to the left
+// per-vehicle storage of a tile staged in LDS, indexed by the tile
+// enumeration j (lanes in order, front first)
+struct LdsView {
+    TileShared& S;
+    __device__ VehRec rec(int j) const { return S.rec[j]; }
+    __device__ float aown(int j) const { return S.aown[j]; }
+    __device__ float lrear(int j) const { return S.lrear[j]; }
+    __device__ float lv(int j) const { return S.lv[j]; }
+    __device__ float nx(int j) const { return S.nx[j]; }
+    __device__ float nv(int j) const { return S.nv[j]; }
+    __device__ uint32_t gmask(int j) const { return S.gmask[j]; }
+    __device__ int merge(int j) const { return S.merge[j]; }
+    __device__ int kind(int j) const { return S.kind[j]; }
+    __device__ int nlane(int j) const { return S.nlane[j]; }
+    __device__ int pref(int j) const { return S.pref[j]; }
+    __device__ void set1(int j, uint32_t g, float a, int mt, float lr, float lvv)
+    {
+        S.gmask[j] = g;
+        S.aown[j] = a;
+        S.merge[j] = (signed char)mt;
+        S.lrear[j] = lr;
+        S.lv[j] = lvv;
+    }
+    __device__ void set2(int j, float x, float v, int kind, int nl)
+    {
+        S.nx[j] = x;
+        S.nv[j] = v;
+        S.kind[j] = (signed char)kind;
+        S.nlane[j] = (signed char)nl;
+    }
+    __device__ void set_pref(int j, int v) { S.pref[j] = v; }
+};
+
+// the same storage in global per-slot scratch, for tiles larger than kTileCap
+struct GlobalView {
+    TileShared& S;
+    const DevNet& D;
+    const VehRec* rd;
+    __device__ uint32_t slot(int j) const
+    {
+        const int li = lane_of(S, j);
+        return S.base[li] + (uint32_t)(j - S.start[li]);
+    }
+    __device__ VehRec rec(int j) const { return rd[slot(j)]; }
+    __device__ float aown(int j) const { return D.sh_aown[slot(j)]; }
+    __device__ float lrear(int j) const { return D.sh_lrear[slot(j)]; }
+    __device__ float lv(int j) const { return D.sh_lv[slot(j)]; }
+    __device__ float nx(int j) const { return D.sh_nx[slot(j)]; }
+    __device__ float nv(int j) const { return D.sh_nv[slot(j)]; }
+    __device__ uint32_t gmask(int j) const { return D.sh_gmask[slot(j)]; }
+    __device__ int merge(int j) const { return D.sh_merge[slot(j)]; }
+    __device__ int kind(int j) const { return D.sh_kind[slot(j)]; }
+    __device__ int nlane(int j) const { return D.sh_nlane[slot(j)]; }
+    __device__ int pref(int j) const { return D.sh_pref[slot(j)]; }
+    __device__ void set1(int j, uint32_t g, float a, int mt, float lr, float lvv)
+    {
+        const uint32_t s = slot(j);
+        D.sh_gmask[s] = g;
+        D.sh_aown[s] = a;
+        D.sh_merge[s] = mt;
+        D.sh_lrear[s] = lr;
+        D.sh_lv[s] = lvv;
+    }
+    __device__ void set2(int j, float x, float v, int kind, int nl)
+    {
+        const uint32_t s = slot(j);
+        D.sh_nx[s] = x;
+        D.sh_nv[s] = v;
+        D.sh_kind[s] = kind;
+        D.sh_nlane[s] = nl;
+    }
+    __device__ void set_pref(int j, int v) { D.sh_pref[slot(j)] = v; }
+};
+
+// nearest lane of the group (bit set) to local lane li
 __device__ __forceinline__ int group_dist(uint32_t gmask, int li, int nroad)
 {
     int best = 1 << 20;
@@ -330,48 +392,561 @@ __device__ __forceinline__ int group_dist(uint32_t gmask, int li, int nroad)
     return best;
 }
 
-// number of vehicles of tile lane li (front first) ahead of (x, vid)
-__device__ __forceinline__ int count_ahead(const TileShared& S, const VehRec* slab, int li, float x, int vid)
+// tile junction lane (local index) leaving local road lane li toward road nr
+__device__ __forceinline__ int tile_jl(const TileShared& S, int li, int nr)
+{
+    if (nr < 0) return -1;
+    for (int q = S.nroad; q < S.nlanes; ++q)
+        if (S.jl_in_local[q] == li && S.jl_out_road[q] == nr) return q;
+    return -1;
+}
+
+__device__ __forceinline__ bool tile_stop(const TileShared& S, int li, int nr, bool with_wrong)
+{
+    if (li >= S.nroad || nr < 0) return false;
+    const int q = tile_jl(S, li, nr);
+    if (q < 0) return with_wrong;
+    return !S.green[q];
+}
+
+// number of vehicles of tile lane li ahead of (x, vid)
+template <class V>
+__device__ __forceinline__ int count_ahead(const TileShared& S, const V& view, int li, float x, int vid)
 {
     int lo = 0, hi = S.cnt[li];
-    const uint32_t b = S.base[li];
+    const int b = S.start[li];
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        const VehRec z = slab[b + mid];
+        const VehRec z = view.rec(b + mid);
         if (ahead(z.x, z.vid, x, vid)) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-__global__ __launch_bounds__(kWave) void k_update(DevNet D)
+// leader substitution for a vehicle at the front of tile lane li (route info
+// nr, rp, rem): rearmost vehicle of the next lane, else of the lane after it
+template <class V>
+__device__ Lead lookahead(const DevNet& D, const TileShared& S, const V& view, const LaneSum* sum, int li, int nr,
+                          int rp, int rem)
+{
+    Lead L{TS_INF, 0.0f, false};
+    const float off = S.len[li];
+    if (li < S.nroad) {
+        const int q = tile_jl(S, li, nr);
+        if (q < 0) return L;
+        if (S.cnt[q] > 0) {
+            const VehRec z = view.rec(S.start[q] + S.cnt[q] - 1);
+            L.ex = true;
+            L.rear = off + (z.x - z.len);
+            L.v = z.v;
+            return L;
+        }
+        const LaneSum s2 = sum[S.jl_out[q]];
+        if (s2.cnt > 0) {
+            L.ex = true;
+            L.rear = (off + S.len[q]) + s2.rear;
+            L.v = s2.rear_v;
+        }
+        return L;
+    }
+    const int g1 = S.jl_out[li];
+    const LaneSum s1 = sum[g1];
+    if (s1.cnt > 0) {
+        L.ex = true;
+        L.rear = off + s1.rear;
+        L.v = s1.rear_v;
+        return L;
+    }
+    if (rem < 2) return L;
+    const int g2 = out_toward(D, g1, D.route[rp + 2]);
+    if (g2 < 0) return L;
+    const LaneSum s2 = sum[g2];
+    if (s2.cnt > 0) {
+        L.ex = true;
+        L.rear = (off + D.lane_len[g1]) + s2.rear;
+        L.v = s2.rear_v;
+    }
+    return L;
+}
+
+template <class V>
+__device__ void process_tile(const DevNet& D, TileShared& S, V& view, const LaneSum* rsum, LaneSum* wsum,
+                             VehRec* wr, long long t, int inst, int tid)
+{
+    const uint32_t key0 = D.inst_key[2 * inst], key1 = D.inst_key[2 * inst + 1];
+    const int vbase = D.inst_vbase[inst];
+    const KParams& P = D.P;
+    const int n = S.n;
+    const int nl = S.nlanes;
+    const int nroad = S.nroad;
+
+    // ---------------- pass 1: own acceleration ----------------
+    for (int j = tid; j < n; j += kWave) {
+        const int li = lane_of(S, j);
+        const int c = j - S.start[li];
+        const VehRec rec = view.rec(j);
+        const bool is_jl = li >= nroad;
+        uint32_t gmask = 0u;
+        if (!is_jl) {
+            if (rec.nr < 0) {
+                gmask = nroad >= 32 ? 0xFFFFFFFFu : ((1u << nroad) - 1u);
+            } else {
+                for (int q = nroad; q < nl; ++q)
+                    if (S.jl_out_road[q] == rec.nr) gmask |= 1u << S.jl_in_local[q];
+            }
+        }
+        Lead ld;
+        if (c > 0) {
+            const VehRec z = view.rec(j - 1);
+            ld.ex = true;
+            ld.rear = z.x - z.len;
+            ld.v = z.v;
+        } else {
+            ld = lookahead(D, S, view, rsum, li, rec.nr, rec.rp, rec.rem);
+        }
+        const bool stop = tile_stop(S, li, rec.nr, true);
+        const float a = accel(rec.v, rec.f * S.lim[li], rec.x, ld, stop, S.len[li], P);
+        int mt = -1;
+        if (!is_jl && rec.nr >= 0 && !((gmask >> li) & 1u)) {
+            int bl = -1, bd = 1 << 20;
+            for (int b = 0; b < nroad; ++b)
+                if ((gmask >> b) & 1u) {
+                    const int d = b > li ? b - li : li - b;
+                    if (d < bd) {
+                        bd = d;
+                        bl = b;
+                    }
+                }
+            if (bl >= 0) mt = bl < li ? li - 1 : li + 1;
+        }
+        view.set1(j, gmask, a, mt, ld.ex ? ld.rear : TS_INF, ld.v);
+        if (mt >= 0) {
+            const int k = atomicAdd(&S.nmerge, 1);
+            if (k < kMergeCap) {
+                S.mrg_tgt[k] = mt;
+                S.mrg_rear[k] = rec.x - rec.len;
+                S.mrg_v[k] = rec.v;
+                S.mrg_vid[k] = rec.vid;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- pass 2: decision and motion ----------------
+    for (int j = tid; j < n; j += kWave) {
+        const int li = lane_of(S, j);
+        const int c = j - S.start[li];
+        const VehRec rec = view.rec(j);
+        const bool is_jl = li >= nroad;
+        const int m = S.lane[li];
+        const float len = S.len[li];
+        const float lim = S.lim[li];
+        const float v0 = rec.f * lim;
+        const float a_e = view.aown(j);
+        const uint32_t gmask = view.gmask(j);
+        const int my_mt = view.merge(j);
+        const bool in_g = !is_jl && ((gmask >> li) & 1u);
+        const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
+        // MOBIL for one direction: utility (or -inf), prospective
+        // acceleration, and the target-lane leader used as a bound
+        auto eval_dir = [&](int d) -> DirEval {
+            DirEval o;
+            o.u = -TS_INF;
+            o.ta = 0.0f;
+            o.lead.ex = false;
+            o.lead.rear = TS_INF;
+            o.lead.v = 0.0f;
+            if (is_jl) return o;
+            const int k = li + d;
+            if (k < 0 || k >= nroad) return o;
+            if (in_g) {
+                if (!((gmask >> k) & 1u)) return o;
+            } else if (!(group_dist(gmask, k, nroad) < dist_l)) {
+                return o;
+            }
+            const int pos = count_ahead(S, view, k, rec.x, rec.vid);
+            const int tl = pos > 0 ? S.start[k] + pos - 1 : -1;
+            const int tf = pos < S.cnt[k] ? S.start[k] + pos : -1;
+            VehRec tlr{}, tfr{};
+            if (tl >= 0) tlr = view.rec(tl);
+            if (tf >= 0) tfr = view.rec(tf);
+            // same gap of k held by a vehicle two lanes right (rightward only)
+            if (d > 0 && k + 1 < nroad) {
+                const int lo2 = tl >= 0 ? count_ahead(S, view, k + 1, tlr.x, tlr.vid) : 0;
+                const int hi2 = tf >= 0 ? count_ahead(S, view, k + 1, tfr.x, tfr.vid) : S.cnt[k + 1];
+                if (lo2 < hi2) return o;
+            }
+            Lead tld;
+            if (tl >= 0) {
+                tld.ex = true;
+                tld.rear = tlr.x - tlr.len;
+                tld.v = tlr.v;
+            } else {
+                tld = lookahead(D, S, view, rsum, k, rec.nr, rec.rp, rec.rem);
+            }
+            const float g3 = tld.ex ? tld.rear - rec.x : TS_INF;
+            if (!(g3 > 0.0f)) return o;
+            const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
+            if (tf >= 0 && !tf_yields) {
+                const float g4 = rec.x - rec.len - tfr.x - (tfr.v * P.dt + P.reach);
+                if (!(g4 >= 0.0f)) return o;
+            }
+            if (tf < 0) {
+                const int mk = S.lane[k];
+                for (int e = D.feed_begin[mk]; e < D.feed_begin[mk + 1]; ++e) {
+                    const LaneSum f = rsum[D.feed_jl[e]];
+                    if (f.cnt == 0) continue;
+                    const float g = (rec.x - rec.len) - f.front_reach;
+                    if (!(g >= 0.0f)) return o;
+                }
+            }
+            const float ta_e = accel(rec.v, v0, rec.x, tld, tile_stop(S, k, rec.nr, false), len, P);
+            float d_new = 0.0f, d_old = 0.0f;
+            if (tf >= 0) {
+                const float a_tf = view.aown(tf);
+                const Lead me_lead{rec.x - rec.len, rec.v, true};
+                const float ta_tf = accel(tfr.v, tfr.f * lim, tfr.x, me_lead, tile_stop(S, k, tfr.nr, true), len, P);
+                if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
+                d_new = ta_tf - a_tf;
+            }
+            if (c + 1 < S.cnt[li]) {
+                const VehRec ofr = view.rec(j + 1);
+                const float a_of = view.aown(j + 1);
+                Lead ol;
+                if (c > 0) {
+                    const VehRec z = view.rec(j - 1);
+                    ol.ex = true;
+                    ol.rear = z.x - z.len;
+                    ol.v = z.v;
+                } else {
+                    ol = lookahead(D, S, view, rsum, li, ofr.nr, ofr.rp, ofr.rem);
+                }
+                const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, tile_stop(S, li, ofr.nr, true), len, P);
+                d_old = ta_of - a_of;
+            }
+            const float da = (ta_e - a_e) + P.p * (d_new + d_old);
+            float ud = da - P.a_th;
+            if (!in_g) ud = fmaxf(ud, 1.0f);
+            o.u = ud;
+            o.ta = ta_e;
+            o.lead = tld;
+            return o;
+        };
+        DirEval eL, eR;
+#pragma unroll 1
+        for (int di = 0; di < 2; ++di) {
+            const DirEval e = eval_dir(di ? 1 : -1);
+            if (di) eR = e;
+            else eL = e;
+        }
+        // randomized decision
+        const float uLp = fmaxf(0.0f, eL.u), uRp = fmaxf(0.0f, eR.u);
+        const float uT = uLp + uRp;
+        const float pLC = uT >= 1.0f ? P.p_max : (uT > 0.0f ? P.p_min + (P.p_max - P.p_min) * uT : P.p_min);
+        const uint32_t w = philox_word0(key0, key1, (uint32_t)(rec.vid - vbase), (uint32_t)t);
+        const float rr = (float)w * 2.3283064365386963e-10f;  // 2^-32
+        int dec = 0;
+        if (uT > 0.0f) {
+            const float bL = pLC * uLp / uT;
+            if (uLp > 0.0f && rr < bL) dec = 1;
+            else if (uRp > 0.0f && rr >= bL && rr < pLC) dec = 2;
+        } else {
+            const bool fL = eL.u > -TS_INF, fR = eR.u > -TS_INF;
+            if (fL && fR) {
+                if (rr < 0.5f * P.p_min) dec = 1;
+                else if (rr < P.p_min) dec = 2;
+            } else if (fL || fR) {
+                if (rr < P.p_min) dec = fL ? 1 : 2;
+            }
+        }
+        const int nli = dec == 1 ? li - 1 : (dec == 2 ? li + 1 : li);
+        float a = dec == 1 ? eL.ta : (dec == 2 ? eR.ta : a_e);
+        // cooperative yielding of lane keepers to vehicles merging into their lane
+        bool has_y = false;
+        float y_rear = TS_INF, y_v = 0.0f;
+        if (!is_jl && !dec) {
+            int y_vid = 0x7FFFFFFF;
+            const int nm = S.nmerge;
+            if (nm <= kMergeCap) {
+                for (int q = 0; q < nm; ++q) {
+                    if (S.mrg_tgt[q] != li) continue;
+                    const float rm = S.mrg_rear[q];
+                    if (!(rm > rec.x)) continue;
+                    if (!has_y || rm < y_rear || (rm == y_rear && S.mrg_vid[q] < y_vid)) {
+                        has_y = true;
+                        y_rear = rm;
+                        y_v = S.mrg_v[q];
+                        y_vid = S.mrg_vid[q];
+                    }
+                }
+            } else {
+                for (int dd = -1; dd <= 1; dd += 2) {
+                    const int k2 = li + dd;
+                    if (k2 < 0 || k2 >= nroad) continue;
+                    for (int q = 0; q < S.cnt[k2]; ++q) {
+                        const int j2 = S.start[k2] + q;
+                        if (view.merge(j2) != li) continue;
+                        const VehRec z = view.rec(j2);
+                        const float rm = z.x - z.len;
+                        if (!(rm > rec.x)) continue;
+                        if (!has_y || rm < y_rear || (rm == y_rear && z.vid < y_vid)) {
+                            has_y = true;
+                            y_rear = rm;
+                            y_v = z.v;
+                            y_vid = z.vid;
+                        }
+                    }
+                }
+            }
+            if (has_y) a = fminf(a, idm_follow(rec.v, v0, y_rear - rec.x, rec.v - y_v, P));
+        }
+        // ballistic update with in-step stop
+        const float x = rec.x, v = rec.v;
+        const float vh = v + a * P.dt;
+        float xn, vn;
+        if (vh >= 0.0f) {
+            xn = x + v * P.dt + 0.5f * a * P.dt * P.dt;
+            vn = vh;
+        } else {
+            xn = x - v * v / (2.0f * a);
+            vn = 0.0f;
+        }
+        // snapshot bounds
+        float B = TS_INF, vcap = TS_INF;
+        const float lr = view.lrear(j);
+        if (lr < TS_INF) {
+            B = lr;
+            vcap = view.lv(j);
+        }
+        if (dec) {
+            const Lead l2 = dec == 1 ? eL.lead : eR.lead;
+            if (l2.ex) {
+                if (l2.rear < B) {
+                    B = l2.rear;
+                    vcap = l2.v;
+                } else if (l2.rear == B) {
+                    vcap = fminf(vcap, l2.v);
+                }
+            }
+        }
+        if (has_y) {
+            if (y_rear < B) {
+                B = y_rear;
+                vcap = y_v;
+            } else if (y_rear == B) {
+                vcap = fminf(vcap, y_v);
+            }
+        }
+        if (tile_stop(S, nli, rec.nr, true)) {
+            if (len < B) {
+                B = len;
+                vcap = 0.0f;
+            } else if (len == B) {
+                vcap = 0.0f;
+            }
+        }
+        if (xn > B) {
+            xn = fmaxf(B, x);
+            vn = fminf(vn, vcap);
+            atomicAdd(&S.clamps, 1);
+        }
+        int kind = dec ? 1 : 0;
+        int tgt_local = nli;
+        if (xn > len) {
+            if (!is_jl && rec.rem == 0) {
+                kind = 4;
+                D.status[rec.vid] = 2;
+                D.finish_step[rec.vid] = (int)t;
+                const double tt = (double)(t + 1) * P.dt_d - (double)D.tau[rec.vid];
+                atomicAdd(&S.sum_tt, (unsigned long long)llrint(tt * kTimeFx));
+                atomicAdd(&S.finished, 1);
+            } else if (!is_jl) {
+                kind = 2;
+                tgt_local = tile_jl(S, nli, rec.nr);
+                xn -= len;
+                atomicAdd(&S.transfers, 1);
+            } else {
+                const int g = S.jl_out[li];
+                bool blocked = false;
+                const int my_ext = D.jl_ext[m];
+                for (int e = D.feed_begin[g]; e < D.feed_begin[g + 1]; ++e) {
+                    const int fl = D.feed_jl[e];
+                    if (D.jl_ext[fl] >= my_ext) break;
+                    const LaneSum f = rsum[fl];
+                    if (f.cnt == 0) continue;
+                    if (f.front_reach > 0.0f) blocked = true;
+                }
+                if (blocked) {
+                    xn = len;
+                    vn = 0.0f;
+                    atomicAdd(&S.fblocks, 1);
+                } else {
+                    kind = 3;
+                    VehRec o;
+                    o.x = xn - len;
+                    o.v = vn;
+                    o.vid = rec.vid;
+                    o.len = rec.len;
+                    o.f = rec.f;
+                    o.rp = rec.rp + 1;
+                    o.rem = rec.rem - 1;
+                    o.nr = rec.rem - 1 > 0 ? D.route[rec.rp + 2] : -1;
+                    if (atomicCAS(&D.inbox_flag[g], 0, 1) != 0) atomicAdd(&S.errors, 1);
+                    D.inbox[g] = o;
+                    atomicAdd(&S.transfers, 1);
+                }
+            }
+        }
+        if (dec) atomicAdd(&S.changes, 1);
+        // metrics: a vehicle counts for the lane it occupied at the step start
+        if (!is_jl) {
+            atomicAdd(&S.sumv, (unsigned long long)(long long)llrintf(vn * kSpeedFx));
+            atomicAdd(&S.cntv, 1);
+        }
+        if (vn < 0.1f) atomicAdd(&S.wait[li], 1);
+        view.set2(j, xn, vn, kind, tgt_local);
+        if (kind == 0) {
+            atomicAdd(&S.nstay[li], 1);
+        } else if (kind == 1) {
+            atomicAdd(&S.nin[nli], 1);
+            const int q = atomicAdd(&S.nchg, 1);
+            if (q < kChangerCap) {
+                S.chg_x[q] = xn;
+                S.chg_vid[q] = rec.vid;
+                S.chg_lane[q] = nli;
+            }
+        } else if (kind == 2) {
+            if (atomicAdd(&S.nenter[tgt_local], 1) != 0) atomicAdd(&S.errors, 1);
+        }
+    }
+    __syncthreads();
+
+    // ---------------- pass 3: new order ----------------
+    {
+        int carry = 0;
+        for (int b0 = 0; b0 < n; b0 += kWave) {
+            const int j = b0 + tid;
+            const bool st = j < n && view.kind(j) == 0;
+            const unsigned long long bal = __ballot(st);
+            if (j < n) view.set_pref(j, carry + __popcll(bal & ((1ull << tid) - 1ull)));
+            carry += __popcll(bal);
+        }
+    }
+    __syncthreads();
+    const int nchg = S.nchg;
+    for (int j = tid; j < n; j += kWave) {
+        const int kind = view.kind(j);
+        if (kind >= 3) continue;
+        const int li = lane_of(S, j);
+        const VehRec rec = view.rec(j);
+        const float xn = view.nx(j);
+        const int nli = view.nlane(j);
+        int rank = 0;
+        if (kind == 0) {
+            rank = view.pref(j) - view.pref(S.start[li]);
+        } else if (kind == 1) {
+            for (int q = 0; q < S.cnt[nli]; ++q) {
+                const int j2 = S.start[nli] + q;
+                if (view.kind(j2) != 0) continue;
+                if (ahead(view.nx(j2), view.rec(j2).vid, xn, rec.vid)) rank++;
+            }
+        } else {
+            rank = S.nstay[nli];
+        }
+        if (kind <= 1) {
+            // changers into the same lane ahead of this vehicle
+            if (nchg <= kChangerCap) {
+                for (int q = 0; q < nchg; ++q)
+                    if (S.chg_lane[q] == nli && S.chg_vid[q] != rec.vid && ahead(S.chg_x[q], S.chg_vid[q], xn, rec.vid))
+                        rank++;
+            } else {
+                for (int dd = -1; dd <= 1; dd += 2) {
+                    const int k2 = nli + dd;
+                    if (k2 < 0 || k2 >= nroad) continue;
+                    for (int q = 0; q < S.cnt[k2]; ++q) {
+                        const int j2 = S.start[k2] + q;
+                        if (view.kind(j2) != 1 || view.nlane(j2) != nli) continue;
+                        const int ov = view.rec(j2).vid;
+                        if (ov != rec.vid && ahead(view.nx(j2), ov, xn, rec.vid)) rank++;
+                    }
+                }
+            }
+        }
+        const int mn = S.lane[nli];
+        const int total = S.nstay[nli] + S.nin[nli] + S.nenter[nli];
+        if (rank < D.lane_cap[mn]) {
+            VehRec o = rec;
+            o.x = xn;
+            o.v = view.nv(j);
+            wr[S.base[nli] + rank] = o;
+            if (rank == 0) wsum[mn].front_reach = front_reach(o.x, o.v, S.len[nli], P);
+            if (rank == total - 1) {
+                wsum[mn].rear = o.x - o.len;
+                wsum[mn].rear_v = o.v;
+            }
+        } else {
+            atomicAdd(&S.errors, 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_update(const DevNet* __restrict__ Dp)
 {
     __shared__ TileShared S;
-    const long long t = D.met->step;
-    const int p = (int)(t & 1);
+    const DevNet& D = *Dp;
+    const long long tg = *D.gstep;
+    const int p = (int)(tg & 1);
     const VehRec* rd = p ? D.slab1 : D.slab0;
     VehRec* wr = p ? D.slab0 : D.slab1;
-    const int32_t* rcnt = p ? D.cnt1 : D.cnt0;
-    int32_t* wcnt = p ? D.cnt0 : D.cnt1;
-    const KParams& P = D.P;
+    const LaneSum* rsum = p ? D.sum1 : D.sum0;
+    LaneSum* wsum = p ? D.sum0 : D.sum1;
+    const int32_t* rtn = p ? D.tile_n1 : D.tile_n0;
+    int32_t* wtn = p ? D.tile_n0 : D.tile_n1;
     const int tid = threadIdx.x;
 
     WGPartial acc{};
+    int acc_inst = -1;
+    // batches: flush the running sums into the instance they belong to
+    auto flush = [&]() {
+        if (acc_inst < 0 || tid != 0) return;
+        unsigned long long* q = (unsigned long long*)&D.inst_acc[acc_inst];
+        const long long* a = (const long long*)&acc;
+        for (int k = 0; k < 10; ++k)
+            if (a[k]) atomicAdd(q + k, (unsigned long long)a[k]);
+    };
+    const int chunk = (D.R + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t_begin = D.blocked ? (int)blockIdx.x * chunk : (int)blockIdx.x;
+    const int t_end = D.blocked ? min(D.R, t_begin + chunk) : D.R;
+    const int t_stride = D.blocked ? 1 : (int)gridDim.x;
 
-    for (int ti = blockIdx.x; ti < D.R; ti += gridDim.x) {
+    for (int ti = t_begin; ti < t_end; ti += t_stride) {
         const int r = D.tile_order[ti];
+        // a tile empty now and at the previous step already has empty
+        // summaries, zero queue counts and no road speed in both buffers
+        if (rtn[r] == 0 && wtn[r] == 0) continue;
+        const int inst = D.tile_inst[r];
+        const long long t = tg - D.inst_t0[inst];
+        if (D.n_inst > 1 && inst != acc_inst) {
+            flush();
+            acc = WGPartial{};
+            acc_inst = inst;
+        }
         const int lb = D.tile_lane_begin[r];
         const int nl = D.tile_lane_begin[r + 1] - lb;
         const int nroad = D.tile_n_road[r];
         if (tid < nl) {
             const int m = lb + tid;
             S.lane[tid] = m;
-            S.cnt[tid] = rcnt[m];
+            S.cnt[tid] = rsum[m].cnt;
             S.base[tid] = D.lane_base[m];
             S.len[tid] = D.lane_len[m];
             S.lim[tid] = D.lane_lim[m];
-            S.jl_out_road[tid] = tid >= nroad ? D.jl_out_road[m] : -1;
-            S.jl_in_local[tid] = tid >= nroad ? D.jl_in_local[m] : -1;
+            const bool jl = tid >= nroad;
+            S.jl_out[tid] = jl ? D.jl_out[m] : -1;
+            S.jl_out_road[tid] = jl ? D.jl_out_road[m] : -1;
+            S.jl_in_local[tid] = jl ? D.jl_in_local[m] : -1;
+            S.green[tid] = jl ? (int)jl_green(D, m) : 1;
             S.nstay[tid] = 0;
             S.nin[tid] = 0;
             S.nenter[tid] = 0;
@@ -388,458 +963,65 @@ __global__ __launch_bounds__(kWave) void k_update(DevNet D)
             S.sum_tt = 0ull;
         }
         __syncthreads();
-        if (tid == 0) {
-            int s = 0;
-            for (int li = 0; li < nl; ++li) {
-                S.start[li] = s;
-                s += S.cnt[li];
+        // lane starts of the tile enumeration (inclusive scan across the wave)
+        {
+            int c = tid < nl ? S.cnt[tid] : 0;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int y = __shfl_up(c, off);
+                if (tid >= off) c += y;
             }
-            S.start[nl] = s;
-            S.n = s;
+            if (tid < nl) S.start[tid + 1] = c;
+            if (tid == 0) S.start[0] = 0;
+            if (tid == kWave - 1) S.n = c;
         }
         __syncthreads();
         const int n = S.n;
         if (n == 0) {
             if (tid < nl) {
-                wcnt[lb + tid] = 0;
+                LaneSum e;
+                e.cnt = 0;
+                e.rear = TS_INF;
+                e.rear_v = 0.0f;
+                e.front_reach = -TS_INF;
+                wsum[lb + tid] = e;
                 D.lane_wait[lb + tid] = 0;
             }
-            if (tid == 0) D.road_speed[r] = -1.0f;
+            if (tid == 0) {
+                D.road_speed[r] = -1.0f;
+                wtn[r] = 0;
+            }
             __syncthreads();
             continue;
         }
-
-        // ---------------- pass 1 ----------------
-        for (int j = tid; j < n; j += kWave) {
-            const int li = lane_of(S, j);
-            const int c = j - S.start[li];
-            const uint32_t slot = S.base[li] + c;
-            const VehRec rec = rd[slot];
-            const bool is_jl = li >= nroad;
-            const int m = S.lane[li];
-            uint32_t gmask = 0u;
-            if (!is_jl) {
-                if (rec.nr < 0) {
-                    gmask = nroad >= 32 ? 0xFFFFFFFFu : ((1u << nroad) - 1u);
-                } else {
-                    for (int q = nroad; q < nl; ++q)
-                        if (S.jl_out_road[q] == rec.nr) gmask |= 1u << S.jl_in_local[q];
-                }
+        if (n <= kTileCap) {
+            for (int j = tid; j < n; j += kWave) {
+                const int li = lane_of(S, j);
+                S.rec[j] = rd[S.base[li] + (j - S.start[li])];
             }
-            Lead ld;
-            if (c > 0) {
-                const VehRec z = rd[slot - 1];
-                ld.ex = true;
-                ld.rear = z.x - z.len;
-                ld.v = z.v;
-            } else {
-                ld = lookahead(D, rd, rcnt, m, is_jl, rec.nr, rec.rp, rec.rem);
-            }
-            const bool stop = stop_end(D, m, is_jl, rec.nr, true);
-            const float a = accel(rec.v, rec.f * S.lim[li], rec.x, ld, stop, S.len[li], P);
-            int mt = -1;
-            if (!is_jl && rec.nr >= 0 && !((gmask >> li) & 1u)) {
-                int bl = -1, bd = 1 << 20;
-                for (int b = 0; b < nroad; ++b)
-                    if ((gmask >> b) & 1u) {
-                        const int d = b > li ? b - li : li - b;
-                        if (d < bd) {
-                            bd = d;
-                            bl = b;
-                        }
-                    }
-                if (bl >= 0) mt = bl < li ? li - 1 : li + 1;
-            }
-            D.sh_gmask[slot] = gmask;
-            D.sh_aown[slot] = a;
-            D.sh_merge[slot] = mt;
-            D.sh_lrear[slot] = ld.ex ? ld.rear : TS_INF;
-            D.sh_lv[slot] = ld.v;
-            if (mt >= 0) {
-                const int k = atomicAdd(&S.nmerge, 1);
-                if (k < kMergeCap) {
-                    S.mrg_tgt[k] = mt;
-                    S.mrg_rear[k] = rec.x - rec.len;
-                    S.mrg_v[k] = rec.v;
-                    S.mrg_vid[k] = rec.vid;
-                }
-            }
-        }
-        __syncthreads();
-
-        // ---------------- pass 2 ----------------
-        for (int j = tid; j < n; j += kWave) {
-            const int li = lane_of(S, j);
-            const int c = j - S.start[li];
-            const uint32_t slot = S.base[li] + c;
-            const VehRec rec = rd[slot];
-            const bool is_jl = li >= nroad;
-            const int m = S.lane[li];
-            const float len = S.len[li];
-            const float lim = S.lim[li];
-            const float v0 = rec.f * lim;
-            const float a_e = D.sh_aown[slot];
-            const uint32_t gmask = D.sh_gmask[slot];
-            const int my_mt = D.sh_merge[slot];
-            const bool in_g = !is_jl && ((gmask >> li) & 1u);
-            const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
-            // MOBIL for one direction: utility (or -inf), prospective
-            // acceleration, and the target-lane leader used as a bound
-            auto eval_dir = [&](int d) -> DirEval {
-                DirEval o;
-                o.u = -TS_INF;
-                o.ta = 0.0f;
-                o.lead.ex = false;
-                o.lead.rear = TS_INF;
-                o.lead.v = 0.0f;
-                if (is_jl) return o;
-                const int k = li + d;
-                if (k < 0 || k >= nroad) return o;
-                if (in_g) {
-                    if (!((gmask >> k) & 1u)) return o;
-                } else if (!(group_dist(gmask, k, nroad) < dist_l)) {
-                    return o;
-                }
-                const int pos = count_ahead(S, rd, k, rec.x, rec.vid);
-                const int tl = pos > 0 ? (int)(S.base[k] + pos - 1) : -1;
-                const int tf = pos < S.cnt[k] ? (int)(S.base[k] + pos) : -1;
-                VehRec tlr{}, tfr{};
-                if (tl >= 0) tlr = rd[tl];
-                if (tf >= 0) tfr = rd[tf];
-                // same gap of k held by a vehicle two lanes right (rightward only)
-                if (d > 0 && k + 1 < nroad) {
-                    const int lo2 = tl >= 0 ? count_ahead(S, rd, k + 1, tlr.x, tlr.vid) : 0;
-                    const int hi2 = tf >= 0 ? count_ahead(S, rd, k + 1, tfr.x, tfr.vid) : S.cnt[k + 1];
-                    if (lo2 < hi2) return o;
-                }
-                const int mk = S.lane[k];
-                Lead tld;
-                if (tl >= 0) {
-                    tld.ex = true;
-                    tld.rear = tlr.x - tlr.len;
-                    tld.v = tlr.v;
-                } else {
-                    tld = lookahead(D, rd, rcnt, mk, false, rec.nr, rec.rp, rec.rem);
-                }
-                const float g3 = tld.ex ? tld.rear - rec.x : TS_INF;
-                if (!(g3 > 0.0f)) return o;
-                const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
-                if (tf >= 0 && !tf_yields) {
-                    const float g4 = rec.x - rec.len - tfr.x - (tfr.v * P.dt + P.reach);
-                    if (!(g4 >= 0.0f)) return o;
-                }
-                if (tf < 0) {
-                    for (int e = D.feed_begin[mk]; e < D.feed_begin[mk + 1]; ++e) {
-                        const int fl = D.feed_jl[e];
-                        if (rcnt[fl] == 0) continue;
-                        const VehRec h = rd[D.lane_base[fl]];
-                        const float g = (rec.x - rec.len) - (h.x + h.v * P.dt + P.reach - D.lane_len[fl]);
-                        if (!(g >= 0.0f)) return o;
-                    }
-                }
-                const float ta_e = accel(rec.v, v0, rec.x, tld, stop_end(D, mk, false, rec.nr, false), len, P);
-                float d_new = 0.0f, d_old = 0.0f;
-                if (tf >= 0) {
-                    const float a_tf = D.sh_aown[tf];
-                    const Lead me_lead{rec.x - rec.len, rec.v, true};
-                    const float ta_tf =
-                        accel(tfr.v, tfr.f * lim, tfr.x, me_lead, stop_end(D, mk, false, tfr.nr, true), len, P);
-                    if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
-                    d_new = ta_tf - a_tf;
-                }
-                if (c + 1 < S.cnt[li]) {
-                    const VehRec ofr = rd[slot + 1];
-                    const float a_of = D.sh_aown[slot + 1];
-                    Lead ol;
-                    if (c > 0) {
-                        const VehRec z = rd[slot - 1];
-                        ol.ex = true;
-                        ol.rear = z.x - z.len;
-                        ol.v = z.v;
-                    } else {
-                        ol = lookahead(D, rd, rcnt, m, false, ofr.nr, ofr.rp, ofr.rem);
-                    }
-                    const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, stop_end(D, m, false, ofr.nr, true), len, P);
-                    d_old = ta_of - a_of;
-                }
-                const float da = (ta_e - a_e) + P.p * (d_new + d_old);
-                float ud = da - P.a_th;
-                if (!in_g) ud = fmaxf(ud, 1.0f);
-                o.u = ud;
-                o.ta = ta_e;
-                o.lead = tld;
-                return o;
-            };
-            const DirEval eL = eval_dir(-1);
-            const DirEval eR = eval_dir(+1);
-            // randomized decision
-            const float uLp = fmaxf(0.0f, eL.u), uRp = fmaxf(0.0f, eR.u);
-            const float uT = uLp + uRp;
-            const float pLC = uT >= 1.0f ? P.p_max : (uT > 0.0f ? P.p_min + (P.p_max - P.p_min) * uT : P.p_min);
-            const uint32_t w = philox_word0(P.key0, P.key1, (uint32_t)rec.vid, (uint32_t)t);
-            const float rr = (float)w * 2.3283064365386963e-10f;  // 2^-32
-            int dec = 0;
-            if (uT > 0.0f) {
-                const float bL = pLC * uLp / uT;
-                if (uLp > 0.0f && rr < bL) dec = 1;
-                else if (uRp > 0.0f && rr >= bL && rr < pLC) dec = 2;
-            } else {
-                const bool fL = eL.u > -TS_INF, fR = eR.u > -TS_INF;
-                if (fL && fR) {
-                    if (rr < 0.5f * P.p_min) dec = 1;
-                    else if (rr < P.p_min) dec = 2;
-                } else if (fL || fR) {
-                    if (rr < P.p_min) dec = fL ? 1 : 2;
-                }
-            }
-            const int nli = dec == 1 ? li - 1 : (dec == 2 ? li + 1 : li);
-            float a = dec == 1 ? eL.ta : (dec == 2 ? eR.ta : a_e);
-            // cooperative yielding of lane keepers to vehicles merging into their lane
-            bool has_y = false;
-            float y_rear = TS_INF, y_v = 0.0f;
-            if (!is_jl && !dec) {
-                int y_vid = 0x7FFFFFFF;
-                const int nm = S.nmerge;
-                if (nm <= kMergeCap) {
-                    for (int q = 0; q < nm; ++q) {
-                        if (S.mrg_tgt[q] != li) continue;
-                        const float rm = S.mrg_rear[q];
-                        if (!(rm > rec.x)) continue;
-                        if (!has_y || rm < y_rear || (rm == y_rear && S.mrg_vid[q] < y_vid)) {
-                            has_y = true;
-                            y_rear = rm;
-                            y_v = S.mrg_v[q];
-                            y_vid = S.mrg_vid[q];
-                        }
-                    }
-                } else {
-                    for (int dd = -1; dd <= 1; dd += 2) {
-                        const int k2 = li + dd;
-                        if (k2 < 0 || k2 >= nroad) continue;
-                        for (int q = 0; q < S.cnt[k2]; ++q) {
-                            const uint32_t s2 = S.base[k2] + q;
-                            if (D.sh_merge[s2] != li) continue;
-                            const VehRec z = rd[s2];
-                            const float rm = z.x - z.len;
-                            if (!(rm > rec.x)) continue;
-                            if (!has_y || rm < y_rear || (rm == y_rear && z.vid < y_vid)) {
-                                has_y = true;
-                                y_rear = rm;
-                                y_v = z.v;
-                                y_vid = z.vid;
-                            }
-                        }
-                    }
-                }
-                if (has_y) a = fminf(a, idm_follow(rec.v, v0, y_rear - rec.x, rec.v - y_v, P));
-            }
-            // ballistic update with in-step stop
-            const float x = rec.x, v = rec.v;
-            const float vh = v + a * P.dt;
-            float xn, vn;
-            if (vh >= 0.0f) {
-                xn = x + v * P.dt + 0.5f * a * P.dt * P.dt;
-                vn = vh;
-            } else {
-                xn = x - v * v / (2.0f * a);
-                vn = 0.0f;
-            }
-            // snapshot bounds
-            float B = TS_INF, vcap = TS_INF;
-            const float lr = D.sh_lrear[slot];
-            if (lr < TS_INF) {
-                B = lr;
-                vcap = D.sh_lv[slot];
-            }
-            if (dec) {
-                const Lead l2 = dec == 1 ? eL.lead : eR.lead;
-                if (l2.ex) {
-                    if (l2.rear < B) {
-                        B = l2.rear;
-                        vcap = l2.v;
-                    } else if (l2.rear == B) {
-                        vcap = fminf(vcap, l2.v);
-                    }
-                }
-            }
-            if (has_y) {
-                if (y_rear < B) {
-                    B = y_rear;
-                    vcap = y_v;
-                } else if (y_rear == B) {
-                    vcap = fminf(vcap, y_v);
-                }
-            }
-            const int mnew = S.lane[nli];
-            if (stop_end(D, mnew, is_jl, rec.nr, true)) {
-                if (len < B) {
-                    B = len;
-                    vcap = 0.0f;
-                } else if (len == B) {
-                    vcap = 0.0f;
-                }
-            }
-            if (xn > B) {
-                xn = fmaxf(B, x);
-                vn = fminf(vn, vcap);
-                atomicAdd(&S.clamps, 1);
-            }
-            int kind = dec ? 1 : 0;
-            int tgt_local = nli;
-            if (xn > len) {
-                if (!is_jl && rec.rem == 0) {
-                    kind = 4;
-                    D.status[rec.vid] = 2;
-                    D.finish_step[rec.vid] = (int)t;
-                    const double tt = (double)(t + 1) * P.dt_d - (double)D.tau[rec.vid];
-                    atomicAdd(&S.sum_tt, (unsigned long long)llrint(tt * kTimeFx));
-                    atomicAdd(&S.finished, 1);
-                } else if (!is_jl) {
-                    const int g = out_toward(D, mnew, rec.nr);
-                    kind = 2;
-                    tgt_local = D.lane_local[g];
-                    xn -= len;
-                    atomicAdd(&S.transfers, 1);
-                } else {
-                    const int g = D.jl_out[m];
-                    bool blocked = false;
-                    const int my_ext = D.jl_ext[m];
-                    for (int e = D.feed_begin[g]; e < D.feed_begin[g + 1]; ++e) {
-                        const int fl = D.feed_jl[e];
-                        if (D.jl_ext[fl] >= my_ext) break;
-                        const int cf = rcnt[fl];
-                        if (cf == 0) continue;
-                        const VehRec h = rd[D.lane_base[fl]];
-                        const float reach = h.x + h.v * P.dt + P.reach - D.lane_len[fl];
-                        if (reach > 0.0f) blocked = true;
-                    }
-                    if (blocked) {
-                        xn = len;
-                        vn = 0.0f;
-                        atomicAdd(&S.fblocks, 1);
-                    } else {
-                        kind = 3;
-                        VehRec o;
-                        o.x = xn - len;
-                        o.v = vn;
-                        o.vid = rec.vid;
-                        o.len = rec.len;
-                        o.f = rec.f;
-                        o.rp = rec.rp + 1;
-                        o.rem = rec.rem - 1;
-                        o.nr = rec.rem - 1 > 0 ? D.route[rec.rp + 2] : -1;
-                        if (atomicCAS(&D.inbox_flag[g], 0, 1) != 0) atomicAdd(&S.errors, 1);
-                        D.inbox[g] = o;
-                        atomicAdd(&S.transfers, 1);
-                    }
-                }
-            }
-            if (dec) atomicAdd(&S.changes, 1);
-            // metrics: a vehicle counts for the lane it occupied at the step start
-            if (!is_jl) {
-                atomicAdd(&S.sumv, (unsigned long long)(long long)llrintf(vn * kSpeedFx));
-                atomicAdd(&S.cntv, 1);
-            }
-            if (vn < 0.1f) atomicAdd(&S.wait[li], 1);
-            D.sh_nx[slot] = xn;
-            D.sh_nv[slot] = vn;
-            D.sh_kind[slot] = kind;
-            D.sh_nlane[slot] = tgt_local;
-            if (kind == 0) {
-                atomicAdd(&S.nstay[li], 1);
-            } else if (kind == 1) {
-                atomicAdd(&S.nin[nli], 1);
-                const int q = atomicAdd(&S.nchg, 1);
-                if (q < kChangerCap) {
-                    S.chg_x[q] = xn;
-                    S.chg_vid[q] = rec.vid;
-                    S.chg_lane[q] = nli;
-                }
-            } else if (kind == 2) {
-                atomicAdd(&S.nenter[tgt_local], 1);
-            }
-        }
-        __syncthreads();
-
-        // ---------------- pass 3 ----------------
-        // exclusive prefix count of stayers over the tile enumeration
-        {
-            int carry = 0;
-            for (int b0 = 0; b0 < n; b0 += kWave) {
-                const int j = b0 + tid;
-                bool st = false;
-                uint32_t slot = 0;
-                if (j < n) {
-                    const int li = lane_of(S, j);
-                    slot = S.base[li] + (j - S.start[li]);
-                    st = D.sh_kind[slot] == 0;
-                }
-                const unsigned long long bal = __ballot(st);
-                const int pre = carry + __popcll(bal & ((1ull << tid) - 1ull));
-                if (j < n) D.sh_pref[slot] = pre;
-                carry += __popcll(bal);
-            }
-        }
-        __syncthreads();
-        const int nchg = S.nchg;
-        for (int j = tid; j < n; j += kWave) {
-            const int li = lane_of(S, j);
-            const int c = j - S.start[li];
-            const uint32_t slot = S.base[li] + c;
-            const int kind = D.sh_kind[slot];
-            if (kind >= 3) continue;
-            const VehRec rec = rd[slot];
-            const float xn = D.sh_nx[slot];
-            const int nli = D.sh_nlane[slot];
-            int rank = 0;
-            if (kind == 0) {
-                rank = D.sh_pref[slot] - D.sh_pref[S.base[li]];
-            } else if (kind == 1) {
-                for (int q = 0; q < S.cnt[nli]; ++q) {
-                    const uint32_t s2 = S.base[nli] + q;
-                    if (D.sh_kind[s2] != 0) continue;
-                    if (ahead(D.sh_nx[s2], rd[s2].vid, xn, rec.vid)) rank++;
-                }
-            } else {
-                rank = S.nstay[nli];
-            }
-            if (kind <= 1) {
-                // changers into the same lane ahead of this vehicle
-                if (nchg <= kChangerCap) {
-                    for (int q = 0; q < nchg; ++q)
-                        if (S.chg_lane[q] == nli && S.chg_vid[q] != rec.vid && ahead(S.chg_x[q], S.chg_vid[q], xn, rec.vid))
-                            rank++;
-                } else {
-                    for (int dd = -1; dd <= 1; dd += 2) {
-                        const int k2 = nli + dd;
-                        if (k2 < 0 || k2 >= nroad) continue;
-                        for (int q = 0; q < S.cnt[k2]; ++q) {
-                            const uint32_t s2 = S.base[k2] + q;
-                            if (D.sh_kind[s2] != 1 || D.sh_nlane[s2] != nli) continue;
-                            const int ov = rd[s2].vid;
-                            if (ov != rec.vid && ahead(D.sh_nx[s2], ov, xn, rec.vid)) rank++;
-                        }
-                    }
-                }
-            }
-            const int mn = S.lane[nli];
-            if (rank < D.lane_cap[mn]) {
-                VehRec o = rec;
-                o.x = xn;
-                o.v = D.sh_nv[slot];
-                wr[S.base[nli] + rank] = o;
-            } else {
-                atomicAdd(&S.errors, 1);
-            }
+            __syncthreads();
+            LdsView view{S};
+            process_tile(D, S, view, rsum, wsum, wr, t, inst, tid);
+        } else {
+            GlobalView view{S, D, rd};
+            process_tile(D, S, view, rsum, wsum, wr, t, inst, tid);
         }
         __syncthreads();
         if (tid < nl) {
             const int m = lb + tid;
             const int c = S.nstay[tid] + S.nin[tid] + S.nenter[tid];
-            wcnt[m] = c < D.lane_cap[m] ? c : D.lane_cap[m];
+            wsum[m].cnt = c < D.lane_cap[m] ? c : D.lane_cap[m];
+            if (c == 0) {
+                wsum[m].rear = TS_INF;
+                wsum[m].rear_v = 0.0f;
+                wsum[m].front_reach = -TS_INF;
+            }
             D.lane_wait[m] = S.wait[tid];
         }
         if (tid == 0) {
+            int tot = 0;
+            for (int q = 0; q < nl; ++q) tot += S.nstay[q] + S.nin[q] + S.nenter[q];
+            wtn[r] = tot;
             D.road_speed[r] = S.cntv > 0 ? (float)((double)(long long)S.sumv / (double)kSpeedFx / (double)S.cntv) : -1.0f;
             acc.sumv_fx += (long long)S.sumv;
             acc.cnt += S.cntv;
@@ -855,21 +1037,60 @@ __global__ __launch_bounds__(kWave) void k_update(DevNet D)
         __syncthreads();
     }
 
+    if (D.n_inst > 1) {
+        flush();
+        acc = WGPartial{};
+    }
     // per-workgroup partials; the last workgroup folds the step
     if (tid == 0) {
         D.part[blockIdx.x] = acc;
         __threadfence();
         const unsigned int old = atomicAdd(D.done_ctr, 1u);
-        S.n = (old == gridDim.x - 1) ? 1 : 0;
+        S.skip = (old == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
-    if (S.n) {
+    if (S.skip && D.n_inst > 1) {
+        __threadfence();
+        for (int i = tid; i < D.n_inst; i += kWave) {
+            volatile long long* q = (volatile long long*)&D.inst_acc[i];
+            long long a[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                a[k] = q[k];
+                q[k] = 0;
+            }
+            DevMetrics* M = &D.met[i];
+            M->vehicle_steps += a[2];
+            M->lane_changes += a[3];
+            M->transfers += a[4];
+            M->clamps += a[5];
+            M->feeder_blocks += a[6];
+            M->finished += a[7];
+            M->sum_tt_fx += a[8];
+            M->errors += a[9];
+            if (a[1] > 0) {
+                M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
+                M->speed_acc += M->mean_speed_last;
+                M->speed_steps += 1;
+            } else {
+                M->mean_speed_last = 0.0;
+            }
+            M->step = tg - D.inst_t0[i] + 1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            *D.gstep = tg + 1;
+            *D.done_ctr = 0u;
+        }
+    } else if (S.skip) {
         __threadfence();
         long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int g = tid; g < (int)gridDim.x; g += kWave) {
             const volatile long long* q = (const volatile long long*)&D.part[g];
+#pragma unroll
             for (int k = 0; k < 10; ++k) a[k] += q[k];
         }
+#pragma unroll
         for (int k = 0; k < 10; ++k) {
             for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
         }
@@ -890,7 +1111,8 @@ __global__ __launch_bounds__(kWave) void k_update(DevNet D)
             } else {
                 M->mean_speed_last = 0.0;
             }
-            M->step = t + 1;
+            M->step = tg - D.inst_t0[0] + 1;
+            *D.gstep = tg + 1;
             *D.done_ctr = 0u;
         }
     }
@@ -899,25 +1121,37 @@ __global__ __launch_bounds__(kWave) void k_update(DevNet D)
 // ---------------------------------------------------------------------------
 // host-driven helpers
 // ---------------------------------------------------------------------------
-__global__ void k_set_phases(DevNet D, const int32_t* ids, const int32_t* ph, int n)
+__global__ void k_set_phases(const DevNet* __restrict__ Dp, const int32_t* ids, const int32_t* ph, int n)
 {
+    const DevNet& D = *Dp;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     D.junc_policy[ids[i]] = 2;
     D.junc_manual[ids[i]] = ph[i];
 }
 
-// per-vehicle export of the state at a step boundary (residents + inboxes)
-__global__ void k_export(DevNet D, const int32_t* lane_ext, int32_t* o_lane, float* o_x, float* o_v, int32_t* o_rpos,
-                         int32_t* o_rank)
+// one phase entry per junction (negative = unchanged)
+__global__ void k_set_all_phases(const DevNet* __restrict__ Dp, const int32_t* ph)
 {
+    const DevNet& D = *Dp;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= D.NJ || ph[j] < 0) return;
+    D.junc_policy[j] = 2;
+    D.junc_manual[j] = ph[j];
+}
+
+// per-vehicle export of the state at a step boundary (residents + inboxes)
+__global__ void k_export(const DevNet* __restrict__ Dp, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
+                         float* o_v, int32_t* o_rpos, int32_t* o_rank)
+{
+    const DevNet& D = *Dp;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= D.NL) return;
-    const long long t = D.met->step;
+    const long long t = *D.gstep;
     const int p = (int)(t & 1);
     const VehRec* slab = p ? D.slab1 : D.slab0;
-    const int32_t* cnt = p ? D.cnt1 : D.cnt0;
-    const int c = cnt[m];
+    const LaneSum* sum = p ? D.sum1 : D.sum0;
+    const int c = sum[m].cnt;
     for (int q = 0; q < c; ++q) {
         const VehRec z = slab[D.lane_base[m] + q];
         o_lane[z.vid] = lane_ext[m];
@@ -937,47 +1171,54 @@ __global__ void k_export(DevNet D, const int32_t* lane_ext, int32_t* o_lane, flo
 }
 
 // scatter of host-ordered records into the read slab of the current step
-__global__ void k_import(DevNet D, const uint32_t* slots, const VehRec* recs, int n)
+__global__ void k_import(const DevNet* __restrict__ Dp, const uint32_t* slots, const VehRec* recs, int n)
 {
+    const DevNet& D = *Dp;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const long long t = D.met->step;
+    const long long t = *D.gstep;
     VehRec* slab = (t & 1) ? D.slab1 : D.slab0;
     slab[slots[i]] = recs[i];
 }
 
-// launch wrappers (host side)
-hipError_t launch_prepare(const DevNet& D, hipStream_t s)
+// launch wrappers (host side); Dd is the device copy of the view, H the host copy
+hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
-    const int n = D.R > D.NJ ? D.R : D.NJ;
-    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, D);
+    const int n = H.R > H.NJ ? H.R : H.NJ;
+    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, Dd);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const DevNet& D, hipStream_t s)
+hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update, dim3(D.G), dim3(kWave), 0, s, D);
+    hipLaunchKernelGGL(k_update, dim3(H.G), dim3(kWave), 0, s, Dd);
     return hipGetLastError();
 }
 
-hipError_t launch_set_phases(const DevNet& D, const int32_t* ids, const int32_t* ph, int n, hipStream_t s)
+hipError_t launch_set_phases(const DevNet* Dd, const int32_t* ids, const int32_t* ph, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_phases, dim3((n + 255) / 256), dim3(256), 0, s, D, ids, ph, n);
+    hipLaunchKernelGGL(k_set_phases, dim3((n + 255) / 256), dim3(256), 0, s, Dd, ids, ph, n);
     return hipGetLastError();
 }
 
-hipError_t launch_export(const DevNet& D, const int32_t* lane_ext, int32_t* o_lane, float* o_x, float* o_v,
-                         int32_t* o_rpos, int32_t* o_rank, hipStream_t s)
+hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_export, dim3((D.NL + 255) / 256), dim3(256), 0, s, D, lane_ext, o_lane, o_x, o_v, o_rpos,
+    hipLaunchKernelGGL(k_set_all_phases, dim3((H.NJ + 255) / 256), dim3(256), 0, s, Dd, ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
+                         float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_export, dim3((H.NL + 255) / 256), dim3(256), 0, s, Dd, lane_ext, o_lane, o_x, o_v, o_rpos,
                        o_rank);
     return hipGetLastError();
 }
 
-hipError_t launch_import(const DevNet& D, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s)
+hipError_t launch_import(const DevNet* Dd, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_import, dim3((n + 255) / 256), dim3(256), 0, s, D, slots, recs, n);
+    hipLaunchKernelGGL(k_import, dim3((n + 255) / 256), dim3(256), 0, s, Dd, slots, recs, n);
     return hipGetLastError();
 }
 

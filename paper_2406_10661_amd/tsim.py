@@ -64,7 +64,10 @@ _lib = None
 
 EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases", "tsim_get_metrics",
            "tsim_get_road_mean_speed", "tsim_get_lane_waiting_counts", "tsim_get_lane_order", "tsim_get_state",
-           "tsim_set_state", "tsim_set_profiling", "tsim_get_kernel_times", "tsim_destroy", "tsim_last_error"]
+           "tsim_set_state", "tsim_set_profiling", "tsim_get_kernel_times", "tsim_destroy", "tsim_last_error",
+           "tsim_batch_footprint", "tsim_batch_create", "tsim_batch_step", "tsim_batch_set_signal_phases",
+           "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
+           "tsim_set_graph_steps", "tsim_batch_set_graph_steps"]
 
 
 def lib():
@@ -86,8 +89,18 @@ def lib():
         L.tsim_get_state.argtypes = [P, P]
         L.tsim_set_state.argtypes = [P, P]
         L.tsim_set_profiling.argtypes = [P, C.c_int32]
+        L.tsim_set_graph_steps.argtypes = [P, C.c_int32]
+        L.tsim_batch_set_graph_steps.argtypes = [P, C.c_int32]
         L.tsim_get_kernel_times.argtypes = [P, P, P, C.c_int32]
         L.tsim_destroy.argtypes = [P]
+        L.tsim_batch_footprint.argtypes = [P, P, P, C.c_int32, C.POINTER(C.c_size_t)]
+        L.tsim_batch_create.argtypes = [P, P, P, C.c_int32, P, P, C.c_size_t, C.POINTER(C.c_void_p)]
+        L.tsim_batch_step.argtypes = [P, C.c_int32]
+        L.tsim_batch_set_signal_phases.argtypes = [P, C.c_int32, P, P, C.c_int32]
+        L.tsim_batch_get_metrics.argtypes = [P, C.c_int32, P]
+        L.tsim_batch_set_all_phases.argtypes = [P, P, C.c_int32]
+        L.tsim_batch_get_state.argtypes = [P, C.c_int32, P]
+        L.tsim_batch_destroy.argtypes = [P]
         L.tsim_last_error.argtypes = [P]
         L.tsim_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -209,6 +222,10 @@ class Sim:
     def set_profiling(self, enable=True):
         _check(lib().tsim_set_profiling(self.h, 1 if enable else 0), self.h)
 
+    def set_graph_steps(self, chunk):
+        """Replay `chunk`-step HIP graphs inside step(); 0 = direct launches."""
+        _check(lib().tsim_set_graph_steps(self.h, int(chunk)), self.h)
+
     def kernel_times(self):
         """{'update': (ms, launches), 'prepare': (ms, launches)} since profiling was enabled."""
         ms = np.zeros(2, np.float64)
@@ -239,3 +256,84 @@ class Sim:
         s = tsim_state_host(int(st["step"]), *[_p(a[k]) for k in ("status", "lane", "route_pos", "x", "v",
                                                                    "finish_step", "junc_policy", "junc_phase")])
         _check(lib().tsim_set_state(self.h, C.byref(s)), self.h)
+
+
+class Batch:
+    """Many independent instances resident together and stepped by the same
+    launches (tsim_batch_* in include/tsim.h)."""
+
+    def __init__(self, nets, trips, params, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("tsim needs a GPU: torch.cuda.is_available() is False")
+        n = len(nets)
+        assert len(trips) == n and len(params) == n and n > 0
+        self.n = n
+        self.nets, self.trips, self.params = nets, trips, params
+        self._ins = [_Inputs(a, b, c) for a, b, c in zip(nets, trips, params)]
+        self._net_arr = (tsim_network * n)(*[i.net for i in self._ins])
+        self._trip_arr = (tsim_trips * n)(*[i.trips for i in self._ins])
+        self._par_arr = (tsim_params * n)(*[i.params for i in self._ins])
+        nbytes = C.c_size_t(0)
+        _check(lib().tsim_batch_footprint(self._net_arr, self._trip_arr, self._par_arr, n, C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().tsim_batch_create(self._net_arr, self._trip_arr, self._par_arr, n,
+                                       C.c_void_p(self.stream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
+                                       C.c_size_t(self.arena.numel()), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tsim_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(lib().tsim_batch_step(self.h, int(n)), self.h)
+
+    def set_graph_steps(self, chunk):
+        _check(lib().tsim_batch_set_graph_steps(self.h, int(chunk)), self.h)
+
+    def set_profiling(self, enable=True):
+        _check(lib().tsim_set_profiling(self.h, 1 if enable else 0), self.h)
+
+    def kernel_times(self):
+        """{'update': (ms, launches), 'prepare': (ms, launches)} since profiling was enabled."""
+        return Sim.kernel_times(self)
+
+    def set_signal_phases(self, instance, junctions, phases):
+        j = np.ascontiguousarray(junctions, np.int32)
+        p = np.ascontiguousarray(phases, np.int32)
+        _check(lib().tsim_batch_set_signal_phases(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
+
+    def set_all_phases(self, phases):
+        """phases: one entry per junction of the batch, instance order; -1 = unchanged."""
+        p = np.ascontiguousarray(phases, np.int32)
+        _check(lib().tsim_batch_set_all_phases(self.h, _p(p), int(p.size)), self.h)
+
+    def metrics(self, instance, check=True):
+        m = tsim_metrics()
+        rc = lib().tsim_batch_get_metrics(self.h, int(instance), C.byref(m))
+        if check:
+            _check(rc, self.h)
+        return {k: getattr(m, k) for k, _ in tsim_metrics._fields_}
+
+    def get_state(self, instance):
+        N = self.trips[instance].n_vehicles
+        NJ = self.nets[instance].n_junctions
+        st = dict(status=np.zeros(N, np.int32), lane=np.zeros(N, np.int32), route_pos=np.zeros(N, np.int32),
+                  x=np.zeros(N, np.float32), v=np.zeros(N, np.float32), finish_step=np.zeros(N, np.int32),
+                  junc_policy=np.zeros(NJ, np.int32), junc_phase=np.zeros(NJ, np.int32))
+        s = tsim_state_host(0, *[_p(st[k]) for k in ("status", "lane", "route_pos", "x", "v", "finish_step",
+                                                       "junc_policy", "junc_phase")])
+        _check(lib().tsim_batch_get_state(self.h, int(instance), C.byref(s)), self.h)
+        st["step"] = int(s.step)
+        return st

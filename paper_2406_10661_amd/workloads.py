@@ -404,8 +404,8 @@ def shortest_routes(net: Network, origins, dests, road_price=None, chunk=64, wor
     return begin, r, reach
 
 
-def _finish_trips(net, rng, origins, dests, depart, road_price=None, length=5.0):
-    begin, roads, reach = shortest_routes(net, origins, dests, road_price)
+def _finish_trips(net, rng, origins, dests, depart, road_price=None, length=5.0, workers=None):
+    begin, roads, reach = shortest_routes(net, origins, dests, road_price, workers=workers)
     if not reach.all():
         # keep only reachable trips (the generators redraw before this point)
         raise RuntimeError(f"{(~reach).sum()} unreachable trips")
@@ -503,9 +503,44 @@ def config4_instance(i, steps=1800):
     net = jittered_grid(n, rng)
     o, d = uniform_od(net, rng, N)
     dep = rng.uniform(0.0, 900.0, N)
-    trips = _finish_trips(net, rng, o, d, dep)
+    trips = _finish_trips(net, rng, o, d, dep, workers=1)
     return Workload(f"batch_inst{i}_grid{n}_{N}", net, trips, Params(seed=1000 + i), steps,
                     extra={"policy_seed": 5000 + i, "policy_every": 15})
+
+
+def _instance_worker(args):
+    kind, i, kw = args
+    if kind == "batch":
+        return config4_instance(i, **kw)
+    return config5_job(i, workers=1, **kw)
+
+
+def batch_workload(n_instances=256, steps=1800, workers=None, first=0):
+    """The batched workload: instances first .. first+n_instances-1 of
+    ``config4_instance``, generated in parallel processes."""
+    import os
+    import multiprocessing as mp
+    ids = list(range(first, first + n_instances))
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    jobs = [("batch", i, {"steps": steps}) for i in ids]
+    if workers > 1 and n_instances > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
+            return pool.map(_instance_worker, jobs, chunksize=1)
+    return [_instance_worker(j) for j in jobs]
+
+
+def served_jobs(n_jobs, workers=None, max_vehicles=None):
+    """Jobs 0 .. n_jobs-1 of ``config5_job``, generated in parallel processes."""
+    import os
+    import multiprocessing as mp
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    jobs = [("serve", j, {"max_vehicles": max_vehicles}) for j in range(n_jobs)]
+    if workers > 1 and n_jobs > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
+            return pool.map(_instance_worker, jobs, chunksize=1)
+    return [_instance_worker(j) for j in jobs]
 
 
 def random_phase_schedule(net: Network, seed, n_updates):
@@ -516,7 +551,7 @@ def random_phase_schedule(net: Network, seed, n_updates):
     return np.minimum((u * nph[None, :]).astype(np.int32), np.maximum(nph - 1, 0)[None, :]).astype(np.int32)
 
 
-def config5_job(j, max_vehicles=None):
+def config5_job(j, max_vehicles=None, workers=None):
     """Job j of the served workload: w.p. 1/2 a C1-style grid (n~U{4..16}),
     else a jittered grid (n~U{8..32}); N log-uniform in [10k, 500k] capped by
     the grid-size coupling; horizon U{300..3600}; w.p. 1/2 a signal-timing
@@ -540,7 +575,7 @@ def config5_job(j, max_vehicles=None):
     price = None if plan else rng.uniform(0.0, 120.0, net.n_roads)
     o, d = uniform_od(net, rng, N)
     dep = rng.uniform(0.0, 0.5 * H, N)
-    trips = _finish_trips(net, rng, o, d, dep, road_price=price)
+    trips = _finish_trips(net, rng, o, d, dep, road_price=price, workers=workers)
     return Workload(f"job{j}", net, trips, Params(seed=10000 + j), H,
                     extra={"kind": "timing_plan" if plan else "pricing"})
 

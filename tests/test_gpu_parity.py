@@ -78,6 +78,25 @@ def test_random_grid_heavy_one_step(O, Sim, seed):
         _log(f"grid3_s{seed}_t{step}", rep)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_big_tiles_one_step(O, Sim, seed):
+    """Dense long roads (1.5 km, 3 lanes): tiles of several hundred vehicles
+    take the kernel's global-memory path instead of the LDS-staged one."""
+    rng = np.random.default_rng(100 + seed)
+    net = W.grid_network(3, spacing=1500.0, length=1500.0, lanes=3)
+    o, d = W.uniform_od(net, rng, 6000)
+    trips = W._finish_trips(net, rng, o, d, rng.uniform(0, 50, 6000))
+    params = W.Params(seed=seed)
+    st = synthetic_state(net, trips, 60, seed=seed, p_active=0.95, min_gap=0.2)
+    lanes = st["lane"][st["status"] == 1]
+    rol = net.road_of_lane()
+    per_road = np.bincount(rol[lanes[lanes < net.n_road_lanes]], minlength=net.n_roads)
+    assert per_road.max() > 150
+    rep = compare_one_step(O, Sim, net, trips, params, st)
+    rep["max_tile"] = int(per_road.max())
+    _log(f"big_tiles_s{seed}", rep)
+
+
 def test_manual_signals_one_step(O, Sim):
     w = W.config1()
     st = synthetic_state(w.network, w.trips, 77, seed=5, p_active=0.5)
@@ -169,3 +188,45 @@ def test_c3_invariants_over_steps(Sim, city):
         assert not errs, (t, errs)
         prev = cur
     assert g.metrics()["errors"] == 0
+
+
+def test_batch_instances_match_alone(Sim):
+    """A batch of uneven instances (different networks, sizes and seeds),
+    stepped through captured graphs, gives each instance the same trajectory,
+    bit for bit, as running it alone with direct launches; phases are set
+    every 15 steps through both batch phase calls."""
+    from paper_2406_10661_amd.tsim import Batch
+    ws = [W.config4_instance(i, steps=200) for i in (3, 7, 11)]
+    ws = [w if w.trips.n_vehicles <= 40000 else None for w in ws]
+    ws = [w for w in ws if w is not None] + [W.config1()]
+    b = Batch([w.network for w in ws], [w.trips for w in ws], [w.params for w in ws])
+    alone = [Sim(w.network, w.trips, w.params) for w in ws]
+    scheds = [W.random_phase_schedule(w.network, 77 + k, 20) for k, w in enumerate(ws)]
+    b.set_graph_steps(15)          # the batch replays captured 15-step graphs
+    for c in range(10):
+        phs = [scheds[k][c] for k in range(len(ws))]
+        if c % 2:
+            # one batch-wide update; instance 1 left unchanged this time
+            allp = [ph if k != 1 else np.full_like(ph, -1) for k, ph in enumerate(phs)]
+            b.set_all_phases(np.concatenate(allp))
+        for k, w in enumerate(ws):
+            js = np.arange(w.network.n_junctions)
+            if c % 2 == 0:
+                b.set_signal_phases(k, js, phs[k])
+            if c % 2 == 0 or k != 1:
+                alone[k].set_signal_phases(js, phs[k])
+        b.step(15)
+        for a in alone:
+            for _ in range(15):
+                a.step(1)
+    for k, w in enumerate(ws):
+        sb = b.get_state(k)
+        sa = alone[k].get_state()
+        for key in ("status", "lane", "route_pos", "x", "v", "finish_step", "junc_policy", "junc_phase"):
+            assert np.array_equal(sb[key], sa[key]), (k, key)
+        mb, ma = b.metrics(k), alone[k].metrics()
+        for key in ("n_finished", "vehicle_steps", "lane_changes", "transfers", "departures", "step"):
+            assert mb[key] == ma[key], (k, key, mb[key], ma[key])
+        assert mb["mean_speed_avg"] == ma["mean_speed_avg"]
+        _log(f"batch_alone_inst{k}", {"vehicles": w.trips.n_vehicles, "active": int(ma["n_active"]),
+                                      "finished": int(ma["n_finished"])})
