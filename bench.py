@@ -107,6 +107,13 @@ def roofline(alg_bytes, upd_ms, upd_n, traffic):
             "us_per_launch": upd_ms / max(upd_n, 1) * 1e3, "bytes_per_launch": alg_bytes / max(upd_n, 1)}
 
 
+def autotune_city(sim, w, W):
+    from paper_2406_10661_amd.workloads import synthetic_state
+    st = synthetic_state(w.network, w.trips, min(3600, w.n_steps // 2), seed=98, p_active=0.5)
+    sim.set_state(st)
+    return sim.autotune(steps=10, rounds=2)
+
+
 def run_batch(args):
     """Batched RL-style stepping of many uneven instances versus the plain
     per-instance loop on the same phase schedule."""
@@ -126,8 +133,21 @@ def run_batch(args):
     log(f"[bench] batch of {len(ws)} instances, {nveh} vehicles, {lanes} lanes, generated in "
         f"{time.time() - t0:.1f} s")
 
+    from paper_2406_10661_amd.tsim import SCHEDULES
+    # schedule: autotuned on a throw-away batch once traffic has built up
+    b = Batch(nets, trips, pars)
+    for c in range(450 // every):
+        b.set_all_phases(allph[c])
+        b.step(every)
+    sched, us = b.autotune(steps=every, rounds=2)
+    b.close()
+    del b
+    torch.cuda.synchronize()
+    log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step {[round(float(x), 1) for x in us]}")
+
     def batched(profile):
         b = Batch(nets, trips, pars)
+        b.set_schedule(sched)
         if profile:
             b.set_profiling(True)
         else:
@@ -151,15 +171,17 @@ def run_batch(args):
         torch.cuda.synchronize()
         return ms, kt, ms_inst
 
-    _, kt, _ = batched(True)
+    _, kt, met_p = batched(True)
     ms_b, _, met_b = batched(False)
     vs_b = sum(m["vehicle_steps"] for m in met_b)
+    vs_p = sum(m["vehicle_steps"] for m in met_p)
 
     # plain loop: one instance at a time, direct launches, same schedule
     plain_ms = 0.0
     same = True
     for k, w in enumerate(ws):
         sim = Sim(w.network, w.trips, w.params)
+        sim.set_schedule(sched)
         js = np.arange(w.network.n_junctions, dtype=np.int32)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -178,14 +200,15 @@ def run_batch(args):
         del sim
     log(f"[bench] plain loop: {plain_ms:.1f} ms; identical per-instance results: {same}")
     upd_ms, upd_n = kt["update"]
-    alg = BYTES_PER_ACTIVE * vs_b + BYTES_PER_LANE * lanes * upd_n
+    alg = BYTES_PER_ACTIVE * vs_p + BYTES_PER_LANE * lanes * upd_n
     steps = n_chunks * every
     out = {
         "metric": METRIC, "value": vs_b / (ms_b / 1e3), "unit": "vehicle-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": 0, "ms_per_step": ms_b / steps, "sim_hz": steps / (ms_b / 1e3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch{len(ws)}_jittered_grids", "instances": len(ws), "vehicles": nveh,
-                   "lanes": lanes, "steps_per_phase_update": every, "launch": "captured 15-step HIP graphs"},
+                   "lanes": lanes, "steps_per_phase_update": every, "launch": "captured 15-step HIP graphs",
+                   "schedule": SCHEDULES[sched]},
         "vs_plain_loop": plain_ms / ms_b,
         "plain_loop": {"value": vs_b / (plain_ms / 1e3), "ms": plain_ms, "identical_results": bool(same)},
         "roofline": roofline(alg, upd_ms, upd_n, traffic_from_profiles(f"batch{len(ws)}")),
@@ -253,10 +276,32 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_copy(args):
+    """Plain device copy of a known size (calibrates the HBM byte counters:
+    FETCH_SIZE and WRITE_SIZE of this kernel versus its 2 x bytes moved)."""
+    import torch
+    n = int(args.copy_mib) << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps or 10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (args.steps or 10)
+    print(json.dumps({"workload": "copy", "bytes_read": n, "bytes_written": n, "ms_per_copy": ms,
+                      "GBps": 2 * n / (ms / 1e3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["city", "batch", "serve"], default="city")
+    ap.add_argument("--workload", choices=["city", "batch", "serve", "copy"], default="city")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=3)
@@ -279,9 +324,12 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "copy":
+        return run_copy(args)
     args.steps = args.steps or 7200
 
     from paper_2406_10661_amd import workloads as W
+    from paper_2406_10661_amd.tsim import SCHEDULES
     t0 = time.time()
     w = W.CONFIGS[args.config]()
     log(f"[bench] workload {w.name}: {w.network.n_roads} roads, {w.network.n_lanes} lanes, "
@@ -293,6 +341,12 @@ def main():
     init = sim.get_state()
     log(f"[bench] device arena {sim.arena.numel() / 2**30:.2f} GiB")
     stream = torch.cuda.current_stream()
+    # schedule: autotuned on a seeded mid-horizon state (about half the
+    # vehicles on the network), outside the timed region
+    sched, us = autotune_city(sim, w, W)
+    log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step by schedule "
+        f"{[round(float(x), 1) for x in us]}")
+    sim.set_state(init)
     if args.warmup:
         sim.step(args.warmup)
         torch.cuda.synchronize()
@@ -348,7 +402,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "junctions": w.network.n_junctions, "roads": w.network.n_roads,
                    "lanes": w.network.n_lanes, "vehicles": w.trips.n_vehicles, "dt_s": w.params.dt,
-                   "horizon_steps": w.n_steps, "timed_from_step": 0},
+                   "horizon_steps": w.n_steps, "timed_from_step": 0, "schedule": SCHEDULES[sched]},
         "result": {"finished": m1["n_finished"], "mean_road_speed": m1["mean_speed_avg"], "att_s": m1["att"],
                    "lane_changes": m1["lane_changes"], "errors": m1["errors"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -204,6 +204,32 @@ int tsim_get_kernel_times(tsim_handle *h, double *ms, int64_t *launches, int32_t
  * [0, 4096]; TSIM_EDEVICE if capture fails. */
 int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
 
+/* Update schedules: how road tiles are laid onto 64-wide wavefronts.
+ *   0 TSIM_SCHED_WIDE    one tile per wavefront
+ *   1 TSIM_SCHED_16X32   tiles of <= 16 lanes: four per wavefront while they
+ *                        hold <= 32 vehicles (fuller ones: one per wavefront)
+ *   2 TSIM_SCHED_16X64   as 1 with <= 64 vehicles
+ *   3 TSIM_SCHED_32X64   tiles of <= 32 lanes: two per wavefront, <= 64 vehicles
+ *   4 TSIM_SCHED_8X16    tiles of <= 8 lanes: eight per wavefront, <= 16 vehicles
+ * Every schedule gives bit-identical results; only speed differs.  Default 1.
+ * Changing the schedule synchronises the stream and drops a captured graph
+ * (recaptured on the next tsim_step). */
+#define TSIM_SCHED_WIDE 0
+#define TSIM_SCHED_16X32 1
+#define TSIM_SCHED_16X64 2
+#define TSIM_SCHED_32X64 3
+#define TSIM_SCHED_8X16 4
+#define TSIM_NUM_SCHED 5
+int tsim_set_schedule(tsim_handle *h, int32_t schedule);
+int tsim_get_schedule(tsim_handle *h, int32_t *schedule);
+/* Autotuner: runs `rounds` rounds of `steps` steps under every schedule in
+ * turn (these are real steps: the simulation advances by
+ * rounds * TSIM_NUM_SCHED * steps), keeps the schedule with the lowest best
+ * round time, and writes it to *chosen; us_per_step (optional, TSIM_NUM_SCHED
+ * entries) receives each schedule's best microseconds per step.  Synchronises
+ * the stream.  Works on batches too. */
+int tsim_autotune(tsim_handle *h, int32_t steps, int32_t rounds, int32_t *chosen, float *us_per_step);
+
 int tsim_destroy(tsim_handle *h);
 const char *tsim_last_error(const tsim_handle *h);
 

@@ -46,7 +46,10 @@ struct Build {
     std::vector<float> tau, vf, vlen;
     std::vector<int32_t> route_begin, route, q_begin, q_veh;
     uint64_t slots = 0;
-    int G = 0;
+    int G = 0;                       // partial slots: max over schedules of GA + GB
+    // tile classes by lane count (<= 8, <= 16, <= 32, more), class-major in
+    // tile_order; n_le[c] = tiles of classes 0..c
+    int n_le[4] = {0, 0, 0, 0};
     // instances of a batch (one for tsim_create)
     int n_inst = 1;
     bool blocked = false;
@@ -68,6 +71,61 @@ int fail(std::string* err, int code, const std::string& msg)
     if (err) *err = msg;
     g_error = msg;
     return code;
+}
+
+int tile_class(const Build& B, int r)
+{
+    const int nl = B.tile_lane_begin[r + 1] - B.tile_lane_begin[r];
+    return nl <= 8 ? 0 : (nl <= 16 ? 1 : (nl <= 32 ? 2 : 3));
+}
+
+// grid of a schedule: tiles of the grouped pass, its workgroups, and the
+// wide pass's workgroups
+struct SchedGrid {
+    int gw, nA, GA, GB;
+};
+
+SchedGrid sched_grid(const Build& B, int sched)
+{
+    SchedGrid g{64, 0, 0, 0};
+    switch (sched) {
+    case kSched8x16: g.gw = 8; g.nA = B.n_le[0]; break;
+    case kSched16x32:
+    case kSched16x64: g.gw = 16; g.nA = B.n_le[1]; break;
+    case kSched32x64: g.gw = 32; g.nA = B.n_le[2]; break;
+    default: g.gw = 64; g.nA = 0; break;
+    }
+    const int ng = 64 / g.gw;
+    g.GA = g.nA > 0 ? std::min((g.nA + ng - 1) / ng, 16384) : 0;
+    g.GB = std::max(1, std::min(8192, (B.R - g.nA) + (g.nA + 3) / 4));
+    return g;
+}
+
+// tile_order: class-major (so every grouped schedule takes a prefix), then
+// by instance (batches), then larger capacity first
+void order_tiles(Build& B, bool by_instance)
+{
+    const int R = B.R;
+    std::vector<long long> tcap(R, 0);
+    std::vector<int> cls(R);
+    for (int r = 0; r < R; ++r) {
+        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) tcap[r] += B.lane_cap[m];
+        cls[r] = tile_class(B, r);
+    }
+    std::stable_sort(B.tile_order.begin(), B.tile_order.end(), [&](int a, int b) {
+        if (cls[a] != cls[b]) return cls[a] < cls[b];
+        if (by_instance && B.tile_inst[a] != B.tile_inst[b]) return B.tile_inst[a] < B.tile_inst[b];
+        return tcap[a] > tcap[b];
+    });
+    int cnt[4] = {0, 0, 0, 0};
+    for (int r = 0; r < R; ++r) cnt[cls[r]]++;
+    B.n_le[0] = cnt[0];
+    for (int c = 1; c < 4; ++c) B.n_le[c] = B.n_le[c - 1] + cnt[c];
+    B.G = 1;
+    for (int s = 0; s < kNumSched; ++s) {
+        const SchedGrid g = sched_grid(B, s);
+        B.G = std::max(B.G, g.GA + g.GB);
+    }
 }
 
 int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_params* prm, Build& B, std::string* err)
@@ -282,14 +340,9 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
                 return B.tau[a] < B.tau[b] || (B.tau[a] == B.tau[b] && a < b);
             });
     }
-    // tiles in decreasing capacity, so long roads start first
-    std::vector<long long> tcap(R, 0);
-    for (int r = 0; r < R; ++r)
-        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) tcap[r] += B.lane_cap[m];
     B.tile_order.resize(R);
     std::iota(B.tile_order.begin(), B.tile_order.end(), 0);
-    std::stable_sort(B.tile_order.begin(), B.tile_order.end(), [&](int a, int b) { return tcap[a] > tcap[b]; });
-    B.G = std::max(1, std::min(R, 8192));
+    order_tiles(B, false);
     return TSIM_OK;
 }
 
@@ -437,14 +490,9 @@ void batch_instances(Build& B, const Union& U, const tsim_params* prm, int n)
         B.inst_key[2 * k] = (uint32_t)prm[k].seed;
         B.inst_key[2 * k + 1] = (uint32_t)(prm[k].seed >> 32);
     }
-    // tiles grouped by instance (each workgroup takes a contiguous run),
-    // larger tiles first within an instance
-    std::vector<long long> tcap(B.R, 0);
-    for (int r = 0; r < B.R; ++r)
-        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) tcap[r] += B.lane_cap[m];
-    std::stable_sort(B.tile_order.begin(), B.tile_order.end(), [&](int a, int b) {
-        return B.tile_inst[a] < B.tile_inst[b] || (B.tile_inst[a] == B.tile_inst[b] && tcap[a] > tcap[b]);
-    });
+    // tiles grouped by instance within each class (each workgroup takes a
+    // contiguous run), larger tiles first within an instance
+    order_tiles(B, true);
 }
 
 }  // namespace
@@ -550,6 +598,10 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.sh_pref, S * 4);
     add(&D.road_speed, R * 4);
     add(&D.lane_wait, NL * 4);
+    add(&D.fgate, (size_t)kGateBufs * NL * 4);
+    add(&D.fmax, (size_t)kGateBufs * NL * 4);
+    add(&D.ovf, std::max<size_t>(R, 1) * 4);
+    add(&D.ovf_cnt, 4);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.done_ctr, 4);
     add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
@@ -699,6 +751,19 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
             recs.push_back(o);
         }
     }
+    // feeder gates of the current step from the junction-lane summaries; the
+    // other two buffers start cleared
+    std::vector<int32_t> gate((size_t)kGateBufs * B.NL, kNoGate), fmx((size_t)kGateBufs * B.NL, kNoFeeder);
+    {
+        const size_t cb = (size_t)(step % kGateBufs) * B.NL;
+        for (int q = 0; q < B.NL; ++q) {
+            const int g = B.jl_out[q];
+            if (g < 0 || sum[q].cnt == 0) continue;
+            const float fr = sum[q].front_reach;
+            fmx[cb + g] = std::max(fmx[cb + g], f2o(fr));
+            if (fr > 0.0f) gate[cb + g] = std::min(gate[cb + g], B.jl_ext[q]);
+        }
+    }
     std::vector<int32_t> qhead(B.R);
     for (int r = 0; r < B.R; ++r) {
         int hd = B.q_begin[r];
@@ -741,6 +806,9 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.ovf_cnt, 0, 4, h->stream));
+    HIPCHK(h, up(h, D.fgate, gate));
+    HIPCHK(h, up(h, D.fmax, fmx));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
@@ -769,6 +837,15 @@ int tsim_footprint(const tsim_network* net, const tsim_trips* trips, const tsim_
 
 static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stream, void* device_arena,
                        size_t arena_bytes, tsim_handle** out);
+
+static void set_sched(DevNet& D, const Build& B, int sched)
+{
+    const SchedGrid g = sched_grid(B, sched);
+    D.sched = sched;
+    D.nA = g.nA;
+    D.GA = g.GA;
+    D.GB = g.GB;
+}
 
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,
                 void* device_arena, size_t arena_bytes, tsim_handle** out)
@@ -849,6 +926,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     D.NL = B.NL;
     D.N = B.N;
     D.G = B.G;
+    set_sched(D, B, kSched16x32);
     D.n_inst = B.n_inst;
     D.blocked = B.blocked ? 1 : 0;
     fill_params(D.P, params);
@@ -981,6 +1059,81 @@ int tsim_set_graph_steps(tsim_handle* h, int32_t chunk)
     }
     h->graph_chunk = chunk;
     return TSIM_OK;
+}
+
+int tsim_set_schedule(tsim_handle* h, int32_t schedule)
+{
+    if (!h || schedule < 0 || schedule >= kNumSched) return fail(nullptr, TSIM_EINVAL, "bad handle or schedule");
+    if (schedule == h->D.sched) return TSIM_OK;
+    if (h->graph) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    set_sched(h->D, h->B, schedule);
+    return TSIM_OK;
+}
+
+int tsim_get_schedule(tsim_handle* h, int32_t* schedule)
+{
+    if (!h || !schedule) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    *schedule = h->D.sched;
+    return TSIM_OK;
+}
+
+int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen, float* us_per_step)
+{
+    if (!h || steps < 1 || rounds < 1 || steps > 100000 || rounds > 100)
+        return fail(nullptr, TSIM_EINVAL, "bad handle, steps or rounds");
+    std::vector<hipEvent_t> ev(2 * (size_t)rounds * kNumSched, nullptr);
+    int rc = TSIM_OK;
+    for (auto& e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            rc = fail(&h->err, TSIM_EDEVICE, "event creation failed");
+            break;
+        }
+    }
+    const int keep = h->D.sched;
+    for (int r = 0; r < rounds && rc == TSIM_OK; ++r) {
+        for (int sc = 0; sc < kNumSched && rc == TSIM_OK; ++sc) {
+            set_sched(h->D, h->B, sc);
+            const size_t k = 2 * ((size_t)r * kNumSched + sc);
+            hipError_t e = hipEventRecord(ev[k], h->stream);
+            for (int t = 0; t < steps && e == hipSuccess; ++t) {
+                e = launch_prepare(h->d_net, h->D, h->stream);
+                if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->stream);
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev[k + 1], h->stream);
+            if (e != hipSuccess) rc = hip_fail(h, e, "autotune");
+        }
+    }
+    float best_ms[kNumSched];
+    for (int sc = 0; sc < kNumSched; ++sc) best_ms[sc] = std::numeric_limits<float>::infinity();
+    if (rc == TSIM_OK) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        for (int r = 0; r < rounds && e == hipSuccess; ++r)
+            for (int sc = 0; sc < kNumSched && e == hipSuccess; ++sc) {
+                const size_t k = 2 * ((size_t)r * kNumSched + sc);
+                float ms = 0.0f;
+                e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                best_ms[sc] = std::min(best_ms[sc], ms);
+            }
+        if (e != hipSuccess) rc = hip_fail(h, e, "autotune timing");
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    int pick = keep;
+    if (rc == TSIM_OK) {
+        pick = 0;
+        for (int sc = 1; sc < kNumSched; ++sc)
+            if (best_ms[sc] < best_ms[pick]) pick = sc;
+        if (us_per_step)
+            for (int sc = 0; sc < kNumSched; ++sc) us_per_step[sc] = best_ms[sc] * 1000.0f / (float)steps;
+    }
+    set_sched(h->D, h->B, keep);
+    const int rc2 = tsim_set_schedule(h, pick);
+    if (chosen) *chosen = h->D.sched;
+    return rc ? rc : rc2;
 }
 
 int tsim_step(tsim_handle* h, int32_t n_steps)

@@ -22,9 +22,18 @@ constexpr int kMaxTileLanes = 64;    // road lanes + junction lanes of one road
 constexpr int kMaxRoadLanes = 32;
 constexpr int kMaxPhases = 32;
 constexpr int kWave = 64;
-constexpr int kChangerCap = 64;      // lane changers per tile kept in LDS
-constexpr int kMergeCap = 64;        // merging vehicles per tile kept in LDS
-constexpr int kTileCap = 128;        // vehicles of a tile staged in LDS
+constexpr int kChangerCap = 64;      // lane changers per tile kept in LDS (wide tiles)
+constexpr int kMergeCap = 64;        // merging vehicles per tile kept in LDS (wide tiles)
+constexpr int kTileCap = 128;        // vehicles of a wide tile staged in LDS
+constexpr int kGateBufs = 3;         // feeder gate buffers: read t%3, write (t+1)%3, clear (t+2)%3
+constexpr int kNoGate = 0x7FFFFFFF;  // no feeder holds the lane
+constexpr int kNoFeeder = (int)0x80000000;  // no nonempty feeder
+
+// Update schedules: how road tiles map onto wavefronts.  A tile of at most
+// `lanes` lanes goes to a group of `width` lanes of a wavefront (64 / width
+// tiles per wavefront) when it holds at most `cap` vehicles; larger tiles run
+// one per wavefront in the wide pass.
+enum Schedule { kSchedWide = 0, kSched16x32 = 1, kSched16x64 = 2, kSched32x64 = 3, kSched8x16 = 4, kNumSched = 5 };
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
 constexpr int kWaitSpeedFlag = 0;
@@ -48,6 +57,21 @@ struct __align__(16) LaneSum {
     float rear_v;       // its speed
     float front_reach;  // front vehicle's x + v dt + a_max dt^2/2 - lane length
 };
+
+// order-preserving map of floats to ints (for atomicMax on floats)
+__host__ __device__ inline int f2o(float f)
+{
+    int i;
+    __builtin_memcpy(&i, &f, 4);
+    return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__host__ __device__ inline float o2f(int i)
+{
+    const int b = i >= 0 ? i : i ^ 0x7FFFFFFF;
+    float f;
+    __builtin_memcpy(&f, &b, 4);
+    return f;
+}
 
 struct KParams {
     float dt, T, a_max, s0, delta, p, a_th, b_safe, p_max, p_min, a_emerg;
@@ -154,10 +178,21 @@ struct DevNet {
     int32_t* sh_kind;                // 0 stay, 1 change, 2 enter junction lane, 3 leave tile, 4 finished
     int32_t* sh_nlane;               // local index of the new lane
     int32_t* sh_pref;                // stayer prefix count within the tile enumeration
+    // feeder gates of each lane (indexed by internal lane id), three buffers
+    // by step: min external index among nonempty feeders whose front vehicle
+    // can pass the lane end within a step (kNoGate if none), and the max front
+    // reach of nonempty feeders as an order-preserving int (kNoFeeder if none)
+    int32_t* fgate;                  // [3 NL]
+    int32_t* fmax;                   // [3 NL]
+    // small-class tiles too full for their group, run by the wide pass
+    int32_t* ovf;                    // [R]
+    int32_t* ovf_cnt;
+    // schedule (host side; passed to the kernels as arguments)
+    int32_t sched, nA, GA, GB;
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)
-    WGPartial* part;                 // [G]
+    WGPartial* part;                 // [G] (G >= GA + GB for every schedule)
     unsigned int* done_ctr;
     DevMetrics* met;                 // [n_inst]
     KParams P;

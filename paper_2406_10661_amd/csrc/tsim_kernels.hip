@@ -153,6 +153,16 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
     const long long t = tg - D.inst_t0[inst];
     const int lb = D.tile_lane_begin[r];
     const int nrl = D.tile_n_road[r];
+    const int32_t* fmax_r = D.fmax + (size_t)(tg % kGateBufs) * D.NL;
+    {
+        // feeder gates of this road's lanes: clear the buffer that the step
+        // after this one fills (nothing reads or writes it during this step)
+        const size_t cb = (size_t)((tg + 2) % kGateBufs) * D.NL;
+        for (int li = 0; li < nrl; ++li) {
+            D.fgate[cb + lb + li] = kNoGate;
+            D.fmax[cb + lb + li] = kNoFeeder;
+        }
+    }
     long long errors = 0;
     int appended = 0;
     for (int li = 0; li < nrl; ++li) {
@@ -197,14 +207,9 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
             if (used & (1u << li)) continue;
             const int m = lb + li;
             if (nr >= 0 && out_toward(D, m, nr) < 0) continue;
-            bool safe = true;
-            for (int e = D.feed_begin[m]; e < D.feed_begin[m + 1]; ++e) {
-                const LaneSum f = sum[D.feed_jl[e]];
-                if (f.cnt == 0) continue;
-                const float mg = -Lv - f.front_reach;
-                if (!(mg >= 0.0f)) safe = false;
-            }
-            if (!safe) continue;
+            // no nonempty feeder may reach past the entrant's rear (x = 0)
+            const int fm = fmax_r[m];
+            if (fm != kNoFeeder && !(-Lv - o2f(fm) >= 0.0f)) continue;
             const LaneSum s = sum[m];
             const float room = s.cnt > 0 ? s.rear : TS_INF;
             if (room > best_room) {
@@ -257,59 +262,70 @@ struct DirEval {
     Lead lead; // target-lane leader
 };
 
-struct TileShared {
-    int lane[kMaxTileLanes];
-    int cnt[kMaxTileLanes];
-    int start[kMaxTileLanes + 1];
-    uint32_t base[kMaxTileLanes];
-    float len[kMaxTileLanes];
-    float lim[kMaxTileLanes];
-    int jl_out[kMaxTileLanes];
-    int jl_out_road[kMaxTileLanes];
-    int jl_in_local[kMaxTileLanes];
-    int green[kMaxTileLanes];
-    int nstay[kMaxTileLanes];
-    int nin[kMaxTileLanes];
-    int nenter[kMaxTileLanes];
-    int wait[kMaxTileLanes];
-    int nlanes, nroad, n, skip;
+// LDS image of one road tile: lane tables, per-tile lists and counters, and
+// (when staged) the tile's records and per-vehicle scratch, indexed by the
+// tile enumeration j (lanes in order, front first)
+template <int LANES, int CAP, int CHG>
+struct TileLds {
+    static constexpr int kLanes = LANES, kCap = CAP, kChg = CHG;
+    int lane[LANES];
+    int cnt[LANES];
+    int start[LANES + 1];
+    uint32_t base[LANES];
+    int cap[LANES];
+    float len[LANES];
+    float lim[LANES];
+    int jl_out[LANES];
+    int jl_out_road[LANES];
+    int jl_in_local[LANES];
+    int jl_ext[LANES];
+    int green[LANES];
+    int fmx[LANES];        // road lanes: feeder max front reach (ordered int)
+    int gate[LANES];       // junction lanes: feeder gate of the out lane
+    LaneSum osum[LANES];   // junction lanes: summary of the out lane
+    int nstay[LANES];
+    int nin[LANES];
+    int nenter[LANES];
+    int wait[LANES];
+    int nlanes, nroad, n;
     int nchg, nmerge;
-    float chg_x[kChangerCap];
-    int chg_vid[kChangerCap];
-    int chg_lane[kChangerCap];
-    int mrg_tgt[kMergeCap];
-    float mrg_rear[kMergeCap];
-    float mrg_v[kMergeCap];
-    int mrg_vid[kMergeCap];
+    float chg_x[CHG];
+    int chg_vid[CHG];
+    int chg_lane[CHG];
+    int mrg_tgt[CHG];
+    float mrg_rear[CHG];
+    float mrg_v[CHG];
+    int mrg_vid[CHG];
     unsigned long long sumv;
     unsigned long long sum_tt;
     int cntv;
     int changes, transfers, clamps, fblocks, finished, errors;
-    // staged tile (n <= kTileCap)
-    VehRec rec[kTileCap];
-    float aown[kTileCap];
-    float lrear[kTileCap];
-    float lv[kTileCap];
-    float nx[kTileCap];
-    float nv[kTileCap];
-    uint32_t gmask[kTileCap];
-    int pref[kTileCap];
-    signed char merge[kTileCap];
-    signed char kind[kTileCap];
-    signed char nlane[kTileCap];
+    VehRec rec[CAP];
+    float aown[CAP];
+    float lrear[CAP];
+    float lv[CAP];
+    float nx[CAP];
+    float nv[CAP];
+    uint32_t gmask[CAP];
+    int pref[CAP];
+    signed char merge[CAP];
+    signed char kind[CAP];
+    signed char nlane[CAP];
+    signed char vl[CAP];   // lane of vehicle j
 };
 
-__device__ __forceinline__ int lane_of(const TileShared& S, int j)
+template <class TS>
+__device__ __forceinline__ int lane_of(const TS& S, int j)
 {
     int li = 0;
     while (j >= S.start[li + 1]) li++;
     return li;
 }
 
-// per-vehicle storage of a tile staged in LDS, indexed by the tile
-// enumeration j (lanes in order, front first)
+template <class TS>
 struct LdsView {
-    TileShared& S;
+    TS& S;
+    __device__ int lane(int j) const { return S.vl[j]; }
     __device__ VehRec rec(int j) const { return S.rec[j]; }
     __device__ float aown(int j) const { return S.aown[j]; }
     __device__ float lrear(int j) const { return S.lrear[j]; }
@@ -339,11 +355,13 @@ struct LdsView {
     __device__ void set_pref(int j, int v) { S.pref[j] = v; }
 };
 
-// the same storage in global per-slot scratch, for tiles larger than kTileCap
+// the same storage in global per-slot scratch, for wide tiles above kTileCap
+template <class TS>
 struct GlobalView {
-    TileShared& S;
+    TS& S;
     const DevNet& D;
     const VehRec* rd;
+    __device__ int lane(int j) const { return lane_of(S, j); }
     __device__ uint32_t slot(int j) const
     {
         const int li = lane_of(S, j);
@@ -393,7 +411,8 @@ __device__ __forceinline__ int group_dist(uint32_t gmask, int li, int nroad)
 }
 
 // tile junction lane (local index) leaving local road lane li toward road nr
-__device__ __forceinline__ int tile_jl(const TileShared& S, int li, int nr)
+template <class TS>
+__device__ __forceinline__ int tile_jl(const TS& S, int li, int nr)
 {
     if (nr < 0) return -1;
     for (int q = S.nroad; q < S.nlanes; ++q)
@@ -401,7 +420,8 @@ __device__ __forceinline__ int tile_jl(const TileShared& S, int li, int nr)
     return -1;
 }
 
-__device__ __forceinline__ bool tile_stop(const TileShared& S, int li, int nr, bool with_wrong)
+template <class TS>
+__device__ __forceinline__ bool tile_stop(const TS& S, int li, int nr, bool with_wrong)
 {
     if (li >= S.nroad || nr < 0) return false;
     const int q = tile_jl(S, li, nr);
@@ -410,8 +430,8 @@ __device__ __forceinline__ bool tile_stop(const TileShared& S, int li, int nr, b
 }
 
 // number of vehicles of tile lane li ahead of (x, vid)
-template <class V>
-__device__ __forceinline__ int count_ahead(const TileShared& S, const V& view, int li, float x, int vid)
+template <class TS, class V>
+__device__ __forceinline__ int count_ahead(const TS& S, const V& view, int li, float x, int vid)
 {
     int lo = 0, hi = S.cnt[li];
     const int b = S.start[li];
@@ -426,9 +446,9 @@ __device__ __forceinline__ int count_ahead(const TileShared& S, const V& view, i
 
 // leader substitution for a vehicle at the front of tile lane li (route info
 // nr, rp, rem): rearmost vehicle of the next lane, else of the lane after it
-template <class V>
-__device__ Lead lookahead(const DevNet& D, const TileShared& S, const V& view, const LaneSum* sum, int li, int nr,
-                          int rp, int rem)
+template <class TS, class V>
+__device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const LaneSum* sum, int li, int nr, int rp,
+                          int rem)
 {
     Lead L{TS_INF, 0.0f, false};
     const float off = S.len[li];
@@ -442,7 +462,7 @@ __device__ Lead lookahead(const DevNet& D, const TileShared& S, const V& view, c
             L.v = z.v;
             return L;
         }
-        const LaneSum s2 = sum[S.jl_out[q]];
+        const LaneSum s2 = S.osum[q];
         if (s2.cnt > 0) {
             L.ex = true;
             L.rear = (off + S.len[q]) + s2.rear;
@@ -450,8 +470,7 @@ __device__ Lead lookahead(const DevNet& D, const TileShared& S, const V& view, c
         }
         return L;
     }
-    const int g1 = S.jl_out[li];
-    const LaneSum s1 = sum[g1];
+    const LaneSum s1 = S.osum[li];
     if (s1.cnt > 0) {
         L.ex = true;
         L.rear = off + s1.rear;
@@ -459,6 +478,7 @@ __device__ Lead lookahead(const DevNet& D, const TileShared& S, const V& view, c
         return L;
     }
     if (rem < 2) return L;
+    const int g1 = S.jl_out[li];
     const int g2 = out_toward(D, g1, D.route[rp + 2]);
     if (g2 < 0) return L;
     const LaneSum s2 = sum[g2];
@@ -470,20 +490,148 @@ __device__ Lead lookahead(const DevNet& D, const TileShared& S, const V& view, c
     return L;
 }
 
-template <class V>
-__device__ void process_tile(const DevNet& D, TileShared& S, V& view, const LaneSum* rsum, LaneSum* wsum,
-                             VehRec* wr, long long t, int inst, int tid)
+// buffers of one step
+struct StepBufs {
+    const VehRec* rd;
+    VehRec* wr;
+    const LaneSum* rsum;
+    LaneSum* wsum;
+    const int32_t* rtn;
+    int32_t* wtn;
+    const int32_t* gate_r;
+    int32_t* gate_w;
+    const int32_t* fmax_r;
+    int32_t* fmax_w;
+};
+
+__device__ __forceinline__ StepBufs step_bufs(const DevNet& D, long long tg)
+{
+    StepBufs B;
+    const int p = (int)(tg & 1);
+    B.rd = p ? D.slab1 : D.slab0;
+    B.wr = p ? D.slab0 : D.slab1;
+    B.rsum = p ? D.sum1 : D.sum0;
+    B.wsum = p ? D.sum0 : D.sum1;
+    B.rtn = p ? D.tile_n1 : D.tile_n0;
+    B.wtn = p ? D.tile_n0 : D.tile_n1;
+    const int rb = (int)(tg % kGateBufs), wb = (int)((tg + 1) % kGateBufs);
+    B.gate_r = D.fgate + (size_t)rb * D.NL;
+    B.gate_w = D.fgate + (size_t)wb * D.NL;
+    B.fmax_r = D.fmax + (size_t)rb * D.NL;
+    B.fmax_w = D.fmax + (size_t)wb * D.NL;
+    return B;
+}
+
+// tile header, loaded one round ahead of its use
+struct Hdr {
+    int r, rt, wt, lb, nl, nroad, inst;
+};
+
+__device__ __forceinline__ Hdr load_hdr(const DevNet& D, const StepBufs& B, int r)
+{
+    Hdr h;
+    h.r = r;
+    h.rt = h.wt = 0;
+    h.lb = h.nl = h.nroad = h.inst = 0;
+    if (r < 0) return h;
+    h.rt = B.rtn[r];
+    h.wt = B.wtn[r];
+    h.lb = D.tile_lane_begin[r];
+    h.nl = D.tile_lane_begin[r + 1] - h.lb;
+    h.nroad = D.tile_n_road[r];
+    h.inst = D.tile_inst[r];
+    return h;
+}
+
+// lane tables of the tile into LDS (thread gt < nl loads lane gt), in two
+// rounds: first what the lane scan needs (one dependent load after the
+// header), then what junction lanes reach through their out lane and signal,
+// issued together with the record staging
+struct LaneRegs {
+    int g;          // out lane of a junction lane
+    int junc;       // its junction
+    uint32_t mask;  // its green phases
+};
+
+template <class TS>
+__device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt)
+{
+    LaneRegs lr{-1, 0, 0u};
+    if (gt >= h.nl) return lr;
+    const int m = h.lb + gt;
+    const bool jl = gt >= h.nroad;
+    S.lane[gt] = m;
+    S.cnt[gt] = B.rsum[m].cnt;
+    S.base[gt] = D.lane_base[m];
+    S.cap[gt] = D.lane_cap[m];
+    S.len[gt] = D.lane_len[m];
+    S.lim[gt] = D.lane_lim[m];
+    S.nstay[gt] = 0;
+    S.nin[gt] = 0;
+    S.nenter[gt] = 0;
+    S.wait[gt] = 0;
+    if (jl) {
+        lr.g = D.jl_out[m];
+        lr.junc = D.jl_junc[m];
+        lr.mask = D.jl_green_mask[m];
+        S.jl_out[gt] = lr.g;
+        S.jl_out_road[gt] = D.jl_out_road[m];
+        S.jl_in_local[gt] = D.jl_in_local[m];
+        S.jl_ext[gt] = D.jl_ext[m];
+        S.fmx[gt] = kNoFeeder;
+    } else {
+        S.jl_out[gt] = -1;
+        S.jl_out_road[gt] = -1;
+        S.jl_in_local[gt] = -1;
+        S.jl_ext[gt] = -1;
+        S.fmx[gt] = B.fmax_r[m];
+        S.green[gt] = 1;
+        S.gate[gt] = kNoGate;
+    }
+    return lr;
+}
+
+template <class TS>
+__device__ __forceinline__ void load_lanes_b(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt,
+                                             const LaneRegs& lr)
+{
+    if (gt >= h.nl || gt < h.nroad) return;
+    const int cur = D.junc_cur[lr.junc];
+    S.green[gt] = (cur < 0 || ((lr.mask >> cur) & 1u)) ? 1 : 0;
+    S.osum[gt] = B.rsum[lr.g];
+    S.gate[gt] = B.gate_r[lr.g];
+}
+
+template <class TS>
+__device__ __forceinline__ void reset_counters(TS& S, const Hdr& h)
+{
+    S.nlanes = h.nl;
+    S.nroad = h.nroad;
+    S.nchg = 0;
+    S.nmerge = 0;
+    S.sumv = 0ull;
+    S.cntv = 0;
+    S.changes = S.transfers = S.clamps = S.fblocks = S.finished = S.errors = 0;
+    S.sum_tt = 0ull;
+}
+
+// the three passes of one tile; n vehicles (0 = nothing to do), run by the
+// GW lanes gt of the group starting at wave lane gbase.  Barriers are
+// reached by every lane of the workgroup whatever n is.
+template <int GW, class TS, class V>
+__device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B, long long t, int inst, int gt,
+                             int gbase, int n)
 {
     const uint32_t key0 = D.inst_key[2 * inst], key1 = D.inst_key[2 * inst + 1];
     const int vbase = D.inst_vbase[inst];
     const KParams& P = D.P;
-    const int n = S.n;
     const int nl = S.nlanes;
     const int nroad = S.nroad;
+    const LaneSum* rsum = B.rsum;
 
     // ---------------- pass 1: own acceleration ----------------
-    for (int j = tid; j < n; j += kWave) {
-        const int li = lane_of(S, j);
+    for (int j = gt; j < n; j += GW) {
+        const int li = view.lane(j);
         const int c = j - S.start[li];
         const VehRec rec = view.rec(j);
         const bool is_jl = li >= nroad;
@@ -523,7 +671,7 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
         view.set1(j, gmask, a, mt, ld.ex ? ld.rear : TS_INF, ld.v);
         if (mt >= 0) {
             const int k = atomicAdd(&S.nmerge, 1);
-            if (k < kMergeCap) {
+            if (k < TS::kChg) {
                 S.mrg_tgt[k] = mt;
                 S.mrg_rear[k] = rec.x - rec.len;
                 S.mrg_v[k] = rec.v;
@@ -534,12 +682,11 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
     __syncthreads();
 
     // ---------------- pass 2: decision and motion ----------------
-    for (int j = tid; j < n; j += kWave) {
-        const int li = lane_of(S, j);
+    for (int j = gt; j < n; j += GW) {
+        const int li = view.lane(j);
         const int c = j - S.start[li];
         const VehRec rec = view.rec(j);
         const bool is_jl = li >= nroad;
-        const int m = S.lane[li];
         const float len = S.len[li];
         const float lim = S.lim[li];
         const float v0 = rec.f * lim;
@@ -593,11 +740,11 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
                 if (!(g4 >= 0.0f)) return o;
             }
             if (tf < 0) {
-                const int mk = S.lane[k];
-                for (int e = D.feed_begin[mk]; e < D.feed_begin[mk + 1]; ++e) {
-                    const LaneSum f = rsum[D.feed_jl[e]];
-                    if (f.cnt == 0) continue;
-                    const float g = (rec.x - rec.len) - f.front_reach;
+                // no follower in the target lane: the lane's feeders must not
+                // reach past the changer's rear (largest reach decides)
+                const int fm = S.fmx[k];
+                if (fm != kNoFeeder) {
+                    const float g = (rec.x - rec.len) - o2f(fm);
                     if (!(g >= 0.0f)) return o;
                 }
             }
@@ -668,7 +815,7 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
         if (!is_jl && !dec) {
             int y_vid = 0x7FFFFFFF;
             const int nm = S.nmerge;
-            if (nm <= kMergeCap) {
+            if (nm <= TS::kChg) {
                 for (int q = 0; q < nm; ++q) {
                     if (S.mrg_tgt[q] != li) continue;
                     const float rm = S.mrg_rear[q];
@@ -713,41 +860,41 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
             vn = 0.0f;
         }
         // snapshot bounds
-        float B = TS_INF, vcap = TS_INF;
+        float Bd = TS_INF, vcap = TS_INF;
         const float lr = view.lrear(j);
         if (lr < TS_INF) {
-            B = lr;
+            Bd = lr;
             vcap = view.lv(j);
         }
         if (dec) {
             const Lead l2 = dec == 1 ? eL.lead : eR.lead;
             if (l2.ex) {
-                if (l2.rear < B) {
-                    B = l2.rear;
+                if (l2.rear < Bd) {
+                    Bd = l2.rear;
                     vcap = l2.v;
-                } else if (l2.rear == B) {
+                } else if (l2.rear == Bd) {
                     vcap = fminf(vcap, l2.v);
                 }
             }
         }
         if (has_y) {
-            if (y_rear < B) {
-                B = y_rear;
+            if (y_rear < Bd) {
+                Bd = y_rear;
                 vcap = y_v;
-            } else if (y_rear == B) {
+            } else if (y_rear == Bd) {
                 vcap = fminf(vcap, y_v);
             }
         }
         if (tile_stop(S, nli, rec.nr, true)) {
-            if (len < B) {
-                B = len;
+            if (len < Bd) {
+                Bd = len;
                 vcap = 0.0f;
-            } else if (len == B) {
+            } else if (len == Bd) {
                 vcap = 0.0f;
             }
         }
-        if (xn > B) {
-            xn = fmaxf(B, x);
+        if (xn > Bd) {
+            xn = fmaxf(Bd, x);
             vn = fminf(vn, vcap);
             atomicAdd(&S.clamps, 1);
         }
@@ -767,17 +914,10 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
                 xn -= len;
                 atomicAdd(&S.transfers, 1);
             } else {
+                // feeder priority: an earlier feeder of the out lane whose
+                // front vehicle can pass its end this step goes first
                 const int g = S.jl_out[li];
-                bool blocked = false;
-                const int my_ext = D.jl_ext[m];
-                for (int e = D.feed_begin[g]; e < D.feed_begin[g + 1]; ++e) {
-                    const int fl = D.feed_jl[e];
-                    if (D.jl_ext[fl] >= my_ext) break;
-                    const LaneSum f = rsum[fl];
-                    if (f.cnt == 0) continue;
-                    if (f.front_reach > 0.0f) blocked = true;
-                }
-                if (blocked) {
+                if (S.gate[li] < S.jl_ext[li]) {
                     xn = len;
                     vn = 0.0f;
                     atomicAdd(&S.fblocks, 1);
@@ -811,7 +951,7 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
         } else if (kind == 1) {
             atomicAdd(&S.nin[nli], 1);
             const int q = atomicAdd(&S.nchg, 1);
-            if (q < kChangerCap) {
+            if (q < TS::kChg) {
                 S.chg_x[q] = xn;
                 S.chg_vid[q] = rec.vid;
                 S.chg_lane[q] = nli;
@@ -825,20 +965,23 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
     // ---------------- pass 3: new order ----------------
     {
         int carry = 0;
-        for (int b0 = 0; b0 < n; b0 += kWave) {
-            const int j = b0 + tid;
+        for (int b0 = 0; b0 < n; b0 += GW) {
+            const int j = b0 + gt;
             const bool st = j < n && view.kind(j) == 0;
             const unsigned long long bal = __ballot(st);
-            if (j < n) view.set_pref(j, carry + __popcll(bal & ((1ull << tid) - 1ull)));
-            carry += __popcll(bal);
+            unsigned long long mine;
+            if constexpr (GW == kWave) mine = bal;
+            else mine = (bal >> gbase) & ((1ull << GW) - 1ull);
+            if (j < n) view.set_pref(j, carry + __popcll(mine & ((1ull << gt) - 1ull)));
+            carry += __popcll(mine);
         }
     }
     __syncthreads();
     const int nchg = S.nchg;
-    for (int j = tid; j < n; j += kWave) {
+    for (int j = gt; j < n; j += GW) {
         const int kind = view.kind(j);
         if (kind >= 3) continue;
-        const int li = lane_of(S, j);
+        const int li = view.lane(j);
         const VehRec rec = view.rec(j);
         const float xn = view.nx(j);
         const int nli = view.nlane(j);
@@ -856,7 +999,7 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
         }
         if (kind <= 1) {
             // changers into the same lane ahead of this vehicle
-            if (nchg <= kChangerCap) {
+            if (nchg <= TS::kChg) {
                 for (int q = 0; q < nchg; ++q)
                     if (S.chg_lane[q] == nli && S.chg_vid[q] != rec.vid && ahead(S.chg_x[q], S.chg_vid[q], xn, rec.vid))
                         rank++;
@@ -875,15 +1018,24 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
         }
         const int mn = S.lane[nli];
         const int total = S.nstay[nli] + S.nin[nli] + S.nenter[nli];
-        if (rank < D.lane_cap[mn]) {
+        if (rank < S.cap[nli]) {
             VehRec o = rec;
             o.x = xn;
             o.v = view.nv(j);
-            wr[S.base[nli] + rank] = o;
-            if (rank == 0) wsum[mn].front_reach = front_reach(o.x, o.v, S.len[nli], P);
+            B.wr[S.base[nli] + rank] = o;
+            if (rank == 0) {
+                const float fr = front_reach(o.x, o.v, S.len[nli], P);
+                B.wsum[mn].front_reach = fr;
+                if (nli >= nroad) {
+                    // this junction lane feeds its out lane next step
+                    const int g = S.jl_out[nli];
+                    atomicMax(&B.fmax_w[g], f2o(fr));
+                    if (fr > 0.0f) atomicMin(&B.gate_w[g], S.jl_ext[nli]);
+                }
+            }
             if (rank == total - 1) {
-                wsum[mn].rear = o.x - o.len;
-                wsum[mn].rear_v = o.v;
+                B.wsum[mn].rear = o.x - o.len;
+                B.wsum[mn].rear_v = o.v;
             }
         } else {
             atomicAdd(&S.errors, 1);
@@ -891,166 +1043,83 @@ __device__ void process_tile(const DevNet& D, TileShared& S, V& view, const Lane
     }
 }
 
-__global__ __launch_bounds__(kWave) void k_update(const DevNet* __restrict__ Dp)
+// lane summaries, waiting counts and tile totals after a processed tile
+template <class TS>
+__device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt, int n,
+                                            WGPartial& acc)
 {
-    __shared__ TileShared S;
-    const DevNet& D = *Dp;
-    const long long tg = *D.gstep;
-    const int p = (int)(tg & 1);
-    const VehRec* rd = p ? D.slab1 : D.slab0;
-    VehRec* wr = p ? D.slab0 : D.slab1;
-    const LaneSum* rsum = p ? D.sum1 : D.sum0;
-    LaneSum* wsum = p ? D.sum0 : D.sum1;
-    const int32_t* rtn = p ? D.tile_n1 : D.tile_n0;
-    int32_t* wtn = p ? D.tile_n0 : D.tile_n1;
+    if (gt < h.nl) {
+        const int m = h.lb + gt;
+        const int c = S.nstay[gt] + S.nin[gt] + S.nenter[gt];
+        B.wsum[m].cnt = c < S.cap[gt] ? c : S.cap[gt];
+        if (c == 0) {
+            B.wsum[m].rear = TS_INF;
+            B.wsum[m].rear_v = 0.0f;
+            B.wsum[m].front_reach = -TS_INF;
+        }
+        D.lane_wait[m] = S.wait[gt];
+    }
+    if (gt == 0) {
+        int tot = 0;
+        for (int q = 0; q < h.nl; ++q) tot += S.nstay[q] + S.nin[q] + S.nenter[q];
+        B.wtn[h.r] = tot;
+        D.road_speed[h.r] = S.cntv > 0 ? (float)((double)(long long)S.sumv / (double)kSpeedFx / (double)S.cntv) : -1.0f;
+        acc.sumv_fx += (long long)S.sumv;
+        acc.cnt += S.cntv;
+        acc.active += n;
+        acc.changes += S.changes;
+        acc.transfers += S.transfers;
+        acc.clamps += S.clamps;
+        acc.feeder_blocks += S.fblocks;
+        acc.finished += S.finished;
+        acc.sum_tt_fx += (long long)S.sum_tt;
+        acc.errors += S.errors;
+    }
+}
+
+// a tile with no vehicle now that had some at the previous step
+__device__ __forceinline__ void empty_tile(const DevNet& D, const StepBufs& B, const Hdr& h, int gt)
+{
+    if (gt < h.nl) {
+        LaneSum e;
+        e.cnt = 0;
+        e.rear = TS_INF;
+        e.rear_v = 0.0f;
+        e.front_reach = -TS_INF;
+        B.wsum[h.lb + gt] = e;
+        D.lane_wait[h.lb + gt] = 0;
+    }
+    if (gt == 0) {
+        D.road_speed[h.r] = -1.0f;
+        B.wtn[h.r] = 0;
+    }
+}
+
+__device__ __forceinline__ void flush_acc(const DevNet& D, WGPartial& acc, int inst)
+{
+    if (inst < 0) return;
+    unsigned long long* q = (unsigned long long*)&D.inst_acc[inst];
+    const long long* a = (const long long*)&acc;
+    for (int k = 0; k < 10; ++k)
+        if (a[k]) atomicAdd(q + k, (unsigned long long)a[k]);
+    acc = WGPartial{};
+}
+
+// per-workgroup partials; the workgroup that finishes last folds the step
+// (called by every lane of the workgroup; acc valid in lane 0)
+__device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc, int slot, int total_wg, int* skip)
+{
     const int tid = threadIdx.x;
-
-    WGPartial acc{};
-    int acc_inst = -1;
-    // batches: flush the running sums into the instance they belong to
-    auto flush = [&]() {
-        if (acc_inst < 0 || tid != 0) return;
-        unsigned long long* q = (unsigned long long*)&D.inst_acc[acc_inst];
-        const long long* a = (const long long*)&acc;
-        for (int k = 0; k < 10; ++k)
-            if (a[k]) atomicAdd(q + k, (unsigned long long)a[k]);
-    };
-    const int chunk = (D.R + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int t_begin = D.blocked ? (int)blockIdx.x * chunk : (int)blockIdx.x;
-    const int t_end = D.blocked ? min(D.R, t_begin + chunk) : D.R;
-    const int t_stride = D.blocked ? 1 : (int)gridDim.x;
-
-    for (int ti = t_begin; ti < t_end; ti += t_stride) {
-        const int r = D.tile_order[ti];
-        // a tile empty now and at the previous step already has empty
-        // summaries, zero queue counts and no road speed in both buffers
-        if (rtn[r] == 0 && wtn[r] == 0) continue;
-        const int inst = D.tile_inst[r];
-        const long long t = tg - D.inst_t0[inst];
-        if (D.n_inst > 1 && inst != acc_inst) {
-            flush();
-            acc = WGPartial{};
-            acc_inst = inst;
-        }
-        const int lb = D.tile_lane_begin[r];
-        const int nl = D.tile_lane_begin[r + 1] - lb;
-        const int nroad = D.tile_n_road[r];
-        if (tid < nl) {
-            const int m = lb + tid;
-            S.lane[tid] = m;
-            S.cnt[tid] = rsum[m].cnt;
-            S.base[tid] = D.lane_base[m];
-            S.len[tid] = D.lane_len[m];
-            S.lim[tid] = D.lane_lim[m];
-            const bool jl = tid >= nroad;
-            S.jl_out[tid] = jl ? D.jl_out[m] : -1;
-            S.jl_out_road[tid] = jl ? D.jl_out_road[m] : -1;
-            S.jl_in_local[tid] = jl ? D.jl_in_local[m] : -1;
-            S.green[tid] = jl ? (int)jl_green(D, m) : 1;
-            S.nstay[tid] = 0;
-            S.nin[tid] = 0;
-            S.nenter[tid] = 0;
-            S.wait[tid] = 0;
-        }
-        if (tid == 0) {
-            S.nlanes = nl;
-            S.nroad = nroad;
-            S.nchg = 0;
-            S.nmerge = 0;
-            S.sumv = 0ull;
-            S.cntv = 0;
-            S.changes = S.transfers = S.clamps = S.fblocks = S.finished = S.errors = 0;
-            S.sum_tt = 0ull;
-        }
-        __syncthreads();
-        // lane starts of the tile enumeration (inclusive scan across the wave)
-        {
-            int c = tid < nl ? S.cnt[tid] : 0;
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const int y = __shfl_up(c, off);
-                if (tid >= off) c += y;
-            }
-            if (tid < nl) S.start[tid + 1] = c;
-            if (tid == 0) S.start[0] = 0;
-            if (tid == kWave - 1) S.n = c;
-        }
-        __syncthreads();
-        const int n = S.n;
-        if (n == 0) {
-            if (tid < nl) {
-                LaneSum e;
-                e.cnt = 0;
-                e.rear = TS_INF;
-                e.rear_v = 0.0f;
-                e.front_reach = -TS_INF;
-                wsum[lb + tid] = e;
-                D.lane_wait[lb + tid] = 0;
-            }
-            if (tid == 0) {
-                D.road_speed[r] = -1.0f;
-                wtn[r] = 0;
-            }
-            __syncthreads();
-            continue;
-        }
-        if (n <= kTileCap) {
-            for (int j = tid; j < n; j += kWave) {
-                const int li = lane_of(S, j);
-                S.rec[j] = rd[S.base[li] + (j - S.start[li])];
-            }
-            __syncthreads();
-            LdsView view{S};
-            process_tile(D, S, view, rsum, wsum, wr, t, inst, tid);
-        } else {
-            GlobalView view{S, D, rd};
-            process_tile(D, S, view, rsum, wsum, wr, t, inst, tid);
-        }
-        __syncthreads();
-        if (tid < nl) {
-            const int m = lb + tid;
-            const int c = S.nstay[tid] + S.nin[tid] + S.nenter[tid];
-            wsum[m].cnt = c < D.lane_cap[m] ? c : D.lane_cap[m];
-            if (c == 0) {
-                wsum[m].rear = TS_INF;
-                wsum[m].rear_v = 0.0f;
-                wsum[m].front_reach = -TS_INF;
-            }
-            D.lane_wait[m] = S.wait[tid];
-        }
-        if (tid == 0) {
-            int tot = 0;
-            for (int q = 0; q < nl; ++q) tot += S.nstay[q] + S.nin[q] + S.nenter[q];
-            wtn[r] = tot;
-            D.road_speed[r] = S.cntv > 0 ? (float)((double)(long long)S.sumv / (double)kSpeedFx / (double)S.cntv) : -1.0f;
-            acc.sumv_fx += (long long)S.sumv;
-            acc.cnt += S.cntv;
-            acc.active += n;
-            acc.changes += S.changes;
-            acc.transfers += S.transfers;
-            acc.clamps += S.clamps;
-            acc.feeder_blocks += S.fblocks;
-            acc.finished += S.finished;
-            acc.sum_tt_fx += (long long)S.sum_tt;
-            acc.errors += S.errors;
-        }
-        __syncthreads();
-    }
-
-    if (D.n_inst > 1) {
-        flush();
-        acc = WGPartial{};
-    }
-    // per-workgroup partials; the last workgroup folds the step
     if (tid == 0) {
-        D.part[blockIdx.x] = acc;
+        D.part[slot] = acc;
         __threadfence();
         const unsigned int old = atomicAdd(D.done_ctr, 1u);
-        S.skip = (old == gridDim.x - 1) ? 1 : 0;
+        *skip = (old == (unsigned)total_wg - 1) ? 1 : 0;
     }
     __syncthreads();
-    if (S.skip && D.n_inst > 1) {
-        __threadfence();
+    if (!*skip) return;
+    __threadfence();
+    if (D.n_inst > 1) {
         for (int i = tid; i < D.n_inst; i += kWave) {
             volatile long long* q = (volatile long long*)&D.inst_acc[i];
             long long a[10];
@@ -1081,41 +1150,228 @@ __global__ __launch_bounds__(kWave) void k_update(const DevNet* __restrict__ Dp)
         if (tid == 0) {
             *D.gstep = tg + 1;
             *D.done_ctr = 0u;
+            *D.ovf_cnt = 0;
         }
-    } else if (S.skip) {
-        __threadfence();
-        long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int g = tid; g < (int)gridDim.x; g += kWave) {
-            const volatile long long* q = (const volatile long long*)&D.part[g];
+        return;
+    }
+    long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int g = tid; g < total_wg; g += kWave) {
+        const volatile long long* q = (const volatile long long*)&D.part[g];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) a[k] += q[k];
-        }
+        for (int k = 0; k < 10; ++k) a[k] += q[k];
+    }
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
+    for (int k = 0; k < 10; ++k) {
+        for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
+    }
+    if (tid == 0) {
+        DevMetrics* M = D.met;
+        M->vehicle_steps += a[2];
+        M->lane_changes += a[3];
+        M->transfers += a[4];
+        M->clamps += a[5];
+        M->feeder_blocks += a[6];
+        M->finished += a[7];
+        M->sum_tt_fx += a[8];
+        M->errors += a[9];
+        if (a[1] > 0) {
+            M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
+            M->speed_acc += M->mean_speed_last;
+            M->speed_steps += 1;
+        } else {
+            M->mean_speed_last = 0.0;
         }
-        if (tid == 0) {
-            DevMetrics* M = D.met;
-            M->vehicle_steps += a[2];
-            M->lane_changes += a[3];
-            M->transfers += a[4];
-            M->clamps += a[5];
-            M->feeder_blocks += a[6];
-            M->finished += a[7];
-            M->sum_tt_fx += a[8];
-            M->errors += a[9];
-            if (a[1] > 0) {
-                M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
-                M->speed_acc += M->mean_speed_last;
-                M->speed_steps += 1;
-            } else {
-                M->mean_speed_last = 0.0;
+        M->step = tg - D.inst_t0[0] + 1;
+        *D.gstep = tg + 1;
+        *D.done_ctr = 0u;
+        *D.ovf_cnt = 0;
+    }
+}
+
+// Grouped pass: tiles tile_order[0, nA) (at most GW lanes each), 64 / GW
+// tiles per wavefront, one group of GW lanes per tile.  A tile holding more
+// than CAP vehicles is left to the wide pass through the overflow list.
+template <int GW, int CAP, int CHG>
+__global__ __launch_bounds__(kWave) void k_update_grouped(const DevNet* __restrict__ Dp, int nA, int total_wg)
+{
+    constexpr int NG = kWave / GW;
+    using TS = TileLds<GW, CAP, CHG>;
+    __shared__ TS Sg[NG];
+    __shared__ WGPartial gacc[NG];
+    __shared__ int skip;
+    const DevNet& D = *Dp;
+    const long long tg = *D.gstep;
+    const StepBufs B = step_bufs(D, tg);
+    const int tid = threadIdx.x;
+    const int g = tid / GW, gt = tid % GW, gbase = g * GW;
+    TS& S = Sg[g];
+    const int GA = (int)gridDim.x;
+
+    // slot k of this workgroup's sequence -> tile position, or -1
+    int first, count, stride;
+    if (D.blocked) {
+        int chunk = (nA + GA - 1) / GA;
+        chunk = (chunk + NG - 1) / NG * NG;
+        first = (int)blockIdx.x * chunk;
+        count = min(nA - first, chunk);
+        stride = 1;
+    } else {
+        first = (int)blockIdx.x * NG;
+        count = nA - first;
+        stride = GA * NG;
+    }
+    auto pos_of = [&](int round) -> int {
+        if (D.blocked) {
+            const int k = round * NG + g;
+            return k < count ? first + k : -1;
+        }
+        const int ps = first + round * stride + g;
+        return ps < nA ? ps : -1;
+    };
+    const int rounds = count <= 0 ? 0 : (D.blocked ? (count + NG - 1) / NG : (count + stride - 1) / stride);
+
+    WGPartial acc{};
+    int acc_inst = -1;
+    int p0 = rounds > 0 ? pos_of(0) : -1;
+    Hdr nxt = load_hdr(D, B, p0 >= 0 ? D.tile_order[p0] : -1);
+    for (int round = 0; round < rounds; ++round) {
+        const Hdr h = nxt;
+        const int pn = round + 1 < rounds ? pos_of(round + 1) : -1;
+        const int rn = pn >= 0 ? D.tile_order[pn] : -1;
+        const long long t = tg - D.inst_t0[h.inst];
+        const bool live = h.r >= 0 && !(h.rt == 0 && h.wt == 0);
+        LaneRegs lr{-1, 0, 0u};
+        if (live) lr = load_lanes_a(D, B, S, h, gt);
+        if (gt == 0) reset_counters(S, h);
+        __syncthreads();
+        // lane starts of the tile enumeration (inclusive scan within the group)
+        {
+            int c = (live && gt < h.nl) ? S.cnt[gt] : 0;
+#pragma unroll
+            for (int off = 1; off < GW; off <<= 1) {
+                const int y = __shfl_up(c, off, GW);
+                if (gt >= off) c += y;
             }
-            M->step = tg - D.inst_t0[0] + 1;
-            *D.gstep = tg + 1;
-            *D.done_ctr = 0u;
+            if (live && gt < h.nl) S.start[gt + 1] = c;
+            if (gt == 0) S.start[0] = 0;
+            if (gt == GW - 1) S.n = live ? c : 0;
+        }
+        __syncthreads();
+        const int n = S.n;
+        const int ne = n <= CAP ? n : 0;
+        if (live && n == 0) empty_tile(D, B, h, gt);
+        if (n > CAP && gt == 0) D.ovf[atomicAdd(D.ovf_cnt, 1)] = h.r;
+        if (ne > 0) load_lanes_b(D, B, S, h, gt, lr);
+        for (int j = gt; j < ne; j += GW) {
+            const int li = lane_of(S, j);
+            S.vl[j] = (signed char)li;
+            S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
+        }
+        nxt = load_hdr(D, B, rn);
+        __syncthreads();
+        LdsView<TS> view{S};
+        process_tile<GW>(D, S, view, B, t, h.inst, gt, gbase, ne);
+        __syncthreads();
+        if (ne > 0) {
+            if (gt == 0 && D.n_inst > 1 && h.inst != acc_inst) {
+                flush_acc(D, acc, acc_inst);
+                acc_inst = h.inst;
+            }
+            finish_tile(D, B, S, h, gt, ne, acc);
+        }
+        __syncthreads();
+    }
+    if (D.n_inst > 1 && gt == 0) flush_acc(D, acc, acc_inst);
+    // group partials -> workgroup partial
+    if (gt == 0) gacc[g] = acc;
+    __syncthreads();
+    WGPartial tot{};
+    if (tid == 0) {
+        for (int q = 0; q < NG; ++q) {
+            long long* a = (long long*)&tot;
+            const long long* b = (const long long*)&gacc[q];
+            for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
+    finish_step(D, tg, tot, (int)blockIdx.x, total_wg, &skip);
+}
+
+// Wide pass: tiles tile_order[nA, R) and the overflow list, one tile per
+// wavefront; up to kTileCap vehicles staged in LDS, more on global scratch.
+// Part slots follow the grouped pass's (offset a_wg).
+__global__ __launch_bounds__(kWave) void k_update_wide(const DevNet* __restrict__ Dp, int nA, int a_wg, int total_wg)
+{
+    using TS = TileLds<kMaxTileLanes, kTileCap, kChangerCap>;
+    __shared__ TS S;
+    __shared__ int skip;
+    const DevNet& D = *Dp;
+    const long long tg = *D.gstep;
+    const StepBufs B = step_bufs(D, tg);
+    const int tid = threadIdx.x;
+    const int GB = (int)gridDim.x;
+    const int RS = D.R - nA;
+    const int novf = *D.ovf_cnt;
+
+    WGPartial acc{};
+    int acc_inst = -1;
+    auto run = [&](int r) {
+        const Hdr h = load_hdr(D, B, r);
+        if (h.rt == 0 && h.wt == 0) return;
+        const long long t = tg - D.inst_t0[h.inst];
+        const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
+        if (tid == 0) reset_counters(S, h);
+        __syncthreads();
+        {
+            int c = tid < h.nl ? S.cnt[tid] : 0;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int y = __shfl_up(c, off);
+                if (tid >= off) c += y;
+            }
+            if (tid < h.nl) S.start[tid + 1] = c;
+            if (tid == 0) S.start[0] = 0;
+            if (tid == kWave - 1) S.n = c;
+        }
+        __syncthreads();
+        const int n = S.n;
+        if (n == 0) {
+            empty_tile(D, B, h, tid);
+            __syncthreads();
+            return;
+        }
+        load_lanes_b(D, B, S, h, tid, lr);
+        if (n <= kTileCap) {
+            for (int j = tid; j < n; j += kWave) {
+                const int li = lane_of(S, j);
+                S.vl[j] = (signed char)li;
+                S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
+            }
+            __syncthreads();
+            LdsView<TS> view{S};
+            process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
+        } else {
+            __syncthreads();
+            GlobalView<TS> view{S, D, B.rd};
+            process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
+        }
+        __syncthreads();
+        if (tid == 0 && D.n_inst > 1 && h.inst != acc_inst) {
+            flush_acc(D, acc, acc_inst);
+            acc_inst = h.inst;
+        }
+        finish_tile(D, B, S, h, tid, n, acc);
+        __syncthreads();
+    };
+    if (D.blocked) {
+        const int chunk = (RS + GB - 1) / GB;
+        const int b = (int)blockIdx.x * chunk, e = min(RS, b + chunk);
+        for (int k = b; k < e; ++k) run(D.tile_order[nA + k]);
+    } else {
+        for (int k = (int)blockIdx.x; k < RS; k += GB) run(D.tile_order[nA + k]);
+    }
+    for (int k = (int)blockIdx.x; k < novf; k += GB) run(D.ovf[k]);
+    if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
+    finish_step(D, tg, acc, a_wg + (int)blockIdx.x, total_wg, &skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1191,7 +1447,28 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update, dim3(H.G), dim3(kWave), 0, s, Dd);
+    const int total = H.GA + H.GB;
+    if (H.GA > 0) {
+        switch (H.sched) {
+        case kSched16x32:
+            hipLaunchKernelGGL((k_update_grouped<16, 32, 16>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            break;
+        case kSched16x64:
+            hipLaunchKernelGGL((k_update_grouped<16, 64, 32>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            break;
+        case kSched32x64:
+            hipLaunchKernelGGL((k_update_grouped<32, 64, 32>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            break;
+        case kSched8x16:
+            hipLaunchKernelGGL((k_update_grouped<8, 16, 8>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_update_wide, dim3(H.GB), dim3(kWave), 0, s, Dd, H.nA, H.GA, total);
     return hipGetLastError();
 }
 

@@ -67,7 +67,10 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_set_state", "tsim_set_profiling", "tsim_get_kernel_times", "tsim_destroy", "tsim_last_error",
            "tsim_batch_footprint", "tsim_batch_create", "tsim_batch_step", "tsim_batch_set_signal_phases",
            "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
-           "tsim_set_graph_steps", "tsim_batch_set_graph_steps"]
+           "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
+           "tsim_autotune"]
+
+SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16"}
 
 
 def lib():
@@ -90,6 +93,9 @@ def lib():
         L.tsim_set_state.argtypes = [P, P]
         L.tsim_set_profiling.argtypes = [P, C.c_int32]
         L.tsim_set_graph_steps.argtypes = [P, C.c_int32]
+        L.tsim_set_schedule.argtypes = [P, C.c_int32]
+        L.tsim_get_schedule.argtypes = [P, P]
+        L.tsim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, P]
         L.tsim_batch_set_graph_steps.argtypes = [P, C.c_int32]
         L.tsim_get_kernel_times.argtypes = [P, P, P, C.c_int32]
         L.tsim_destroy.argtypes = [P]
@@ -226,6 +232,22 @@ class Sim:
         """Replay `chunk`-step HIP graphs inside step(); 0 = direct launches."""
         _check(lib().tsim_set_graph_steps(self.h, int(chunk)), self.h)
 
+    def set_schedule(self, schedule):
+        _check(lib().tsim_set_schedule(self.h, int(schedule)), self.h)
+
+    def schedule(self):
+        out = np.zeros(1, np.int32)
+        _check(lib().tsim_get_schedule(self.h, _p(out)), self.h)
+        return int(out[0])
+
+    def autotune(self, steps=10, rounds=2):
+        """Tries every schedule for `rounds` x `steps` real steps (the state
+        advances), keeps the fastest; returns (schedule, us_per_step array)."""
+        ch = np.zeros(1, np.int32)
+        us = np.zeros(len(SCHEDULES), np.float32)
+        _check(lib().tsim_autotune(self.h, int(steps), int(rounds), _p(ch), _p(us)), self.h)
+        return int(ch[0]), us
+
     def kernel_times(self):
         """{'update': (ms, launches), 'prepare': (ms, launches)} since profiling was enabled."""
         ms = np.zeros(2, np.float64)
@@ -308,6 +330,15 @@ class Batch:
     def kernel_times(self):
         """{'update': (ms, launches), 'prepare': (ms, launches)} since profiling was enabled."""
         return Sim.kernel_times(self)
+
+    def set_schedule(self, schedule):
+        Sim.set_schedule(self, schedule)
+
+    def schedule(self):
+        return Sim.schedule(self)
+
+    def autotune(self, steps=10, rounds=2):
+        return Sim.autotune(self, steps, rounds)
 
     def set_signal_phases(self, instance, junctions, phases):
         j = np.ascontiguousarray(junctions, np.int32)

@@ -230,3 +230,85 @@ def test_batch_instances_match_alone(Sim):
         assert mb["mean_speed_avg"] == ma["mean_speed_avg"]
         _log(f"batch_alone_inst{k}", {"vehicles": w.trips.n_vehicles, "active": int(ma["n_active"]),
                                       "finished": int(ma["n_finished"])})
+
+
+def _dense_big_tile_case(seed=0):
+    rng = np.random.default_rng(100 + seed)
+    net = W.grid_network(3, spacing=1500.0, length=1500.0, lanes=3)
+    o, d = W.uniform_od(net, rng, 6000)
+    trips = W._finish_trips(net, rng, o, d, rng.uniform(0, 50, 6000))
+    params = W.Params(seed=seed)
+    st = synthetic_state(net, trips, 60, seed=seed, p_active=0.95, min_gap=0.2)
+    return net, trips, params, st
+
+
+@pytest.mark.parametrize("case", ["c1", "grid3", "big"])
+def test_schedules_bit_identical(Sim, case):
+    """Every update schedule (tiles per wavefront, LDS capacity, overflow to
+    the wide pass) gives the same trajectory bit for bit."""
+    if case == "c1":
+        w = W.config1()
+        net, trips, params = w.network, w.trips, w.params
+        st = synthetic_state(net, trips, 200, seed=9, p_active=0.7)
+    elif case == "grid3":
+        rng = np.random.default_rng(5)
+        net = W.grid_network(3, spacing=250.0, jitter=20.0, rng=rng, random_edges=True)
+        o, d = W.uniform_od(net, rng, 1500)
+        trips = W._finish_trips(net, rng, o, d, rng.uniform(0, 100, 1500))
+        params = W.Params(seed=5)
+        st = synthetic_state(net, trips, 60, seed=55, p_active=0.6)
+    else:
+        net, trips, params, st = _dense_big_tile_case(1)
+    from paper_2406_10661_amd.tsim import SCHEDULES
+    ref = None
+    for sc in sorted(SCHEDULES):
+        g = Sim(net, trips, params)
+        g.set_schedule(sc)
+        assert g.schedule() == sc
+        g.set_state(st)
+        g.step(40)
+        s, m = g.get_state(), g.metrics()
+        assert m["errors"] == 0
+        if ref is None:
+            ref = (s, m)
+            continue
+        for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+            assert np.array_equal(s[key], ref[0][key]), (sc, key)
+        for key in ("vehicle_steps", "lane_changes", "transfers", "departures", "feeder_blocks", "clamps",
+                    "n_finished", "mean_speed_avg"):
+            assert m[key] == ref[1][key], (sc, key, m[key], ref[1][key])
+    _log(f"schedules_{case}", {"active": int((ref[0]["status"] == 1).sum()), "changes": int(ref[1]["lane_changes"])})
+
+
+@pytest.mark.parametrize("sched", [0, 4])
+def test_big_tiles_one_step_other_schedules(O, Sim, sched):
+    """Oracle parity of the wide-only and 8-lane schedules on tiles far above
+    every group capacity (all of them overflow to the wide pass)."""
+    net, trips, params, st = _dense_big_tile_case(0)
+
+    class S(Sim):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.set_schedule(sched)
+    rep = compare_one_step(O, S, net, trips, params, st)
+    _log(f"big_tiles_sched{sched}", rep)
+
+
+def test_autotune_steps_like_plain(Sim):
+    """The autotuner's trial steps are real steps: afterwards the state equals
+    a plain run of the same length, and the chosen schedule is reported."""
+    from paper_2406_10661_amd.tsim import SCHEDULES
+    w = W.config1()
+    a = Sim(w.network, w.trips, w.params)
+    b = Sim(w.network, w.trips, w.params)
+    a.step(100)
+    b.step(100)
+    sc, us = a.autotune(steps=5, rounds=2)
+    b.step(5 * 2 * len(SCHEDULES))
+    assert sc in SCHEDULES and a.schedule() == sc
+    assert np.all(us > 0)
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+        assert np.array_equal(sa[key], sb[key]), key
+    assert a.metrics()["vehicle_steps"] == b.metrics()["vehicle_steps"]
+    _log("autotune_c1", {"chosen": sc, "us_per_step": [float(x) for x in us]})
