@@ -314,6 +314,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--tick", type=int, default=30)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--graph-steps", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
@@ -352,7 +353,10 @@ def main():
         torch.cuda.synchronize()
         sim.set_state(init)
 
-    # timed pass
+    # timed pass (steps replayed from captured HIP graphs of graph_steps steps)
+    if args.graph_steps:
+        sim.set_graph_steps(args.graph_steps)
+        sim.step(0)                     # capture outside the timed region
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -371,6 +375,7 @@ def main():
         f"finished {m1['n_finished']}, mean speed {m1['mean_speed_avg']:.2f} m/s, errors {m1['errors']}")
 
     # kernel timing pass (events around every launch) from the same start
+    sim.set_graph_steps(0)
     sim.set_state(init)
     sim.set_profiling(True)
     m2 = sim.metrics()
@@ -402,7 +407,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "junctions": w.network.n_junctions, "roads": w.network.n_roads,
                    "lanes": w.network.n_lanes, "vehicles": w.trips.n_vehicles, "dt_s": w.params.dt,
-                   "horizon_steps": w.n_steps, "timed_from_step": 0, "schedule": SCHEDULES[sched]},
+                   "horizon_steps": w.n_steps, "timed_from_step": 0, "schedule": SCHEDULES[sched],
+                   "graph_steps": args.graph_steps},
         "result": {"finished": m1["n_finished"], "mean_road_speed": m1["mean_speed_avg"], "att_s": m1["att"],
                    "lane_changes": m1["lane_changes"], "errors": m1["errors"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

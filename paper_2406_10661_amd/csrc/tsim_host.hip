@@ -23,6 +23,7 @@ hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
 hipError_t launch_import(const DevNet* Dd, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
 hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s);
+int update_blocks_per_cu(int sched);
 }  // namespace tsim
 
 using namespace tsim;
@@ -79,13 +80,16 @@ int tile_class(const Build& B, int r)
     return nl <= 8 ? 0 : (nl <= 16 ? 1 : (nl <= 32 ? 2 : 3));
 }
 
-// grid of a schedule: tiles of the grouped pass, its workgroups, and the
-// wide pass's workgroups
+// grids of a schedule: the grouped pass strides over at most nA tiles (those
+// with few enough lanes), the wide pass over at most R; each gets no more
+// workgroups than the device keeps resident (res_a, res_b; 0 = unknown)
 struct SchedGrid {
     int gw, nA, GA, GB;
 };
 
-SchedGrid sched_grid(const Build& B, int sched)
+constexpr int kMaxGridA = 8192, kMaxGridB = 8192;
+
+SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0)
 {
     SchedGrid g{64, 0, 0, 0};
     switch (sched) {
@@ -96,8 +100,10 @@ SchedGrid sched_grid(const Build& B, int sched)
     default: g.gw = 64; g.nA = 0; break;
     }
     const int ng = 64 / g.gw;
-    g.GA = g.nA > 0 ? std::min((g.nA + ng - 1) / ng, 16384) : 0;
-    g.GB = std::max(1, std::min(8192, (B.R - g.nA) + (g.nA + 3) / 4));
+    const int capA = res_a > 0 ? std::min(res_a, kMaxGridA) : kMaxGridA;
+    const int capB = res_b > 0 ? std::min(res_b, kMaxGridB) : kMaxGridB;
+    g.GA = g.nA > 0 ? std::max(1, std::min((g.nA + ng - 1) / ng, capA)) : 0;
+    g.GB = std::max(1, std::min(B.R, capB));
     return g;
 }
 
@@ -527,6 +533,7 @@ struct tsim_handle {
     int graph_chunk = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
+    int res[kNumSched + 1] = {};        // resident update workgroups per schedule (last: wide pass)
     std::string err;
 };
 
@@ -546,6 +553,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.tile_lane_begin, (R + 1) * 4);
     add(&D.tile_n_road, R * 4);
     add(&D.tile_order, R * 4);
+    add(&D.lane_info, NL * sizeof(LaneInfo));
     add(&D.lane_len, NL * 4);
     add(&D.lane_lim, NL * 4);
     add(&D.lane_base, NL * 4);
@@ -560,6 +568,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.jl_out_road, NL * 4);
     add(&D.out_begin, (NL + 1) * 4);
     add(&D.out_jl, std::max<size_t>(NJL, 1) * 4);
+    add(&D.out_pair, std::max<size_t>(NJL, 1) * 8);
     add(&D.feed_begin, (NL + 1) * 4);
     add(&D.feed_jl, std::max<size_t>(NJL, 1) * 4);
     add(&D.junc_phase_begin, (NJ + 1) * 4);
@@ -577,6 +586,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.finish_step, std::max<size_t>(N, 1) * 4);
     add(&D.q_begin, (R + 1) * 4);
     add(&D.q_veh, std::max<size_t>(N, 1) * 4);
+    add(&D.q_tau, std::max<size_t>(N, 1) * 4);
     add(&D.q_head, R * 4);
     add(&D.slab0, S * sizeof(VehRec));
     add(&D.slab1, S * sizeof(VehRec));
@@ -587,6 +597,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.inbox, NL * sizeof(VehRec));
     add(&D.inbox_flag, NL * 4);
     add(&D.sh_gmask, S * 4);
+    add(&D.sh_jq, S * 4);
     add(&D.sh_aown, S * 4);
     add(&D.sh_merge, S * 4);
     add(&D.sh_lrear, S * 4);
@@ -598,10 +609,9 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.sh_pref, S * 4);
     add(&D.road_speed, R * 4);
     add(&D.lane_wait, NL * 4);
-    add(&D.fgate, (size_t)kGateBufs * NL * 4);
-    add(&D.fmax, (size_t)kGateBufs * NL * 4);
-    add(&D.ovf, std::max<size_t>(R, 1) * 4);
-    add(&D.ovf_cnt, 4);
+    add(&D.list_small, std::max<size_t>(R, 1) * 4);
+    add(&D.list_big, std::max<size_t>(R, 1) * 4);
+    add(&D.list_cnt, 8);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.done_ctr, 4);
     add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
@@ -716,7 +726,15 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     empty.rear = INF;
     empty.rear_v = 0.0f;
     empty.front_reach = -INF;
-    std::vector<LaneSum> sum(B.NL, empty), sum_other(B.NL, empty);
+    empty.gate = kNoGate;
+    empty.fmax = kNoFeeder;
+    empty.ob = empty.oe = 0;
+    std::vector<LaneSum> sum(B.NL, empty);
+    for (int m = 0; m < B.NL; ++m) {
+        sum[m].ob = B.out_begin[m];
+        sum[m].oe = B.out_begin[m + 1];
+    }
+    std::vector<LaneSum> sum_other(sum);
     std::vector<int32_t> tile_n(B.R, 0), tile_zero(B.R, 0);
     std::vector<float> road_speed(B.R, -1.0f);
     std::vector<int32_t> lane_wait(B.NL, 0);
@@ -751,18 +769,14 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
             recs.push_back(o);
         }
     }
-    // feeder gates of the current step from the junction-lane summaries; the
-    // other two buffers start cleared
-    std::vector<int32_t> gate((size_t)kGateBufs * B.NL, kNoGate), fmx((size_t)kGateBufs * B.NL, kNoFeeder);
-    {
-        const size_t cb = (size_t)(step % kGateBufs) * B.NL;
-        for (int q = 0; q < B.NL; ++q) {
-            const int g = B.jl_out[q];
-            if (g < 0 || sum[q].cnt == 0) continue;
-            const float fr = sum[q].front_reach;
-            fmx[cb + g] = std::max(fmx[cb + g], f2o(fr));
-            if (fr > 0.0f) gate[cb + g] = std::min(gate[cb + g], B.jl_ext[q]);
-        }
+    // feeder gates of the current step from the junction-lane summaries (the
+    // other buffer's are cleared by the prepare kernel before they are built)
+    for (int q = 0; q < B.NL; ++q) {
+        const int g = B.jl_out[q];
+        if (g < 0 || sum[q].cnt == 0) continue;
+        const float fr = sum[q].front_reach;
+        sum[g].fmax = std::max(sum[g].fmax, f2o(fr));
+        if (fr > 0.0f) sum[g].gate = std::min(sum[g].gate, B.jl_ext[q]);
     }
     std::vector<int32_t> qhead(B.R);
     for (int r = 0; r < B.R; ++r) {
@@ -806,9 +820,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.ovf_cnt, 0, 4, h->stream));
-    HIPCHK(h, up(h, D.fgate, gate));
-    HIPCHK(h, up(h, D.fmax, fmx));
+    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 8, h->stream));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
@@ -838,13 +850,12 @@ int tsim_footprint(const tsim_network* net, const tsim_trips* trips, const tsim_
 static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stream, void* device_arena,
                        size_t arena_bytes, tsim_handle** out);
 
-static void set_sched(DevNet& D, const Build& B, int sched)
+static void set_sched(tsim_handle* h, int sched)
 {
-    const SchedGrid g = sched_grid(B, sched);
-    D.sched = sched;
-    D.nA = g.nA;
-    D.GA = g.GA;
-    D.GB = g.GB;
+    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], h->res[kNumSched]);
+    h->D.sched = sched;
+    h->D.GA = g.GA;
+    h->D.GB = g.GB;
 }
 
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,
@@ -926,7 +937,14 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     D.NL = B.NL;
     D.N = B.N;
     D.G = B.G;
-    set_sched(D, B, kSched16x32);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+            for (int sc = 0; sc < kNumSched; ++sc) h->res[sc] = cus * update_blocks_per_cu(sc);
+            h->res[kNumSched] = cus * update_blocks_per_cu(-1);
+        }
+    }
+    set_sched(h, kSched16x32);
     D.n_inst = B.n_inst;
     D.blocked = B.blocked ? 1 : 0;
     fill_params(D.P, params);
@@ -936,6 +954,24 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     e = e ? e : chk(up(h, (int32_t*)D.tile_n_road, B.tile_n_road), "tiles");
     e = e ? e : chk(up(h, (int32_t*)D.tile_order, B.tile_order), "tiles");
     e = e ? e : chk(up(h, (float*)D.lane_len, B.lane_len), "lanes");
+    {
+        std::vector<LaneInfo> li(B.NL);
+        for (int m = 0; m < B.NL; ++m) {
+            LaneInfo& L = li[m];
+            L.base = B.lane_base[m];
+            L.cap = B.lane_cap[m];
+            L.len = B.lane_len[m];
+            L.lim = B.lane_lim[m];
+            L.jl_out = B.jl_out[m];
+            L.jl_out_road = B.jl_out_road[m];
+            L.jl_junc = B.jl_junc[m];
+            L.green_mask = B.jl_green_mask[m];
+            L.jl_ext = B.jl_ext[m];
+            L.jl_in_local = B.jl_in_local[m];
+            L.pad0 = L.pad1 = 0;
+        }
+        e = e ? e : chk(up(h, (LaneInfo*)D.lane_info, li), "lanes");
+    }
     e = e ? e : chk(up(h, (float*)D.lane_lim, B.lane_lim), "lanes");
     e = e ? e : chk(up(h, (uint32_t*)D.lane_base, B.lane_base), "lanes");
     e = e ? e : chk(up(h, (int32_t*)D.lane_cap, B.lane_cap), "lanes");
@@ -949,6 +985,14 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     e = e ? e : chk(up(h, (int32_t*)D.jl_out_road, B.jl_out_road), "lanes");
     e = e ? e : chk(up(h, (int32_t*)D.out_begin, B.out_begin), "conn");
     e = e ? e : chk(up(h, (int32_t*)D.out_jl, B.out_jl), "conn");
+    {
+        std::vector<int32_t> pairs(2 * B.out_jl.size());
+        for (size_t k = 0; k < B.out_jl.size(); ++k) {
+            pairs[2 * k] = B.jl_out_road[B.out_jl[k]];
+            pairs[2 * k + 1] = B.out_jl[k];
+        }
+        e = e ? e : chk(up(h, (int32_t*)D.out_pair, pairs), "conn");
+    }
     e = e ? e : chk(up(h, (int32_t*)D.feed_begin, B.feed_begin), "conn");
     e = e ? e : chk(up(h, (int32_t*)D.feed_jl, B.feed_jl), "conn");
     e = e ? e : chk(up(h, (int32_t*)D.junc_phase_begin, B.junc_phase_begin), "junctions");
@@ -961,6 +1005,11 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     e = e ? e : chk(up(h, (float*)D.vlen, B.vlen), "trips");
     e = e ? e : chk(up(h, (int32_t*)D.q_begin, B.q_begin), "queues");
     e = e ? e : chk(up(h, (int32_t*)D.q_veh, B.q_veh), "queues");
+    {
+        std::vector<float> qt(B.q_veh.size());
+        for (size_t k = 0; k < qt.size(); ++k) qt[k] = B.tau[B.q_veh[k]];
+        e = e ? e : chk(up(h, (float*)D.q_tau, qt), "queues");
+    }
     e = e ? e : chk(up(h, h->d_lane_ext, B.ext_of_int), "lanes");
     e = e ? e : chk(up(h, (int32_t*)D.tile_inst, B.tile_inst), "instances");
     e = e ? e : chk(up(h, (int32_t*)D.junc_inst, B.junc_inst), "instances");
@@ -1070,7 +1119,7 @@ int tsim_set_schedule(tsim_handle* h, int32_t schedule)
         (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
     }
-    set_sched(h->D, h->B, schedule);
+    set_sched(h, schedule);
     return TSIM_OK;
 }
 
@@ -1096,7 +1145,7 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
     const int keep = h->D.sched;
     for (int r = 0; r < rounds && rc == TSIM_OK; ++r) {
         for (int sc = 0; sc < kNumSched && rc == TSIM_OK; ++sc) {
-            set_sched(h->D, h->B, sc);
+            set_sched(h, sc);
             const size_t k = 2 * ((size_t)r * kNumSched + sc);
             hipError_t e = hipEventRecord(ev[k], h->stream);
             for (int t = 0; t < steps && e == hipSuccess; ++t) {
@@ -1130,7 +1179,7 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
         if (us_per_step)
             for (int sc = 0; sc < kNumSched; ++sc) us_per_step[sc] = best_ms[sc] * 1000.0f / (float)steps;
     }
-    set_sched(h->D, h->B, keep);
+    set_sched(h, keep);
     const int rc2 = tsim_set_schedule(h, pick);
     if (chosen) *chosen = h->D.sched;
     return rc ? rc : rc2;

@@ -24,15 +24,14 @@ constexpr int kMaxPhases = 32;
 constexpr int kWave = 64;
 constexpr int kChangerCap = 64;      // lane changers per tile kept in LDS (wide tiles)
 constexpr int kMergeCap = 64;        // merging vehicles per tile kept in LDS (wide tiles)
-constexpr int kTileCap = 128;        // vehicles of a wide tile staged in LDS
-constexpr int kGateBufs = 3;         // feeder gate buffers: read t%3, write (t+1)%3, clear (t+2)%3
+constexpr int kWideCap = 256;        // vehicles of a wide tile staged in LDS
 constexpr int kNoGate = 0x7FFFFFFF;  // no feeder holds the lane
 constexpr int kNoFeeder = (int)0x80000000;  // no nonempty feeder
 
 // Update schedules: how road tiles map onto wavefronts.  A tile of at most
-// `lanes` lanes goes to a group of `width` lanes of a wavefront (64 / width
-// tiles per wavefront) when it holds at most `cap` vehicles; larger tiles run
-// one per wavefront in the wide pass.
+// `width` lanes that holds at most `cap` vehicles goes to a group of `width`
+// lanes of a wavefront (64 / width tiles per wavefront); other tiles run one
+// per wavefront in the wide pass.
 enum Schedule { kSchedWide = 0, kSched16x32 = 1, kSched16x64 = 2, kSched32x64 = 3, kSched8x16 = 4, kNumSched = 5 };
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
@@ -50,12 +49,37 @@ struct __align__(16) VehRec {
 };
 
 // per-lane summary of one step's state, read by other tiles (lookahead,
-// merge priority, departure safety) so that they need a single load
-struct __align__(16) LaneSum {
+// merge priority, departure safety) so that one 32-byte load serves them
+struct __align__(32) LaneSum {
     int32_t cnt;        // vehicles in the lane
     float rear;         // rearmost vehicle's rear bumper (x - length)
     float rear_v;       // its speed
     float front_reach;  // front vehicle's x + v dt + a_max dt^2/2 - lane length
+    // feeder gates of a road lane (built by the tiles that write its feeders'
+    // front vehicles): smallest external index of a nonempty feeder whose
+    // front vehicle can cross the lane end within the step (kNoGate if none),
+    // and the largest front reach of a nonempty feeder (order-preserving int,
+    // kNoFeeder if none)
+    int32_t gate;
+    int32_t fmax;
+    // static: junction lanes leaving this lane, out_pair[ob, oe)
+    int32_t ob, oe;
+};
+
+// static per-lane tables, one 48-byte record per lane so that a tile's lanes
+// load as one contiguous run
+struct __align__(16) LaneInfo {
+    uint32_t base;        // first slab slot
+    int32_t cap;          // slab capacity
+    float len;
+    float lim;
+    int32_t jl_out;       // junction lanes: out lane (internal), else -1
+    int32_t jl_out_road;  // its road
+    int32_t jl_junc;      // junction
+    uint32_t green_mask;  // phases in which it is green
+    int32_t jl_ext;       // external junction-lane index (feeder priority)
+    int32_t jl_in_local;  // local index of its in lane within the tile
+    int32_t pad0, pad1;
 };
 
 // order-preserving map of floats to ints (for atomicMax on floats)
@@ -123,6 +147,7 @@ struct DevNet {
     const int32_t* tile_n_road;      // [R]
     const int32_t* tile_order;       // [R]
     // lanes (internal ids)
+    const LaneInfo* lane_info;       // [NL]
     const float* lane_len;
     const float* lane_lim;
     const uint32_t* lane_base;
@@ -138,6 +163,7 @@ struct DevNet {
     const int32_t* jl_out_road;      // road of its out lane
     const int32_t* out_begin;        // [NL+1] junction lanes leaving a road lane
     const int32_t* out_jl;
+    const int2* out_pair;            // per out_jl entry: (road of its out lane, junction lane)
     const int32_t* feed_begin;       // [NL+1] junction lanes entering a road lane, by external id
     const int32_t* feed_jl;
     // junctions
@@ -157,6 +183,7 @@ struct DevNet {
     int32_t* finish_step;
     const int32_t* q_begin;          // [R+1] departure queue of each origin road
     const int32_t* q_veh;
+    const float* q_tau;              // departure time of each queue entry
     int32_t* q_head;
     // slabs
     VehRec* slab0;
@@ -169,6 +196,7 @@ struct DevNet {
     int32_t* inbox_flag;             // [NL]
     // per-slot scratch of the update kernel (indexed like the read slab)
     uint32_t* sh_gmask;
+    int32_t* sh_jq;                  // packed junction lanes of the route
     float* sh_aown;
     int32_t* sh_merge;               // local index of the merge target lane, -1 none
     float* sh_lrear;                 // own leader's rear (lane coordinate), +inf none
@@ -178,17 +206,13 @@ struct DevNet {
     int32_t* sh_kind;                // 0 stay, 1 change, 2 enter junction lane, 3 leave tile, 4 finished
     int32_t* sh_nlane;               // local index of the new lane
     int32_t* sh_pref;                // stayer prefix count within the tile enumeration
-    // feeder gates of each lane (indexed by internal lane id), three buffers
-    // by step: min external index among nonempty feeders whose front vehicle
-    // can pass the lane end within a step (kNoGate if none), and the max front
-    // reach of nonempty feeders as an order-preserving int (kNoFeeder if none)
-    int32_t* fgate;                  // [3 NL]
-    int32_t* fmax;                   // [3 NL]
-    // small-class tiles too full for their group, run by the wide pass
-    int32_t* ovf;                    // [R]
-    int32_t* ovf_cnt;
+    // work lists of the step's update, filled by the prepare kernel: tiles
+    // with vehicles that fit a group of the schedule, and all others
+    int32_t* list_small;             // [R]
+    int32_t* list_big;               // [R]
+    int32_t* list_cnt;               // [2]
     // schedule (host side; passed to the kernels as arguments)
-    int32_t sched, nA, GA, GB;
+    int32_t sched, GA, GB;
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)

@@ -1,20 +1,24 @@
 // Device kernels of the gfx950 microscopic traffic stepper.
 //
 // One simulation step (Section 3.1 two-phase process, Appendix B.2):
-//   k_prepare  one thread per junction: phase of the step (Section 3.2
-//              FIXED_TIME / MANUAL / NONE); one thread per road: append the
-//              junction-to-road entrant held in each road lane's inbox, then
-//              release due departures into the origin road's lanes when safe.
-//   k_update   one wavefront per road tile, grid-stride over tiles.  A tile of
-//              up to kTileCap vehicles is staged in LDS (records and per-vehicle
-//              scratch); larger tiles run the same code on global scratch.
-//              Pass 1: own leader (or two-lane lookahead), lane group, stop
-//              obstacle, own IDM acceleration, merge target.  Pass 2: randomized
-//              MOBIL (Appendix B.3), Philox draw, ballistic integration with
-//              snapshot bounds, lane-end transfer.  Pass 3: new per-lane order
-//              (stayers keep theirs, changers merge by position) written to the
-//              other slab buffer with the lane summaries other tiles read next
-//              step.  The last workgroup folds the step's metrics.
+//   k_prepare         one thread per junction: phase of the step (Section 3.2
+//                     FIXED_TIME / MANUAL / NONE); one thread per road: append
+//                     the junction-to-road entrant held in each road lane's
+//                     inbox, release due departures into the origin road's
+//                     lanes when safe, clear the feeder gates the step builds,
+//                     and put the road's tile on the step's small or wide work
+//                     list (or finish it if it has just become empty).
+//   k_update_grouped  the small list: 64 / W tiles per wavefront, a group of W
+//                     lanes per tile, tile staged in LDS.
+//   k_update_wide     the wide list: one tile per wavefront, up to kWideCap
+//                     vehicles in LDS, larger tiles on global scratch; the last
+//                     workgroup folds the step's metrics.
+// Per tile: pass 1 own leader (or two-lane lookahead), lane group, stop
+// obstacle, own IDM acceleration, merge target; pass 2 randomized MOBIL
+// (Appendix B.3), Philox draw, ballistic integration with snapshot bounds,
+// lane-end transfer; pass 3 new per-lane order (stayers keep theirs, changers
+// and entrants merge by position) written to the other slab buffer with the
+// lane summaries and feeder gates other tiles read next step.
 // Reads of the step come only from slab buffer t&1 and its lane summaries;
 // writes go to buffer (t+1)&1, the inboxes and per-vehicle status, so the update
 // is free of read/write races without any lock.
@@ -23,6 +27,17 @@
 namespace tsim {
 
 #define TS_INF __builtin_huge_valf()
+
+// Every update workgroup is a single wavefront: LDS written by one lane is
+// visible to the others once the wave has passed this point in program order
+// (LDS requests of a wave complete in order), so no workgroup barrier and no
+// wait for outstanding global stores is needed between passes.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 struct Lead {
     float rear;  // rear bumper in the follower's lane coordinate
@@ -94,14 +109,18 @@ __device__ __forceinline__ bool jl_green(const DevNet& D, int g)
 }
 
 // junction lane leaving road lane m toward road nr (global tables), or -1
-__device__ __forceinline__ int out_toward(const DevNet& D, int m, int nr)
+__device__ __forceinline__ int out_toward_range(const DevNet& D, int b, int e, int nr)
 {
-    if (nr < 0) return -1;
-    for (int e = D.out_begin[m]; e < D.out_begin[m + 1]; ++e) {
-        const int g = D.out_jl[e];
-        if (D.jl_out_road[g] == nr) return g;
+    for (; e > b && nr >= 0; ++b) {
+        const int2 pr = D.out_pair[b];
+        if (pr.x == nr) return pr.y;
     }
     return -1;
+}
+
+__device__ __forceinline__ int out_toward(const DevNet& D, int m, int nr)
+{
+    return out_toward_range(D, D.out_begin[m], D.out_begin[m + 1], nr);
 }
 
 __device__ __forceinline__ float front_reach(float x, float v, float len, const KParams& P)
@@ -109,10 +128,34 @@ __device__ __forceinline__ float front_reach(float x, float v, float len, const 
     return x + v * P.dt + P.reach - len;
 }
 
+// writes the per-step part of a lane summary (count, rear, front reach),
+// leaving the feeder gates and the static connection range alone
+__device__ __forceinline__ void put_dyn(LaneSum& d, const LaneSum& s)
+{
+    d.cnt = s.cnt;
+    d.rear = s.rear;
+    d.rear_v = s.rear_v;
+    d.front_reach = s.front_reach;
+}
+
+// appends val to list for every lane of the wave with pred set, one atomic per
+// wavefront (call from converged code)
+__device__ __forceinline__ void append_wave(int32_t* list, int32_t* cnt, bool pred, int val)
+{
+    const unsigned long long m = __ballot(pred);
+    if (!m) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
 // ---------------------------------------------------------------------------
 // prepare
 // ---------------------------------------------------------------------------
-__global__ void k_prepare(const DevNet* __restrict__ Dp)
+__global__ void k_prepare(const DevNet* __restrict__ Dp, int small_lanes, int small_cap)
 {
     const DevNet& D = *Dp;
     const long long tg = *D.gstep;
@@ -120,6 +163,8 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
     VehRec* slab = p ? D.slab1 : D.slab0;
     LaneSum* sum = p ? D.sum1 : D.sum0;
     int32_t* tile_n = p ? D.tile_n1 : D.tile_n0;
+    int32_t* tile_n_w = p ? D.tile_n0 : D.tile_n1;
+    LaneSum* wsum = p ? D.sum0 : D.sum1;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const KParams& P = D.P;
 
@@ -153,15 +198,11 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
     const long long t = tg - D.inst_t0[inst];
     const int lb = D.tile_lane_begin[r];
     const int nrl = D.tile_n_road[r];
-    const int32_t* fmax_r = D.fmax + (size_t)(tg % kGateBufs) * D.NL;
-    {
-        // feeder gates of this road's lanes: clear the buffer that the step
-        // after this one fills (nothing reads or writes it during this step)
-        const size_t cb = (size_t)((tg + 2) % kGateBufs) * D.NL;
-        for (int li = 0; li < nrl; ++li) {
-            D.fgate[cb + lb + li] = kNoGate;
-            D.fmax[cb + lb + li] = kNoFeeder;
-        }
+    // feeder gates of this road's lanes in the summaries this step writes
+    // (the update kernels fill them)
+    for (int li = 0; li < nrl; ++li) {
+        wsum[lb + li].gate = kNoGate;
+        wsum[lb + li].fmax = kNoFeeder;
     }
     long long errors = 0;
     int appended = 0;
@@ -176,7 +217,7 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
                 s.cnt += 1;
                 s.rear = z.x - z.len;
                 s.rear_v = z.v;
-                sum[m] = s;
+                put_dyn(sum[m], s);
                 appended++;
             } else {
                 errors++;
@@ -191,12 +232,14 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
     unsigned used = 0u;
     int departed = 0;
     while (head < qe) {
+        // departure times ascend along the queue: the first future one ends
+        // the scan (entries already departed are skipped once they are due)
+        if (!((double)D.q_tau[head] <= now)) break;
         const int v = D.q_veh[head];
         if (D.status[v] != 0) {
             head++;
             continue;
         }
-        if (!((double)D.tau[v] <= now)) break;
         const int rb = D.route_begin[v];
         const int rl = D.route_begin[v + 1] - rb;
         const int nr = rl > 1 ? D.route[rb + 1] : -1;
@@ -208,9 +251,8 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
             const int m = lb + li;
             if (nr >= 0 && out_toward(D, m, nr) < 0) continue;
             // no nonempty feeder may reach past the entrant's rear (x = 0)
-            const int fm = fmax_r[m];
-            if (fm != kNoFeeder && !(-Lv - o2f(fm) >= 0.0f)) continue;
             const LaneSum s = sum[m];
+            if (s.fmax != kNoFeeder && !(-Lv - o2f(s.fmax) >= 0.0f)) continue;
             const float room = s.cnt > 0 ? s.rear : TS_INF;
             if (room > best_room) {
                 best_room = room;
@@ -238,14 +280,34 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp)
         s.cnt += 1;
         s.rear = 0.0f - Lv;
         s.rear_v = 0.0f;
-        sum[m] = s;
+        put_dyn(sum[m], s);
         D.status[v] = 1;
         used |= 1u << best;
         departed++;
         head++;
     }
     D.q_head[r] = head;
-    if (appended + departed) tile_n[r] += appended + departed;
+    const int n = tile_n[r] + appended + departed;
+    if (appended + departed) tile_n[r] = n;
+    // the update kernels' work lists: tiles with vehicles, by size; a tile
+    // emptied since the last step gets its empty summaries here
+    const int nl = D.tile_lane_begin[r + 1] - lb;
+    const bool small = n > 0 && nl <= small_lanes && n <= small_cap;
+    append_wave(D.list_small, &D.list_cnt[0], small, r);
+    append_wave(D.list_big, &D.list_cnt[1], n > 0 && !small, r);
+    if (n == 0 && tile_n_w[r] != 0) {
+        LaneSum e;
+        e.cnt = 0;
+        e.rear = TS_INF;
+        e.rear_v = 0.0f;
+        e.front_reach = -TS_INF;
+        for (int li = 0; li < nl; ++li) {
+            put_dyn(wsum[lb + li], e);
+            D.lane_wait[lb + li] = 0;
+        }
+        D.road_speed[r] = -1.0f;
+        tile_n_w[r] = 0;
+    }
     if (departed) {
         atomicAdd((unsigned long long*)&D.met[inst].departed, (unsigned long long)departed);
         atomicAdd((unsigned long long*)&D.met[inst].dep_events, (unsigned long long)departed);
@@ -281,8 +343,7 @@ struct TileLds {
     int jl_ext[LANES];
     int green[LANES];
     int fmx[LANES];        // road lanes: feeder max front reach (ordered int)
-    int gate[LANES];       // junction lanes: feeder gate of the out lane
-    LaneSum osum[LANES];   // junction lanes: summary of the out lane
+    LaneSum osum[LANES];   // junction lanes: summary of the out lane (with its gate and connections)
     int nstay[LANES];
     int nin[LANES];
     int nenter[LANES];
@@ -307,6 +368,7 @@ struct TileLds {
     float nx[CAP];
     float nv[CAP];
     uint32_t gmask[CAP];
+    int jq[CAP];           // packed junction lanes of the route (jq_pack)
     int pref[CAP];
     signed char merge[CAP];
     signed char kind[CAP];
@@ -333,15 +395,18 @@ struct LdsView {
     __device__ float nx(int j) const { return S.nx[j]; }
     __device__ float nv(int j) const { return S.nv[j]; }
     __device__ uint32_t gmask(int j) const { return S.gmask[j]; }
-    __device__ int merge(int j) const { return S.merge[j]; }
+    __device__ int merge(int j) const { return (S.merge[j] & 63) - 1; }
+    __device__ bool stopf(int j) const { return (S.merge[j] >> 6) & 1; }
     __device__ int kind(int j) const { return S.kind[j]; }
     __device__ int nlane(int j) const { return S.nlane[j]; }
     __device__ int pref(int j) const { return S.pref[j]; }
-    __device__ void set1(int j, uint32_t g, float a, int mt, float lr, float lvv)
+    __device__ int jq(int j) const { return S.jq[j]; }
+    __device__ void set1(int j, uint32_t g, float a, int mt, float lr, float lvv, bool stop, int jq)
     {
         S.gmask[j] = g;
+        S.jq[j] = jq;
         S.aown[j] = a;
-        S.merge[j] = (signed char)mt;
+        S.merge[j] = (signed char)((mt + 1) | (stop ? 64 : 0));
         S.lrear[j] = lr;
         S.lv[j] = lvv;
     }
@@ -355,7 +420,7 @@ struct LdsView {
     __device__ void set_pref(int j, int v) { S.pref[j] = v; }
 };
 
-// the same storage in global per-slot scratch, for wide tiles above kTileCap
+// the same storage in global per-slot scratch, for wide tiles above kWideCap
 template <class TS>
 struct GlobalView {
     TS& S;
@@ -374,16 +439,19 @@ struct GlobalView {
     __device__ float nx(int j) const { return D.sh_nx[slot(j)]; }
     __device__ float nv(int j) const { return D.sh_nv[slot(j)]; }
     __device__ uint32_t gmask(int j) const { return D.sh_gmask[slot(j)]; }
-    __device__ int merge(int j) const { return D.sh_merge[slot(j)]; }
+    __device__ int merge(int j) const { return (D.sh_merge[slot(j)] & 63) - 1; }
+    __device__ bool stopf(int j) const { return (D.sh_merge[slot(j)] >> 6) & 1; }
     __device__ int kind(int j) const { return D.sh_kind[slot(j)]; }
     __device__ int nlane(int j) const { return D.sh_nlane[slot(j)]; }
     __device__ int pref(int j) const { return D.sh_pref[slot(j)]; }
-    __device__ void set1(int j, uint32_t g, float a, int mt, float lr, float lvv)
+    __device__ int jq(int j) const { return D.sh_jq[slot(j)]; }
+    __device__ void set1(int j, uint32_t g, float a, int mt, float lr, float lvv, bool stop, int jq)
     {
         const uint32_t s = slot(j);
         D.sh_gmask[s] = g;
+        D.sh_jq[s] = jq;
         D.sh_aown[s] = a;
-        D.sh_merge[s] = mt;
+        D.sh_merge[s] = (mt + 1) | (stop ? 64 : 0);
         D.sh_lrear[s] = lr;
         D.sh_lv[s] = lvv;
     }
@@ -410,21 +478,24 @@ __device__ __forceinline__ int group_dist(uint32_t gmask, int li, int nroad)
     return best;
 }
 
-// tile junction lane (local index) leaving local road lane li toward road nr
-template <class TS>
-__device__ __forceinline__ int tile_jl(const TS& S, int li, int nr)
+// junction lanes (local indices) toward a vehicle's next road from the lane
+// left of its own (d = -1), its own (0) and the one right of it (+1), packed
+// one byte each (-1 = none)
+__device__ __forceinline__ int jq_pack(int qm, int q0, int qp)
 {
-    if (nr < 0) return -1;
-    for (int q = S.nroad; q < S.nlanes; ++q)
-        if (S.jl_in_local[q] == li && S.jl_out_road[q] == nr) return q;
-    return -1;
+    return (qm + 1) | ((q0 + 1) << 8) | ((qp + 1) << 16);
+}
+__device__ __forceinline__ int jq_get(int pk, int d)
+{
+    return ((pk >> (8 * (d + 1))) & 255) - 1;
 }
 
+// stop obstacle at the end of tile lane li for a vehicle whose next road is
+// nr, reaching it through junction lane q (-1: the lane does not lead there)
 template <class TS>
-__device__ __forceinline__ bool tile_stop(const TS& S, int li, int nr, bool with_wrong)
+__device__ __forceinline__ bool stop_at(const TS& S, int li, int nr, int q, bool with_wrong)
 {
     if (li >= S.nroad || nr < 0) return false;
-    const int q = tile_jl(S, li, nr);
     if (q < 0) return with_wrong;
     return !S.green[q];
 }
@@ -446,14 +517,14 @@ __device__ __forceinline__ int count_ahead(const TS& S, const V& view, int li, f
 
 // leader substitution for a vehicle at the front of tile lane li (route info
 // nr, rp, rem): rearmost vehicle of the next lane, else of the lane after it
+// (q: the junction lane toward the vehicle's next road when li is a road lane)
 template <class TS, class V>
-__device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const LaneSum* sum, int li, int nr, int rp,
+__device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const LaneSum* sum, int li, int q, int rp,
                           int rem)
 {
     Lead L{TS_INF, 0.0f, false};
     const float off = S.len[li];
     if (li < S.nroad) {
-        const int q = tile_jl(S, li, nr);
         if (q < 0) return L;
         if (S.cnt[q] > 0) {
             const VehRec z = view.rec(S.start[q] + S.cnt[q] - 1);
@@ -479,7 +550,7 @@ __device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const Lan
     }
     if (rem < 2) return L;
     const int g1 = S.jl_out[li];
-    const int g2 = out_toward(D, g1, D.route[rp + 2]);
+    const int g2 = out_toward_range(D, s1.ob, s1.oe, D.route[rp + 2]);
     if (g2 < 0) return L;
     const LaneSum s2 = sum[g2];
     if (s2.cnt > 0) {
@@ -498,10 +569,6 @@ struct StepBufs {
     LaneSum* wsum;
     const int32_t* rtn;
     int32_t* wtn;
-    const int32_t* gate_r;
-    int32_t* gate_w;
-    const int32_t* fmax_r;
-    int32_t* fmax_w;
 };
 
 __device__ __forceinline__ StepBufs step_bufs(const DevNet& D, long long tg)
@@ -514,11 +581,6 @@ __device__ __forceinline__ StepBufs step_bufs(const DevNet& D, long long tg)
     B.wsum = p ? D.sum0 : D.sum1;
     B.rtn = p ? D.tile_n1 : D.tile_n0;
     B.wtn = p ? D.tile_n0 : D.tile_n1;
-    const int rb = (int)(tg % kGateBufs), wb = (int)((tg + 1) % kGateBufs);
-    B.gate_r = D.fgate + (size_t)rb * D.NL;
-    B.gate_w = D.fgate + (size_t)wb * D.NL;
-    B.fmax_r = D.fmax + (size_t)rb * D.NL;
-    B.fmax_w = D.fmax + (size_t)wb * D.NL;
     return B;
 }
 
@@ -560,33 +622,29 @@ __device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs
     if (gt >= h.nl) return lr;
     const int m = h.lb + gt;
     const bool jl = gt >= h.nroad;
+    const LaneInfo L = D.lane_info[m];
     S.lane[gt] = m;
     S.cnt[gt] = B.rsum[m].cnt;
-    S.base[gt] = D.lane_base[m];
-    S.cap[gt] = D.lane_cap[m];
-    S.len[gt] = D.lane_len[m];
-    S.lim[gt] = D.lane_lim[m];
+    S.base[gt] = L.base;
+    S.cap[gt] = L.cap;
+    S.len[gt] = L.len;
+    S.lim[gt] = L.lim;
     S.nstay[gt] = 0;
     S.nin[gt] = 0;
     S.nenter[gt] = 0;
     S.wait[gt] = 0;
+    S.jl_out[gt] = L.jl_out;
+    S.jl_out_road[gt] = L.jl_out_road;
+    S.jl_in_local[gt] = L.jl_in_local;
+    S.jl_ext[gt] = L.jl_ext;
     if (jl) {
-        lr.g = D.jl_out[m];
-        lr.junc = D.jl_junc[m];
-        lr.mask = D.jl_green_mask[m];
-        S.jl_out[gt] = lr.g;
-        S.jl_out_road[gt] = D.jl_out_road[m];
-        S.jl_in_local[gt] = D.jl_in_local[m];
-        S.jl_ext[gt] = D.jl_ext[m];
+        lr.g = L.jl_out;
+        lr.junc = L.jl_junc;
+        lr.mask = L.green_mask;
         S.fmx[gt] = kNoFeeder;
     } else {
-        S.jl_out[gt] = -1;
-        S.jl_out_road[gt] = -1;
-        S.jl_in_local[gt] = -1;
-        S.jl_ext[gt] = -1;
-        S.fmx[gt] = B.fmax_r[m];
+        S.fmx[gt] = B.rsum[m].fmax;
         S.green[gt] = 1;
-        S.gate[gt] = kNoGate;
     }
     return lr;
 }
@@ -599,7 +657,6 @@ __device__ __forceinline__ void load_lanes_b(const DevNet& D, const StepBufs& B,
     const int cur = D.junc_cur[lr.junc];
     S.green[gt] = (cur < 0 || ((lr.mask >> cur) & 1u)) ? 1 : 0;
     S.osum[gt] = B.rsum[lr.g];
-    S.gate[gt] = B.gate_r[lr.g];
 }
 
 template <class TS>
@@ -636,14 +693,22 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
         const VehRec rec = view.rec(j);
         const bool is_jl = li >= nroad;
         uint32_t gmask = 0u;
+        int qm = -1, q0 = -1, qp = -1;
         if (!is_jl) {
             if (rec.nr < 0) {
                 gmask = nroad >= 32 ? 0xFFFFFFFFu : ((1u << nroad) - 1u);
             } else {
                 for (int q = nroad; q < nl; ++q)
-                    if (S.jl_out_road[q] == rec.nr) gmask |= 1u << S.jl_in_local[q];
+                    if (S.jl_out_road[q] == rec.nr) {
+                        const int in = S.jl_in_local[q];
+                        gmask |= 1u << in;
+                        if (in == li - 1) qm = q;
+                        else if (in == li) q0 = q;
+                        else if (in == li + 1) qp = q;
+                    }
             }
         }
+        const int jqp = jq_pack(qm, q0, qp);
         Lead ld;
         if (c > 0) {
             const VehRec z = view.rec(j - 1);
@@ -651,9 +716,9 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
             ld.rear = z.x - z.len;
             ld.v = z.v;
         } else {
-            ld = lookahead(D, S, view, rsum, li, rec.nr, rec.rp, rec.rem);
+            ld = lookahead(D, S, view, rsum, li, q0, rec.rp, rec.rem);
         }
-        const bool stop = tile_stop(S, li, rec.nr, true);
+        const bool stop = stop_at(S, li, rec.nr, q0, true);
         const float a = accel(rec.v, rec.f * S.lim[li], rec.x, ld, stop, S.len[li], P);
         int mt = -1;
         if (!is_jl && rec.nr >= 0 && !((gmask >> li) & 1u)) {
@@ -668,7 +733,7 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
                 }
             if (bl >= 0) mt = bl < li ? li - 1 : li + 1;
         }
-        view.set1(j, gmask, a, mt, ld.ex ? ld.rear : TS_INF, ld.v);
+        view.set1(j, gmask, a, mt, ld.ex ? ld.rear : TS_INF, ld.v, stop, jqp);
         if (mt >= 0) {
             const int k = atomicAdd(&S.nmerge, 1);
             if (k < TS::kChg) {
@@ -679,7 +744,7 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
             }
         }
     }
-    __syncthreads();
+    wave_sync();
 
     // ---------------- pass 2: decision and motion ----------------
     for (int j = gt; j < n; j += GW) {
@@ -692,9 +757,14 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
         const float v0 = rec.f * lim;
         const float a_e = view.aown(j);
         const uint32_t gmask = view.gmask(j);
+        const int jqp = view.jq(j);
         const int my_mt = view.merge(j);
         const bool in_g = !is_jl && ((gmask >> li) & 1u);
         const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
+        // acceleration change of the old follower when this vehicle leaves
+        // (the same for both directions; computed on first use)
+        bool have_old = false;
+        float d_old_c = 0.0f;
         // MOBIL for one direction: utility (or -inf), prospective
         // acceleration, and the target-lane leader used as a bound
         auto eval_dir = [&](int d) -> DirEval {
@@ -730,7 +800,7 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
                 tld.rear = tlr.x - tlr.len;
                 tld.v = tlr.v;
             } else {
-                tld = lookahead(D, S, view, rsum, k, rec.nr, rec.rp, rec.rem);
+                tld = lookahead(D, S, view, rsum, k, jq_get(jqp, d), rec.rp, rec.rem);
             }
             const float g3 = tld.ex ? tld.rear - rec.x : TS_INF;
             if (!(g3 > 0.0f)) return o;
@@ -748,29 +818,33 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
                     if (!(g >= 0.0f)) return o;
                 }
             }
-            const float ta_e = accel(rec.v, v0, rec.x, tld, tile_stop(S, k, rec.nr, false), len, P);
+            const float ta_e = accel(rec.v, v0, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false), len, P);
             float d_new = 0.0f, d_old = 0.0f;
             if (tf >= 0) {
                 const float a_tf = view.aown(tf);
                 const Lead me_lead{rec.x - rec.len, rec.v, true};
-                const float ta_tf = accel(tfr.v, tfr.f * lim, tfr.x, me_lead, tile_stop(S, k, tfr.nr, true), len, P);
+                const float ta_tf = accel(tfr.v, tfr.f * lim, tfr.x, me_lead, view.stopf(tf), len, P);
                 if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
                 d_new = ta_tf - a_tf;
             }
             if (c + 1 < S.cnt[li]) {
-                const VehRec ofr = view.rec(j + 1);
-                const float a_of = view.aown(j + 1);
-                Lead ol;
-                if (c > 0) {
-                    const VehRec z = view.rec(j - 1);
-                    ol.ex = true;
-                    ol.rear = z.x - z.len;
-                    ol.v = z.v;
-                } else {
-                    ol = lookahead(D, S, view, rsum, li, ofr.nr, ofr.rp, ofr.rem);
+                if (!have_old) {
+                    const VehRec ofr = view.rec(j + 1);
+                    const float a_of = view.aown(j + 1);
+                    Lead ol;
+                    if (c > 0) {
+                        const VehRec z = view.rec(j - 1);
+                        ol.ex = true;
+                        ol.rear = z.x - z.len;
+                        ol.v = z.v;
+                    } else {
+                        ol = lookahead(D, S, view, rsum, li, jq_get(view.jq(j + 1), 0), ofr.rp, ofr.rem);
+                    }
+                    const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, view.stopf(j + 1), len, P);
+                    d_old_c = ta_of - a_of;
+                    have_old = true;
                 }
-                const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, tile_stop(S, li, ofr.nr, true), len, P);
-                d_old = ta_of - a_of;
+                d_old = d_old_c;
             }
             const float da = (ta_e - a_e) + P.p * (d_new + d_old);
             float ud = da - P.a_th;
@@ -885,7 +959,8 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
                 vcap = fminf(vcap, y_v);
             }
         }
-        if (tile_stop(S, nli, rec.nr, true)) {
+        const int qn = jq_get(jqp, nli - li);   // junction lane from the lane it ends the step in
+        if (stop_at(S, nli, rec.nr, qn, true)) {
             if (len < Bd) {
                 Bd = len;
                 vcap = 0.0f;
@@ -910,14 +985,14 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
                 atomicAdd(&S.finished, 1);
             } else if (!is_jl) {
                 kind = 2;
-                tgt_local = tile_jl(S, nli, rec.nr);
+                tgt_local = qn;
                 xn -= len;
                 atomicAdd(&S.transfers, 1);
             } else {
                 // feeder priority: an earlier feeder of the out lane whose
                 // front vehicle can pass its end this step goes first
                 const int g = S.jl_out[li];
-                if (S.gate[li] < S.jl_ext[li]) {
+                if (S.osum[li].gate < S.jl_ext[li]) {
                     xn = len;
                     vn = 0.0f;
                     atomicAdd(&S.fblocks, 1);
@@ -960,7 +1035,7 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
             if (atomicAdd(&S.nenter[tgt_local], 1) != 0) atomicAdd(&S.errors, 1);
         }
     }
-    __syncthreads();
+    wave_sync();
 
     // ---------------- pass 3: new order ----------------
     {
@@ -976,7 +1051,7 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
             carry += __popcll(mine);
         }
     }
-    __syncthreads();
+    wave_sync();
     const int nchg = S.nchg;
     for (int j = gt; j < n; j += GW) {
         const int kind = view.kind(j);
@@ -1029,8 +1104,8 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
                 if (nli >= nroad) {
                     // this junction lane feeds its out lane next step
                     const int g = S.jl_out[nli];
-                    atomicMax(&B.fmax_w[g], f2o(fr));
-                    if (fr > 0.0f) atomicMin(&B.gate_w[g], S.jl_ext[nli]);
+                    atomicMax(&B.wsum[g].fmax, f2o(fr));
+                    if (fr > 0.0f) atomicMin(&B.wsum[g].gate, S.jl_ext[nli]);
                 }
             }
             if (rank == total - 1) {
@@ -1077,24 +1152,6 @@ __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, 
     }
 }
 
-// a tile with no vehicle now that had some at the previous step
-__device__ __forceinline__ void empty_tile(const DevNet& D, const StepBufs& B, const Hdr& h, int gt)
-{
-    if (gt < h.nl) {
-        LaneSum e;
-        e.cnt = 0;
-        e.rear = TS_INF;
-        e.rear_v = 0.0f;
-        e.front_reach = -TS_INF;
-        B.wsum[h.lb + gt] = e;
-        D.lane_wait[h.lb + gt] = 0;
-    }
-    if (gt == 0) {
-        D.road_speed[h.r] = -1.0f;
-        B.wtn[h.r] = 0;
-    }
-}
-
 __device__ __forceinline__ void flush_acc(const DevNet& D, WGPartial& acc, int inst)
 {
     if (inst < 0) return;
@@ -1106,7 +1163,8 @@ __device__ __forceinline__ void flush_acc(const DevNet& D, WGPartial& acc, int i
 }
 
 // per-workgroup partials; the workgroup that finishes last folds the step
-// (called by every lane of the workgroup; acc valid in lane 0)
+// with its first wavefront (called by every thread of the workgroup; acc
+// valid in thread 0)
 __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc, int slot, int total_wg, int* skip)
 {
     const int tid = threadIdx.x;
@@ -1117,7 +1175,7 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
         *skip = (old == (unsigned)total_wg - 1) ? 1 : 0;
     }
     __syncthreads();
-    if (!*skip) return;
+    if (!*skip || tid >= kWave) return;
     __threadfence();
     if (D.n_inst > 1) {
         for (int i = tid; i < D.n_inst; i += kWave) {
@@ -1146,11 +1204,12 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
             }
             M->step = tg - D.inst_t0[i] + 1;
         }
-        __syncthreads();
+        wave_sync();
         if (tid == 0) {
             *D.gstep = tg + 1;
             *D.done_ctr = 0u;
-            *D.ovf_cnt = 0;
+            D.list_cnt[0] = 0;
+            D.list_cnt[1] = 0;
         }
         return;
     }
@@ -1184,66 +1243,49 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
         M->step = tg - D.inst_t0[0] + 1;
         *D.gstep = tg + 1;
         *D.done_ctr = 0u;
-        *D.ovf_cnt = 0;
+        D.list_cnt[0] = 0;
+        D.list_cnt[1] = 0;
     }
 }
 
-// Grouped pass: tiles tile_order[0, nA) (at most GW lanes each), 64 / GW
-// tiles per wavefront, one group of GW lanes per tile.  A tile holding more
-// than CAP vehicles is left to the wide pass through the overflow list.
-template <int GW, int CAP, int CHG>
-__global__ __launch_bounds__(kWave) void k_update_grouped(const DevNet* __restrict__ Dp, int nA, int total_wg)
+// Grouped pass: the step's small-tile list (tiles of at most GW lanes and
+// CAP vehicles, built by the prepare kernel), 64 / GW tiles per wavefront,
+// one group of GW lanes per tile; the grid strides over the list.
+template <int GW, int CAP, int CHG, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet* __restrict__ Dp, int total_wg)
 {
     constexpr int NG = kWave / GW;
     using TS = TileLds<GW, CAP, CHG>;
-    __shared__ TS Sg[NG];
-    __shared__ WGPartial gacc[NG];
+    __shared__ TS Sg[WPB * NG];
+    __shared__ WGPartial gacc[WPB * NG];
     __shared__ int skip;
     const DevNet& D = *Dp;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
-    const int tid = threadIdx.x;
+    // the WPB wavefronts of a workgroup work independently (each its own
+    // groups and tiles); they meet only to combine their partial sums
+    const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
-    TS& S = Sg[g];
-    const int GA = (int)gridDim.x;
-
-    // slot k of this workgroup's sequence -> tile position, or -1
-    int first, count, stride;
-    if (D.blocked) {
-        int chunk = (nA + GA - 1) / GA;
-        chunk = (chunk + NG - 1) / NG * NG;
-        first = (int)blockIdx.x * chunk;
-        count = min(nA - first, chunk);
-        stride = 1;
-    } else {
-        first = (int)blockIdx.x * NG;
-        count = nA - first;
-        stride = GA * NG;
-    }
-    auto pos_of = [&](int round) -> int {
-        if (D.blocked) {
-            const int k = round * NG + g;
-            return k < count ? first + k : -1;
-        }
-        const int ps = first + round * stride + g;
-        return ps < nA ? ps : -1;
-    };
-    const int rounds = count <= 0 ? 0 : (D.blocked ? (count + NG - 1) / NG : (count + stride - 1) / stride);
+    TS& S = Sg[w * NG + g];
+    const int count = D.list_cnt[0];
+    const int first = ((int)blockIdx.x * WPB + w) * NG;
+    const int stride = (int)gridDim.x * WPB * NG;
+    const int rounds = count > first ? (count - first + stride - 1) / stride : 0;
 
     WGPartial acc{};
     int acc_inst = -1;
-    int p0 = rounds > 0 ? pos_of(0) : -1;
-    Hdr nxt = load_hdr(D, B, p0 >= 0 ? D.tile_order[p0] : -1);
+    int p0 = first + g;
+    Hdr nxt = load_hdr(D, B, (rounds > 0 && p0 < count) ? D.list_small[p0] : -1);
     for (int round = 0; round < rounds; ++round) {
         const Hdr h = nxt;
-        const int pn = round + 1 < rounds ? pos_of(round + 1) : -1;
-        const int rn = pn >= 0 ? D.tile_order[pn] : -1;
+        const int pn = first + (round + 1) * stride + g;
+        const int rn = (round + 1 < rounds && pn < count) ? D.list_small[pn] : -1;
         const long long t = tg - D.inst_t0[h.inst];
-        const bool live = h.r >= 0 && !(h.rt == 0 && h.wt == 0);
+        const bool live = h.r >= 0;
         LaneRegs lr{-1, 0, 0u};
         if (live) lr = load_lanes_a(D, B, S, h, gt);
         if (gt == 0) reset_counters(S, h);
-        __syncthreads();
+        wave_sync();
         // lane starts of the tile enumeration (inclusive scan within the group)
         {
             int c = (live && gt < h.nl) ? S.cnt[gt] : 0;
@@ -1256,38 +1298,38 @@ __global__ __launch_bounds__(kWave) void k_update_grouped(const DevNet* __restri
             if (gt == 0) S.start[0] = 0;
             if (gt == GW - 1) S.n = live ? c : 0;
         }
-        __syncthreads();
-        const int n = S.n;
-        const int ne = n <= CAP ? n : 0;
-        if (live && n == 0) empty_tile(D, B, h, gt);
-        if (n > CAP && gt == 0) D.ovf[atomicAdd(D.ovf_cnt, 1)] = h.r;
-        if (ne > 0) load_lanes_b(D, B, S, h, gt, lr);
-        for (int j = gt; j < ne; j += GW) {
+        wave_sync();
+        // the list holds tiles of at most CAP vehicles; a tile count that
+        // disagrees with its lanes (only after a capacity error) is skipped
+        const int n = S.n <= CAP ? S.n : 0;
+        if (S.n > CAP && gt == 0) atomicAdd((unsigned long long*)&D.met[h.inst].errors, 1ull);
+        if (n > 0) load_lanes_b(D, B, S, h, gt, lr);
+        for (int j = gt; j < n; j += GW) {
             const int li = lane_of(S, j);
             S.vl[j] = (signed char)li;
             S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
         }
         nxt = load_hdr(D, B, rn);
-        __syncthreads();
+        wave_sync();
         LdsView<TS> view{S};
-        process_tile<GW>(D, S, view, B, t, h.inst, gt, gbase, ne);
-        __syncthreads();
-        if (ne > 0) {
+        process_tile<GW>(D, S, view, B, t, h.inst, gt, gbase, n);
+        wave_sync();
+        if (n > 0) {
             if (gt == 0 && D.n_inst > 1 && h.inst != acc_inst) {
                 flush_acc(D, acc, acc_inst);
                 acc_inst = h.inst;
             }
-            finish_tile(D, B, S, h, gt, ne, acc);
+            finish_tile(D, B, S, h, gt, n, acc);
         }
-        __syncthreads();
+        wave_sync();
     }
     if (D.n_inst > 1 && gt == 0) flush_acc(D, acc, acc_inst);
     // group partials -> workgroup partial
-    if (gt == 0) gacc[g] = acc;
+    if (gt == 0) gacc[w * NG + g] = acc;
     __syncthreads();
     WGPartial tot{};
-    if (tid == 0) {
-        for (int q = 0; q < NG; ++q) {
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < WPB * NG; ++q) {
             long long* a = (long long*)&tot;
             const long long* b = (const long long*)&gacc[q];
             for (int k = 0; k < 10; ++k) a[k] += b[k];
@@ -1296,31 +1338,33 @@ __global__ __launch_bounds__(kWave) void k_update_grouped(const DevNet* __restri
     finish_step(D, tg, tot, (int)blockIdx.x, total_wg, &skip);
 }
 
-// Wide pass: tiles tile_order[nA, R) and the overflow list, one tile per
-// wavefront; up to kTileCap vehicles staged in LDS, more on global scratch.
-// Part slots follow the grouped pass's (offset a_wg).
-__global__ __launch_bounds__(kWave) void k_update_wide(const DevNet* __restrict__ Dp, int nA, int a_wg, int total_wg)
+constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
+
+// Wide pass: the step's wide-tile list, one tile per wavefront; up to
+// kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
+// the grouped pass's (offset a_wg).  The last workgroup folds the step.
+template <int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet* __restrict__ Dp, int a_wg, int total_wg)
 {
-    using TS = TileLds<kMaxTileLanes, kTileCap, kChangerCap>;
-    __shared__ TS S;
+    using TS = TileLds<kMaxTileLanes, kWideCap, kChangerCap>;
+    __shared__ TS Sw[WPB];
+    __shared__ WGPartial wacc[WPB];
     __shared__ int skip;
     const DevNet& D = *Dp;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
-    const int tid = threadIdx.x;
-    const int GB = (int)gridDim.x;
-    const int RS = D.R - nA;
-    const int novf = *D.ovf_cnt;
+    const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
+    TS& S = Sw[w];
+    const int count = D.list_cnt[1];
 
     WGPartial acc{};
     int acc_inst = -1;
-    auto run = [&](int r) {
-        const Hdr h = load_hdr(D, B, r);
-        if (h.rt == 0 && h.wt == 0) return;
+    for (int k = (int)blockIdx.x * WPB + w; k < count; k += (int)gridDim.x * WPB) {
+        const Hdr h = load_hdr(D, B, D.list_big[k]);
         const long long t = tg - D.inst_t0[h.inst];
         const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
         if (tid == 0) reset_counters(S, h);
-        __syncthreads();
+        wave_sync();
         {
             int c = tid < h.nl ? S.cnt[tid] : 0;
 #pragma unroll
@@ -1332,46 +1376,43 @@ __global__ __launch_bounds__(kWave) void k_update_wide(const DevNet* __restrict_
             if (tid == 0) S.start[0] = 0;
             if (tid == kWave - 1) S.n = c;
         }
-        __syncthreads();
+        wave_sync();
         const int n = S.n;
-        if (n == 0) {
-            empty_tile(D, B, h, tid);
-            __syncthreads();
-            return;
-        }
         load_lanes_b(D, B, S, h, tid, lr);
-        if (n <= kTileCap) {
+        if (n <= kWideCap) {
             for (int j = tid; j < n; j += kWave) {
                 const int li = lane_of(S, j);
                 S.vl[j] = (signed char)li;
                 S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
             }
-            __syncthreads();
+            wave_sync();
             LdsView<TS> view{S};
             process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
         } else {
-            __syncthreads();
+            wave_sync();
             GlobalView<TS> view{S, D, B.rd};
             process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
         }
-        __syncthreads();
+        wave_sync();
         if (tid == 0 && D.n_inst > 1 && h.inst != acc_inst) {
             flush_acc(D, acc, acc_inst);
             acc_inst = h.inst;
         }
         finish_tile(D, B, S, h, tid, n, acc);
-        __syncthreads();
-    };
-    if (D.blocked) {
-        const int chunk = (RS + GB - 1) / GB;
-        const int b = (int)blockIdx.x * chunk, e = min(RS, b + chunk);
-        for (int k = b; k < e; ++k) run(D.tile_order[nA + k]);
-    } else {
-        for (int k = (int)blockIdx.x; k < RS; k += GB) run(D.tile_order[nA + k]);
+        wave_sync();
     }
-    for (int k = (int)blockIdx.x; k < novf; k += GB) run(D.ovf[k]);
     if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
-    finish_step(D, tg, acc, a_wg + (int)blockIdx.x, total_wg, &skip);
+    if (tid == 0) wacc[w] = acc;
+    __syncthreads();
+    WGPartial tot{};
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < WPB; ++q) {
+            long long* a = (long long*)&tot;
+            const long long* b = (const long long*)&wacc[q];
+            for (int k = 0; k < 10; ++k) a[k] += b[k];
+        }
+    }
+    finish_step(D, tg, tot, a_wg + (int)blockIdx.x, total_wg, &skip);
 }
 
 // ---------------------------------------------------------------------------
@@ -1441,7 +1482,15 @@ __global__ void k_import(const DevNet* __restrict__ Dp, const uint32_t* slots, c
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
     const int n = H.R > H.NJ ? H.R : H.NJ;
-    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, Dd);
+    int lanes = 0, cap = 0;
+    switch (H.sched) {
+    case kSched16x32: lanes = 16; cap = 32; break;
+    case kSched16x64: lanes = 16; cap = 64; break;
+    case kSched32x64: lanes = 32; cap = 64; break;
+    case kSched8x16: lanes = 8; cap = 16; break;
+    default: break;
+    }
+    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, Dd, lanes, cap);
     return hipGetLastError();
 }
 
@@ -1451,16 +1500,16 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
     if (H.GA > 0) {
         switch (H.sched) {
         case kSched16x32:
-            hipLaunchKernelGGL((k_update_grouped<16, 32, 16>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, Dd, total);
             break;
         case kSched16x64:
-            hipLaunchKernelGGL((k_update_grouped<16, 64, 32>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, Dd, total);
             break;
         case kSched32x64:
-            hipLaunchKernelGGL((k_update_grouped<32, 64, 32>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, Dd, total);
             break;
         case kSched8x16:
-            hipLaunchKernelGGL((k_update_grouped<8, 16, 8>), dim3(H.GA), dim3(kWave), 0, s, Dd, H.nA, total);
+            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, Dd, total);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1468,8 +1517,34 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_update_wide, dim3(H.GB), dim3(kWave), 0, s, Dd, H.nA, H.GA, total);
+    hipLaunchKernelGGL((k_update_wide<kWideWaves>), dim3(H.GB), dim3(kWideWaves * kWave), 0, s, Dd, H.GA, total);
     return hipGetLastError();
+}
+
+// resident workgroups per compute unit of the update kernels (sched < 0:
+// the wide pass), from the compiled kernels' register and LDS use
+int update_blocks_per_cu(int sched)
+{
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    switch (sched) {
+    case kSched16x32:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<16, 32, 16, 4>, 4 * kWave, 0);
+        break;
+    case kSched16x64:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<16, 64, 32, 2>, 2 * kWave, 0);
+        break;
+    case kSched32x64:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<32, 64, 32, 4>, 4 * kWave, 0);
+        break;
+    case kSched8x16:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<8, 16, 8, 4>, 4 * kWave, 0);
+        break;
+    default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_wide<kWideWaves>, kWideWaves * kWave, 0);
+        break;
+    }
+    return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_set_phases(const DevNet* Dd, const int32_t* ids, const int32_t* ph, int n, hipStream_t s)
