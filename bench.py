@@ -24,7 +24,9 @@ same schedule are the baseline (ratio in "vs_plain_loop").
 --workload serve: a Poisson stream (20 jobs/s) of pre-generated jobs (signal
 timing plans or road prices; 10k-500k vehicles; 300-3,600 steps) run by the
 continuous-batching loop of ``paper_2406_10661_amd.serve`` under an HBM
-budget; reports jobs/s, p50/p99 latency and the plain one-job-at-a-time loop.
+budget (default: jobs gathered into batches, each frozen at its own
+horizon); reports jobs/s, p50/p99 latency and the plain one-job-at-a-time
+loop.
 
 Prints one JSON line on stdout.
 """
@@ -230,8 +232,13 @@ def run_serve(args):
         f"{sum(w.trips.n_vehicles for w in ws)} vehicles in total")
     jobs = [SV.Job(jid=k, arrival=float(arr[k]), network=w.network, trips=w.trips, params=w.params,
                    horizon=w.n_steps) for k, w in enumerate(ws)]
-    fac = SV.GpuFactory(n_streams=args.streams, graph_steps=args.tick)
-    loop = SV.ServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick)
+    if args.serve_mode == "batched":
+        fac = SV.BatchFactory(n_streams=args.streams, graph_steps=args.tick)
+        loop = SV.BatchedServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick,
+                                   max_batches=args.max_batches, max_jobs_per_batch=args.max_jobs_per_batch)
+    else:
+        fac = SV.GpuFactory(n_streams=args.streams, graph_steps=args.tick)
+        loop = SV.ServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick)
     res = loop.run(jobs)
     summ = SV.summarize(res, skip=args.skip)
     log(f"[bench] served: {json.dumps(summ)}")
@@ -265,7 +272,7 @@ def run_serve(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "served_poisson", "jobs": len(jobs), "measured_after": args.skip,
                    "rate_jobs_per_s": args.rate, "hbm_budget_gib": args.budget_gib, "steps_per_tick": args.tick,
-                   "streams": args.streams},
+                   "streams": args.streams, "mode": args.serve_mode, "batches": res.get("batches")},
         "latency_p50_s": summ["latency_p50_s"], "latency_p99_s": summ["latency_p99_s"],
         "queue_wait_p99_s": summ["queue_wait_p99_s"],
         "vehicle_steps_per_s": summ["vehicle_steps_per_s"],
@@ -315,6 +322,9 @@ def main():
     ap.add_argument("--tick", type=int, default=30)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=60)
+    ap.add_argument("--serve-mode", choices=["batched", "streams"], default="batched")
+    ap.add_argument("--max-batches", type=int, default=3)
+    ap.add_argument("--max-jobs-per-batch", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "

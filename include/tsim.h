@@ -254,6 +254,11 @@ int tsim_batch_create(const tsim_network *nets, const tsim_trips *trips, const t
 int tsim_batch_step(tsim_batch *b, int32_t n_steps);
 /* As tsim_set_graph_steps, for the whole batch. */
 int tsim_batch_set_graph_steps(tsim_batch *b, int32_t chunk);
+/* Instance `instance` is simulated for its first n_steps local steps only;
+ * from then on it is frozen (no signal, departure, update or metric changes)
+ * while the rest of the batch goes on, so jobs of different horizons can share
+ * a batch.  Enqueued on the stream; default: no horizon. */
+int tsim_batch_set_horizon(tsim_batch *b, int32_t instance, int64_t n_steps);
 int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
                                  const int32_t *phase_index, int32_t n);
 /* Every junction of every instance at once: phase_index[k] for the k-th

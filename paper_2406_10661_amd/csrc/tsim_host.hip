@@ -18,11 +18,12 @@
 namespace tsim {
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s);
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s);
-hipError_t launch_set_phases(const DevNet* Dd, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
+hipError_t launch_set_phases(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
 hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
-hipError_t launch_import(const DevNet* Dd, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
+hipError_t launch_import(const DevNet* Dd, const DevNet& H, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
 hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s);
+hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
 int update_blocks_per_cu(int sched);
 }  // namespace tsim
 
@@ -620,6 +621,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.inst_vbase, (size_t)B.n_inst * 4);
     add(&D.inst_key, (size_t)B.n_inst * 8);
     add(&D.inst_t0, (size_t)B.n_inst * 8);
+    add(&D.inst_end, (size_t)B.n_inst * 8);
     add(&D.inst_acc, (size_t)B.n_inst * sizeof(WGPartial));
     add(&D.gstep, 8);
     add(&h->d_lane_ext, NL * 4);
@@ -827,7 +829,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     if (!slots.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_io_i0, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_io_rec, recs.data(), recs.size() * sizeof(VehRec), hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, launch_import(h->d_net, (const uint32_t*)h->d_io_i0, h->d_io_rec, (int)slots.size(), h->stream));
+        HIPCHK(h, launch_import(h->d_net, h->D, (const uint32_t*)h->d_io_i0, h->d_io_rec, (int)slots.size(), h->stream));
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
@@ -1016,6 +1018,8 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     e = e ? e : chk(up(h, (int32_t*)D.inst_vbase, B.inst_vbase), "instances");
     e = e ? e : chk(up(h, (uint32_t*)D.inst_key, B.inst_key), "instances");
     e = e ? e : chk(up(h, (long long*)D.inst_t0, B.inst_t0), "instances");
+    e = e ? e : chk(up(h, (long long*)D.inst_end, std::vector<long long>(B.n_inst, std::numeric_limits<long long>::max())),
+                    "instances");
     e = e ? e : chk(hipMemcpyAsync(h->d_net, &h->D, sizeof(DevNet), hipMemcpyHostToDevice, h->stream), "view");
     if (e) {
         delete h;
@@ -1275,7 +1279,7 @@ static int set_phases_impl(tsim_handle* h, int inst, const int32_t* junction_ids
     std::memcpy(hp, ids.data(), (size_t)n * 4);
     std::memcpy(hp + B.NJ, ph.data(), (size_t)n * 4);
     HIPCHK(h, hipMemcpyAsync(dp, hp, (size_t)2 * B.NJ * 4, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, launch_set_phases(h->d_net, dp, dp + B.NJ, n, h->stream));
+    HIPCHK(h, launch_set_phases(h->d_net, h->D, dp, dp + B.NJ, n, h->stream));
     HIPCHK(h, hipEventRecord(h->pin_ev[h->pin_slot ^ 1], h->stream));
     return TSIM_OK;
 }
@@ -1289,6 +1293,14 @@ int tsim_batch_set_signal_phases(tsim_batch* b, int32_t instance, const int32_t*
                                  const int32_t* phase_index, int32_t n)
 {
     return set_phases_impl(b, instance, junction_ids, phase_index, n);
+}
+
+int tsim_batch_set_horizon(tsim_batch* b, int32_t instance, int64_t n_steps)
+{
+    if (!b || instance < 0 || instance >= b->B.n_inst || n_steps < 0)
+        return fail(nullptr, TSIM_EINVAL, "bad batch, instance or step count");
+    HIPCHK(b, launch_set_end(b->D, instance, (long long)n_steps, b->stream));
+    return TSIM_OK;
 }
 
 int tsim_batch_set_all_phases(tsim_batch* b, const int32_t* phase_index, int32_t n_total)

@@ -140,6 +140,7 @@ struct DevNet {
     const int32_t* inst_vbase;       // [n_inst] first vehicle id of each instance
     const uint32_t* inst_key;        // [2 n_inst] Philox key of each instance
     const long long* inst_t0;        // [n_inst] global step at which the instance starts
+    long long* inst_end;             // [n_inst] local step from which the instance is frozen
     WGPartial* inst_acc;             // [n_inst] sums of the current step (batches)
     long long* gstep;                // global step counter
     // tiles

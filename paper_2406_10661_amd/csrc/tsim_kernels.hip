@@ -155,9 +155,8 @@ __device__ __forceinline__ void append_wave(int32_t* list, int32_t* cnt, bool pr
 // ---------------------------------------------------------------------------
 // prepare
 // ---------------------------------------------------------------------------
-__global__ void k_prepare(const DevNet* __restrict__ Dp, int small_lanes, int small_cap)
+__global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
 {
-    const DevNet& D = *Dp;
     const long long tg = *D.gstep;
     const int p = (int)(tg & 1);
     VehRec* slab = p ? D.slab1 : D.slab0;
@@ -168,7 +167,7 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp, int small_lanes, int sm
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const KParams& P = D.P;
 
-    if (i < D.NJ) {
+    if (i < D.NJ && tg - D.inst_t0[D.junc_inst[i]] < D.inst_end[D.junc_inst[i]]) {
         const long long t = tg - D.inst_t0[D.junc_inst[i]];
         const int b = D.junc_phase_begin[i], e = D.junc_phase_begin[i + 1];
         int cur = -1;
@@ -196,6 +195,8 @@ __global__ void k_prepare(const DevNet* __restrict__ Dp, int small_lanes, int sm
     const int r = i;
     const int inst = D.tile_inst[r];
     const long long t = tg - D.inst_t0[inst];
+    // an instance past its horizon is frozen: none of its tiles is listed
+    if (t >= D.inst_end[inst]) return;
     const int lb = D.tile_lane_begin[r];
     const int nrl = D.tile_n_road[r];
     // feeder gates of this road's lanes in the summaries this step writes
@@ -672,12 +673,10 @@ __device__ __forceinline__ void reset_counters(TS& S, const Hdr& h)
     S.sum_tt = 0ull;
 }
 
-// the three passes of one tile; n vehicles (0 = nothing to do), run by the
-// GW lanes gt of the group starting at wave lane gbase.  Barriers are
-// reached by every lane of the workgroup whatever n is.
+// passes 1 and 2 of one tile (see process_tile)
 template <int GW, class TS, class V>
-__device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B, long long t, int inst, int gt,
-                             int gbase, int n)
+__device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& B, long long t, int inst, int gt,
+                               int n)
 {
     const uint32_t key0 = D.inst_key[2 * inst], key1 = D.inst_key[2 * inst + 1];
     const int vbase = D.inst_vbase[inst];
@@ -861,23 +860,23 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
             if (di) eR = e;
             else eL = e;
         }
-        // randomized decision
+        // randomized decision (the draw only matters when a side is feasible)
         const float uLp = fmaxf(0.0f, eL.u), uRp = fmaxf(0.0f, eR.u);
         const float uT = uLp + uRp;
         const float pLC = uT >= 1.0f ? P.p_max : (uT > 0.0f ? P.p_min + (P.p_max - P.p_min) * uT : P.p_min);
-        const uint32_t w = philox_word0(key0, key1, (uint32_t)(rec.vid - vbase), (uint32_t)t);
-        const float rr = (float)w * 2.3283064365386963e-10f;  // 2^-32
+        const bool fL = eL.u > -TS_INF, fR = eR.u > -TS_INF;
         int dec = 0;
-        if (uT > 0.0f) {
-            const float bL = pLC * uLp / uT;
-            if (uLp > 0.0f && rr < bL) dec = 1;
-            else if (uRp > 0.0f && rr >= bL && rr < pLC) dec = 2;
-        } else {
-            const bool fL = eL.u > -TS_INF, fR = eR.u > -TS_INF;
-            if (fL && fR) {
+        if (fL || fR) {
+            const uint32_t w = philox_word0(key0, key1, (uint32_t)(rec.vid - vbase), (uint32_t)t);
+            const float rr = (float)w * 2.3283064365386963e-10f;  // 2^-32
+            if (uT > 0.0f) {
+                const float bL = pLC * uLp / uT;
+                if (uLp > 0.0f && rr < bL) dec = 1;
+                else if (uRp > 0.0f && rr >= bL && rr < pLC) dec = 2;
+            } else if (fL && fR) {
                 if (rr < 0.5f * P.p_min) dec = 1;
                 else if (rr < P.p_min) dec = 2;
-            } else if (fL || fR) {
+            } else {
                 if (rr < P.p_min) dec = fL ? 1 : 2;
             }
         }
@@ -1036,8 +1035,14 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
         }
     }
     wave_sync();
+}
 
-    // ---------------- pass 3: new order ----------------
+// pass 3 of one tile: new per-lane order, records and summaries written
+template <int GW, class TS, class V>
+__device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B, int gt, int gbase, int n)
+{
+    const KParams& P = D.P;
+    const int nroad = S.nroad;
     {
         int carry = 0;
         for (int b0 = 0; b0 < n; b0 += GW) {
@@ -1118,6 +1123,17 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
     }
 }
 
+// the three passes of one tile; n vehicles (0 = nothing to do), run by the
+// GW lanes gt of the group starting at wave lane gbase.  Every lane of the
+// wavefront passes the same fences whatever its group's n is.
+template <int GW, class TS, class V>
+__device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B, long long t, int inst, int gt,
+                             int gbase, int n)
+{
+    process_pass12<GW>(D, S, view, B, t, inst, gt, n);
+    process_pass3<GW>(D, S, view, B, gt, gbase, n);
+}
+
 // lane summaries, waiting counts and tile totals after a processed tile
 template <class TS>
 __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt, int n,
@@ -1179,6 +1195,7 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
     __threadfence();
     if (D.n_inst > 1) {
         for (int i = tid; i < D.n_inst; i += kWave) {
+            if (tg - D.inst_t0[i] >= D.inst_end[i]) continue;   // frozen instance
             volatile long long* q = (volatile long long*)&D.inst_acc[i];
             long long a[10];
 #pragma unroll
@@ -1252,14 +1269,13 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
 // CAP vehicles, built by the prepare kernel), 64 / GW tiles per wavefront,
 // one group of GW lanes per tile; the grid strides over the list.
 template <int GW, int CAP, int CHG, int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet* __restrict__ Dp, int total_wg)
+__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, int total_wg)
 {
     constexpr int NG = kWave / GW;
     using TS = TileLds<GW, CAP, CHG>;
     __shared__ TS Sg[WPB * NG];
     __shared__ WGPartial gacc[WPB * NG];
     __shared__ int skip;
-    const DevNet& D = *Dp;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
     // the WPB wavefronts of a workgroup work independently (each its own
@@ -1274,45 +1290,145 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet* __
 
     WGPartial acc{};
     int acc_inst = -1;
-    int p0 = first + g;
-    Hdr nxt = load_hdr(D, B, (rounds > 0 && p0 < count) ? D.list_small[p0] : -1);
+
+    // Software pipeline over the group's tiles: while tile k is processed,
+    // the lane tables, out-lane summaries, signal states and records of tile
+    // k+1 are loaded into registers (lane gt holds lane gt of the next tile
+    // and records gt, gt + GW, ...), so a round starts from data in hand.
+    constexpr int RPT = (CAP + GW - 1) / GW;
+    static_assert(RPT <= 4, "at most four prefetched records per lane");
+    __shared__ int pst_all[WPB * NG][GW + 1];      // next tile: lane starts
+    __shared__ uint32_t pbs_all[WPB * NG][GW];     // next tile: lane slab bases
+    int* const pst = pst_all[w * NG + g];
+    uint32_t* const pbs = pbs_all[w * NG + g];
+    LaneInfo pL{};
+    int pcnt = 0, pfmx = kNoFeeder, pcur = -1, pn = 0;
+    LaneSum po{};
+    // records as pairs of 16-byte vectors (register-friendly)
+    int4 r0a{}, r0b{}, r1a{}, r1b{}, r2a{}, r2b{}, r3a{}, r3b{};
+
+#define TSIM_PF_LANES(H)                                                       \
+    do {                                                                       \
+        pcnt = 0;                                                              \
+        if ((H).r >= 0 && gt < (H).nl) {                                       \
+            const int m_ = (H).lb + gt;                                        \
+            pL = D.lane_info[m_];                                              \
+            pcnt = B.rsum[m_].cnt;                                             \
+            pfmx = gt < (H).nroad ? B.rsum[m_].fmax : kNoFeeder;               \
+        }                                                                      \
+    } while (0)
+#define TSIM_PF_LANE_OF(J, LI)                                                 \
+    int LI = 0;                                                                \
+    while ((J) >= pst[LI + 1]) LI++
+#define TSIM_PF_LOAD(I, RA, RB)                                                \
+    do {                                                                       \
+        const int j_ = gt + (I) * GW;                                          \
+        if ((I) < RPT && j_ < pn) {                                            \
+            TSIM_PF_LANE_OF(j_, li_);                                          \
+            const int4* src_ = (const int4*)(B.rd + pbs[li_] + (uint32_t)(j_ - pst[li_])); \
+            RA = src_[0];                                                      \
+            RB = src_[1];                                                      \
+        }                                                                      \
+    } while (0)
+#define TSIM_PF_STORE(I, RA, RB)                                               \
+    do {                                                                       \
+        const int j_ = gt + (I) * GW;                                          \
+        if ((I) < RPT && j_ < pn) {                                            \
+            TSIM_PF_LANE_OF(j_, li_);                                          \
+            int4* dst_ = (int4*)&S.rec[j_];                                    \
+            dst_[0] = RA;                                                      \
+            dst_[1] = RB;                                                      \
+            S.vl[j_] = (signed char)li_;                                       \
+        }                                                                      \
+    } while (0)
+    // stage 2 (stage 1 in hand): lane starts, records, out-lane summaries and
+    // signal states of tile H
+#define TSIM_PF_REST(H)                                                        \
+    do {                                                                       \
+        int c_ = pcnt;                                                         \
+        _Pragma("unroll") for (int off = 1; off < GW; off <<= 1)               \
+        {                                                                      \
+            const int y_ = __shfl_up(c_, off, GW);                             \
+            if (gt >= off) c_ += y_;                                           \
+        }                                                                      \
+        pst[gt + 1] = c_;                                                      \
+        if (gt == 0) pst[0] = 0;                                               \
+        pbs[gt] = pL.base;                                                     \
+        pn = __shfl(c_, gbase + GW - 1);                                       \
+        wave_sync();                                                           \
+        if (pn <= CAP) {                                                       \
+            TSIM_PF_LOAD(0, r0a, r0b);                                         \
+            TSIM_PF_LOAD(1, r1a, r1b);                                         \
+            TSIM_PF_LOAD(2, r2a, r2b);                                         \
+            TSIM_PF_LOAD(3, r3a, r3b);                                         \
+        }                                                                      \
+        if ((H).r >= 0 && gt < (H).nl && gt >= (H).nroad) {                    \
+            po = B.rsum[pL.jl_out];                                            \
+            pcur = D.junc_cur[pL.jl_junc];                                     \
+        }                                                                      \
+    } while (0)
+
+    auto pos_of = [&](int round) -> int {
+        const int ps = first + round * stride + g;
+        return (round < rounds && ps < count) ? ps : -1;
+    };
+
+    Hdr cur = load_hdr(D, B, pos_of(0) >= 0 ? D.list_small[pos_of(0)] : -1);
+    int rn = pos_of(1) >= 0 ? D.list_small[pos_of(1)] : -1;
+    TSIM_PF_LANES(cur);
+    TSIM_PF_REST(cur);
     for (int round = 0; round < rounds; ++round) {
-        const Hdr h = nxt;
-        const int pn = first + (round + 1) * stride + g;
-        const int rn = (round + 1 < rounds && pn < count) ? D.list_small[pn] : -1;
+        const Hdr h = cur;
         const long long t = tg - D.inst_t0[h.inst];
-        const bool live = h.r >= 0;
-        LaneRegs lr{-1, 0, 0u};
-        if (live) lr = load_lanes_a(D, B, S, h, gt);
-        if (gt == 0) reset_counters(S, h);
-        wave_sync();
-        // lane starts of the tile enumeration (inclusive scan within the group)
-        {
-            int c = (live && gt < h.nl) ? S.cnt[gt] : 0;
-#pragma unroll
-            for (int off = 1; off < GW; off <<= 1) {
-                const int y = __shfl_up(c, off, GW);
-                if (gt >= off) c += y;
+        // the prefetched tile becomes the LDS image of the current tile
+        if (h.r >= 0 && gt < h.nl) {
+            S.lane[gt] = h.lb + gt;
+            S.cnt[gt] = pcnt;
+            S.base[gt] = pL.base;
+            S.cap[gt] = pL.cap;
+            S.len[gt] = pL.len;
+            S.lim[gt] = pL.lim;
+            S.nstay[gt] = 0;
+            S.nin[gt] = 0;
+            S.nenter[gt] = 0;
+            S.wait[gt] = 0;
+            S.jl_out[gt] = pL.jl_out;
+            S.jl_out_road[gt] = pL.jl_out_road;
+            S.jl_in_local[gt] = pL.jl_in_local;
+            S.jl_ext[gt] = pL.jl_ext;
+            S.fmx[gt] = pfmx;
+            if (gt >= h.nroad) {
+                S.green[gt] = (pcur < 0 || ((pL.green_mask >> pcur) & 1u)) ? 1 : 0;
+                S.osum[gt] = po;
+            } else {
+                S.green[gt] = 1;
             }
-            if (live && gt < h.nl) S.start[gt + 1] = c;
-            if (gt == 0) S.start[0] = 0;
-            if (gt == GW - 1) S.n = live ? c : 0;
+        }
+        S.start[gt + 1] = pst[gt + 1];
+        if (gt == 0) {
+            S.start[0] = 0;
+            reset_counters(S, h);
+            S.n = h.r >= 0 ? pn : 0;
+        }
+        if (pn <= CAP) {
+            TSIM_PF_STORE(0, r0a, r0b);
+            TSIM_PF_STORE(1, r1a, r1b);
+            TSIM_PF_STORE(2, r2a, r2b);
+            TSIM_PF_STORE(3, r3a, r3b);
         }
         wave_sync();
         // the list holds tiles of at most CAP vehicles; a tile count that
         // disagrees with its lanes (only after a capacity error) is skipped
         const int n = S.n <= CAP ? S.n : 0;
         if (S.n > CAP && gt == 0) atomicAdd((unsigned long long*)&D.met[h.inst].errors, 1ull);
-        if (n > 0) load_lanes_b(D, B, S, h, gt, lr);
-        for (int j = gt; j < n; j += GW) {
-            const int li = lane_of(S, j);
-            S.vl[j] = (signed char)li;
-            S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
-        }
-        nxt = load_hdr(D, B, rn);
-        wave_sync();
+        // next tile: header and lane tables now, the rest after pass 2
+        const Hdr hn = load_hdr(D, B, rn);
+        const int rn2 = pos_of(round + 2) >= 0 ? D.list_small[pos_of(round + 2)] : -1;
+        TSIM_PF_LANES(hn);
         LdsView<TS> view{S};
-        process_tile<GW>(D, S, view, B, t, h.inst, gt, gbase, n);
+        process_pass12<GW>(D, S, view, B, t, h.inst, gt, n);
+        TSIM_PF_REST(hn);
+        process_pass3<GW>(D, S, view, B, gt, gbase, n);
         wave_sync();
         if (n > 0) {
             if (gt == 0 && D.n_inst > 1 && h.inst != acc_inst) {
@@ -1322,7 +1438,14 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet* __
             finish_tile(D, B, S, h, gt, n, acc);
         }
         wave_sync();
+        cur = hn;
+        rn = rn2;
     }
+#undef TSIM_PF_LANES
+#undef TSIM_PF_LANE_OF
+#undef TSIM_PF_LOAD
+#undef TSIM_PF_STORE
+#undef TSIM_PF_REST
     if (D.n_inst > 1 && gt == 0) flush_acc(D, acc, acc_inst);
     // group partials -> workgroup partial
     if (gt == 0) gacc[w * NG + g] = acc;
@@ -1344,13 +1467,12 @@ constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
 // kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
 // the grouped pass's (offset a_wg).  The last workgroup folds the step.
 template <int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet* __restrict__ Dp, int a_wg, int total_wg)
+__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg, int total_wg)
 {
     using TS = TileLds<kMaxTileLanes, kWideCap, kChangerCap>;
     __shared__ TS Sw[WPB];
     __shared__ WGPartial wacc[WPB];
     __shared__ int skip;
-    const DevNet& D = *Dp;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
@@ -1418,19 +1540,23 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet* __res
 // ---------------------------------------------------------------------------
 // host-driven helpers
 // ---------------------------------------------------------------------------
-__global__ void k_set_phases(const DevNet* __restrict__ Dp, const int32_t* ids, const int32_t* ph, int n)
+__global__ void k_set_phases(const DevNet D, const int32_t* ids, const int32_t* ph, int n)
 {
-    const DevNet& D = *Dp;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     D.junc_policy[ids[i]] = 2;
     D.junc_manual[ids[i]] = ph[i];
 }
 
-// one phase entry per junction (negative = unchanged)
-__global__ void k_set_all_phases(const DevNet* __restrict__ Dp, const int32_t* ph)
+// horizon of one instance (local steps after which it is frozen)
+__global__ void k_set_end(const DevNet D, int inst, long long end)
 {
-    const DevNet& D = *Dp;
+    D.inst_end[inst] = end;
+}
+
+// one phase entry per junction (negative = unchanged)
+__global__ void k_set_all_phases(const DevNet D, const int32_t* ph)
+{
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= D.NJ || ph[j] < 0) return;
     D.junc_policy[j] = 2;
@@ -1438,10 +1564,9 @@ __global__ void k_set_all_phases(const DevNet* __restrict__ Dp, const int32_t* p
 }
 
 // per-vehicle export of the state at a step boundary (residents + inboxes)
-__global__ void k_export(const DevNet* __restrict__ Dp, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
+__global__ void k_export(const DevNet D, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
                          float* o_v, int32_t* o_rpos, int32_t* o_rank)
 {
-    const DevNet& D = *Dp;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= D.NL) return;
     const long long t = *D.gstep;
@@ -1468,9 +1593,8 @@ __global__ void k_export(const DevNet* __restrict__ Dp, const int32_t* lane_ext,
 }
 
 // scatter of host-ordered records into the read slab of the current step
-__global__ void k_import(const DevNet* __restrict__ Dp, const uint32_t* slots, const VehRec* recs, int n)
+__global__ void k_import(const DevNet D, const uint32_t* slots, const VehRec* recs, int n)
 {
-    const DevNet& D = *Dp;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const long long t = *D.gstep;
@@ -1490,7 +1614,7 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     case kSched8x16: lanes = 8; cap = 16; break;
     default: break;
     }
-    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, Dd, lanes, cap);
+    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, H, lanes, cap);
     return hipGetLastError();
 }
 
@@ -1500,16 +1624,16 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
     if (H.GA > 0) {
         switch (H.sched) {
         case kSched16x32:
-            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, Dd, total);
+            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, total);
             break;
         case kSched16x64:
-            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, Dd, total);
+            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, H, total);
             break;
         case kSched32x64:
-            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, Dd, total);
+            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, total);
             break;
         case kSched8x16:
-            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, Dd, total);
+            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, total);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1517,7 +1641,7 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_update_wide<kWideWaves>), dim3(H.GB), dim3(kWideWaves * kWave), 0, s, Dd, H.GA, total);
+    hipLaunchKernelGGL((k_update_wide<kWideWaves>), dim3(H.GB), dim3(kWideWaves * kWave), 0, s, H, H.GA, total);
     return hipGetLastError();
 }
 
@@ -1547,30 +1671,36 @@ int update_blocks_per_cu(int sched)
     return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_set_phases(const DevNet* Dd, const int32_t* ids, const int32_t* ph, int n, hipStream_t s)
+hipError_t launch_set_phases(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* ph, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_phases, dim3((n + 255) / 256), dim3(256), 0, s, Dd, ids, ph, n);
+    hipLaunchKernelGGL(k_set_phases, dim3((n + 255) / 256), dim3(256), 0, s, H, ids, ph, n);
     return hipGetLastError();
 }
 
 hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_all_phases, dim3((H.NJ + 255) / 256), dim3(256), 0, s, Dd, ph);
+    hipLaunchKernelGGL(k_set_all_phases, dim3((H.NJ + 255) / 256), dim3(256), 0, s, H, ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_end, dim3(1), dim3(1), 0, s, H, inst, end);
     return hipGetLastError();
 }
 
 hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_export, dim3((H.NL + 255) / 256), dim3(256), 0, s, Dd, lane_ext, o_lane, o_x, o_v, o_rpos,
+    hipLaunchKernelGGL(k_export, dim3((H.NL + 255) / 256), dim3(256), 0, s, H, lane_ext, o_lane, o_x, o_v, o_rpos,
                        o_rank);
     return hipGetLastError();
 }
 
-hipError_t launch_import(const DevNet* Dd, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s)
+hipError_t launch_import(const DevNet* Dd, const DevNet& H, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_import, dim3((n + 255) / 256), dim3(256), 0, s, Dd, slots, recs, n);
+    hipLaunchKernelGGL(k_import, dim3((n + 255) / 256), dim3(256), 0, s, H, slots, recs, n);
     return hipGetLastError();
 }
 

@@ -193,6 +193,172 @@ class ServeLoop:
         return {"jobs": done, "wall_s": wall, "ticks": ticks, "peak_bytes": peak_used}
 
 
+class BatchFactory:
+    """Jobs grouped into batches (``tsim_batch_*``: one set of launches steps
+    every instance of a batch), each batch on one stream of a pool; each
+    instance is frozen at its own horizon."""
+
+    def __init__(self, n_streams=3, device="cuda:0", graph_steps=30):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.graph_steps = int(graph_steps)
+        self._next = 0
+        self._lock = threading.Lock()
+
+    def footprint(self, job):
+        from paper_2406_10661_amd.tsim import footprint
+        return footprint(job.network, job.trips, job.params)
+
+    def create_batch(self, jobs):
+        from paper_2406_10661_amd.tsim import Batch
+        with self._lock:
+            s = self.streams[self._next % len(self.streams)]
+            self._next += 1
+        with self.torch.cuda.stream(s):
+            b = Batch([j.network for j in jobs], [j.trips for j in jobs], [j.params for j in jobs],
+                      device=self.device, stream=s)
+            for k, j in enumerate(jobs):
+                b.set_horizon(k, j.horizon)
+            if self.graph_steps:
+                b.set_graph_steps(self.graph_steps)
+        return b, s
+
+    def done_event(self, stream):
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return ev
+
+    def sync(self):
+        self.torch.cuda.synchronize(self.device)
+
+
+class BatchedServeLoop:
+    """Continuous batching over batches of jobs: admitted jobs that are not
+    yet running are gathered into a new batch whenever fewer than
+    ``max_batches`` batches are running or being built; each batch is stepped
+    in chunks of ``steps_per_tick`` steps (at most ``depth`` chunks ahead of
+    the device) until its longest job's horizon, and each job's result is
+    read as soon as the device has passed that job's own horizon.  A job's
+    memory stays counted against the budget until its batch is released."""
+
+    def __init__(self, factory, hbm_budget, steps_per_tick=30, depth=2, max_batches=3, max_jobs_per_batch=64,
+                 builders=2, clock=time.perf_counter):
+        self.f = factory
+        self.budget = int(hbm_budget)
+        self.k = int(steps_per_tick)
+        self.depth = int(depth)
+        self.max_batches = int(max_batches)
+        self.max_jobs = int(max_jobs_per_batch)
+        self.n_builders = int(builders)
+        self.clock = clock
+
+    def run(self, jobs):
+        jobs = sorted(jobs, key=lambda j: j.arrival)
+        for j in jobs:
+            j.footprint = self.f.footprint(j)
+            if j.footprint > self.budget:
+                raise ValueError(f"job {j.jid} needs {j.footprint} bytes, more than the whole budget")
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        waiting = collections.deque(jobs)
+        admitted = collections.deque()
+        lock = threading.Lock()
+        build_q = collections.deque()
+        build_cv = threading.Condition(lock)
+        ready = collections.deque()
+        stop = [False]
+        errors = []
+        state = {"used": 0, "peak": 0, "building": 0}
+
+        def builder():
+            while True:
+                with build_cv:
+                    while not build_q and not stop[0]:
+                        build_cv.wait(0.05)
+                    if stop[0] and not build_q:
+                        return
+                    grp = build_q.popleft()
+                try:
+                    b, st = self.f.create_batch(grp)
+                except Exception as e:
+                    errors.append(e)
+                    return
+                with lock:
+                    ready.append({"batch": b, "stream": st, "jobs": grp, "steps": 0, "inflight": collections.deque(),
+                                  "done_steps": 0, "horizon": max(j.horizon for j in grp)})
+
+        threads = [threading.Thread(target=builder, daemon=True) for _ in range(self.n_builders)]
+        for th in threads:
+            th.start()
+        running = []
+        done = []
+        n_batches = 0
+        try:
+            while len(done) < len(jobs):
+                if errors:
+                    raise errors[0]
+                tnow = now()
+                with lock:
+                    while waiting and waiting[0].arrival <= tnow and state["used"] + waiting[0].footprint <= self.budget:
+                        j = waiting.popleft()
+                        state["used"] += j.footprint
+                        state["peak"] = max(state["peak"], state["used"])
+                        j.admitted = tnow
+                        admitted.append(j)
+                    if admitted and len(running) + state["building"] < self.max_batches:
+                        grp = [admitted.popleft() for _ in range(min(self.max_jobs, len(admitted)))]
+                        state["building"] += 1
+                        build_q.append(grp)
+                        build_cv.notify()
+                    while ready:
+                        rb = ready.popleft()
+                        state["building"] -= 1
+                        n_batches += 1
+                        tst = now()
+                        for j in rb["jobs"]:
+                            j.started = tst
+                        running.append(rb)
+                enqueued = 0
+                still = []
+                for rb in running:
+                    # chunks the device has finished
+                    while rb["inflight"] and rb["inflight"][0][0].query():
+                        rb["done_steps"] = rb["inflight"].popleft()[1]
+                    for j in rb["jobs"]:
+                        if j.finished < 0 and j.horizon <= rb["done_steps"]:
+                            k = rb["jobs"].index(j)
+                            j.metrics = rb["batch"].metrics(k)
+                            j.steps_done = j.horizon
+                            j.finished = now()
+                            done.append(j)
+                    if rb["steps"] < rb["horizon"] and len(rb["inflight"]) < self.depth:
+                        n = min(self.k, rb["horizon"] - rb["steps"])
+                        rb["batch"].step(n)
+                        rb["steps"] += n
+                        rb["inflight"].append((self.f.done_event(rb["stream"]), rb["steps"]))
+                        enqueued += 1
+                    if rb["done_steps"] >= rb["horizon"] and all(j.finished >= 0 for j in rb["jobs"]):
+                        rb["batch"].close()
+                        rb["batch"] = None
+                        with lock:
+                            state["used"] -= sum(j.footprint for j in rb["jobs"])
+                    else:
+                        still.append(rb)
+                running = still
+                if not enqueued:
+                    time.sleep(0.0002)
+        finally:
+            with build_cv:
+                stop[0] = True
+                build_cv.notify_all()
+            for th in threads:
+                th.join(timeout=60)
+        self.f.sync()
+        return {"jobs": done, "wall_s": now(), "batches": n_batches, "peak_bytes": state["peak"]}
+
+
 def summarize(result, skip=0):
     """p50/p99 latency, jobs/s and vehicle-steps/s over the jobs after the
     first `skip` (by arrival)."""

@@ -68,7 +68,7 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_footprint", "tsim_batch_create", "tsim_batch_step", "tsim_batch_set_signal_phases",
            "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
-           "tsim_autotune"]
+           "tsim_autotune", "tsim_batch_set_horizon"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16"}
 
@@ -94,6 +94,7 @@ def lib():
         L.tsim_set_profiling.argtypes = [P, C.c_int32]
         L.tsim_set_graph_steps.argtypes = [P, C.c_int32]
         L.tsim_set_schedule.argtypes = [P, C.c_int32]
+        L.tsim_batch_set_horizon.argtypes = [P, C.c_int32, C.c_int64]
         L.tsim_get_schedule.argtypes = [P, P]
         L.tsim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, P]
         L.tsim_batch_set_graph_steps.argtypes = [P, C.c_int32]
@@ -344,6 +345,10 @@ class Batch:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(phases, np.int32)
         _check(lib().tsim_batch_set_signal_phases(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
+
+    def set_horizon(self, instance, n_steps):
+        """Freeze instance after n_steps local steps (the others go on)."""
+        _check(lib().tsim_batch_set_horizon(self.h, int(instance), int(n_steps)), self.h)
 
     def set_all_phases(self, phases):
         """phases: one entry per junction of the batch, instance order; -1 = unchanged."""

@@ -39,3 +39,28 @@ def test_served_jobs_match_alone():
     s = SV.summarize(res)
     print("served", s, flush=True)
     assert s["latency_p99_s"] >= s["latency_p50_s"] > 0
+
+
+def test_batched_serving_jobs_match_alone():
+    """The batched serve loop (jobs sharing batches, each frozen at its own
+    horizon) gives every job the same metrics as running it alone."""
+    from paper_2406_10661_amd import serve as SV
+    from paper_2406_10661_amd.tsim import Sim
+    ws = W.served_jobs(10, workers=4, max_vehicles=12000)
+    horizons = [min(w.n_steps, 200 + 41 * k) for k, w in enumerate(ws)]
+    jobs = [SV.Job(jid=k, arrival=0.003 * k, network=w.network, trips=w.trips, params=w.params,
+                   horizon=horizons[k]) for k, w in enumerate(ws)]
+    fac = SV.BatchFactory(n_streams=2, graph_steps=30)
+    budget = 4 * max(fac.footprint(j) for j in jobs)
+    res = SV.BatchedServeLoop(fac, hbm_budget=budget, steps_per_tick=30, max_batches=2,
+                              max_jobs_per_batch=4).run(jobs)
+    assert len(res["jobs"]) == len(jobs) and res["batches"] >= 3
+    for j in res["jobs"]:
+        w = ws[j.jid]
+        sim = Sim(w.network, w.trips, w.params)
+        sim.step(j.horizon)
+        m = sim.metrics()
+        sim.close()
+        for k in KEYS:
+            assert m[k] == j.metrics[k], (j.jid, k, m[k], j.metrics[k])
+    print("batched served", SV.summarize(res), res["batches"], flush=True)

@@ -160,3 +160,68 @@ def test_summarize_percentiles():
     assert s["latency_p99_s"] == pytest.approx(float(np.percentile(lat, 99)))
     assert s["latency_p99_s"] >= s["latency_p50_s"] > 0
     assert s["jobs_per_s"] > 0
+
+
+class FakeBatch:
+    def __init__(self, fac, jobs):
+        self.fac, self.jobs = fac, jobs
+        self.steps = 0
+        self.busy_until = time.perf_counter()
+
+    def step(self, n):
+        self.steps += n
+        self.busy_until = max(self.busy_until, time.perf_counter()) + n * self.fac.sec_per_step
+
+    def metrics(self, k):
+        j = self.jobs[k]
+        # a frozen instance stops at its horizon
+        return {"vehicle_steps": 100 * min(self.steps, j.horizon), "step": min(self.steps, j.horizon)}
+
+    def close(self):
+        with self.fac.lock:
+            for j in self.jobs:
+                self.fac.resident.discard(j.jid)
+            self.fac.batches.append([j.jid for j in self.jobs])
+
+
+class FakeBatchFactory(FakeFactory):
+    def __init__(self, sec_per_step=2e-5):
+        super().__init__(sec_per_step)
+        self.batches = []
+
+    def create_batch(self, jobs):
+        b = FakeBatch(self, jobs)
+        st = FakeStream()
+        st.sim = b
+        with self.lock:
+            for j in jobs:
+                self.resident.add(j.jid)
+                self.sizes[j.jid] = j.params["bytes"]
+            cur = sum(self.sizes[j] for j in self.resident)
+            self.max_resident_bytes = max(self.max_resident_bytes, cur)
+        return b, st
+
+
+def test_batched_loop_completes_every_job_at_its_horizon():
+    fac = FakeBatchFactory()
+    jobs = make_jobs(60, seed=4, rate=800.0)
+    res = SV.BatchedServeLoop(fac, hbm_budget=3000, steps_per_tick=25, max_batches=3, max_jobs_per_batch=8).run(jobs)
+    assert len(res["jobs"]) == 60
+    for j in res["jobs"]:
+        assert j.metrics["step"] == j.horizon
+        assert j.metrics["vehicle_steps"] == 100 * j.horizon
+        assert 0 <= j.arrival <= j.admitted <= j.started <= j.finished
+    assert fac.max_resident_bytes <= 3000 and res["peak_bytes"] <= 3000
+    assert all(len(b) <= 8 for b in fac.batches)
+    assert sorted(x for b in fac.batches for x in b) == list(range(60))
+    assert not fac.resident
+
+
+def test_batched_loop_short_job_leaves_before_long_batchmate():
+    fac = FakeBatchFactory(sec_per_step=2e-4)
+    a = SV.Job(jid=0, arrival=0.0, network=None, trips=None, params={"bytes": 10}, horizon=600)
+    b = SV.Job(jid=1, arrival=0.0, network=None, trips=None, params={"bytes": 10}, horizon=30)
+    res = SV.BatchedServeLoop(fac, hbm_budget=100, steps_per_tick=30).run([a, b])
+    d = {j.jid: j for j in res["jobs"]}
+    assert fac.batches == [[0, 1]]              # one batch
+    assert d[1].finished < d[0].finished        # delivered at its own horizon
