@@ -105,7 +105,7 @@ METRIC = "vehicle-steps/s + sim Hz at 2.46M veh; batched jobs/s, p50/p99 job lat
 def roofline(alg_bytes, upd_ms, upd_n, traffic):
     achieved = alg_bytes / (upd_ms / 1e3) / 1e9 if upd_ms > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update_grouped + k_update_wide (one step)",
             "us_per_launch": upd_ms / max(upd_n, 1) * 1e3, "bytes_per_launch": alg_bytes / max(upd_n, 1)}
 
 
@@ -422,7 +422,7 @@ def main():
         "result": {"finished": m1["n_finished"], "mean_road_speed": m1["mean_speed_avg"], "att_s": m1["att"],
                    "lane_changes": m1["lane_changes"], "errors": m1["errors"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update_grouped + k_update_wide (one step)",
                      "us_per_launch": upd_ms / max(upd_n, 1) * 1e3,
                      "bytes_per_launch": alg_bytes / max(upd_n, 1)},
         "paper_context": {"hz": 84.09, "vehicles": 2464950, "hardware": "RTX 4090 + Xeon Platinum 8462Y"},
