@@ -322,6 +322,7 @@ def main():
     ap.add_argument("--tick", type=int, default=30)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=60)
+    ap.add_argument("--schedule", type=int, default=None, help="fixed update schedule (default: autotuned)")
     ap.add_argument("--serve-mode", choices=["batched", "streams"], default="batched")
     ap.add_argument("--max-batches", type=int, default=3)
     ap.add_argument("--max-jobs-per-batch", type=int, default=64)
@@ -354,9 +355,14 @@ def main():
     stream = torch.cuda.current_stream()
     # schedule: autotuned on a seeded mid-horizon state (about half the
     # vehicles on the network), outside the timed region
-    sched, us = autotune_city(sim, w, W)
-    log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step by schedule "
-        f"{[round(float(x), 1) for x in us]}")
+    if args.schedule is None:
+        sched, us = autotune_city(sim, w, W)
+        log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step by schedule "
+            f"{[round(float(x), 1) for x in us]}")
+    else:
+        sched = args.schedule
+        sim.set_schedule(sched)
+        log(f"[bench] fixed schedule {sched} ({SCHEDULES[sched]})")
     sim.set_state(init)
     if args.warmup:
         sim.step(args.warmup)

@@ -85,14 +85,14 @@ int tile_class(const Build& B, int r)
 // with few enough lanes), the wide pass over at most R; each gets no more
 // workgroups than the device keeps resident (res_a, res_b; 0 = unknown)
 struct SchedGrid {
-    int gw, nA, GA, GB;
+    int gw, nA, GA, GB, GC;
 };
 
 constexpr int kMaxGridA = 8192, kMaxGridB = 8192;
 
-SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0)
+SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, int res_c = 0)
 {
-    SchedGrid g{64, 0, 0, 0};
+    SchedGrid g{64, 0, 0, 0, 0};
     switch (sched) {
     case kSched8x16: g.gw = 8; g.nA = B.n_le[0]; break;
     case kSched16x32:
@@ -105,6 +105,8 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0)
     const int capB = res_b > 0 ? std::min(res_b, kMaxGridB) : kMaxGridB;
     g.GA = g.nA > 0 ? std::max(1, std::min((g.nA + ng - 1) / ng, capA)) : 0;
     g.GB = std::max(1, std::min(B.R, capB));
+    const int capC = res_c > 0 ? std::min(res_c, kMaxGridB) : kMaxGridB;
+    g.GC = std::max(1, std::min(B.R, capC));
     return g;
 }
 
@@ -131,7 +133,7 @@ void order_tiles(Build& B, bool by_instance)
     B.G = 1;
     for (int s = 0; s < kNumSched; ++s) {
         const SchedGrid g = sched_grid(B, s);
-        B.G = std::max(B.G, g.GA + g.GB);
+        B.G = std::max(B.G, g.GA + g.GB + g.GC);
     }
 }
 
@@ -534,7 +536,7 @@ struct tsim_handle {
     int graph_chunk = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
-    int res[kNumSched + 1] = {};        // resident update workgroups per schedule (last: wide pass)
+    int res[kNumSched + 2] = {};        // resident update workgroups per schedule, then wide and huge passes
     std::string err;
 };
 
@@ -612,7 +614,8 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.lane_wait, NL * 4);
     add(&D.list_small, std::max<size_t>(R, 1) * 4);
     add(&D.list_big, std::max<size_t>(R, 1) * 4);
-    add(&D.list_cnt, 8);
+    add(&D.list_huge, std::max<size_t>(R, 1) * 4);
+    add(&D.list_cnt, 12);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.done_ctr, 4);
     add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
@@ -822,7 +825,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 8, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 12, h->stream));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
@@ -854,10 +857,11 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
 
 static void set_sched(tsim_handle* h, int sched)
 {
-    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], h->res[kNumSched]);
+    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], h->res[kNumSched], h->res[kNumSched + 1]);
     h->D.sched = sched;
     h->D.GA = g.GA;
     h->D.GB = g.GB;
+    h->D.GC = g.GC;
 }
 
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,
@@ -944,6 +948,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
             for (int sc = 0; sc < kNumSched; ++sc) h->res[sc] = cus * update_blocks_per_cu(sc);
             h->res[kNumSched] = cus * update_blocks_per_cu(-1);
+            h->res[kNumSched + 1] = cus * update_blocks_per_cu(-2);
         }
     }
     set_sched(h, kSched16x32);

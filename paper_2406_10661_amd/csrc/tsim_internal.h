@@ -24,7 +24,9 @@ constexpr int kMaxPhases = 32;
 constexpr int kWave = 64;
 constexpr int kChangerCap = 64;      // lane changers per tile kept in LDS (wide tiles)
 constexpr int kMergeCap = 64;        // merging vehicles per tile kept in LDS (wide tiles)
-constexpr int kWideCap = 256;        // vehicles of a wide tile staged in LDS
+constexpr int kWideLanes = 32;       // lanes of a tile of the wide list
+constexpr int kWideCap = 128;        // vehicles of a tile of the wide list (staged in LDS)
+constexpr int kHugeCap = 512;        // vehicles of a huge tile staged in LDS (more: global scratch)
 constexpr int kNoGate = 0x7FFFFFFF;  // no feeder holds the lane
 constexpr int kNoFeeder = (int)0x80000000;  // no nonempty feeder
 
@@ -208,12 +210,13 @@ struct DevNet {
     int32_t* sh_nlane;               // local index of the new lane
     int32_t* sh_pref;                // stayer prefix count within the tile enumeration
     // work lists of the step's update, filled by the prepare kernel: tiles
-    // with vehicles that fit a group of the schedule, and all others
+    // with vehicles that fit a group of the schedule, wide tiles, huge tiles
     int32_t* list_small;             // [R]
-    int32_t* list_big;               // [R]
-    int32_t* list_cnt;               // [2]
+    int32_t* list_big;               // [R] tiles of at most kWideLanes lanes and kWideCap vehicles
+    int32_t* list_huge;              // [R] the rest
+    int32_t* list_cnt;               // [3]
     // schedule (host side; passed to the kernels as arguments)
-    int32_t sched, GA, GB;
+    int32_t sched, GA, GB, GC;
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)

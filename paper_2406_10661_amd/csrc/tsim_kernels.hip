@@ -10,9 +10,11 @@
 //                     list (or finish it if it has just become empty).
 //   k_update_grouped  the small list: 64 / W tiles per wavefront, a group of W
 //                     lanes per tile, tile staged in LDS.
-//   k_update_wide     the wide list: one tile per wavefront, up to kWideCap
-//                     vehicles in LDS, larger tiles on global scratch; the last
-//                     workgroup folds the step's metrics.
+//   k_update_wide     the wide list (tiles of up to kWideLanes lanes and
+//                     kWideCap vehicles) and then the huge list (all others,
+//                     up to kHugeCap vehicles in LDS, more on global scratch):
+//                     one tile per wavefront; the last workgroup folds the
+//                     step's metrics.
 // Per tile: pass 1 own leader (or two-lane lookahead), lane group, stop
 // obstacle, own IDM acceleration, merge target; pass 2 randomized MOBIL
 // (Appendix B.3), Philox draw, ballistic integration with snapshot bounds,
@@ -294,8 +296,10 @@ __global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
     // emptied since the last step gets its empty summaries here
     const int nl = D.tile_lane_begin[r + 1] - lb;
     const bool small = n > 0 && nl <= small_lanes && n <= small_cap;
+    const bool wide = n > 0 && !small && nl <= kWideLanes && n <= kWideCap;
     append_wave(D.list_small, &D.list_cnt[0], small, r);
-    append_wave(D.list_big, &D.list_cnt[1], n > 0 && !small, r);
+    append_wave(D.list_big, &D.list_cnt[1], wide, r);
+    append_wave(D.list_huge, &D.list_cnt[2], n > 0 && !small && !wide, r);
     if (n == 0 && tile_n_w[r] != 0) {
         LaneSum e;
         e.cnt = 0;
@@ -421,7 +425,7 @@ struct LdsView {
     __device__ void set_pref(int j, int v) { S.pref[j] = v; }
 };
 
-// the same storage in global per-slot scratch, for wide tiles above kWideCap
+// the same storage in global per-slot scratch, for tiles above kHugeCap
 template <class TS>
 struct GlobalView {
     TS& S;
@@ -1227,6 +1231,7 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
             *D.done_ctr = 0u;
             D.list_cnt[0] = 0;
             D.list_cnt[1] = 0;
+            D.list_cnt[2] = 0;
         }
         return;
     }
@@ -1262,6 +1267,7 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
         *D.done_ctr = 0u;
         D.list_cnt[0] = 0;
         D.list_cnt[1] = 0;
+        D.list_cnt[2] = 0;
     }
 }
 
@@ -1462,14 +1468,15 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
 }
 
 constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
+constexpr int kHugeWaves = 1;   // wavefronts per huge-pass workgroup
 
 // Wide pass: the step's wide-tile list, one tile per wavefront; up to
 // kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
 // the grouped pass's (offset a_wg).  The last workgroup folds the step.
-template <int WPB>
+template <int LANES, int CAP, int WPB, int LIST>
 __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg, int total_wg)
 {
-    using TS = TileLds<kMaxTileLanes, kWideCap, kChangerCap>;
+    using TS = TileLds<LANES, CAP, kChangerCap>;
     __shared__ TS Sw[WPB];
     __shared__ WGPartial wacc[WPB];
     __shared__ int skip;
@@ -1477,12 +1484,13 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     TS& S = Sw[w];
-    const int count = D.list_cnt[1];
+    const int count = D.list_cnt[LIST];
+    const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
     int acc_inst = -1;
     for (int k = (int)blockIdx.x * WPB + w; k < count; k += (int)gridDim.x * WPB) {
-        const Hdr h = load_hdr(D, B, D.list_big[k]);
+        const Hdr h = load_hdr(D, B, list[k]);
         const long long t = tg - D.inst_t0[h.inst];
         const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
         if (tid == 0) reset_counters(S, h);
@@ -1501,7 +1509,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
         wave_sync();
         const int n = S.n;
         load_lanes_b(D, B, S, h, tid, lr);
-        if (n <= kWideCap) {
+        if (n <= CAP) {
             for (int j = tid; j < n; j += kWave) {
                 const int li = lane_of(S, j);
                 S.vl[j] = (signed char)li;
@@ -1620,7 +1628,7 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
-    const int total = H.GA + H.GB;
+    const int total = H.GA + H.GB + H.GC;
     if (H.GA > 0) {
         switch (H.sched) {
         case kSched16x32:
@@ -1641,12 +1649,18 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_update_wide<kWideWaves>), dim3(H.GB), dim3(kWideWaves * kWave), 0, s, H, H.GA, total);
+    hipLaunchKernelGGL((k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>), dim3(H.GB), dim3(kWideWaves * kWave), 0,
+                       s, H, H.GA, total);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_update_wide<kMaxTileLanes, kHugeCap, kHugeWaves, 2>), dim3(H.GC), dim3(kHugeWaves * kWave), 0,
+                       s, H, H.GA + H.GB, total);
     return hipGetLastError();
 }
 
-// resident workgroups per compute unit of the update kernels (sched < 0:
-// the wide pass), from the compiled kernels' register and LDS use
+// resident workgroups per compute unit of the update kernels (sched -1: the
+// wide pass, -2: the huge pass), from the compiled kernels' register and LDS
+// use
 int update_blocks_per_cu(int sched)
 {
     int nb = 0;
@@ -1665,7 +1679,12 @@ int update_blocks_per_cu(int sched)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<8, 16, 8, 4>, 4 * kWave, 0);
         break;
     default:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_wide<kWideWaves>, kWideWaves * kWave, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>,
+                                                         kWideWaves * kWave, 0);
+        break;
+    case -2:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_wide<kMaxTileLanes, kHugeCap, kHugeWaves, 2>,
+                                                         kHugeWaves * kWave, 0);
         break;
     }
     return e == hipSuccess ? nb : 0;

@@ -97,6 +97,24 @@ def test_big_tiles_one_step(O, Sim, seed):
     _log(f"big_tiles_s{seed}", rep)
 
 
+def test_huge_tiles_global_scratch_one_step(O, Sim):
+    """4 km, 3-lane roads packed with vehicles: tiles above the LDS capacity
+    of the huge pass (512) run on the global per-slot scratch."""
+    rng = np.random.default_rng(300)
+    net = W.grid_network(3, spacing=4000.0, length=4000.0, lanes=3)
+    o, d = W.uniform_od(net, rng, 20000)
+    trips = W._finish_trips(net, rng, o, d, rng.uniform(0, 30, 20000))
+    params = W.Params(seed=1)
+    st = synthetic_state(net, trips, 40, seed=3, p_active=0.97, min_gap=0.2)
+    lanes = st["lane"][st["status"] == 1]
+    rol = net.road_of_lane()
+    per_road = np.bincount(rol[lanes[lanes < net.n_road_lanes]], minlength=net.n_roads)
+    assert (per_road > 512).sum() >= 5
+    rep = compare_one_step(O, Sim, net, trips, params, st)
+    rep["max_tile"] = int(per_road.max())
+    _log("huge_tiles", rep)
+
+
 def test_manual_signals_one_step(O, Sim):
     w = W.config1()
     st = synthetic_state(w.network, w.trips, 77, seed=5, p_active=0.5)
