@@ -169,7 +169,9 @@ __global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const KParams& P = D.P;
 
-    if (i < D.NJ && tg - D.inst_t0[D.junc_inst[i]] < D.inst_end[D.junc_inst[i]]) {
+    // threads [0, NJ): junction signals; threads [NJ, NJ + R): roads
+    if (i < D.NJ) {
+        if (!(tg - D.inst_t0[D.junc_inst[i]] < D.inst_end[D.junc_inst[i]])) return;
         const long long t = tg - D.inst_t0[D.junc_inst[i]];
         const int b = D.junc_phase_begin[i], e = D.junc_phase_begin[i + 1];
         int cur = -1;
@@ -192,9 +194,10 @@ __global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
             }
         }
         D.junc_cur[i] = cur;
+        return;
     }
-    if (i >= D.R) return;
-    const int r = i;
+    if (i >= D.NJ + D.R) return;
+    const int r = i - D.NJ;
     const int inst = D.tile_inst[r];
     const long long t = tg - D.inst_t0[inst];
     // an instance past its horizon is frozen: none of its tiles is listed
@@ -1182,25 +1185,28 @@ __device__ __forceinline__ void flush_acc(const DevNet& D, WGPartial& acc, int i
     acc = WGPartial{};
 }
 
-// per-workgroup partials; the workgroup that finishes last folds the step
-// with its first wavefront (called by every thread of the workgroup; acc
-// valid in thread 0)
-__device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc, int slot, int total_wg, int* skip)
+// per-workgroup partial of the step (acc valid in thread 0); the fold kernel
+// that follows the update passes sums them (the kernel boundary makes these
+// plain stores visible, so no fence or counter is needed here)
+__device__ __forceinline__ void finish_step(const DevNet& D, const WGPartial& acc, int slot)
 {
+    if (threadIdx.x == 0) D.part[slot] = acc;
+}
+
+// folds the step: sums the update workgroups' partials (or, for batches, the
+// per-instance sums), updates the metrics, clears the work lists and
+// advances the global step.  One workgroup of kFoldThreads threads.
+constexpr int kFoldThreads = 256;
+
+__global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total_wg)
+{
+    __shared__ long long red[kFoldThreads / kWave][10];
+    const long long tg = *D.gstep;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        D.part[slot] = acc;
-        __threadfence();
-        const unsigned int old = atomicAdd(D.done_ctr, 1u);
-        *skip = (old == (unsigned)total_wg - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!*skip || tid >= kWave) return;
-    __threadfence();
     if (D.n_inst > 1) {
-        for (int i = tid; i < D.n_inst; i += kWave) {
+        for (int i = tid; i < D.n_inst; i += kFoldThreads) {
             if (tg - D.inst_t0[i] >= D.inst_end[i]) continue;   // frozen instance
-            volatile long long* q = (volatile long long*)&D.inst_acc[i];
+            long long* q = (long long*)&D.inst_acc[i];
             long long a[10];
 #pragma unroll
             for (int k = 0; k < 10; ++k) {
@@ -1225,63 +1231,64 @@ __device__ void finish_step(const DevNet& D, long long tg, const WGPartial& acc,
             }
             M->step = tg - D.inst_t0[i] + 1;
         }
-        wave_sync();
+    } else {
+        long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int g = tid; g < total_wg; g += kFoldThreads) {
+            const long long* q = (const long long*)&D.part[g];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) a[k] += q[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
+        }
+        if (tid % kWave == 0) {
+#pragma unroll
+            for (int k = 0; k < 10; ++k) red[tid / kWave][k] = a[k];
+        }
+        __syncthreads();
         if (tid == 0) {
-            *D.gstep = tg + 1;
-            *D.done_ctr = 0u;
-            D.list_cnt[0] = 0;
-            D.list_cnt[1] = 0;
-            D.list_cnt[2] = 0;
+            for (int w = 1; w < kFoldThreads / kWave; ++w)
+                for (int k = 0; k < 10; ++k) a[k] += red[w][k];
+            DevMetrics* M = D.met;
+            M->vehicle_steps += a[2];
+            M->lane_changes += a[3];
+            M->transfers += a[4];
+            M->clamps += a[5];
+            M->feeder_blocks += a[6];
+            M->finished += a[7];
+            M->sum_tt_fx += a[8];
+            M->errors += a[9];
+            if (a[1] > 0) {
+                M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
+                M->speed_acc += M->mean_speed_last;
+                M->speed_steps += 1;
+            } else {
+                M->mean_speed_last = 0.0;
+            }
+            M->step = tg - D.inst_t0[0] + 1;
         }
-        return;
     }
-    long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int g = tid; g < total_wg; g += kWave) {
-        const volatile long long* q = (const volatile long long*)&D.part[g];
-#pragma unroll
-        for (int k = 0; k < 10; ++k) a[k] += q[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
-    }
+    __syncthreads();
     if (tid == 0) {
-        DevMetrics* M = D.met;
-        M->vehicle_steps += a[2];
-        M->lane_changes += a[3];
-        M->transfers += a[4];
-        M->clamps += a[5];
-        M->feeder_blocks += a[6];
-        M->finished += a[7];
-        M->sum_tt_fx += a[8];
-        M->errors += a[9];
-        if (a[1] > 0) {
-            M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
-            M->speed_acc += M->mean_speed_last;
-            M->speed_steps += 1;
-        } else {
-            M->mean_speed_last = 0.0;
-        }
-        M->step = tg - D.inst_t0[0] + 1;
         *D.gstep = tg + 1;
-        *D.done_ctr = 0u;
         D.list_cnt[0] = 0;
         D.list_cnt[1] = 0;
         D.list_cnt[2] = 0;
     }
 }
 
+
 // Grouped pass: the step's small-tile list (tiles of at most GW lanes and
 // CAP vehicles, built by the prepare kernel), 64 / GW tiles per wavefront,
 // one group of GW lanes per tile; the grid strides over the list.
 template <int GW, int CAP, int CHG, int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, int total_wg)
+__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
 {
     constexpr int NG = kWave / GW;
     using TS = TileLds<GW, CAP, CHG>;
     __shared__ TS Sg[WPB * NG];
     __shared__ WGPartial gacc[WPB * NG];
-    __shared__ int skip;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
     // the WPB wavefronts of a workgroup work independently (each its own
@@ -1464,7 +1471,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
             for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tg, tot, (int)blockIdx.x, total_wg, &skip);
+    finish_step(D, tot, (int)blockIdx.x);
 }
 
 constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
@@ -1474,12 +1481,11 @@ constexpr int kHugeWaves = 1;   // wavefronts per huge-pass workgroup
 // kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
 // the grouped pass's (offset a_wg).  The last workgroup folds the step.
 template <int LANES, int CAP, int WPB, int LIST>
-__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg, int total_wg)
+__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg)
 {
     using TS = TileLds<LANES, CAP, kChangerCap>;
     __shared__ TS Sw[WPB];
     __shared__ WGPartial wacc[WPB];
-    __shared__ int skip;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
@@ -1542,7 +1548,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
             for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tg, tot, a_wg + (int)blockIdx.x, total_wg, &skip);
+    finish_step(D, tot, a_wg + (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1613,7 +1619,7 @@ __global__ void k_import(const DevNet D, const uint32_t* slots, const VehRec* re
 // launch wrappers (host side); Dd is the device copy of the view, H the host copy
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
-    const int n = H.R > H.NJ ? H.R : H.NJ;
+    const int n = H.R + H.NJ;
     int lanes = 0, cap = 0;
     switch (H.sched) {
     case kSched16x32: lanes = 16; cap = 32; break;
@@ -1632,16 +1638,16 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
     if (H.GA > 0) {
         switch (H.sched) {
         case kSched16x32:
-            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, total);
+            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H);
             break;
         case kSched16x64:
-            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, H, total);
+            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, H);
             break;
         case kSched32x64:
-            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, total);
+            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H);
             break;
         case kSched8x16:
-            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, total);
+            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1650,11 +1656,14 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>), dim3(H.GB), dim3(kWideWaves * kWave), 0,
-                       s, H, H.GA, total);
+                       s, H, H.GA);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_update_wide<kMaxTileLanes, kHugeCap, kHugeWaves, 2>), dim3(H.GC), dim3(kHugeWaves * kWave), 0,
-                       s, H, H.GA + H.GB, total);
+                       s, H, H.GA + H.GB);
+    const hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H, total);
     return hipGetLastError();
 }
 
