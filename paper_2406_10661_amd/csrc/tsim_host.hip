@@ -47,6 +47,7 @@ struct Build {
     std::vector<double> junc_cycle;
     std::vector<float> tau, vf, vlen;
     std::vector<int32_t> route_begin, route, q_begin, q_veh;
+    std::vector<uint32_t> q_mask;    // per queue entry: origin-road lanes that lead to its next road
     uint64_t slots = 0;
     int G = 0;                       // partial slots: max over schedules of GA + GB
     // tile classes by lane count (<= 8, <= 16, <= 32, more), class-major in
@@ -96,6 +97,7 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
     switch (sched) {
     case kSched8x16: g.gw = 8; g.nA = B.n_le[0]; break;
     case kSched16x32:
+    case kSched16x32P:
     case kSched16x64: g.gw = 16; g.nA = B.n_le[1]; break;
     case kSched32x64: g.gw = 32; g.nA = B.n_le[2]; break;
     default: g.gw = 64; g.nA = 0; break;
@@ -348,6 +350,23 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
             std::sort(B.q_veh.begin() + B.q_begin[r], B.q_veh.begin() + B.q_begin[r + 1], [&](int a, int b) {
                 return B.tau[a] < B.tau[b] || (B.tau[a] == B.tau[b] && a < b);
             });
+        B.q_mask.assign(N, 0u);
+        for (int r = 0; r < R; ++r) {
+            const int lb = B.tile_lane_begin[r], nrl = B.tile_n_road[r];
+            for (int k = B.q_begin[r]; k < B.q_begin[r + 1]; ++k) {
+                const int v = B.q_veh[k];
+                const int rb = B.route_begin[v];
+                const int nr = B.route_begin[v + 1] - rb > 1 ? B.route[rb + 1] : -1;
+                uint32_t m = 0u;
+                for (int li = 0; li < nrl; ++li) {
+                    bool ok = nr < 0;
+                    for (int e = B.out_begin[lb + li]; e < B.out_begin[lb + li + 1] && !ok; ++e)
+                        ok = B.jl_out_road[B.out_jl[e]] == nr;
+                    if (ok) m |= 1u << li;
+                }
+                B.q_mask[k] = m;
+            }
+        }
     }
     B.tile_order.resize(R);
     std::iota(B.tile_order.begin(), B.tile_order.end(), 0);
@@ -536,7 +555,7 @@ struct tsim_handle {
     int graph_chunk = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
-    int res[kNumSched + 2] = {};        // resident update workgroups per schedule, then wide and huge passes
+    int res[kNumSched + 3] = {};        // resident workgroups: grouped pass per schedule, wide, huge, pipelined wide
     std::string err;
 };
 
@@ -590,6 +609,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.q_begin, (R + 1) * 4);
     add(&D.q_veh, std::max<size_t>(N, 1) * 4);
     add(&D.q_tau, std::max<size_t>(N, 1) * 4);
+    add(&D.q_mask, std::max<size_t>(N, 1) * 4);
     add(&D.q_head, R * 4);
     add(&D.slab0, S * sizeof(VehRec));
     add(&D.slab1, S * sizeof(VehRec));
@@ -857,7 +877,8 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
 
 static void set_sched(tsim_handle* h, int sched)
 {
-    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], h->res[kNumSched], h->res[kNumSched + 1]);
+    const int res_b = sched == kSched16x32P ? h->res[kNumSched + 2] : h->res[kNumSched];
+    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], res_b, h->res[kNumSched + 1]);
     h->D.sched = sched;
     h->D.GA = g.GA;
     h->D.GB = g.GB;
@@ -949,6 +970,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
             for (int sc = 0; sc < kNumSched; ++sc) h->res[sc] = cus * update_blocks_per_cu(sc);
             h->res[kNumSched] = cus * update_blocks_per_cu(-1);
             h->res[kNumSched + 1] = cus * update_blocks_per_cu(-2);
+            h->res[kNumSched + 2] = cus * update_blocks_per_cu(-3);
         }
     }
     set_sched(h, kSched16x32);
@@ -1016,6 +1038,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
         std::vector<float> qt(B.q_veh.size());
         for (size_t k = 0; k < qt.size(); ++k) qt[k] = B.tau[B.q_veh[k]];
         e = e ? e : chk(up(h, (float*)D.q_tau, qt), "queues");
+        e = e ? e : chk(up(h, (uint32_t*)D.q_mask, B.q_mask), "queues");
     }
     e = e ? e : chk(up(h, h->d_lane_ext, B.ext_of_int), "lanes");
     e = e ? e : chk(up(h, (int32_t*)D.tile_inst, B.tile_inst), "instances");

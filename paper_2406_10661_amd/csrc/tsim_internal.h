@@ -34,7 +34,15 @@ constexpr int kNoFeeder = (int)0x80000000;  // no nonempty feeder
 // `width` lanes that holds at most `cap` vehicles goes to a group of `width`
 // lanes of a wavefront (64 / width tiles per wavefront); other tiles run one
 // per wavefront in the wide pass.
-enum Schedule { kSchedWide = 0, kSched16x32 = 1, kSched16x64 = 2, kSched32x64 = 3, kSched8x16 = 4, kNumSched = 5 };
+enum Schedule {
+    kSchedWide = 0,
+    kSched16x32 = 1,
+    kSched16x64 = 2,
+    kSched32x64 = 3,
+    kSched8x16 = 4,
+    kSched16x32P = 5,   // as 16x32, with the wide pass software-pipelined like the grouped one
+    kNumSched = 6
+};
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
 constexpr int kWaitSpeedFlag = 0;
@@ -187,6 +195,7 @@ struct DevNet {
     const int32_t* q_begin;          // [R+1] departure queue of each origin road
     const int32_t* q_veh;
     const float* q_tau;              // departure time of each queue entry
+    const uint32_t* q_mask;          // origin-road lanes (bits) leading to the entry's next road
     int32_t* q_head;
     // slabs
     VehRec* slab0;

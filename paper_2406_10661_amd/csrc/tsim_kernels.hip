@@ -41,6 +41,15 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// a tile worked on by GW threads: one wavefront (or a part of one) needs only
+// the wavefront fence, a whole workgroup needs its barrier
+template <int GW>
+__device__ __forceinline__ void tile_sync()
+{
+    if constexpr (GW > 64) __syncthreads();
+    else wave_sync();
+}
+
 struct Lead {
     float rear;  // rear bumper in the follower's lane coordinate
     float v;
@@ -157,16 +166,24 @@ __device__ __forceinline__ void append_wave(int32_t* list, int32_t* cnt, bool pr
 // ---------------------------------------------------------------------------
 // prepare
 // ---------------------------------------------------------------------------
-__global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
+// what one prepare thread hands to its workgroup
+struct PrepOut {
+    int r = -1;          // road
+    int list = -1;       // work list of its tile (0 small, 1 wide, 2 huge), -1 none
+    int inst = 0;
+    int departed = 0;
+    int errors = 0;
+};
+
+__device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i, int small_lanes, int small_cap,
+                                            PrepOut& out)
 {
-    const long long tg = *D.gstep;
     const int p = (int)(tg & 1);
     VehRec* slab = p ? D.slab1 : D.slab0;
     LaneSum* sum = p ? D.sum1 : D.sum0;
     int32_t* tile_n = p ? D.tile_n1 : D.tile_n0;
     int32_t* tile_n_w = p ? D.tile_n0 : D.tile_n1;
     LaneSum* wsum = p ? D.sum0 : D.sum1;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const KParams& P = D.P;
 
     // threads [0, NJ): junction signals; threads [NJ, NJ + R): roads
@@ -252,10 +269,10 @@ __global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
         const float Lv = D.vlen[v];
         int best = -1;
         float best_room = -TS_INF;
+        const uint32_t lanes_ok = D.q_mask[head] & ~used;
         for (int li = 0; li < nrl; ++li) {
-            if (used & (1u << li)) continue;
+            if (!((lanes_ok >> li) & 1u)) continue;
             const int m = lb + li;
-            if (nr >= 0 && out_toward(D, m, nr) < 0) continue;
             // no nonempty feeder may reach past the entrant's rear (x = 0)
             const LaneSum s = sum[m];
             if (s.fmax != kNoFeeder && !(-Lv - o2f(s.fmax) >= 0.0f)) continue;
@@ -298,11 +315,15 @@ __global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
     // the update kernels' work lists: tiles with vehicles, by size; a tile
     // emptied since the last step gets its empty summaries here
     const int nl = D.tile_lane_begin[r + 1] - lb;
-    const bool small = n > 0 && nl <= small_lanes && n <= small_cap;
-    const bool wide = n > 0 && !small && nl <= kWideLanes && n <= kWideCap;
-    append_wave(D.list_small, &D.list_cnt[0], small, r);
-    append_wave(D.list_big, &D.list_cnt[1], wide, r);
-    append_wave(D.list_huge, &D.list_cnt[2], n > 0 && !small && !wide, r);
+    out.r = r;
+    out.inst = inst;
+    out.departed = departed;
+    out.errors = (int)errors;
+    if (n > 0) {
+        if (nl <= small_lanes && n <= small_cap) out.list = 0;
+        else if (nl <= kWideLanes && n <= kWideCap) out.list = 1;
+        else out.list = 2;
+    }
     if (n == 0 && tile_n_w[r] != 0) {
         LaneSum e;
         e.cnt = 0;
@@ -316,11 +337,75 @@ __global__ void k_prepare(const DevNet D, int small_lanes, int small_cap)
         D.road_speed[r] = -1.0f;
         tile_n_w[r] = 0;
     }
-    if (departed) {
-        atomicAdd((unsigned long long*)&D.met[inst].departed, (unsigned long long)departed);
-        atomicAdd((unsigned long long*)&D.met[inst].dep_events, (unsigned long long)departed);
+}
+
+constexpr int kPrepThreads = 512;
+
+// Work lists and departure counts are combined per workgroup before they
+// touch the shared counters: one atomic per list (and per metric) per
+// workgroup instead of one per road or wavefront.
+__global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int small_lanes, int small_cap)
+{
+    constexpr int NW = kPrepThreads / kWave;
+    __shared__ int wcnt[3][NW];
+    __shared__ int base[3];
+    __shared__ long long bsum[2][NW];
+    const long long tg = *D.gstep;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    PrepOut o;
+    prepare_one(D, tg, i, small_lanes, small_cap, o);
+    const int wv = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+    unsigned long long m[3];
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        m[L] = __ballot(o.list == L);
+        if (lane == 0) wcnt[L][wv] = __popcll(m[L]);
     }
-    if (errors) atomicAdd((unsigned long long*)&D.met[inst].errors, (unsigned long long)errors);
+    const bool one = D.n_inst == 1;
+    long long dep = one ? o.departed : 0, err = one ? o.errors : 0;
+    for (int off = 32; off > 0; off >>= 1) {
+        dep += __shfl_down(dep, off);
+        err += __shfl_down(err, off);
+    }
+    if (lane == 0) {
+        bsum[0][wv] = dep;
+        bsum[1][wv] = err;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int L = threadIdx.x;
+        int tot = 0;
+        for (int w = 0; w < NW; ++w) tot += wcnt[L][w];
+        base[L] = tot ? atomicAdd(&D.list_cnt[L], tot) : 0;
+    } else if (threadIdx.x == 3 && one) {
+        long long d = 0, e = 0;
+        for (int w = 0; w < NW; ++w) {
+            d += bsum[0][w];
+            e += bsum[1][w];
+        }
+        if (d) {
+            atomicAdd((unsigned long long*)&D.met[0].departed, (unsigned long long)d);
+            atomicAdd((unsigned long long*)&D.met[0].dep_events, (unsigned long long)d);
+        }
+        if (e) atomicAdd((unsigned long long*)&D.met[0].errors, (unsigned long long)e);
+    }
+    __syncthreads();
+    if (o.list >= 0) {
+        const int L = o.list;
+        int off = base[L];
+        for (int w = 0; w < wv; ++w) off += wcnt[L][w];
+        off += __popcll(m[L] & ((1ull << lane) - 1ull));
+        int32_t* list = L == 0 ? D.list_small : (L == 1 ? D.list_big : D.list_huge);
+        list[off] = o.r;
+    }
+    if (!one && o.r >= 0) {
+        // batches: per-instance counts
+        if (o.departed) {
+            atomicAdd((unsigned long long*)&D.met[o.inst].departed, (unsigned long long)o.departed);
+            atomicAdd((unsigned long long*)&D.met[o.inst].dep_events, (unsigned long long)o.departed);
+        }
+        if (o.errors) atomicAdd((unsigned long long*)&D.met[o.inst].errors, (unsigned long long)o.errors);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -355,6 +440,7 @@ struct TileLds {
     int nstay[LANES];
     int nin[LANES];
     int nenter[LANES];
+    int mcnt[LANES];       // vehicles whose merge target is this lane
     int wait[LANES];
     int nlanes, nroad, n;
     int nchg, nmerge;
@@ -640,6 +726,7 @@ __device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs
     S.nstay[gt] = 0;
     S.nin[gt] = 0;
     S.nenter[gt] = 0;
+    S.mcnt[gt] = 0;
     S.wait[gt] = 0;
     S.jl_out[gt] = L.jl_out;
     S.jl_out_road[gt] = L.jl_out_road;
@@ -741,6 +828,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         }
         view.set1(j, gmask, a, mt, ld.ex ? ld.rear : TS_INF, ld.v, stop, jqp);
         if (mt >= 0) {
+            atomicAdd(&S.mcnt[mt], 1);
             const int k = atomicAdd(&S.nmerge, 1);
             if (k < TS::kChg) {
                 S.mrg_tgt[k] = mt;
@@ -750,7 +838,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             }
         }
     }
-    wave_sync();
+    tile_sync<GW>();
 
     // ---------------- pass 2: decision and motion ----------------
     for (int j = gt; j < n; j += GW) {
@@ -892,7 +980,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         // cooperative yielding of lane keepers to vehicles merging into their lane
         bool has_y = false;
         float y_rear = TS_INF, y_v = 0.0f;
-        if (!is_jl && !dec) {
+        if (!is_jl && !dec && S.mcnt[li] > 0) {
             int y_vid = 0x7FFFFFFF;
             const int nm = S.nmerge;
             if (nm <= TS::kChg) {
@@ -1041,7 +1129,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             if (atomicAdd(&S.nenter[tgt_local], 1) != 0) atomicAdd(&S.errors, 1);
         }
     }
-    wave_sync();
+    tile_sync<GW>();
 }
 
 // pass 3 of one tile: new per-lane order, records and summaries written
@@ -1050,7 +1138,29 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
 {
     const KParams& P = D.P;
     const int nroad = S.nroad;
-    {
+    if constexpr (GW > kWave) {
+        // several wavefronts on one tile: wavefront ballots plus a prefix
+        // over the wavefronts through LDS (n is the same for the workgroup)
+        __shared__ int wc[GW / kWave];
+        int carry = 0;
+        const int wv = gt / kWave, ln = gt % kWave;
+        for (int b0 = 0; b0 < n; b0 += GW) {
+            const int j = b0 + gt;
+            const bool st = j < n && view.kind(j) == 0;
+            const unsigned long long bal = __ballot(st);
+            if (ln == 0) wc[wv] = __popcll(bal);
+            __syncthreads();
+            int pw = 0, tot = 0;
+            for (int q = 0; q < GW / kWave; ++q) {
+                const int c = wc[q];
+                if (q < wv) pw += c;
+                tot += c;
+            }
+            if (j < n) view.set_pref(j, carry + pw + __popcll(bal & ((1ull << ln) - 1ull)));
+            carry += tot;
+            __syncthreads();
+        }
+    } else {
         int carry = 0;
         for (int b0 = 0; b0 < n; b0 += GW) {
             const int j = b0 + gt;
@@ -1063,7 +1173,7 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
             carry += __popcll(mine);
         }
     }
-    wave_sync();
+    tile_sync<GW>();
     const int nchg = S.nchg;
     for (int j = gt; j < n; j += GW) {
         const int kind = view.kind(j);
@@ -1084,7 +1194,7 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
         } else {
             rank = S.nstay[nli];
         }
-        if (kind <= 1) {
+        if (kind <= 1 && S.nin[nli] > (kind == 1 ? 1 : 0)) {
             // changers into the same lane ahead of this vehicle
             if (nchg <= TS::kChg) {
                 for (int q = 0; q < nchg; ++q)
@@ -1282,11 +1392,12 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
 // Grouped pass: the step's small-tile list (tiles of at most GW lanes and
 // CAP vehicles, built by the prepare kernel), 64 / GW tiles per wavefront,
 // one group of GW lanes per tile; the grid strides over the list.
-template <int GW, int CAP, int CHG, int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
+template <int GW, int CAP, int CHG, int WPB, int LANES = GW, int LIST = 0>
+__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, int a_wg)
 {
     constexpr int NG = kWave / GW;
-    using TS = TileLds<GW, CAP, CHG>;
+    static_assert(LANES <= GW, "a group covers the lanes of its tile");
+    using TS = TileLds<LANES, CAP, CHG>;
     __shared__ TS Sg[WPB * NG];
     __shared__ WGPartial gacc[WPB * NG];
     const long long tg = *D.gstep;
@@ -1296,7 +1407,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
     TS& S = Sg[w * NG + g];
-    const int count = D.list_cnt[0];
+    const int count = D.list_cnt[LIST];
+    const int32_t* const list = LIST == 0 ? D.list_small : D.list_big;
     const int first = ((int)blockIdx.x * WPB + w) * NG;
     const int stride = (int)gridDim.x * WPB * NG;
     const int rounds = count > first ? (count - first + stride - 1) / stride : 0;
@@ -1316,7 +1428,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
     uint32_t* const pbs = pbs_all[w * NG + g];
     LaneInfo pL{};
     int pcnt = 0, pfmx = kNoFeeder, pcur = -1, pn = 0;
-    LaneSum po{};
+    int4 poa{}, pob{};   // out-lane summary of the next tile's junction lane gt (LaneSum as two vectors)
     // records as pairs of 16-byte vectors (register-friendly)
     int4 r0a{}, r0b{}, r1a{}, r1b{}, r2a{}, r2b{}, r3a{}, r3b{};
 
@@ -1376,7 +1488,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
             TSIM_PF_LOAD(3, r3a, r3b);                                         \
         }                                                                      \
         if ((H).r >= 0 && gt < (H).nl && gt >= (H).nroad) {                    \
-            po = B.rsum[pL.jl_out];                                            \
+            poa = ((const int4*)(B.rsum + pL.jl_out))[0];                      \
+            pob = ((const int4*)(B.rsum + pL.jl_out))[1];                      \
             pcur = D.junc_cur[pL.jl_junc];                                     \
         }                                                                      \
     } while (0)
@@ -1386,8 +1499,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
         return (round < rounds && ps < count) ? ps : -1;
     };
 
-    Hdr cur = load_hdr(D, B, pos_of(0) >= 0 ? D.list_small[pos_of(0)] : -1);
-    int rn = pos_of(1) >= 0 ? D.list_small[pos_of(1)] : -1;
+    Hdr cur = load_hdr(D, B, pos_of(0) >= 0 ? list[pos_of(0)] : -1);
+    int rn = pos_of(1) >= 0 ? list[pos_of(1)] : -1;
     TSIM_PF_LANES(cur);
     TSIM_PF_REST(cur);
     for (int round = 0; round < rounds; ++round) {
@@ -1404,6 +1517,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
             S.nstay[gt] = 0;
             S.nin[gt] = 0;
             S.nenter[gt] = 0;
+            S.mcnt[gt] = 0;
             S.wait[gt] = 0;
             S.jl_out[gt] = pL.jl_out;
             S.jl_out_road[gt] = pL.jl_out_road;
@@ -1412,12 +1526,13 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
             S.fmx[gt] = pfmx;
             if (gt >= h.nroad) {
                 S.green[gt] = (pcur < 0 || ((pL.green_mask >> pcur) & 1u)) ? 1 : 0;
-                S.osum[gt] = po;
+                ((int4*)&S.osum[gt])[0] = poa;
+                ((int4*)&S.osum[gt])[1] = pob;
             } else {
                 S.green[gt] = 1;
             }
         }
-        S.start[gt + 1] = pst[gt + 1];
+        if (gt < LANES) S.start[gt + 1] = pst[gt + 1];
         if (gt == 0) {
             S.start[0] = 0;
             reset_counters(S, h);
@@ -1436,7 +1551,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
         if (S.n > CAP && gt == 0) atomicAdd((unsigned long long*)&D.met[h.inst].errors, 1ull);
         // next tile: header and lane tables now, the rest after pass 2
         const Hdr hn = load_hdr(D, B, rn);
-        const int rn2 = pos_of(round + 2) >= 0 ? D.list_small[pos_of(round + 2)] : -1;
+        const int rn2 = pos_of(round + 2) >= 0 ? list[pos_of(round + 2)] : -1;
         TSIM_PF_LANES(hn);
         LdsView<TS> view{S};
         process_pass12<GW>(D, S, view, B, t, h.inst, gt, n);
@@ -1471,11 +1586,10 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D)
             for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tot, (int)blockIdx.x);
+    finish_step(D, tot, a_wg + (int)blockIdx.x);
 }
 
 constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
-constexpr int kHugeWaves = 1;   // wavefronts per huge-pass workgroup
 
 // Wide pass: the step's wide-tile list, one tile per wavefront; up to
 // kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
@@ -1551,6 +1665,71 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
     finish_step(D, tot, a_wg + (int)blockIdx.x);
 }
 
+constexpr int kHugeThreads = 256;   // threads working together on one huge tile
+
+// Huge pass: the step's huge list, one tile per workgroup of TPB threads
+// (several wavefronts per tile, barrier-separated passes); up to CAP vehicles
+// staged in LDS, more on global per-slot scratch.
+template <int LANES, int CAP, int TPB, int LIST>
+__global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
+{
+    static_assert(LANES <= kWave, "lane scan by the first wavefront");
+    using TS = TileLds<LANES, CAP, kChangerCap>;
+    __shared__ TS S;
+    const long long tg = *D.gstep;
+    const StepBufs B = step_bufs(D, tg);
+    const int tid = (int)threadIdx.x;
+    const int count = D.list_cnt[LIST];
+    const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
+
+    WGPartial acc{};
+    int acc_inst = -1;
+    for (int k = (int)blockIdx.x; k < count; k += (int)gridDim.x) {
+        const Hdr h = load_hdr(D, B, list[k]);
+        const long long t = tg - D.inst_t0[h.inst];
+        const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
+        if (tid == 0) reset_counters(S, h);
+        __syncthreads();
+        if (tid < kWave) {
+            int c = tid < h.nl ? S.cnt[tid] : 0;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int y = __shfl_up(c, off);
+                if (tid >= off) c += y;
+            }
+            if (tid < h.nl) S.start[tid + 1] = c;
+            if (tid == 0) S.start[0] = 0;
+            if (tid == kWave - 1) S.n = c;
+        }
+        __syncthreads();
+        const int n = S.n;
+        load_lanes_b(D, B, S, h, tid, lr);
+        if (n <= CAP) {
+            for (int j = tid; j < n; j += TPB) {
+                const int li = lane_of(S, j);
+                S.vl[j] = (signed char)li;
+                S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
+            }
+            __syncthreads();
+            LdsView<TS> view{S};
+            process_tile<TPB>(D, S, view, B, t, h.inst, tid, 0, n);
+        } else {
+            __syncthreads();
+            GlobalView<TS> view{S, D, B.rd};
+            process_tile<TPB>(D, S, view, B, t, h.inst, tid, 0, n);
+        }
+        __syncthreads();
+        if (tid == 0 && D.n_inst > 1 && h.inst != acc_inst) {
+            flush_acc(D, acc, acc_inst);
+            acc_inst = h.inst;
+        }
+        finish_tile(D, B, S, h, tid, n, acc);
+        __syncthreads();
+    }
+    if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
+    finish_step(D, acc, a_wg + (int)blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // host-driven helpers
 // ---------------------------------------------------------------------------
@@ -1622,13 +1801,14 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     const int n = H.R + H.NJ;
     int lanes = 0, cap = 0;
     switch (H.sched) {
-    case kSched16x32: lanes = 16; cap = 32; break;
+    case kSched16x32:
+    case kSched16x32P: lanes = 16; cap = 32; break;
     case kSched16x64: lanes = 16; cap = 64; break;
     case kSched32x64: lanes = 32; cap = 64; break;
     case kSched8x16: lanes = 8; cap = 16; break;
     default: break;
     }
-    hipLaunchKernelGGL(k_prepare, dim3((n + 255) / 256), dim3(256), 0, s, H, lanes, cap);
+    hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap);
     return hipGetLastError();
 }
 
@@ -1638,16 +1818,17 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
     if (H.GA > 0) {
         switch (H.sched) {
         case kSched16x32:
-            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H);
+        case kSched16x32P:
+            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
             break;
         case kSched16x64:
-            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, H);
+            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, H, 0);
             break;
         case kSched32x64:
-            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H);
+            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
             break;
         case kSched8x16:
-            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H);
+            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1655,11 +1836,15 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>), dim3(H.GB), dim3(kWideWaves * kWave), 0,
-                       s, H, H.GA);
+    if (H.sched == kSched16x32P)
+        hipLaunchKernelGGL((k_update_grouped<kWave, kWideCap, kChangerCap, kWideWaves, kWideLanes, 1>), dim3(H.GB),
+                           dim3(kWideWaves * kWave), 0, s, H, H.GA);
+    else
+        hipLaunchKernelGGL((k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>), dim3(H.GB), dim3(kWideWaves * kWave), 0,
+                           s, H, H.GA);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_update_wide<kMaxTileLanes, kHugeCap, kHugeWaves, 2>), dim3(H.GC), dim3(kHugeWaves * kWave), 0,
+    hipLaunchKernelGGL((k_update_block<kMaxTileLanes, kHugeCap, kHugeThreads, 2>), dim3(H.GC), dim3(kHugeThreads), 0,
                        s, H, H.GA + H.GB);
     const hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
@@ -1668,15 +1853,20 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
 }
 
 // resident workgroups per compute unit of the update kernels (sched -1: the
-// wide pass, -2: the huge pass), from the compiled kernels' register and LDS
-// use
+// wide pass, -2: the huge pass, -3: the software-pipelined wide pass), from
+// the compiled kernels' register and LDS use
 int update_blocks_per_cu(int sched)
 {
     int nb = 0;
     hipError_t e = hipSuccess;
     switch (sched) {
     case kSched16x32:
+    case kSched16x32P:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<16, 32, 16, 4>, 4 * kWave, 0);
+        break;
+    case -3:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_update_grouped<kWave, kWideCap, kChangerCap, kWideWaves, kWideLanes, 1>, kWideWaves * kWave, 0);
         break;
     case kSched16x64:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<16, 64, 32, 2>, 2 * kWave, 0);
@@ -1692,8 +1882,8 @@ int update_blocks_per_cu(int sched)
                                                          kWideWaves * kWave, 0);
         break;
     case -2:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_wide<kMaxTileLanes, kHugeCap, kHugeWaves, 2>,
-                                                         kHugeWaves * kWave, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_block<kMaxTileLanes, kHugeCap, kHugeThreads, 2>,
+                                                         kHugeThreads, 0);
         break;
     }
     return e == hipSuccess ? nb : 0;
