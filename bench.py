@@ -61,15 +61,20 @@ def kernel_source_hash():
 
 
 def traffic_from_profiles(name):
-    """HBM bytes per update launch measured by rocprofv3 counters for this
-    workload, if taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    """HBM bytes per step of the update kernels measured by rocprofv3
+    counters for this workload (profiles/traffic_<name>.md, lines
+    'kernel_hash: ...' and 'hbm_bytes_per_step: ...'), if they were taken on
+    the current kernel source; else None."""
+    import re
+    p = os.path.join(ROOT, "profiles", f"traffic_{name}.md")
     if not os.path.exists(p):
         return None
-    d = json.load(open(p))
-    if d.get("kernel_hash") != kernel_source_hash():
+    txt = open(p).read()
+    h = re.search(r"^kernel_hash:\s*(\S+)", txt, re.M)
+    b = re.search(r"^hbm_bytes_per_step:\s*([0-9.eE+]+)", txt, re.M)
+    if not h or not b or h.group(1) != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return float(b.group(1))
 
 
 def cpu_baseline(w, seconds=12.0):

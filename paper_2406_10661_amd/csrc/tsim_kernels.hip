@@ -1499,8 +1499,11 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
         return (round < rounds && ps < count) ? ps : -1;
     };
 
+    // headers run two tiles ahead and tile ids three ahead, so that no load
+    // of a round waits for a load issued in the same round
     Hdr cur = load_hdr(D, B, pos_of(0) >= 0 ? list[pos_of(0)] : -1);
-    int rn = pos_of(1) >= 0 ? list[pos_of(1)] : -1;
+    Hdr nxt = load_hdr(D, B, pos_of(1) >= 0 ? list[pos_of(1)] : -1);
+    int rn2 = pos_of(2) >= 0 ? list[pos_of(2)] : -1;
     TSIM_PF_LANES(cur);
     TSIM_PF_REST(cur);
     for (int round = 0; round < rounds; ++round) {
@@ -1549,13 +1552,13 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
         // disagrees with its lanes (only after a capacity error) is skipped
         const int n = S.n <= CAP ? S.n : 0;
         if (S.n > CAP && gt == 0) atomicAdd((unsigned long long*)&D.met[h.inst].errors, 1ull);
-        // next tile: header and lane tables now, the rest after pass 2
-        const Hdr hn = load_hdr(D, B, rn);
-        const int rn2 = pos_of(round + 2) >= 0 ? list[pos_of(round + 2)] : -1;
-        TSIM_PF_LANES(hn);
+        // next tile: lane tables now, the rest after pass 2
+        TSIM_PF_LANES(nxt);
+        const int rn3 = pos_of(round + 3) >= 0 ? list[pos_of(round + 3)] : -1;
         LdsView<TS> view{S};
         process_pass12<GW>(D, S, view, B, t, h.inst, gt, n);
-        TSIM_PF_REST(hn);
+        TSIM_PF_REST(nxt);
+        const Hdr nn = load_hdr(D, B, rn2);
         process_pass3<GW>(D, S, view, B, gt, gbase, n);
         wave_sync();
         if (n > 0) {
@@ -1566,8 +1569,9 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
             finish_tile(D, B, S, h, gt, n, acc);
         }
         wave_sync();
-        cur = hn;
-        rn = rn2;
+        cur = nxt;
+        nxt = nn;
+        rn2 = rn3;
     }
 #undef TSIM_PF_LANES
 #undef TSIM_PF_LANE_OF
