@@ -213,6 +213,8 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
  *   4 TSIM_SCHED_8X16    tiles of <= 8 lanes: eight per wavefront, <= 16 vehicles
  *   5 TSIM_SCHED_16X32P  as 1, with the pass over wider tiles loading each
  *                        wavefront's next tile while it works on the current
+ *   6 TSIM_SCHED_8AND16  as 5, with tiles of <= 8 lanes and <= 16 vehicles
+ *                        eight per wavefront
  * Every schedule gives bit-identical results; only speed differs.  Default 1.
  * Changing the schedule synchronises the stream and drops a captured graph
  * (recaptured on the next tsim_step). */
@@ -222,7 +224,8 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
 #define TSIM_SCHED_32X64 3
 #define TSIM_SCHED_8X16 4
 #define TSIM_SCHED_16X32P 5
-#define TSIM_NUM_SCHED 6
+#define TSIM_SCHED_8AND16 6
+#define TSIM_NUM_SCHED 7
 int tsim_set_schedule(tsim_handle *h, int32_t schedule);
 int tsim_get_schedule(tsim_handle *h, int32_t *schedule);
 /* Autotuner: runs `rounds` rounds of `steps` steps under every schedule in

@@ -86,18 +86,19 @@ int tile_class(const Build& B, int r)
 // with few enough lanes), the wide pass over at most R; each gets no more
 // workgroups than the device keeps resident (res_a, res_b; 0 = unknown)
 struct SchedGrid {
-    int gw, nA, GA, GB, GC;
+    int gw, nA, GA, GB, GC, GT;
 };
 
 constexpr int kMaxGridA = 8192, kMaxGridB = 8192;
 
-SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, int res_c = 0)
+SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, int res_c = 0, int res_t = 0)
 {
-    SchedGrid g{64, 0, 0, 0, 0};
+    SchedGrid g{64, 0, 0, 0, 0, 0};
     switch (sched) {
     case kSched8x16: g.gw = 8; g.nA = B.n_le[0]; break;
     case kSched16x32:
     case kSched16x32P:
+    case kSched8and16:
     case kSched16x64: g.gw = 16; g.nA = B.n_le[1]; break;
     case kSched32x64: g.gw = 32; g.nA = B.n_le[2]; break;
     default: g.gw = 64; g.nA = 0; break;
@@ -109,6 +110,10 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
     g.GB = std::max(1, std::min(B.R, capB));
     const int capC = res_c > 0 ? std::min(res_c, kMaxGridB) : kMaxGridB;
     g.GC = std::max(1, std::min(B.R, capC));
+    if (sched == kSched8and16 && B.n_le[0] > 0) {
+        const int capT = res_t > 0 ? std::min(res_t, kMaxGridA) : kMaxGridA;
+        g.GT = std::max(1, std::min((B.n_le[0] + 7) / 8, capT));
+    }
     return g;
 }
 
@@ -135,7 +140,7 @@ void order_tiles(Build& B, bool by_instance)
     B.G = 1;
     for (int s = 0; s < kNumSched; ++s) {
         const SchedGrid g = sched_grid(B, s);
-        B.G = std::max(B.G, g.GA + g.GB + g.GC);
+        B.G = std::max(B.G, g.GA + g.GB + g.GC + g.GT);
     }
 }
 
@@ -555,7 +560,7 @@ struct tsim_handle {
     int graph_chunk = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
-    int res[kNumSched + 3] = {};        // resident workgroups: grouped pass per schedule, wide, huge, pipelined wide
+    int res[kNumSched + 4] = {};        // resident workgroups: grouped pass per schedule, wide, huge, pipelined wide, tiny
     std::string err;
 };
 
@@ -635,7 +640,8 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.list_small, std::max<size_t>(R, 1) * 4);
     add(&D.list_big, std::max<size_t>(R, 1) * 4);
     add(&D.list_huge, std::max<size_t>(R, 1) * 4);
-    add(&D.list_cnt, 12);
+    add(&D.list_tiny, std::max<size_t>(R, 1) * 4);
+    add(&D.list_cnt, 16);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.done_ctr, 4);
     add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
@@ -845,7 +851,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 12, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 16, h->stream));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
@@ -877,12 +883,13 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
 
 static void set_sched(tsim_handle* h, int sched)
 {
-    const int res_b = sched == kSched16x32P ? h->res[kNumSched + 2] : h->res[kNumSched];
-    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], res_b, h->res[kNumSched + 1]);
+    const int res_b = (sched == kSched16x32P || sched == kSched8and16) ? h->res[kNumSched + 2] : h->res[kNumSched];
+    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], res_b, h->res[kNumSched + 1], h->res[kNumSched + 3]);
     h->D.sched = sched;
     h->D.GA = g.GA;
     h->D.GB = g.GB;
     h->D.GC = g.GC;
+    h->D.GT = g.GT;
 }
 
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,
@@ -971,6 +978,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
             h->res[kNumSched] = cus * update_blocks_per_cu(-1);
             h->res[kNumSched + 1] = cus * update_blocks_per_cu(-2);
             h->res[kNumSched + 2] = cus * update_blocks_per_cu(-3);
+            h->res[kNumSched + 3] = cus * update_blocks_per_cu(-4);
         }
     }
     set_sched(h, kSched16x32);

@@ -41,7 +41,8 @@ enum Schedule {
     kSched32x64 = 3,
     kSched8x16 = 4,
     kSched16x32P = 5,   // as 16x32, with the wide pass software-pipelined like the grouped one
-    kNumSched = 6
+    kSched8and16 = 6,   // as 16x32P, with tiles of <= 8 lanes and <= 16 vehicles in groups of 8
+    kNumSched = 7
 };
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
@@ -223,9 +224,10 @@ struct DevNet {
     int32_t* list_small;             // [R]
     int32_t* list_big;               // [R] tiles of at most kWideLanes lanes and kWideCap vehicles
     int32_t* list_huge;              // [R] the rest
-    int32_t* list_cnt;               // [3]
+    int32_t* list_tiny;              // [R] tiles for the narrowest groups (two-width schedules)
+    int32_t* list_cnt;               // [4] small, wide, huge, tiny
     // schedule (host side; passed to the kernels as arguments)
-    int32_t sched, GA, GB, GC;
+    int32_t sched, GA, GB, GC, GT;   // GT: workgroups of the tiny-tile pass
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)

@@ -176,7 +176,7 @@ struct PrepOut {
 };
 
 __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i, int small_lanes, int small_cap,
-                                            PrepOut& out)
+                                            int tiny_lanes, int tiny_cap, PrepOut& out)
 {
     const int p = (int)(tg & 1);
     VehRec* slab = p ? D.slab1 : D.slab0;
@@ -320,7 +320,8 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     out.departed = departed;
     out.errors = (int)errors;
     if (n > 0) {
-        if (nl <= small_lanes && n <= small_cap) out.list = 0;
+        if (nl <= tiny_lanes && n <= tiny_cap) out.list = 3;
+        else if (nl <= small_lanes && n <= small_cap) out.list = 0;
         else if (nl <= kWideLanes && n <= kWideCap) out.list = 1;
         else out.list = 2;
     }
@@ -344,20 +345,22 @@ constexpr int kPrepThreads = 512;
 // Work lists and departure counts are combined per workgroup before they
 // touch the shared counters: one atomic per list (and per metric) per
 // workgroup instead of one per road or wavefront.
-__global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int small_lanes, int small_cap)
+__global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int small_lanes, int small_cap,
+                                                          int tiny_lanes, int tiny_cap)
 {
     constexpr int NW = kPrepThreads / kWave;
-    __shared__ int wcnt[3][NW];
-    __shared__ int base[3];
+    constexpr int NL = 4;
+    __shared__ int wcnt[NL][NW];
+    __shared__ int base[NL];
     __shared__ long long bsum[2][NW];
     const long long tg = *D.gstep;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     PrepOut o;
-    prepare_one(D, tg, i, small_lanes, small_cap, o);
+    prepare_one(D, tg, i, small_lanes, small_cap, tiny_lanes, tiny_cap, o);
     const int wv = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-    unsigned long long m[3];
+    unsigned long long m[NL];
 #pragma unroll
-    for (int L = 0; L < 3; ++L) {
+    for (int L = 0; L < NL; ++L) {
         m[L] = __ballot(o.list == L);
         if (lane == 0) wcnt[L][wv] = __popcll(m[L]);
     }
@@ -372,12 +375,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         bsum[1][wv] = err;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < NL) {
         const int L = threadIdx.x;
         int tot = 0;
         for (int w = 0; w < NW; ++w) tot += wcnt[L][w];
         base[L] = tot ? atomicAdd(&D.list_cnt[L], tot) : 0;
-    } else if (threadIdx.x == 3 && one) {
+    } else if (threadIdx.x == NL && one) {
         long long d = 0, e = 0;
         for (int w = 0; w < NW; ++w) {
             d += bsum[0][w];
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         int off = base[L];
         for (int w = 0; w < wv; ++w) off += wcnt[L][w];
         off += __popcll(m[L] & ((1ull << lane) - 1ull));
-        int32_t* list = L == 0 ? D.list_small : (L == 1 ? D.list_big : D.list_huge);
+        int32_t* list = L == 0 ? D.list_small : (L == 1 ? D.list_big : (L == 2 ? D.list_huge : D.list_tiny));
         list[off] = o.r;
     }
     if (!one && o.r >= 0) {
@@ -1385,6 +1388,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
         D.list_cnt[0] = 0;
         D.list_cnt[1] = 0;
         D.list_cnt[2] = 0;
+        D.list_cnt[3] = 0;
     }
 }
 
@@ -1408,7 +1412,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
     TS& S = Sg[w * NG + g];
     const int count = D.list_cnt[LIST];
-    const int32_t* const list = LIST == 0 ? D.list_small : D.list_big;
+    const int32_t* const list = LIST == 0 ? D.list_small : (LIST == 1 ? D.list_big : D.list_tiny);
     const int first = ((int)blockIdx.x * WPB + w) * NG;
     const int stride = (int)gridDim.x * WPB * NG;
     const int rounds = count > first ? (count - first + stride - 1) / stride : 0;
@@ -1803,8 +1807,9 @@ __global__ void k_import(const DevNet D, const uint32_t* slots, const VehRec* re
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
     const int n = H.R + H.NJ;
-    int lanes = 0, cap = 0;
+    int lanes = 0, cap = 0, tl = 0, tc = 0;
     switch (H.sched) {
+    case kSched8and16: lanes = 16; cap = 32; tl = 8; tc = 16; break;
     case kSched16x32:
     case kSched16x32P: lanes = 16; cap = 32; break;
     case kSched16x64: lanes = 16; cap = 64; break;
@@ -1812,17 +1817,24 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     case kSched8x16: lanes = 8; cap = 16; break;
     default: break;
     }
-    hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap);
+    hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap,
+                       tl, tc);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
-    const int total = H.GA + H.GB + H.GC;
+    const int total = H.GT + H.GA + H.GB + H.GC;
+    if (H.GT > 0) {
+        hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4, 8, 3>), dim3(H.GT), dim3(4 * kWave), 0, s, H, H.GA + H.GB + H.GC);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (H.GA > 0) {
         switch (H.sched) {
         case kSched16x32:
         case kSched16x32P:
+        case kSched8and16:
             hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
             break;
         case kSched16x64:
@@ -1840,7 +1852,7 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (H.sched == kSched16x32P)
+    if (H.sched == kSched16x32P || H.sched == kSched8and16)
         hipLaunchKernelGGL((k_update_grouped<kWave, kWideCap, kChangerCap, kWideWaves, kWideLanes, 1>), dim3(H.GB),
                            dim3(kWideWaves * kWave), 0, s, H, H.GA);
     else
@@ -1853,6 +1865,7 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
     const hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
     hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H, total);
+    (void)total;
     return hipGetLastError();
 }
 
@@ -1866,7 +1879,11 @@ int update_blocks_per_cu(int sched)
     switch (sched) {
     case kSched16x32:
     case kSched16x32P:
+    case kSched8and16:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<16, 32, 16, 4>, 4 * kWave, 0);
+        break;
+    case -4:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<8, 16, 8, 4, 8, 3>, 4 * kWave, 0);
         break;
     case -3:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
