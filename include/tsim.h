@@ -228,6 +228,14 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
 #define TSIM_NUM_SCHED 7
 int tsim_set_schedule(tsim_handle *h, int32_t schedule);
 int tsim_get_schedule(tsim_handle *h, int32_t *schedule);
+/* Pass concurrency.  A step's update passes (one per class of tile size) work
+ * on disjoint tiles and meet only in the final fold; with enable = 1 they are
+ * launched on three side streams of the handle (default priority, ordered
+ * after the step's prepare kernel and before its fold by events), so that one
+ * pass's last workgroups overlap the next pass.  Results are bit-identical
+ * either way.  Synchronises the stream and drops a captured graph.  Works on
+ * batches too.  Default 0. */
+int tsim_set_concurrency(tsim_handle *h, int32_t enable);
 /* Autotuner: runs `rounds` rounds of `steps` steps under every schedule in
  * turn (these are real steps: the simulation advances by
  * rounds * TSIM_NUM_SCHED * steps), keeps the schedule with the lowest best

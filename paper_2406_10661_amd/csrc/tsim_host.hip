@@ -17,7 +17,7 @@
 
 namespace tsim {
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s);
-hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s);
+hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps);
 hipError_t launch_set_phases(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
 hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
@@ -560,6 +560,7 @@ struct tsim_handle {
     int graph_chunk = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
+    PassStreams ps;                     // tsim_set_concurrency
     int res[kNumSched + 4] = {};        // resident workgroups: grouped pass per schedule, wide, huge, pipelined wide, tiny
     std::string err;
 };
@@ -1095,7 +1096,7 @@ int flush_events(tsim_handle* h, int k)
 
 int timed_launch(tsim_handle* h, int k)
 {
-    if (!h->prof) return (k == 0 ? launch_update(h->d_net, h->D, h->stream) : launch_prepare(h->d_net, h->D, h->stream)) == hipSuccess
+    if (!h->prof) return (k == 0 ? launch_update(h->d_net, h->D, h->stream, &h->ps) : launch_prepare(h->d_net, h->D, h->stream)) == hipSuccess
                              ? TSIM_OK
                              : hip_fail(h, hipGetLastError(), "kernel launch");
     if (h->ev_used[k] == kEventPairs) {
@@ -1108,7 +1109,7 @@ int timed_launch(tsim_handle* h, int k)
     }
     const int i = h->ev_used[k]++;
     HIPCHK(h, hipEventRecord(h->ev[k][2 * i], h->stream));
-    HIPCHK(h, k == 0 ? launch_update(h->d_net, h->D, h->stream) : launch_prepare(h->d_net, h->D, h->stream));
+    HIPCHK(h, k == 0 ? launch_update(h->d_net, h->D, h->stream, &h->ps) : launch_prepare(h->d_net, h->D, h->stream));
     HIPCHK(h, hipEventRecord(h->ev[k][2 * i + 1], h->stream));
     return TSIM_OK;
 }
@@ -1122,7 +1123,7 @@ static int capture_chunk(tsim_handle* h)
     hipError_t e = hipSuccess;
     for (int s = 0; s < h->graph_chunk && e == hipSuccess; ++s) {
         e = launch_prepare(h->d_net, h->D, h->cap_stream);
-        if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->cap_stream);
+        if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->cap_stream, &h->ps);
     }
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1163,6 +1164,26 @@ int tsim_set_schedule(tsim_handle* h, int32_t schedule)
     return TSIM_OK;
 }
 
+int tsim_set_concurrency(tsim_handle* h, int32_t enable)
+{
+    if (!h || enable < 0 || enable > 1) return fail(nullptr, TSIM_EINVAL, "bad handle or flag");
+    if ((h->ps.n > 0) == (enable == 1)) return TSIM_OK;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    if (enable) {
+        if (!h->ps.fork) HIPCHK(h, hipEventCreateWithFlags(&h->ps.fork, hipEventDisableTiming));
+        for (int i = 0; i < 3; ++i) {
+            if (!h->ps.aux[i]) HIPCHK(h, hipStreamCreateWithFlags(&h->ps.aux[i], hipStreamNonBlocking));
+            if (!h->ps.join[i]) HIPCHK(h, hipEventCreateWithFlags(&h->ps.join[i], hipEventDisableTiming));
+        }
+    }
+    h->ps.n = enable ? 3 : 0;
+    return TSIM_OK;
+}
+
 int tsim_get_schedule(tsim_handle* h, int32_t* schedule)
 {
     if (!h || !schedule) return fail(nullptr, TSIM_EINVAL, "bad arguments");
@@ -1190,7 +1211,7 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
             hipError_t e = hipEventRecord(ev[k], h->stream);
             for (int t = 0; t < steps && e == hipSuccess; ++t) {
                 e = launch_prepare(h->d_net, h->D, h->stream);
-                if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->stream);
+                if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->stream, &h->ps);
             }
             if (e == hipSuccess) e = hipEventRecord(ev[k + 1], h->stream);
             if (e != hipSuccess) rc = hip_fail(h, e, "autotune");
@@ -1533,6 +1554,11 @@ int tsim_destroy(tsim_handle* h)
         for (auto& e : h->ev[k]) (void)hipEventDestroy(e);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (int i = 0; i < 3; ++i) {
+        if (h->ps.aux[i]) (void)hipStreamDestroy(h->ps.aux[i]);
+        if (h->ps.join[i]) (void)hipEventDestroy(h->ps.join[i]);
+    }
+    if (h->ps.fork) (void)hipEventDestroy(h->ps.fork);
     for (int k = 0; k < 2; ++k) {
         if (h->pin_ev[k]) (void)hipEventDestroy(h->pin_ev[k]);
         if (h->h_pin[k]) (void)hipHostFree(h->h_pin[k]);

@@ -237,4 +237,16 @@ struct DevNet {
     KParams P;
 };
 
+// Side streams on which the update passes of a step run concurrently: the
+// passes touch disjoint tiles (the feeder gates they raise in other tiles are
+// atomic min/max), so they need no order among themselves, only after the
+// prepare kernel and before the fold.  n = 0 keeps every pass on the step's
+// stream.
+struct PassStreams {
+    int n = 0;
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+};
+
 }  // namespace tsim

@@ -1822,11 +1822,40 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
+hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps)
 {
     const int total = H.GT + H.GA + H.GB + H.GC;
+    // pass streams: the wide pass on the step's stream, the huge, grouped and
+    // tiny passes on the side streams when they are enabled
+    hipStream_t sw = s, sh = s, sg = s, st = s;
+    const int naux = ps ? ps->n : 0;
+    if (naux > 0) {
+        hipError_t e = hipEventRecord(ps->fork, s);
+        for (int i = 0; i < naux && e == hipSuccess; ++i) e = hipStreamWaitEvent(ps->aux[i], ps->fork, 0);
+        if (e != hipSuccess) return e;
+        sh = ps->aux[0];
+        sg = ps->aux[naux > 1 ? 1 : 0];
+        st = ps->aux[naux > 2 ? 2 : naux - 1];
+    }
+    // huge tiles first: their workgroups run longest
+    hipLaunchKernelGGL((k_update_block<kMaxTileLanes, kHugeCap, kHugeThreads, 2>), dim3(H.GC), dim3(kHugeThreads), 0,
+                       sh, H, H.GA + H.GB);
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (H.sched == kSched16x32P || H.sched == kSched8and16)
+        hipLaunchKernelGGL((k_update_grouped<kWave, kWideCap, kChangerCap, kWideWaves, kWideLanes, 1>), dim3(H.GB),
+                           dim3(kWideWaves * kWave), 0, sw, H, H.GA);
+    else
+        hipLaunchKernelGGL((k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>), dim3(H.GB), dim3(kWideWaves * kWave), 0,
+                           sw, H, H.GA);
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (H.GT > 0) {
-        hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4, 8, 3>), dim3(H.GT), dim3(4 * kWave), 0, s, H, H.GA + H.GB + H.GC);
+        hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4, 8, 3>), dim3(H.GT), dim3(4 * kWave), 0, st, H, H.GA + H.GB + H.GC);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1835,16 +1864,16 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         case kSched16x32:
         case kSched16x32P:
         case kSched8and16:
-            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
+            hipLaunchKernelGGL((k_update_grouped<16, 32, 16, 4>), dim3(H.GA), dim3(4 * kWave), 0, sg, H, 0);
             break;
         case kSched16x64:
-            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, s, H, 0);
+            hipLaunchKernelGGL((k_update_grouped<16, 64, 32, 2>), dim3(H.GA), dim3(2 * kWave), 0, sg, H, 0);
             break;
         case kSched32x64:
-            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
+            hipLaunchKernelGGL((k_update_grouped<32, 64, 32, 4>), dim3(H.GA), dim3(4 * kWave), 0, sg, H, 0);
             break;
         case kSched8x16:
-            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, s, H, 0);
+            hipLaunchKernelGGL((k_update_grouped<8, 16, 8, 4>), dim3(H.GA), dim3(4 * kWave), 0, sg, H, 0);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1852,18 +1881,11 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (H.sched == kSched16x32P || H.sched == kSched8and16)
-        hipLaunchKernelGGL((k_update_grouped<kWave, kWideCap, kChangerCap, kWideWaves, kWideLanes, 1>), dim3(H.GB),
-                           dim3(kWideWaves * kWave), 0, s, H, H.GA);
-    else
-        hipLaunchKernelGGL((k_update_wide<kWideLanes, kWideCap, kWideWaves, 1>), dim3(H.GB), dim3(kWideWaves * kWave), 0,
-                           s, H, H.GA);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_update_block<kMaxTileLanes, kHugeCap, kHugeThreads, 2>), dim3(H.GC), dim3(kHugeThreads), 0,
-                       s, H, H.GA + H.GB);
-    const hipError_t e2 = hipGetLastError();
-    if (e2 != hipSuccess) return e2;
+    for (int i = 0; i < naux; ++i) {
+        hipError_t e = hipEventRecord(ps->join[i], ps->aux[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ps->join[i], 0);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H, total);
     (void)total;
     return hipGetLastError();

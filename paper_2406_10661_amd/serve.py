@@ -196,14 +196,16 @@ class ServeLoop:
 class BatchFactory:
     """Jobs grouped into batches (``tsim_batch_*``: one set of launches steps
     every instance of a batch), each batch on one stream of a pool; each
-    instance is frozen at its own horizon."""
+    instance is frozen at its own horizon.  ``concurrent`` runs each batch's
+    update passes on side streams (``tsim_set_concurrency``)."""
 
-    def __init__(self, n_streams=3, device="cuda:0", graph_steps=30):
+    def __init__(self, n_streams=3, device="cuda:0", graph_steps=30, concurrent=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.graph_steps = int(graph_steps)
+        self.concurrent = bool(concurrent)
         self._next = 0
         self._lock = threading.Lock()
 
@@ -221,6 +223,8 @@ class BatchFactory:
                       device=self.device, stream=s)
             for k, j in enumerate(jobs):
                 b.set_horizon(k, j.horizon)
+            if self.concurrent:
+                b.set_concurrency(True)
             if self.graph_steps:
                 b.set_graph_steps(self.graph_steps)
         return b, s

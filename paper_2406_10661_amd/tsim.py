@@ -68,7 +68,7 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_footprint", "tsim_batch_create", "tsim_batch_step", "tsim_batch_set_signal_phases",
            "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
-           "tsim_autotune", "tsim_batch_set_horizon"]
+           "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide"}
 
@@ -94,6 +94,7 @@ def lib():
         L.tsim_set_profiling.argtypes = [P, C.c_int32]
         L.tsim_set_graph_steps.argtypes = [P, C.c_int32]
         L.tsim_set_schedule.argtypes = [P, C.c_int32]
+        L.tsim_set_concurrency.argtypes = [P, C.c_int32]
         L.tsim_batch_set_horizon.argtypes = [P, C.c_int32, C.c_int64]
         L.tsim_get_schedule.argtypes = [P, P]
         L.tsim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, P]
@@ -236,6 +237,10 @@ class Sim:
     def set_schedule(self, schedule):
         _check(lib().tsim_set_schedule(self.h, int(schedule)), self.h)
 
+    def set_concurrency(self, enable=True):
+        """Run the update passes of each step on side streams, concurrently."""
+        _check(lib().tsim_set_concurrency(self.h, 1 if enable else 0), self.h)
+
     def schedule(self):
         out = np.zeros(1, np.int32)
         _check(lib().tsim_get_schedule(self.h, _p(out)), self.h)
@@ -334,6 +339,9 @@ class Batch:
 
     def set_schedule(self, schedule):
         Sim.set_schedule(self, schedule)
+
+    def set_concurrency(self, enable=True):
+        Sim.set_concurrency(self, enable)
 
     def schedule(self):
         return Sim.schedule(self)

@@ -312,6 +312,38 @@ def test_big_tiles_one_step_other_schedules(O, Sim, sched):
     _log(f"big_tiles_sched{sched}", rep)
 
 
+@pytest.mark.parametrize("case,graph", [("c1", 0), ("c1", 7), ("big", 7)])
+def test_concurrent_passes_bit_identical(Sim, case, graph):
+    """Update passes on side streams (eager and captured) give the same
+    trajectory as the serial launch order, under the schedules that use three
+    and four passes."""
+    if case == "c1":
+        w = W.config1()
+        net, trips, params = w.network, w.trips, w.params
+        st = synthetic_state(net, trips, 200, seed=9, p_active=0.7)
+    else:
+        net, trips, params, st = _dense_big_tile_case(1)
+    for sc in (1, 6):
+        runs = []
+        for conc in (0, 1):
+            g = Sim(net, trips, params)
+            g.set_schedule(sc)
+            g.set_concurrency(bool(conc))
+            g.set_graph_steps(graph)
+            g.set_state(st)
+            g.step(33)
+            runs.append((g.get_state(), g.metrics()))
+            g.close()
+        (s0, m0), (s1, m1) = runs
+        assert m0["errors"] == 0
+        for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+            assert np.array_equal(s0[key], s1[key]), (sc, key)
+        for key in ("step", "vehicle_steps", "lane_changes", "transfers", "departures", "n_finished",
+                    "mean_speed_avg", "mean_speed_last"):
+            assert m0[key] == m1[key], (sc, key, m0[key], m1[key])
+    _log(f"concurrent_{case}_graph{graph}", {"changes": int(m0["lane_changes"])})
+
+
 def test_autotune_steps_like_plain(Sim):
     """The autotuner's trial steps are real steps: afterwards the state equals
     a plain run of the same length, and the chosen schedule is reported."""
