@@ -152,6 +152,7 @@ def run_batch(args):
     from paper_2406_10661_amd.tsim import SCHEDULES
     # schedule: autotuned on a throw-away batch once traffic has built up
     b = Batch(nets, trips, pars)
+    b.set_concurrency(bool(args.concurrent))
     for c in range(450 // every):
         b.set_all_phases(allph[c])
         b.step(every)
@@ -373,6 +374,7 @@ def main():
     stream = torch.cuda.current_stream()
     # schedule: autotuned on a seeded mid-horizon state (about half the
     # vehicles on the network), outside the timed region
+    sim.set_concurrency(bool(args.concurrent))
     if args.schedule is None:
         sched, us = autotune_city(sim, w, W)
         log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step by schedule "
@@ -381,7 +383,6 @@ def main():
         sched = args.schedule
         sim.set_schedule(sched)
         log(f"[bench] fixed schedule {sched} ({SCHEDULES[sched]})")
-    sim.set_concurrency(bool(args.concurrent))
     sim.set_state(init)
     if args.warmup:
         sim.step(args.warmup)

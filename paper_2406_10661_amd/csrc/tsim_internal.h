@@ -140,6 +140,7 @@ struct DevMetrics {
 struct WGPartial {
     long long sumv_fx, cnt, active, changes, transfers, clamps, feeder_blocks, finished, sum_tt_fx, errors;
 };
+static_assert(sizeof(WGPartial) == 80, "the fold reads partials as five 16-byte words");
 
 struct DevNet {
     int32_t R, NJ, NL, N, G;     // roads, junctions, lanes, vehicles, update grid size

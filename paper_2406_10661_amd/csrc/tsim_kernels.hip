@@ -215,12 +215,24 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     }
     if (i >= D.NJ + D.R) return;
     const int r = i - D.NJ;
+    // the road's words, its lanes' inbox flags and the first queued departure
+    // time are all read before the first store, so that their loads overlap
     const int inst = D.tile_inst[r];
-    const long long t = tg - D.inst_t0[inst];
-    // an instance past its horizon is frozen: none of its tiles is listed
-    if (t >= D.inst_end[inst]) return;
     const int lb = D.tile_lane_begin[r];
+    const int nl = D.tile_lane_begin[r + 1] - lb;
     const int nrl = D.tile_n_road[r];
+    int head = D.q_head[r];
+    const int qe = D.q_begin[r + 1];
+    const int n_prev = tile_n[r];
+    const int n_w = tile_n_w[r];
+    const long long t = tg - D.inst_t0[inst];
+    const long long t_end = D.inst_end[inst];
+    const float tau0 = head < qe ? D.q_tau[head] : 0.0f;
+    uint32_t inb = 0u;
+#pragma unroll 4
+    for (int li = 0; li < nrl; ++li) inb |= (D.inbox_flag[lb + li] != 0 ? 1u : 0u) << li;
+    // an instance past its horizon is frozen: none of its tiles is listed
+    if (t >= t_end) return;
     // feeder gates of this road's lanes in the summaries this step writes
     // (the update kernels fill them)
     for (int li = 0; li < nrl; ++li) {
@@ -231,7 +243,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     int appended = 0;
     for (int li = 0; li < nrl; ++li) {
         const int m = lb + li;
-        if (D.inbox_flag[m]) {
+        if ((inb >> li) & 1u) {
             LaneSum s = sum[m];
             const VehRec z = D.inbox[m];
             if (s.cnt < D.lane_cap[m]) {
@@ -249,15 +261,16 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         }
     }
     // departures (FIFO per origin road, one per lane per step, safe entry)
-    int head = D.q_head[r];
-    const int qe = D.q_begin[r + 1];
     const double now = (double)t * P.dt_d;
     unsigned used = 0u;
     int departed = 0;
+    bool first = true;
     while (head < qe) {
         // departure times ascend along the queue: the first future one ends
         // the scan (entries already departed are skipped once they are due)
-        if (!((double)D.q_tau[head] <= now)) break;
+        const float tau = first ? tau0 : D.q_tau[head];
+        first = false;
+        if (!((double)tau <= now)) break;
         const int v = D.q_veh[head];
         if (D.status[v] != 0) {
             head++;
@@ -310,11 +323,10 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         head++;
     }
     D.q_head[r] = head;
-    const int n = tile_n[r] + appended + departed;
+    const int n = n_prev + appended + departed;
     if (appended + departed) tile_n[r] = n;
     // the update kernels' work lists: tiles with vehicles, by size; a tile
     // emptied since the last step gets its empty summaries here
-    const int nl = D.tile_lane_begin[r + 1] - lb;
     out.r = r;
     out.inst = inst;
     out.departed = departed;
@@ -325,7 +337,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         else if (nl <= kWideLanes && n <= kWideCap) out.list = 1;
         else out.list = 2;
     }
-    if (n == 0 && tile_n_w[r] != 0) {
+    if (n == 0 && n_w != 0) {
         LaneSum e;
         e.cnt = 0;
         e.rear = TS_INF;
@@ -1346,10 +1358,15 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
         }
     } else {
         long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // partials are 80 bytes (five 16-byte words) at 16-byte alignment
         for (int g = tid; g < total_wg; g += kFoldThreads) {
-            const long long* q = (const long long*)&D.part[g];
+            const longlong2* q = (const longlong2*)&D.part[g];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) a[k] += q[k];
+            for (int k = 0; k < 5; ++k) {
+                const longlong2 x = q[k];
+                a[2 * k] += x.x;
+                a[2 * k + 1] += x.y;
+            }
         }
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
