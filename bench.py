@@ -28,7 +28,8 @@ timing plans or road prices; 10k-500k vehicles; 300-3,600 steps) run by the
 continuous-batching loop of ``paper_2406_10661_amd.serve`` under an HBM
 budget (default: jobs gathered into batches, each frozen at its own
 horizon); reports jobs/s, p50/p99 latency and the plain one-job-at-a-time
-loop.
+loop, and the served capacity: the same jobs all arriving at once
+("saturated").
 
 Prints one JSON line on stdout.
 """
@@ -259,6 +260,19 @@ def run_serve(args):
     res = loop.run(jobs)
     summ = SV.summarize(res, skip=args.skip)
     log(f"[bench] served: {json.dumps(summ)}")
+    # served capacity: the same jobs all arriving at once, so that the loop
+    # is never short of work (the Poisson stream above is bound by its rate)
+    summ_s = None
+    if not args.no_saturate:
+        jobs_s = [SV.Job(jid=k, arrival=0.0, network=w.network, trips=w.trips, params=w.params,
+                         horizon=w.n_steps) for k, w in enumerate(ws)]
+        if args.serve_mode == "batched":
+            loop_s = SV.BatchedServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick,
+                                         max_batches=args.max_batches, max_jobs_per_batch=args.max_jobs_per_batch)
+        else:
+            loop_s = SV.ServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick)
+        summ_s = SV.summarize(loop_s.run(jobs_s))
+        log(f"[bench] saturated: {json.dumps(summ_s)}")
     # plain loop over the measured jobs: one job at a time, direct launches
     sel = sorted(res["jobs"], key=lambda j: j.arrival)[args.skip:]
     plain_ms = 0.0
@@ -297,6 +311,12 @@ def run_serve(args):
         "plain_loop": {"vehicle_steps_per_s": plain, "ms": plain_ms, "identical_results": bool(same)},
         "offered_vehicle_trip_steps": offered,
     }
+    if summ_s is not None:
+        out["saturated"] = {"jobs": summ_s["jobs"], "jobs_per_s": summ_s["jobs_per_s"],
+                            "vehicle_steps_per_s": summ_s["vehicle_steps_per_s"],
+                            "vs_plain_loop": summ_s["vehicle_steps_per_s"] / plain,
+                            "latency_p50_s": summ_s["latency_p50_s"], "latency_p99_s": summ_s["latency_p99_s"],
+                            "wall_s": summ_s["wall_s"]}
     print(json.dumps(out), flush=True)
 
 
@@ -335,6 +355,7 @@ def main():
     ap.add_argument("--jobs", type=int, default=400)
     ap.add_argument("--skip", type=int, default=50)
     ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--no-saturate", action="store_true", help="serve: skip the all-at-once capacity run")
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--tick", type=int, default=30)
     ap.add_argument("--streams", type=int, default=4)
