@@ -462,10 +462,7 @@ struct TileLds {
     float chg_x[CHG];
     int chg_vid[CHG];
     int chg_lane[CHG];
-    int mrg_tgt[CHG];
-    float mrg_rear[CHG];
-    float mrg_v[CHG];
-    int mrg_vid[CHG];
+    int4 mrg[CHG];         // vehicles merging: target lane, rear and speed (float bits), id
     unsigned long long sumv;
     unsigned long long sum_tt;
     int cntv;
@@ -609,19 +606,42 @@ __device__ __forceinline__ bool stop_at(const TS& S, int li, int nr, int q, bool
     return !S.green[q];
 }
 
-// number of vehicles of tile lane li ahead of (x, vid)
+// numbers of vehicles ahead of (xa, va) in tile lane la and of (xb, vb) in
+// tile lane lb: two binary searches run interleaved, so that their LDS reads
+// overlap; a negative lane leaves its result untouched
 template <class TS, class V>
-__device__ __forceinline__ int count_ahead(const TS& S, const V& view, int li, float x, int vid)
+__device__ __forceinline__ void count_ahead2(const TS& S, const V& view, int la, float xa, int va, int& ra, int lb,
+                                             float xb, int vb, int& rb)
 {
-    int lo = 0, hi = S.cnt[li];
-    const int b = S.start[li];
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const VehRec z = view.rec(b + mid);
-        if (ahead(z.x, z.vid, x, vid)) lo = mid + 1;
-        else hi = mid;
+    int loa = 0, hia = la >= 0 ? S.cnt[la] : 0;
+    int lob = 0, hib = lb >= 0 ? S.cnt[lb] : 0;
+    const int ba = la >= 0 ? S.start[la] : 0, bb = lb >= 0 ? S.start[lb] : 0;
+    while (loa < hia || lob < hib) {
+        const bool ga = loa < hia, gb = lob < hib;
+        const int ma = (loa + hia) >> 1, mb = (lob + hib) >> 1;
+        float zxa = 0.0f, zxb = 0.0f;
+        int zva = 0, zvb = 0;
+        if (ga) {
+            const VehRec z = view.rec(ba + ma);
+            zxa = z.x;
+            zva = z.vid;
+        }
+        if (gb) {
+            const VehRec z = view.rec(bb + mb);
+            zxb = z.x;
+            zvb = z.vid;
+        }
+        if (ga) {
+            if (ahead(zxa, zva, xa, va)) loa = ma + 1;
+            else hia = ma;
+        }
+        if (gb) {
+            if (ahead(zxb, zvb, xb, vb)) lob = mb + 1;
+            else hib = mb;
+        }
     }
-    return lo;
+    if (la >= 0) ra = loa;
+    if (lb >= 0) rb = lob;
 }
 
 // leader substitution for a vehicle at the front of tile lane li (route info
@@ -806,14 +826,16 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             if (rec.nr < 0) {
                 gmask = nroad >= 32 ? 0xFFFFFFFFu : ((1u << nroad) - 1u);
             } else {
-                for (int q = nroad; q < nl; ++q)
-                    if (S.jl_out_road[q] == rec.nr) {
-                        const int in = S.jl_in_local[q];
-                        gmask |= 1u << in;
-                        if (in == li - 1) qm = q;
-                        else if (in == li) q0 = q;
-                        else if (in == li + 1) qp = q;
-                    }
+                // branch-free so that the unrolled LDS reads issue together
+#pragma unroll 4
+                for (int q = nroad; q < nl; ++q) {
+                    const int in = S.jl_in_local[q];
+                    const bool hit = S.jl_out_road[q] == rec.nr;
+                    gmask |= hit ? (1u << in) : 0u;
+                    qm = (hit && in == li - 1) ? q : qm;
+                    q0 = (hit && in == li) ? q : q0;
+                    qp = (hit && in == li + 1) ? q : qp;
+                }
             }
         }
         const int jqp = jq_pack(qm, q0, qp);
@@ -846,10 +868,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             atomicAdd(&S.mcnt[mt], 1);
             const int k = atomicAdd(&S.nmerge, 1);
             if (k < TS::kChg) {
-                S.mrg_tgt[k] = mt;
-                S.mrg_rear[k] = rec.x - rec.len;
-                S.mrg_v[k] = rec.v;
-                S.mrg_vid[k] = rec.vid;
+                S.mrg[k] = make_int4(mt, __float_as_int(rec.x - rec.len), __float_as_int(rec.v), rec.vid);
             }
         }
     }
@@ -874,6 +893,16 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         // (the same for both directions; computed on first use)
         bool have_old = false;
         float d_old_c = 0.0f;
+        // the vehicle's position in each side lane it may consider (both
+        // searches at once; eval_dir repeats the eligibility checks)
+        int posL = 0, posR = 0;
+        {
+            const bool okL = !is_jl && li >= 1 &&
+                             (in_g ? ((gmask >> (li - 1)) & 1u) != 0u : group_dist(gmask, li - 1, nroad) < dist_l);
+            const bool okR = !is_jl && li + 1 < nroad &&
+                             (in_g ? ((gmask >> (li + 1)) & 1u) != 0u : group_dist(gmask, li + 1, nroad) < dist_l);
+            count_ahead2(S, view, okL ? li - 1 : -1, rec.x, rec.vid, posL, okR ? li + 1 : -1, rec.x, rec.vid, posR);
+        }
         // MOBIL for one direction: utility (or -inf), prospective
         // acceleration, and the target-lane leader used as a bound
         auto eval_dir = [&](int d) -> DirEval {
@@ -891,7 +920,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             } else if (!(group_dist(gmask, k, nroad) < dist_l)) {
                 return o;
             }
-            const int pos = count_ahead(S, view, k, rec.x, rec.vid);
+            const int pos = d < 0 ? posL : posR;
             const int tl = pos > 0 ? S.start[k] + pos - 1 : -1;
             const int tf = pos < S.cnt[k] ? S.start[k] + pos : -1;
             VehRec tlr{}, tfr{};
@@ -899,8 +928,9 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             if (tf >= 0) tfr = view.rec(tf);
             // same gap of k held by a vehicle two lanes right (rightward only)
             if (d > 0 && k + 1 < nroad) {
-                const int lo2 = tl >= 0 ? count_ahead(S, view, k + 1, tlr.x, tlr.vid) : 0;
-                const int hi2 = tf >= 0 ? count_ahead(S, view, k + 1, tfr.x, tfr.vid) : S.cnt[k + 1];
+                int lo2 = 0, hi2 = S.cnt[k + 1];
+                count_ahead2(S, view, tl >= 0 ? k + 1 : -1, tlr.x, tlr.vid, lo2, tf >= 0 ? k + 1 : -1, tfr.x, tfr.vid,
+                             hi2);
                 if (lo2 < hi2) return o;
             }
             Lead tld;
@@ -999,16 +1029,19 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             int y_vid = 0x7FFFFFFF;
             const int nm = S.nmerge;
             if (nm <= TS::kChg) {
+                // one 16-byte broadcast read per merger, selects instead of
+                // branches, so that the unrolled reads issue together (the
+                // choice does not depend on the scan order)
+#pragma unroll 4
                 for (int q = 0; q < nm; ++q) {
-                    if (S.mrg_tgt[q] != li) continue;
-                    const float rm = S.mrg_rear[q];
-                    if (!(rm > rec.x)) continue;
-                    if (!has_y || rm < y_rear || (rm == y_rear && S.mrg_vid[q] < y_vid)) {
-                        has_y = true;
-                        y_rear = rm;
-                        y_v = S.mrg_v[q];
-                        y_vid = S.mrg_vid[q];
-                    }
+                    const int4 e = S.mrg[q];
+                    const float rm = __int_as_float(e.y);
+                    const bool take = e.x == li && rm > rec.x &&
+                                      (!has_y || rm < y_rear || (rm == y_rear && e.w < y_vid));
+                    has_y = has_y || take;
+                    y_rear = take ? rm : y_rear;
+                    y_v = take ? __int_as_float(e.z) : y_v;
+                    y_vid = take ? e.w : y_vid;
                 }
             } else {
                 for (int dd = -1; dd <= 1; dd += 2) {
