@@ -1234,10 +1234,13 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
         if (kind == 0) {
             rank = view.pref(j) - view.pref(S.start[li]);
         } else if (kind == 1) {
-            for (int q = 0; q < S.cnt[nli]; ++q) {
-                const int j2 = S.start[nli] + q;
-                if (view.kind(j2) != 0) continue;
-                if (ahead(view.nx(j2), view.rec(j2).vid, xn, rec.vid)) rank++;
+            // stayers of the target lane ahead of the changer (branch-free,
+            // so that the unrolled reads issue together)
+            const int b2 = S.start[nli], c2 = S.cnt[nli];
+#pragma unroll 4
+            for (int q = 0; q < c2; ++q) {
+                const int j2 = b2 + q;
+                rank += ((view.kind(j2) == 0) & ahead(view.nx(j2), view.rec(j2).vid, xn, rec.vid)) ? 1 : 0;
             }
         } else {
             rank = S.nstay[nli];
@@ -1245,9 +1248,11 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
         if (kind <= 1 && S.nin[nli] > (kind == 1 ? 1 : 0)) {
             // changers into the same lane ahead of this vehicle
             if (nchg <= TS::kChg) {
-                for (int q = 0; q < nchg; ++q)
-                    if (S.chg_lane[q] == nli && S.chg_vid[q] != rec.vid && ahead(S.chg_x[q], S.chg_vid[q], xn, rec.vid))
-                        rank++;
+#pragma unroll 4
+                for (int q = 0; q < nchg; ++q) {
+                    const int cv = S.chg_vid[q];
+                    rank += ((S.chg_lane[q] == nli) & (cv != rec.vid) & ahead(S.chg_x[q], cv, xn, rec.vid)) ? 1 : 0;
+                }
             } else {
                 for (int dd = -1; dd <= 1; dd += 2) {
                     const int k2 = nli + dd;
@@ -1300,13 +1305,14 @@ __device__ void process_tile(const DevNet& D, TS& S, V& view, const StepBufs& B,
 }
 
 // lane summaries, waiting counts and tile totals after a processed tile
-template <class TS>
+template <int GW, class TS>
 __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt, int n,
                                             WGPartial& acc)
 {
+    int c = 0;
     if (gt < h.nl) {
         const int m = h.lb + gt;
-        const int c = S.nstay[gt] + S.nin[gt] + S.nenter[gt];
+        c = S.nstay[gt] + S.nin[gt] + S.nenter[gt];
         B.wsum[m].cnt = c < S.cap[gt] ? c : S.cap[gt];
         if (c == 0) {
             B.wsum[m].rear = TS_INF;
@@ -1315,9 +1321,18 @@ __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, 
         }
         D.lane_wait[m] = S.wait[gt];
     }
+    // the tile's vehicle count: a group reduction of the lane counts when
+    // the group fits in a wavefront (its lanes are active together)
+    int tot = c;
+    if constexpr (GW <= kWave) {
+#pragma unroll
+        for (int off = 1; off < GW; off <<= 1) tot += __shfl_xor(tot, off, GW);
+    }
     if (gt == 0) {
-        int tot = 0;
-        for (int q = 0; q < h.nl; ++q) tot += S.nstay[q] + S.nin[q] + S.nenter[q];
+        if constexpr (GW > kWave) {
+            tot = 0;
+            for (int q = 0; q < h.nl; ++q) tot += S.nstay[q] + S.nin[q] + S.nenter[q];
+        }
         B.wtn[h.r] = tot;
         D.road_speed[h.r] = S.cntv > 0 ? (float)((double)(long long)S.sumv / (double)kSpeedFx / (double)S.cntv) : -1.0f;
         acc.sumv_fx += (long long)S.sumv;
@@ -1620,7 +1635,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
                 flush_acc(D, acc, acc_inst);
                 acc_inst = h.inst;
             }
-            finish_tile(D, B, S, h, gt, n, acc);
+            finish_tile<GW>(D, B, S, h, gt, n, acc);
         }
         wave_sync();
         cur = nxt;
@@ -1706,7 +1721,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
             flush_acc(D, acc, acc_inst);
             acc_inst = h.inst;
         }
-        finish_tile(D, B, S, h, tid, n, acc);
+        finish_tile<kWave>(D, B, S, h, tid, n, acc);
         wave_sync();
     }
     if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
@@ -1781,7 +1796,7 @@ __global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
             flush_acc(D, acc, acc_inst);
             acc_inst = h.inst;
         }
-        finish_tile(D, B, S, h, tid, n, acc);
+        finish_tile<TPB>(D, B, S, h, tid, n, acc);
         __syncthreads();
     }
     if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
