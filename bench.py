@@ -124,11 +124,28 @@ def roofline(alg_bytes, ms, steps, traffic):
             "us_per_launch": ms / max(steps, 1) * 1e3, "bytes_per_launch": alg_bytes / max(steps, 1)}
 
 
-def autotune_city(sim, w, W):
-    from paper_2406_10661_amd.workloads import synthetic_state
-    st = synthetic_state(w.network, w.trips, min(3600, w.n_steps // 2), seed=98, p_active=0.5)
-    sim.set_state(st)
-    return sim.autotune(steps=10, rounds=2)
+def autotune_city(sim, w, concurrent):
+    """Schedule (and, when concurrent is None, pass concurrency) autotuned on
+    the workload's own state five eighths into the horizon (congestion built
+    up), reached by stepping from the initial state; the caller resets the
+    state afterwards.  Returns (schedule, concurrent, us_per_step)."""
+    sim.step(w.n_steps * 5 // 8)
+    return tune(sim, 10, concurrent)
+
+
+def tune(obj, steps, concurrent):
+    """Autotunes the schedule of a Sim or Batch, and its pass concurrency
+    unless that is fixed; returns (schedule, concurrent, us_per_step)."""
+    if concurrent is None:
+        return obj.autotune_launch(steps=steps, rounds=2)
+    obj.set_concurrency(concurrent)
+    sched, us = obj.autotune(steps=steps, rounds=2)
+    return sched, concurrent, us
+
+
+def concurrency_arg(args):
+    """--concurrent: None (autotuned) or a fixed bool."""
+    return None if args.concurrent == "auto" else args.concurrent == "1"
 
 
 def run_batch(args):
@@ -153,20 +170,20 @@ def run_batch(args):
     from paper_2406_10661_amd.tsim import SCHEDULES
     # schedule: autotuned on a throw-away batch once traffic has built up
     b = Batch(nets, trips, pars)
-    b.set_concurrency(bool(args.concurrent))
     for c in range(450 // every):
         b.set_all_phases(allph[c])
         b.step(every)
-    sched, us = b.autotune(steps=every, rounds=2)
+    sched, conc, us = tune(b, every, concurrency_arg(args))
     b.close()
     del b
     torch.cuda.synchronize()
-    log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step {[round(float(x), 1) for x in us]}")
+    log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}), concurrent passes {conc}; us/step "
+        f"{[[round(float(x), 1) for x in row] for row in us] if us.ndim == 2 else [round(float(x), 1) for x in us]}")
 
     def batched(profile):
         b = Batch(nets, trips, pars)
         b.set_schedule(sched)
-        b.set_concurrency(bool(args.concurrent))
+        b.set_concurrency(conc)
         if profile:
             b.set_profiling(True)
         else:
@@ -227,7 +244,7 @@ def run_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch{len(ws)}_jittered_grids", "instances": len(ws), "vehicles": nveh,
                    "lanes": lanes, "steps_per_phase_update": every, "launch": "captured 15-step HIP graphs",
-                   "schedule": SCHEDULES[sched], "concurrent_passes": bool(args.concurrent)},
+                   "schedule": SCHEDULES[sched], "concurrent_passes": bool(conc)},
         "vs_plain_loop": plain_ms / ms_b,
         "plain_loop": {"value": vs_b / (plain_ms / 1e3), "ms": plain_ms, "identical_results": bool(same)},
         "roofline": roofline(alg, ms_b, steps, traffic_from_profiles(f"batch{len(ws)}")),
@@ -251,7 +268,7 @@ def run_serve(args):
     jobs = [SV.Job(jid=k, arrival=float(arr[k]), network=w.network, trips=w.trips, params=w.params,
                    horizon=w.n_steps) for k, w in enumerate(ws)]
     if args.serve_mode == "batched":
-        fac = SV.BatchFactory(n_streams=args.streams, graph_steps=args.tick, concurrent=bool(args.concurrent))
+        fac = SV.BatchFactory(n_streams=args.streams, graph_steps=args.tick, concurrent=args.concurrent == "1")
         loop = SV.BatchedServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick,
                                    max_batches=args.max_batches, max_jobs_per_batch=args.max_jobs_per_batch)
     else:
@@ -361,8 +378,9 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=60)
     ap.add_argument("--schedule", type=int, default=None, help="fixed update schedule (default: autotuned)")
-    ap.add_argument("--concurrent", type=int, choices=[0, 1], default=1,
-                    help="run the update passes of a step on side streams")
+    ap.add_argument("--concurrent", choices=["auto", "0", "1"], default="auto",
+                    help="update passes of a step on side streams (1), serial (0), or autotuned with the schedule "
+                         "(auto; on when the schedule is fixed; serving: off)")
     ap.add_argument("--serve-mode", choices=["batched", "streams"], default="batched")
     ap.add_argument("--max-batches", type=int, default=3)
     ap.add_argument("--max-jobs-per-batch", type=int, default=64)
@@ -393,17 +411,19 @@ def main():
     init = sim.get_state()
     log(f"[bench] device arena {sim.arena.numel() / 2**30:.2f} GiB")
     stream = torch.cuda.current_stream()
-    # schedule: autotuned on a seeded mid-horizon state (about half the
-    # vehicles on the network), outside the timed region
-    sim.set_concurrency(bool(args.concurrent))
+    # schedule and pass concurrency: autotuned on the run's own state 4,500
+    # steps in, outside the timed region (the state is reset to t = 0 below)
     if args.schedule is None:
-        sched, us = autotune_city(sim, w, W)
-        log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}); us/step by schedule "
-            f"{[round(float(x), 1) for x in us]}")
+        sched, conc, us = autotune_city(sim, w, concurrency_arg(args))
+        log(f"[bench] autotuned schedule {sched} ({SCHEDULES[sched]}), concurrent passes {conc}; us/step by "
+            f"schedule {[[round(float(x), 1) for x in row] for row in us] if us.ndim == 2 else [round(float(x), 1) for x in us]}")
     else:
         sched = args.schedule
+        conc = concurrency_arg(args)
+        conc = True if conc is None else conc
         sim.set_schedule(sched)
-        log(f"[bench] fixed schedule {sched} ({SCHEDULES[sched]})")
+        sim.set_concurrency(conc)
+        log(f"[bench] fixed schedule {sched} ({SCHEDULES[sched]}), concurrent passes {conc}")
     sim.set_state(init)
     if args.warmup:
         sim.step(args.warmup)
@@ -463,7 +483,7 @@ def main():
         "config": {"workload": w.name, "junctions": w.network.n_junctions, "roads": w.network.n_roads,
                    "lanes": w.network.n_lanes, "vehicles": w.trips.n_vehicles, "dt_s": w.params.dt,
                    "horizon_steps": w.n_steps, "timed_from_step": 0, "schedule": SCHEDULES[sched],
-                   "concurrent_passes": bool(args.concurrent),
+                   "concurrent_passes": bool(conc),
                    "graph_steps": args.graph_steps},
         "result": {"finished": m1["n_finished"], "mean_road_speed": m1["mean_speed_avg"], "att_s": m1["att"],
                    "lane_changes": m1["lane_changes"], "errors": m1["errors"]},

@@ -243,6 +243,14 @@ int tsim_set_concurrency(tsim_handle *h, int32_t enable);
  * entries) receives each schedule's best microseconds per step.  Synchronises
  * the stream.  Works on batches too. */
 int tsim_autotune(tsim_handle *h, int32_t steps, int32_t rounds, int32_t *chosen, float *us_per_step);
+/* As tsim_autotune over every (schedule, pass concurrency) pair: first all
+ * schedules with serial passes, then all with concurrent ones
+ * (rounds * 2 * TSIM_NUM_SCHED * steps real steps).  Keeps the fastest pair
+ * and writes it to *schedule and *concurrent; us_per_step (optional,
+ * 2 * TSIM_NUM_SCHED entries) receives the serial times, then the concurrent
+ * ones.  Synchronises the stream.  Works on batches too. */
+int tsim_autotune_launch(tsim_handle *h, int32_t steps, int32_t rounds, int32_t *schedule, int32_t *concurrent,
+                         float *us_per_step);
 
 int tsim_destroy(tsim_handle *h);
 const char *tsim_last_error(const tsim_handle *h);

@@ -613,9 +613,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.status, std::max<size_t>(N, 1) * 4);
     add(&D.finish_step, std::max<size_t>(N, 1) * 4);
     add(&D.q_begin, (R + 1) * 4);
-    add(&D.q_veh, std::max<size_t>(N, 1) * 4);
-    add(&D.q_tau, std::max<size_t>(N, 1) * 4);
-    add(&D.q_mask, std::max<size_t>(N, 1) * 4);
+    add(&D.q_rec, std::max<size_t>(N, 1) * sizeof(QRec));
     add(&D.q_head, R * 4);
     add(&D.slab0, S * sizeof(VehRec));
     add(&D.slab1, S * sizeof(VehRec));
@@ -1042,12 +1040,22 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     e = e ? e : chk(up(h, (float*)D.vf, B.vf), "trips");
     e = e ? e : chk(up(h, (float*)D.vlen, B.vlen), "trips");
     e = e ? e : chk(up(h, (int32_t*)D.q_begin, B.q_begin), "queues");
-    e = e ? e : chk(up(h, (int32_t*)D.q_veh, B.q_veh), "queues");
     {
-        std::vector<float> qt(B.q_veh.size());
-        for (size_t k = 0; k < qt.size(); ++k) qt[k] = B.tau[B.q_veh[k]];
-        e = e ? e : chk(up(h, (float*)D.q_tau, qt), "queues");
-        e = e ? e : chk(up(h, (uint32_t*)D.q_mask, B.q_mask), "queues");
+        std::vector<QRec> qr(B.q_veh.size());
+        for (size_t k = 0; k < qr.size(); ++k) {
+            const int v = B.q_veh[k];
+            const int rb = B.route_begin[v], rl = B.route_begin[v + 1] - rb;
+            QRec& q = qr[k];
+            q.tau = B.tau[v];
+            q.mask = B.q_mask[k];
+            q.vid = v;
+            q.len = B.vlen[v];
+            q.f = B.vf[v];
+            q.rp = rb;
+            q.rem = rl - 1;
+            q.nr = rl > 1 ? B.route[rb + 1] : -1;
+        }
+        e = e ? e : chk(up(h, (QRec*)D.q_rec, qr), "queues");
     }
     e = e ? e : chk(up(h, h->d_lane_ext, B.ext_of_int), "lanes");
     e = e ? e : chk(up(h, (int32_t*)D.tile_inst, B.tile_inst), "instances");
@@ -1191,10 +1199,11 @@ int tsim_get_schedule(tsim_handle* h, int32_t* schedule)
     return TSIM_OK;
 }
 
-int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen, float* us_per_step)
+// times `rounds` rounds of `steps` real steps under every schedule in turn,
+// with the handle's current pass concurrency; best_ms[sc] receives each
+// schedule's best round.  Leaves the schedule as it found it.
+static int time_schedules(tsim_handle* h, int32_t steps, int32_t rounds, float* best_ms)
 {
-    if (!h || steps < 1 || rounds < 1 || steps > 100000 || rounds > 100)
-        return fail(nullptr, TSIM_EINVAL, "bad handle, steps or rounds");
     std::vector<hipEvent_t> ev(2 * (size_t)rounds * kNumSched, nullptr);
     int rc = TSIM_OK;
     for (auto& e : ev) {
@@ -1217,7 +1226,6 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
             if (e != hipSuccess) rc = hip_fail(h, e, "autotune");
         }
     }
-    float best_ms[kNumSched];
     for (int sc = 0; sc < kNumSched; ++sc) best_ms[sc] = std::numeric_limits<float>::infinity();
     if (rc == TSIM_OK) {
         hipError_t e = hipStreamSynchronize(h->stream);
@@ -1232,7 +1240,17 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
     }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
-    int pick = keep;
+    set_sched(h, keep);
+    return rc;
+}
+
+int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen, float* us_per_step)
+{
+    if (!h || steps < 1 || rounds < 1 || steps > 100000 || rounds > 100)
+        return fail(nullptr, TSIM_EINVAL, "bad handle, steps or rounds");
+    float best_ms[kNumSched];
+    const int rc = time_schedules(h, steps, rounds, best_ms);
+    int pick = h->D.sched;
     if (rc == TSIM_OK) {
         pick = 0;
         for (int sc = 1; sc < kNumSched; ++sc)
@@ -1240,9 +1258,42 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
         if (us_per_step)
             for (int sc = 0; sc < kNumSched; ++sc) us_per_step[sc] = best_ms[sc] * 1000.0f / (float)steps;
     }
-    set_sched(h, keep);
     const int rc2 = tsim_set_schedule(h, pick);
     if (chosen) *chosen = h->D.sched;
+    return rc ? rc : rc2;
+}
+
+int tsim_autotune_launch(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* schedule, int32_t* concurrent,
+                         float* us_per_step)
+{
+    if (!h || steps < 1 || rounds < 1 || steps > 100000 || rounds > 100)
+        return fail(nullptr, TSIM_EINVAL, "bad handle, steps or rounds");
+    const int keep_conc = h->ps.n > 0 ? 1 : 0;
+    float best_ms[2][kNumSched];
+    int rc = TSIM_OK;
+    for (int c = 0; c < 2 && rc == TSIM_OK; ++c) {
+        rc = tsim_set_concurrency(h, c);
+        if (rc == TSIM_OK) rc = time_schedules(h, steps, rounds, best_ms[c]);
+    }
+    int pick_s = h->D.sched, pick_c = keep_conc;
+    if (rc == TSIM_OK) {
+        pick_s = 0;
+        pick_c = 0;
+        for (int c = 0; c < 2; ++c)
+            for (int sc = 0; sc < kNumSched; ++sc)
+                if (best_ms[c][sc] < best_ms[pick_c][pick_s]) {
+                    pick_c = c;
+                    pick_s = sc;
+                }
+        if (us_per_step)
+            for (int c = 0; c < 2; ++c)
+                for (int sc = 0; sc < kNumSched; ++sc)
+                    us_per_step[c * kNumSched + sc] = best_ms[c][sc] * 1000.0f / (float)steps;
+    }
+    int rc2 = tsim_set_concurrency(h, pick_c);
+    if (rc2 == TSIM_OK) rc2 = tsim_set_schedule(h, pick_s);
+    if (schedule) *schedule = h->D.sched;
+    if (concurrent) *concurrent = h->ps.n > 0 ? 1 : 0;
     return rc ? rc : rc2;
 }
 

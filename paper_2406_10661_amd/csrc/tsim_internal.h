@@ -59,6 +59,20 @@ struct __align__(16) VehRec {
     int32_t nr;   // next road of the route, -1 on the last road
 };
 
+// one departure queue entry with everything the prepare kernel needs to
+// place the vehicle (one 32-byte load instead of a chain through the trip
+// tables)
+struct __align__(16) QRec {
+    float tau;       // departure time
+    uint32_t mask;   // origin-road lanes (bits) that lead to the next road
+    int32_t vid;
+    float len;
+    float f;         // desired-speed factor
+    int32_t rp;      // route position of the origin road
+    int32_t rem;     // roads after the origin road
+    int32_t nr;      // next road, -1 if none
+};
+
 // per-lane summary of one step's state, read by other tiles (lookahead,
 // merge priority, departure safety) so that one 32-byte load serves them
 struct __align__(32) LaneSum {
@@ -195,9 +209,7 @@ struct DevNet {
     int32_t* status;
     int32_t* finish_step;
     const int32_t* q_begin;          // [R+1] departure queue of each origin road
-    const int32_t* q_veh;
-    const float* q_tau;              // departure time of each queue entry
-    const uint32_t* q_mask;          // origin-road lanes (bits) leading to the entry's next road
+    const QRec* q_rec;               // [N] departure queue entries
     int32_t* q_head;
     // slabs
     VehRec* slab0;

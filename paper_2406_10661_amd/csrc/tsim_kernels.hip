@@ -227,7 +227,8 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     const int n_w = tile_n_w[r];
     const long long t = tg - D.inst_t0[inst];
     const long long t_end = D.inst_end[inst];
-    const float tau0 = head < qe ? D.q_tau[head] : 0.0f;
+    QRec qr0{};
+    if (head < qe) qr0 = D.q_rec[head];
     uint32_t inb = 0u;
 #pragma unroll 4
     for (int li = 0; li < nrl; ++li) inb |= (D.inbox_flag[lb + li] != 0 ? 1u : 0u) << li;
@@ -268,32 +269,29 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     while (head < qe) {
         // departure times ascend along the queue: the first future one ends
         // the scan (entries already departed are skipped once they are due)
-        const float tau = first ? tau0 : D.q_tau[head];
+        const QRec qr = first ? qr0 : D.q_rec[head];
         first = false;
-        if (!((double)tau <= now)) break;
-        const int v = D.q_veh[head];
+        if (!((double)qr.tau <= now)) break;
+        const int v = qr.vid;
         if (D.status[v] != 0) {
             head++;
             continue;
         }
-        const int rb = D.route_begin[v];
-        const int rl = D.route_begin[v + 1] - rb;
-        const int nr = rl > 1 ? D.route[rb + 1] : -1;
-        const float Lv = D.vlen[v];
+        const float Lv = qr.len;
         int best = -1;
         float best_room = -TS_INF;
-        const uint32_t lanes_ok = D.q_mask[head] & ~used;
+        const uint32_t lanes_ok = qr.mask & ~used;
+        // every lane's summary is read (no load behind a branch), the choice
+        // is made by selects
+#pragma unroll 4
         for (int li = 0; li < nrl; ++li) {
-            if (!((lanes_ok >> li) & 1u)) continue;
-            const int m = lb + li;
+            const LaneSum s = sum[lb + li];
             // no nonempty feeder may reach past the entrant's rear (x = 0)
-            const LaneSum s = sum[m];
-            if (s.fmax != kNoFeeder && !(-Lv - o2f(s.fmax) >= 0.0f)) continue;
+            const bool ok = ((lanes_ok >> li) & 1u) && !(s.fmax != kNoFeeder && !(-Lv - o2f(s.fmax) >= 0.0f));
             const float room = s.cnt > 0 ? s.rear : TS_INF;
-            if (room > best_room) {
-                best_room = room;
-                best = li;
-            }
+            const bool better = ok && room > best_room;
+            best_room = better ? room : best_room;
+            best = better ? li : best;
         }
         if (best < 0 || !(best_room >= P.s0)) break;
         const int m = lb + best;
@@ -307,10 +305,10 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         nrec.v = 0.0f;
         nrec.vid = v;
         nrec.len = Lv;
-        nrec.f = D.vf[v];
-        nrec.rp = rb;
-        nrec.rem = rl - 1;
-        nrec.nr = nr;
+        nrec.f = qr.f;
+        nrec.rp = qr.rp;
+        nrec.rem = qr.rem;
+        nrec.nr = qr.nr;
         slab[D.lane_base[m] + s.cnt] = nrec;
         if (s.cnt == 0) s.front_reach = front_reach(0.0f, 0.0f, D.lane_len[m], P);
         s.cnt += 1;
@@ -1407,6 +1405,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
     } else {
         long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         // partials are 80 bytes (five 16-byte words) at 16-byte alignment
+#pragma unroll 4
         for (int g = tid; g < total_wg; g += kFoldThreads) {
             const longlong2* q = (const longlong2*)&D.part[g];
 #pragma unroll

@@ -68,7 +68,7 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_footprint", "tsim_batch_create", "tsim_batch_step", "tsim_batch_set_signal_phases",
            "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
-           "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency"]
+           "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency", "tsim_autotune_launch"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide"}
 
@@ -98,6 +98,7 @@ def lib():
         L.tsim_batch_set_horizon.argtypes = [P, C.c_int32, C.c_int64]
         L.tsim_get_schedule.argtypes = [P, P]
         L.tsim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, P]
+        L.tsim_autotune_launch.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.tsim_batch_set_graph_steps.argtypes = [P, C.c_int32]
         L.tsim_get_kernel_times.argtypes = [P, P, P, C.c_int32]
         L.tsim_destroy.argtypes = [P]
@@ -254,6 +255,16 @@ class Sim:
         _check(lib().tsim_autotune(self.h, int(steps), int(rounds), _p(ch), _p(us)), self.h)
         return int(ch[0]), us
 
+    def autotune_launch(self, steps=10, rounds=2):
+        """As autotune over (schedule, pass concurrency) pairs (2 x the
+        steps of autotune); returns (schedule, concurrent, us_per_step of
+        shape (2, n_schedules): serial row, then concurrent row)."""
+        sc = np.zeros(1, np.int32)
+        cc = np.zeros(1, np.int32)
+        us = np.zeros(2 * len(SCHEDULES), np.float32)
+        _check(lib().tsim_autotune_launch(self.h, int(steps), int(rounds), _p(sc), _p(cc), _p(us)), self.h)
+        return int(sc[0]), bool(cc[0]), us.reshape(2, len(SCHEDULES))
+
     def kernel_times(self):
         """{'update': (ms, launches), 'prepare': (ms, launches)} since profiling was enabled."""
         ms = np.zeros(2, np.float64)
@@ -348,6 +359,9 @@ class Batch:
 
     def autotune(self, steps=10, rounds=2):
         return Sim.autotune(self, steps, rounds)
+
+    def autotune_launch(self, steps=10, rounds=2):
+        return Sim.autotune_launch(self, steps, rounds)
 
     def set_signal_phases(self, instance, junctions, phases):
         j = np.ascontiguousarray(junctions, np.int32)

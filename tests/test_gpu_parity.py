@@ -344,6 +344,28 @@ def test_concurrent_passes_bit_identical(Sim, case, graph):
     _log(f"concurrent_{case}_graph{graph}", {"changes": int(m0["lane_changes"])})
 
 
+def test_autotune_launch_steps_like_plain(Sim):
+    """The schedule-and-concurrency autotuner also runs real steps (twice as
+    many as the schedule autotuner) and leaves the chosen pair set."""
+    from paper_2406_10661_amd.tsim import SCHEDULES
+    w = W.config1()
+    a = Sim(w.network, w.trips, w.params)
+    b = Sim(w.network, w.trips, w.params)
+    a.step(80)
+    b.step(80)
+    sc, conc, us = a.autotune_launch(steps=4, rounds=1)
+    b.step(4 * 2 * len(SCHEDULES))
+    assert sc in SCHEDULES and a.schedule() == sc and isinstance(conc, bool)
+    assert us.shape == (2, len(SCHEDULES)) and np.all(us > 0)
+    a.step(25)
+    b.step(25)
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+        assert np.array_equal(sa[key], sb[key]), key
+    assert a.metrics()["vehicle_steps"] == b.metrics()["vehicle_steps"]
+    _log("autotune_launch_c1", {"chosen": sc, "concurrent": conc})
+
+
 def test_autotune_steps_like_plain(Sim):
     """The autotuner's trial steps are real steps: afterwards the state equals
     a plain run of the same length, and the chosen schedule is reported."""
