@@ -1492,8 +1492,10 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
     static_assert(RPT <= 4, "at most four prefetched records per lane");
     __shared__ int pst_all[WPB * NG][GW + 1];      // next tile: lane starts
     __shared__ uint32_t pbs_all[WPB * NG][GW];     // next tile: lane slab bases
+    __shared__ signed char pvl_all[WPB * NG][CAP]; // next tile: lane of each record
     int* const pst = pst_all[w * NG + g];
     uint32_t* const pbs = pbs_all[w * NG + g];
+    signed char* const pvl = pvl_all[w * NG + g];
     LaneInfo pL{};
     int pcnt = 0, pfmx = kNoFeeder, pcur = -1, pn = 0;
     int4 poa{}, pob{};   // out-lane summary of the next tile's junction lane gt (LaneSum as two vectors)
@@ -1510,9 +1512,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
             pfmx = gt < (H).nroad ? B.rsum[m_].fmax : kNoFeeder;               \
         }                                                                      \
     } while (0)
-#define TSIM_PF_LANE_OF(J, LI)                                                 \
-    int LI = 0;                                                                \
-    while ((J) >= pst[LI + 1]) LI++
+#define TSIM_PF_LANE_OF(J, LI) const int LI = pvl[J]
 #define TSIM_PF_LOAD(I, RA, RB)                                                \
     do {                                                                       \
         const int j_ = gt + (I) * GW;                                          \
@@ -1548,6 +1548,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
         if (gt == 0) pst[0] = 0;                                               \
         pbs[gt] = pL.base;                                                     \
         pn = __shfl(c_, gbase + GW - 1);                                       \
+        /* lane map: lane gt marks its own records */                          \
+        for (int k_ = c_ - pcnt; k_ < c_ && k_ < CAP; ++k_) pvl[k_] = (signed char)gt; \
         wave_sync();                                                           \
         if (pn <= CAP) {                                                       \
             TSIM_PF_LOAD(0, r0a, r0b);                                         \
