@@ -215,6 +215,9 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
  *                        wavefront's next tile while it works on the current
  *   6 TSIM_SCHED_8AND16  as 5, with tiles of <= 8 lanes and <= 16 vehicles
  *                        eight per wavefront
+ *   7 TSIM_SCHED_FUSED   the tile classes of 6, every update pass in one
+ *                        launch (workgroup ranges per class; the pass
+ *                        concurrency setting does not apply)
  * Every schedule gives bit-identical results; only speed differs.  Default 1.
  * Changing the schedule synchronises the stream and drops a captured graph
  * (recaptured on the next tsim_step). */
@@ -225,7 +228,8 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
 #define TSIM_SCHED_8X16 4
 #define TSIM_SCHED_16X32P 5
 #define TSIM_SCHED_8AND16 6
-#define TSIM_NUM_SCHED 7
+#define TSIM_SCHED_FUSED 7
+#define TSIM_NUM_SCHED 8
 int tsim_set_schedule(tsim_handle *h, int32_t schedule);
 int tsim_get_schedule(tsim_handle *h, int32_t *schedule);
 /* Pass concurrency.  A step's update passes (one per class of tile size) work

@@ -99,6 +99,7 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
     case kSched16x32:
     case kSched16x32P:
     case kSched8and16:
+    case kSchedFused:
     case kSched16x64: g.gw = 16; g.nA = B.n_le[1]; break;
     case kSched32x64: g.gw = 32; g.nA = B.n_le[2]; break;
     default: g.gw = 64; g.nA = 0; break;
@@ -110,7 +111,7 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
     g.GB = std::max(1, std::min(B.R, capB));
     const int capC = res_c > 0 ? std::min(res_c, kMaxGridB) : kMaxGridB;
     g.GC = std::max(1, std::min(B.R, capC));
-    if (sched == kSched8and16 && B.n_le[0] > 0) {
+    if ((sched == kSched8and16 || sched == kSchedFused) && B.n_le[0] > 0) {
         const int capT = res_t > 0 ? std::min(res_t, kMaxGridA) : kMaxGridA;
         g.GT = std::max(1, std::min((B.n_le[0] + 7) / 8, capT));
     }
@@ -640,7 +641,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.list_big, std::max<size_t>(R, 1) * 4);
     add(&D.list_huge, std::max<size_t>(R, 1) * 4);
     add(&D.list_tiny, std::max<size_t>(R, 1) * 4);
-    add(&D.list_cnt, 16);
+    add(&D.list_cnt, 4 * kCntStride * 4);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.done_ctr, 4);
     add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
@@ -850,7 +851,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 16, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 4 * kCntStride * 4, h->stream));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
@@ -882,8 +883,13 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
 
 static void set_sched(tsim_handle* h, int sched)
 {
-    const int res_b = (sched == kSched16x32P || sched == kSched8and16) ? h->res[kNumSched + 2] : h->res[kNumSched];
-    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], res_b, h->res[kNumSched + 1], h->res[kNumSched + 3]);
+    // the fused launch sizes every range by its own occupancy
+    const bool fused = sched == kSchedFused;
+    const int res_b = fused ? h->res[sched]
+                      : (sched == kSched16x32P || sched == kSched8and16) ? h->res[kNumSched + 2]
+                                                                          : h->res[kNumSched];
+    const SchedGrid g = sched_grid(h->B, sched, h->res[sched], res_b, fused ? h->res[sched] : h->res[kNumSched + 1],
+                                   fused ? h->res[sched] : h->res[kNumSched + 3]);
     h->D.sched = sched;
     h->D.GA = g.GA;
     h->D.GB = g.GB;

@@ -42,8 +42,10 @@ enum Schedule {
     kSched8x16 = 4,
     kSched16x32P = 5,   // as 16x32, with the wide pass software-pipelined like the grouped one
     kSched8and16 = 6,   // as 16x32P, with tiles of <= 8 lanes and <= 16 vehicles in groups of 8
-    kNumSched = 7
+    kSchedFused = 7,    // the lists of 8and16, all passes in one launch
+    kNumSched = 8
 };
+constexpr int kCntStride = 32;           // work-list counters one 128-byte line apart
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
 constexpr int kWaitSpeedFlag = 0;
@@ -238,7 +240,7 @@ struct DevNet {
     int32_t* list_big;               // [R] tiles of at most kWideLanes lanes and kWideCap vehicles
     int32_t* list_huge;              // [R] the rest
     int32_t* list_tiny;              // [R] tiles for the narrowest groups (two-width schedules)
-    int32_t* list_cnt;               // [4] small, wide, huge, tiny
+    int32_t* list_cnt;               // [4 kCntStride] small, wide, huge, tiny (one 128-byte line each)
     // schedule (host side; passed to the kernels as arguments)
     int32_t sched, GA, GB, GC, GT;   // GT: workgroups of the tiny-tile pass
     // metrics

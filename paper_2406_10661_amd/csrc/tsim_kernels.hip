@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         const int L = threadIdx.x;
         int tot = 0;
         for (int w = 0; w < NW; ++w) tot += wcnt[L][w];
-        base[L] = tot ? atomicAdd(&D.list_cnt[L], tot) : 0;
+        base[L] = tot ? atomicAdd(&D.list_cnt[L * kCntStride], tot) : 0;
     } else if (threadIdx.x == NL && one) {
         long long d = 0, e = 0;
         for (int w = 0; w < NW; ++w) {
@@ -1238,7 +1238,7 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
 #pragma unroll 4
             for (int q = 0; q < c2; ++q) {
                 const int j2 = b2 + q;
-                rank += ((view.kind(j2) == 0) & ahead(view.nx(j2), view.rec(j2).vid, xn, rec.vid)) ? 1 : 0;
+                rank += (int)(view.kind(j2) == 0) & (int)ahead(view.nx(j2), view.rec(j2).vid, xn, rec.vid);
             }
         } else {
             rank = S.nstay[nli];
@@ -1249,7 +1249,7 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
 #pragma unroll 4
                 for (int q = 0; q < nchg; ++q) {
                     const int cv = S.chg_vid[q];
-                    rank += ((S.chg_lane[q] == nli) & (cv != rec.vid) & ahead(S.chg_x[q], cv, xn, rec.vid)) ? 1 : 0;
+                    rank += (int)(S.chg_lane[q] == nli) & (int)(cv != rec.vid) & (int)ahead(S.chg_x[q], cv, xn, rec.vid);
                 }
             } else {
                 for (int dd = -1; dd <= 1; dd += 2) {
@@ -1450,9 +1450,9 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
     if (tid == 0) {
         *D.gstep = tg + 1;
         D.list_cnt[0] = 0;
-        D.list_cnt[1] = 0;
-        D.list_cnt[2] = 0;
-        D.list_cnt[3] = 0;
+        D.list_cnt[kCntStride] = 0;
+        D.list_cnt[2 * kCntStride] = 0;
+        D.list_cnt[3 * kCntStride] = 0;
     }
 }
 
@@ -1460,14 +1460,27 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
 // Grouped pass: the step's small-tile list (tiles of at most GW lanes and
 // CAP vehicles, built by the prepare kernel), 64 / GW tiles per wavefront,
 // one group of GW lanes per tile; the grid strides over the list.
-template <int GW, int CAP, int CHG, int WPB, int LANES = GW, int LIST = 0>
-__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, int a_wg)
+// LDS of one grouped-pass workgroup
+template <int GW, int CAP, int CHG, int WPB, int LANES>
+struct GroupedLds {
+    static constexpr int NG = kWave / GW;
+    TileLds<LANES, CAP, CHG> Sg[WPB * NG];
+    WGPartial gacc[WPB * NG];
+    int pst_all[WPB * NG][GW + 1];      // next tile: lane starts
+    uint32_t pbs_all[WPB * NG][GW];     // next tile: lane slab bases
+    signed char pvl_all[WPB * NG][CAP]; // next tile: lane of each record
+};
+
+// the grouped pass as run by workgroup blk of nblk
+template <int GW, int CAP, int CHG, int WPB, int LANES, int LIST>
+__device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk, int nblk,
+                                             GroupedLds<GW, CAP, CHG, WPB, LANES>& L)
 {
     constexpr int NG = kWave / GW;
     static_assert(LANES <= GW, "a group covers the lanes of its tile");
     using TS = TileLds<LANES, CAP, CHG>;
-    __shared__ TS Sg[WPB * NG];
-    __shared__ WGPartial gacc[WPB * NG];
+    TS* const Sg = L.Sg;
+    WGPartial* const gacc = L.gacc;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
     // the WPB wavefronts of a workgroup work independently (each its own
@@ -1475,10 +1488,10 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
     TS& S = Sg[w * NG + g];
-    const int count = D.list_cnt[LIST];
+    const int count = D.list_cnt[LIST * kCntStride];
     const int32_t* const list = LIST == 0 ? D.list_small : (LIST == 1 ? D.list_big : D.list_tiny);
-    const int first = ((int)blockIdx.x * WPB + w) * NG;
-    const int stride = (int)gridDim.x * WPB * NG;
+    const int first = (blk * WPB + w) * NG;
+    const int stride = nblk * WPB * NG;
     const int rounds = count > first ? (count - first + stride - 1) / stride : 0;
 
     WGPartial acc{};
@@ -1490,12 +1503,9 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
     // and records gt, gt + GW, ...), so a round starts from data in hand.
     constexpr int RPT = (CAP + GW - 1) / GW;
     static_assert(RPT <= 4, "at most four prefetched records per lane");
-    __shared__ int pst_all[WPB * NG][GW + 1];      // next tile: lane starts
-    __shared__ uint32_t pbs_all[WPB * NG][GW];     // next tile: lane slab bases
-    __shared__ signed char pvl_all[WPB * NG][CAP]; // next tile: lane of each record
-    int* const pst = pst_all[w * NG + g];
-    uint32_t* const pbs = pbs_all[w * NG + g];
-    signed char* const pvl = pvl_all[w * NG + g];
+    int* const pst = L.pst_all[w * NG + g];
+    uint32_t* const pbs = L.pbs_all[w * NG + g];
+    signed char* const pvl = L.pvl_all[w * NG + g];
     LaneInfo pL{};
     int pcnt = 0, pfmx = kNoFeeder, pcur = -1, pn = 0;
     int4 poa{}, pob{};   // out-lane summary of the next tile's junction lane gt (LaneSum as two vectors)
@@ -1660,7 +1670,14 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
             for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tot, a_wg + (int)blockIdx.x);
+    finish_step(D, tot, a_wg + blk);
+}
+
+template <int GW, int CAP, int CHG, int WPB, int LANES = GW, int LIST = 0>
+__global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, int a_wg)
+{
+    __shared__ GroupedLds<GW, CAP, CHG, WPB, LANES> L;
+    grouped_pass<GW, CAP, CHG, WPB, LANES, LIST>(D, a_wg, (int)blockIdx.x, (int)gridDim.x, L);
 }
 
 constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
@@ -1678,7 +1695,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     TS& S = Sw[w];
-    const int count = D.list_cnt[LIST];
+    const int count = D.list_cnt[LIST * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
@@ -1744,21 +1761,22 @@ constexpr int kHugeThreads = 256;   // threads working together on one huge tile
 // Huge pass: the step's huge list, one tile per workgroup of TPB threads
 // (several wavefronts per tile, barrier-separated passes); up to CAP vehicles
 // staged in LDS, more on global per-slot scratch.
+// the huge-tile pass as run by workgroup blk of nblk
 template <int LANES, int CAP, int TPB, int LIST>
-__global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
+__device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, int nblk,
+                                           TileLds<LANES, CAP, kChangerCap>& S)
 {
     static_assert(LANES <= kWave, "lane scan by the first wavefront");
     using TS = TileLds<LANES, CAP, kChangerCap>;
-    __shared__ TS S;
     const long long tg = *D.gstep;
     const StepBufs B = step_bufs(D, tg);
     const int tid = (int)threadIdx.x;
-    const int count = D.list_cnt[LIST];
+    const int count = D.list_cnt[LIST * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
     int acc_inst = -1;
-    for (int k = (int)blockIdx.x; k < count; k += (int)gridDim.x) {
+    for (int k = blk; k < count; k += nblk) {
         const Hdr h = load_hdr(D, B, list[k]);
         const long long t = tg - D.inst_t0[h.inst];
         const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
@@ -1801,7 +1819,53 @@ __global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
         __syncthreads();
     }
     if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
-    finish_step(D, acc, a_wg + (int)blockIdx.x);
+    finish_step(D, acc, a_wg + blk);
+}
+
+template <int LANES, int CAP, int TPB, int LIST>
+__global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
+{
+    __shared__ TileLds<LANES, CAP, kChangerCap> S;
+    block_pass<LANES, CAP, TPB, LIST>(D, a_wg, (int)blockIdx.x, (int)gridDim.x, S);
+}
+
+// All update passes of a step in one launch (schedule 8x16+16x32, fused):
+// workgroups [0, GC) take the huge tiles, then GB the wide ones (four
+// wavefronts per workgroup), GA the small and GT the tiny ones; each range
+// strides over its own list, the LDS of each range is carved from one
+// dynamic allocation, and the workgroups of later ranges start as earlier
+// ones finish (no launches or stream joins between the passes).
+using FusedHuge = TileLds<kMaxTileLanes, kHugeCap, kChangerCap>;
+using FusedWide = GroupedLds<kWave, kWideCap, kChangerCap, 4, kWideLanes>;
+using FusedSmall = GroupedLds<16, 32, 16, 4, 16>;
+using FusedTiny = GroupedLds<8, 16, 8, 4, 8>;
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kFusedLds = cmax(cmax(sizeof(FusedHuge), sizeof(FusedWide)), cmax(sizeof(FusedSmall), sizeof(FusedTiny)));
+constexpr int kFusedThreads = 4 * kWave;
+static_assert(kHugeThreads == kFusedThreads, "one workgroup size for every range");
+
+__global__ __launch_bounds__(kFusedThreads) void k_update_fused(const DevNet D)
+{
+    extern __shared__ __align__(16) char fused_lds[];
+    int b = (int)blockIdx.x;
+    if (b < D.GC) {
+        block_pass<kMaxTileLanes, kHugeCap, kHugeThreads, 2>(D, D.GA + D.GB, b, D.GC,
+                                                            *reinterpret_cast<FusedHuge*>(fused_lds));
+        return;
+    }
+    b -= D.GC;
+    if (b < D.GB) {
+        grouped_pass<kWave, kWideCap, kChangerCap, 4, kWideLanes, 1>(D, D.GA, b, D.GB,
+                                                                     *reinterpret_cast<FusedWide*>(fused_lds));
+        return;
+    }
+    b -= D.GB;
+    if (b < D.GA) {
+        grouped_pass<16, 32, 16, 4, 16, 0>(D, 0, b, D.GA, *reinterpret_cast<FusedSmall*>(fused_lds));
+        return;
+    }
+    b -= D.GA;
+    grouped_pass<8, 16, 8, 4, 8, 3>(D, D.GA + D.GB + D.GC, b, D.GT, *reinterpret_cast<FusedTiny*>(fused_lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -1875,7 +1939,8 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     const int n = H.R + H.NJ;
     int lanes = 0, cap = 0, tl = 0, tc = 0;
     switch (H.sched) {
-    case kSched8and16: lanes = 16; cap = 32; tl = 8; tc = 16; break;
+    case kSched8and16:
+    case kSchedFused: lanes = 16; cap = 32; tl = 8; tc = 16; break;
     case kSched16x32:
     case kSched16x32P: lanes = 16; cap = 32; break;
     case kSched16x64: lanes = 16; cap = 64; break;
@@ -1891,6 +1956,13 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps)
 {
     const int total = H.GT + H.GA + H.GB + H.GC;
+    if (H.sched == kSchedFused) {
+        hipLaunchKernelGGL(k_update_fused, dim3(total), dim3(kFusedThreads), kFusedLds, s, H);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H, total);
+        return hipGetLastError();
+    }
     // pass streams: the wide pass on the step's stream, the huge, grouped and
     // tiny passes on the side streams when they are enabled
     hipStream_t sw = s, sh = s, sg = s, st = s;
@@ -1972,6 +2044,11 @@ int update_blocks_per_cu(int sched)
         break;
     case -4:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<8, 16, 8, 4, 8, 3>, 4 * kWave, 0);
+        break;
+    case kSchedFused:
+        e = hipFuncSetAttribute((const void*)k_update_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_fused, kFusedThreads, kFusedLds);
         break;
     case -3:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(

@@ -70,7 +70,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
            "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency", "tsim_autotune_launch"]
 
-SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide"}
+SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
+             7: "8x16+16x32+wide, fused launch"}
 
 
 def lib():
