@@ -18,6 +18,7 @@
 namespace tsim {
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s);
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps);
+hipError_t launch_fold(const DevNet& H, hipStream_t s);
 hipError_t launch_set_phases(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
 hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
@@ -641,9 +642,10 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.list_big, std::max<size_t>(R, 1) * 4);
     add(&D.list_huge, std::max<size_t>(R, 1) * 4);
     add(&D.list_tiny, std::max<size_t>(R, 1) * 4);
-    add(&D.list_cnt, 4 * kCntStride * 4);
+    add(&D.list_cnt, 2 * 4 * kCntStride * 4);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
-    add(&D.done_ctr, 4);
+    add(&D.ustep, 8);
+    add(&D.fold_flag, 8);
     add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
     add(&D.tile_inst, R * 4);
     add(&D.junc_inst, NJ * 4);
@@ -835,6 +837,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     std::vector<WGPartial> zacc(B.n_inst);
     std::memset(zacc.data(), 0, zacc.size() * sizeof(WGPartial));
     const long long gstep = step;
+    const long long ustep = step - 1;   // the last step run (none folded yet)
     std::vector<int32_t> st(status, status + N), fs(finish_step, finish_step + N);
     std::vector<int32_t> jp(pol, pol + B.NJ), jm(ph, ph + B.NJ);
     const bool odd = (step & 1) != 0;
@@ -850,11 +853,12 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.junc_manual, jm));
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.done_ctr, 0, 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 4 * kCntStride * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.fold_flag, 0, 8, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 2 * 4 * kCntStride * 4, h->stream));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(D.ustep, &ustep, sizeof(ustep), hipMemcpyHostToDevice, h->stream));
     if (!slots.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_io_i0, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_io_rec, recs.data(), recs.size() * sizeof(VehRec), hipMemcpyHostToDevice, h->stream));
@@ -1440,6 +1444,7 @@ static int metrics_impl(tsim_handle* h, int inst, tsim_metrics* out)
 {
     if (!h || !out) return fail(nullptr, TSIM_EINVAL, "bad arguments");
     if (inst < 0 || inst >= h->B.n_inst) return fail(&h->err, TSIM_EINVAL, "instance out of range");
+    HIPCHK(h, launch_fold(h->D, h->stream));
     DevMetrics M;
     HIPCHK(h, hipMemcpyAsync(&M, h->D.met + inst, sizeof(M), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1551,6 +1556,7 @@ static int get_state_impl(tsim_handle* h, int inst, tsim_state_host* out)
     int rc = export_state(h, lane, x, v, rpos, rank);
     if (rc) return rc;
     std::vector<int32_t> status(N), finish(N), pol(B.NJ), man(B.NJ);
+    HIPCHK(h, launch_fold(h->D, h->stream));
     DevMetrics M;
     HIPCHK(h, hipMemcpyAsync(status.data(), h->D.status, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(finish.data(), h->D.finish_step, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));

@@ -240,14 +240,19 @@ struct DevNet {
     int32_t* list_big;               // [R] tiles of at most kWideLanes lanes and kWideCap vehicles
     int32_t* list_huge;              // [R] the rest
     int32_t* list_tiny;              // [R] tiles for the narrowest groups (two-width schedules)
-    int32_t* list_cnt;               // [4 kCntStride] small, wide, huge, tiny (one 128-byte line each)
+    int32_t* list_cnt;               // [2][4 kCntStride] by step parity: small, wide, huge, tiny (one 128-byte line each)
     // schedule (host side; passed to the kernels as arguments)
     int32_t sched, GA, GB, GC, GT;   // GT: workgroups of the tiny-tile pass
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)
     WGPartial* part;                 // [G] (G >= GA + GB for every schedule)
-    unsigned int* done_ctr;
+    // step protocol: the prepare kernel of step t publishes t in *ustep (read
+    // by that step's update kernels, whose workgroups then advance *gstep to
+    // t + 1) and folds the partial sums of step t - 1 when fold_flag[0] is
+    // set; fold_flag[1] is the number of partials the last step wrote
+    long long* ustep;
+    int32_t* fold_flag;
     DevMetrics* met;                 // [n_inst]
     KParams P;
 };

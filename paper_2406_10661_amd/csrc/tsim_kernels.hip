@@ -355,8 +355,11 @@ constexpr int kPrepThreads = 512;
 // Work lists and departure counts are combined per workgroup before they
 // touch the shared counters: one atomic per list (and per metric) per
 // workgroup instead of one per road or wavefront.
+template <int NT>
+__device__ void fold_step(const DevNet& D, int total_wg);
+
 __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int small_lanes, int small_cap,
-                                                          int tiny_lanes, int tiny_cap)
+                                                          int tiny_lanes, int tiny_cap, int total_wg)
 {
     constexpr int NW = kPrepThreads / kWave;
     constexpr int NL = 4;
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         const int L = threadIdx.x;
         int tot = 0;
         for (int w = 0; w < NW; ++w) tot += wcnt[L][w];
-        base[L] = tot ? atomicAdd(&D.list_cnt[L * kCntStride], tot) : 0;
+        base[L] = tot ? atomicAdd(&D.list_cnt[((int)(tg & 1) * 4 + L) * kCntStride], tot) : 0;
     } else if (threadIdx.x == NL && one) {
         long long d = 0, e = 0;
         for (int w = 0; w < NW; ++w) {
@@ -418,6 +421,20 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
             atomicAdd((unsigned long long*)&D.met[o.inst].dep_events, (unsigned long long)o.departed);
         }
         if (o.errors) atomicAdd((unsigned long long*)&D.met[o.inst].errors, (unsigned long long)o.errors);
+    }
+    // step protocol (workgroup 0): fold the step before this one, publish
+    // this one for the update kernels (with its number of partials), clear
+    // the other parity's work-list counters for the next step
+    if (blockIdx.x == 0) {
+        const int pending = D.fold_flag[0];
+        if (pending) fold_step<kPrepThreads>(D, D.fold_flag[1]);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            D.fold_flag[0] = 1;
+            D.fold_flag[1] = total_wg;
+            *D.ustep = tg;
+        }
+        if (threadIdx.x < 4) D.list_cnt[((int)((tg + 1) & 1) * 4 + (int)threadIdx.x) * kCntStride] = 0;
     }
 }
 
@@ -1356,27 +1373,33 @@ __device__ __forceinline__ void flush_acc(const DevNet& D, WGPartial& acc, int i
     acc = WGPartial{};
 }
 
-// per-workgroup partial of the step (acc valid in thread 0); the fold kernel
-// that follows the update passes sums them (the kernel boundary makes these
-// plain stores visible, so no fence or counter is needed here)
-__device__ __forceinline__ void finish_step(const DevNet& D, const WGPartial& acc, int slot)
+// per-workgroup partial of the step (acc valid in thread 0), folded by the
+// next step's prepare kernel (or a fold launched before the host reads the
+// metrics); the kernel boundary makes these plain stores visible, so no
+// fence or counter is needed.  Every update workgroup also advances the
+// global step (all write the same value; no update workgroup reads it).
+__device__ __forceinline__ void finish_step(const DevNet& D, const WGPartial& acc, int slot, long long tg)
 {
-    if (threadIdx.x == 0) D.part[slot] = acc;
+    if (threadIdx.x == 0) {
+        D.part[slot] = acc;
+        *D.gstep = tg + 1;
+    }
 }
 
-// folds the step: sums the update workgroups' partials (or, for batches, the
-// per-instance sums), updates the metrics, clears the work lists and
-// advances the global step.  One workgroup of kFoldThreads threads.
-constexpr int kFoldThreads = 256;
-
-__global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total_wg)
+// folds the last step run (*ustep): sums its update workgroups' partials
+// (or, for batches, the per-instance sums) into the metrics.  Run by one
+// whole workgroup of NT threads.  The prepare kernel's other workgroups may
+// be adding departures and errors to the same metrics, so those fields take
+// atomics here.
+template <int NT>
+__device__ void fold_step(const DevNet& D, int total_wg)
 {
-    __shared__ long long red[kFoldThreads / kWave][10];
-    const long long tg = *D.gstep;
+    __shared__ long long red[NT / kWave][10];
+    const long long fs = *D.ustep;
     const int tid = threadIdx.x;
     if (D.n_inst > 1) {
-        for (int i = tid; i < D.n_inst; i += kFoldThreads) {
-            if (tg - D.inst_t0[i] >= D.inst_end[i]) continue;   // frozen instance
+        for (int i = tid; i < D.n_inst; i += NT) {
+            if (fs - D.inst_t0[i] >= D.inst_end[i]) continue;   // frozen instance
             long long* q = (long long*)&D.inst_acc[i];
             long long a[10];
 #pragma unroll
@@ -1392,7 +1415,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
             M->feeder_blocks += a[6];
             M->finished += a[7];
             M->sum_tt_fx += a[8];
-            M->errors += a[9];
+            if (a[9]) atomicAdd((unsigned long long*)&M->errors, (unsigned long long)a[9]);
             if (a[1] > 0) {
                 M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
                 M->speed_acc += M->mean_speed_last;
@@ -1400,13 +1423,13 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
             } else {
                 M->mean_speed_last = 0.0;
             }
-            M->step = tg - D.inst_t0[i] + 1;
+            M->step = fs - D.inst_t0[i] + 1;
         }
     } else {
         long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         // partials are 80 bytes (five 16-byte words) at 16-byte alignment
 #pragma unroll 4
-        for (int g = tid; g < total_wg; g += kFoldThreads) {
+        for (int g = tid; g < total_wg; g += NT) {
             const longlong2* q = (const longlong2*)&D.part[g];
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
@@ -1425,7 +1448,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
         }
         __syncthreads();
         if (tid == 0) {
-            for (int w = 1; w < kFoldThreads / kWave; ++w)
+            for (int w = 1; w < NT / kWave; ++w)
                 for (int k = 0; k < 10; ++k) a[k] += red[w][k];
             DevMetrics* M = D.met;
             M->vehicle_steps += a[2];
@@ -1435,7 +1458,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
             M->feeder_blocks += a[6];
             M->finished += a[7];
             M->sum_tt_fx += a[8];
-            M->errors += a[9];
+            if (a[9]) atomicAdd((unsigned long long*)&M->errors, (unsigned long long)a[9]);
             if (a[1] > 0) {
                 M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
                 M->speed_acc += M->mean_speed_last;
@@ -1443,17 +1466,21 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D, int total
             } else {
                 M->mean_speed_last = 0.0;
             }
-            M->step = tg - D.inst_t0[0] + 1;
+            M->step = fs - D.inst_t0[0] + 1;
         }
     }
+}
+
+// folds a step that no prepare kernel has folded yet (launched before the
+// host reads metrics); does nothing when none is pending
+constexpr int kFoldThreads = 256;
+
+__global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D)
+{
+    if (D.fold_flag[0] == 0) return;
+    fold_step<kFoldThreads>(D, D.fold_flag[1]);
     __syncthreads();
-    if (tid == 0) {
-        *D.gstep = tg + 1;
-        D.list_cnt[0] = 0;
-        D.list_cnt[kCntStride] = 0;
-        D.list_cnt[2 * kCntStride] = 0;
-        D.list_cnt[3 * kCntStride] = 0;
-    }
+    if (threadIdx.x == 0) D.fold_flag[0] = 0;
 }
 
 
@@ -1481,14 +1508,14 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
     using TS = TileLds<LANES, CAP, CHG>;
     TS* const Sg = L.Sg;
     WGPartial* const gacc = L.gacc;
-    const long long tg = *D.gstep;
+    const long long tg = *D.ustep;
     const StepBufs B = step_bufs(D, tg);
     // the WPB wavefronts of a workgroup work independently (each its own
     // groups and tiles); they meet only to combine their partial sums
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
     TS& S = Sg[w * NG + g];
-    const int count = D.list_cnt[LIST * kCntStride];
+    const int count = D.list_cnt[((int)(tg & 1) * 4 + LIST) * kCntStride];
     const int32_t* const list = LIST == 0 ? D.list_small : (LIST == 1 ? D.list_big : D.list_tiny);
     const int first = (blk * WPB + w) * NG;
     const int stride = nblk * WPB * NG;
@@ -1670,7 +1697,7 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
             for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tot, a_wg + blk);
+    finish_step(D, tot, a_wg + blk, tg);
 }
 
 template <int GW, int CAP, int CHG, int WPB, int LANES = GW, int LIST = 0>
@@ -1691,11 +1718,11 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
     using TS = TileLds<LANES, CAP, kChangerCap>;
     __shared__ TS Sw[WPB];
     __shared__ WGPartial wacc[WPB];
-    const long long tg = *D.gstep;
+    const long long tg = *D.ustep;
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     TS& S = Sw[w];
-    const int count = D.list_cnt[LIST * kCntStride];
+    const int count = D.list_cnt[((int)(tg & 1) * 4 + LIST) * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
@@ -1753,7 +1780,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
             for (int k = 0; k < 10; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tot, a_wg + (int)blockIdx.x);
+    finish_step(D, tot, a_wg + (int)blockIdx.x, tg);
 }
 
 constexpr int kHugeThreads = 256;   // threads working together on one huge tile
@@ -1768,10 +1795,10 @@ __device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, i
 {
     static_assert(LANES <= kWave, "lane scan by the first wavefront");
     using TS = TileLds<LANES, CAP, kChangerCap>;
-    const long long tg = *D.gstep;
+    const long long tg = *D.ustep;
     const StepBufs B = step_bufs(D, tg);
     const int tid = (int)threadIdx.x;
-    const int count = D.list_cnt[LIST * kCntStride];
+    const int count = D.list_cnt[((int)(tg & 1) * 4 + LIST) * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
@@ -1819,7 +1846,7 @@ __device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, i
         __syncthreads();
     }
     if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
-    finish_step(D, acc, a_wg + blk);
+    finish_step(D, acc, a_wg + blk, tg);
 }
 
 template <int LANES, int CAP, int TPB, int LIST>
@@ -1949,7 +1976,7 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     default: break;
     }
     hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap,
-                       tl, tc);
+                       tl, tc, H.GT + H.GA + H.GB + H.GC);
     return hipGetLastError();
 }
 
@@ -1958,9 +1985,6 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const
     const int total = H.GT + H.GA + H.GB + H.GC;
     if (H.sched == kSchedFused) {
         hipLaunchKernelGGL(k_update_fused, dim3(total), dim3(kFusedThreads), kFusedLds, s, H);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H, total);
         return hipGetLastError();
     }
     // pass streams: the wide pass on the step's stream, the huge, grouped and
@@ -2024,8 +2048,12 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const
         if (e == hipSuccess) e = hipStreamWaitEvent(s, ps->join[i], 0);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H, total);
-    (void)total;
+    return hipSuccess;
+}
+
+hipError_t launch_fold(const DevNet& H, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H);
     return hipGetLastError();
 }
 
