@@ -50,10 +50,14 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_ACTIVE = 64      # 32-byte record read + written
 BYTES_PER_LANE = 8         # lane count read + written
 # the roofline's unit: one whole step as launched in the timed region
-# (k_prepare; the update passes k_update_block and k_update_grouped, on side
-# streams unless --concurrent 0; k_fold), its time taken from the events
-# around the timed region
-STEP_LABEL = "one step: k_prepare + update passes (k_update_block, k_update_grouped) + k_fold"
+# (k_prepare, then the update: k_update_fused under the fused schedule, else
+# the per-class passes k_update_block and k_update_grouped), its time taken
+# from the events around the timed region
+
+
+def step_label(schedule_name):
+    upd = "k_update_fused" if "fused" in schedule_name else "update passes (k_update_block, k_update_grouped)"
+    return f"one step: k_prepare + {upd}"
 
 
 def log(*a):
@@ -115,12 +119,12 @@ def cpu_baseline(w, seconds=12.0):
 METRIC = "vehicle-steps/s + sim Hz at 2.46M veh; batched jobs/s, p50/p99 job latency"
 
 
-def roofline(alg_bytes, ms, steps, traffic):
+def roofline(alg_bytes, ms, steps, traffic, label):
     """Achieved bandwidth of one step: algorithmic bytes of the timed steps
     over their event-timed milliseconds."""
     achieved = alg_bytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": STEP_LABEL,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": label,
             "us_per_launch": ms / max(steps, 1) * 1e3, "bytes_per_launch": alg_bytes / max(steps, 1)}
 
 
@@ -247,7 +251,7 @@ def run_batch(args):
                    "schedule": SCHEDULES[sched], "concurrent_passes": bool(conc)},
         "vs_plain_loop": plain_ms / ms_b,
         "plain_loop": {"value": vs_b / (plain_ms / 1e3), "ms": plain_ms, "identical_results": bool(same)},
-        "roofline": roofline(alg, ms_b, steps, traffic_from_profiles(f"batch{len(ws)}")),
+        "roofline": roofline(alg, ms_b, steps, traffic_from_profiles(f"batch{len(ws)}"), step_label(SCHEDULES[sched])),
         "update_passes_us_eager": upd_ms / max(upd_n, 1) * 1e3,
     }
     print(json.dumps(out), flush=True)
@@ -461,7 +465,7 @@ def main():
     upd_ms, upd_n = kt["update"]
     prep_ms, prep_n = kt["prepare"]
     alg_bytes = BYTES_PER_ACTIVE * vsteps + BYTES_PER_LANE * w.network.n_lanes * args.steps
-    rl = roofline(alg_bytes, ms, args.steps, traffic_from_profiles(w.name))
+    rl = roofline(alg_bytes, ms, args.steps, traffic_from_profiles(w.name), step_label(SCHEDULES[sched]))
     log(f"[bench] eager launches with events: update passes {upd_ms / max(upd_n, 1) * 1e3:.1f} us/step, prepare "
         f"{prep_ms / max(prep_n, 1) * 1e3:.1f} us/step; timed steps {ms / args.steps * 1e3:.1f} us, "
         f"achieved {rl['achieved']:.1f} GB/s")
