@@ -218,7 +218,7 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
  *   7 TSIM_SCHED_FUSED   the tile classes of 6, every update pass in one
  *                        launch (workgroup ranges per class; the pass
  *                        concurrency setting does not apply)
- * Every schedule gives bit-identical results; only speed differs.  Default 1.
+ * Every schedule gives bit-identical results; only speed differs.  Default 7 (TSIM_SCHED_FUSED).
  * Changing the schedule synchronises the stream and drops a captured graph
  * (recaptured on the next tsim_step). */
 #define TSIM_SCHED_WIDE 0

@@ -990,7 +990,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
             h->res[kNumSched + 3] = cus * update_blocks_per_cu(-4);
         }
     }
-    set_sched(h, kSched16x32);
+    set_sched(h, kSchedFused);
     D.n_inst = B.n_inst;
     D.blocked = B.blocked ? 1 : 0;
     fill_params(D.P, params);
