@@ -344,6 +344,47 @@ def test_concurrent_passes_bit_identical(Sim, case, graph):
     _log(f"concurrent_{case}_graph{graph}", {"changes": int(m0["lane_changes"])})
 
 
+@pytest.mark.parametrize("sched", [7, 1])
+def test_metrics_read_between_steps_change_nothing(Sim, sched):
+    """A step's metric sums are folded by the next step's prepare kernel, or
+    on demand when the host reads metrics first: reading the metrics after
+    every few steps (eager and captured) gives the same final metrics as one
+    read at the end, for a single instance and for the same network twice in
+    a batch."""
+    from paper_2406_10661_amd.tsim import Batch
+    w = W.config1()
+    reads = []
+    for every, graph in ((None, 0), (7, 0), (7, 7), (1, 0)):
+        a = Sim(w.network, w.trips, w.params)
+        a.set_schedule(sched)
+        a.set_graph_steps(graph)
+        done = 0
+        while done < 140:
+            k = 140 - done if every is None else min(every, 140 - done)
+            a.step(k)
+            done += k
+            if every is not None:
+                m = a.metrics()
+                assert m["step"] == done
+        reads.append(a.metrics())
+        a.close()
+    for m in reads[1:]:
+        for key in ("step", "vehicle_steps", "lane_changes", "transfers", "departures", "n_finished", "errors",
+                    "sum_travel_time", "mean_speed_avg", "mean_speed_last"):
+            assert m[key] == reads[0][key], (key, m[key], reads[0][key])
+    b = Batch([w.network, w.network], [w.trips, w.trips], [w.params, w.params])
+    b.set_schedule(sched)
+    for _ in range(20):
+        b.step(7)
+        b.metrics(1)
+    for k in range(2):
+        m = b.metrics(k)
+        for key in ("step", "vehicle_steps", "lane_changes", "n_finished", "mean_speed_avg", "mean_speed_last"):
+            assert m[key] == reads[0][key], (k, key, m[key], reads[0][key])
+    b.close()
+    _log(f"metrics_reads_sched{sched}", {"vehicle_steps": int(reads[0]["vehicle_steps"])})
+
+
 def test_autotune_launch_steps_like_plain(Sim):
     """The schedule-and-concurrency autotuner also runs real steps (twice as
     many as the schedule autotuner) and leaves the chosen pair set."""
