@@ -113,7 +113,7 @@ def cpu_baseline(w, seconds=12.0):
     return {"value": vs / el, "unit": "vehicle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{w.name}: seeded synthetic state at t=3600 s with {int((st['status'] == 1).sum())} "
                       f"active vehicles, {steps} oracle steps in {el:.1f} s",
-            "hz": steps / el}
+            "hz": steps / el, "host_cpus": os.cpu_count()}
 
 
 METRIC = "vehicle-steps/s + sim Hz at 2.46M veh; batched jobs/s, p50/p99 job latency"
@@ -338,6 +338,8 @@ def run_serve(args):
                             "vs_plain_loop": summ_s["vehicle_steps_per_s"] / plain,
                             "latency_p50_s": summ_s["latency_p50_s"], "latency_p99_s": summ_s["latency_p99_s"],
                             "wall_s": summ_s["wall_s"]}
+        # share of the loop's capacity that the Poisson stream used
+        out["utilisation"] = summ["vehicle_steps_per_s"] / summ_s["vehicle_steps_per_s"]
     print(json.dumps(out), flush=True)
 
 

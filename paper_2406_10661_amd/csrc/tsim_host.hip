@@ -36,7 +36,7 @@ thread_local std::string g_error;
 
 struct Build {
     int R = 0, NJ = 0, NRL = 0, NJL = 0, NL = 0, N = 0;
-    std::vector<int32_t> tile_lane_begin, tile_n_road, tile_order;
+    std::vector<int32_t> tile_lane_begin, tile_n_road;
     std::vector<float> lane_len, lane_lim;
     std::vector<uint32_t> lane_base;
     std::vector<int32_t> lane_cap, lane_tile, lane_local, jl_out, jl_junc, jl_ext, jl_in_local, jl_out_road;
@@ -50,13 +50,12 @@ struct Build {
     std::vector<int32_t> route_begin, route, q_begin, q_veh;
     std::vector<uint32_t> q_mask;    // per queue entry: origin-road lanes that lead to its next road
     uint64_t slots = 0;
-    int G = 0;                       // partial slots: max over schedules of GA + GB
-    // tile classes by lane count (<= 8, <= 16, <= 32, more), class-major in
-    // tile_order; n_le[c] = tiles of classes 0..c
+    int G = 0;                       // partial slots: max over schedules of GT + GA + GB + GC
+    // tile classes by lane count (<= 8, <= 16, <= 32, more); n_le[c] = tiles
+    // of classes 0..c
     int n_le[4] = {0, 0, 0, 0};
     // instances of a batch (one for tsim_create)
     int n_inst = 1;
-    bool blocked = false;
     std::vector<int32_t> tile_inst, junc_inst, inst_vbase;
     std::vector<uint32_t> inst_key;
     std::vector<long long> inst_t0;
@@ -119,24 +118,13 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
     return g;
 }
 
-// tile_order: class-major (so every grouped schedule takes a prefix), then
-// by instance (batches), then larger capacity first
-void order_tiles(Build& B, bool by_instance)
+// tiles per static size class (n_le: classes 0..c), which bound the grids of
+// every schedule, and the partial-sum slots the largest grid needs
+void count_tiles(Build& B)
 {
     const int R = B.R;
-    std::vector<long long> tcap(R, 0);
-    std::vector<int> cls(R);
-    for (int r = 0; r < R; ++r) {
-        for (int m = B.tile_lane_begin[r]; m < B.tile_lane_begin[r + 1]; ++m) tcap[r] += B.lane_cap[m];
-        cls[r] = tile_class(B, r);
-    }
-    std::stable_sort(B.tile_order.begin(), B.tile_order.end(), [&](int a, int b) {
-        if (cls[a] != cls[b]) return cls[a] < cls[b];
-        if (by_instance && B.tile_inst[a] != B.tile_inst[b]) return B.tile_inst[a] < B.tile_inst[b];
-        return tcap[a] > tcap[b];
-    });
     int cnt[4] = {0, 0, 0, 0};
-    for (int r = 0; r < R; ++r) cnt[cls[r]]++;
+    for (int r = 0; r < R; ++r) cnt[tile_class(B, r)]++;
     B.n_le[0] = cnt[0];
     for (int c = 1; c < 4; ++c) B.n_le[c] = B.n_le[c - 1] + cnt[c];
     B.G = 1;
@@ -375,9 +363,7 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
             }
         }
     }
-    B.tile_order.resize(R);
-    std::iota(B.tile_order.begin(), B.tile_order.end(), 0);
-    order_tiles(B, false);
+    count_tiles(B);
     return TSIM_OK;
 }
 
@@ -385,7 +371,6 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
 void single_instance(Build& B, const tsim_params* prm)
 {
     B.n_inst = 1;
-    B.blocked = false;
     B.tile_inst.assign(B.R, 0);
     B.junc_inst.assign(B.NJ, 0);
     B.inst_vbase.assign(1, 0);
@@ -507,7 +492,6 @@ int make_union(const tsim_network* nets, const tsim_trips* trips, const tsim_par
 void batch_instances(Build& B, const Union& U, const tsim_params* prm, int n)
 {
     B.n_inst = n;
-    B.blocked = n > 1;
     B.road_off = U.road_off;
     B.junc_off = U.junc_off;
     B.rl_off = U.rl_off;
@@ -527,7 +511,7 @@ void batch_instances(Build& B, const Union& U, const tsim_params* prm, int n)
     }
     // tiles grouped by instance within each class (each workgroup takes a
     // contiguous run), larger tiles first within an instance
-    order_tiles(B, true);
+    count_tiles(B);
 }
 
 }  // namespace
@@ -582,7 +566,6 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     (void)assign;
     add(&D.tile_lane_begin, (R + 1) * 4);
     add(&D.tile_n_road, R * 4);
-    add(&D.tile_order, R * 4);
     add(&D.lane_info, NL * sizeof(LaneInfo));
     add(&D.lane_len, NL * 4);
     add(&D.lane_lim, NL * 4);
@@ -992,13 +975,11 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     }
     set_sched(h, kSchedFused);
     D.n_inst = B.n_inst;
-    D.blocked = B.blocked ? 1 : 0;
     fill_params(D.P, params);
     auto chk = [&](hipError_t e, const char* what) -> int { return e == hipSuccess ? 0 : hip_fail(h, e, what); };
     int e = 0;
     e = e ? e : chk(up(h, (int32_t*)D.tile_lane_begin, B.tile_lane_begin), "tiles");
     e = e ? e : chk(up(h, (int32_t*)D.tile_n_road, B.tile_n_road), "tiles");
-    e = e ? e : chk(up(h, (int32_t*)D.tile_order, B.tile_order), "tiles");
     e = e ? e : chk(up(h, (float*)D.lane_len, B.lane_len), "lanes");
     {
         std::vector<LaneInfo> li(B.NL);

@@ -162,7 +162,6 @@ struct DevNet {
     int32_t R, NJ, NL, N, G;     // roads, junctions, lanes, vehicles, update grid size
     // instances (a batch is the disjoint union of several networks)
     int32_t n_inst;
-    int32_t blocked;                 // 1: each workgroup takes a contiguous run of tiles
     const int32_t* tile_inst;        // [R] instance of each road tile
     const int32_t* junc_inst;        // [NJ]
     const int32_t* inst_vbase;       // [n_inst] first vehicle id of each instance
@@ -174,7 +173,6 @@ struct DevNet {
     // tiles
     const int32_t* tile_lane_begin;  // [R+1]
     const int32_t* tile_n_road;      // [R]
-    const int32_t* tile_order;       // [R]
     // lanes (internal ids)
     const LaneInfo* lane_info;       // [NL]
     const float* lane_len;
