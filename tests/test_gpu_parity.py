@@ -190,6 +190,22 @@ def test_c3_full_size_one_step(O, Sim, city):
 
 
 @pytest.mark.timeout(900)
+def test_c3_own_congested_state_one_step(O, Sim, city):
+    """The city's own congested state (t = 4,500, reached on the GPU as the
+    bench runs it: default schedule, 60-step HIP graphs), then one step on
+    both sides from that state."""
+    g = Sim(city.network, city.trips, city.params)
+    g.set_graph_steps(60)
+    g.step(4500)
+    st = g.get_state()
+    g.close()
+    assert st["step"] == 4500
+    rep = compare_one_step(O, Sim, city.network, city.trips, city.params, st)
+    _log("c3_own_state_t4500", rep)
+    assert rep["active"] > 1000000
+
+
+@pytest.mark.timeout(900)
 def test_c3_invariants_over_steps(Sim, city):
     """Properties at full size: I1-I7 after each of 20 GPU steps from a
     synthetic mid-horizon state."""
