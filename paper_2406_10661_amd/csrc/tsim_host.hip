@@ -19,6 +19,7 @@ namespace tsim {
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s);
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps);
 hipError_t launch_fold(const DevNet& H, hipStream_t s);
+hipError_t prepare_update_kernels();
 hipError_t launch_set_phases(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* ph, int n, hipStream_t s);
 hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_ext, int32_t* o_lane, float* o_x,
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
@@ -978,6 +979,9 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     fill_params(D.P, params);
     auto chk = [&](hipError_t e, const char* what) -> int { return e == hipSuccess ? 0 : hip_fail(h, e, what); };
     int e = 0;
+    // the fused update kernel's LDS (above the default dynamic limit), set
+    // whether or not the occupancy queries above ran
+    e = e ? e : chk(prepare_update_kernels(), "fused update kernel attributes");
     e = e ? e : chk(up(h, (int32_t*)D.tile_lane_begin, B.tile_lane_begin), "tiles");
     e = e ? e : chk(up(h, (int32_t*)D.tile_n_road, B.tile_n_road), "tiles");
     e = e ? e : chk(up(h, (float*)D.lane_len, B.lane_len), "lanes");

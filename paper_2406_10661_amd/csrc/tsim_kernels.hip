@@ -2078,6 +2078,11 @@ hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const
     return hipSuccess;
 }
 
+hipError_t prepare_update_kernels()
+{
+    return hipFuncSetAttribute((const void*)k_update_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds);
+}
+
 hipError_t launch_fold(const DevNet& H, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fold, dim3(1), dim3(kFoldThreads), 0, s, H);
@@ -2101,7 +2106,7 @@ int update_blocks_per_cu(int sched)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_grouped<8, 16, 8, 4, 8, 3>, 4 * kWave, 0);
         break;
     case kSchedFused:
-        e = hipFuncSetAttribute((const void*)k_update_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds);
+        e = prepare_update_kernels();
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_fused, kFusedThreads, kFusedLds);
         break;
