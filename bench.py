@@ -392,8 +392,8 @@ def main():
     ap.add_argument("--max-jobs-per-batch", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this "
-              f"build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the stepper has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         args.steps = args.steps or 1800
