@@ -19,7 +19,10 @@ from tests import simcheck as S
 
 pytestmark = pytest.mark.gpu
 
-REPORT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# one JSON line per parity case (counts, largest deviations); directory from
+# TSIM_PARITY_REPORT_DIR, else reports/ at the repository root
+REPORT = os.environ.get("TSIM_PARITY_REPORT_DIR",
+                        os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "reports"))
 
 
 @pytest.fixture(scope="module")
