@@ -192,7 +192,8 @@ int tsim_set_state(tsim_handle *h, const tsim_state_host *in);
  * every launch with HIP events on the handle's stream (a small overhead);
  * tsim_get_kernel_times synchronises and returns, per kernel, the summed
  * milliseconds and the number of launches since profiling was enabled.
- * Kernel 0 is the update kernel, kernel 1 the prepare kernel; n_kernels <= 2. */
+ * Kernel 0 is the update (every update launch of a step), kernel 1 the
+ * prepare kernel; n_kernels <= 2. */
 int tsim_set_profiling(tsim_handle *h, int32_t enable);
 int tsim_get_kernel_times(tsim_handle *h, double *ms, int64_t *launches, int32_t n_kernels);
 
@@ -232,13 +233,13 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
 #define TSIM_NUM_SCHED 8
 int tsim_set_schedule(tsim_handle *h, int32_t schedule);
 int tsim_get_schedule(tsim_handle *h, int32_t *schedule);
-/* Pass concurrency.  A step's update passes (one per class of tile size) work
- * on disjoint tiles and meet only in the final fold; with enable = 1 they are
- * launched on three side streams of the handle (default priority, ordered
- * after the step's prepare kernel and before its fold by events), so that one
- * pass's last workgroups overlap the next pass.  Results are bit-identical
- * either way.  Synchronises the stream and drops a captured graph.  Works on
- * batches too.  Default 0. */
+/* Pass concurrency (schedules 0-6).  A step's update passes (one per class of
+ * tile size) work on disjoint tiles and meet only in the step's metric sums;
+ * with enable = 1 they are launched on three side streams of the handle
+ * (default priority, ordered after the step's prepare kernel and joined
+ * before the next step by events), so that one pass's last workgroups overlap
+ * the next pass.  Results are bit-identical either way.  Synchronises the
+ * stream and drops a captured graph.  Works on batches too.  Default 0. */
 int tsim_set_concurrency(tsim_handle *h, int32_t enable);
 /* Autotuner: runs `rounds` rounds of `steps` steps under every schedule in
  * turn (these are real steps: the simulation advances by
