@@ -65,10 +65,16 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and white space removed (a
+    change to either invalidates counters taken before it)."""
+    import re
     h = hashlib.sha256()
     for f in ("tsim_kernels.hip", "tsim_internal.h"):
-        with open(os.path.join(ROOT, "paper_2406_10661_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2406_10661_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -133,8 +133,8 @@ struct KParams {
     int delta_is_4;
 };
 
-// cumulative metrics, folded once per step by the last workgroup of the
-// update kernel
+// cumulative metrics; a step's sums are folded in by the next step's prepare
+// kernel, or before the host reads them
 struct DevMetrics {
     long long step;
     long long departed;
@@ -258,8 +258,8 @@ struct DevNet {
 // Side streams on which the update passes of a step run concurrently: the
 // passes touch disjoint tiles (the feeder gates they raise in other tiles are
 // atomic min/max), so they need no order among themselves, only after the
-// prepare kernel and before the fold.  n = 0 keeps every pass on the step's
-// stream.
+// prepare kernel and before the next step.  n = 0 keeps every pass on the
+// step's stream.
 struct PassStreams {
     int n = 0;
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};

@@ -6,15 +6,17 @@
 //                     the junction-to-road entrant held in each road lane's
 //                     inbox, release due departures into the origin road's
 //                     lanes when safe, clear the feeder gates the step builds,
-//                     and put the road's tile on the step's small or wide work
-//                     list (or finish it if it has just become empty).
-//   k_update_grouped  the small list: 64 / W tiles per wavefront, a group of W
-//                     lanes per tile, tile staged in LDS.
-//   k_update_wide     the wide list (tiles of up to kWideLanes lanes and
-//                     kWideCap vehicles) and then the huge list (all others,
-//                     up to kHugeCap vehicles in LDS, more on global scratch):
-//                     one tile per wavefront; the last workgroup folds the
-//                     step's metrics.
+//                     and put the road's tile on the step's work list of its
+//                     size class (or finish it if it has just become empty);
+//                     workgroup 0 folds the previous step's metric sums and
+//                     publishes the step.
+//   k_update_fused    (default) every size class in one launch, workgroup
+//                     ranges: huge tiles (a workgroup per tile, up to
+//                     kHugeCap vehicles in LDS, more on global scratch), wide
+//                     tiles (one per wavefront), small and tiny tiles (64 / W
+//                     per wavefront, a group of W lanes per tile, staged in
+//                     LDS).  k_update_grouped / k_update_wide / k_update_block
+//                     run one class each for the other schedules.
 // Per tile: pass 1 own leader (or two-lane lookahead), lane group, stop
 // obstacle, own IDM acceleration, merge target; pass 2 randomized MOBIL
 // (Appendix B.3), Philox draw, ballistic integration with snapshot bounds,
@@ -1738,7 +1740,7 @@ constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
 
 // Wide pass: the step's wide-tile list, one tile per wavefront; up to
 // kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
-// the grouped pass's (offset a_wg).  The last workgroup folds the step.
+// the grouped pass's (offset a_wg).
 template <int LANES, int CAP, int WPB, int LIST>
 __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg)
 {
