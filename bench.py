@@ -422,7 +422,7 @@ def main():
     sim = Sim(w.network, w.trips, w.params)
     init = sim.get_state()
     log(f"[bench] device arena {sim.arena.numel() / 2**30:.2f} GiB")
-    stream = torch.cuda.current_stream()
+    stream = sim.stream   # the library's stream: every step kernel and graph launch goes there
     # schedule and pass concurrency: autotuned on the run's own state 4,500
     # steps in, outside the timed region (the state is reset to t = 0 below)
     if args.schedule is None:
