@@ -87,14 +87,14 @@ int tile_class(const Build& B, int r)
 // with few enough lanes), the wide pass over at most R; each gets no more
 // workgroups than the device keeps resident (res_a, res_b; 0 = unknown)
 struct SchedGrid {
-    int gw, nA, GA, GB, GC, GT;
+    int gw, nA, GA, GB, GC, GT, GM;
 };
 
 constexpr int kMaxGridA = 8192, kMaxGridB = 8192;
 
 SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, int res_c = 0, int res_t = 0)
 {
-    SchedGrid g{64, 0, 0, 0, 0, 0};
+    SchedGrid g{64, 0, 0, 0, 0, 0, 0};
     switch (sched) {
     case kSched8x16: g.gw = 8; g.nA = B.n_le[0]; break;
     case kSched16x32:
@@ -116,6 +116,11 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
         const int capT = res_t > 0 ? std::min(res_t, kMaxGridA) : kMaxGridA;
         g.GT = std::max(1, std::min((B.n_le[0] + 7) / 8, capT));
     }
+    // medium tiles (fused schedule): at most kWideLanes lanes, two per wavefront
+    if (sched == kSchedFused && B.n_le[2] > 0) {
+        const int capM = res_t > 0 ? std::min(res_t, kMaxGridA) : kMaxGridA;
+        g.GM = std::max(1, std::min((B.n_le[2] + 1) / 2, capM));
+    }
     return g;
 }
 
@@ -131,7 +136,7 @@ void count_tiles(Build& B)
     B.G = 1;
     for (int s = 0; s < kNumSched; ++s) {
         const SchedGrid g = sched_grid(B, s);
-        B.G = std::max(B.G, g.GA + g.GB + g.GC + g.GT);
+        B.G = std::max(B.G, g.GA + g.GB + g.GC + g.GT + g.GM);
     }
 }
 
@@ -626,7 +631,8 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.list_big, std::max<size_t>(R, 1) * 4);
     add(&D.list_huge, std::max<size_t>(R, 1) * 4);
     add(&D.list_tiny, std::max<size_t>(R, 1) * 4);
-    add(&D.list_cnt, 2 * 4 * kCntStride * 4);
+    add(&D.list_med, std::max<size_t>(R, 1) * 4);
+    add(&D.list_cnt, 2 * kNumLists * kCntStride * 4);
     add(&D.part, (size_t)B.G * sizeof(WGPartial));
     add(&D.ustep, 8);
     add(&D.fold_flag, 8);
@@ -838,7 +844,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
     HIPCHK(h, hipMemsetAsync(D.fold_flag, 0, 8, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 2 * 4 * kCntStride * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 2 * kNumLists * kCntStride * 4, h->stream));
     HIPCHK(h, up(h, D.met, Ms));
     HIPCHK(h, up(h, D.inst_acc, zacc));
     HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
@@ -883,6 +889,7 @@ static void set_sched(tsim_handle* h, int sched)
     h->D.GB = g.GB;
     h->D.GC = g.GC;
     h->D.GT = g.GT;
+    h->D.GM = g.GM;
 }
 
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,

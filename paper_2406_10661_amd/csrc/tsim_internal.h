@@ -46,6 +46,8 @@ enum Schedule {
     kNumSched = 8
 };
 constexpr int kCntStride = 32;           // work-list counters one 128-byte line apart
+constexpr int kNumLists = 5;             // small, wide, huge, tiny, medium
+constexpr int kMedCap = 64;              // medium tiles (fused schedule): at most kWideLanes lanes and 64 vehicles
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
 constexpr int kWaitSpeedFlag = 0;
@@ -238,9 +240,10 @@ struct DevNet {
     int32_t* list_big;               // [R] tiles of at most kWideLanes lanes and kWideCap vehicles
     int32_t* list_huge;              // [R] the rest
     int32_t* list_tiny;              // [R] tiles for the narrowest groups (two-width schedules)
-    int32_t* list_cnt;               // [2][4 kCntStride] by step parity: small, wide, huge, tiny (one 128-byte line each)
+    int32_t* list_med;               // [R] tiles of at most kWideLanes lanes and kMedCap vehicles (fused schedule)
+    int32_t* list_cnt;               // [2][kNumLists kCntStride] by step parity (one 128-byte line each)
     // schedule (host side; passed to the kernels as arguments)
-    int32_t sched, GA, GB, GC, GT;   // GT: workgroups of the tiny-tile pass
+    int32_t sched, GA, GB, GC, GT, GM;   // GT, GM: workgroups of the tiny and medium passes
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)

@@ -336,6 +336,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     if (n > 0) {
         if (nl <= tiny_lanes && n <= tiny_cap) out.list = 3;
         else if (nl <= small_lanes && n <= small_cap) out.list = 0;
+        else if (D.sched == kSchedFused && nl <= kWideLanes && n <= kMedCap) out.list = 4;
         else if (nl <= kWideLanes && n <= kWideCap) out.list = 1;
         else out.list = 2;
     }
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
                                                           int tiny_lanes, int tiny_cap, int total_wg)
 {
     constexpr int NW = kPrepThreads / kWave;
-    constexpr int NL = 4;
+    constexpr int NL = kNumLists;
     __shared__ int wcnt[NL][NW];
     __shared__ int base[NL];
     __shared__ long long bsum[2][NW];
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         const int L = threadIdx.x;
         int tot = 0;
         for (int w = 0; w < NW; ++w) tot += wcnt[L][w];
-        base[L] = tot ? atomicAdd(&D.list_cnt[((int)(tg & 1) * 4 + L) * kCntStride], tot) : 0;
+        base[L] = tot ? atomicAdd(&D.list_cnt[((int)(tg & 1) * kNumLists + L) * kCntStride], tot) : 0;
     } else if (threadIdx.x == NL && one) {
         long long d = 0, e = 0;
         for (int w = 0; w < NW; ++w) {
@@ -415,7 +416,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         int off = base[L];
         for (int w = 0; w < wv; ++w) off += wcnt[L][w];
         off += __popcll(m[L] & ((1ull << lane) - 1ull));
-        int32_t* list = L == 0 ? D.list_small : (L == 1 ? D.list_big : (L == 2 ? D.list_huge : D.list_tiny));
+        int32_t* list = L == 0   ? D.list_small
+                        : L == 1 ? D.list_big
+                        : L == 2 ? D.list_huge
+                        : L == 3 ? D.list_tiny
+                                 : D.list_med;
         list[off] = o.r;
     }
     if (!one && o.r >= 0) {
@@ -438,7 +443,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
             D.fold_flag[1] = total_wg;
             *D.ustep = tg;
         }
-        if (threadIdx.x < 4) D.list_cnt[((int)((tg + 1) & 1) * 4 + (int)threadIdx.x) * kCntStride] = 0;
+        if (threadIdx.x < kNumLists)
+            D.list_cnt[((int)((tg + 1) & 1) * kNumLists + (int)threadIdx.x) * kCntStride] = 0;
     }
 }
 
@@ -1544,8 +1550,8 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
     TS& S = Sg[w * NG + g];
-    const int count = D.list_cnt[((int)(tg & 1) * 4 + LIST) * kCntStride];
-    const int32_t* const list = LIST == 0 ? D.list_small : (LIST == 1 ? D.list_big : D.list_tiny);
+    const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
+    const int32_t* const list = LIST == 0 ? D.list_small : (LIST == 1 ? D.list_big : (LIST == 3 ? D.list_tiny : D.list_med));
     const int first = (blk * WPB + w) * NG;
     const int stride = nblk * WPB * NG;
     const int rounds = count > first ? (count - first + stride - 1) / stride : 0;
@@ -1751,7 +1757,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     TS& S = Sw[w];
-    const int count = D.list_cnt[((int)(tg & 1) * 4 + LIST) * kCntStride];
+    const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
@@ -1827,7 +1833,7 @@ __device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, i
     const long long tg = *D.ustep;
     const StepBufs B = step_bufs(D, tg);
     const int tid = (int)threadIdx.x;
-    const int count = D.list_cnt[((int)(tg & 1) * 4 + LIST) * kCntStride];
+    const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
@@ -1885,18 +1891,21 @@ __global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
     block_pass<LANES, CAP, TPB, LIST>(D, a_wg, (int)blockIdx.x, (int)gridDim.x, S);
 }
 
-// All update passes of a step in one launch (schedule 8x16+16x32, fused):
-// workgroups [0, GC) take the huge tiles, then GB the wide ones (four
-// wavefronts per workgroup), GA the small and GT the tiny ones; each range
+// All update passes of a step in one launch (fused schedule): workgroups
+// [0, GC) take the huge tiles, then GB the wide ones (one per wavefront, four
+// wavefronts per workgroup), GM the medium ones (two per wavefront), GA the
+// small and GT the tiny ones; each range
 // strides over its own list, the LDS of each range is carved from one
 // dynamic allocation, and the workgroups of later ranges start as earlier
 // ones finish (no launches or stream joins between the passes).
 using FusedHuge = TileLds<kMaxTileLanes, kHugeCap, kChangerCap>;
 using FusedWide = GroupedLds<kWave, kWideCap, kChangerCap, 4, kWideLanes>;
+using FusedMed = GroupedLds<32, kMedCap, 32, 4, kWideLanes>;
 using FusedSmall = GroupedLds<16, 32, 16, 4, 16>;
 using FusedTiny = GroupedLds<8, 16, 8, 4, 8>;
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kFusedLds = cmax(cmax(sizeof(FusedHuge), sizeof(FusedWide)), cmax(sizeof(FusedSmall), sizeof(FusedTiny)));
+constexpr size_t kFusedLds =
+    cmax(cmax(cmax(sizeof(FusedHuge), sizeof(FusedWide)), cmax(sizeof(FusedSmall), sizeof(FusedTiny))), sizeof(FusedMed));
 constexpr int kFusedThreads = 4 * kWave;
 static_assert(kHugeThreads == kFusedThreads, "one workgroup size for every range");
 
@@ -1916,6 +1925,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_update_fused(const DevNet D)
         return;
     }
     b -= D.GB;
+    if (b < D.GM) {
+        grouped_pass<32, kMedCap, 32, 4, kWideLanes, 4>(D, D.GA + D.GB + D.GC + D.GT, b, D.GM,
+                                                        *reinterpret_cast<FusedMed*>(fused_lds));
+        return;
+    }
+    b -= D.GM;
     if (b < D.GA) {
         grouped_pass<16, 32, 16, 4, 16, 0>(D, 0, b, D.GA, *reinterpret_cast<FusedSmall*>(fused_lds));
         return;
@@ -2005,13 +2020,13 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     default: break;
     }
     hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap,
-                       tl, tc, H.GT + H.GA + H.GB + H.GC);
+                       tl, tc, H.GT + H.GA + H.GB + H.GC + H.GM);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps)
 {
-    const int total = H.GT + H.GA + H.GB + H.GC;
+    const int total = H.GT + H.GA + H.GB + H.GC + H.GM;
     if (H.sched == kSchedFused) {
         hipLaunchKernelGGL(k_update_fused, dim3(total), dim3(kFusedThreads), kFusedLds, s, H);
         return hipGetLastError();
