@@ -216,8 +216,9 @@ int tsim_set_graph_steps(tsim_handle *h, int32_t chunk);
  *                        wavefront's next tile while it works on the current
  *   6 TSIM_SCHED_8AND16  as 5, with tiles of <= 8 lanes and <= 16 vehicles
  *                        eight per wavefront
- *   7 TSIM_SCHED_FUSED   the tile classes of 6, every update pass in one
- *                        launch (workgroup ranges per class; the pass
+ *   7 TSIM_SCHED_FUSED   the tile classes of 6 plus tiles of <= 32 lanes and
+ *                        <= 64 vehicles two per wavefront, every update pass
+ *                        in one launch (workgroup ranges per class; the pass
  *                        concurrency setting does not apply)
  * Every schedule gives bit-identical results; only speed differs.  Default 7 (TSIM_SCHED_FUSED).
  * Changing the schedule synchronises the stream and drops a captured graph
