@@ -13,9 +13,9 @@
 //   k_update_fused    (default) every size class in one launch, workgroup
 //                     ranges: huge tiles (a workgroup per tile, up to
 //                     kHugeCap vehicles in LDS, more on global scratch), wide
-//                     tiles (one per wavefront), small and tiny tiles (64 / W
-//                     per wavefront, a group of W lanes per tile, staged in
-//                     LDS).  k_update_grouped / k_update_wide / k_update_block
+//                     tiles (one per wavefront), medium, small and tiny tiles
+//                     (64 / W per wavefront, a group of W lanes per tile,
+//                     staged in LDS).  k_update_grouped / k_update_wide / k_update_block
 //                     run one class each for the other schedules.
 // Per tile: pass 1 own leader (or two-lane lookahead), lane group, stop
 // obstacle, own IDM acceleration, merge target; pass 2 randomized MOBIL
