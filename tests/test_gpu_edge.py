@@ -1,0 +1,199 @@
+"""GPU parity on tiny and degenerate scenes: one lane, one vehicle, a road
+that loops back onto itself, a permanently red signal, a vehicle outside the
+lane group of its next road, no demand, demand that has not started, demand
+that has finished.
+
+Trajectory cases walk the oracle's own trajectory and, at every step, start
+the HIP path from the oracle's state (positions and speeds as float32) and
+compare one step with the same bar as the larger parity cases (decisions
+identical away from counted near-threshold cases, x' and v' within 1e-5
+relative with scale, per-lane order identical).
+"""
+
+import numpy as np
+import pytest
+
+from paper_2406_10661_amd import workloads as W
+from tests.parity import compare_one_step
+from tests.scenes import line_network, left_turn_network, trips_for, state_from
+from tests.test_oracle_scenarios import ring_state, v_equilibrium
+
+pytestmark = pytest.mark.gpu
+
+P = W.Params()
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as O
+    O.build()
+    return O
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    from paper_2406_10661_amd.tsim import Sim
+    return Sim
+
+
+def _track(O, Sim, net, trips, st0, steps, params=P, signals=None):
+    """Step-by-step parity along the oracle's trajectory from st0; `signals`
+    = (junctions, phases) held under manual control on both sides."""
+    o = O.OracleSim(net, trips, params)
+    o.set_state(st0)
+    extra = {}
+    if signals is not None:
+        j, ph = signals
+        o.set_signal_phases(j, ph)
+        pol = np.array(net.junc_policy, np.int32)
+        phase = np.zeros(net.n_junctions, np.int32)
+        pol[j] = W.POLICY_MANUAL
+        phase[j] = ph
+        extra = dict(junc_policy=pol, junc_phase=phase)
+    g = Sim(net, trips, params)
+    tot = dict(changes=0, transfers=0, near=0, near_mismatch=0, active=0)
+    for _ in range(steps):
+        st = o.get_state()
+        if not (st["status"] == 1).any() and not (st["status"] == 0).any():
+            break
+        st["x"] = st["x"].astype(np.float32)
+        st["v"] = st["v"].astype(np.float32)
+        st.update(extra)
+        rep = compare_one_step(O, Sim, net, trips, params, st, sim=g)
+        for k in tot:
+            tot[k] += rep[k]
+        o.step(1)
+    g.close()
+    print(tot, flush=True)
+    return tot, o
+
+
+def test_ring_road_uniform_flow(O, Sim):
+    """Ten vehicles on a one-lane road that loops onto itself through one
+    junction lane: the leader of the front vehicle is found through the
+    junction lane and across the road's own rear."""
+    net, trips = W.ring_road(circumference_road=275.0, n_vehicles=10, laps=40)
+    v = v_equilibrium(30.0 - 5.0, float(np.float32(13.9)))
+    st0 = ring_state(net, 10, np.arange(10) * 30.0 + 3.0, v)
+    tot, _ = _track(O, Sim, net, trips, st0, 80)
+    assert tot["transfers"] > 10
+
+
+def test_ring_road_from_rest(O, Sim):
+    net, trips = W.ring_road(circumference_road=275.0, n_vehicles=10, laps=40)
+    rng = np.random.default_rng(3)
+    pos = np.sort(rng.uniform(0, 300.0 - 80.0, 10)) + np.arange(10) * 8.0
+    tot, _ = _track(O, Sim, net, trips, ring_state(net, 10, pos, 0.0), 80)
+    assert tot["transfers"] > 0
+
+
+def test_red_light_single_vehicle(O, Sim):
+    """One vehicle before a signal held red: it brakes to a stop in front of
+    the stop line and never enters the junction."""
+    net = line_network(lanes=1)
+    trips = trips_for([[0, 2]])
+    rol = net.road_of_lane()
+    road0_jl = {q for q in range(net.n_jlanes) if rol[net.jl_in_lane[q]] == 0}
+    pb = net.junc_phase_begin
+    red = None
+    for p in range(pb[2] - pb[1]):
+        gb = net.phase_green_begin[pb[1] + p]
+        if not road0_jl & set(net.phase_green_jl[gb:net.phase_green_begin[pb[1] + p + 1]].tolist()):
+            red = p
+    assert red is not None
+    tot, o = _track(O, Sim, net, trips, state_from(1, [0], [0.0], [12.0]), 60, signals=([1], [red]))
+    assert o.get_state()["lane"][0] == 0
+
+
+def test_wrong_lane_vehicle_changes_and_turns(O, Sim):
+    """Two-lane road whose left turn leaves from lane 0 only: a vehicle
+    starting in lane 1 changes lane, turns and ends its trip."""
+    net = left_turn_network(lanes=2, policy=W.POLICY_NONE)
+    trips = trips_for([[0, 2]])
+    tot, o = _track(O, Sim, net, trips, state_from(1, [1], [0.0], [10.0]), 200)
+    assert tot["changes"] >= 1 and o.get_state()["status"][0] == 2
+
+
+def test_free_road_single_vehicle(O, Sim):
+    net = line_network(lanes=1, length=2000.0, policy=W.POLICY_NONE)
+    trips = trips_for([[0, 2]])
+    _track(O, Sim, net, trips, state_from(1, [0], [0.0], [0.0]), 30)
+
+
+def test_three_lane_randomized_lane_changes(O, Sim):
+    """Twelve vehicles of different desired speeds on a three-lane line:
+    overtaking by the randomized lane change, Philox draws keyed by
+    (seed, step, vehicle) on both sides."""
+    net = line_network(lanes=3, length=600.0, policy=W.POLICY_NONE)
+    rng = np.random.default_rng(7)
+    n = 12
+    trips = trips_for([[0, 2]] * n, v0_factor=rng.uniform(0.6, 1.3, n))
+    lanes = rng.integers(0, 3, n)
+    xs = np.zeros(n)
+    for ln in range(3):
+        k = np.nonzero(lanes == ln)[0]
+        xs[k] = np.sort(rng.choice(np.arange(0, 400, 25), k.size, replace=False)).astype(float)
+    st0 = state_from(n, lanes, xs, rng.uniform(3.0, 12.0, n))
+    tot, _ = _track(O, Sim, net, trips, st0, 90, params=W.Params(seed=11))
+    assert tot["changes"] > 0
+
+
+def _empty_trips():
+    return W.Trips(depart_time=np.zeros(0, np.float32), route_begin=np.zeros(1, np.int32),
+                   route_roads=np.zeros(0, np.int32), v0_factor=np.zeros(0, np.float32),
+                   length=np.zeros(0, np.float32))
+
+
+@pytest.mark.parametrize("graph", [0, 7])
+def test_no_vehicles(O, Sim, graph):
+    net = line_network(lanes=2)
+    g = Sim(net, _empty_trips(), P)
+    g.set_graph_steps(graph)
+    g.step(25)
+    m = g.metrics()
+    st = g.get_state()
+    g.close()
+    assert st["step"] == 25 and st["status"].size == 0
+    for k in ("n_finished", "n_active", "n_waiting", "vehicle_steps", "lane_changes", "transfers", "departures",
+              "errors"):
+        assert m[k] == 0, k
+
+
+def test_departures_not_yet_due(O, Sim):
+    net = line_network(lanes=2)
+    trips = trips_for([[0, 2], [2], [0]], depart=[500.0, 600.0, 700.0])
+    o = O.OracleSim(net, trips, P)
+    o.step(20)
+    om = o.metrics()
+    g = Sim(net, trips, P)
+    g.step(20)
+    m = g.metrics()
+    st = g.get_state()
+    g.close()
+    assert m["n_waiting"] == om["waiting"] == 3
+    assert m["n_active"] == om["active"] == 0 and m["departures"] == 0
+    assert (st["status"] == 0).all()
+
+
+def test_finished_demand_is_a_fixed_point(O, Sim):
+    """Every vehicle has ended its trip: steps change nothing but the clock."""
+    net = line_network(lanes=2)
+    trips = trips_for([[0, 2], [2], [0]])
+    st0 = state_from(3, [-1, -1, -1], [0.0] * 3, [0.0] * 3, route_pos=[1, 0, 0], step=40, status=[2, 2, 2])
+    st0["finish_step"] = np.array([31, 17, 25], np.int32)
+    o = O.OracleSim(net, trips, P)
+    o.set_state(st0)
+    o.step(10)
+    ost = o.get_state()
+    g = Sim(net, trips, P)
+    g.set_state(st0)
+    g.step(10)
+    st = g.get_state()
+    m = g.metrics()
+    g.close()
+    assert st["step"] == ost["step"] == 50
+    for k in ("status", "lane", "route_pos", "finish_step"):
+        assert np.array_equal(st[k], ost[k]), k
+        assert np.array_equal(st[k], np.asarray(st0[k])), k
+    assert m["n_finished"] == 3
+    assert m["n_active"] == 0 and m["vehicle_steps"] == 0 and m["errors"] == 0
