@@ -1,4 +1,7 @@
-"""Tiny hand-built networks and scenes for the oracle pins."""
+"""Tiny hand-built networks and scenes for the oracle pins and the GPU
+edge-case parity tests."""
+
+import math
 
 import numpy as np
 
@@ -41,3 +44,38 @@ def state_from(n, lanes, xs, vs, route_pos=None, step=0, status=None):
               route_pos=np.zeros(n, np.int32) if route_pos is None else np.asarray(route_pos, np.int32),
               finish_step=np.full(n, -1, np.int32), step=step)
     return st
+
+
+def v_equilibrium(gap, v0, P=W.Params()):
+    """Speed at which the IDM acceleration vanishes behind a leader of equal
+    speed at the given gap (s0 + v T = gap sqrt(1 - (v / v0)^4)), by
+    bisection."""
+    lo, hi = 0.0, v0 * (1 - 1e-12)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        s_e = (P.s0 + mid * P.T) / math.sqrt(1 - (mid / v0) ** 4)
+        if s_e < gap:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def ring_state(net, n, gaps_front, v):
+    """Place n vehicles on the ring (road 0 then junction lane 0) with front
+    bumpers at the given ring coordinates."""
+    road_len = float(net.road_length[0])
+    lanes, xs, k = [], [], []
+    for s in gaps_front:
+        s = s % (road_len + float(net.jl_length[0]))
+        if s < road_len:
+            lanes.append(0); xs.append(s)
+        else:
+            lanes.append(1); xs.append(s - road_len)
+        k.append(0)
+    return state_from(n, lanes, xs, [v] * n, route_pos=k)
+
+
+def ring_coords(net, st):
+    road_len = float(net.road_length[0])
+    return np.where(st["lane"] == 0, st["x"], st["x"] + road_len)

@@ -15,8 +15,7 @@ import pytest
 
 from paper_2406_10661_amd import workloads as W
 from tests.parity import compare_one_step
-from tests.scenes import line_network, left_turn_network, trips_for, state_from
-from tests.test_oracle_scenarios import ring_state, v_equilibrium
+from tests.scenes import line_network, left_turn_network, trips_for, state_from, ring_state, v_equilibrium
 
 pytestmark = pytest.mark.gpu
 

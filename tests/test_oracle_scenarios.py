@@ -13,47 +13,14 @@ transfer + signals + lane groups), each against a fact fixed by the model:
   * free-road speed follows v' = v + a dt with the free-road IDM until v0.
 """
 
-import math
-
 import numpy as np
 import pytest
 
 from paper_2406_10661_amd import workloads as W
-from tests.scenes import line_network, left_turn_network, trips_for, state_from
+from tests.scenes import (line_network, left_turn_network, trips_for, state_from, ring_state, ring_coords,
+                          v_equilibrium)
 
 P = W.Params()
-
-
-def v_equilibrium(gap, v0):
-    lo, hi = 0.0, v0 * (1 - 1e-12)
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        s_e = (P.s0 + mid * P.T) / math.sqrt(1 - (mid / v0) ** 4)
-        if s_e < gap:
-            lo = mid
-        else:
-            hi = mid
-    return 0.5 * (lo + hi)
-
-
-def ring_state(net, n, gaps_front, v):
-    """Place n vehicles on the ring (road 0 then junction lane 0) with front
-    bumpers at the given ring coordinates."""
-    road_len = float(net.road_length[0])
-    lanes, xs, k = [], [], []
-    for s in gaps_front:
-        s = s % (road_len + float(net.jl_length[0]))
-        if s < road_len:
-            lanes.append(0); xs.append(s)
-        else:
-            lanes.append(1); xs.append(s - road_len)
-        k.append(0)
-    return state_from(n, lanes, xs, [v] * n, route_pos=k)
-
-
-def ring_coords(net, st):
-    road_len = float(net.road_length[0])
-    return np.where(st["lane"] == 0, st["x"], st["x"] + road_len)
 
 
 def test_ring_uniform_flow_is_fixed_point(oracle_lib):
