@@ -129,6 +129,8 @@ typedef struct tsim_metrics {
     int64_t departures;
     int64_t speed_steps;      /* steps with at least one road-lane vehicle */
     int64_t errors;           /* device-detected capacity/ordering violations */
+    int64_t lane_steps;       /* sum over steps of lanes holding a vehicle at the step start */
+    int64_t road_entries;     /* junction-lane-to-road crossings (the vehicle moves to its next road) */
 } tsim_metrics;
 
 /* Vehicle state for checkpoint/resume and tests (host arrays of n_vehicles,

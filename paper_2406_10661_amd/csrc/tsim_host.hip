@@ -1458,6 +1458,8 @@ static int metrics_impl(tsim_handle* h, int inst, tsim_metrics* out)
     out->departures = M.dep_events;
     out->speed_steps = M.speed_steps;
     out->errors = M.errors;
+    out->lane_steps = M.lane_steps;
+    out->road_entries = M.road_entries;
     return M.errors ? TSIM_ESTATE : TSIM_OK;
 }
 

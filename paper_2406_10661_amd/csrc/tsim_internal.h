@@ -150,15 +150,20 @@ struct DevMetrics {
     long long errors;
     long long speed_steps;
     long long dep_events;    // departures since create / set_state
+    long long lane_steps;    // sum over steps of lanes holding vehicles at the step start
+    long long road_entries;  // junction-to-road crossings (each reads one route word)
     double speed_acc;
     double mean_speed_last;
 };
 
 // per-workgroup partial sums of one step
 struct WGPartial {
-    long long sumv_fx, cnt, active, changes, transfers, clamps, feeder_blocks, finished, sum_tt_fx, errors;
+    long long sumv_fx, cnt, active, changes, transfers, clamps, feeder_blocks, finished, sum_tt_fx, errors,
+        lanes_busy, road_entries;
 };
-static_assert(sizeof(WGPartial) == 80, "the fold reads partials as five 16-byte words");
+constexpr int kPartWords = 12;
+static_assert(sizeof(WGPartial) == 8 * kPartWords && kPartWords % 2 == 0,
+              "the fold reads partials as 16-byte words");
 
 struct DevNet {
     int32_t R, NJ, NL, N, G;     // roads, junctions, lanes, vehicles, update grid size

@@ -491,7 +491,7 @@ struct TileLds {
     unsigned long long sumv;
     unsigned long long sum_tt;
     int cntv;
-    int changes, transfers, clamps, fblocks, finished, errors;
+    int changes, transfers, clamps, fblocks, finished, errors, entries;
     VehRec rec[CAP];
     float aown[CAP];
     float lrear[CAP];
@@ -823,7 +823,7 @@ __device__ __forceinline__ void reset_counters(TS& S, const Hdr& h)
     S.nmerge = 0;
     S.sumv = 0ull;
     S.cntv = 0;
-    S.changes = S.transfers = S.clamps = S.fblocks = S.finished = S.errors = 0;
+    S.changes = S.transfers = S.clamps = S.fblocks = S.finished = S.errors = S.entries = 0;
     S.sum_tt = 0ull;
 }
 
@@ -1179,6 +1179,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
                     if (atomicCAS(&D.inbox_flag[g], 0, 1) != 0) atomicAdd(&S.errors, 1);
                     D.inbox[g] = o;
                     atomicAdd(&S.transfers, 1);
+                    atomicAdd(&S.entries, 1);
                 }
             }
         }
@@ -1359,9 +1360,10 @@ template <int GW, class TS>
 __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt, int n,
                                             WGPartial& acc)
 {
-    int c = 0;
+    int c = 0, busy = 0;
     if (gt < h.nl) {
         const int m = h.lb + gt;
+        busy = S.cnt[gt] > 0 ? 1 : 0;
         c = S.nstay[gt] + S.nin[gt] + S.nenter[gt];
         B.wsum[m].cnt = c < S.cap[gt] ? c : S.cap[gt];
         if (c == 0) {
@@ -1376,12 +1378,19 @@ __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, 
     int tot = c;
     if constexpr (GW <= kWave) {
 #pragma unroll
-        for (int off = 1; off < GW; off <<= 1) tot += __shfl_xor(tot, off, GW);
+        for (int off = 1; off < GW; off <<= 1) {
+            tot += __shfl_xor(tot, off, GW);
+            busy += __shfl_xor(busy, off, GW);
+        }
     }
     if (gt == 0) {
         if constexpr (GW > kWave) {
             tot = 0;
-            for (int q = 0; q < h.nl; ++q) tot += S.nstay[q] + S.nin[q] + S.nenter[q];
+            busy = 0;
+            for (int q = 0; q < h.nl; ++q) {
+                tot += S.nstay[q] + S.nin[q] + S.nenter[q];
+                busy += S.cnt[q] > 0 ? 1 : 0;
+            }
         }
         B.wtn[h.r] = tot;
         D.road_speed[h.r] = S.cntv > 0 ? (float)((double)(long long)S.sumv / (double)kSpeedFx / (double)S.cntv) : -1.0f;
@@ -1395,6 +1404,8 @@ __device__ __forceinline__ void finish_tile(const DevNet& D, const StepBufs& B, 
         acc.finished += S.finished;
         acc.sum_tt_fx += (long long)S.sum_tt;
         acc.errors += S.errors;
+        acc.lanes_busy += busy;
+        acc.road_entries += S.entries;
     }
 }
 
@@ -1403,7 +1414,7 @@ __device__ __forceinline__ void flush_acc(const DevNet& D, WGPartial& acc, int i
     if (inst < 0) return;
     unsigned long long* q = (unsigned long long*)&D.inst_acc[inst];
     const long long* a = (const long long*)&acc;
-    for (int k = 0; k < 10; ++k)
+    for (int k = 0; k < kPartWords; ++k)
         if (a[k]) atomicAdd(q + k, (unsigned long long)a[k]);
     acc = WGPartial{};
 }
@@ -1429,16 +1440,16 @@ __device__ __forceinline__ void finish_step(const DevNet& D, const WGPartial& ac
 template <int NT>
 __device__ void fold_step(const DevNet& D, int total_wg)
 {
-    __shared__ long long red[NT / kWave][10];
+    __shared__ long long red[NT / kWave][kPartWords];
     const long long fs = *D.ustep;
     const int tid = threadIdx.x;
     if (D.n_inst > 1) {
         for (int i = tid; i < D.n_inst; i += NT) {
             if (fs - D.inst_t0[i] >= D.inst_end[i]) continue;   // frozen instance
             long long* q = (long long*)&D.inst_acc[i];
-            long long a[10];
+            long long a[kPartWords];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) {
+            for (int k = 0; k < kPartWords; ++k) {
                 a[k] = q[k];
                 q[k] = 0;
             }
@@ -1450,6 +1461,8 @@ __device__ void fold_step(const DevNet& D, int total_wg)
             M->feeder_blocks += a[6];
             M->finished += a[7];
             M->sum_tt_fx += a[8];
+            M->lane_steps += a[10];
+            M->road_entries += a[11];
             if (a[9]) atomicAdd((unsigned long long*)&M->errors, (unsigned long long)a[9]);
             if (a[1] > 0) {
                 M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
@@ -1461,30 +1474,30 @@ __device__ void fold_step(const DevNet& D, int total_wg)
             M->step = fs - D.inst_t0[i] + 1;
         }
     } else {
-        long long a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        // partials are 80 bytes (five 16-byte words) at 16-byte alignment
+        long long a[kPartWords] = {};
+        // partials are kPartWords / 2 16-byte words at 16-byte alignment
 #pragma unroll 4
         for (int g = tid; g < total_wg; g += NT) {
             const longlong2* q = (const longlong2*)&D.part[g];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
+            for (int k = 0; k < kPartWords / 2; ++k) {
                 const longlong2 x = q[k];
                 a[2 * k] += x.x;
                 a[2 * k + 1] += x.y;
             }
         }
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
+        for (int k = 0; k < kPartWords; ++k) {
             for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
         }
         if (tid % kWave == 0) {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) red[tid / kWave][k] = a[k];
+            for (int k = 0; k < kPartWords; ++k) red[tid / kWave][k] = a[k];
         }
         __syncthreads();
         if (tid == 0) {
             for (int w = 1; w < NT / kWave; ++w)
-                for (int k = 0; k < 10; ++k) a[k] += red[w][k];
+                for (int k = 0; k < kPartWords; ++k) a[k] += red[w][k];
             DevMetrics* M = D.met;
             M->vehicle_steps += a[2];
             M->lane_changes += a[3];
@@ -1493,6 +1506,8 @@ __device__ void fold_step(const DevNet& D, int total_wg)
             M->feeder_blocks += a[6];
             M->finished += a[7];
             M->sum_tt_fx += a[8];
+            M->lane_steps += a[10];
+            M->road_entries += a[11];
             if (a[9]) atomicAdd((unsigned long long*)&M->errors, (unsigned long long)a[9]);
             if (a[1] > 0) {
                 M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
@@ -1729,7 +1744,7 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
         for (int q = 0; q < WPB * NG; ++q) {
             long long* a = (long long*)&tot;
             const long long* b = (const long long*)&gacc[q];
-            for (int k = 0; k < 10; ++k) a[k] += b[k];
+            for (int k = 0; k < kPartWords; ++k) a[k] += b[k];
         }
     }
     finish_step(D, tot, a_wg + blk, tg);
@@ -1812,7 +1827,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
         for (int q = 0; q < WPB; ++q) {
             long long* a = (long long*)&tot;
             const long long* b = (const long long*)&wacc[q];
-            for (int k = 0; k < 10; ++k) a[k] += b[k];
+            for (int k = 0; k < kPartWords; ++k) a[k] += b[k];
         }
     }
     finish_step(D, tot, a_wg + (int)blockIdx.x, tg);

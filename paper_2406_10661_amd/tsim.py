@@ -51,7 +51,8 @@ class tsim_metrics(C.Structure):
                 ("sum_travel_time", C.c_double), ("att", C.c_double), ("mean_speed_last", C.c_double),
                 ("mean_speed_avg", C.c_double), ("vehicle_steps", C.c_int64), ("lane_changes", C.c_int64),
                 ("transfers", C.c_int64), ("clamps", C.c_int64), ("feeder_blocks", C.c_int64),
-                ("departures", C.c_int64), ("speed_steps", C.c_int64), ("errors", C.c_int64)]
+                ("departures", C.c_int64), ("speed_steps", C.c_int64), ("errors", C.c_int64),
+                ("lane_steps", C.c_int64), ("road_entries", C.c_int64)]
 
 
 class tsim_state_host(C.Structure):
