@@ -27,9 +27,13 @@
  * implements them (tagged [reading]).
  *
  * Parity pins: IDM closed forms, Philox against rocRAND's host engine,
- * brute-force MOBIL scenes, ring-road equilibrium, red-light stop, and the
+ * brute-force MOBIL scenes, ring-road equilibrium, red-light stop, the
  * per-step invariants (no overlap, v >= 0, conservation, per-lane order,
- * no entry on red, lane group kept, no lane change on junction lanes).
+ * no entry on red, lane group kept, no lane change on junction lanes), and
+ * hand-derived tiny scenes for the departure rules (most room, room >= s0,
+ * tau <= t dt, one per lane, blocked head, feeder reach), merge priority,
+ * travelling time, mean speed and its horizon average, lane queue length
+ * and cooperative yielding, each shown to fail under a named mistake.
  */
 #include <math.h>
 #include <stdint.h>
@@ -89,6 +93,7 @@ typedef struct osim {
     double *road_sumv;           /* [R] last step */
     int *road_cnt;               /* [R] */
     int *lane_wait;              /* [NL] */
+    double *vend;                /* [N] end-of-step speed of the last step (active vehicles) */
     /* diagnostics of the last step */
     double *margin;              /* [N * NMARGIN] */
     double *mobil;               /* [N * 4]: u_L, u_R, u_T, p_LC */
@@ -283,6 +288,7 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
     s->road_sumv = (double *)xcalloc(R, sizeof(double));
     s->road_cnt = (int *)xcalloc(R, sizeof(int));
     s->lane_wait = (int *)xcalloc(NL, sizeof(int));
+    s->vend = (double *)xcalloc(N, sizeof(double));
     s->margin = (double *)xcalloc((size_t)N * NMARGIN, sizeof(double));
     s->mobil = (double *)xcalloc((size_t)N * 4, sizeof(double));
     s->decision = (int *)xcalloc(N, sizeof(int));
@@ -299,7 +305,7 @@ void osim_destroy(osim *s)
                     s->feed_begin, s->feed_jl, s->tau, s->f, s->L, s->route_begin, s->route, s->q_begin,
                     s->q_veh, s->status, s->lane, s->k, s->finish_step, s->x, s->v, s->n_status, s->n_lane,
                     s->n_k, s->n_x, s->n_v, s->sorted, s->lane_start, s->lane_cnt, s->green, s->road_sumv,
-                    s->road_cnt, s->lane_wait, s->margin, s->mobil, s->decision, s->event};
+                    s->road_cnt, s->lane_wait, s->vend, s->margin, s->mobil, s->decision, s->event};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
     free(s);
 }
@@ -937,7 +943,17 @@ static void step_once(osim *s)
             s->road_sumv[s->lane_road[l]] += vn;
             s->road_cnt[s->lane_road[l]] += 1;
         }
-        if (vn < 0.1) s->lane_wait[l] += 1;
+        s->vend[i] = vn;
+    }
+    /* U6 lane queue length (Section 3.3: vehicles waiting to be released at
+     * the end of the lane) [reading]: the unbroken run of vehicles, counted
+     * from the front of the lane in the snapshot order, whose end-of-step
+     * speed is below 0.1 m/s; a stopped vehicle behind a moving one is not in
+     * the queue at the lane end */
+    for (int m = 0; m < s->NL; ++m) {
+        int q = 0;
+        while (q < s->lane_cnt[m] && s->vend[LANE(s, m)[q]] < 0.1) q++;
+        s->lane_wait[m] = q;
     }
     (void)reach_extra;
     /* metrics of the step */

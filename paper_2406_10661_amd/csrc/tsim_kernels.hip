@@ -481,7 +481,7 @@ struct TileLds {
     int nin[LANES];
     int nenter[LANES];
     int mcnt[LANES];       // vehicles whose merge target is this lane
-    int wait[LANES];
+    int wait[LANES];       // queue at the lane end: first snapshot rank whose end-of-step speed is >= 0.1
     int nlanes, nroad, n;
     int nchg, nmerge;
     float chg_x[CHG];
@@ -778,7 +778,8 @@ __device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs
     const bool jl = gt >= h.nroad;
     const LaneInfo L = D.lane_info[m];
     S.lane[gt] = m;
-    S.cnt[gt] = B.rsum[m].cnt;
+    const int c0 = B.rsum[m].cnt;
+    S.cnt[gt] = c0;
     S.base[gt] = L.base;
     S.cap[gt] = L.cap;
     S.len[gt] = L.len;
@@ -787,7 +788,7 @@ __device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs
     S.nin[gt] = 0;
     S.nenter[gt] = 0;
     S.mcnt[gt] = 0;
-    S.wait[gt] = 0;
+    S.wait[gt] = c0;
     S.jl_out[gt] = L.jl_out;
     S.jl_out_road[gt] = L.jl_out_road;
     S.jl_in_local[gt] = L.jl_in_local;
@@ -1189,7 +1190,10 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             sv_acc += (long long)llrintf(vn * kSpeedFx);
             cv_acc += 1;
         }
-        if (vn < 0.1f) atomicAdd(&S.wait[li], 1);
+        // lane queue length (Section 3.3, waiting at the lane end): the run
+        // of vehicles from the lane front, in snapshot order, slower than
+        // 0.1 m/s at the step end ends at the first faster one
+        if (!(vn < 0.1f)) atomicMin(&S.wait[li], c);
         view.set2(j, xn, vn, kind, tgt_local);
         if (kind == 0) {
             atomicAdd(&S.nstay[li], 1);
@@ -1678,7 +1682,7 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
             S.nin[gt] = 0;
             S.nenter[gt] = 0;
             S.mcnt[gt] = 0;
-            S.wait[gt] = 0;
+            S.wait[gt] = pcnt;
             S.jl_out[gt] = pL.jl_out;
             S.jl_out_road[gt] = pL.jl_out_road;
             S.jl_in_local[gt] = pL.jl_in_local;

@@ -79,3 +79,19 @@ def ring_state(net, n, gaps_front, v):
 def ring_coords(net, st):
     road_len = float(net.road_length[0])
     return np.where(st["lane"] == 0, st["x"], st["x"] + road_len)
+
+
+def merge_network(length=200.0, limit=13.9, policy=W.POLICY_NONE):
+    """Two one-lane roads merging: J0 (0, 100) -> J2 (100, 0) is road 0 and
+    J1 (0, -100) -> J2 is road 2; both continue straight (within 45 degrees)
+    into road 4, J2 -> J3 (400, 0), so two junction lanes feed road 4's lane."""
+    xy = np.array([[0.0, 100.0], [0.0, -100.0], [100.0, 0.0], [400.0, 0.0]])
+    return W._build_network(xy, np.array([[0, 2], [1, 2], [2, 3]]), [length] * 3, [1, 1, 1],
+                            [limit] * 3, policy=policy)
+
+
+def jl_between(net, lane_in, lane_out):
+    """Junction-lane index from road lane lane_in to road lane lane_out."""
+    q = np.nonzero((net.jl_in_lane == lane_in) & (net.jl_out_lane == lane_out))[0]
+    assert q.size == 1
+    return int(q[0])
