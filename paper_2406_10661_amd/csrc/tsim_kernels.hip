@@ -52,11 +52,19 @@ __device__ __forceinline__ void tile_sync()
     else wave_sync();
 }
 
+// A leader at rear bumper a + b in the follower's lane coordinate.  The IDM
+// gap is formed as (a - x) + b: for a leader on the follower's own lane a is
+// its front and b minus its length, so a - x is exact for nearby vehicles and
+// the gap is rounded at its own magnitude, not at that of the positions; for
+// a leader on a later lane a is the distance to that lane's start and b its
+// rear there.
 struct Lead {
-    float rear;  // rear bumper in the follower's lane coordinate
+    float a, b;
     float v;
     bool ex;
 };
+__device__ __forceinline__ float lead_rear(const Lead& L) { return L.a + L.b; }
+__device__ __forceinline__ float lead_gap(const Lead& L, float x) { return (L.a - x) + L.b; }
 
 __device__ __forceinline__ bool ahead(float xa, int va, float xb, int vb)
 {
@@ -112,7 +120,7 @@ __device__ __forceinline__ float idm_freeroad(float v, float v0, const KParams& 
 
 __device__ __forceinline__ float accel(float v, float v0, float x, Lead ld, bool stop, float len, const KParams& P)
 {
-    float a = ld.ex ? idm_follow(v, v0, ld.rear - x, v - ld.v, P) : idm_freeroad(v, v0, P);
+    float a = ld.ex ? idm_follow(v, v0, lead_gap(ld, x), v - ld.v, P) : idm_freeroad(v, v0, P);
     if (stop) a = fminf(a, idm_follow(v, v0, len - x, v, P));
     return a;
 }
@@ -676,21 +684,23 @@ template <class TS, class V>
 __device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const LaneSum* sum, int li, int q, int rp,
                           int rem)
 {
-    Lead L{TS_INF, 0.0f, false};
+    Lead L{TS_INF, 0.0f, 0.0f, false};
     const float off = S.len[li];
     if (li < S.nroad) {
         if (q < 0) return L;
         if (S.cnt[q] > 0) {
             const VehRec z = view.rec(S.start[q] + S.cnt[q] - 1);
             L.ex = true;
-            L.rear = off + (z.x - z.len);
+            L.a = off;
+            L.b = z.x - z.len;
             L.v = z.v;
             return L;
         }
         const LaneSum s2 = S.osum[q];
         if (s2.cnt > 0) {
             L.ex = true;
-            L.rear = (off + S.len[q]) + s2.rear;
+            L.a = off + S.len[q];
+            L.b = s2.rear;
             L.v = s2.rear_v;
         }
         return L;
@@ -698,7 +708,8 @@ __device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const Lan
     const LaneSum s1 = S.osum[li];
     if (s1.cnt > 0) {
         L.ex = true;
-        L.rear = off + s1.rear;
+        L.a = off;
+        L.b = s1.rear;
         L.v = s1.rear_v;
         return L;
     }
@@ -709,7 +720,8 @@ __device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const Lan
     const LaneSum s2 = sum[g2];
     if (s2.cnt > 0) {
         L.ex = true;
-        L.rear = (off + D.lane_len[g1]) + s2.rear;
+        L.a = off + D.lane_len[g1];
+        L.b = s2.rear;
         L.v = s2.rear_v;
     }
     return L;
@@ -869,7 +881,8 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         if (c > 0) {
             const VehRec z = view.rec(j - 1);
             ld.ex = true;
-            ld.rear = z.x - z.len;
+            ld.a = z.x;
+            ld.b = -z.len;
             ld.v = z.v;
         } else {
             ld = lookahead(D, S, view, rsum, li, q0, rec.rp, rec.rem);
@@ -889,7 +902,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
                 }
             if (bl >= 0) mt = bl < li ? li - 1 : li + 1;
         }
-        view.set1(j, gmask, a, mt, ld.ex ? ld.rear : TS_INF, ld.v, stop, jqp);
+        view.set1(j, gmask, a, mt, ld.ex ? lead_rear(ld) : TS_INF, ld.v, stop, jqp);
         if (mt >= 0) {
             atomicAdd(&S.mcnt[mt], 1);
             const int k = atomicAdd(&S.nmerge, 1);
@@ -938,7 +951,8 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             o.u = -TS_INF;
             o.ta = 0.0f;
             o.lead.ex = false;
-            o.lead.rear = TS_INF;
+            o.lead.a = TS_INF;
+            o.lead.b = 0.0f;
             o.lead.v = 0.0f;
             if (is_jl) return o;
             const int k = li + d;
@@ -964,16 +978,17 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             Lead tld;
             if (tl >= 0) {
                 tld.ex = true;
-                tld.rear = tlr.x - tlr.len;
+                tld.a = tlr.x;
+                tld.b = -tlr.len;
                 tld.v = tlr.v;
             } else {
                 tld = lookahead(D, S, view, rsum, k, jq_get(jqp, d), rec.rp, rec.rem);
             }
-            const float g3 = tld.ex ? tld.rear - rec.x : TS_INF;
+            const float g3 = tld.ex ? lead_gap(tld, rec.x) : TS_INF;
             if (!(g3 > 0.0f)) return o;
             const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
             if (tf >= 0 && !tf_yields) {
-                const float g4 = rec.x - rec.len - tfr.x - (tfr.v * P.dt + P.reach);
+                const float g4 = ((rec.x - tfr.x) - rec.len) - (tfr.v * P.dt + P.reach);
                 if (!(g4 >= 0.0f)) return o;
             }
             if (tf < 0) {
@@ -989,7 +1004,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             float d_new = 0.0f, d_old = 0.0f;
             if (tf >= 0) {
                 const float a_tf = view.aown(tf);
-                const Lead me_lead{rec.x - rec.len, rec.v, true};
+                const Lead me_lead{rec.x, -rec.len, rec.v, true};
                 const float ta_tf = accel(tfr.v, tfr.f * lim, tfr.x, me_lead, view.stopf(tf), len, P);
                 if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
                 d_new = ta_tf - a_tf;
@@ -1002,7 +1017,8 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
                     if (c > 0) {
                         const VehRec z = view.rec(j - 1);
                         ol.ex = true;
-                        ol.rear = z.x - z.len;
+                        ol.a = z.x;
+                        ol.b = -z.len;
                         ol.v = z.v;
                     } else {
                         ol = lookahead(D, S, view, rsum, li, jq_get(view.jq(j + 1), 0), ofr.rp, ofr.rem);
@@ -1113,10 +1129,11 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         if (dec) {
             const Lead l2 = dec == 1 ? eL.lead : eR.lead;
             if (l2.ex) {
-                if (l2.rear < Bd) {
-                    Bd = l2.rear;
+                const float r2 = lead_rear(l2);
+                if (r2 < Bd) {
+                    Bd = r2;
                     vcap = l2.v;
-                } else if (l2.rear == Bd) {
+                } else if (r2 == Bd) {
                     vcap = fminf(vcap, l2.v);
                 }
             }
