@@ -50,6 +50,16 @@ extern "C" {
 #define TSIM_POLICY_NONE 0       /* every junction lane always green */
 #define TSIM_POLICY_FIXED_TIME 1 /* phases in order with their durations, phase 0 at t = 0 */
 #define TSIM_POLICY_MANUAL 2     /* phase set through tsim_set_signal_phases */
+/* Adaptive maximum pressure (Section 3.2, the cited maximum-pressure
+ * algorithm; Appendix B.2: lane pressures in the prepare phase).  A
+ * movement (junction lane from road lane a to road lane b) has pressure
+ * n(a) - n(b), n = vehicles on the lane at the step start before the step's
+ * departures; a phase's pressure is the sum over the movements it makes
+ * green; the junction takes the largest (ties to the lowest phase index).
+ * It decides at the steps t with floor(t dt / d0) > floor((t - 1) dt / d0),
+ * d0 the duration of its first phase (t = 0, then every d0 seconds), and
+ * holds the phase in between (tsim_state_host.junc_phase).  Needs d0 > 0. */
+#define TSIM_POLICY_MAX_PRESSURE 3
 
 /* vehicle status */
 #define TSIM_WAITING 0
@@ -144,7 +154,7 @@ typedef struct tsim_state_host {
     float *v;                 /* speed, m/s */
     int32_t *finish_step;     /* step during which the trip ended, else -1 */
     int32_t *junc_policy;     /* [n_junctions] */
-    int32_t *junc_phase;      /* [n_junctions] MANUAL phase index */
+    int32_t *junc_phase;      /* [n_junctions] MANUAL phase index, or the phase a MAX_PRESSURE junction holds */
 } tsim_state_host;
 
 typedef struct tsim_handle tsim_handle;
@@ -168,6 +178,14 @@ int tsim_step(tsim_handle *h, int32_t n_steps);
  * the stream without waiting; the host arrays may be reused on return. */
 int tsim_set_signal_phases(tsim_handle *h, const int32_t *junction_ids, const int32_t *phase_index,
                            int32_t n);
+
+/* Junctions junction_ids[c] take signal policy policy[c] (TSIM_POLICY_*)
+ * from the next step on (Section 3.2 set_tl_policy).  A junction switched to
+ * MAX_PRESSURE holds its stored phase (tsim_state_host.junc_phase) until its
+ * next decision step.  Enqueued on the stream; TSIM_EINVAL for an unknown
+ * junction or policy, or a max-pressure junction whose first phase has no
+ * positive duration.  The host arrays may be reused on return. */
+int tsim_set_signal_policy(tsim_handle *h, const int32_t *junction_ids, const int32_t *policy, int32_t n);
 
 /* Synchronises the stream, then fills *out. */
 int tsim_get_metrics(tsim_handle *h, tsim_metrics *out);
@@ -291,6 +309,9 @@ int tsim_batch_set_graph_steps(tsim_batch *b, int32_t chunk);
 int tsim_batch_set_horizon(tsim_batch *b, int32_t instance, int64_t n_steps);
 int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
                                  const int32_t *phase_index, int32_t n);
+/* As tsim_set_signal_policy, for the junctions of one instance. */
+int tsim_batch_set_signal_policy(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
+                                 const int32_t *policy, int32_t n);
 /* Every junction of every instance at once: phase_index[k] for the k-th
  * junction of the batch in instance order (instance 0's junctions first), a
  * negative entry leaves that junction unchanged; non-negative entries switch

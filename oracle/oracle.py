@@ -51,6 +51,8 @@ def lib():
         L.osim_set_state.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 6
         L.osim_set_signal_phases.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_policy.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.osim_set_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.osim_get_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_get_metrics.argtypes = [C.c_void_p, C.c_void_p]
         L.osim_get_road_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_get_lane_waiting.argtypes = [C.c_void_p, C.c_void_p]
@@ -153,6 +155,20 @@ class OracleSim:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(policies, np.int32)
         lib().osim_set_policy(self.h, int(j.size), _p(j), _p(p))
+
+    def set_junctions(self, policy, phase):
+        """Policy and phase of every junction (MANUAL phase, or the phase in
+        force of a MAX_PRESSURE junction)."""
+        p = np.ascontiguousarray(policy, np.int32)
+        ph = np.ascontiguousarray(phase, np.int32)
+        assert p.size == ph.size == self.net.n_junctions
+        lib().osim_set_junctions(self.h, _p(p), _p(ph))
+
+    def junctions(self):
+        p = np.zeros(self.net.n_junctions, np.int32)
+        ph = np.zeros(self.net.n_junctions, np.int32)
+        lib().osim_get_junctions(self.h, _p(p), _p(ph))
+        return p, ph
 
     def metrics(self):
         out = np.zeros(16, np.float64)

@@ -41,7 +41,7 @@
 #include <string.h>
 
 enum { WAITING = 0, ACTIVE = 1, FINISHED = 2 };
-enum { POL_NONE = 0, POL_FIXED = 1, POL_MANUAL = 2 };
+enum { POL_NONE = 0, POL_FIXED = 1, POL_MANUAL = 2, POL_MAX_PRESSURE = 3 };
 enum { EV_TRANSFER = 1, EV_FINISH = 2, EV_FEEDER_BLOCK = 4, EV_CLAMP = 8, EV_DEPART = 16 };
 
 #define NMARGIN 6
@@ -69,7 +69,7 @@ typedef struct osim {
     int *jl_junction;          /* [NJL] */
     int *junc_phase_begin, *phase_green_begin, *phase_green_jl;
     double *phase_dur;
-    int *policy, *manual_phase;  /* [NJ] */
+    int *policy, *manual_phase;  /* [NJ]; manual_phase is also the phase in force of a MAX_PRESSURE junction */
     int *out_begin, *out_jl;     /* [NRL+1], junction lanes leaving a road lane (global ids) */
     int *feed_begin, *feed_jl;   /* [NRL+1], junction lanes entering a road lane, ascending */
     /* trips */
@@ -510,11 +510,55 @@ static int yield_leader(const osim *s, int i)
 /* ------------------------------------------------------------------------ */
 /* P1 signals (Section 3.2 traffic-signal policies)                          */
 /* ------------------------------------------------------------------------ */
-static int current_phase(const osim *s, int j)
+
+static void build_index(osim *s);
+
+/* MAX_PRESSURE (Section 3.2; the maximum-pressure algorithm of Varaiya 2013
+ * that the paper cites; Appendix B.2: lane pressures in the prepare phase,
+ * the junction's phase update from them) [reading]:
+ *   - the pressure of a movement (a junction lane g from road lane in(g) to
+ *     road lane out(g)) is n(in(g)) - n(out(g)), n(l) the number of vehicles
+ *     on road lane l at the start of the step, before its departures;
+ *   - the pressure of a phase is the sum over the movements it makes green;
+ *   - the junction takes the phase of largest pressure, ties to the lowest
+ *     phase index;
+ *   - it decides only at the steps t in which a multiple of the duration of
+ *     its first phase falls (floor(t dt / d0) > floor((t - 1) dt / d0), so
+ *     at t = 0 and then every d0 seconds) and holds the phase in between. */
+static int max_pressure_decides(const osim *s, int j)
+{
+    double d0 = s->phase_dur[s->junc_phase_begin[j]];
+    if (!(d0 > 0.0)) return 1;
+    return floor((double)s->t * s->P.dt / d0) > floor((double)(s->t - 1) * s->P.dt / d0);
+}
+
+static int max_pressure_phase(const osim *s, int j)
+{
+    int b = s->junc_phase_begin[j], e = s->junc_phase_begin[j + 1];
+    int best = 0;
+    long best_p = 0;
+    for (int p = b; p < e; ++p) {
+        long pr = 0;
+        for (int k = s->phase_green_begin[p]; k < s->phase_green_begin[p + 1]; ++k) {
+            int g = s->phase_green_jl[k];
+            pr += (long)s->lane_cnt[s->jl_in[g]] - (long)s->lane_cnt[s->jl_out[g]];
+        }
+        if (p == b || pr > best_p) { best_p = pr; best = p - b; }
+    }
+    return best;
+}
+
+/* phase in force at junction j for step t (needs the lane counts of the step
+ * start for MAX_PRESSURE junctions, which it may update) */
+static int current_phase(osim *s, int j)
 {
     int b = s->junc_phase_begin[j], e = s->junc_phase_begin[j + 1];
     if (e == b) return -1;
     if (s->policy[j] == POL_MANUAL) return s->manual_phase[j];
+    if (s->policy[j] == POL_MAX_PRESSURE) {
+        if (max_pressure_decides(s, j)) s->manual_phase[j] = max_pressure_phase(s, j);
+        return s->manual_phase[j];
+    }
     /* FIXED_TIME: phases in order, starting with phase 0 at t = 0 */
     double cycle = 0.0;
     for (int p = b; p < e; ++p) cycle += s->phase_dur[p];
@@ -765,8 +809,8 @@ static void step_once(osim *s)
         s->event[i] = 0;
     }
     /* prepare */
-    update_signals(s);
     build_index(s);
+    update_signals(s);
     departures(s);
     build_index(s);
 
@@ -1027,6 +1071,22 @@ void osim_set_policy(osim *s, int n, const int *junction, const int *policy)
     for (int c = 0; c < n; ++c) s->policy[junction[c]] = policy[c];
 }
 
+/* policy and phase of every junction (the phase is the MANUAL phase, or the
+ * phase in force of a MAX_PRESSURE junction; ignored otherwise) */
+void osim_set_junctions(osim *s, const int *policy, const int *phase)
+{
+    for (int j = 0; j < s->NJ; ++j) {
+        s->policy[j] = policy[j];
+        s->manual_phase[j] = phase[j];
+    }
+}
+
+void osim_get_junctions(const osim *s, int *policy, int *phase)
+{
+    memcpy(policy, s->policy, s->NJ * sizeof(int));
+    memcpy(phase, s->manual_phase, s->NJ * sizeof(int));
+}
+
 /* out[NMETRIC]: t, waiting, active, finished, sum_tt, att, mean_speed_last,
  * mean_speed_avg, vehicle_steps, lane_changes, transfers, clamps,
  * feeder_blocks, departures, speed_steps, 0 */
@@ -1060,6 +1120,7 @@ void osim_get_green(const osim *s, unsigned char *out) { memcpy(out, s->green, s
 /* signal state for step t without stepping (P1 for the current t) */
 void osim_eval_signals(osim *s, unsigned char *out)
 {
+    build_index(s);
     update_signals(s);
     memcpy(out, s->green, s->NJL);
 }

@@ -25,6 +25,7 @@ hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_
                          float* o_v, int32_t* o_rpos, int32_t* o_rank, hipStream_t s);
 hipError_t launch_import(const DevNet* Dd, const DevNet& H, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
 hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s);
+hipError_t launch_set_policy(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* pol, int n, hipStream_t s);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
 int update_blocks_per_cu(int sched);
 }  // namespace tsim
@@ -45,6 +46,7 @@ struct Build {
     std::vector<int32_t> out_begin, out_jl, feed_begin, feed_jl;
     std::vector<int32_t> int_of_ext, ext_of_int;
     std::vector<int32_t> junc_phase_begin, junc_policy;
+    std::vector<int32_t> mp_begin, mp_mov;   // movements per junction: (in, out, green mask, 0) internal lanes
     std::vector<float> phase_dur;
     std::vector<double> junc_cycle;
     std::vector<float> tau, vf, vlen;
@@ -222,7 +224,9 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
         const int b = net->junc_phase_begin[j], e = net->junc_phase_begin[j + 1];
         if (e < b || e - b > kMaxPhases) return fail(err, TSIM_EINVAL, "junction " + std::to_string(j) + ": 0..32 phases");
         const int pol = net->junc_policy[j];
-        if (pol < 0 || pol > 2) return fail(err, TSIM_EINVAL, "bad policy");
+        if (pol < 0 || pol > 3) return fail(err, TSIM_EINVAL, "bad policy");
+        if (pol == TSIM_POLICY_MAX_PRESSURE && e > b && !(net->phase_duration[b] > 0))
+            return fail(err, TSIM_EINVAL, "max-pressure junction with a non-positive first phase duration");
         double cyc = 0.0;
         for (int p = b; p < e; ++p) {
             if (pol == TSIM_POLICY_FIXED_TIME && !(net->phase_duration[p] > 0))
@@ -329,6 +333,20 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
             const int a = B.int_of_ext[net->jl_in_lane[q]], b = B.int_of_ext[net->jl_out_lane[q]];
             B.out_jl[B.out_begin[a] + fo[a]++] = B.int_of_ext[NRL + q];
             B.feed_jl[B.feed_begin[b] + ff[b]++] = B.int_of_ext[NRL + q];
+        }
+    }
+    // movements of each junction for the max-pressure policy
+    B.mp_begin.assign(NJ + 1, 0);
+    for (int q = 0; q < NJL; ++q) B.mp_begin[jl_junc_ext[q] + 1]++;
+    for (int j = 0; j < NJ; ++j) B.mp_begin[j + 1] += B.mp_begin[j];
+    B.mp_mov.assign(4 * (size_t)NJL, 0);
+    {
+        std::vector<int> fill(NJ, 0);
+        for (int q = 0; q < NJL; ++q) {
+            const int k = B.mp_begin[jl_junc_ext[q]] + fill[jl_junc_ext[q]]++;
+            B.mp_mov[4 * k] = B.int_of_ext[net->jl_in_lane[q]];
+            B.mp_mov[4 * k + 1] = B.int_of_ext[net->jl_out_lane[q]];
+            B.mp_mov[4 * k + 2] = (int32_t)mask_ext[q];
         }
     }
     // vehicles and departure queues (tau, id) per origin road
@@ -591,6 +609,8 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.feed_begin, (NL + 1) * 4);
     add(&D.feed_jl, std::max<size_t>(NJL, 1) * 4);
     add(&D.junc_phase_begin, (NJ + 1) * 4);
+    add(&D.mp_begin, (NJ + 1) * 4);
+    add(&D.mp_mov, std::max<size_t>(NJL, 1) * 16);
     add(&D.phase_dur, std::max<size_t>(B.phase_dur.size(), 1) * 4);
     add(&D.junc_cycle, NJ * 8);
     add(&D.junc_policy, NJ * 4);
@@ -704,6 +724,20 @@ void fill_params(KParams& P, const tsim_params* p)
     P.key0 = (uint32_t)p->seed;
     P.key1 = (uint32_t)(p->seed >> 32);
     P.delta_is_4 = p->delta == 4.0 ? 1 : 0;
+}
+
+// whether the step launches k_signals (some junction may use MAX_PRESSURE);
+// a captured graph that launches otherwise is dropped (recaptured on the next
+// step)
+void set_mp_any(tsim_handle* h, bool any)
+{
+    if ((h->D.mp_any != 0) == any) return;
+    if (h->graph) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    h->D.mp_any = any ? 1 : 0;
 }
 
 // uploads a full state: per-lane orders are rebuilt on the host
@@ -840,6 +874,7 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     HIPCHK(h, up(h, D.status, st));
     HIPCHK(h, up(h, D.finish_step, fs));
     HIPCHK(h, up(h, D.junc_policy, jp));
+    set_mp_any(h, std::any_of(jp.begin(), jp.end(), [](int32_t p) { return p == TSIM_POLICY_MAX_PRESSURE; }));
     HIPCHK(h, up(h, D.junc_manual, jm));
     HIPCHK(h, up(h, D.q_head, qhead));
     HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
@@ -1034,6 +1069,8 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     e = e ? e : chk(up(h, (int32_t*)D.feed_begin, B.feed_begin), "conn");
     e = e ? e : chk(up(h, (int32_t*)D.feed_jl, B.feed_jl), "conn");
     e = e ? e : chk(up(h, (int32_t*)D.junc_phase_begin, B.junc_phase_begin), "junctions");
+    e = e ? e : chk(up(h, (int32_t*)D.mp_begin, B.mp_begin), "junctions");
+    e = e ? e : chk(up(h, (int32_t*)D.mp_mov, B.mp_mov), "junctions");
     e = e ? e : chk(up(h, (float*)D.phase_dur, B.phase_dur), "junctions");
     e = e ? e : chk(up(h, (double*)D.junc_cycle, B.junc_cycle), "junctions");
     e = e ? e : chk(up(h, (float*)D.tau, B.tau), "trips");
@@ -1405,6 +1442,51 @@ int tsim_batch_set_signal_phases(tsim_batch* b, int32_t instance, const int32_t*
     return set_phases_impl(b, instance, junction_ids, phase_index, n);
 }
 
+static int set_policy_impl(tsim_handle* h, int inst, const int32_t* junction_ids, const int32_t* policy, int32_t n)
+{
+    if (!h || n < 0 || (n && (!junction_ids || !policy))) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = h->B;
+    if (inst < 0 || inst >= B.n_inst) return fail(&h->err, TSIM_EINVAL, "instance out of range");
+    if (n == 0) return TSIM_OK;
+    const int jo = B.junc_off[inst], nj = B.junc_off[inst + 1] - jo;
+    if (n > nj) return fail(&h->err, TSIM_EINVAL, "more updates than junctions");
+    std::vector<int32_t> ids(n), pol(n);
+    bool mp = false;
+    for (int c = 0; c < n; ++c) {
+        const int j = junction_ids[c];
+        if (j < 0 || j >= nj) return fail(&h->err, TSIM_EINVAL, "junction id out of range");
+        if (policy[c] < 0 || policy[c] > 3) return fail(&h->err, TSIM_EINVAL, "bad policy");
+        const int pb = B.junc_phase_begin[jo + j], np = B.junc_phase_begin[jo + j + 1] - pb;
+        if (policy[c] == TSIM_POLICY_MAX_PRESSURE && np > 0 && !(B.phase_dur[pb] > 0))
+            return fail(&h->err, TSIM_EINVAL, "max-pressure junction with a non-positive first phase duration");
+        mp |= policy[c] == TSIM_POLICY_MAX_PRESSURE;
+        ids[c] = jo + j;
+        pol[c] = policy[c];
+    }
+    if (mp) set_mp_any(h, true);
+    int32_t* hp = nullptr;
+    int32_t* dp = nullptr;
+    int rc = stage_slot(h, &hp, &dp);
+    if (rc) return rc;
+    std::memcpy(hp, ids.data(), (size_t)n * 4);
+    std::memcpy(hp + B.NJ, pol.data(), (size_t)n * 4);
+    HIPCHK(h, hipMemcpyAsync(dp, hp, (size_t)2 * B.NJ * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_set_policy(h->d_net, h->D, dp, dp + B.NJ, n, h->stream));
+    HIPCHK(h, hipEventRecord(h->pin_ev[h->pin_slot ^ 1], h->stream));
+    return TSIM_OK;
+}
+
+int tsim_set_signal_policy(tsim_handle* h, const int32_t* junction_ids, const int32_t* policy, int32_t n)
+{
+    return set_policy_impl(h, 0, junction_ids, policy, n);
+}
+
+int tsim_batch_set_signal_policy(tsim_batch* b, int32_t instance, const int32_t* junction_ids, const int32_t* policy,
+                                 int32_t n)
+{
+    return set_policy_impl(b, instance, junction_ids, policy, n);
+}
+
 int tsim_batch_set_horizon(tsim_batch* b, int32_t instance, int64_t n_steps)
 {
     if (!b || instance < 0 || instance >= b->B.n_inst || n_steps < 0)
@@ -1594,10 +1676,14 @@ int tsim_set_state(tsim_handle* h, const tsim_state_host* in)
         !in->junc_policy || !in->junc_phase || in->step < 0 || h->B.n_inst != 1)
         return fail(nullptr, TSIM_EINVAL, "bad arguments");
     for (int j = 0; j < h->B.NJ; ++j) {
-        if (in->junc_policy[j] < 0 || in->junc_policy[j] > 2) return fail(&h->err, TSIM_EINVAL, "bad policy");
-        const int np = h->B.junc_phase_begin[j + 1] - h->B.junc_phase_begin[j];
-        if (in->junc_policy[j] == TSIM_POLICY_MANUAL && (in->junc_phase[j] < 0 || in->junc_phase[j] >= np))
-            return fail(&h->err, TSIM_EINVAL, "manual phase out of range");
+        const int pol = in->junc_policy[j];
+        if (pol < 0 || pol > 3) return fail(&h->err, TSIM_EINVAL, "bad policy");
+        const int pb = h->B.junc_phase_begin[j], np = h->B.junc_phase_begin[j + 1] - pb;
+        if ((pol == TSIM_POLICY_MANUAL || pol == TSIM_POLICY_MAX_PRESSURE) && np > 0 &&
+            (in->junc_phase[j] < 0 || in->junc_phase[j] >= np))
+            return fail(&h->err, TSIM_EINVAL, "manual or held phase out of range");
+        if (pol == TSIM_POLICY_MAX_PRESSURE && np > 0 && !(h->B.phase_dur[pb] > 0))
+            return fail(&h->err, TSIM_EINVAL, "max-pressure junction with a non-positive first phase duration");
     }
     return upload_state(h, in->step, in->status, in->lane, in->route_pos, in->x, in->v, in->finish_step, in->junc_policy,
                         in->junc_phase);

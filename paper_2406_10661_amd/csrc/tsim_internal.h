@@ -202,10 +202,12 @@ struct DevNet {
     const int32_t* feed_jl;
     // junctions
     const int32_t* junc_phase_begin; // [NJ+1]
+    const int32_t* mp_begin;         // [NJ+1] movements (junction lanes) of each junction
+    const int4* mp_mov;              // (in road lane, out road lane, green phase mask, 0), internal lane ids
     const float* phase_dur;
     const double* junc_cycle;
     int32_t* junc_policy;
-    int32_t* junc_manual;
+    int32_t* junc_manual;            // MANUAL phase, or the phase a MAX_PRESSURE junction holds
     int32_t* junc_cur;               // phase index of the current step, -1 = all green
     // vehicles
     const float* tau;
@@ -249,6 +251,7 @@ struct DevNet {
     int32_t* list_cnt;               // [2][kNumLists kCntStride] by step parity (one 128-byte line each)
     // schedule (host side; passed to the kernels as arguments)
     int32_t sched, GA, GB, GC, GT, GM;   // GT, GM: workgroups of the tiny and medium passes
+    int32_t mp_any;                  // host side: some junction may use MAX_PRESSURE (k_signals is launched)
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty
     int32_t* lane_wait;              // [NL] (internal ids)

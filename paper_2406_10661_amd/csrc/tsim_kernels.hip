@@ -206,7 +206,9 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         int cur = -1;
         const int pol = D.junc_policy[i];
         if (pol != 0 && e > b) {
-            if (pol == 2) {
+            if (pol == 2 || pol == 3) {
+                // MANUAL, or the phase a MAX_PRESSURE junction holds (decided
+                // by k_signals before this kernel)
                 cur = D.junc_manual[i];
             } else {
                 const double cyc = D.junc_cycle[i];
@@ -2040,9 +2042,64 @@ __global__ void k_import(const DevNet D, const uint32_t* slots, const VehRec* re
     slab[slots[i]] = recs[i];
 }
 
+// MAX_PRESSURE signals (Section 3.2 policy list; Appendix B.2: lane pressures
+// computed in the prepare phase, junction phases updated from them).  One
+// thread per junction, launched before k_prepare while some junction may use
+// the policy, so that the lane counts it reads are those of the step start
+// (the summaries the last update wrote, plus the entrant waiting in each
+// lane's inbox) before any departure or inbox merge of the step.  A
+// movement's pressure is n(in lane) - n(out lane), a phase's the sum over the
+// movements it makes green; the largest wins, ties to the lowest phase.  A
+// junction decides only at the steps in which a multiple of its first phase's
+// duration falls (t = 0, then every d0 seconds) and holds the phase in
+// junc_manual in between, which the prepare kernel reads like a MANUAL phase.
+constexpr int kSignalThreads = 256;
+
+__global__ __launch_bounds__(kSignalThreads) void k_signals(const DevNet D)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= D.NJ || D.junc_policy[j] != 3) return;
+    const int inst = D.junc_inst[j];
+    const long long tg = *D.gstep;
+    const long long t = tg - D.inst_t0[inst];
+    if (!(t < D.inst_end[inst])) return;
+    const int b = D.junc_phase_begin[j], e = D.junc_phase_begin[j + 1];
+    if (e == b) return;
+    const double d0 = (double)D.phase_dur[b];
+    if (d0 > 0.0 && !(floor((double)t * D.P.dt_d / d0) > floor((double)(t - 1) * D.P.dt_d / d0))) return;
+    const LaneSum* sum = (tg & 1) ? D.sum1 : D.sum0;
+    const int mb = D.mp_begin[j], me = D.mp_begin[j + 1];
+    int best = 0;
+    long long best_p = 0;
+    for (int p = 0; p < e - b; ++p) {
+        long long pr = 0;
+        for (int k = mb; k < me; ++k) {
+            const int4 mv = D.mp_mov[k];
+            if (!(((uint32_t)mv.z >> p) & 1u)) continue;
+            pr += (long long)(sum[mv.x].cnt + D.inbox_flag[mv.x]) - (long long)(sum[mv.y].cnt + D.inbox_flag[mv.y]);
+        }
+        if (p == 0 || pr > best_p) {
+            best_p = pr;
+            best = p;
+        }
+    }
+    D.junc_manual[j] = best;
+}
+
+// signal policies of some junctions (host-staged ids and policies)
+__global__ void k_set_policy(const DevNet D, const int32_t* ids, const int32_t* pol, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    D.junc_policy[ids[i]] = pol[i];
+}
+
 // launch wrappers (host side); Dd is the device copy of the view, H the host copy
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
 {
+    if (H.mp_any)
+        hipLaunchKernelGGL(k_signals, dim3((H.NJ + kSignalThreads - 1) / kSignalThreads), dim3(kSignalThreads), 0, s,
+                           H);
     const int n = H.R + H.NJ;
     int lanes = 0, cap = 0, tl = 0, tc = 0;
     switch (H.sched) {
@@ -2191,6 +2248,12 @@ int update_blocks_per_cu(int sched)
 hipError_t launch_set_phases(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* ph, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_phases, dim3((n + 255) / 256), dim3(256), 0, s, H, ids, ph, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_policy(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* pol, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_policy, dim3((n + 255) / 256), dim3(256), 0, s, H, ids, pol, n);
     return hipGetLastError();
 }
 

@@ -69,7 +69,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_footprint", "tsim_batch_create", "tsim_batch_step", "tsim_batch_set_signal_phases",
            "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
-           "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency", "tsim_autotune_launch"]
+           "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency", "tsim_autotune_launch",
+           "tsim_set_signal_policy", "tsim_batch_set_signal_policy"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -87,6 +88,8 @@ def lib():
         L.tsim_create.argtypes = [P, P, P, P, P, C.c_size_t, C.POINTER(C.c_void_p)]
         L.tsim_step.argtypes = [P, C.c_int32]
         L.tsim_set_signal_phases.argtypes = [P, P, P, C.c_int32]
+        L.tsim_set_signal_policy.argtypes = [P, P, P, C.c_int32]
+        L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_get_metrics.argtypes = [P, P]
         L.tsim_get_road_mean_speed.argtypes = [P, P, C.c_int32]
         L.tsim_get_lane_waiting_counts.argtypes = [P, P, C.c_int32]
@@ -206,6 +209,13 @@ class Sim:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(phases, np.int32)
         _check(lib().tsim_set_signal_phases(self.h, _p(j), _p(p), int(j.size)), self.h)
+
+    def set_signal_policy(self, junctions, policies):
+        """Signal policy per junction (TSIM_POLICY_*: 0 none, 1 fixed time,
+        2 manual, 3 max pressure) from the next step on."""
+        j = np.ascontiguousarray(junctions, np.int32)
+        p = np.ascontiguousarray(policies, np.int32)
+        _check(lib().tsim_set_signal_policy(self.h, _p(j), _p(p), int(j.size)), self.h)
 
     def metrics(self, check=True):
         m = tsim_metrics()
@@ -369,6 +379,11 @@ class Batch:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(phases, np.int32)
         _check(lib().tsim_batch_set_signal_phases(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
+
+    def set_signal_policy(self, instance, junctions, policies):
+        j = np.ascontiguousarray(junctions, np.int32)
+        p = np.ascontiguousarray(policies, np.int32)
+        _check(lib().tsim_batch_set_signal_policy(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
 
     def set_horizon(self, instance, n_steps):
         """Freeze instance after n_steps local steps (the others go on)."""

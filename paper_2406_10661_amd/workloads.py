@@ -36,6 +36,7 @@ from scipy.sparse.csgraph import dijkstra, connected_components, minimum_spannin
 POLICY_NONE = 0
 POLICY_FIXED_TIME = 1
 POLICY_MANUAL = 2
+POLICY_MAX_PRESSURE = 3
 
 JUNCTION_LANE_LENGTH = 25.0
 TURN_STRAIGHT_DEG = 45.0

@@ -35,12 +35,7 @@ def oracle_one_step(O, net, trips, params, st):
     s64["v"] = np.asarray(st["v"], np.float32).astype(np.float64)
     o.set_state(s64)
     if "junc_policy" in st:
-        man = np.nonzero(st["junc_policy"] == 2)[0]
-        if man.size:
-            o.set_signal_phases(man, st["junc_phase"][man])
-        none = np.nonzero(st["junc_policy"] == 0)[0]
-        if none.size:
-            o.set_policy(none, np.zeros(none.size, np.int32))
+        o.set_junctions(st["junc_policy"], st["junc_phase"])
     o.step(1)
     return o
 
@@ -143,6 +138,15 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None):
         assert int(gm["n_finished"]) == int(om["finished"])
         assert abs(gm["mean_speed_last"] - om["mean_speed_last"]) <= 1e-5 * max(1.0, om["mean_speed_last"])
     assert gm["errors"] == 0
+    # signal state after the step: policies, and the phase every MANUAL or
+    # MAX_PRESSURE junction holds (decided from the step-start lane counts,
+    # which no decision of this step changes)
+    if "junc_policy" in st:
+        opol, oph = o.junctions()
+        assert np.array_equal(gst["junc_policy"], opol), "junction policies differ"
+        held = (opol == 2) | (opol == 3)
+        assert np.array_equal(gst["junc_phase"][held], oph[held]), "held junction phases differ"
+        rep["max_pressure_junctions"] = int((opol == 3).sum())
     rep["gpu_metrics"] = gm
     rep["oracle_metrics"] = om
     return rep

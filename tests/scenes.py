@@ -95,3 +95,15 @@ def jl_between(net, lane_in, lane_out):
     q = np.nonzero((net.jl_in_lane == lane_in) & (net.jl_out_lane == lane_out))[0]
     assert q.size == 1
     return int(q[0])
+
+
+def plus_network(length=200.0, limit=13.9, policy=W.POLICY_FIXED_TIME):
+    """A four-way junction J4 at (200, 200) with arms to J0 (west), J1 (east),
+    J2 (south) and J3 (north), one lane each way.  Roads 0, 2, 4, 6 enter J4
+    (from J0, J1, J2, J3); roads 1, 3, 5, 7 leave it (to J0, J1, J2, J3).
+    J4 has one phase per approach in in-road order: phase 0 = road 0, 1 =
+    road 2, 2 = road 4, 3 = road 6, each with its three movements (left,
+    straight, right; no U-turn)."""
+    xy = np.array([[0.0, 200.0], [400.0, 200.0], [200.0, 0.0], [200.0, 400.0], [200.0, 200.0]])
+    return W._build_network(xy, np.array([[0, 4], [1, 4], [2, 4], [3, 4]]), [length] * 4, [1] * 4,
+                            [limit] * 4, policy=policy)

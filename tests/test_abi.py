@@ -40,6 +40,8 @@ def test_footprint_valid_config1(L):
     w = W.config1()
     nb = T.footprint(w.network, w.trips, w.params)
     assert nb > 0
+    w.network.junc_policy[:] = W.POLICY_MAX_PRESSURE
+    assert T.footprint(w.network, w.trips, w.params) == nb
 
 
 def _broken(mut):
@@ -57,6 +59,8 @@ def _broken(mut):
     ("bad policy", lambda n, t, p: n.junc_policy.__setitem__(0, 7)),
     ("bad dt", lambda n, t, p: setattr(p, "dt", 0.0)),
     ("foreign phase lane", lambda n, t, p: n.phase_green_jl.__setitem__(0, n.n_jlanes - 1)),
+    ("max pressure without a first phase duration",
+     lambda n, t, p: (n.junc_policy.__setitem__(0, 3), n.phase_duration.__setitem__(n.junc_phase_begin[0], 0.0))),
 ])
 def test_footprint_rejects(L, name, mut):
     net, trips, params = _broken(mut)

@@ -130,6 +130,49 @@ def test_manual_signals_one_step(O, Sim):
     _log("c1_manual_signals", rep)
 
 
+@pytest.mark.parametrize("step", [90, 91])
+def test_max_pressure_one_step(O, Sim, step):
+    """Half the junctions of a loaded 4x4 grid under MAX_PRESSURE (the rest
+    fixed-time or manual), each entering the step with a random held phase:
+    at t = 90 (a multiple of the 30 s first phase: every max-pressure junction
+    decides from the lane counts) and t = 91 (they hold).  Vehicles and the
+    phases held after the step are compared with the oracle."""
+    w = W.config1()
+    st = synthetic_state(w.network, w.trips, step, seed=8, p_active=0.8)
+    rng = np.random.default_rng(step)
+    nph = np.diff(w.network.junc_phase_begin)
+    st["junc_policy"] = np.where(rng.random(w.network.n_junctions) < 0.5, 3,
+                                 rng.integers(1, 3, w.network.n_junctions)).astype(np.int32)
+    st["junc_phase"] = (rng.integers(0, 1000, w.network.n_junctions) % nph).astype(np.int32)
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st)
+    _log(f"c1_max_pressure_t{step}", rep)
+    assert rep["max_pressure_junctions"] >= 5
+
+
+def test_max_pressure_horizon_statistics(O, Sim):
+    """Every junction of the 4x4 grid under MAX_PRESSURE (set through the
+    ABI at t = 0) for the 600-step horizon: completed trips and time-averaged
+    mean road speed within 1% of the oracle's."""
+    w = W.config1()
+    nj = w.network.n_junctions
+    o = O.OracleSim(w.network, w.trips, w.params)
+    o.set_junctions(np.full(nj, 3, np.int32), np.zeros(nj, np.int32))
+    o.step(w.n_steps)
+    om = o.metrics()
+    g = Sim(w.network, w.trips, w.params)
+    g.set_signal_policy(np.arange(nj), np.full(nj, 3))
+    g.step(w.n_steps)
+    gm = g.metrics()
+    gst = g.get_state()
+    rep = dict(oracle_finished=om["finished"], gpu_finished=gm["n_finished"],
+               oracle_speed=om["mean_speed_avg"], gpu_speed=gm["mean_speed_avg"])
+    _log("c1_max_pressure_horizon", rep)
+    assert np.all(gst["junc_policy"] == 3)
+    assert gm["errors"] == 0
+    assert abs(gm["n_finished"] - om["finished"]) <= 0.01 * om["finished"]
+    assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
+
+
 def test_c1_horizon_statistics(O, Sim):
     """Full 600-step run from t = 0 on both sides: completed trips and the
     time-averaged mean road speed agree within 1%."""
