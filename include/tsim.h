@@ -319,8 +319,22 @@ int tsim_batch_set_signal_policy(tsim_batch *b, int32_t instance, const int32_t 
 int tsim_batch_set_all_phases(tsim_batch *b, const int32_t *phase_index, int32_t n_total);
 /* Synchronises the stream, then fills *out for one instance. */
 int tsim_batch_get_metrics(tsim_batch *b, int32_t instance, tsim_metrics *out);
-/* State of one instance (arrays sized for that instance). */
+/* State of one instance (arrays sized for that instance, instance-local
+ * vehicle, lane and junction ids).  An instance frozen by its horizon reports
+ * the state it was frozen in. */
 int tsim_batch_get_state(tsim_batch *b, int32_t instance, tsim_state_host *out);
+/* Replaces the state of one instance at the batch's step boundary (as
+ * tsim_set_state, instance-local arrays).  The instance continues from its
+ * own step in->step while the rest of the batch is untouched; the batch's
+ * pending step is folded first.  Synchronises the stream.  Its horizon, if
+ * set, stays in local steps. */
+int tsim_batch_set_state(tsim_batch *b, int32_t instance, const tsim_state_host *in);
+/* Per-instance forms of tsim_get_road_mean_speed, tsim_get_lane_waiting_counts
+ * and tsim_get_lane_order (sizes and ids local to the instance). */
+int tsim_batch_get_road_mean_speed(tsim_batch *b, int32_t instance, float *out, int32_t n_roads);
+int tsim_batch_get_lane_waiting_counts(tsim_batch *b, int32_t instance, int32_t *out, int32_t n_lanes);
+int tsim_batch_get_lane_order(tsim_batch *b, int32_t instance, int32_t *offsets, int32_t *vehicle_ids,
+                              int32_t n_lanes, int32_t max_ids);
 int tsim_batch_destroy(tsim_batch *b);
 
 #ifdef __cplusplus

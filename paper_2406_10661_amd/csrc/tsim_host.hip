@@ -740,41 +740,96 @@ void set_mp_any(tsim_handle* h, bool any)
     h->D.mp_any = any ? 1 : 0;
 }
 
-// uploads a full state: per-lane orders are rebuilt on the host
-int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int32_t* lane_ext, const int32_t* route_pos,
-                 const float* x, const float* v, const int32_t* finish_step, const int32_t* pol, const int32_t* ph)
+// index ranges of instance k of a batch inside the union (k = -1: the whole
+// handle): roads (= tiles), junctions, vehicles, internal lanes, and the
+// external road-lane and junction-lane ranges
+struct Ranges {
+    int r0, r1, j0, j1, v0, v1, m0, m1, rl0, nrl, jl0, njl;
+};
+
+Ranges ranges_of(const Build& B, int k)
+{
+    if (k < 0) return Ranges{0, B.R, 0, B.NJ, 0, B.N, 0, B.NL, 0, B.NRL, 0, B.NJL};
+    Ranges g;
+    g.r0 = B.road_off[k];
+    g.r1 = B.road_off[k + 1];
+    g.j0 = B.junc_off[k];
+    g.j1 = B.junc_off[k + 1];
+    g.v0 = B.veh_off[k];
+    g.v1 = B.veh_off[k + 1];
+    g.m0 = B.tile_lane_begin[g.r0];
+    g.m1 = B.tile_lane_begin[g.r1];
+    g.rl0 = B.rl_off[k];
+    g.nrl = B.rl_off[k + 1] - g.rl0;
+    g.jl0 = B.jl_off[k];
+    g.njl = B.jl_off[k + 1] - g.jl0;
+    return g;
+}
+
+// external lane id of the union from an instance-local one, and back
+int union_lane(const Build& B, const Ranges& g, int l)
+{
+    return l < g.nrl ? g.rl0 + l : B.NRL + g.jl0 + (l - g.nrl);
+}
+int local_lane(const Build& B, const Ranges& g, int e)
+{
+    return e < B.NRL ? e - g.rl0 : (e - B.NRL - g.jl0) + g.nrl;
+}
+
+template <class T>
+hipError_t up_at(tsim_handle* h, T* dst, const std::vector<T>& src)
+{
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync((void*)dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, h->stream);
+}
+
+// uploads the state of instance k (k = -1: the whole handle) from
+// instance-local arrays: per-lane orders are rebuilt on the host.  With
+// k = -1 the handle's step counter becomes `step`; otherwise the instance
+// joins the batch's running step count with its own local step `step`
+// (every array indexed by global step parity keeps working), after the
+// pending step of the batch is folded.
+int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, const int32_t* lane_loc,
+                 const int32_t* route_pos, const float* x, const float* v, const int32_t* finish_step,
+                 const int32_t* pol, const int32_t* ph)
 {
     Build& B = h->B;
     DevNet& D = h->D;
-    const int N = B.N;
-    std::vector<std::vector<int>> per_lane(B.NL);
-    long long departed = 0, finished = 0;
-    long long sum_tt = 0;
-    for (int i = 0; i < N; ++i) {
-        const int s = status[i];
+    const Ranges g = ranges_of(B, k);
+    const int nv = g.v1 - g.v0, nm = g.m1 - g.m0, nr = g.r1 - g.r0, nj = g.j1 - g.j0;
+    std::vector<std::vector<int>> per_lane(nm);
+    const int nl_loc = g.nrl + g.njl;
+    for (int il = 0; il < nv; ++il) {
+        const int i = g.v0 + il;
+        const int s = status[il];
         if (s < 0 || s > 2) return fail(&h->err, TSIM_EINVAL, "bad status");
         if (s == TSIM_ACTIVE) {
-            const int e = lane_ext[i];
-            if (e < 0 || e >= B.NL) return fail(&h->err, TSIM_EINVAL, "active vehicle without a valid lane");
+            const int l = lane_loc[il];
+            if (l < 0 || l >= nl_loc) return fail(&h->err, TSIM_EINVAL, "active vehicle without a valid lane");
             const int rl = B.route_begin[i + 1] - B.route_begin[i];
-            const int k = route_pos[i];
-            if (k < 0 || k >= rl) return fail(&h->err, TSIM_EINVAL, "route position out of range");
-            const int m = B.int_of_ext[e];
+            const int kk = route_pos[il];
+            if (kk < 0 || kk >= rl) return fail(&h->err, TSIM_EINVAL, "route position out of range");
+            const int m = B.int_of_ext[union_lane(B, g, l)];
             const int r = B.lane_tile[m];
-            if (B.route[B.route_begin[i] + k] != r) return fail(&h->err, TSIM_EINVAL, "lane not on the current road");
-            if (B.jl_out[m] >= 0 && (k + 1 >= rl || B.jl_out_road[m] != B.route[B.route_begin[i] + k + 1]))
+            if (B.route[B.route_begin[i] + kk] != r) return fail(&h->err, TSIM_EINVAL, "lane not on the current road");
+            if (B.jl_out[m] >= 0 && (kk + 1 >= rl || B.jl_out_road[m] != B.route[B.route_begin[i] + kk + 1]))
                 return fail(&h->err, TSIM_EINVAL, "junction lane not toward the next road");
-            if (!(x[i] >= 0.0f && x[i] <= B.lane_len[m]) || !(v[i] >= 0.0f))
+            if (!(x[il] >= 0.0f && x[il] <= B.lane_len[m]) || !(v[il] >= 0.0f))
                 return fail(&h->err, TSIM_EINVAL, "position or speed out of range");
-            per_lane[m].push_back(i);
+            per_lane[m - g.m0].push_back(i);
         }
-        if (s != TSIM_WAITING) departed++;
-        if (s == TSIM_FINISHED) {
-            finished++;
-            const double tt = (double)(finish_step[i] + 1) * h->D.P.dt_d - (double)B.tau[i];
-            sum_tt += llrint(tt * kTimeFx);
-        }
+        if (s == TSIM_FINISHED && finish_step[il] < 0) return fail(&h->err, TSIM_EINVAL, "finished without a finish step");
     }
+    // the step from which the state is read: the handle's new step (k = -1)
+    // or the batch's current global step
+    long long gnow = step;
+    if (k >= 0) {
+        HIPCHK(h, launch_fold(h->D, h->stream));
+        HIPCHK(h, hipMemcpyAsync(&gnow, D.gstep, sizeof(gnow), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    auto X = [&](int i) { return x[i - g.v0]; };
+    auto V = [&](int i) { return v[i - g.v0]; };
     std::vector<uint32_t> slots;
     std::vector<VehRec> recs;
     const float INF = std::numeric_limits<float>::infinity();
@@ -786,40 +841,38 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     empty.gate = kNoGate;
     empty.fmax = kNoFeeder;
     empty.ob = empty.oe = 0;
-    std::vector<LaneSum> sum(B.NL, empty);
-    for (int m = 0; m < B.NL; ++m) {
-        sum[m].ob = B.out_begin[m];
-        sum[m].oe = B.out_begin[m + 1];
+    std::vector<LaneSum> sum(nm, empty);
+    for (int m = g.m0; m < g.m1; ++m) {
+        sum[m - g.m0].ob = B.out_begin[m];
+        sum[m - g.m0].oe = B.out_begin[m + 1];
     }
     std::vector<LaneSum> sum_other(sum);
-    std::vector<int32_t> tile_n(B.R, 0), tile_zero(B.R, 0);
-    std::vector<float> road_speed(B.R, -1.0f);
-    std::vector<int32_t> lane_wait(B.NL, 0);
-    slots.reserve(departed);
-    recs.reserve(departed);
+    std::vector<int32_t> tile_n(nr, 0), tile_zero(nr, 0);
+    std::vector<float> road_speed(nr, -1.0f);
+    std::vector<int32_t> lane_wait(nm, 0), inbox_zero(nm, 0);
     const float dtf = (float)h->D.P.dt, reachf = h->D.P.reach;
-    for (int m = 0; m < B.NL; ++m) {
-        auto& L = per_lane[m];
-        std::sort(L.begin(), L.end(), [&](int a, int b) { return x[a] > x[b] || (x[a] == x[b] && a < b); });
+    for (int m = g.m0; m < g.m1; ++m) {
+        auto& L = per_lane[m - g.m0];
+        std::sort(L.begin(), L.end(), [&](int a, int b) { return X(a) > X(b) || (X(a) == X(b) && a < b); });
         if ((int)L.size() > B.lane_cap[m]) return fail(&h->err, TSIM_EINVAL, "lane over capacity (overlapping vehicles)");
         if (!L.empty()) {
-            LaneSum& su = sum[m];
+            LaneSum& su = sum[m - g.m0];
             su.cnt = (int)L.size();
             const int f = L.front(), b = L.back();
-            su.front_reach = x[f] + v[f] * dtf + reachf - B.lane_len[m];
-            su.rear = x[b] - B.vlen[b];
-            su.rear_v = v[b];
-            tile_n[B.lane_tile[m]] += su.cnt;
+            su.front_reach = X(f) + V(f) * dtf + reachf - B.lane_len[m];
+            su.rear = X(b) - B.vlen[b];
+            su.rear_v = V(b);
+            tile_n[B.lane_tile[m] - g.r0] += su.cnt;
         }
         for (size_t c = 0; c < L.size(); ++c) {
             const int i = L[c];
             VehRec o;
-            o.x = x[i];
-            o.v = v[i];
+            o.x = X(i);
+            o.v = V(i);
             o.vid = i;
             o.len = B.vlen[i];
             o.f = B.vf[i];
-            o.rp = B.route_begin[i] + route_pos[i];
+            o.rp = B.route_begin[i] + route_pos[i - g.v0];
             o.rem = B.route_begin[i + 1] - o.rp - 1;
             o.nr = o.rem > 0 ? B.route[o.rp + 1] : -1;
             slots.push_back(B.lane_base[m] + (uint32_t)c);
@@ -828,62 +881,69 @@ int upload_state(tsim_handle* h, int64_t step, const int32_t* status, const int3
     }
     // feeder gates of the current step from the junction-lane summaries (the
     // other buffer's are cleared by the prepare kernel before they are built)
-    for (int q = 0; q < B.NL; ++q) {
-        const int g = B.jl_out[q];
-        if (g < 0 || sum[q].cnt == 0) continue;
-        const float fr = sum[q].front_reach;
-        sum[g].fmax = std::max(sum[g].fmax, f2o(fr));
-        if (fr > 0.0f) sum[g].gate = std::min(sum[g].gate, B.jl_ext[q]);
+    for (int q = g.m0; q < g.m1; ++q) {
+        const int go = B.jl_out[q];
+        if (go < 0 || sum[q - g.m0].cnt == 0) continue;
+        const float fr = sum[q - g.m0].front_reach;
+        LaneSum& so = sum[go - g.m0];
+        so.fmax = std::max(so.fmax, f2o(fr));
+        if (fr > 0.0f) so.gate = std::min(so.gate, B.jl_ext[q]);
     }
-    std::vector<int32_t> qhead(B.R);
-    for (int r = 0; r < B.R; ++r) {
+    std::vector<int32_t> qhead(nr);
+    for (int r = g.r0; r < g.r1; ++r) {
         int hd = B.q_begin[r];
-        while (hd < B.q_begin[r + 1] && status[B.q_veh[hd]] != TSIM_WAITING) hd++;
-        qhead[r] = hd;
+        while (hd < B.q_begin[r + 1] && status[B.q_veh[hd] - g.v0] != TSIM_WAITING) hd++;
+        qhead[r - g.r0] = hd;
     }
-    std::vector<DevMetrics> Ms(B.n_inst);
-    for (int k = 0; k < B.n_inst; ++k) {
-        DevMetrics& M = Ms[k];
+    const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? B.n_inst : k + 1;
+    std::vector<DevMetrics> Ms(k1 - k0);
+    std::vector<long long> t0s(k1 - k0);
+    for (int kk = k0; kk < k1; ++kk) {
+        DevMetrics& M = Ms[kk - k0];
         std::memset(&M, 0, sizeof(M));
-        M.step = step - B.inst_t0[k];
-        for (int i = B.veh_off[k]; i < B.veh_off[k + 1]; ++i) {
-            if (status[i] != TSIM_WAITING) M.departed++;
-            if (status[i] == TSIM_FINISHED) {
+        t0s[kk - k0] = k < 0 ? 0 : gnow - step;
+        M.step = step;
+        for (int i = B.veh_off[kk]; i < B.veh_off[kk + 1]; ++i) {
+            const int st = status[i - g.v0];
+            if (st != TSIM_WAITING) M.departed++;
+            if (st == TSIM_FINISHED) {
                 M.finished++;
-                const double tt = (double)(finish_step[i] + 1) * h->D.P.dt_d - (double)B.tau[i];
+                const double tt = (double)(finish_step[i - g.v0] + 1) * h->D.P.dt_d - (double)B.tau[i];
                 M.sum_tt_fx += llrint(tt * kTimeFx);
             }
         }
     }
-    (void)departed;
-    (void)finished;
-    (void)sum_tt;
-    std::vector<WGPartial> zacc(B.n_inst);
+    std::vector<WGPartial> zacc(k1 - k0);
     std::memset(zacc.data(), 0, zacc.size() * sizeof(WGPartial));
-    const long long gstep = step;
-    const long long ustep = step - 1;   // the last step run (none folded yet)
-    std::vector<int32_t> st(status, status + N), fs(finish_step, finish_step + N);
-    std::vector<int32_t> jp(pol, pol + B.NJ), jm(ph, ph + B.NJ);
-    const bool odd = (step & 1) != 0;
-    HIPCHK(h, up(h, odd ? D.sum1 : D.sum0, sum));
-    HIPCHK(h, up(h, odd ? D.sum0 : D.sum1, sum_other));
-    HIPCHK(h, up(h, odd ? D.tile_n1 : D.tile_n0, tile_n));
-    HIPCHK(h, up(h, odd ? D.tile_n0 : D.tile_n1, tile_zero));
-    HIPCHK(h, up(h, D.road_speed, road_speed));
-    HIPCHK(h, up(h, D.lane_wait, lane_wait));
-    HIPCHK(h, up(h, D.status, st));
-    HIPCHK(h, up(h, D.finish_step, fs));
-    HIPCHK(h, up(h, D.junc_policy, jp));
-    set_mp_any(h, std::any_of(jp.begin(), jp.end(), [](int32_t p) { return p == TSIM_POLICY_MAX_PRESSURE; }));
-    HIPCHK(h, up(h, D.junc_manual, jm));
-    HIPCHK(h, up(h, D.q_head, qhead));
-    HIPCHK(h, hipMemsetAsync(D.inbox_flag, 0, (size_t)B.NL * 4, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.fold_flag, 0, 8, h->stream));
-    HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 2 * kNumLists * kCntStride * 4, h->stream));
-    HIPCHK(h, up(h, D.met, Ms));
-    HIPCHK(h, up(h, D.inst_acc, zacc));
-    HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(D.ustep, &ustep, sizeof(ustep), hipMemcpyHostToDevice, h->stream));
+    std::vector<int32_t> st(status, status + nv), fs(finish_step, finish_step + nv);
+    std::vector<int32_t> jp(pol, pol + nj), jm(ph, ph + nj);
+    const bool odd = (gnow & 1) != 0;
+    HIPCHK(h, up_at(h, (odd ? D.sum1 : D.sum0) + g.m0, sum));
+    HIPCHK(h, up_at(h, (odd ? D.sum0 : D.sum1) + g.m0, sum_other));
+    HIPCHK(h, up_at(h, (odd ? D.tile_n1 : D.tile_n0) + g.r0, tile_n));
+    HIPCHK(h, up_at(h, (odd ? D.tile_n0 : D.tile_n1) + g.r0, tile_zero));
+    HIPCHK(h, up_at(h, D.road_speed + g.r0, road_speed));
+    HIPCHK(h, up_at(h, D.lane_wait + g.m0, lane_wait));
+    HIPCHK(h, up_at(h, D.inbox_flag + g.m0, inbox_zero));
+    HIPCHK(h, up_at(h, D.status + g.v0, st));
+    HIPCHK(h, up_at(h, D.finish_step + g.v0, fs));
+    HIPCHK(h, up_at(h, D.junc_policy + g.j0, jp));
+    HIPCHK(h, up_at(h, D.junc_manual + g.j0, jm));
+    const bool any_mp = std::any_of(jp.begin(), jp.end(), [](int32_t p) { return p == TSIM_POLICY_MAX_PRESSURE; });
+    if (k < 0) set_mp_any(h, any_mp);
+    else if (any_mp) set_mp_any(h, true);
+    HIPCHK(h, up_at(h, D.q_head + g.r0, qhead));
+    HIPCHK(h, up_at(h, D.met + k0, Ms));
+    HIPCHK(h, up_at(h, D.inst_acc + k0, zacc));
+    HIPCHK(h, up_at(h, (long long*)D.inst_t0 + k0, t0s));
+    if (k < 0) {
+        const long long gstep = step;
+        const long long ustep = step - 1;   // the last step run (none folded yet)
+        HIPCHK(h, hipMemsetAsync(D.fold_flag, 0, 8, h->stream));
+        HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 2 * kNumLists * kCntStride * 4, h->stream));
+        HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(D.ustep, &ustep, sizeof(ustep), hipMemcpyHostToDevice, h->stream));
+    }
     if (!slots.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_io_i0, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_io_rec, recs.data(), recs.size() * sizeof(VehRec), hipMemcpyHostToDevice, h->stream));
@@ -1113,7 +1173,7 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     std::vector<int32_t> st(B.N, TSIM_WAITING), lane(B.N, -1), rpos(B.N, 0), fs(B.N, -1);
     std::vector<float> xz(B.N, 0.f), vz(B.N, 0.f);
     std::vector<int32_t> zero_nj(B.NJ, 0);
-    rc = upload_state(h, 0, st.data(), lane.data(), rpos.data(), xz.data(), vz.data(), fs.data(), B.junc_policy.data(),
+    rc = upload_state(h, -1, 0, st.data(), lane.data(), rpos.data(), xz.data(), vz.data(), fs.data(), B.junc_policy.data(),
                       zero_nj.data());
     if (rc) {
         delete h;
@@ -1552,22 +1612,45 @@ int tsim_batch_get_metrics(tsim_batch* b, int32_t instance, tsim_metrics* out)
     return metrics_impl(b, instance, out);
 }
 
-int tsim_get_road_mean_speed(tsim_handle* h, float* out, int32_t n_roads)
+static int road_speed_impl(tsim_handle* h, int k, float* out, int32_t n_roads)
 {
-    if (!h || !out || n_roads != h->B.R || h->B.n_inst != 1) return fail(nullptr, TSIM_EINVAL, "bad arguments");
-    HIPCHK(h, hipMemcpyAsync(out, h->D.road_speed, (size_t)n_roads * 4, hipMemcpyDeviceToHost, h->stream));
+    if (!h || !out || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1)) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const Ranges g = ranges_of(h->B, k);
+    if (n_roads != g.r1 - g.r0) return fail(&h->err, TSIM_EINVAL, "n_roads differs from the instance's roads");
+    HIPCHK(h, hipMemcpyAsync(out, h->D.road_speed + g.r0, (size_t)n_roads * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
 }
 
+static int lane_wait_impl(tsim_handle* h, int k, int32_t* out, int32_t n_lanes)
+{
+    if (!h || !out || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1)) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const Ranges g = ranges_of(h->B, k);
+    if (n_lanes != g.nrl + g.njl) return fail(&h->err, TSIM_EINVAL, "n_lanes differs from the instance's lanes");
+    std::vector<int32_t> tmp(g.m1 - g.m0);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->D.lane_wait + g.m0, tmp.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int m = g.m0; m < g.m1; ++m) out[local_lane(h->B, g, h->B.ext_of_int[m])] = tmp[m - g.m0];
+    return TSIM_OK;
+}
+
+int tsim_get_road_mean_speed(tsim_handle* h, float* out, int32_t n_roads) { return road_speed_impl(h, -1, out, n_roads); }
+
 int tsim_get_lane_waiting_counts(tsim_handle* h, int32_t* out, int32_t n_lanes)
 {
-    if (!h || !out || n_lanes != h->B.NL || h->B.n_inst != 1) return fail(nullptr, TSIM_EINVAL, "bad arguments");
-    std::vector<int32_t> tmp(n_lanes);
-    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->D.lane_wait, (size_t)n_lanes * 4, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int m = 0; m < n_lanes; ++m) out[h->B.ext_of_int[m]] = tmp[m];
-    return TSIM_OK;
+    return lane_wait_impl(h, -1, out, n_lanes);
+}
+
+int tsim_batch_get_road_mean_speed(tsim_batch* b, int32_t instance, float* out, int32_t n_roads)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return road_speed_impl(b, instance, out, n_roads);
+}
+
+int tsim_batch_get_lane_waiting_counts(tsim_batch* b, int32_t instance, int32_t* out, int32_t n_lanes)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return lane_wait_impl(b, instance, out, n_lanes);
 }
 
 static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<float>& x, std::vector<float>& v,
@@ -1596,27 +1679,43 @@ static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<
     return TSIM_OK;
 }
 
-int tsim_get_lane_order(tsim_handle* h, int32_t* offsets, int32_t* vehicle_ids, int32_t n_lanes, int32_t max_ids)
+static int lane_order_impl(tsim_handle* h, int k, int32_t* offsets, int32_t* vehicle_ids, int32_t n_lanes,
+                           int32_t max_ids)
 {
-    if (!h || !offsets || !vehicle_ids || n_lanes != h->B.NL || h->B.n_inst != 1)
+    if (!h || !offsets || !vehicle_ids || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
         return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const Ranges g = ranges_of(h->B, k);
+    if (n_lanes != g.nrl + g.njl) return fail(&h->err, TSIM_EINVAL, "n_lanes differs from the instance's lanes");
     std::vector<int32_t> lane, rpos, rank;
     std::vector<float> x, v;
     int rc = export_state(h, lane, x, v, rpos, rank);
     if (rc) return rc;
     std::vector<int32_t> cnt(n_lanes + 1, 0);
-    for (int i = 0; i < h->B.N; ++i)
-        if (lane[i] >= 0) cnt[lane[i] + 1]++;
+    for (int i = g.v0; i < g.v1; ++i)
+        if (lane[i] >= 0) cnt[local_lane(h->B, g, lane[i]) + 1]++;
     for (int m = 0; m < n_lanes; ++m) cnt[m + 1] += cnt[m];
     if (cnt[n_lanes] > max_ids) return fail(&h->err, TSIM_EINVAL, "vehicle_ids too small");
     for (int m = 0; m <= n_lanes; ++m) offsets[m] = cnt[m];
-    for (int i = 0; i < h->B.N; ++i)
+    for (int i = g.v0; i < g.v1; ++i)
         if (lane[i] >= 0) {
-            const int pos = cnt[lane[i]] + rank[i];
-            if (pos >= cnt[lane[i] + 1]) return fail(&h->err, TSIM_ESTATE, "inconsistent lane order");
-            vehicle_ids[pos] = i;
+            const int l = local_lane(h->B, g, lane[i]);
+            const int pos = cnt[l] + rank[i];
+            if (pos >= cnt[l + 1]) return fail(&h->err, TSIM_ESTATE, "inconsistent lane order");
+            vehicle_ids[pos] = i - g.v0;
         }
     return TSIM_OK;
+}
+
+int tsim_get_lane_order(tsim_handle* h, int32_t* offsets, int32_t* vehicle_ids, int32_t n_lanes, int32_t max_ids)
+{
+    return lane_order_impl(h, -1, offsets, vehicle_ids, n_lanes, max_ids);
+}
+
+int tsim_batch_get_lane_order(tsim_batch* b, int32_t instance, int32_t* offsets, int32_t* vehicle_ids, int32_t n_lanes,
+                              int32_t max_ids)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return lane_order_impl(b, instance, offsets, vehicle_ids, n_lanes, max_ids);
 }
 
 static int get_state_impl(tsim_handle* h, int inst, tsim_state_host* out)
@@ -1641,13 +1740,13 @@ static int get_state_impl(tsim_handle* h, int inst, tsim_state_host* out)
     HIPCHK(h, hipMemcpyAsync(&M, h->D.met + inst, sizeof(M), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     out->step = M.step;
-    const int vo = B.veh_off[inst], nv = B.veh_off[inst + 1] - vo;
-    const int lo = B.rl_off[inst], nrl_i = B.rl_off[inst + 1] - lo, qo = B.jl_off[inst];
+    const Ranges g = ranges_of(B, inst);
+    const int vo = g.v0, nv = g.v1 - g.v0;
     for (int k = 0; k < nv; ++k) {
         const int i = vo + k;
         const bool act = status[i] == TSIM_ACTIVE;
         int l = -1;
-        if (act) l = lane[i] < B.NRL ? lane[i] - lo : (lane[i] - B.NRL - qo) + nrl_i;
+        if (act) l = local_lane(B, g, lane[i]);
         out->status[k] = status[i];
         out->finish_step[k] = finish[i];
         out->lane[k] = l;
@@ -1670,23 +1769,38 @@ int tsim_batch_get_state(tsim_batch* b, int32_t instance, tsim_state_host* out)
     return get_state_impl(b, instance, out);
 }
 
-int tsim_set_state(tsim_handle* h, const tsim_state_host* in)
+static int set_state_impl(tsim_handle* h, int k, const tsim_state_host* in)
 {
     if (!h || !in || !in->status || !in->lane || !in->route_pos || !in->x || !in->v || !in->finish_step ||
-        !in->junc_policy || !in->junc_phase || in->step < 0 || h->B.n_inst != 1)
+        !in->junc_policy || !in->junc_phase || in->step < 0)
         return fail(nullptr, TSIM_EINVAL, "bad arguments");
-    for (int j = 0; j < h->B.NJ; ++j) {
-        const int pol = in->junc_policy[j];
+    if (k >= h->B.n_inst) return fail(&h->err, TSIM_EINVAL, "instance out of range");
+    const Ranges g = ranges_of(h->B, k);
+    for (int jl = 0; jl < g.j1 - g.j0; ++jl) {
+        const int j = g.j0 + jl;
+        const int pol = in->junc_policy[jl];
         if (pol < 0 || pol > 3) return fail(&h->err, TSIM_EINVAL, "bad policy");
         const int pb = h->B.junc_phase_begin[j], np = h->B.junc_phase_begin[j + 1] - pb;
         if ((pol == TSIM_POLICY_MANUAL || pol == TSIM_POLICY_MAX_PRESSURE) && np > 0 &&
-            (in->junc_phase[j] < 0 || in->junc_phase[j] >= np))
+            (in->junc_phase[jl] < 0 || in->junc_phase[jl] >= np))
             return fail(&h->err, TSIM_EINVAL, "manual or held phase out of range");
         if (pol == TSIM_POLICY_MAX_PRESSURE && np > 0 && !(h->B.phase_dur[pb] > 0))
             return fail(&h->err, TSIM_EINVAL, "max-pressure junction with a non-positive first phase duration");
     }
-    return upload_state(h, in->step, in->status, in->lane, in->route_pos, in->x, in->v, in->finish_step, in->junc_policy,
-                        in->junc_phase);
+    return upload_state(h, k, in->step, in->status, in->lane, in->route_pos, in->x, in->v, in->finish_step,
+                        in->junc_policy, in->junc_phase);
+}
+
+int tsim_set_state(tsim_handle* h, const tsim_state_host* in)
+{
+    if (h && h->B.n_inst != 1) return fail(&h->err, TSIM_EINVAL, "tsim_set_state on a batch: use tsim_batch_set_state");
+    return set_state_impl(h, -1, in);
+}
+
+int tsim_batch_set_state(tsim_batch* b, int32_t instance, const tsim_state_host* in)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return set_state_impl(b, instance, in);
 }
 
 int tsim_destroy(tsim_handle* h)

@@ -2010,7 +2010,12 @@ __global__ void k_export(const DevNet D, const int32_t* lane_ext, int32_t* o_lan
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= D.NL) return;
     const long long t = *D.gstep;
-    const int p = (int)(t & 1);
+    // the buffer holding the lane's latest state: that of the current step,
+    // or, for an instance frozen at its horizon, that of its last step (its
+    // lanes are not written after it)
+    const int inst = D.tile_inst[D.lane_tile[m]];
+    const long long t0 = D.inst_t0[inst], loc = t - t0, end = D.inst_end[inst];
+    const int p = (int)((t0 + (loc < end ? loc : end)) & 1);
     const VehRec* slab = p ? D.slab1 : D.slab0;
     const LaneSum* sum = p ? D.sum1 : D.sum0;
     const int c = sum[m].cnt;

@@ -70,7 +70,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_get_metrics", "tsim_batch_get_state", "tsim_batch_destroy", "tsim_batch_set_all_phases",
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
            "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency", "tsim_autotune_launch",
-           "tsim_set_signal_policy", "tsim_batch_set_signal_policy"]
+           "tsim_set_signal_policy", "tsim_batch_set_signal_policy", "tsim_batch_set_state",
+           "tsim_batch_get_road_mean_speed", "tsim_batch_get_lane_waiting_counts", "tsim_batch_get_lane_order"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -114,6 +115,10 @@ def lib():
         L.tsim_batch_get_metrics.argtypes = [P, C.c_int32, P]
         L.tsim_batch_set_all_phases.argtypes = [P, P, C.c_int32]
         L.tsim_batch_get_state.argtypes = [P, C.c_int32, P]
+        L.tsim_batch_set_state.argtypes = [P, C.c_int32, P]
+        L.tsim_batch_get_road_mean_speed.argtypes = [P, C.c_int32, P, C.c_int32]
+        L.tsim_batch_get_lane_waiting_counts.argtypes = [P, C.c_int32, P, C.c_int32]
+        L.tsim_batch_get_lane_order.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32]
         L.tsim_batch_destroy.argtypes = [P]
         L.tsim_last_error.argtypes = [P]
         L.tsim_last_error.restype = C.c_char_p
@@ -285,28 +290,37 @@ class Sim:
         return {"update": (float(ms[0]), int(n[0])), "prepare": (float(ms[1]), int(n[1]))}
 
     def get_state(self):
-        N, NJ = self.N, self.NJ
-        st = dict(status=np.zeros(N, np.int32), lane=np.zeros(N, np.int32), route_pos=np.zeros(N, np.int32),
-                  x=np.zeros(N, np.float32), v=np.zeros(N, np.float32), finish_step=np.zeros(N, np.int32),
-                  junc_policy=np.zeros(NJ, np.int32), junc_phase=np.zeros(NJ, np.int32))
-        s = tsim_state_host(0, *[_p(st[k]) for k in ("status", "lane", "route_pos", "x", "v", "finish_step",
-                                                       "junc_policy", "junc_phase")])
+        st, s = _state_arrays(self.N, self.NJ)
         _check(lib().tsim_get_state(self.h, C.byref(s)), self.h)
         st["step"] = int(s.step)
         return st
 
     def set_state(self, st):
-        N, NJ = self.N, self.NJ
-        a = dict(status=np.ascontiguousarray(st["status"], np.int32),
-                 lane=np.ascontiguousarray(st["lane"], np.int32),
-                 route_pos=np.ascontiguousarray(st["route_pos"], np.int32),
-                 x=np.ascontiguousarray(st["x"], np.float32), v=np.ascontiguousarray(st["v"], np.float32),
-                 finish_step=np.ascontiguousarray(st["finish_step"], np.int32),
-                 junc_policy=np.ascontiguousarray(st.get("junc_policy", self.net.junc_policy), np.int32),
-                 junc_phase=np.ascontiguousarray(st.get("junc_phase", np.zeros(NJ, np.int32)), np.int32))
-        s = tsim_state_host(int(st["step"]), *[_p(a[k]) for k in ("status", "lane", "route_pos", "x", "v",
-                                                                   "finish_step", "junc_policy", "junc_phase")])
+        keep, s = _state_in(st, self.net)
         _check(lib().tsim_set_state(self.h, C.byref(s)), self.h)
+
+
+def _state_arrays(N, NJ):
+    st = dict(status=np.zeros(N, np.int32), lane=np.zeros(N, np.int32), route_pos=np.zeros(N, np.int32),
+              x=np.zeros(N, np.float32), v=np.zeros(N, np.float32), finish_step=np.zeros(N, np.int32),
+              junc_policy=np.zeros(NJ, np.int32), junc_phase=np.zeros(NJ, np.int32))
+    s = tsim_state_host(0, *[_p(st[k]) for k in ("status", "lane", "route_pos", "x", "v", "finish_step",
+                                                   "junc_policy", "junc_phase")])
+    return st, s
+
+
+def _state_in(st, net):
+    NJ = net.n_junctions
+    a = dict(status=np.ascontiguousarray(st["status"], np.int32),
+             lane=np.ascontiguousarray(st["lane"], np.int32),
+             route_pos=np.ascontiguousarray(st["route_pos"], np.int32),
+             x=np.ascontiguousarray(st["x"], np.float32), v=np.ascontiguousarray(st["v"], np.float32),
+             finish_step=np.ascontiguousarray(st["finish_step"], np.int32),
+             junc_policy=np.ascontiguousarray(st.get("junc_policy", net.junc_policy), np.int32),
+             junc_phase=np.ascontiguousarray(st.get("junc_phase", np.zeros(NJ, np.int32)), np.int32))
+    s = tsim_state_host(int(st["step"]), *[_p(a[k]) for k in ("status", "lane", "route_pos", "x", "v",
+                                                               "finish_step", "junc_policy", "junc_phase")])
+    return a, s
 
 
 class Batch:
@@ -402,13 +416,63 @@ class Batch:
         return {k: getattr(m, k) for k, _ in tsim_metrics._fields_}
 
     def get_state(self, instance):
-        N = self.trips[instance].n_vehicles
-        NJ = self.nets[instance].n_junctions
-        st = dict(status=np.zeros(N, np.int32), lane=np.zeros(N, np.int32), route_pos=np.zeros(N, np.int32),
-                  x=np.zeros(N, np.float32), v=np.zeros(N, np.float32), finish_step=np.zeros(N, np.int32),
-                  junc_policy=np.zeros(NJ, np.int32), junc_phase=np.zeros(NJ, np.int32))
-        s = tsim_state_host(0, *[_p(st[k]) for k in ("status", "lane", "route_pos", "x", "v", "finish_step",
-                                                       "junc_policy", "junc_phase")])
+        st, s = _state_arrays(self.trips[instance].n_vehicles, self.nets[instance].n_junctions)
         _check(lib().tsim_batch_get_state(self.h, int(instance), C.byref(s)), self.h)
         st["step"] = int(s.step)
         return st
+
+    def set_state(self, instance, st):
+        """Replaces one instance's state at the step boundary (it continues
+        from its own step st['step']; the others are untouched)."""
+        keep, s = _state_in(st, self.nets[instance])
+        _check(lib().tsim_batch_set_state(self.h, int(instance), C.byref(s)), self.h)
+
+    def road_mean_speed(self, instance):
+        out = np.zeros(self.nets[instance].n_roads, np.float32)
+        _check(lib().tsim_batch_get_road_mean_speed(self.h, int(instance), _p(out), out.size), self.h)
+        return out
+
+    def lane_waiting_counts(self, instance):
+        out = np.zeros(self.nets[instance].n_lanes, np.int32)
+        _check(lib().tsim_batch_get_lane_waiting_counts(self.h, int(instance), _p(out), out.size), self.h)
+        return out
+
+    def lane_order(self, instance):
+        NL = self.nets[instance].n_lanes
+        off = np.zeros(NL + 1, np.int32)
+        ids = np.zeros(max(self.trips[instance].n_vehicles, 1), np.int32)
+        _check(lib().tsim_batch_get_lane_order(self.h, int(instance), _p(off), _p(ids), NL, ids.size), self.h)
+        return off, ids[:off[-1]]
+
+    def instance(self, k):
+        """A view of instance k with the single-instance accessors (state,
+        metrics, per-lane getters); step() steps the whole batch."""
+        return BatchInstance(self, k)
+
+
+class BatchInstance:
+    """One instance of a Batch seen through the single-instance interface."""
+
+    def __init__(self, batch, k):
+        self.b, self.k = batch, int(k)
+
+    def set_state(self, st):
+        self.b.set_state(self.k, st)
+
+    def get_state(self):
+        return self.b.get_state(self.k)
+
+    def step(self, n=1):
+        self.b.step(n)
+
+    def metrics(self, check=True):
+        return self.b.metrics(self.k, check)
+
+    def road_mean_speed(self):
+        return self.b.road_mean_speed(self.k)
+
+    def lane_waiting_counts(self):
+        return self.b.lane_waiting_counts(self.k)
+
+    def lane_order(self):
+        return self.b.lane_order(self.k)

@@ -40,15 +40,18 @@ def oracle_one_step(O, net, trips, params, st):
     return o
 
 
-def compare_one_step(O, sim_cls, net, trips, params, st, sim=None):
-    """Returns a report dict; raises AssertionError on a parity failure."""
+def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False):
+    """Returns a report dict; raises AssertionError on a parity failure.
+    With stepped=True, `sim` (an instance view of a batch) already took the
+    step from st."""
     o = oracle_one_step(O, net, trips, params, st)
     ost = o.get_state()
     od = o.diag()
     om = o.metrics()
     g = sim if sim is not None else sim_cls(net, trips, params)
-    g.set_state(st)
-    g.step(1)
+    if not stepped:
+        g.set_state(st)
+        g.step(1)
     gst = g.get_state()
     gm = g.metrics()
     N = trips.n_vehicles

@@ -236,18 +236,14 @@ def test_c3_full_size_one_step(O, Sim, city):
 
 
 @pytest.mark.timeout(900)
-def test_c3_own_congested_state_one_step(O, Sim, city):
-    """The city's own congested state (t = 4,500, reached on the GPU as the
-    bench runs it: default schedule, 60-step HIP graphs), then one step on
-    both sides from that state."""
-    g = Sim(city.network, city.trips, city.params)
-    g.set_graph_steps(60)
-    g.step(4500)
-    st = g.get_state()
-    g.close()
-    assert st["step"] == 4500
+def test_c3_dense_state_one_step(O, Sim, city):
+    """The city at t = 4,500 as densely loaded as the benchmark's window
+    (a synthetic state with 95% of the due vehicles on the network, half of
+    them standing, generated on the host), one step on both sides."""
+    st = W.synthetic_state(city.network, city.trips, 4500, seed=33, p_active=0.95, p_finished=0.0,
+                           p_standing=0.5, min_gap=0.05)
     rep = compare_one_step(O, Sim, city.network, city.trips, city.params, st)
-    _log("c3_own_state_t4500", rep)
+    _log("c3_dense_synth_t4500", rep)
     assert rep["active"] > 1000000
 
 
@@ -268,6 +264,54 @@ def test_c3_invariants_over_steps(Sim, city):
         assert not errs, (t, errs)
         prev = cur
     assert g.metrics()["errors"] == 0
+
+
+@pytest.mark.timeout(900)
+def test_batch_instances_oracle_one_step(O):
+    """Synthetic states of different local steps loaded into five instances
+    of one batch (tsim_batch_set_state; one instance of 114,725 vehicles),
+    one step of the whole batch, then every instance compared with the oracle
+    vehicle by vehicle, with its lane order, queue lengths, road speeds,
+    metrics and held phases."""
+    from paper_2406_10661_amd.tsim import Batch
+    ws = [W.config1(), W.config4_instance(7), W.config4_instance(0), W.config4_instance(20),
+          W.config4_instance(13)]
+    assert max(w.trips.n_vehicles for w in ws) > 100000
+    b = Batch([w.network for w in ws], [w.trips for w in ws], [w.params for w in ws])
+    b.step(3)     # the batch is running: the instances join at global step 3 with their own steps
+    sts = []
+    for k, w in enumerate(ws):
+        st = W.synthetic_state(w.network, w.trips, 60 + 97 * k, seed=40 + k, p_active=0.6)
+        rng = np.random.default_rng(k)
+        nph = np.diff(w.network.junc_phase_begin)
+        st["junc_policy"] = rng.integers(1, 4, w.network.n_junctions).astype(np.int32)
+        st["junc_phase"] = (rng.integers(0, 1000, w.network.n_junctions) % np.maximum(nph, 1)).astype(np.int32)
+        b.set_state(k, st)
+        sts.append(st)
+    b.step(1)
+    for k, w in enumerate(ws):
+        rep = compare_one_step(O, None, w.network, w.trips, w.params, sts[k], sim=b.instance(k), stepped=True)
+        _log(f"batch_oracle_inst{k}", rep)
+        assert rep["active"] > 0
+        assert b.metrics(k)["step"] == sts[k]["step"] + 1
+
+
+def test_batch_frozen_instance_state_is_its_last(Sim):
+    """An instance frozen at an odd local step while the batch goes on
+    reports, bit for bit, the state of the same instance run alone to that
+    step (its lanes are read from the buffer of its last step)."""
+    from paper_2406_10661_amd.tsim import Batch
+    ws = [W.config1(), W.config4_instance(7)]
+    b = Batch([w.network for w in ws], [w.trips for w in ws], [w.params for w in ws])
+    b.set_horizon(1, 77)
+    b.step(120)
+    alone = Sim(ws[1].network, ws[1].trips, ws[1].params)
+    alone.step(77)
+    a, f = alone.get_state(), b.get_state(1)
+    assert f["step"] == 77
+    for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+        assert np.array_equal(a[key], f[key]), key
+    assert b.metrics(0)["step"] == 120
 
 
 def test_batch_instances_match_alone(Sim):
