@@ -337,6 +337,64 @@ int tsim_batch_get_lane_order(tsim_batch *b, int32_t instance, int32_t *offsets,
                               int32_t n_lanes, int32_t max_ids);
 int tsim_batch_destroy(tsim_batch *b);
 
+/*
+ * Instances joining and leaving a running batch (continuous batching of
+ * simulation jobs; the serving form of the step, not in the paper).
+ *
+ * A batch reserved with tsim_batch_reserve starts empty with room for the
+ * given totals; tsim_batch_add appends an instance (built on the host by
+ * tsim_instance_build, so a serving loop can build jobs on other threads)
+ * at the batch's next step boundary, and tsim_batch_add_member appends a copy
+ * of a live single-instance handle (its network, trips, parameters and
+ * current state; the member stays valid).  An added instance starts its own
+ * step count where its state is (local step 0 for tsim_batch_add) while the
+ * other instances go on: its trajectory is bit-identical to the same instance
+ * stepped alone.  tsim_batch_remove freezes an instance for good; the space
+ * of removed instances at the end of the batch is given back (all of it once
+ * the batch has drained).  Instance ids are the order of addition (ids of
+ * removed trailing instances are reused).  Batches made by tsim_batch_create
+ * hold exactly their instances (no room to add until some are removed).
+ * Every call here synchronises the batch's stream; calls that would exceed
+ * the reserved totals return TSIM_ENOMEM and change nothing.
+ */
+typedef struct tsim_instance tsim_instance;
+
+typedef struct tsim_batch_capacity {
+    int32_t instances;
+    int32_t junctions;
+    int32_t roads;
+    int32_t road_lanes;
+    int32_t jlanes;          /* junction lanes */
+    int32_t phases;
+    int32_t vehicles;
+    int64_t route_entries;   /* total route length (roads) over the vehicles */
+    int64_t slots;           /* lane slab slots: sum over lanes of floor(length / shortest vehicle) + 2 */
+} tsim_batch_capacity;
+
+/* Validates and lays out one simulation on the host (no device work); the
+ * same checks as tsim_create.  Free with tsim_instance_free. */
+int tsim_instance_build(const tsim_network *net, const tsim_trips *trips, const tsim_params *params,
+                        tsim_instance **out);
+int tsim_instance_free(tsim_instance *in);
+/* The totals one instance takes in a batch (instances = 1); add them up for
+ * a reservation. */
+int tsim_instance_capacity(const tsim_instance *in, tsim_batch_capacity *out);
+/* Device bytes of a reservation, and the empty batch itself (params: the
+ * model parameters every instance must share, the seed apart). */
+int tsim_batch_reserve_footprint(const tsim_batch_capacity *cap, size_t *bytes_out);
+int tsim_batch_reserve(const tsim_batch_capacity *cap, const tsim_params *params, void *hip_stream,
+                       void *device_arena, size_t arena_bytes, tsim_batch **out);
+/* Appends an instance at the step boundary; *instance receives its id. */
+int tsim_batch_add(tsim_batch *b, const tsim_instance *in, int32_t *instance);
+int tsim_batch_add_member(tsim_batch *b, tsim_handle *member, int32_t *instance);
+/* Freezes an instance at its current step for good (its metrics and state
+ * stay readable until its space is given back). */
+int tsim_batch_remove(tsim_batch *b, int32_t instance);
+/* Remaining room, and the number of instance ids in use (removed ones
+ * included until their space is given back). */
+int tsim_batch_capacity_left(tsim_batch *b, tsim_batch_capacity *out);
+int tsim_batch_num_instances(tsim_batch *b, int32_t *n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,12 @@ struct Build {
     std::vector<int> road_off, junc_off, rl_off, jl_off, veh_off;
 };
 
+// sizes the arena of a handle is laid out for: the network itself, or the
+// capacity reserved for a batch that instances join later
+struct Caps {
+    long long R = 0, NJ = 0, NL = 0, NRL = 0, NJL = 0, N = 0, S = 0, P = 0, E = 0, G = 0, n_inst = 0;
+};
+
 struct Region {
     void** ptr;
     size_t bytes;
@@ -141,6 +147,38 @@ void count_tiles(Build& B)
         B.G = std::max(B.G, g.GA + g.GB + g.GC + g.GT + g.GM);
     }
 }
+
+// partial-sum slots enough for any tile mix of at most R tiles
+long long g_bound(int R)
+{
+    Build f;
+    f.R = R;
+    for (int c = 0; c < 4; ++c) f.n_le[c] = R;
+    long long G = 1;
+    for (int s = 0; s < kNumSched; ++s) {
+        const SchedGrid g = sched_grid(f, s, 0, 0, 0, 0);
+        G = std::max<long long>(G, g.GA + g.GB + g.GC + g.GT + g.GM);
+    }
+    return G;
+}
+
+Caps caps_of(const Build& B)
+{
+    Caps c;
+    c.R = B.R;
+    c.NJ = B.NJ;
+    c.NL = B.NL;
+    c.NRL = B.NRL;
+    c.NJL = B.NJL;
+    c.N = B.N;
+    c.S = (long long)B.slots;
+    c.P = (long long)B.phase_dur.size();
+    c.E = (long long)B.route.size();
+    c.G = std::max<long long>(B.G, g_bound(B.R));
+    c.n_inst = B.n_inst;
+    return c;
+}
+
 
 int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_params* prm, Build& B, std::string* err)
 {
@@ -572,6 +610,9 @@ struct tsim_handle {
     hipStream_t cap_stream = nullptr;   // capture only (the caller's stream may be the null stream)
     PassStreams ps;                     // tsim_set_concurrency
     int res[kNumSched + 4] = {};        // resident workgroups: grouped pass per schedule, wide, huge, pipelined wide, tiny
+    Caps cap;                           // sizes the arena is laid out for
+    tsim_params params{};               // model parameters (batches: shared by every instance but the seed)
+    std::vector<char> removed;          // batches: instances taken out by tsim_batch_remove
     std::string err;
 };
 
@@ -582,27 +623,27 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // every device array of a handle, in arena order
 std::vector<Region> regions(tsim_handle* h, bool assign)
 {
-    Build& B = h->B;
+    const Caps& c = h->cap;
     DevNet& D = h->D;
-    const size_t NL = B.NL, R = B.R, NJ = B.NJ, N = B.N, S = B.slots, NJL = B.NJL;
+    const size_t NL = c.NL, R = c.R, NJ = c.NJ, N = c.N, S = c.S, NJL = c.NJL;
     std::vector<Region> v;
     auto add = [&](void* field, size_t bytes) { v.push_back({(void**)field, bytes}); };
     (void)assign;
     add(&D.tile_lane_begin, (R + 1) * 4);
-    add(&D.tile_n_road, R * 4);
-    add(&D.lane_info, NL * sizeof(LaneInfo));
-    add(&D.lane_len, NL * 4);
-    add(&D.lane_lim, NL * 4);
-    add(&D.lane_base, NL * 4);
-    add(&D.lane_cap, NL * 4);
-    add(&D.lane_tile, NL * 4);
-    add(&D.lane_local, NL * 4);
-    add(&D.jl_out, NL * 4);
-    add(&D.jl_junc, NL * 4);
-    add(&D.jl_green_mask, NL * 4);
-    add(&D.jl_ext, NL * 4);
-    add(&D.jl_in_local, NL * 4);
-    add(&D.jl_out_road, NL * 4);
+    add(&D.tile_n_road, std::max<size_t>(R, 1) * 4);
+    add(&D.lane_info, std::max<size_t>(NL, 1) * sizeof(LaneInfo));
+    add(&D.lane_len, std::max<size_t>(NL, 1) * 4);
+    add(&D.lane_lim, std::max<size_t>(NL, 1) * 4);
+    add(&D.lane_base, std::max<size_t>(NL, 1) * 4);
+    add(&D.lane_cap, std::max<size_t>(NL, 1) * 4);
+    add(&D.lane_tile, std::max<size_t>(NL, 1) * 4);
+    add(&D.lane_local, std::max<size_t>(NL, 1) * 4);
+    add(&D.jl_out, std::max<size_t>(NL, 1) * 4);
+    add(&D.jl_junc, std::max<size_t>(NL, 1) * 4);
+    add(&D.jl_green_mask, std::max<size_t>(NL, 1) * 4);
+    add(&D.jl_ext, std::max<size_t>(NL, 1) * 4);
+    add(&D.jl_in_local, std::max<size_t>(NL, 1) * 4);
+    add(&D.jl_out_road, std::max<size_t>(NL, 1) * 4);
     add(&D.out_begin, (NL + 1) * 4);
     add(&D.out_jl, std::max<size_t>(NJL, 1) * 4);
     add(&D.out_pair, std::max<size_t>(NJL, 1) * 8);
@@ -611,68 +652,68 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.junc_phase_begin, (NJ + 1) * 4);
     add(&D.mp_begin, (NJ + 1) * 4);
     add(&D.mp_mov, std::max<size_t>(NJL, 1) * 16);
-    add(&D.phase_dur, std::max<size_t>(B.phase_dur.size(), 1) * 4);
-    add(&D.junc_cycle, NJ * 8);
-    add(&D.junc_policy, NJ * 4);
-    add(&D.junc_manual, NJ * 4);
-    add(&D.junc_cur, NJ * 4);
+    add(&D.phase_dur, std::max<size_t>(c.P, 1) * 4);
+    add(&D.junc_cycle, std::max<size_t>(NJ, 1) * 8);
+    add(&D.junc_policy, std::max<size_t>(NJ, 1) * 4);
+    add(&D.junc_manual, std::max<size_t>(NJ, 1) * 4);
+    add(&D.junc_cur, std::max<size_t>(NJ, 1) * 4);
     add(&D.tau, std::max<size_t>(N, 1) * 4);
     add(&D.route_begin, (N + 1) * 4);
-    add(&D.route, std::max<size_t>(B.route.size(), 1) * 4);
+    add(&D.route, std::max<size_t>(c.E, 1) * 4);
     add(&D.vf, std::max<size_t>(N, 1) * 4);
     add(&D.vlen, std::max<size_t>(N, 1) * 4);
     add(&D.status, std::max<size_t>(N, 1) * 4);
     add(&D.finish_step, std::max<size_t>(N, 1) * 4);
     add(&D.q_begin, (R + 1) * 4);
     add(&D.q_rec, std::max<size_t>(N, 1) * sizeof(QRec));
-    add(&D.q_head, R * 4);
-    add(&D.slab0, S * sizeof(VehRec));
-    add(&D.slab1, S * sizeof(VehRec));
-    add(&D.sum0, NL * sizeof(LaneSum));
-    add(&D.sum1, NL * sizeof(LaneSum));
-    add(&D.tile_n0, R * 4);
-    add(&D.tile_n1, R * 4);
-    add(&D.inbox, NL * sizeof(VehRec));
-    add(&D.inbox_flag, NL * 4);
-    add(&D.sh_gmask, S * 4);
-    add(&D.sh_jq, S * 4);
-    add(&D.sh_aown, S * 4);
-    add(&D.sh_merge, S * 4);
-    add(&D.sh_lrear, S * 4);
-    add(&D.sh_lv, S * 4);
-    add(&D.sh_nx, S * 4);
-    add(&D.sh_nv, S * 4);
-    add(&D.sh_kind, S * 4);
-    add(&D.sh_nlane, S * 4);
-    add(&D.sh_pref, S * 4);
-    add(&D.road_speed, R * 4);
-    add(&D.lane_wait, NL * 4);
+    add(&D.q_head, std::max<size_t>(R, 1) * 4);
+    add(&D.slab0, std::max<size_t>(S, 1) * sizeof(VehRec));
+    add(&D.slab1, std::max<size_t>(S, 1) * sizeof(VehRec));
+    add(&D.sum0, std::max<size_t>(NL, 1) * sizeof(LaneSum));
+    add(&D.sum1, std::max<size_t>(NL, 1) * sizeof(LaneSum));
+    add(&D.tile_n0, std::max<size_t>(R, 1) * 4);
+    add(&D.tile_n1, std::max<size_t>(R, 1) * 4);
+    add(&D.inbox, std::max<size_t>(NL, 1) * sizeof(VehRec));
+    add(&D.inbox_flag, std::max<size_t>(NL, 1) * 4);
+    add(&D.sh_gmask, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_jq, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_aown, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_merge, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_lrear, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_lv, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_nx, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_nv, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_kind, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_nlane, std::max<size_t>(S, 1) * 4);
+    add(&D.sh_pref, std::max<size_t>(S, 1) * 4);
+    add(&D.road_speed, std::max<size_t>(R, 1) * 4);
+    add(&D.lane_wait, std::max<size_t>(NL, 1) * 4);
     add(&D.list_small, std::max<size_t>(R, 1) * 4);
     add(&D.list_big, std::max<size_t>(R, 1) * 4);
     add(&D.list_huge, std::max<size_t>(R, 1) * 4);
     add(&D.list_tiny, std::max<size_t>(R, 1) * 4);
     add(&D.list_med, std::max<size_t>(R, 1) * 4);
     add(&D.list_cnt, 2 * kNumLists * kCntStride * 4);
-    add(&D.part, (size_t)B.G * sizeof(WGPartial));
+    add(&D.part, (size_t)std::max<long long>(c.G, 1) * sizeof(WGPartial));
     add(&D.ustep, 8);
     add(&D.fold_flag, 8);
-    add(&D.met, (size_t)B.n_inst * sizeof(DevMetrics));
-    add(&D.tile_inst, R * 4);
-    add(&D.junc_inst, NJ * 4);
-    add(&D.inst_vbase, (size_t)B.n_inst * 4);
-    add(&D.inst_key, (size_t)B.n_inst * 8);
-    add(&D.inst_t0, (size_t)B.n_inst * 8);
-    add(&D.inst_end, (size_t)B.n_inst * 8);
-    add(&D.inst_acc, (size_t)B.n_inst * sizeof(WGPartial));
+    add(&D.met, (size_t)std::max<long long>(c.n_inst, 1) * sizeof(DevMetrics));
+    add(&D.tile_inst, std::max<size_t>(R, 1) * 4);
+    add(&D.junc_inst, std::max<size_t>(NJ, 1) * 4);
+    add(&D.inst_vbase, (size_t)std::max<long long>(c.n_inst, 1) * 4);
+    add(&D.inst_key, (size_t)std::max<long long>(c.n_inst, 1) * 8);
+    add(&D.inst_t0, (size_t)std::max<long long>(c.n_inst, 1) * 8);
+    add(&D.inst_end, (size_t)std::max<long long>(c.n_inst, 1) * 8);
+    add(&D.inst_acc, (size_t)std::max<long long>(c.n_inst, 1) * sizeof(WGPartial));
     add(&D.gstep, 8);
-    add(&h->d_lane_ext, NL * 4);
+    add(&h->d_lane_ext, std::max<size_t>(NL, 1) * 4);
     add(&h->d_io_i0, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_i1, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_i2, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_f0, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_f1, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_rec, std::max<size_t>(N, 1) * sizeof(VehRec));
-    add(&h->d_io_ph, 4 * NJ * 4);
+    add(&h->d_io_ph, 4 * std::max<size_t>(NJ, 1) * 4);
     add(&h->d_net, sizeof(DevNet));
     return v;
 }
@@ -963,6 +1004,8 @@ int tsim_footprint(const tsim_network* net, const tsim_trips* trips, const tsim_
     tsim_handle tmp;
     int rc = build_tables(net, trips, params, tmp.B, nullptr);
     if (rc) return rc;
+    single_instance(tmp.B, params);
+    tmp.cap = caps_of(tmp.B);
     *bytes_out = arena_size(&tmp) + 256;
     return TSIM_OK;
 }
@@ -1001,6 +1044,7 @@ int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_par
         return rc;
     }
     single_instance(h->B, params);
+    h->cap = caps_of(h->B);
     return create_impl(h, params, hip_stream, device_arena, arena_bytes, out);
 }
 
@@ -1015,6 +1059,7 @@ int tsim_batch_footprint(const tsim_network* nets, const tsim_trips* trips, cons
     rc = build_tables(&U.net, &U.trips, params, tmp.B, nullptr);
     if (rc) return rc;
     batch_instances(tmp.B, U, params, n);
+    tmp.cap = caps_of(tmp.B);
     *bytes_out = arena_size(&tmp) + 256;
     return TSIM_OK;
 }
@@ -1036,8 +1081,152 @@ int tsim_batch_create(const tsim_network* nets, const tsim_trips* trips, const t
         return rc;
     }
     batch_instances(h->B, U, params, n);
+    h->cap = caps_of(h->B);
     return create_impl(h, params, hip_stream, device_arena, arena_bytes, out);
 }
+
+}  // extern "C"
+
+namespace {
+
+// index spans of the host tables whose device copies are (re)written:
+// roads, internal lanes, junctions, vehicles, junction-lane CSR entries,
+// phases, route entries, instances
+struct Span {
+    int r0, r1, m0, m1, j0, j1, v0, v1, q0, q1, p0, p1, k0, k1;
+    long long e0, e1;
+};
+
+Span full_span(const Build& B)
+{
+    return Span{0, B.R, 0, B.NL, 0, B.NJ, 0, B.N, 0, (int)B.out_jl.size(), 0, (int)B.phase_dur.size(), 0, B.n_inst,
+                0, (long long)B.route.size()};
+}
+
+// copies src[lo, hi) to dst + lo
+template <class T>
+hipError_t up_range(tsim_handle* h, T* dst, const std::vector<T>& src, long long lo, long long hi)
+{
+    if (hi <= lo) return hipSuccess;
+    return hipMemcpyAsync((void*)(dst + lo), src.data() + lo, (size_t)(hi - lo) * sizeof(T), hipMemcpyHostToDevice,
+                          h->stream);
+}
+
+// device copies of the static tables over a span (prefix arrays include
+// their end entry); per-instance keys, start steps and horizons of the span's
+// instances
+int upload_tables(tsim_handle* h, const Span& sp)
+{
+    Build& B = h->B;
+    DevNet& D = h->D;
+    auto chk = [&](hipError_t e, const char* what) -> int { return e == hipSuccess ? 0 : hip_fail(h, e, what); };
+    int e = 0;
+    e = e ? e : chk(up_range(h, (int32_t*)D.tile_lane_begin, B.tile_lane_begin, sp.r0, sp.r1 + 1), "tiles");
+    e = e ? e : chk(up_range(h, (int32_t*)D.tile_n_road, B.tile_n_road, sp.r0, sp.r1), "tiles");
+    e = e ? e : chk(up_range(h, (float*)D.lane_len, B.lane_len, sp.m0, sp.m1), "lanes");
+    {
+        std::vector<LaneInfo> li(B.NL);
+        for (int m = sp.m0; m < sp.m1; ++m) {
+            LaneInfo& L = li[m];
+            L.base = B.lane_base[m];
+            L.cap = B.lane_cap[m];
+            L.len = B.lane_len[m];
+            L.lim = B.lane_lim[m];
+            L.jl_out = B.jl_out[m];
+            L.jl_out_road = B.jl_out_road[m];
+            L.jl_junc = B.jl_junc[m];
+            L.green_mask = B.jl_green_mask[m];
+            L.jl_ext = B.jl_ext[m];
+            L.jl_in_local = B.jl_in_local[m];
+            L.pad0 = L.pad1 = 0;
+        }
+        e = e ? e : chk(up_range(h, (LaneInfo*)D.lane_info, li, sp.m0, sp.m1), "lanes");
+    }
+    e = e ? e : chk(up_range(h, (float*)D.lane_lim, B.lane_lim, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (uint32_t*)D.lane_base, B.lane_base, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.lane_cap, B.lane_cap, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.lane_tile, B.lane_tile, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.lane_local, B.lane_local, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.jl_out, B.jl_out, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.jl_junc, B.jl_junc, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (uint32_t*)D.jl_green_mask, B.jl_green_mask, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.jl_ext, B.jl_ext, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.jl_in_local, B.jl_in_local, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.jl_out_road, B.jl_out_road, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.out_begin, B.out_begin, sp.m0, sp.m1 + 1), "conn");
+    e = e ? e : chk(up_range(h, (int32_t*)D.out_jl, B.out_jl, sp.q0, sp.q1), "conn");
+    {
+        std::vector<int32_t> pairs(2 * B.out_jl.size());
+        for (int k = sp.q0; k < sp.q1; ++k) {
+            pairs[2 * k] = B.jl_out_road[B.out_jl[k]];
+            pairs[2 * k + 1] = B.out_jl[k];
+        }
+        e = e ? e : chk(up_range(h, (int32_t*)D.out_pair, pairs, 2LL * sp.q0, 2LL * sp.q1), "conn");
+    }
+    e = e ? e : chk(up_range(h, (int32_t*)D.feed_begin, B.feed_begin, sp.m0, sp.m1 + 1), "conn");
+    e = e ? e : chk(up_range(h, (int32_t*)D.feed_jl, B.feed_jl, sp.q0, sp.q1), "conn");
+    e = e ? e : chk(up_range(h, (int32_t*)D.junc_phase_begin, B.junc_phase_begin, sp.j0, sp.j1 + 1), "junctions");
+    e = e ? e : chk(up_range(h, (int32_t*)D.mp_begin, B.mp_begin, sp.j0, sp.j1 + 1), "junctions");
+    e = e ? e : chk(up_range(h, (int32_t*)D.mp_mov, B.mp_mov, 4LL * sp.q0, 4LL * sp.q1), "junctions");
+    e = e ? e : chk(up_range(h, (float*)D.phase_dur, B.phase_dur, sp.p0, sp.p1), "junctions");
+    e = e ? e : chk(up_range(h, (double*)D.junc_cycle, B.junc_cycle, sp.j0, sp.j1), "junctions");
+    e = e ? e : chk(up_range(h, (float*)D.tau, B.tau, sp.v0, sp.v1), "trips");
+    e = e ? e : chk(up_range(h, (int32_t*)D.route_begin, B.route_begin, sp.v0, sp.v1 + 1), "trips");
+    e = e ? e : chk(up_range(h, (int32_t*)D.route, B.route, sp.e0, sp.e1), "trips");
+    e = e ? e : chk(up_range(h, (float*)D.vf, B.vf, sp.v0, sp.v1), "trips");
+    e = e ? e : chk(up_range(h, (float*)D.vlen, B.vlen, sp.v0, sp.v1), "trips");
+    e = e ? e : chk(up_range(h, (int32_t*)D.q_begin, B.q_begin, sp.r0, sp.r1 + 1), "queues");
+    {
+        // queue entries of the span's roads are those of its vehicles
+        const int k0 = B.q_begin[sp.r0], k1 = B.q_begin[sp.r1];
+        std::vector<QRec> qr(B.q_veh.size());
+        for (int k = k0; k < k1; ++k) {
+            const int v = B.q_veh[k];
+            const int rb = B.route_begin[v], rl = B.route_begin[v + 1] - rb;
+            QRec& q = qr[k];
+            q.tau = B.tau[v];
+            q.mask = B.q_mask[k];
+            q.vid = v;
+            q.len = B.vlen[v];
+            q.f = B.vf[v];
+            q.rp = rb;
+            q.rem = rl - 1;
+            q.nr = rl > 1 ? B.route[rb + 1] : -1;
+        }
+        e = e ? e : chk(up_range(h, (QRec*)D.q_rec, qr, k0, k1), "queues");
+    }
+    e = e ? e : chk(up_range(h, h->d_lane_ext, B.ext_of_int, sp.m0, sp.m1), "lanes");
+    e = e ? e : chk(up_range(h, (int32_t*)D.tile_inst, B.tile_inst, sp.r0, sp.r1), "instances");
+    e = e ? e : chk(up_range(h, (int32_t*)D.junc_inst, B.junc_inst, sp.j0, sp.j1), "instances");
+    e = e ? e : chk(up_range(h, (int32_t*)D.inst_vbase, B.inst_vbase, sp.k0, sp.k1), "instances");
+    e = e ? e : chk(up_range(h, (uint32_t*)D.inst_key, B.inst_key, 2LL * sp.k0, 2LL * sp.k1), "instances");
+    e = e ? e : chk(up_range(h, (long long*)D.inst_t0, B.inst_t0, sp.k0, sp.k1), "instances");
+    {
+        std::vector<long long> ends(B.n_inst, std::numeric_limits<long long>::max());
+        e = e ? e : chk(up_range(h, (long long*)D.inst_end, ends, sp.k0, sp.k1), "instances");
+    }
+    return e;
+}
+
+// the view's sizes and schedule grids from the host tables (after a create
+// or a change of the batch's instances)
+void refresh_view(tsim_handle* h)
+{
+    Build& B = h->B;
+    DevNet& D = h->D;
+    count_tiles(B);
+    D.R = B.R;
+    D.NJ = B.NJ;
+    D.NL = B.NL;
+    D.N = B.N;
+    D.G = B.G;
+    D.n_inst = B.n_inst;
+    set_sched(h, D.sched);
+}
+
+}  // namespace
+
+extern "C" {
 
 static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stream, void* device_arena,
                        size_t arena_bytes, tsim_handle** out)
@@ -1061,11 +1250,6 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     }
     Build& B = h->B;
     DevNet& D = h->D;
-    D.R = B.R;
-    D.NJ = B.NJ;
-    D.NL = B.NL;
-    D.N = B.N;
-    D.G = B.G;
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
@@ -1076,95 +1260,23 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
             h->res[kNumSched + 3] = cus * update_blocks_per_cu(-4);
         }
     }
-    set_sched(h, kSchedFused);
-    D.n_inst = B.n_inst;
+    D.sched = kSchedFused;
+    refresh_view(h);
+    h->removed.assign(B.n_inst, 0);
+    h->params = *params;
     fill_params(D.P, params);
-    auto chk = [&](hipError_t e, const char* what) -> int { return e == hipSuccess ? 0 : hip_fail(h, e, what); };
     int e = 0;
     // the fused update kernel's LDS (above the default dynamic limit), set
     // whether or not the occupancy queries above ran
-    e = e ? e : chk(prepare_update_kernels(), "fused update kernel attributes");
-    e = e ? e : chk(up(h, (int32_t*)D.tile_lane_begin, B.tile_lane_begin), "tiles");
-    e = e ? e : chk(up(h, (int32_t*)D.tile_n_road, B.tile_n_road), "tiles");
-    e = e ? e : chk(up(h, (float*)D.lane_len, B.lane_len), "lanes");
     {
-        std::vector<LaneInfo> li(B.NL);
-        for (int m = 0; m < B.NL; ++m) {
-            LaneInfo& L = li[m];
-            L.base = B.lane_base[m];
-            L.cap = B.lane_cap[m];
-            L.len = B.lane_len[m];
-            L.lim = B.lane_lim[m];
-            L.jl_out = B.jl_out[m];
-            L.jl_out_road = B.jl_out_road[m];
-            L.jl_junc = B.jl_junc[m];
-            L.green_mask = B.jl_green_mask[m];
-            L.jl_ext = B.jl_ext[m];
-            L.jl_in_local = B.jl_in_local[m];
-            L.pad0 = L.pad1 = 0;
-        }
-        e = e ? e : chk(up(h, (LaneInfo*)D.lane_info, li), "lanes");
+        const hipError_t pe = prepare_update_kernels();
+        if (pe != hipSuccess) e = hip_fail(h, pe, "fused update kernel attributes");
     }
-    e = e ? e : chk(up(h, (float*)D.lane_lim, B.lane_lim), "lanes");
-    e = e ? e : chk(up(h, (uint32_t*)D.lane_base, B.lane_base), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.lane_cap, B.lane_cap), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.lane_tile, B.lane_tile), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.lane_local, B.lane_local), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.jl_out, B.jl_out), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.jl_junc, B.jl_junc), "lanes");
-    e = e ? e : chk(up(h, (uint32_t*)D.jl_green_mask, B.jl_green_mask), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.jl_ext, B.jl_ext), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.jl_in_local, B.jl_in_local), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.jl_out_road, B.jl_out_road), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.out_begin, B.out_begin), "conn");
-    e = e ? e : chk(up(h, (int32_t*)D.out_jl, B.out_jl), "conn");
-    {
-        std::vector<int32_t> pairs(2 * B.out_jl.size());
-        for (size_t k = 0; k < B.out_jl.size(); ++k) {
-            pairs[2 * k] = B.jl_out_road[B.out_jl[k]];
-            pairs[2 * k + 1] = B.out_jl[k];
-        }
-        e = e ? e : chk(up(h, (int32_t*)D.out_pair, pairs), "conn");
+    e = e ? e : upload_tables(h, full_span(B));
+    if (!e) {
+        const hipError_t ce = hipMemcpyAsync(h->d_net, &h->D, sizeof(DevNet), hipMemcpyHostToDevice, h->stream);
+        if (ce != hipSuccess) e = hip_fail(h, ce, "view");
     }
-    e = e ? e : chk(up(h, (int32_t*)D.feed_begin, B.feed_begin), "conn");
-    e = e ? e : chk(up(h, (int32_t*)D.feed_jl, B.feed_jl), "conn");
-    e = e ? e : chk(up(h, (int32_t*)D.junc_phase_begin, B.junc_phase_begin), "junctions");
-    e = e ? e : chk(up(h, (int32_t*)D.mp_begin, B.mp_begin), "junctions");
-    e = e ? e : chk(up(h, (int32_t*)D.mp_mov, B.mp_mov), "junctions");
-    e = e ? e : chk(up(h, (float*)D.phase_dur, B.phase_dur), "junctions");
-    e = e ? e : chk(up(h, (double*)D.junc_cycle, B.junc_cycle), "junctions");
-    e = e ? e : chk(up(h, (float*)D.tau, B.tau), "trips");
-    e = e ? e : chk(up(h, (int32_t*)D.route_begin, B.route_begin), "trips");
-    e = e ? e : chk(up(h, (int32_t*)D.route, B.route), "trips");
-    e = e ? e : chk(up(h, (float*)D.vf, B.vf), "trips");
-    e = e ? e : chk(up(h, (float*)D.vlen, B.vlen), "trips");
-    e = e ? e : chk(up(h, (int32_t*)D.q_begin, B.q_begin), "queues");
-    {
-        std::vector<QRec> qr(B.q_veh.size());
-        for (size_t k = 0; k < qr.size(); ++k) {
-            const int v = B.q_veh[k];
-            const int rb = B.route_begin[v], rl = B.route_begin[v + 1] - rb;
-            QRec& q = qr[k];
-            q.tau = B.tau[v];
-            q.mask = B.q_mask[k];
-            q.vid = v;
-            q.len = B.vlen[v];
-            q.f = B.vf[v];
-            q.rp = rb;
-            q.rem = rl - 1;
-            q.nr = rl > 1 ? B.route[rb + 1] : -1;
-        }
-        e = e ? e : chk(up(h, (QRec*)D.q_rec, qr), "queues");
-    }
-    e = e ? e : chk(up(h, h->d_lane_ext, B.ext_of_int), "lanes");
-    e = e ? e : chk(up(h, (int32_t*)D.tile_inst, B.tile_inst), "instances");
-    e = e ? e : chk(up(h, (int32_t*)D.junc_inst, B.junc_inst), "instances");
-    e = e ? e : chk(up(h, (int32_t*)D.inst_vbase, B.inst_vbase), "instances");
-    e = e ? e : chk(up(h, (uint32_t*)D.inst_key, B.inst_key), "instances");
-    e = e ? e : chk(up(h, (long long*)D.inst_t0, B.inst_t0), "instances");
-    e = e ? e : chk(up(h, (long long*)D.inst_end, std::vector<long long>(B.n_inst, std::numeric_limits<long long>::max())),
-                    "instances");
-    e = e ? e : chk(hipMemcpyAsync(h->d_net, &h->D, sizeof(DevNet), hipMemcpyHostToDevice, h->stream), "view");
     if (e) {
         delete h;
         return e;
@@ -1347,6 +1459,7 @@ int tsim_autotune(tsim_handle* h, int32_t steps, int32_t rounds, int32_t* chosen
 {
     if (!h || steps < 1 || rounds < 1 || steps > 100000 || rounds > 100)
         return fail(nullptr, TSIM_EINVAL, "bad handle, steps or rounds");
+    if (h->D.R + h->D.NJ == 0) return fail(&h->err, TSIM_EINVAL, "autotune of an empty batch");
     float best_ms[kNumSched];
     const int rc = time_schedules(h, steps, rounds, best_ms);
     int pick = h->D.sched;
@@ -1367,6 +1480,7 @@ int tsim_autotune_launch(tsim_handle* h, int32_t steps, int32_t rounds, int32_t*
 {
     if (!h || steps < 1 || rounds < 1 || steps > 100000 || rounds > 100)
         return fail(nullptr, TSIM_EINVAL, "bad handle, steps or rounds");
+    if (h->D.R + h->D.NJ == 0) return fail(&h->err, TSIM_EINVAL, "autotune of an empty batch");
     const int keep_conc = h->ps.n > 0 ? 1 : 0;
     float best_ms[2][kNumSched];
     int rc = TSIM_OK;
@@ -1399,6 +1513,7 @@ int tsim_autotune_launch(tsim_handle* h, int32_t steps, int32_t rounds, int32_t*
 int tsim_step(tsim_handle* h, int32_t n_steps)
 {
     if (!h || n_steps < 0) return fail(nullptr, TSIM_EINVAL, "bad handle or step count");
+    if (h->D.R + h->D.NJ == 0) return TSIM_OK;   // an empty batch has nothing to step
     if (h->graph_chunk > 0 && !h->prof) {
         if (!h->graph) {
             int rc = capture_chunk(h);
@@ -1829,6 +1944,385 @@ int tsim_batch_step(tsim_batch* b, int32_t n_steps) { return tsim_step(b, n_step
 int tsim_batch_set_graph_steps(tsim_batch* b, int32_t chunk) { return tsim_set_graph_steps(b, chunk); }
 
 int tsim_batch_destroy(tsim_batch* b) { return tsim_destroy(b); }
+
+// ---------------------------------------------------------------------------
+// instances joining and leaving a running batch
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct tsim_instance {
+    Build B;
+    tsim_params params{};
+};
+
+namespace {
+
+// appends the tables of a single-instance build M (instance key from seed)
+// to the batch's host tables; returns the span of the new entries, or sets
+// the error and returns false when the reserved capacity is exceeded
+bool append_build(tsim_handle* h, const Build& M, uint64_t seed, Span& sp)
+{
+    Build& B = h->B;
+    const Caps& c = h->cap;
+    const int R0 = B.R, NJ0 = B.NJ, NL0 = B.NL, N0 = B.N, k = B.n_inst;
+    const int NRL0 = B.rl_off.back(), NJL0 = B.jl_off.back();
+    const long long S0 = (long long)B.slots, P0 = (long long)B.phase_dur.size(), E0 = (long long)B.route.size();
+    const int Q0 = (int)B.out_jl.size(), QV0 = (int)B.q_veh.size();
+    if (k + 1 > c.n_inst || R0 + M.R > c.R || NJ0 + M.NJ > c.NJ || NL0 + M.NL > c.NL || NRL0 + M.NRL > c.NRL ||
+        NJL0 + M.NJL > c.NJL || N0 + M.N > c.N || S0 + (long long)M.slots > c.S ||
+        P0 + (long long)M.phase_dur.size() > c.P || E0 + (long long)M.route.size() > c.E) {
+        h->err = "the instance does not fit the batch's remaining capacity";
+        return false;
+    }
+    auto uext = [&](int e) { return e < M.NRL ? NRL0 + e : B.NRL + NJL0 + (e - M.NRL); };
+    for (int r = 0; r < M.R; ++r) {
+        B.tile_lane_begin.push_back(M.tile_lane_begin[r + 1] + NL0);
+        B.tile_n_road.push_back(M.tile_n_road[r]);
+        B.q_begin.push_back(M.q_begin[r + 1] + QV0);
+        B.tile_inst.push_back(k);
+    }
+    for (int m = 0; m < M.NL; ++m) {
+        const bool jl = M.jl_out[m] >= 0;
+        B.lane_len.push_back(M.lane_len[m]);
+        B.lane_lim.push_back(M.lane_lim[m]);
+        B.lane_base.push_back((uint32_t)(M.lane_base[m] + S0));
+        B.lane_cap.push_back(M.lane_cap[m]);
+        B.lane_tile.push_back(M.lane_tile[m] + R0);
+        B.lane_local.push_back(M.lane_local[m]);
+        B.jl_out.push_back(jl ? M.jl_out[m] + NL0 : -1);
+        B.jl_junc.push_back(jl ? M.jl_junc[m] + NJ0 : 0);
+        B.jl_green_mask.push_back(M.jl_green_mask[m]);
+        B.jl_ext.push_back(jl ? M.jl_ext[m] + NJL0 : -1);
+        B.jl_in_local.push_back(M.jl_in_local[m]);
+        B.jl_out_road.push_back(jl ? M.jl_out_road[m] + R0 : -1);
+        B.out_begin.push_back(M.out_begin[m + 1] + Q0);
+        B.feed_begin.push_back(M.feed_begin[m + 1] + Q0);
+        const int e = uext(M.ext_of_int[m]);
+        B.ext_of_int[NL0 + m] = e;
+        B.int_of_ext[e] = NL0 + m;
+    }
+    for (int q : M.out_jl) B.out_jl.push_back(q + NL0);
+    for (int q : M.feed_jl) B.feed_jl.push_back(q + NL0);
+    for (int j = 0; j < M.NJ; ++j) {
+        B.junc_phase_begin.push_back(M.junc_phase_begin[j + 1] + (int)P0);
+        B.junc_policy.push_back(M.junc_policy[j]);
+        B.junc_cycle.push_back(M.junc_cycle[j]);
+        B.mp_begin.push_back(M.mp_begin[j + 1] + Q0);
+        B.junc_inst.push_back(k);
+    }
+    for (size_t q = 0; q < M.mp_mov.size(); q += 4) {
+        B.mp_mov.push_back(M.mp_mov[q] + NL0);
+        B.mp_mov.push_back(M.mp_mov[q + 1] + NL0);
+        B.mp_mov.push_back(M.mp_mov[q + 2]);
+        B.mp_mov.push_back(0);
+    }
+    for (float d : M.phase_dur) B.phase_dur.push_back(d);
+    for (int i = 0; i < M.N; ++i) {
+        B.tau.push_back(M.tau[i]);
+        B.vf.push_back(M.vf[i]);
+        B.vlen.push_back(M.vlen[i]);
+        B.route_begin.push_back(M.route_begin[i + 1] + (int)E0);
+    }
+    for (int r : M.route) B.route.push_back(r + R0);
+    for (size_t q = 0; q < M.q_veh.size(); ++q) {
+        B.q_veh.push_back(M.q_veh[q] + N0);
+        B.q_mask.push_back(M.q_mask[q]);
+    }
+    B.slots += M.slots;
+    B.R += M.R;
+    B.NJ += M.NJ;
+    B.NL += M.NL;
+    B.N += M.N;
+    B.NJL += M.NJL;
+    B.n_inst += 1;
+    B.inst_vbase.push_back(N0);
+    B.inst_key.push_back((uint32_t)seed);
+    B.inst_key.push_back((uint32_t)(seed >> 32));
+    B.inst_t0.push_back(0);
+    B.road_off.push_back(B.R);
+    B.junc_off.push_back(B.NJ);
+    B.rl_off.push_back(NRL0 + M.NRL);
+    B.jl_off.push_back(NJL0 + M.NJL);
+    B.veh_off.push_back(B.N);
+    sp = Span{R0, B.R, NL0, B.NL, NJ0, B.NJ, N0, B.N, Q0, (int)B.out_jl.size(), (int)P0, (int)B.phase_dur.size(), k,
+              k + 1, E0, (long long)B.route.size()};
+    return true;
+}
+
+// removes the last instance's entries from the host tables
+void pop_build(tsim_handle* h)
+{
+    Build& B = h->B;
+    const int k = B.n_inst - 1;
+    const int r0 = B.road_off[k], j0 = B.junc_off[k], v0 = B.veh_off[k];
+    const int m0 = B.tile_lane_begin[r0];
+    const int q0 = B.out_begin[m0], qv0 = B.q_begin[r0];
+    const int p0 = B.junc_phase_begin[j0], e0 = B.route_begin[v0];
+    const uint64_t s0 = m0 < (int)B.lane_base.size() ? B.lane_base[m0] : B.slots;
+    for (int m = m0; m < B.NL; ++m) B.int_of_ext[B.ext_of_int[m]] = -1;
+    B.tile_lane_begin.resize(r0 + 1);
+    B.tile_n_road.resize(r0);
+    B.q_begin.resize(r0 + 1);
+    B.tile_inst.resize(r0);
+    for (auto* v : {&B.lane_cap, &B.lane_tile, &B.lane_local, &B.jl_out, &B.jl_junc, &B.jl_ext, &B.jl_in_local,
+                    &B.jl_out_road})
+        v->resize(m0);
+    B.lane_len.resize(m0);
+    B.lane_lim.resize(m0);
+    B.lane_base.resize(m0);
+    B.jl_green_mask.resize(m0);
+    B.out_begin.resize(m0 + 1);
+    B.feed_begin.resize(m0 + 1);
+    B.out_jl.resize(q0);
+    B.feed_jl.resize(q0);
+    B.junc_phase_begin.resize(j0 + 1);
+    B.junc_policy.resize(j0);
+    B.junc_cycle.resize(j0);
+    B.mp_begin.resize(j0 + 1);
+    B.mp_mov.resize(4 * (size_t)q0);
+    B.junc_inst.resize(j0);
+    B.phase_dur.resize(p0);
+    B.tau.resize(v0);
+    B.vf.resize(v0);
+    B.vlen.resize(v0);
+    B.route_begin.resize(v0 + 1);
+    B.route.resize(e0);
+    B.q_veh.resize(qv0);
+    B.q_mask.resize(qv0);
+    B.slots = s0;
+    B.R = r0;
+    B.NJ = j0;
+    B.NL = m0;
+    B.N = v0;
+    B.NJL = B.jl_off[k];
+    B.n_inst = k;
+    B.inst_vbase.resize(k);
+    B.inst_key.resize(2 * (size_t)k);
+    B.inst_t0.resize(k);
+    for (auto* v : {&B.road_off, &B.junc_off, &B.rl_off, &B.jl_off, &B.veh_off}) v->resize(k + 1);
+}
+
+// after the batch's instances changed: sizes and grids, the device view, and
+// no captured graph of the old launches
+int batch_changed(tsim_handle* h)
+{
+    refresh_view(h);
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->d_net, &h->D, sizeof(DevNet), hipMemcpyHostToDevice, h->stream));
+    return TSIM_OK;
+}
+
+bool same_model(const tsim_params& a, const tsim_params& b)
+{
+    return a.dt == b.dt && a.T == b.T && a.a_max == b.a_max && a.b_comf == b.b_comf && a.s0 == b.s0 &&
+           a.delta == b.delta && a.politeness == b.politeness && a.a_th == b.a_th && a.b_safe == b.b_safe &&
+           a.p_max == b.p_max && a.p_min == b.p_min && a.a_emerg == b.a_emerg;
+}
+
+// appends a built instance and uploads its tables; the state follows
+int add_impl(tsim_handle* b, const Build& M, const tsim_params& prm, int32_t* instance)
+{
+    if (!same_model(prm, b->params))
+        return fail(&b->err, TSIM_EINVAL, "batch instances must share every parameter but the seed");
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    Span sp;
+    if (!append_build(b, M, prm.seed, sp)) return fail(&b->err, TSIM_ENOMEM, b->err);
+    b->removed.push_back(0);
+    int rc = upload_tables(b, sp);
+    if (rc == TSIM_OK) rc = batch_changed(b);
+    if (rc) return rc;
+    *instance = b->B.n_inst - 1;
+    return TSIM_OK;
+}
+
+void fill_capacity(const Caps& c, tsim_batch_capacity* out)
+{
+    out->instances = (int32_t)c.n_inst;
+    out->junctions = (int32_t)c.NJ;
+    out->roads = (int32_t)c.R;
+    out->road_lanes = (int32_t)c.NRL;
+    out->jlanes = (int32_t)c.NJL;
+    out->phases = (int32_t)c.P;
+    out->vehicles = (int32_t)c.N;
+    out->route_entries = c.E;
+    out->slots = c.S;
+}
+
+int caps_from(const tsim_batch_capacity* cap, Caps& c)
+{
+    if (!cap || cap->instances < 0 || cap->junctions < 0 || cap->roads < 0 || cap->road_lanes < 0 || cap->jlanes < 0 ||
+        cap->phases < 0 || cap->vehicles < 0 || cap->route_entries < 0 || cap->slots < 0 || cap->slots >= (1ll << 31))
+        return TSIM_EINVAL;
+    c.n_inst = cap->instances;
+    c.NJ = cap->junctions;
+    c.R = cap->roads;
+    c.NRL = cap->road_lanes;
+    c.NJL = cap->jlanes;
+    c.NL = (long long)cap->road_lanes + cap->jlanes;
+    c.P = cap->phases;
+    c.N = cap->vehicles;
+    c.E = cap->route_entries;
+    c.S = cap->slots;
+    c.G = g_bound((int)c.R);
+    return TSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsim_instance_build(const tsim_network* net, const tsim_trips* trips, const tsim_params* params,
+                        tsim_instance** out)
+{
+    if (!out) return fail(nullptr, TSIM_EINVAL, "null out");
+    *out = nullptr;
+    tsim_instance* in = new (std::nothrow) tsim_instance();
+    if (!in) return fail(nullptr, TSIM_ENOMEM, "host allocation failed");
+    const int rc = build_tables(net, trips, params, in->B, nullptr);
+    if (rc) {
+        delete in;
+        return rc;
+    }
+    single_instance(in->B, params);
+    in->params = *params;
+    *out = in;
+    return TSIM_OK;
+}
+
+int tsim_instance_free(tsim_instance* in)
+{
+    delete in;
+    return TSIM_OK;
+}
+
+int tsim_instance_capacity(const tsim_instance* in, tsim_batch_capacity* out)
+{
+    if (!in || !out) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Caps c = caps_of(in->B);
+    fill_capacity(c, out);
+    return TSIM_OK;
+}
+
+int tsim_batch_reserve_footprint(const tsim_batch_capacity* cap, size_t* bytes_out)
+{
+    if (!bytes_out) return fail(nullptr, TSIM_EINVAL, "null bytes_out");
+    tsim_handle tmp;
+    if (caps_from(cap, tmp.cap)) return fail(nullptr, TSIM_EINVAL, "bad capacity");
+    *bytes_out = arena_size(&tmp) + 256;
+    return TSIM_OK;
+}
+
+int tsim_batch_reserve(const tsim_batch_capacity* cap, const tsim_params* params, void* hip_stream,
+                       void* device_arena, size_t arena_bytes, tsim_batch** out)
+{
+    if (!out || !params || !device_arena) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    *out = nullptr;
+    if (!(params->dt > 0) || !(params->a_max > 0) || !(params->b_comf > 0) || !(params->T >= 0) || !(params->s0 >= 0))
+        return fail(nullptr, TSIM_EINVAL, "bad parameters");
+    tsim_handle* h = new (std::nothrow) tsim_handle();
+    if (!h) return fail(nullptr, TSIM_ENOMEM, "host allocation failed");
+    if (caps_from(cap, h->cap)) {
+        delete h;
+        return fail(nullptr, TSIM_EINVAL, "bad capacity");
+    }
+    // an empty union: external road lanes of later instances from 0, their
+    // junction lanes after the reserved road lanes
+    Build& B = h->B;
+    B.NRL = (int)h->cap.NRL;
+    B.n_inst = 0;
+    B.tile_lane_begin.assign(1, 0);
+    B.out_begin.assign(1, 0);
+    B.feed_begin.assign(1, 0);
+    B.junc_phase_begin.assign(1, 0);
+    B.mp_begin.assign(1, 0);
+    B.route_begin.assign(1, 0);
+    B.q_begin.assign(1, 0);
+    B.int_of_ext.assign(h->cap.NRL + h->cap.NJL, -1);
+    B.ext_of_int.assign(h->cap.NL, -1);
+    for (auto* v : {&B.road_off, &B.junc_off, &B.rl_off, &B.jl_off, &B.veh_off}) v->assign(1, 0);
+    count_tiles(B);
+    return create_impl(h, params, hip_stream, device_arena, arena_bytes, out);
+}
+
+int tsim_batch_add(tsim_batch* b, const tsim_instance* in, int32_t* instance)
+{
+    if (!b || !in || !instance) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    int rc = add_impl(b, in->B, in->params, instance);
+    if (rc) return rc;
+    // a fresh instance: every vehicle waiting at local step 0
+    const Build& M = in->B;
+    std::vector<int32_t> st(M.N, TSIM_WAITING), lane(M.N, -1), rpos(M.N, 0), fs(M.N, -1);
+    std::vector<float> xz(M.N, 0.f), vz(M.N, 0.f);
+    std::vector<int32_t> zero_nj(M.NJ, 0);
+    return upload_state(b, *instance, 0, st.data(), lane.data(), rpos.data(), xz.data(), vz.data(), fs.data(),
+                        M.junc_policy.data(), zero_nj.data());
+}
+
+int tsim_batch_add_member(tsim_batch* b, tsim_handle* member, int32_t* instance)
+{
+    if (!b || !member || !instance || member == b || member->B.n_inst != 1)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments (the member must be a single-instance handle)");
+    const Build& M = member->B;
+    std::vector<int32_t> status(M.N), lane(M.N), rpos(M.N), fs(M.N), pol(M.NJ), ph(M.NJ);
+    std::vector<float> x(M.N), v(M.N);
+    tsim_state_host st{0, status.data(), lane.data(), rpos.data(), x.data(), v.data(), fs.data(), pol.data(), ph.data()};
+    int rc = tsim_get_state(member, &st);
+    if (rc) return rc;
+    rc = add_impl(b, M, member->params, instance);
+    if (rc) return rc;
+    return upload_state(b, *instance, st.step, status.data(), lane.data(), rpos.data(), x.data(), v.data(), fs.data(),
+                        pol.data(), ph.data());
+}
+
+int tsim_batch_remove(tsim_batch* b, int32_t instance)
+{
+    if (!b || instance < 0 || instance >= b->B.n_inst || b->removed[instance])
+        return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    // frozen from its current local step on (no further change of any kind)
+    tsim_metrics m;
+    int rc = metrics_impl(b, instance, &m);
+    if (rc && rc != TSIM_ESTATE) return rc;
+    HIPCHK(b, launch_set_end(b->D, instance, (long long)m.step, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    b->removed[instance] = 1;
+    // trailing removed instances give their space back
+    bool popped = false;
+    while (b->B.n_inst > 0 && b->removed.back()) {
+        pop_build(b);
+        b->removed.pop_back();
+        popped = true;
+    }
+    return popped ? batch_changed(b) : TSIM_OK;
+}
+
+int tsim_batch_capacity_left(tsim_batch* b, tsim_batch_capacity* out)
+{
+    if (!b || !out) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const Build& B = b->B;
+    Caps c = b->cap;
+    c.n_inst -= B.n_inst;
+    c.R -= B.R;
+    c.NJ -= B.NJ;
+    c.NL -= B.NL;
+    c.NRL -= B.rl_off.back();
+    c.NJL -= B.jl_off.back();
+    c.N -= B.N;
+    c.S -= (long long)B.slots;
+    c.P -= (long long)B.phase_dur.size();
+    c.E -= (long long)B.route.size();
+    fill_capacity(c, out);
+    return TSIM_OK;
+}
+
+int tsim_batch_num_instances(tsim_batch* b, int32_t* n)
+{
+    if (!b || !n) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    *n = b->B.n_inst;
+    return TSIM_OK;
+}
 
 const char* tsim_last_error(const tsim_handle* h)
 {

@@ -61,6 +61,13 @@ class tsim_state_host(C.Structure):
                 ("junc_phase", C.c_void_p)]
 
 
+class tsim_batch_capacity(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("instances", "junctions", "roads", "road_lanes", "jlanes", "phases",
+                                         "vehicles")] + [("route_entries", C.c_int64), ("slots", C.c_int64)]
+
+
+CAPACITY_FIELDS = [n for n, _ in tsim_batch_capacity._fields_]
+
 _lib = None
 
 EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases", "tsim_get_metrics",
@@ -71,7 +78,10 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_set_graph_steps", "tsim_batch_set_graph_steps", "tsim_set_schedule", "tsim_get_schedule",
            "tsim_autotune", "tsim_batch_set_horizon", "tsim_set_concurrency", "tsim_autotune_launch",
            "tsim_set_signal_policy", "tsim_batch_set_signal_policy", "tsim_batch_set_state",
-           "tsim_batch_get_road_mean_speed", "tsim_batch_get_lane_waiting_counts", "tsim_batch_get_lane_order"]
+           "tsim_batch_get_road_mean_speed", "tsim_batch_get_lane_waiting_counts", "tsim_batch_get_lane_order",
+           "tsim_instance_build", "tsim_instance_free", "tsim_instance_capacity", "tsim_batch_reserve_footprint",
+           "tsim_batch_reserve", "tsim_batch_add", "tsim_batch_add_member", "tsim_batch_remove",
+           "tsim_batch_capacity_left", "tsim_batch_num_instances"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -119,6 +129,16 @@ def lib():
         L.tsim_batch_get_road_mean_speed.argtypes = [P, C.c_int32, P, C.c_int32]
         L.tsim_batch_get_lane_waiting_counts.argtypes = [P, C.c_int32, P, C.c_int32]
         L.tsim_batch_get_lane_order.argtypes = [P, C.c_int32, P, P, C.c_int32, C.c_int32]
+        L.tsim_instance_build.argtypes = [P, P, P, C.POINTER(C.c_void_p)]
+        L.tsim_instance_free.argtypes = [P]
+        L.tsim_instance_capacity.argtypes = [P, P]
+        L.tsim_batch_reserve_footprint.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.tsim_batch_reserve.argtypes = [P, P, P, P, C.c_size_t, C.POINTER(C.c_void_p)]
+        L.tsim_batch_add.argtypes = [P, P, P]
+        L.tsim_batch_add_member.argtypes = [P, P, P]
+        L.tsim_batch_remove.argtypes = [P, C.c_int32]
+        L.tsim_batch_capacity_left.argtypes = [P, P]
+        L.tsim_batch_num_instances.argtypes = [P, P]
         L.tsim_batch_destroy.argtypes = [P]
         L.tsim_last_error.argtypes = [P]
         L.tsim_last_error.restype = C.c_char_p
@@ -154,9 +174,13 @@ class _Inputs:
                                  "phase_duration", "phase_green_begin", "phase_green_jl", "junc_policy")])
         self.trips = tsim_trips(trips.n_vehicles, *[_p(a[k]) for k in (
             "depart_time", "route_begin", "route_roads", "v0_factor", "length")])
-        self.params = tsim_params(params.dt, params.T, params.a_max, params.b_comf, params.s0, params.delta,
-                                  params.politeness, params.a_th, params.b_safe, params.p_max, params.p_min,
-                                  params.a_emerg, int(params.seed))
+        self.params = _Inputs.params_of(params)
+
+    @staticmethod
+    def params_of(params):
+        return tsim_params(params.dt, params.T, params.a_max, params.b_comf, params.s0, params.delta,
+                           params.politeness, params.a_th, params.b_safe, params.p_max, params.p_min,
+                           params.a_emerg, int(params.seed))
 
 
 def _check(rc, h=None):
@@ -323,9 +347,118 @@ def _state_in(st, net):
     return a, s
 
 
+class Instance:
+    """A simulation validated and laid out on the host (tsim_instance_build),
+    ready to join a batch; building needs no GPU."""
+
+    def __init__(self, net, trips, params):
+        self.net, self.trips, self.params = net, trips, params
+        ins = _Inputs(net, trips, params)
+        h = C.c_void_p()
+        _check(lib().tsim_instance_build(C.byref(ins.net), C.byref(ins.trips), C.byref(ins.params), C.byref(h)))
+        self.h = h
+
+    def capacity(self):
+        c = tsim_batch_capacity()
+        _check(lib().tsim_instance_capacity(self.h, C.byref(c)))
+        return {k: int(getattr(c, k)) for k in CAPACITY_FIELDS}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tsim_instance_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _capacity_struct(cap):
+    return tsim_batch_capacity(*[int(cap[k]) for k in CAPACITY_FIELDS])
+
+
+def reserve_footprint(cap):
+    n = C.c_size_t(0)
+    _check(lib().tsim_batch_reserve_footprint(C.byref(_capacity_struct(cap)), C.byref(n)))
+    return int(n.value)
+
+
+def add_capacity(a, b, scale=1):
+    return {k: int(a.get(k, 0)) + int(scale * b[k]) for k in CAPACITY_FIELDS}
+
+
 class Batch:
     """Many independent instances resident together and stepped by the same
     launches (tsim_batch_* in include/tsim.h)."""
+
+    @classmethod
+    def reserve(cls, capacity, params, device="cuda:0", stream=None):
+        """An empty batch with room for the given totals (a dict of the
+        tsim_batch_capacity fields); instances join with add()."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("tsim needs a GPU: torch.cuda.is_available() is False")
+        self = cls.__new__(cls)
+        self.n = 0
+        self.nets, self.trips, self.params = [], [], []
+        self._ins = []
+        cs = _capacity_struct(capacity)
+        nbytes = C.c_size_t(0)
+        _check(lib().tsim_batch_reserve_footprint(C.byref(cs), C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        p = _Inputs.params_of(params)
+        h = C.c_void_p()
+        _check(lib().tsim_batch_reserve(C.byref(cs), C.byref(p), C.c_void_p(self.stream.cuda_stream),
+                                        C.c_void_p(self.arena.data_ptr()), C.c_size_t(self.arena.numel()),
+                                        C.byref(h)))
+        self.h = h
+        return self
+
+    def add(self, net, trips=None, params=None):
+        """Appends an instance (an Instance, or net/trips/params) at the step
+        boundary, starting at its local step 0; returns its id."""
+        inst = net if isinstance(net, Instance) else Instance(net, trips, params)
+        k = C.c_int32(0)
+        _check(lib().tsim_batch_add(self.h, inst.h, C.byref(k)), self.h)
+        self._place(int(k.value), inst.net, inst.trips, inst.params)
+        return int(k.value)
+
+    def add_member(self, sim):
+        """Appends a copy of a live Sim (network, trips, parameters and
+        current state); returns its id."""
+        k = C.c_int32(0)
+        _check(lib().tsim_batch_add_member(self.h, sim.h, C.byref(k)), self.h)
+        self._place(int(k.value), sim.net, sim.trips, sim.params)
+        return int(k.value)
+
+    def _place(self, k, net, trips, params):
+        del self.nets[k:], self.trips[k:], self.params[k:]
+        self.nets.append(net)
+        self.trips.append(trips)
+        self.params.append(params)
+        self.n = len(self.nets)
+
+    def remove(self, k):
+        """Freezes instance k for good; trailing removed instances give their
+        space (and ids) back."""
+        _check(lib().tsim_batch_remove(self.h, int(k)), self.h)
+        n = self.num_instances()
+        del self.nets[n:], self.trips[n:], self.params[n:]
+        self.n = n
+
+    def num_instances(self):
+        n = C.c_int32(0)
+        _check(lib().tsim_batch_num_instances(self.h, C.byref(n)), self.h)
+        return int(n.value)
+
+    def capacity_left(self):
+        c = tsim_batch_capacity()
+        _check(lib().tsim_batch_capacity_left(self.h, C.byref(c)), self.h)
+        return {k: int(getattr(c, k)) for k in CAPACITY_FIELDS}
 
     def __init__(self, nets, trips, params, device="cuda:0", stream=None):
         import torch

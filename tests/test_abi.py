@@ -76,3 +76,20 @@ def test_no_gpu_fails_loudly(L):
     w = W.config1()
     with pytest.raises(RuntimeError):
         T.Sim(w.network, w.trips, w.params)
+
+
+def test_instance_capacity_and_reservation_without_gpu(L):
+    w = W.config1()
+    inst = T.Instance(w.network, w.trips, w.params)
+    cap = inst.capacity()
+    assert cap["instances"] == 1 and cap["vehicles"] == w.trips.n_vehicles
+    assert cap["roads"] == w.network.n_roads and cap["junctions"] == w.network.n_junctions
+    assert cap["road_lanes"] == w.network.n_road_lanes and cap["jlanes"] == w.network.n_jlanes
+    one = T.reserve_footprint(cap)
+    two = T.reserve_footprint(T.add_capacity(cap, cap))
+    assert 0 < one < two <= 2 * one + 4096
+    # the reservation for exactly one instance holds what a single handle needs, give or take alignment
+    assert abs(one - T.footprint(w.network, w.trips, w.params)) < 64 * 1024
+    bad = dict(cap, vehicles=-1)
+    with pytest.raises(T.TsimError):
+        T.reserve_footprint(bad)
