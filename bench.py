@@ -288,7 +288,7 @@ def run_serve(args):
     if args.serve_mode == "batched":
         fac = SV.BatchFactory(n_streams=args.streams, graph_steps=args.tick, concurrent=args.concurrent == "1")
         loop = SV.BatchedServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick,
-                                   max_batches=args.max_batches, max_jobs_per_batch=args.max_jobs_per_batch)
+                                   max_batches=args.max_batches)
     else:
         fac = SV.GpuFactory(n_streams=args.streams, graph_steps=args.tick)
         loop = SV.ServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick)
@@ -303,7 +303,7 @@ def run_serve(args):
                          horizon=w.n_steps) for k, w in enumerate(ws)]
         if args.serve_mode == "batched":
             loop_s = SV.BatchedServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick,
-                                         max_batches=args.max_batches, max_jobs_per_batch=args.max_jobs_per_batch)
+                                         max_batches=args.max_batches)
         else:
             loop_s = SV.ServeLoop(fac, hbm_budget=int(args.budget_gib * 2**30), steps_per_tick=args.tick)
         summ_s = SV.summarize(loop_s.run(jobs_s))
@@ -461,7 +461,6 @@ def main():
                          "(auto; on when the schedule is fixed; serving: off)")
     ap.add_argument("--serve-mode", choices=["batched", "streams"], default="batched")
     ap.add_argument("--max-batches", type=int, default=3)
-    ap.add_argument("--max-jobs-per-batch", type=int, default=64)
     args = ap.parse_args()
     if args.summarize:
         summarize_window(args.summarize, args.steps if args.steps is not None else 200)

@@ -194,10 +194,11 @@ class ServeLoop:
 
 
 class BatchFactory:
-    """Jobs grouped into batches (``tsim_batch_*``: one set of launches steps
-    every instance of a batch), each batch on one stream of a pool; each
-    instance is frozen at its own horizon.  ``concurrent`` runs each batch's
-    update passes on side streams (``tsim_set_concurrency``)."""
+    """Resident batches reserved once (``tsim_batch_reserve``), each on one
+    stream of a pool; jobs are laid out on the host (``tsim_instance_build``,
+    no GPU work, so builder threads can do it) and join a running batch at
+    its next step boundary (``tsim_batch_add``).  ``concurrent`` runs each
+    batch's update passes on side streams (``tsim_set_concurrency``)."""
 
     def __init__(self, n_streams=3, device="cuda:0", graph_steps=30, concurrent=False):
         import torch
@@ -207,22 +208,31 @@ class BatchFactory:
         self.graph_steps = int(graph_steps)
         self.concurrent = bool(concurrent)
         self._next = 0
-        self._lock = threading.Lock()
 
     def footprint(self, job):
         from paper_2406_10661_amd.tsim import footprint
         return footprint(job.network, job.trips, job.params)
 
-    def create_batch(self, jobs):
+    def instance(self, job):
+        from paper_2406_10661_amd.tsim import Instance
+        return Instance(job.network, job.trips, job.params)
+
+    def capacity_of(self, job):
+        inst = self.instance(job)
+        cap = inst.capacity()
+        inst.close()
+        return cap
+
+    def reserve_footprint(self, cap):
+        from paper_2406_10661_amd.tsim import reserve_footprint
+        return reserve_footprint(cap)
+
+    def reserve(self, cap, params):
         from paper_2406_10661_amd.tsim import Batch
-        with self._lock:
-            s = self.streams[self._next % len(self.streams)]
-            self._next += 1
+        s = self.streams[self._next % len(self.streams)]
+        self._next += 1
         with self.torch.cuda.stream(s):
-            b = Batch([j.network for j in jobs], [j.trips for j in jobs], [j.params for j in jobs],
-                      device=self.device, stream=s)
-            for k, j in enumerate(jobs):
-                b.set_horizon(k, j.horizon)
+            b = Batch.reserve(cap, params, device=self.device, stream=s)
             if self.concurrent:
                 b.set_concurrency(True)
             if self.graph_steps:
@@ -238,43 +248,86 @@ class BatchFactory:
         self.torch.cuda.synchronize(self.device)
 
 
-class BatchedServeLoop:
-    """Continuous batching over batches of jobs: admitted jobs that are not
-    yet running are gathered into a new batch whenever fewer than
-    ``max_batches`` batches are running or being built; each batch is stepped
-    in chunks of ``steps_per_tick`` steps (at most ``depth`` chunks ahead of
-    the device) until its longest job's horizon, and each job's result is
-    read as soon as the device has passed that job's own horizon.  A job's
-    memory stays counted against the budget until its batch is released."""
+CAP_KEYS = ("instances", "junctions", "roads", "road_lanes", "jlanes", "phases", "vehicles", "route_entries", "slots")
 
-    def __init__(self, factory, hbm_budget, steps_per_tick=30, depth=2, max_batches=3, max_jobs_per_batch=64,
-                 builders=2, clock=time.perf_counter):
+
+def fits(need, left):
+    return all(need[k] <= left[k] for k in CAP_KEYS)
+
+
+def batch_capacity(caps, budget_bytes, reserve_footprint):
+    """Totals of one batch sized to a byte budget: every dimension scaled from
+    the largest per-vehicle ratio among the given job capacities, plus room
+    for the largest single job, so that any of the jobs fits an empty batch."""
+    ratio = {k: max(c[k] / max(c["vehicles"], 1) for c in caps) for k in CAP_KEYS}
+    big = {k: max(c[k] for c in caps) for k in CAP_KEYS}
+
+    def cap_for(v):
+        return {k: int(big[k] + ratio[k] * v) + (1 if k == "instances" else 0) for k in CAP_KEYS}
+
+    lo, hi = 0, 1 << 27
+    if reserve_footprint(cap_for(0)) > budget_bytes:
+        raise ValueError("the HBM share of a batch cannot hold the largest job")
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if reserve_footprint(cap_for(mid)) <= budget_bytes:
+            lo = mid
+        else:
+            hi = mid
+    return cap_for(lo)
+
+
+class BatchedServeLoop:
+    """Continuous batching: ``max_batches`` resident batches share the HBM
+    budget, each reserved once (``batch_capacity``).  An arriving job is laid
+    out on the host by a builder thread; it then joins the first running
+    batch with room for it (arrival order, first fit) at that batch's next
+    step boundary, with its horizon set, so requests that arrive while others
+    are on the GPU join them.  Each batch is stepped in chunks of
+    ``steps_per_tick`` steps (at most ``depth`` chunks ahead of the device);
+    when a job's horizon has passed on the device, or a waiting job fits, the
+    batch stops taking new chunks until the device has caught up, then the
+    finished jobs' results are read and the jobs removed
+    (``tsim_batch_remove``), and waiting jobs are added."""
+
+    def __init__(self, factory, hbm_budget, steps_per_tick=30, depth=2, max_batches=3, builders=2,
+                 capacity=None, clock=time.perf_counter, max_jobs_per_batch=None):
         self.f = factory
         self.budget = int(hbm_budget)
         self.k = int(steps_per_tick)
         self.depth = int(depth)
         self.max_batches = int(max_batches)
-        self.max_jobs = int(max_jobs_per_batch)
         self.n_builders = int(builders)
+        self.capacity = capacity
         self.clock = clock
 
     def run(self, jobs):
         jobs = sorted(jobs, key=lambda j: j.arrival)
+        if not jobs:
+            return {"jobs": [], "wall_s": 0.0, "batches": 0, "peak_bytes": 0}
+        # batch sizing from the jobs' shapes (host work, before the clock starts)
+        insts = {}
         for j in jobs:
             j.footprint = self.f.footprint(j)
-            if j.footprint > self.budget:
-                raise ValueError(f"job {j.jid} needs {j.footprint} bytes, more than the whole budget")
+        cap = self.capacity
+        if cap is None:
+            sample = [self.f.capacity_of(j) for j in jobs]
+            cap = batch_capacity(sample, self.budget // self.max_batches, self.f.reserve_footprint)
+        batches = []
+        for _ in range(self.max_batches):
+            b, st = self.f.reserve(cap, jobs[0].params)
+            batches.append({"batch": b, "stream": st, "jobs": {}, "inflight": collections.deque(), "steps": 0,
+                            "done": 0})
+        reserved = sum(self.f.reserve_footprint(cap) for _ in batches)
         t0 = self.clock()
         now = lambda: self.clock() - t0
-        waiting = collections.deque(jobs)
-        admitted = collections.deque()
+        waiting = collections.deque(jobs)     # not yet arrived
         lock = threading.Lock()
         build_q = collections.deque()
         build_cv = threading.Condition(lock)
-        ready = collections.deque()
+        ready = []                            # built, waiting for room (arrival order)
         stop = [False]
         errors = []
-        state = {"used": 0, "peak": 0, "building": 0}
 
         def builder():
             while True:
@@ -283,74 +336,76 @@ class BatchedServeLoop:
                         build_cv.wait(0.05)
                     if stop[0] and not build_q:
                         return
-                    grp = build_q.popleft()
+                    j = build_q.popleft()
                 try:
-                    b, st = self.f.create_batch(grp)
-                except Exception as e:
+                    inst = self.f.instance(j)
+                    need = inst.capacity()
+                except Exception as e:  # surfaced by the main loop
                     errors.append(e)
                     return
                 with lock:
-                    ready.append({"batch": b, "stream": st, "jobs": grp, "steps": 0, "inflight": collections.deque(),
-                                  "done_steps": 0, "horizon": max(j.horizon for j in grp)})
+                    insts[j.jid] = (inst, need)
+                    ready.append(j)
+                    ready.sort(key=lambda x: x.arrival)
 
         threads = [threading.Thread(target=builder, daemon=True) for _ in range(self.n_builders)]
         for th in threads:
             th.start()
-        running = []
         done = []
-        n_batches = 0
         try:
             while len(done) < len(jobs):
                 if errors:
                     raise errors[0]
                 tnow = now()
                 with lock:
-                    while waiting and waiting[0].arrival <= tnow and state["used"] + waiting[0].footprint <= self.budget:
-                        j = waiting.popleft()
-                        state["used"] += j.footprint
-                        state["peak"] = max(state["peak"], state["used"])
-                        j.admitted = tnow
-                        admitted.append(j)
-                    if admitted and len(running) + state["building"] < self.max_batches:
-                        grp = [admitted.popleft() for _ in range(min(self.max_jobs, len(admitted)))]
-                        state["building"] += 1
-                        build_q.append(grp)
+                    while waiting and waiting[0].arrival <= tnow:
+                        build_q.append(waiting.popleft())
                         build_cv.notify()
-                    while ready:
-                        rb = ready.popleft()
-                        state["building"] -= 1
-                        n_batches += 1
-                        tst = now()
-                        for j in rb["jobs"]:
-                            j.started = tst
-                        running.append(rb)
+                    cand = list(ready)
                 enqueued = 0
-                still = []
-                for rb in running:
-                    # chunks the device has finished
+                for rb in batches:
+                    b = rb["batch"]
                     while rb["inflight"] and rb["inflight"][0][0].query():
-                        rb["done_steps"] = rb["inflight"].popleft()[1]
-                    for j in rb["jobs"]:
-                        if j.finished < 0 and j.horizon <= rb["done_steps"]:
-                            k = rb["jobs"].index(j)
-                            j.metrics = rb["batch"].metrics(k)
+                        rb["done"] = rb["inflight"].popleft()[1]
+                    fin = [(k, j) for k, j in rb["jobs"].items() if j.g0 + j.horizon <= rb["done"]]
+                    left = b.capacity_left() if cand else None
+                    joining = [j for j in cand if fits(insts[j.jid][1], left)] if cand else []
+                    if (fin or joining) and not rb["inflight"]:
+                        # step boundary on the device: deliver, remove, add
+                        for k, j in sorted(fin, reverse=True):
+                            j.metrics = b.metrics(k)
                             j.steps_done = j.horizon
                             j.finished = now()
                             done.append(j)
-                    if rb["steps"] < rb["horizon"] and len(rb["inflight"]) < self.depth:
-                        n = min(self.k, rb["horizon"] - rb["steps"])
-                        rb["batch"].step(n)
+                            del rb["jobs"][k]
+                            b.remove(k)
+                        left = b.capacity_left()
+                        for j in cand:
+                            if j.jid not in insts or not fits(insts[j.jid][1], left):
+                                continue
+                            inst = insts[j.jid][0]
+                            k = b.add(inst)
+                            b.set_horizon(k, j.horizon)
+                            j.k, j.g0 = k, rb["steps"]
+                            j.admitted = j.started = now()
+                            rb["jobs"][k] = j
+                            with lock:
+                                ready.remove(j)
+                                del insts[j.jid]
+                            inst.close()
+                            left = b.capacity_left()
+                        cand = [j for j in cand if j.jid in insts]
+                        continue
+                    if fin or joining:
+                        continue   # let the device reach the step boundary first
+                    active = [j.g0 + j.horizon - rb["steps"] for j in rb["jobs"].values()]
+                    todo = max(active, default=0)
+                    if todo > 0 and len(rb["inflight"]) < self.depth:
+                        n = min(self.k, todo)
+                        b.step(n)
                         rb["steps"] += n
                         rb["inflight"].append((self.f.done_event(rb["stream"]), rb["steps"]))
                         enqueued += 1
-                    if rb["done_steps"] >= rb["horizon"] and all(j.finished >= 0 for j in rb["jobs"]):
-                        rb["batch"].close()
-                        rb["batch"] = None
-                        with lock:
-                            state["used"] -= sum(j.footprint for j in rb["jobs"])
-                    else:
-                        still.append(rb)
-                running = still
                 if not enqueued:
                     time.sleep(0.0002)
         finally:
@@ -360,7 +415,10 @@ class BatchedServeLoop:
             for th in threads:
                 th.join(timeout=60)
         self.f.sync()
-        return {"jobs": done, "wall_s": now(), "batches": n_batches, "peak_bytes": state["peak"]}
+        wall = now()
+        for rb in batches:
+            rb["batch"].close()
+        return {"jobs": done, "wall_s": wall, "batches": len(batches), "peak_bytes": reserved, "capacity": cap}
 
 
 def summarize(result, skip=0):

@@ -162,66 +162,118 @@ def test_summarize_percentiles():
     assert s["jobs_per_s"] > 0
 
 
+class FakeInstance:
+    def __init__(self, job):
+        self.job = job
+
+    def capacity(self):
+        return fake_capacity(self.job)
+
+    def close(self):
+        pass
+
+
+def fake_capacity(job):
+    c = {k: 1 for k in SV.CAP_KEYS}
+    c["vehicles"] = job.params["bytes"]
+    return c
+
+
 class FakeBatch:
-    def __init__(self, fac, jobs):
-        self.fac, self.jobs = fac, jobs
+    """Library semantics of a reserved batch: instance ids in order of
+    addition, removed trailing instances give their room back."""
+
+    def __init__(self, fac, cap):
+        self.fac, self.cap = fac, dict(cap)
         self.steps = 0
+        self.inst = []          # [job, g0, horizon, removed]
         self.busy_until = time.perf_counter()
 
     def step(self, n):
+        assert any(not e[3] for e in self.inst), "stepping a batch without live jobs"
         self.steps += n
         self.busy_until = max(self.busy_until, time.perf_counter()) + n * self.fac.sec_per_step
 
+    def add(self, inst):
+        assert SV.fits(inst.capacity(), self.capacity_left())
+        self.inst.append([inst.job, self.steps, 1 << 30, False])
+        with self.fac.lock:
+            self.fac.resident.add(inst.job.jid)
+            self.fac.joined_at[inst.job.jid] = self.steps
+        return len(self.inst) - 1
+
+    def set_horizon(self, k, h):
+        self.inst[k][2] = h
+
     def metrics(self, k):
-        j = self.jobs[k]
-        # a frozen instance stops at its horizon
-        return {"vehicle_steps": 100 * min(self.steps, j.horizon), "step": min(self.steps, j.horizon)}
+        job, g0, h, _ = self.inst[k]
+        n = min(self.steps - g0, h)
+        return {"vehicle_steps": 100 * n, "step": n}
+
+    def remove(self, k):
+        assert not self.inst[k][3]
+        self.inst[k][3] = True
+        with self.fac.lock:
+            self.fac.resident.discard(self.inst[k][0].jid)
+        while self.inst and self.inst[-1][3]:
+            self.inst.pop()
+
+    def capacity_left(self):
+        left = dict(self.cap)
+        for job, _, _, _ in self.inst:
+            for k, v in fake_capacity(job).items():
+                left[k] -= v
+        return left
 
     def close(self):
-        with self.fac.lock:
-            for j in self.jobs:
-                self.fac.resident.discard(j.jid)
-            self.fac.batches.append([j.jid for j in self.jobs])
+        self.fac.closed += 1
 
 
 class FakeBatchFactory(FakeFactory):
     def __init__(self, sec_per_step=2e-5):
         super().__init__(sec_per_step)
-        self.batches = []
+        self.closed = 0
+        self.joined_at = {}
 
-    def create_batch(self, jobs):
-        b = FakeBatch(self, jobs)
+    def capacity_of(self, job):
+        return fake_capacity(job)
+
+    def instance(self, job):
+        return FakeInstance(job)
+
+    def reserve_footprint(self, cap):
+        return cap["vehicles"]
+
+    def reserve(self, cap, params):
+        b = FakeBatch(self, cap)
         st = FakeStream()
         st.sim = b
-        with self.lock:
-            for j in jobs:
-                self.resident.add(j.jid)
-                self.sizes[j.jid] = j.params["bytes"]
-            cur = sum(self.sizes[j] for j in self.resident)
-            self.max_resident_bytes = max(self.max_resident_bytes, cur)
         return b, st
 
 
 def test_batched_loop_completes_every_job_at_its_horizon():
     fac = FakeBatchFactory()
     jobs = make_jobs(60, seed=4, rate=800.0)
-    res = SV.BatchedServeLoop(fac, hbm_budget=3000, steps_per_tick=25, max_batches=3, max_jobs_per_batch=8).run(jobs)
+    res = SV.BatchedServeLoop(fac, hbm_budget=3000, steps_per_tick=25, max_batches=3).run(jobs)
     assert len(res["jobs"]) == 60
     for j in res["jobs"]:
         assert j.metrics["step"] == j.horizon
         assert j.metrics["vehicle_steps"] == 100 * j.horizon
         assert 0 <= j.arrival <= j.admitted <= j.started <= j.finished
-    assert fac.max_resident_bytes <= 3000 and res["peak_bytes"] <= 3000
-    assert all(len(b) <= 8 for b in fac.batches)
-    assert sorted(x for b in fac.batches for x in b) == list(range(60))
-    assert not fac.resident
+    assert res["peak_bytes"] <= 3000
+    assert sorted(j.jid for j in res["jobs"]) == list(range(60))
+    assert not fac.resident and fac.closed == 3
+    # jobs joined batches that were already running
+    assert sum(1 for g in fac.joined_at.values() if g > 0) >= 10
 
 
 def test_batched_loop_short_job_leaves_before_long_batchmate():
     fac = FakeBatchFactory(sec_per_step=2e-4)
     a = SV.Job(jid=0, arrival=0.0, network=None, trips=None, params={"bytes": 10}, horizon=600)
     b = SV.Job(jid=1, arrival=0.0, network=None, trips=None, params={"bytes": 10}, horizon=30)
-    res = SV.BatchedServeLoop(fac, hbm_budget=100, steps_per_tick=30).run([a, b])
+    c = SV.Job(jid=2, arrival=0.05, network=None, trips=None, params={"bytes": 10}, horizon=60)
+    res = SV.BatchedServeLoop(fac, hbm_budget=100, steps_per_tick=30, max_batches=1).run([a, b, c])
     d = {j.jid: j for j in res["jobs"]}
-    assert fac.batches == [[0, 1]]              # one batch
     assert d[1].finished < d[0].finished        # delivered at its own horizon
+    assert fac.joined_at[2] > 0                 # joined the running batch
+    assert d[2].finished < d[0].finished
