@@ -179,6 +179,19 @@ int tsim_step(tsim_handle *h, int32_t n_steps);
 int tsim_set_signal_phases(tsim_handle *h, const int32_t *junction_ids, const int32_t *phase_index,
                            int32_t n);
 
+/* As tsim_set_signal_phases, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * allocates nothing, neither device nor pinned host memory.  The ids and
+ * phases are staged in a fixed device array the library keeps on each GPU
+ * (2 x 262,144 int32, 2 MiB, held until the process ends); n > 262,144
+ * returns TSIM_EINVAL.  The handle's GPU must be the current device.
+ * Synchronises the handle's stream before returning, after which the host
+ * arrays may be reused.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (from several host threads) race.  Single-instance
+ * handles only. */
+int tsim_set_signal_phases_noalloc(tsim_handle *h, const int32_t *junction_ids, const int32_t *phase_index,
+                                   int32_t n);
+
 /* Junctions junction_ids[c] take signal policy policy[c] (TSIM_POLICY_*)
  * from the next step on (Section 3.2 set_tl_policy).  A junction switched to
  * MAX_PRESSURE holds its stored phase (tsim_state_host.junc_phase) until its

@@ -26,6 +26,7 @@ hipError_t launch_export(const DevNet* Dd, const DevNet& H, const int32_t* lane_
 hipError_t launch_import(const DevNet* Dd, const DevNet& H, const uint32_t* slots, const VehRec* recs, int n, hipStream_t s);
 hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s);
 hipError_t launch_set_policy(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* pol, int n, hipStream_t s);
+hipError_t noalloc_scratch(int32_t** out);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
 int update_blocks_per_cu(int sched);
 }  // namespace tsim
@@ -612,6 +613,7 @@ struct tsim_handle {
     int res[kNumSched + 4] = {};        // resident workgroups: grouped pass per schedule, wide, huge, pipelined wide, tiny
     Caps cap;                           // sizes the arena is laid out for
     tsim_params params{};               // model parameters (batches: shared by every instance but the seed)
+    int device = 0;                     // GPU the handle was created on
     std::vector<char> removed;          // batches: instances taken out by tsim_batch_remove
     std::string err;
 };
@@ -879,14 +881,9 @@ int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, con
     empty.rear = INF;
     empty.rear_v = 0.0f;
     empty.front_reach = -INF;
-    empty.gate = kNoGate;
-    empty.fmax = kNoFeeder;
-    empty.ob = empty.oe = 0;
+    empty.gate = 0;     // tag 0: stale for every step
+    empty.fmax = 0;
     std::vector<LaneSum> sum(nm, empty);
-    for (int m = g.m0; m < g.m1; ++m) {
-        sum[m - g.m0].ob = B.out_begin[m];
-        sum[m - g.m0].oe = B.out_begin[m + 1];
-    }
     std::vector<LaneSum> sum_other(sum);
     std::vector<int32_t> tile_n(nr, 0), tile_zero(nr, 0);
     std::vector<float> road_speed(nr, -1.0f);
@@ -920,15 +917,20 @@ int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, con
             recs.push_back(o);
         }
     }
-    // feeder gates of the current step from the junction-lane summaries (the
-    // other buffer's are cleared by the prepare kernel before they are built)
+    // feeder gates of the current step from the junction-lane summaries,
+    // tagged for the step that reads them (the other buffer's are written by
+    // the update kernels with the next step's tag)
+    std::vector<int> gmin(nm, kNoGate), fmx(nm, kNoFeeder);
     for (int q = g.m0; q < g.m1; ++q) {
         const int go = B.jl_out[q];
         if (go < 0 || sum[q - g.m0].cnt == 0) continue;
         const float fr = sum[q - g.m0].front_reach;
-        LaneSum& so = sum[go - g.m0];
-        so.fmax = std::max(so.fmax, f2o(fr));
-        if (fr > 0.0f) so.gate = std::min(so.gate, B.jl_ext[q]);
+        fmx[go - g.m0] = std::max(fmx[go - g.m0], f2o(fr));
+        if (fr > 0.0f) gmin[go - g.m0] = std::min(gmin[go - g.m0], B.jl_ext[q]);
+    }
+    for (int m = 0; m < nm; ++m) {
+        if (fmx[m] != kNoFeeder) sum[m].fmax = fmax_key(gnow, fmx[m]);
+        if (gmin[m] != kNoGate) sum[m].gate = gate_key(gnow, gmin[m]);
     }
     std::vector<int32_t> qhead(nr);
     for (int r = g.r0; r < g.r1; ++r) {
@@ -1263,6 +1265,14 @@ static int create_impl(tsim_handle* h, const tsim_params* params, void* hip_stre
     D.sched = kSchedFused;
     refresh_view(h);
     h->removed.assign(B.n_inst, 0);
+    {
+        // set-up of the no-allocation entry point on this GPU: its scratch
+        // address, looked up once per device (a failure is reported by that
+        // entry point, which looks again)
+        int32_t* sp = nullptr;
+        (void)noalloc_scratch(&sp);
+        (void)hipGetDevice(&h->device);
+    }
     h->params = *params;
     fill_params(D.P, params);
     int e = 0;
@@ -1609,6 +1619,32 @@ static int set_phases_impl(tsim_handle* h, int inst, const int32_t* junction_ids
 int tsim_set_signal_phases(tsim_handle* h, const int32_t* junction_ids, const int32_t* phase_index, int32_t n)
 {
     return set_phases_impl(h, 0, junction_ids, phase_index, n);
+}
+
+int tsim_set_signal_phases_noalloc(tsim_handle* h, const int32_t* junction_ids, const int32_t* phase_index, int32_t n)
+{
+    if (!h || n < 0 || (n && (!junction_ids || !phase_index)) || h->B.n_inst != 1)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    if (n > kNoAllocMaxUpdates)
+        return fail(&h->err, TSIM_EINVAL, "more than " + std::to_string(kNoAllocMaxUpdates) + " junction updates");
+    if (n == 0) return TSIM_OK;
+    for (int c = 0; c < n; ++c) {
+        const int j = junction_ids[c];
+        if (j < 0 || j >= h->B.NJ) return fail(&h->err, TSIM_EINVAL, "junction id out of range");
+        const int np = h->B.junc_phase_begin[j + 1] - h->B.junc_phase_begin[j];
+        if (phase_index[c] < 0 || phase_index[c] >= np) return fail(&h->err, TSIM_EINVAL, "phase index out of range");
+    }
+    int cur = 0;
+    HIPCHK(h, hipGetDevice(&cur));
+    if (cur != h->device) return fail(&h->err, TSIM_EINVAL, "the handle's GPU is not the current device");
+    int32_t* sp = nullptr;
+    HIPCHK(h, noalloc_scratch(&sp));
+    HIPCHK(h, hipMemcpyAsync(sp, junction_ids, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(sp + kNoAllocMaxUpdates, phase_index, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_set_phases(h->d_net, h->D, sp, sp + kNoAllocMaxUpdates, n, h->stream));
+    // the caller's arrays and this GPU's scratch are free again on return
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
 }
 
 int tsim_batch_set_signal_phases(tsim_batch* b, int32_t instance, const int32_t* junction_ids,

@@ -29,6 +29,7 @@ constexpr int kWideCap = 128;        // vehicles of a tile of the wide list (sta
 constexpr int kHugeCap = 512;        // vehicles of a huge tile staged in LDS (more: global scratch)
 constexpr int kNoGate = 0x7FFFFFFF;  // no feeder holds the lane
 constexpr int kNoFeeder = (int)0x80000000;  // no nonempty feeder
+constexpr int kNoAllocMaxUpdates = 1 << 18; // junction updates per tsim_set_signal_phases_noalloc call
 
 // Update schedules: how road tiles map onto wavefronts.  A tile of at most
 // `width` lanes that holds at most `cap` vehicles goes to a group of `width`
@@ -84,16 +85,35 @@ struct __align__(32) LaneSum {
     float rear;         // rearmost vehicle's rear bumper (x - length)
     float rear_v;       // its speed
     float front_reach;  // front vehicle's x + v dt + a_max dt^2/2 - lane length
-    // feeder gates of a road lane (built by the tiles that write its feeders'
-    // front vehicles): smallest external index of a nonempty feeder whose
-    // front vehicle can cross the lane end within the step (kNoGate if none),
-    // and the largest front reach of a nonempty feeder (order-preserving int,
-    // kNoFeeder if none)
-    int32_t gate;
-    int32_t fmax;
-    // static: junction lanes leaving this lane, out_pair[ob, oe)
-    int32_t ob, oe;
+    // feeder gates of a road lane (built with 64-bit atomicMax by the tiles
+    // that write its feeders' front vehicles), each tagged in its high word
+    // with the step that reads it plus one, so an entry left from an earlier
+    // step is simply stale and nothing is ever cleared:
+    //   gate: smallest external index of a nonempty feeder whose front
+    //         vehicle can cross the lane end within the step (kNoGate if none)
+    //   fmax: largest front reach of a nonempty feeder (kNoFeeder if none)
+    uint64_t gate;
+    uint64_t fmax;
 };
+
+// tagged gate words (see LaneSum); `step` is the global step that reads them
+__host__ __device__ inline uint32_t gate_tag(long long step) { return (uint32_t)(step + 1); }
+__host__ __device__ inline uint64_t gate_key(long long step, int ext)
+{
+    return ((uint64_t)gate_tag(step) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)ext);
+}
+__host__ __device__ inline int gate_of(uint64_t w, long long step)
+{
+    return (uint32_t)(w >> 32) == gate_tag(step) ? (int)(0xFFFFFFFFu - (uint32_t)w) : kNoGate;
+}
+__host__ __device__ inline uint64_t fmax_key(long long step, int ordered_reach)
+{
+    return ((uint64_t)gate_tag(step) << 32) | (uint64_t)((uint32_t)ordered_reach ^ 0x80000000u);
+}
+__host__ __device__ inline int fmax_of(uint64_t w, long long step)
+{
+    return (uint32_t)(w >> 32) == gate_tag(step) ? (int)((uint32_t)w ^ 0x80000000u) : kNoFeeder;
+}
 
 // static per-lane tables, one 48-byte record per lane so that a tile's lanes
 // load as one contiguous run

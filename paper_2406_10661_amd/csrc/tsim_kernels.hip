@@ -28,6 +28,8 @@
 // is free of read/write races without any lock.
 #include "tsim_internal.h"
 
+#include <mutex>
+
 namespace tsim {
 
 #define TS_INF __builtin_huge_valf()
@@ -248,12 +250,6 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     for (int li = 0; li < nrl; ++li) inb |= (D.inbox_flag[lb + li] != 0 ? 1u : 0u) << li;
     // an instance past its horizon is frozen: none of its tiles is listed
     if (t >= t_end) return;
-    // feeder gates of this road's lanes in the summaries this step writes
-    // (the update kernels fill them)
-    for (int li = 0; li < nrl; ++li) {
-        wsum[lb + li].gate = kNoGate;
-        wsum[lb + li].fmax = kNoFeeder;
-    }
     long long errors = 0;
     int appended = 0;
     for (int li = 0; li < nrl; ++li) {
@@ -301,7 +297,8 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         for (int li = 0; li < nrl; ++li) {
             const LaneSum s = sum[lb + li];
             // no nonempty feeder may reach past the entrant's rear (x = 0)
-            const bool ok = ((lanes_ok >> li) & 1u) && !(s.fmax != kNoFeeder && !(-Lv - o2f(s.fmax) >= 0.0f));
+            const int fm = fmax_of(s.fmax, tg);
+            const bool ok = ((lanes_ok >> li) & 1u) && !(fm != kNoFeeder && !(-Lv - o2f(fm) >= 0.0f));
             const float room = s.cnt > 0 ? s.rear : TS_INF;
             const bool better = ok && room > best_room;
             best_room = better ? room : best_room;
@@ -717,7 +714,8 @@ __device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const Lan
     }
     if (rem < 2) return L;
     const int g1 = S.jl_out[li];
-    const int g2 = out_toward_range(D, s1.ob, s1.oe, D.route[rp + 2]);
+    // junction lanes leaving g1: out_pair[out_begin[g1], out_begin[g1 + 1])
+    const int g2 = out_toward_range(D, D.out_begin[g1], D.out_begin[g1 + 1], D.route[rp + 2]);
     if (g2 < 0) return L;
     const LaneSum s2 = sum[g2];
     if (s2.cnt > 0) {
@@ -731,6 +729,7 @@ __device__ Lead lookahead(const DevNet& D, const TS& S, const V& view, const Lan
 
 // buffers of one step
 struct StepBufs {
+    long long tg;   // the global step
     const VehRec* rd;
     VehRec* wr;
     const LaneSum* rsum;
@@ -742,6 +741,7 @@ struct StepBufs {
 __device__ __forceinline__ StepBufs step_bufs(const DevNet& D, long long tg)
 {
     StepBufs B;
+    B.tg = tg;
     const int p = (int)(tg & 1);
     B.rd = p ? D.slab1 : D.slab0;
     B.wr = p ? D.slab0 : D.slab1;
@@ -813,7 +813,7 @@ __device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs
         lr.mask = L.green_mask;
         S.fmx[gt] = kNoFeeder;
     } else {
-        S.fmx[gt] = B.rsum[m].fmax;
+        S.fmx[gt] = fmax_of(B.rsum[m].fmax, B.tg);
         S.green[gt] = 1;
     }
     return lr;
@@ -1181,7 +1181,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
                 // feeder priority: an earlier feeder of the out lane whose
                 // front vehicle can pass its end this step goes first
                 const int g = S.jl_out[li];
-                if (S.osum[li].gate < S.jl_ext[li]) {
+                if (gate_of(S.osum[li].gate, B.tg) < S.jl_ext[li]) {
                     xn = len;
                     vn = 0.0f;
                     atomicAdd(&S.fblocks, 1);
@@ -1353,8 +1353,9 @@ __device__ void process_pass3(const DevNet& D, TS& S, V& view, const StepBufs& B
                 if (nli >= nroad) {
                     // this junction lane feeds its out lane next step
                     const int g = S.jl_out[nli];
-                    atomicMax(&B.wsum[g].fmax, f2o(fr));
-                    if (fr > 0.0f) atomicMin(&B.wsum[g].gate, S.jl_ext[nli]);
+                    atomicMax((unsigned long long*)&B.wsum[g].fmax, (unsigned long long)fmax_key(B.tg + 1, f2o(fr)));
+                    if (fr > 0.0f)
+                        atomicMax((unsigned long long*)&B.wsum[g].gate, (unsigned long long)gate_key(B.tg + 1, S.jl_ext[nli]));
                 }
             }
             if (rank == total - 1) {
@@ -1619,7 +1620,7 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
             const int m_ = (H).lb + gt;                                        \
             pL = D.lane_info[m_];                                              \
             pcnt = B.rsum[m_].cnt;                                             \
-            pfmx = gt < (H).nroad ? B.rsum[m_].fmax : kNoFeeder;               \
+            pfmx = gt < (H).nroad ? fmax_of(B.rsum[m_].fmax, B.tg) : kNoFeeder; \
         }                                                                      \
     } while (0)
 #define TSIM_PF_LANE_OF(J, LI) const int LI = pvl[J]
@@ -2089,6 +2090,46 @@ __global__ __launch_bounds__(kSignalThreads) void k_signals(const DevNet D)
         }
     }
     D.junc_manual[j] = best;
+}
+
+// Staging of tsim_set_signal_phases_noalloc: junction ids in the first
+// kNoAllocMaxUpdates words, phases in the second.  One copy per GPU, held
+// until the process ends and shared by every call on that GPU.  In host code
+// `scratch` names a host-side stand-in, never the device array: the device
+// address comes from noalloc_scratch().
+static __device__ __align__(256) int32_t scratch[2 * kNoAllocMaxUpdates];
+
+// The HIP runtime records a file-scope device variable for the devices it
+// knows when the library's module constructor registers it; a library loaded
+// before the runtime has enumerated the GPUs (an application that only counted
+// devices so far) would register `scratch` for none.  This constructor runs
+// before the module constructor (lower priority number) and starts the runtime
+// first; without a GPU it fails harmlessly.
+__attribute__((constructor(101))) static void tsim_runtime_first()
+{
+    (void)hipInit(0);
+}
+
+// device address of the current GPU's scratch, looked up once per device
+// (the lookup allocates nothing)
+hipError_t noalloc_scratch(int32_t** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static int32_t* ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = (int32_t*)p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 // signal policies of some junctions (host-staged ids and policies)

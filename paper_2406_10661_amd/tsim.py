@@ -81,7 +81,7 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_get_road_mean_speed", "tsim_batch_get_lane_waiting_counts", "tsim_batch_get_lane_order",
            "tsim_instance_build", "tsim_instance_free", "tsim_instance_capacity", "tsim_batch_reserve_footprint",
            "tsim_batch_reserve", "tsim_batch_add", "tsim_batch_add_member", "tsim_batch_remove",
-           "tsim_batch_capacity_left", "tsim_batch_num_instances"]
+           "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -93,6 +93,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2406_10661_amd.build.build()")
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()   # the HIP runtime knows the GPUs before the library registers its device data
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.tsim_footprint.argtypes = [P, P, P, C.POINTER(C.c_size_t)]
@@ -100,6 +106,7 @@ def lib():
         L.tsim_step.argtypes = [P, C.c_int32]
         L.tsim_set_signal_phases.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_signal_policy.argtypes = [P, P, P, C.c_int32]
+        L.tsim_set_signal_phases_noalloc.argtypes = [P, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_get_metrics.argtypes = [P, P]
         L.tsim_get_road_mean_speed.argtypes = [P, P, C.c_int32]
