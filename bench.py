@@ -21,6 +21,11 @@ traffic from rocprofv3 counters when they were taken on the current kernel
 source over the same window, and the CPU oracle's throughput on a bounded
 sample (a synthetic state of the same city at time S).
 
+The same line carries, under "batched" and "served", compact forms of the
+two serving-style workloads timed in the same run (64 instances for 300
+steps; 100 jobs of at most 100,000 vehicles), each against its plain
+one-instance-at-a-time loop (--no-legs leaves them out).
+
 --workload batch: 256 uneven jittered-grid instances (1k-150k vehicles each,
 about 15M in total) stepped together through captured 15-step HIP graphs for
 1,800 steps, with every junction's phase set from a seeded random policy every
@@ -165,7 +170,7 @@ def concurrency_arg(args):
     return None if args.concurrent == "auto" else args.concurrent == "1"
 
 
-def run_batch(args):
+def run_batch(args, emit=True):
     """Batched RL-style stepping of many uneven instances versus the plain
     per-instance loop on the same phase schedule."""
     import numpy as np
@@ -187,7 +192,7 @@ def run_batch(args):
     from paper_2406_10661_amd.tsim import SCHEDULES
     # schedule: autotuned on a throw-away batch once traffic has built up
     b = Batch(nets, trips, pars)
-    for c in range(450 // every):
+    for c in range(min(450 // every, n_chunks)):
         b.set_all_phases(allph[c])
         b.step(every)
     sched, conc, us = tune(b, every, concurrency_arg(args))
@@ -268,10 +273,12 @@ def run_batch(args):
         "roofline": roofline(alg, ms_b, steps, traffic_from_profiles(f"batch{len(ws)}", None), step_label(SCHEDULES[sched])),
         "update_passes_us_eager": upd_ms / max(upd_n, 1) * 1e3,
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def run_serve(args):
+def run_serve(args, emit=True):
     """Continuous batching of a Poisson job stream versus the plain loop."""
     import numpy as np
     import torch
@@ -279,7 +286,7 @@ def run_serve(args):
     from paper_2406_10661_amd import serve as SV
     from paper_2406_10661_amd.tsim import Sim
     t0 = time.time()
-    ws = W.served_jobs(args.jobs)
+    ws = W.served_jobs(args.jobs, max_vehicles=getattr(args, "max_vehicles", None))
     arr = W.poisson_arrivals(args.jobs, rate=args.rate)
     log(f"[bench] {len(ws)} jobs generated in {time.time() - t0:.1f} s; "
         f"{sum(w.trips.n_vehicles for w in ws)} vehicles in total")
@@ -354,7 +361,9 @@ def run_serve(args):
                             "wall_s": summ_s["wall_s"]}
         # share of the loop's capacity that the Poisson stream used
         out["utilisation"] = summ["vehicle_steps_per_s"] / summ_s["vehicle_steps_per_s"]
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def run_copy(args):
@@ -445,6 +454,9 @@ def main():
                     help="city: first step of the timed window (default 5/8 of the horizon)")
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="city: skip the compact batched and served legs added to the line")
+    ap.add_argument("--max-vehicles", type=int, default=None, help="serve: cap on a job's vehicles")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--jobs", type=int, default=400)
@@ -606,7 +618,36 @@ def run_city(args):
     torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, from_step, args.cpu_seconds)
+    if not args.no_legs:
+        out.update(compact_legs(args))
     print(json.dumps(out), flush=True)
+
+
+def compact_legs(args):
+    """The batched and served forms at a compact size, timed in the same
+    run: 64 uneven jittered-grid instances (3.8M vehicles) stepped together
+    for 300 steps with phases set every 15 steps, against the same instances
+    stepped one by one; and 100 served jobs (at most 100,000 vehicles each,
+    Poisson 20 jobs/s, statistics after the first 10) through the
+    continuous-batching loop, against the one-job-at-a-time loop."""
+    import copy
+    b = copy.copy(args)
+    b.instances, b.steps, b.concurrent = 64, 300, "0"
+    rb = run_batch(b, emit=False)
+    v = copy.copy(args)
+    v.jobs, v.skip, v.rate, v.budget_gib, v.tick, v.streams = 100, 10, 20.0, 16.0, 30, 3
+    v.max_batches, v.serve_mode, v.no_saturate, v.max_vehicles, v.concurrent = 3, "batched", False, 100000, "0"
+    rs = run_serve(v, emit=False)
+    batched = {k: rb[k] for k in ("value", "unit", "steps", "ms_per_step", "vs_plain_loop", "plain_loop")}
+    batched["config"] = rb["config"]
+    batched["roofline_frac"] = rb["roofline"]["frac"]
+    served = {k: rs[k] for k in ("value", "unit", "latency_p50_s", "latency_p99_s", "queue_wait_p99_s",
+                                 "vehicle_steps_per_s", "vs_plain_loop", "plain_loop", "utilisation")
+              if k in rs}
+    served["config"] = rs["config"]
+    if "saturated" in rs:
+        served["saturated"] = rs["saturated"]
+    return {"batched": batched, "served": served}
 
 
 if __name__ == "__main__":

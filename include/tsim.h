@@ -159,18 +159,25 @@ typedef struct tsim_state_host {
 
 typedef struct tsim_handle tsim_handle;
 
-/* Device bytes tsim_create needs for this input (arena size). */
+/* Device bytes tsim_create needs for this input (arena size): the road
+ * network, trip table and vehicle state resident on the GPU, in the
+ * snapshot/runtime pair of Section 3.1's two-phase process (two slab buffers
+ * alternating by step parity).  Validates the input like tsim_create. */
 int tsim_footprint(const tsim_network *net, const tsim_trips *trips, const tsim_params *params,
                    size_t *bytes_out);
 
 /* Builds the device state inside the caller's arena (device pointer, at
- * least tsim_footprint bytes, 256-byte aligned, alive until tsim_destroy).
+ * least tsim_footprint bytes, 256-byte aligned, alive until tsim_destroy):
+ * the simulator instance of Section 3.1 ("Python API": the engine created
+ * from map and trip data), every vehicle waiting at t = 0.
  * hip_stream (a hipStream_t, or NULL for the null stream) carries every later
  * launch and copy.  Validates the input (TSIM_EINVAL with a message). */
 int tsim_create(const tsim_network *net, const tsim_trips *trips, const tsim_params *params,
                 void *hip_stream, void *device_arena, size_t arena_bytes, tsim_handle **out);
 
-/* Enqueues n_steps steps on the stream and returns without waiting. */
+/* Enqueues n_steps steps on the stream and returns without waiting
+ * (Section 3.1 "Python API" next_step; one step is the prepare and update
+ * phases of Appendix B.2 with the vehicle models of Appendix B.3). */
 int tsim_step(tsim_handle *h, int32_t n_steps);
 
 /* Junctions junction_ids[c] switch to MANUAL with phase phase_index[c] from
@@ -200,6 +207,14 @@ int tsim_set_signal_phases_noalloc(tsim_handle *h, const int32_t *junction_ids, 
  * positive duration.  The host arrays may be reused on return. */
 int tsim_set_signal_policy(tsim_handle *h, const int32_t *junction_ids, const int32_t *policy, int32_t n);
 
+/* Speed limits of lanes (road lanes and junction lanes, lane ids as in the
+ * network) from the next step on (Section 3.2 "Lane" set_lane_max_speed);
+ * a vehicle's desired speed on such a lane is its v0_factor times the new
+ * limit.  TSIM_EINVAL for a bad id, a non-positive limit, or a lane shorter
+ * than one step of travel at the new limit (largest v0_factor of the
+ * instance); nothing changes then.  Synchronises the stream. */
+int tsim_set_lane_max_speed(tsim_handle *h, const int32_t *lane_ids, const float *max_speed, int32_t n);
+
 /* Synchronises the stream, then fills *out. */
 int tsim_get_metrics(tsim_handle *h, tsim_metrics *out);
 
@@ -216,6 +231,10 @@ int tsim_get_lane_waiting_counts(tsim_handle *h, int32_t *out, int32_t n_lanes);
 int tsim_get_lane_order(tsim_handle *h, int32_t *offsets, int32_t *vehicle_ids, int32_t n_lanes,
                         int32_t max_ids);
 
+/* The vehicle state at the step boundary (positions, speeds, lanes, route
+ * positions, status; signal policies and phases): the per-vehicle and
+ * per-junction quantities the getters of Section 3.1 "Python API" expose,
+ * all at once, for checkpoints and tests.  Synchronises the stream. */
 int tsim_get_state(tsim_handle *h, tsim_state_host *out);
 /* Replaces the state.  Finished-trip totals are recomputed from finish_step;
  * the running averages and event counters restart from zero. */
@@ -322,6 +341,9 @@ int tsim_batch_set_graph_steps(tsim_batch *b, int32_t chunk);
 int tsim_batch_set_horizon(tsim_batch *b, int32_t instance, int64_t n_steps);
 int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
                                  const int32_t *phase_index, int32_t n);
+/* As tsim_set_lane_max_speed, for the lanes of one instance. */
+int tsim_batch_set_lane_max_speed(tsim_batch *b, int32_t instance, const int32_t *lane_ids, const float *max_speed,
+                                  int32_t n);
 /* As tsim_set_signal_policy, for the junctions of one instance. */
 int tsim_batch_set_signal_policy(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
                                  const int32_t *policy, int32_t n);

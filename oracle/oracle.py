@@ -52,6 +52,7 @@ def lib():
         L.osim_set_signal_phases.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_policy.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.osim_set_lane_max_speed.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_get_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_get_metrics.argtypes = [C.c_void_p, C.c_void_p]
         L.osim_get_road_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -163,6 +164,12 @@ class OracleSim:
         ph = np.ascontiguousarray(phase, np.int32)
         assert p.size == ph.size == self.net.n_junctions
         lib().osim_set_junctions(self.h, _p(p), _p(ph))
+
+    def set_lane_max_speed(self, lanes, speeds):
+        """Speed limits of lanes (global lane ids) from the next step on."""
+        l = np.ascontiguousarray(lanes, np.int32)
+        v = np.ascontiguousarray(speeds, np.float64)
+        lib().osim_set_lane_max_speed(self.h, int(l.size), _p(l), _p(v))
 
     def junctions(self):
         p = np.zeros(self.net.n_junctions, np.int32)

@@ -1071,6 +1071,14 @@ void osim_set_policy(osim *s, int n, const int *junction, const int *policy)
     for (int c = 0; c < n; ++c) s->policy[junction[c]] = policy[c];
 }
 
+/* Section 3.2 "Lane" set_lane_max_speed: the speed limit of lanes (road or
+ * junction lanes, global lane ids) from the next step on; every vehicle's
+ * desired speed on such a lane is its factor times the new limit */
+void osim_set_lane_max_speed(osim *s, int n, const int *lanes, const double *speed)
+{
+    for (int c = 0; c < n; ++c) s->lane_lim[lanes[c]] = speed[c];
+}
+
 /* policy and phase of every junction (the phase is the MANUAL phase, or the
  * phase in force of a MAX_PRESSURE junction; ignored otherwise) */
 void osim_set_junctions(osim *s, const int *policy, const int *phase)

@@ -27,6 +27,7 @@ hipError_t launch_import(const DevNet* Dd, const DevNet& H, const uint32_t* slot
 hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_t* ph, hipStream_t s);
 hipError_t launch_set_policy(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* pol, int n, hipStream_t s);
 hipError_t noalloc_scratch(int32_t** out);
+hipError_t launch_set_lane_speed(const DevNet& H, const int32_t* ids, const float* lim, int n, hipStream_t s);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
 int update_blocks_per_cu(int sched);
 }  // namespace tsim
@@ -594,6 +595,7 @@ struct tsim_handle {
     float* d_io_f1 = nullptr;
     VehRec* d_io_rec = nullptr;      // staging: import records
     int32_t* d_io_ph = nullptr;      // staging: phase updates (2 slots of 2 x NJ)
+    int32_t* d_io_lane = nullptr;    // staging: lane updates (NL ids, then NL values)
     int32_t* h_pin[2] = {nullptr, nullptr};   // pinned host staging of the two slots
     hipEvent_t pin_ev[2] = {nullptr, nullptr};
     bool pin_used[2] = {false, false};
@@ -716,6 +718,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&h->d_io_f1, std::max<size_t>(N, 1) * 4);
     add(&h->d_io_rec, std::max<size_t>(N, 1) * sizeof(VehRec));
     add(&h->d_io_ph, 4 * std::max<size_t>(NJ, 1) * 4);
+    add(&h->d_io_lane, 2 * std::max<size_t>(NL, 1) * 4);
     add(&h->d_net, sizeof(DevNet));
     return v;
 }
@@ -1696,6 +1699,52 @@ int tsim_batch_set_signal_policy(tsim_batch* b, int32_t instance, const int32_t*
                                  int32_t n)
 {
     return set_policy_impl(b, instance, junction_ids, policy, n);
+}
+
+static int lane_speed_impl(tsim_handle* h, int k, const int32_t* lane_ids, const float* max_speed, int32_t n)
+{
+    if (!h || n < 0 || (n && (!lane_ids || !max_speed)) || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = h->B;
+    const Ranges g = ranges_of(B, k);
+    const int nl = g.nrl + g.njl;
+    if (n > nl) return fail(&h->err, TSIM_EINVAL, "more updates than lanes");
+    if (n == 0) return TSIM_OK;
+    // the largest desired-speed factor of the instance bounds one step of travel
+    float fmax = 0.0f;
+    for (int i = g.v0; i < g.v1; ++i) fmax = std::max(fmax, B.vf[i]);
+    const double reach = 0.5 * h->params.a_max * h->params.dt * h->params.dt;
+    std::vector<int32_t> ids(n);
+    std::vector<float> val(n);
+    for (int c = 0; c < n; ++c) {
+        const int l = lane_ids[c];
+        if (l < 0 || l >= nl) return fail(&h->err, TSIM_EINVAL, "lane id out of range");
+        const float v = max_speed[c];
+        if (!(v > 0.0f) || !std::isfinite(v)) return fail(&h->err, TSIM_EINVAL, "speed limit must be positive");
+        const int m = B.int_of_ext[union_lane(B, g, l)];
+        if (!(B.lane_len[m] > (double)fmax * v * h->params.dt + reach))
+            return fail(&h->err, TSIM_EINVAL, "lane " + std::to_string(l) + " shorter than one step of travel at that limit");
+        ids[c] = m;
+        val[c] = v;
+    }
+    for (int c = 0; c < n; ++c) B.lane_lim[ids[c]] = val[c];
+    HIPCHK(h, hipMemcpyAsync(h->d_io_lane, ids.data(), (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_io_lane + B.NL, val.data(), (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_set_lane_speed(h->D, h->d_io_lane, (const float*)(h->d_io_lane + B.NL), n, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_set_lane_max_speed(tsim_handle* h, const int32_t* lane_ids, const float* max_speed, int32_t n)
+{
+    return lane_speed_impl(h, -1, lane_ids, max_speed, n);
+}
+
+int tsim_batch_set_lane_max_speed(tsim_batch* b, int32_t instance, const int32_t* lane_ids, const float* max_speed,
+                                  int32_t n)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return lane_speed_impl(b, instance, lane_ids, max_speed, n);
 }
 
 int tsim_batch_set_horizon(tsim_batch* b, int32_t instance, int64_t n_steps)

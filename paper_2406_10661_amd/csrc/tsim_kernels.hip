@@ -2132,6 +2132,23 @@ hipError_t noalloc_scratch(int32_t** out)
     return hipSuccess;
 }
 
+// speed limits of some lanes (host-staged internal lane ids and limits):
+// the lane record every tile loads and the plain limit table
+__global__ void k_set_lane_speed(const DevNet D, const int32_t* ids, const float* lim, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = ids[i];
+    const_cast<LaneInfo*>(D.lane_info)[m].lim = lim[i];
+    const_cast<float*>(D.lane_lim)[m] = lim[i];
+}
+
+hipError_t launch_set_lane_speed(const DevNet& H, const int32_t* ids, const float* lim, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_lane_speed, dim3((n + 255) / 256), dim3(256), 0, s, H, ids, lim, n);
+    return hipGetLastError();
+}
+
 // signal policies of some junctions (host-staged ids and policies)
 __global__ void k_set_policy(const DevNet D, const int32_t* ids, const int32_t* pol, int n)
 {

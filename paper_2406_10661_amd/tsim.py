@@ -81,7 +81,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_get_road_mean_speed", "tsim_batch_get_lane_waiting_counts", "tsim_batch_get_lane_order",
            "tsim_instance_build", "tsim_instance_free", "tsim_instance_capacity", "tsim_batch_reserve_footprint",
            "tsim_batch_reserve", "tsim_batch_add", "tsim_batch_add_member", "tsim_batch_remove",
-           "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc"]
+           "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc",
+           "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -107,6 +108,8 @@ def lib():
         L.tsim_set_signal_phases.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_signal_policy.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_signal_phases_noalloc.argtypes = [P, P, P, C.c_int32]
+        L.tsim_set_lane_max_speed.argtypes = [P, P, P, C.c_int32]
+        L.tsim_batch_set_lane_max_speed.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_get_metrics.argtypes = [P, P]
         L.tsim_get_road_mean_speed.argtypes = [P, P, C.c_int32]
@@ -245,6 +248,12 @@ class Sim:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(phases, np.int32)
         _check(lib().tsim_set_signal_phases(self.h, _p(j), _p(p), int(j.size)), self.h)
+
+    def set_lane_max_speed(self, lanes, speeds):
+        """Speed limits of lanes (network lane ids) from the next step on."""
+        l = np.ascontiguousarray(lanes, np.int32)
+        v = np.ascontiguousarray(speeds, np.float32)
+        _check(lib().tsim_set_lane_max_speed(self.h, _p(l), _p(v), int(l.size)), self.h)
 
     def set_signal_policy(self, junctions, policies):
         """Signal policy per junction (TSIM_POLICY_*: 0 none, 1 fixed time,
@@ -538,6 +547,11 @@ class Batch:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(policies, np.int32)
         _check(lib().tsim_batch_set_signal_policy(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
+
+    def set_lane_max_speed(self, instance, lanes, speeds):
+        l = np.ascontiguousarray(lanes, np.int32)
+        v = np.ascontiguousarray(speeds, np.float32)
+        _check(lib().tsim_batch_set_lane_max_speed(self.h, int(instance), _p(l), _p(v), int(l.size)), self.h)
 
     def set_horizon(self, instance, n_steps):
         """Freeze instance after n_steps local steps (the others go on)."""

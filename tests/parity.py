@@ -36,6 +36,9 @@ def oracle_one_step(O, net, trips, params, st):
     o.set_state(s64)
     if "junc_policy" in st:
         o.set_junctions(st["junc_policy"], st["junc_phase"])
+    if "lane_limits" in st:
+        ids, lim = st["lane_limits"]
+        o.set_lane_max_speed(ids, np.asarray(lim, np.float32).astype(np.float64))
     o.step(1)
     return o
 
@@ -51,6 +54,8 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False
     g = sim if sim is not None else sim_cls(net, trips, params)
     if not stepped:
         g.set_state(st)
+        if "lane_limits" in st:
+            g.set_lane_max_speed(*st["lane_limits"])
         g.step(1)
     gst = g.get_state()
     gm = g.metrics()

@@ -93,3 +93,12 @@ def test_instance_capacity_and_reservation_without_gpu(L):
     bad = dict(cap, vehicles=-1)
     with pytest.raises(T.TsimError):
         T.reserve_footprint(bad)
+
+
+def test_lane_max_speed_rejects_without_touching_the_gpu(L):
+    """Validation happens on the host before any device work: a bad handle
+    is refused."""
+    ids = np.zeros(1, np.int32)
+    v = np.ones(1, np.float32)
+    assert L.tsim_set_lane_max_speed(None, ids.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p), 1) \
+        == T.TSIM_EINVAL

@@ -173,6 +173,43 @@ def test_max_pressure_horizon_statistics(O, Sim):
     assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
 
 
+def test_lane_max_speed_one_step(O, Sim):
+    """Section 3.2 set_lane_max_speed: 30% of the lanes of a loaded 4x4 grid
+    (road and junction lanes) get limits U(5, 13.9) m/s; one step from the
+    same state on both sides."""
+    w = W.config1()
+    st = synthetic_state(w.network, w.trips, 150, seed=9, p_active=0.7)
+    rng = np.random.default_rng(4)
+    ids = np.nonzero(rng.random(w.network.n_lanes) < 0.3)[0].astype(np.int32)
+    st["lane_limits"] = (ids, rng.uniform(5.0, 13.9, ids.size).astype(np.float32))
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st)
+    _log("c1_lane_max_speed", rep)
+    assert rep["active"] > 300
+
+
+def test_lane_max_speed_horizon_statistics(O, Sim):
+    """Every road lane of half the roads of the 4x4 grid limited to 8 m/s
+    from t = 0 (through the ABI on the GPU): completed trips and mean road
+    speed over the 600-step horizon within 1% of the oracle's."""
+    w = W.config1()
+    rl = w.network.road_of_lane()
+    ids = np.nonzero(rl % 2 == 0)[0].astype(np.int32)
+    lim = np.full(ids.size, 8.0, np.float32)
+    o = O.OracleSim(w.network, w.trips, w.params)
+    o.set_lane_max_speed(ids, lim.astype(np.float64))
+    o.step(w.n_steps)
+    om = o.metrics()
+    g = Sim(w.network, w.trips, w.params)
+    g.set_lane_max_speed(ids, lim)
+    g.step(w.n_steps)
+    gm = g.metrics()
+    _log("c1_lane_max_speed_horizon", dict(oracle_finished=om["finished"], gpu_finished=gm["n_finished"],
+                                           oracle_speed=om["mean_speed_avg"], gpu_speed=gm["mean_speed_avg"]))
+    assert gm["errors"] == 0
+    assert abs(gm["n_finished"] - om["finished"]) <= 0.01 * om["finished"]
+    assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
+
+
 def test_c1_horizon_statistics(O, Sim):
     """Full 600-step run from t = 0 on both sides: completed trips and the
     time-averaged mean road speed agree within 1%."""

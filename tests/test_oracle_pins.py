@@ -290,3 +290,25 @@ def test_fast_keeper_is_bounded_by_the_merger_rear(oracle_lib):
     o.step(1)
     s = o.get_state()
     assert s["lane"][1] == 0 and s["x"][1] == 95.0 and s["v"][1] == 0.0
+
+
+# ---------------------------------------------------------------- lane control
+
+@pytest.mark.parametrize("limit,expect_v", [(10.0, 10.0), (None, None)])
+def test_lane_max_speed_sets_the_desired_speed(oracle_lib, limit, expect_v):
+    """Section 3.2 set_lane_max_speed: a lone vehicle at 10 m/s on a lane whose
+    limit becomes 10 m/s (factor 1) has zero free-road acceleration and keeps
+    exactly 10 m/s; under the original 13.9 m/s limit it speeds up by
+    a_max (1 - (10 / 13.9)^4) in one step (mistake caught: the new limit not
+    used for the desired speed)."""
+    net = line_network(lanes=1, length=1000.0, policy=W.POLICY_NONE)
+    trips = trips_for([[0, 2]])
+    o = _sim(oracle_lib, net, trips, _state(1, [0], [100.0], [10.0], [1]))
+    if limit is not None:
+        o.set_lane_max_speed([0], [float(np.float32(limit))])
+    o.step(1)
+    v = o.get_state()["v"][0]
+    if expect_v is not None:
+        assert v == expect_v
+    else:
+        assert v == pytest.approx(10.0 + P.a_max * (1 - (10.0 / LIM) ** 4), abs=1e-12)
