@@ -215,6 +215,20 @@ int tsim_set_signal_policy(tsim_handle *h, const int32_t *junction_ids, const in
  * instance); nothing changes then.  Synchronises the stream. */
 int tsim_set_lane_max_speed(tsim_handle *h, const int32_t *lane_ids, const float *max_speed, int32_t n);
 
+/* Vehicle vehicle_id follows the route roads[0 .. n_roads-1] from the next
+ * step on (Section 3.2 "Vehicle" set_vehicle_route, for congestion pricing
+ * and rerouting).  The route must begin with the road the vehicle is on (its
+ * origin road while it waits; on a junction lane, the road it left, followed
+ * by the road that lane enters), and consecutive roads must be joined by a
+ * junction lane; its trip ends at the end of the last road (the paper's end
+ * lane and position are not modelled: trips end at a road's end).  Its
+ * route position becomes 0; a vehicle outside the new next road's lane group
+ * changes lanes toward it as usual.  Changed routes are kept in a route pool
+ * with room for a quarter of the creation routes plus 4,096 entries
+ * (TSIM_ENOMEM when it is full); TSIM_EINVAL for a finished vehicle or a bad
+ * route.  Synchronises the stream. */
+int tsim_set_vehicle_route(tsim_handle *h, int32_t vehicle_id, const int32_t *roads, int32_t n_roads);
+
 /* Synchronises the stream, then fills *out. */
 int tsim_get_metrics(tsim_handle *h, tsim_metrics *out);
 
@@ -341,6 +355,9 @@ int tsim_batch_set_graph_steps(tsim_batch *b, int32_t chunk);
 int tsim_batch_set_horizon(tsim_batch *b, int32_t instance, int64_t n_steps);
 int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
                                  const int32_t *phase_index, int32_t n);
+/* As tsim_set_vehicle_route, for a vehicle of one instance (local ids). */
+int tsim_batch_set_vehicle_route(tsim_batch *b, int32_t instance, int32_t vehicle_id, const int32_t *roads,
+                                 int32_t n_roads);
 /* As tsim_set_lane_max_speed, for the lanes of one instance. */
 int tsim_batch_set_lane_max_speed(tsim_batch *b, int32_t instance, const int32_t *lane_ids, const float *max_speed,
                                   int32_t n);

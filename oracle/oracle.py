@@ -53,6 +53,8 @@ def lib():
         L.osim_set_policy.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_set_lane_max_speed.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.osim_set_vehicle_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
+        L.osim_get_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.osim_get_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_get_metrics.argtypes = [C.c_void_p, C.c_void_p]
         L.osim_get_road_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -170,6 +172,20 @@ class OracleSim:
         l = np.ascontiguousarray(lanes, np.int32)
         v = np.ascontiguousarray(speeds, np.float64)
         lib().osim_set_lane_max_speed(self.h, int(l.size), _p(l), _p(v))
+
+    def set_vehicle_route(self, vid, route):
+        """Vehicle vid follows `route` (road ids, beginning with the road it is
+        on) from the next step on, at route position 0."""
+        r = np.ascontiguousarray(route, np.int32)
+        lib().osim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size))
+
+    def route(self, vid, max_len=100000):
+        """(route position, roads of the route in force) of vehicle vid."""
+        k = np.zeros(1, np.int32)
+        n = np.zeros(1, np.int32)
+        out = np.zeros(max_len, np.int32)
+        lib().osim_get_route(self.h, int(vid), _p(k), _p(n), _p(out), max_len)
+        return int(k[0]), out[:int(n[0])].copy()
 
     def junctions(self):
         p = np.zeros(self.net.n_junctions, np.int32)

@@ -75,7 +75,9 @@ typedef struct osim {
     /* trips */
     int N;
     double *tau, *f, *L;
-    int *route_begin, *route;
+    int *route_begin, *route;    /* CSR of the routes given at creation */
+    int *rstart, *rlen;          /* [N] the route in force: route[rstart, rstart + rlen) */
+    long route_n, route_cap;     /* route entries used / allocated (set_vehicle_route appends) */
     int *q_begin, *q_veh;        /* [R+1] departure queue of each origin road, (tau, id) order */
     /* state */
     int64_t t;
@@ -255,8 +257,13 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
     s->L = (double *)xcalloc(N, sizeof(double));
     s->route_begin = (int *)xcalloc(N + 1, sizeof(int));
     memcpy(s->route_begin, route_begin, (N + 1) * sizeof(int));
-    s->route = (int *)xcalloc(route_begin[N], sizeof(int));
+    s->route_cap = route_begin[N] > 0 ? route_begin[N] : 1;
+    s->route_n = route_begin[N];
+    s->route = (int *)xcalloc(s->route_cap, sizeof(int));
     memcpy(s->route, route_roads, (size_t)route_begin[N] * sizeof(int));
+    s->rstart = (int *)xcalloc(N, sizeof(int));
+    s->rlen = (int *)xcalloc(N, sizeof(int));
+    for (int i = 0; i < N; ++i) { s->rstart[i] = route_begin[i]; s->rlen[i] = route_begin[i + 1] - route_begin[i]; }
     for (int i = 0; i < N; ++i) { s->tau[i] = depart[i]; s->f[i] = v0_factor[i]; s->L[i] = veh_length[i]; }
     s->q_begin = (int *)xcalloc(R + 1, sizeof(int));
     s->q_veh = (int *)xcalloc(N, sizeof(int));
@@ -302,7 +309,7 @@ void osim_destroy(osim *s)
     void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim,
                     s->jl_in, s->jl_out, s->jl_junction, s->junc_phase_begin, s->phase_green_begin,
                     s->phase_green_jl, s->phase_dur, s->policy, s->manual_phase, s->out_begin, s->out_jl,
-                    s->feed_begin, s->feed_jl, s->tau, s->f, s->L, s->route_begin, s->route, s->q_begin,
+                    s->feed_begin, s->feed_jl, s->tau, s->f, s->L, s->route_begin, s->route, s->rstart, s->rlen, s->q_begin,
                     s->q_veh, s->status, s->lane, s->k, s->finish_step, s->x, s->v, s->n_status, s->n_lane,
                     s->n_k, s->n_x, s->n_v, s->sorted, s->lane_start, s->lane_cnt, s->green, s->road_sumv,
                     s->road_cnt, s->lane_wait, s->vend, s->margin, s->mobil, s->decision, s->event};
@@ -321,11 +328,11 @@ static int ahead(const osim *s, int a, int b)
     return s->x[a] > s->x[b] || (s->x[a] == s->x[b] && a < b);
 }
 
-static int route_len(const osim *s, int i) { return s->route_begin[i + 1] - s->route_begin[i]; }
+static int route_len(const osim *s, int i) { return s->rlen[i]; }
 
 static int next_road(const osim *s, int i)
 {
-    return (s->k[i] + 1 < route_len(s, i)) ? s->route[s->route_begin[i] + s->k[i] + 1] : -1;
+    return (s->k[i] + 1 < route_len(s, i)) ? s->route[s->rstart[i] + s->k[i] + 1] : -1;
 }
 
 /* junction lane (global id) from road lane l into road r2, or -1 */
@@ -420,7 +427,7 @@ static int sigma2(const osim *s, int j, int g1)
     if (g1 >= s->NRL) return s->jl_out[g1 - s->NRL];
     int kk = s->k[j] + 2;
     if (kk >= route_len(s, j)) return -1;
-    return jl_to_road(s, g1, s->route[s->route_begin[j] + kk]);
+    return jl_to_road(s, g1, s->route[s->rstart[j] + kk]);
 }
 
 /* leader of vehicle j if it drives in lane m: the rearmost vehicle of m ahead
@@ -1069,6 +1076,31 @@ void osim_set_signal_phases(osim *s, int n, const int *junction, const int *phas
 void osim_set_policy(osim *s, int n, const int *junction, const int *policy)
 {
     for (int c = 0; c < n; ++c) s->policy[junction[c]] = policy[c];
+}
+
+/* Section 3.2 "Vehicle" set_vehicle_route: vehicle i follows `route` from
+ * now on.  The new route begins with the road the vehicle is on (its origin
+ * road while it waits), and, on a junction lane, continues with that lane's
+ * road; the vehicle's route position becomes 0.  The trip ends at the end of
+ * the new route's last road.  The caller checks the route is connected. */
+void osim_set_vehicle_route(osim *s, int i, const int *route, int len)
+{
+    if (s->route_n + len > s->route_cap) {
+        while (s->route_n + len > s->route_cap) s->route_cap *= 2;
+        s->route = (int *)realloc(s->route, (size_t)s->route_cap * sizeof(int));
+    }
+    memcpy(s->route + s->route_n, route, (size_t)len * sizeof(int));
+    s->rstart[i] = (int)s->route_n;
+    s->rlen[i] = len;
+    s->route_n += len;
+    s->k[i] = 0;
+}
+
+void osim_get_route(const osim *s, int i, int *start_pos, int *len, int *out, int max)
+{
+    *start_pos = s->k[i];
+    *len = s->rlen[i];
+    for (int c = 0; c < s->rlen[i] && c < max; ++c) out[c] = s->route[s->rstart[i] + c];
 }
 
 /* Section 3.2 "Lane" set_lane_max_speed: the speed limit of lanes (road or

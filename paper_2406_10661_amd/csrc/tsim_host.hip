@@ -52,7 +52,8 @@ struct Build {
     std::vector<float> phase_dur;
     std::vector<double> junc_cycle;
     std::vector<float> tau, vf, vlen;
-    std::vector<int32_t> route_begin, route, q_begin, q_veh;
+    std::vector<int32_t> route_begin, route, q_begin, q_veh;   // route_begin: CSR of the routes given at creation
+    std::vector<int32_t> rstart, rlen;   // the route in force of each vehicle: route[rstart, rstart + rlen)
     std::vector<uint32_t> q_mask;    // per queue entry: origin-road lanes that lead to its next road
     uint64_t slots = 0;
     int G = 0;                       // partial slots: max over schedules of GT + GA + GB + GC
@@ -175,7 +176,8 @@ Caps caps_of(const Build& B)
     c.N = B.N;
     c.S = (long long)B.slots;
     c.P = (long long)B.phase_dur.size();
-    c.E = (long long)B.route.size();
+    // room for routes changed by tsim_set_vehicle_route (appended)
+    c.E = (long long)B.route.size() + (long long)B.route.size() / 4 + 4096;
     c.G = std::max<long long>(B.G, g_bound(B.R));
     c.n_inst = B.n_inst;
     return c;
@@ -395,6 +397,9 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
     B.vlen.assign(tr->length, tr->length + N);
     B.route_begin.assign(tr->route_begin, tr->route_begin + N + 1);
     B.route.assign(tr->route_roads, tr->route_roads + tr->route_begin[N]);
+    B.rstart.assign(B.route_begin.begin(), B.route_begin.begin() + N);
+    B.rlen.resize(N);
+    for (int i = 0; i < N; ++i) B.rlen[i] = B.route_begin[i + 1] - B.route_begin[i];
     B.q_begin.assign(R + 1, 0);
     for (int i = 0; i < N; ++i) B.q_begin[B.route[B.route_begin[i]] + 1]++;
     for (int r = 0; r < R; ++r) B.q_begin[r + 1] += B.q_begin[r];
@@ -852,13 +857,13 @@ int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, con
         if (s == TSIM_ACTIVE) {
             const int l = lane_loc[il];
             if (l < 0 || l >= nl_loc) return fail(&h->err, TSIM_EINVAL, "active vehicle without a valid lane");
-            const int rl = B.route_begin[i + 1] - B.route_begin[i];
+            const int rl = B.rlen[i];
             const int kk = route_pos[il];
             if (kk < 0 || kk >= rl) return fail(&h->err, TSIM_EINVAL, "route position out of range");
             const int m = B.int_of_ext[union_lane(B, g, l)];
             const int r = B.lane_tile[m];
-            if (B.route[B.route_begin[i] + kk] != r) return fail(&h->err, TSIM_EINVAL, "lane not on the current road");
-            if (B.jl_out[m] >= 0 && (kk + 1 >= rl || B.jl_out_road[m] != B.route[B.route_begin[i] + kk + 1]))
+            if (B.route[B.rstart[i] + kk] != r) return fail(&h->err, TSIM_EINVAL, "lane not on the current road");
+            if (B.jl_out[m] >= 0 && (kk + 1 >= rl || B.jl_out_road[m] != B.route[B.rstart[i] + kk + 1]))
                 return fail(&h->err, TSIM_EINVAL, "junction lane not toward the next road");
             if (!(x[il] >= 0.0f && x[il] <= B.lane_len[m]) || !(v[il] >= 0.0f))
                 return fail(&h->err, TSIM_EINVAL, "position or speed out of range");
@@ -913,8 +918,8 @@ int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, con
             o.vid = i;
             o.len = B.vlen[i];
             o.f = B.vf[i];
-            o.rp = B.route_begin[i] + route_pos[i - g.v0];
-            o.rem = B.route_begin[i + 1] - o.rp - 1;
+            o.rp = B.rstart[i] + route_pos[i - g.v0];
+            o.rem = B.rstart[i] + B.rlen[i] - o.rp - 1;
             o.nr = o.rem > 0 ? B.route[o.rp + 1] : -1;
             slots.push_back(B.lane_base[m] + (uint32_t)c);
             recs.push_back(o);
@@ -1176,7 +1181,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
     e = e ? e : chk(up_range(h, (float*)D.phase_dur, B.phase_dur, sp.p0, sp.p1), "junctions");
     e = e ? e : chk(up_range(h, (double*)D.junc_cycle, B.junc_cycle, sp.j0, sp.j1), "junctions");
     e = e ? e : chk(up_range(h, (float*)D.tau, B.tau, sp.v0, sp.v1), "trips");
-    e = e ? e : chk(up_range(h, (int32_t*)D.route_begin, B.route_begin, sp.v0, sp.v1 + 1), "trips");
+    e = e ? e : chk(up_range(h, (int32_t*)D.route_begin, B.rstart, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (int32_t*)D.route, B.route, sp.e0, sp.e1), "trips");
     e = e ? e : chk(up_range(h, (float*)D.vf, B.vf, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (float*)D.vlen, B.vlen, sp.v0, sp.v1), "trips");
@@ -1187,7 +1192,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
         std::vector<QRec> qr(B.q_veh.size());
         for (int k = k0; k < k1; ++k) {
             const int v = B.q_veh[k];
-            const int rb = B.route_begin[v], rl = B.route_begin[v + 1] - rb;
+            const int rb = B.rstart[v], rl = B.rlen[v];
             QRec& q = qr[k];
             q.tau = B.tau[v];
             q.mask = B.q_mask[k];
@@ -1747,6 +1752,124 @@ int tsim_batch_set_lane_max_speed(tsim_batch* b, int32_t instance, const int32_t
     return lane_speed_impl(b, instance, lane_ids, max_speed, n);
 }
 
+static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<float>& x, std::vector<float>& v,
+                        std::vector<int32_t>& rpos, std::vector<int32_t>& rank);
+
+// a junction lane leads from some lane of road a to road b
+static bool roads_joined(const Build& B, int a, int b)
+{
+    const int lb = B.tile_lane_begin[a], nrl = B.tile_n_road[a];
+    for (int m = lb; m < lb + nrl; ++m)
+        for (int e = B.out_begin[m]; e < B.out_begin[m + 1]; ++e)
+            if (B.jl_out_road[B.out_jl[e]] == b) return true;
+    return false;
+}
+
+static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* roads_local, int32_t len)
+{
+    if (!h || !roads_local || len < 1 || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = h->B;
+    DevNet& D = h->D;
+    const Ranges g = ranges_of(B, k);
+    if (vid_local < 0 || vid_local >= g.v1 - g.v0) return fail(&h->err, TSIM_EINVAL, "vehicle id out of range");
+    const int i = g.v0 + vid_local;
+    std::vector<int32_t> roads(len);
+    for (int c = 0; c < len; ++c) {
+        const int r = roads_local[c];
+        if (r < 0 || r >= g.r1 - g.r0) return fail(&h->err, TSIM_EINVAL, "road id out of range");
+        roads[c] = g.r0 + r;
+        if (c > 0 && !roads_joined(B, roads[c - 1], roads[c]))
+            return fail(&h->err, TSIM_EINVAL, "consecutive roads of the route are not joined by a junction lane");
+    }
+    if ((long long)B.route.size() + len > h->cap.E)
+        return fail(&h->err, TSIM_ENOMEM, "no room left for changed routes");
+    // where the vehicle is: status, and for an active vehicle its lane and
+    // place in the lane order at this step boundary
+    std::vector<int32_t> lane, rpos, rank;
+    std::vector<float> x, v;
+    int32_t st = 0;
+    HIPCHK(h, hipMemcpyAsync(&st, D.status + i, 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (st == TSIM_FINISHED) return fail(&h->err, TSIM_EINVAL, "the vehicle has finished its trip");
+    const int32_t nst = (int32_t)B.route.size();
+    const int32_t rem = len - 1, nr = len > 1 ? roads[1] : -1;
+    if (st == TSIM_WAITING) {
+        const int origin = B.route[B.rstart[i]];
+        if (roads[0] != origin) return fail(&h->err, TSIM_EINVAL, "a waiting vehicle's route must start at its origin road");
+        // its departure queue entry: place, lanes toward the new next road
+        int q = -1;
+        for (int e = B.q_begin[origin]; e < B.q_begin[origin + 1]; ++e)
+            if (B.q_veh[e] == i) q = e;
+        if (q < 0) return fail(&h->err, TSIM_ESTATE, "vehicle missing from its departure queue");
+        const int lb = B.tile_lane_begin[origin];
+        uint32_t mask = 0u;
+        for (int li = 0; li < B.tile_n_road[origin]; ++li) {
+            bool ok = nr < 0;
+            for (int e = B.out_begin[lb + li]; e < B.out_begin[lb + li + 1] && !ok; ++e)
+                ok = B.jl_out_road[B.out_jl[e]] == nr;
+            if (ok) mask |= 1u << li;
+        }
+        B.q_mask[q] = mask;
+        QRec qr;
+        qr.tau = B.tau[i];
+        qr.mask = mask;
+        qr.vid = i;
+        qr.len = B.vlen[i];
+        qr.f = B.vf[i];
+        qr.rp = nst;
+        qr.rem = rem;
+        qr.nr = nr;
+        HIPCHK(h, hipMemcpyAsync((void*)(D.q_rec + q), &qr, sizeof(QRec), hipMemcpyHostToDevice, h->stream));
+    } else {
+        int rc = export_state(h, lane, x, v, rpos, rank);
+        if (rc) return rc;
+        const int m = B.int_of_ext[lane[i]];
+        const int cur = B.lane_tile[m];
+        if (roads[0] != cur) return fail(&h->err, TSIM_EINVAL, "the route must start with the vehicle's current road");
+        if (B.jl_out[m] >= 0 && (len < 2 || roads[1] != B.jl_out_road[m]))
+            return fail(&h->err, TSIM_EINVAL, "a vehicle on a junction lane must keep the road that lane leads to");
+        // its record: a lane slot of the current buffer, or the lane's inbox
+        long long gnow = 0;
+        int32_t cnt = 0;
+        HIPCHK(h, hipMemcpyAsync(&gnow, D.gstep, 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        const int inst = B.tile_inst[cur];
+        long long t0 = 0, end = 0;
+        HIPCHK(h, hipMemcpyAsync(&t0, D.inst_t0 + inst, 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(&end, D.inst_end + inst, 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        const long long loc = gnow - t0;
+        const bool odd = ((t0 + (loc < end ? loc : end)) & 1) != 0;
+        const LaneSum* sum = odd ? D.sum1 : D.sum0;
+        VehRec* slab = odd ? D.slab1 : D.slab0;
+        HIPCHK(h, hipMemcpyAsync(&cnt, &sum[m].cnt, 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        VehRec* rec = rank[i] < cnt ? slab + B.lane_base[m] + rank[i] : D.inbox + m;
+        const int32_t tail[3] = {nst, rem, nr};   // rp, rem, nr: the record's last three words
+        HIPCHK(h, hipMemcpyAsync(&rec->rp, tail, sizeof(tail), hipMemcpyHostToDevice, h->stream));
+    }
+    B.route.insert(B.route.end(), roads.begin(), roads.end());
+    B.rstart[i] = nst;
+    B.rlen[i] = len;
+    HIPCHK(h, up_range(h, (int32_t*)D.route, B.route, nst, nst + len));
+    HIPCHK(h, hipMemcpyAsync((void*)(D.route_begin + i), &B.rstart[i], 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_set_vehicle_route(tsim_handle* h, int32_t vehicle_id, const int32_t* roads, int32_t n_roads)
+{
+    return route_impl(h, -1, vehicle_id, roads, n_roads);
+}
+
+int tsim_batch_set_vehicle_route(tsim_batch* b, int32_t instance, int32_t vehicle_id, const int32_t* roads,
+                                 int32_t n_roads)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return route_impl(b, instance, vehicle_id, roads, n_roads);
+}
+
 int tsim_batch_set_horizon(tsim_batch* b, int32_t instance, int64_t n_steps)
 {
     if (!b || instance < 0 || instance >= b->B.n_inst || n_steps < 0)
@@ -1952,7 +2075,7 @@ static int get_state_impl(tsim_handle* h, int inst, tsim_state_host* out)
         out->lane[k] = l;
         out->x[k] = act ? x[i] : 0.0f;
         out->v[k] = act ? v[i] : 0.0f;
-        out->route_pos[k] = act ? rpos[i] : (status[i] == TSIM_WAITING ? 0 : B.route_begin[i + 1] - B.route_begin[i] - 1);
+        out->route_pos[k] = act ? rpos[i] : (status[i] == TSIM_WAITING ? 0 : B.rlen[i] - 1);
     }
     const int jo = B.junc_off[inst], nj = B.junc_off[inst + 1] - jo;
     for (int j = 0; j < nj; ++j) {
@@ -2107,6 +2230,8 @@ bool append_build(tsim_handle* h, const Build& M, uint64_t seed, Span& sp)
         B.vf.push_back(M.vf[i]);
         B.vlen.push_back(M.vlen[i]);
         B.route_begin.push_back(M.route_begin[i + 1] + (int)E0);
+        B.rstart.push_back(M.rstart[i] + (int)E0);
+        B.rlen.push_back(M.rlen[i]);
     }
     for (int r : M.route) B.route.push_back(r + R0);
     for (size_t q = 0; q < M.q_veh.size(); ++q) {
@@ -2142,7 +2267,11 @@ void pop_build(tsim_handle* h)
     const int r0 = B.road_off[k], j0 = B.junc_off[k], v0 = B.veh_off[k];
     const int m0 = B.tile_lane_begin[r0];
     const int q0 = B.out_begin[m0], qv0 = B.q_begin[r0];
-    const int p0 = B.junc_phase_begin[j0], e0 = B.route_begin[v0];
+    const int p0 = B.junc_phase_begin[j0];
+    // the route pool keeps every route in force of the remaining instances
+    // (routes changed after an instance joined are appended after it)
+    int e0 = B.route_begin[v0];
+    for (int i = 0; i < v0; ++i) e0 = std::max(e0, B.rstart[i] + B.rlen[i]);
     const uint64_t s0 = m0 < (int)B.lane_base.size() ? B.lane_base[m0] : B.slots;
     for (int m = m0; m < B.NL; ++m) B.int_of_ext[B.ext_of_int[m]] = -1;
     B.tile_lane_begin.resize(r0 + 1);
@@ -2172,6 +2301,8 @@ void pop_build(tsim_handle* h)
     B.vlen.resize(v0);
     B.route_begin.resize(v0 + 1);
     B.route.resize(e0);
+    B.rstart.resize(v0);
+    B.rlen.resize(v0);
     B.q_veh.resize(qv0);
     B.q_mask.resize(qv0);
     B.slots = s0;

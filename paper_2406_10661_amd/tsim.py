@@ -82,7 +82,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_instance_build", "tsim_instance_free", "tsim_instance_capacity", "tsim_batch_reserve_footprint",
            "tsim_batch_reserve", "tsim_batch_add", "tsim_batch_add_member", "tsim_batch_remove",
            "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc",
-           "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed"]
+           "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed", "tsim_set_vehicle_route",
+           "tsim_batch_set_vehicle_route"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -109,6 +110,8 @@ def lib():
         L.tsim_set_signal_policy.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_signal_phases_noalloc.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_lane_max_speed.argtypes = [P, P, P, C.c_int32]
+        L.tsim_set_vehicle_route.argtypes = [P, C.c_int32, P, C.c_int32]
+        L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32]
         L.tsim_batch_set_lane_max_speed.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_get_metrics.argtypes = [P, P]
@@ -248,6 +251,12 @@ class Sim:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(phases, np.int32)
         _check(lib().tsim_set_signal_phases(self.h, _p(j), _p(p), int(j.size)), self.h)
+
+    def set_vehicle_route(self, vid, roads):
+        """Vehicle vid follows `roads` (beginning with the road it is on) from
+        the next step on."""
+        r = np.ascontiguousarray(roads, np.int32)
+        _check(lib().tsim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size)), self.h)
 
     def set_lane_max_speed(self, lanes, speeds):
         """Speed limits of lanes (network lane ids) from the next step on."""
@@ -547,6 +556,10 @@ class Batch:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(policies, np.int32)
         _check(lib().tsim_batch_set_signal_policy(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
+
+    def set_vehicle_route(self, instance, vid, roads):
+        r = np.ascontiguousarray(roads, np.int32)
+        _check(lib().tsim_batch_set_vehicle_route(self.h, int(instance), int(vid), _p(r), int(r.size)), self.h)
 
     def set_lane_max_speed(self, instance, lanes, speeds):
         l = np.ascontiguousarray(lanes, np.int32)

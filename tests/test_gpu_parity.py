@@ -210,6 +210,76 @@ def test_lane_max_speed_horizon_statistics(O, Sim):
     assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
 
 
+def _reroutes(net, trips, st, rng, n):
+    """Valid new routes for n vehicles of state st: a waiting vehicle ends
+    its trip on its origin road; an active one on a road lane turns onto a
+    random road its road leads to; one on a junction lane keeps the road that
+    lane enters and stops there."""
+    rol = net.road_of_lane()
+    NRL = net.n_road_lanes
+    nexts = {}
+    for q in range(net.n_jlanes):
+        nexts.setdefault(int(rol[net.jl_in_lane[q]]), set()).add(int(rol[net.jl_out_lane[q]]))
+    out = []
+    cand = np.nonzero(st["status"] != 2)[0]
+    for i in rng.choice(cand, size=min(n, cand.size), replace=False):
+        rb = trips.route_begin[i]
+        if st["status"][i] == 0:
+            out.append((int(i), [int(trips.route_roads[rb])]))
+            continue
+        lane = int(st["lane"][i])
+        cur = int(trips.route_roads[rb + st["route_pos"][i]])
+        if lane >= NRL:
+            out.append((int(i), [cur, int(rol[net.jl_out_lane[lane - NRL]])]))
+        else:
+            out.append((int(i), [cur, int(rng.choice(sorted(nexts[cur])))]))
+    return out
+
+
+def test_reroute_one_step(O, Sim):
+    """Section 3.2 set_vehicle_route: 150 vehicles of a loaded 4x4 grid
+    (waiting, on road lanes and on junction lanes) get new routes; one step
+    from the same state on both sides."""
+    w = W.config1()
+    st = synthetic_state(w.network, w.trips, 120, seed=13, p_active=0.6)
+    st["routes"] = _reroutes(w.network, w.trips, st, np.random.default_rng(3), 150)
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st)
+    _log("c1_reroute", rep)
+    assert rep["active"] > 200
+
+
+def test_reroute_horizon_statistics(O, Sim):
+    """200 vehicles rerouted before they depart (t = 0: every one waits, so
+    the new routes are valid on both sides whatever happens later): each
+    turns onto a random road its origin leads to and ends there.  Completed
+    trips and mean road speed over the 600-step run within 1% of the
+    oracle's."""
+    w = W.config1()
+    o = O.OracleSim(w.network, w.trips, w.params)
+    st0 = o.get_state()
+    rol = w.network.road_of_lane()
+    nexts = {}
+    for q in range(w.network.n_jlanes):
+        nexts.setdefault(int(rol[w.network.jl_in_lane[q]]), set()).add(int(rol[w.network.jl_out_lane[q]]))
+    rng = np.random.default_rng(5)
+    routes = []
+    for i in rng.choice(np.nonzero(st0["status"] == 0)[0], size=200, replace=False):
+        org = int(w.trips.route_roads[w.trips.route_begin[i]])
+        routes.append((int(i), [org, int(rng.choice(sorted(nexts[org])))]))
+    g = Sim(w.network, w.trips, w.params)
+    for vid, roads in routes:
+        o.set_vehicle_route(vid, roads)
+        g.set_vehicle_route(vid, roads)
+    o.step(w.n_steps)
+    g.step(w.n_steps)
+    om, gm = o.metrics(), g.metrics()
+    _log("c1_reroute_horizon", dict(oracle_finished=om["finished"], gpu_finished=gm["n_finished"],
+                                    oracle_speed=om["mean_speed_avg"], gpu_speed=gm["mean_speed_avg"]))
+    assert gm["errors"] == 0
+    assert abs(gm["n_finished"] - om["finished"]) <= 0.01 * om["finished"]
+    assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
+
+
 def test_c1_horizon_statistics(O, Sim):
     """Full 600-step run from t = 0 on both sides: completed trips and the
     time-averaged mean road speed agree within 1%."""

@@ -312,3 +312,52 @@ def test_lane_max_speed_sets_the_desired_speed(oracle_lib, limit, expect_v):
         assert v == expect_v
     else:
         assert v == pytest.approx(10.0 + P.a_max * (1 - (10.0 / LIM) ** 4), abs=1e-12)
+
+
+# ------------------------------------------------------------------- rerouting
+
+def test_reroute_ends_the_trip_on_the_current_road(oracle_lib):
+    """Section 3.2 set_vehicle_route: a vehicle 10 m before the end of road
+    0, bound for road 2, is given the route [0]; its trip ends when it
+    crosses the end of road 0 (mistake caught: the old route kept, the
+    vehicle enters the junction lane)."""
+    net = line_network(lanes=1, policy=W.POLICY_NONE)
+    trips = trips_for([[0, 2]])
+    o = _sim(oracle_lib, net, trips, _state(1, [0], [290.0], [12.0], [1], step=7))
+    o.set_vehicle_route(0, [0])
+    o.step(1)
+    s = o.get_state()
+    assert s["status"][0] == 2 and s["finish_step"][0] == 7
+
+
+def test_reroute_of_a_waiting_vehicle_changes_its_departure_lanes(oracle_lib):
+    """A waiting vehicle turning left may only enter lane 0 of its origin
+    road, which is blocked; rerouted to end on its origin road it may use
+    lane 1 and departs there (mistake caught: the lane group of the old
+    route kept for departures)."""
+    net = left_turn_network(lanes=2, policy=W.POLICY_NONE)
+    trips = trips_for([[0, 2], [0, 2]])
+    o = _sim(oracle_lib, net, trips, _state(2, [0, -1], [3.0, 0.0], [0.0, 0.0], [1, 0]))
+    o.step(1)
+    assert o.get_state()["status"][1] == 0
+    o.set_vehicle_route(1, [0])
+    o.step(1)
+    s = o.get_state()
+    assert s["status"][1] == 1 and s["lane"][1] == 1
+
+
+def test_reroute_makes_a_lane_change_mandatory(oracle_lib):
+    """A vehicle on lane 1 ending its trip on road 0 (every lane in its
+    group) is rerouted to turn left into road 2, which only lane 0 reaches:
+    outside its lane group its utility toward lane 0 is at least 1 (mistake
+    caught: the lane group of the old route kept, utility -a_th)."""
+    net = left_turn_network(lanes=2, policy=W.POLICY_NONE)
+    trips = trips_for([[0]])
+    o = _sim(oracle_lib, net, trips, _state(1, [1], [50.0], [10.0], [1]))
+    o.step(1)
+    assert o.diag()["mobil"][0, 0] == pytest.approx(-W.Params().a_th, abs=1e-9)
+    o.set_vehicle_route(0, [0, 2])
+    o.step(1)
+    assert o.diag()["mobil"][0, 0] >= 1.0
+    k, route = o.route(0)
+    assert list(route) == [0, 2]
