@@ -2343,6 +2343,9 @@ int add_impl(tsim_handle* b, const Build& M, const tsim_params& prm, int32_t* in
 {
     if (!same_model(prm, b->params))
         return fail(&b->err, TSIM_EINVAL, "batch instances must share every parameter but the seed");
+    // the step still pending is folded under the view it ran with (one
+    // instance folds workgroup partials, several fold per-instance sums)
+    HIPCHK(b, launch_fold(b->D, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     Span sp;
     if (!append_build(b, M, prm.seed, sp)) return fail(&b->err, TSIM_ENOMEM, b->err);

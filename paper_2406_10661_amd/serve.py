@@ -265,12 +265,20 @@ def batch_capacity(caps, budget_bytes, reserve_footprint):
     def cap_for(v):
         return {k: int(big[k] + ratio[k] * v) + (1 if k == "instances" else 0) for k in CAP_KEYS}
 
-    lo, hi = 0, 1 << 27
-    if reserve_footprint(cap_for(0)) > budget_bytes:
+    def ok(v):
+        try:
+            return reserve_footprint(cap_for(v)) <= budget_bytes
+        except Exception:       # past the library's limits
+            return False
+
+    if not ok(0):
         raise ValueError("the HBM share of a batch cannot hold the largest job")
+    lo, hi = 0, 1
+    while ok(hi):
+        lo, hi = hi, 2 * hi
     while hi - lo > 1:
         mid = (lo + hi) // 2
-        if reserve_footprint(cap_for(mid)) <= budget_bytes:
+        if ok(mid):
             lo = mid
         else:
             hi = mid
