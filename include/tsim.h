@@ -263,6 +263,22 @@ int tsim_set_state(tsim_handle *h, const tsim_state_host *in);
 int tsim_set_profiling(tsim_handle *h, int32_t enable);
 int tsim_get_kernel_times(tsim_handle *h, double *ms, int64_t *launches, int32_t n_kernels);
 
+/* Trajectory output (Appendix B.2: every vehicle's motion state saved for
+ * output).  With every > 0, each step boundary reached by tsim_step whose
+ * step number is a multiple of `every` appends one record per vehicle on the
+ * network to device_buffer (caller-owned device memory of `capacity`
+ * records, alive while recording), in no particular order:
+ *   struct { int64_t step; int32_t vehicle; int32_t lane; float x, v; }
+ * (24 bytes; the state at the start of `step`, lane ids as in the network).
+ * Records beyond the capacity are counted but not written.  every = 0 stops
+ * recording.  Setting resets the count, synchronises the stream and drops a
+ * captured graph.  Single-instance handles; steps taken by the autotuner are
+ * not recorded. */
+int tsim_set_trajectory(tsim_handle *h, void *device_buffer, int64_t capacity, int32_t every);
+/* Records appended since tsim_set_trajectory (may exceed the capacity).
+ * Synchronises the stream. */
+int tsim_get_trajectory_count(tsim_handle *h, int64_t *n);
+
 /* Launch mode.  chunk > 0: tsim_step captures `chunk` steps (both kernels of
  * each) into one HIP graph on its first call and replays that graph for every
  * whole chunk of a call; the remaining steps are launched one by one.  chunk

@@ -28,6 +28,8 @@ hipError_t launch_set_all_phases(const DevNet* Dd, const DevNet& H, const int32_
 hipError_t launch_set_policy(const DevNet* Dd, const DevNet& H, const int32_t* ids, const int32_t* pol, int n, hipStream_t s);
 hipError_t noalloc_scratch(int32_t** out);
 hipError_t launch_set_lane_speed(const DevNet& H, const int32_t* ids, const float* lim, int n, hipStream_t s);
+hipError_t launch_record(const DevNet& H, const int32_t* lane_ext, TrajRec* out, long long cap,
+                         unsigned long long* count, int every, hipStream_t s);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
 int update_blocks_per_cu(int sched);
 }  // namespace tsim
@@ -601,6 +603,10 @@ struct tsim_handle {
     VehRec* d_io_rec = nullptr;      // staging: import records
     int32_t* d_io_ph = nullptr;      // staging: phase updates (2 slots of 2 x NJ)
     int32_t* d_io_lane = nullptr;    // staging: lane updates (NL ids, then NL values)
+    unsigned long long* d_traj_n = nullptr;   // trajectory records appended so far
+    TrajRec* traj = nullptr;         // caller's trajectory buffer (device), traj_cap records
+    long long traj_cap = 0;
+    int traj_every = 0;              // 0: not recording
     int32_t* h_pin[2] = {nullptr, nullptr};   // pinned host staging of the two slots
     hipEvent_t pin_ev[2] = {nullptr, nullptr};
     bool pin_used[2] = {false, false};
@@ -724,6 +730,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&h->d_io_rec, std::max<size_t>(N, 1) * sizeof(VehRec));
     add(&h->d_io_ph, 4 * std::max<size_t>(NJ, 1) * 4);
     add(&h->d_io_lane, 2 * std::max<size_t>(NL, 1) * 4);
+    add(&h->d_traj_n, 8);
     add(&h->d_net, sizeof(DevNet));
     return v;
 }
@@ -1361,6 +1368,8 @@ static int capture_chunk(tsim_handle* h)
     for (int s = 0; s < h->graph_chunk && e == hipSuccess; ++s) {
         e = launch_prepare(h->d_net, h->D, h->cap_stream);
         if (e == hipSuccess) e = launch_update(h->d_net, h->D, h->cap_stream, &h->ps);
+        if (e == hipSuccess && h->traj_every > 0)
+            e = launch_record(h->D, h->d_lane_ext, h->traj, h->traj_cap, h->d_traj_n, h->traj_every, h->cap_stream);
     }
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1547,7 +1556,36 @@ int tsim_step(tsim_handle* h, int32_t n_steps)
         if (rc) return rc;
         rc = timed_launch(h, 0);
         if (rc) return rc;
+        if (h->traj_every > 0)
+            HIPCHK(h, launch_record(h->D, h->d_lane_ext, h->traj, h->traj_cap, h->d_traj_n, h->traj_every, h->stream));
     }
+    return TSIM_OK;
+}
+
+int tsim_set_trajectory(tsim_handle* h, void* device_buffer, int64_t capacity, int32_t every)
+{
+    if (!h || every < 0 || (every > 0 && (!device_buffer || capacity < 0)) || h->B.n_inst != 1)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments (single-instance handles only)");
+    if (h->graph) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    h->traj = (TrajRec*)device_buffer;
+    h->traj_cap = every > 0 ? capacity : 0;
+    h->traj_every = every;
+    HIPCHK(h, hipMemsetAsync(h->d_traj_n, 0, 8, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_get_trajectory_count(tsim_handle* h, int64_t* n)
+{
+    if (!h || !n) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    unsigned long long c = 0;
+    HIPCHK(h, hipMemcpyAsync(&c, h->d_traj_n, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *n = (int64_t)c;
     return TSIM_OK;
 }
 

@@ -155,6 +155,15 @@ struct KParams {
     int delta_is_4;
 };
 
+// one vehicle's state at a recorded step boundary (trajectory output)
+struct TrajRec {
+    int64_t step;   // the step about to run (the state is the end of step - 1)
+    int32_t vid;
+    int32_t lane;   // external lane id
+    float x, v;
+};
+static_assert(sizeof(TrajRec) == 24, "trajectory records are 24 bytes");
+
 // cumulative metrics; a step's sums are folded in by the next step's prepare
 // kernel, or before the host reads them
 struct DevMetrics {

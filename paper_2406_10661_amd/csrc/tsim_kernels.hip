@@ -1002,12 +1002,16 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
                     if (!(g >= 0.0f)) return o;
                 }
             }
-            const float ta_e = accel(rec.v, v0, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false), len, P);
+            // desired speeds in lane k from k's own limit (lanes of a road may
+            // have different limits)
+            const float lim_k = S.lim[k];
+            const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false),
+                                     len, P);
             float d_new = 0.0f, d_old = 0.0f;
             if (tf >= 0) {
                 const float a_tf = view.aown(tf);
                 const Lead me_lead{rec.x, -rec.len, rec.v, true};
-                const float ta_tf = accel(tfr.v, tfr.f * lim, tfr.x, me_lead, view.stopf(tf), len, P);
+                const float ta_tf = accel(tfr.v, tfr.f * lim_k, tfr.x, me_lead, view.stopf(tf), len, P);
                 if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
                 d_new = ta_tf - a_tf;
             }
@@ -2036,6 +2040,46 @@ __global__ void k_export(const DevNet D, const int32_t* lane_ext, int32_t* o_lan
         o_rpos[z.vid] = z.rp - D.route_begin[z.vid];
         o_rank[z.vid] = c;
     }
+}
+
+// trajectory output (Appendix B.2: every vehicle's motion state saved for
+// output): at a step boundary whose step number is a multiple of `every`,
+// one record per vehicle on the network (lane residents and inbox entrants),
+// appended to the caller's buffer through a counter; records beyond
+// `cap` are counted but not written.  Launched after every update while
+// recording is on; other steps return at once.
+__global__ void k_record(const DevNet D, const int32_t* lane_ext, TrajRec* out, long long cap,
+                         unsigned long long* count, int every)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= D.NL) return;
+    const long long t = *D.gstep;
+    if (t % every != 0) return;
+    const int p = (int)(t & 1);
+    const VehRec* slab = p ? D.slab1 : D.slab0;
+    const LaneSum* sum = p ? D.sum1 : D.sum0;
+    const int c = sum[m].cnt;
+    const int in = D.inbox_flag[m] != 0 ? 1 : 0;
+    if (c + in == 0) return;
+    const unsigned long long base = atomicAdd(count, (unsigned long long)(c + in));
+    for (int q = 0; q < c + in; ++q) {
+        if ((long long)(base + q) >= cap) break;
+        const VehRec z = q < c ? slab[D.lane_base[m] + q] : D.inbox[m];
+        TrajRec r;
+        r.step = t;
+        r.vid = z.vid;
+        r.lane = lane_ext[m];
+        r.x = z.x;
+        r.v = z.v;
+        out[base + q] = r;
+    }
+}
+
+hipError_t launch_record(const DevNet& H, const int32_t* lane_ext, TrajRec* out, long long cap,
+                         unsigned long long* count, int every, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_record, dim3((H.NL + 255) / 256), dim3(256), 0, s, H, lane_ext, out, cap, count, every);
+    return hipGetLastError();
 }
 
 // scatter of host-ordered records into the read slab of the current step

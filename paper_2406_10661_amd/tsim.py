@@ -83,7 +83,7 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_reserve", "tsim_batch_add", "tsim_batch_add_member", "tsim_batch_remove",
            "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc",
            "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed", "tsim_set_vehicle_route",
-           "tsim_batch_set_vehicle_route"]
+           "tsim_batch_set_vehicle_route", "tsim_set_trajectory", "tsim_get_trajectory_count"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -111,6 +111,8 @@ def lib():
         L.tsim_set_signal_phases_noalloc.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_lane_max_speed.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_vehicle_route.argtypes = [P, C.c_int32, P, C.c_int32]
+        L.tsim_set_trajectory.argtypes = [P, P, C.c_int64, C.c_int32]
+        L.tsim_get_trajectory_count.argtypes = [P, P]
         L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32]
         L.tsim_batch_set_lane_max_speed.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
@@ -232,6 +234,7 @@ class Sim:
                                  C.c_void_p(self.stream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
                                  C.c_size_t(self.arena.numel()), C.byref(h)))
         self.h = h
+        self.traj = None
 
     def close(self):
         if getattr(self, "h", None):
@@ -251,6 +254,32 @@ class Sim:
         j = np.ascontiguousarray(junctions, np.int32)
         p = np.ascontiguousarray(phases, np.int32)
         _check(lib().tsim_set_signal_phases(self.h, _p(j), _p(p), int(j.size)), self.h)
+
+    def record_trajectory(self, every, capacity):
+        """Record every vehicle's (step, id, lane, x, v) at each step boundary
+        whose step is a multiple of `every` into a device buffer of
+        `capacity` records (every = 0 stops)."""
+        import torch
+        if every > 0:
+            self.traj = torch.zeros((int(capacity), 24), dtype=torch.uint8, device=self.device)
+            ptr = C.c_void_p(self.traj.data_ptr())
+        else:
+            self.traj, ptr = None, C.c_void_p()
+        _check(lib().tsim_set_trajectory(self.h, ptr, int(capacity) if every > 0 else 0, int(every)), self.h)
+
+    def trajectory(self):
+        """The recorded trajectory as numpy arrays (step, vehicle, lane, x, v),
+        sorted by (step, vehicle), and the number of records dropped for want
+        of capacity."""
+        n = np.zeros(1, np.int64)
+        _check(lib().tsim_get_trajectory_count(self.h, _p(n)), self.h)
+        cap = 0 if self.traj is None else self.traj.shape[0]
+        k = int(min(n[0], cap))
+        raw = self.traj[:k].cpu().numpy().reshape(-1)
+        rec = np.frombuffer(raw.tobytes(), dtype=np.dtype([("step", "<i8"), ("vehicle", "<i4"), ("lane", "<i4"),
+                                                           ("x", "<f4"), ("v", "<f4")]))
+        rec = np.sort(rec, order=["step", "vehicle"])
+        return {f: rec[f].copy() for f in rec.dtype.names}, int(n[0]) - k
 
     def set_vehicle_route(self, vid, roads):
         """Vehicle vid follows `roads` (beginning with the road it is on) from

@@ -196,3 +196,28 @@ def test_finished_demand_is_a_fixed_point(O, Sim):
         assert np.array_equal(st[k], np.asarray(st0[k])), k
     assert m["n_finished"] == 3
     assert m["n_active"] == 0 and m["vehicle_steps"] == 0 and m["errors"] == 0
+
+
+@pytest.mark.parametrize("graph_steps", [0, 10])
+def test_trajectory_records_equal_states(graph_steps):
+    """Trajectory output (Appendix B.2): records at every 25th step boundary
+    over 100 steps equal, vehicle by vehicle, the state read at those steps
+    from a second instance; with and without captured graphs."""
+    from paper_2406_10661_amd.tsim import Sim
+    w = W.config1()
+    a = Sim(w.network, w.trips, w.params)
+    a.set_graph_steps(graph_steps)
+    a.record_trajectory(every=25, capacity=100000)
+    a.step(100)
+    tr, dropped = a.trajectory()
+    assert dropped == 0
+    assert sorted(set(tr["step"].tolist())) == [25, 50, 75, 100]
+    b = Sim(w.network, w.trips, w.params)
+    for t in (25, 50, 75, 100):
+        b.step(25)
+        st = b.get_state()
+        act = np.nonzero(st["status"] == 1)[0]
+        sel = tr["step"] == t
+        assert np.array_equal(tr["vehicle"][sel], act)
+        assert np.array_equal(tr["lane"][sel], st["lane"][act])
+        assert np.array_equal(tr["x"][sel], st["x"][act]) and np.array_equal(tr["v"][sel], st["v"][act])
