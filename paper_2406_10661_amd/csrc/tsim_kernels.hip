@@ -491,6 +491,7 @@ struct TileLds {
     int wait[LANES];       // queue at the lane end: first snapshot rank whose end-of-step speed is >= 0.1
     int nlanes, nroad, n;
     int nchg, nmerge;
+    int ncand;             // MOBIL candidates of the tile (listed as bytes in chg_vid until the changers use it)
     float chg_x[CHG];
     int chg_vid[CHG];
     int chg_lane[CHG];
@@ -556,6 +557,21 @@ struct LdsView {
         S.nlane[j] = (signed char)nl;
     }
     __device__ void set_pref(int j, int v) { S.pref[j] = v; }
+    // MOBIL result of pass 2, held in the slots pass 2 fills last: decision
+    // and leader flag (kind), acceleration or draw (nx), leader rear (nv)
+    // and speed (pref)
+    __device__ void set_mobil(int j, int dec, float ta, float rear, float lv, bool ex)
+    {
+        S.kind[j] = (signed char)(dec | (ex ? 4 : 0));
+        S.nx[j] = ta;
+        S.nv[j] = rear;
+        S.pref[j] = __float_as_int(lv);
+    }
+    __device__ int mobil_dec(int j) const { return S.kind[j] & 3; }
+    __device__ bool mobil_ex(int j) const { return (S.kind[j] & 4) != 0; }
+    __device__ float mobil_ta(int j) const { return S.nx[j]; }
+    __device__ float mobil_rear(int j) const { return S.nv[j]; }
+    __device__ float mobil_lv(int j) const { return __int_as_float(S.pref[j]); }
 };
 
 // the same storage in global per-slot scratch, for tiles above kHugeCap
@@ -602,18 +618,32 @@ struct GlobalView {
         D.sh_nlane[s] = nl;
     }
     __device__ void set_pref(int j, int v) { D.sh_pref[slot(j)] = v; }
+    __device__ void set_mobil(int j, int dec, float ta, float rear, float lv, bool ex)
+    {
+        const uint32_t s = slot(j);
+        D.sh_kind[s] = dec | (ex ? 4 : 0);
+        D.sh_nx[s] = ta;
+        D.sh_nv[s] = rear;
+        D.sh_pref[s] = __float_as_int(lv);
+    }
+    __device__ int mobil_dec(int j) const { return D.sh_kind[slot(j)] & 3; }
+    __device__ bool mobil_ex(int j) const { return (D.sh_kind[slot(j)] & 4) != 0; }
+    __device__ float mobil_ta(int j) const { return D.sh_nx[slot(j)]; }
+    __device__ float mobil_rear(int j) const { return D.sh_nv[slot(j)]; }
+    __device__ float mobil_lv(int j) const { return __int_as_float(D.sh_pref[slot(j)]); }
 };
 
-// nearest lane of the group (bit set) to local lane li
+// distance from local lane li (< 32) to the nearest lane of the group (bit
+// set), 1 << 20 when the group is empty: the lowest set bit at or above li
+// and the highest at or below it
 __device__ __forceinline__ int group_dist(uint32_t gmask, int li, int nroad)
 {
-    int best = 1 << 20;
-    for (int b = 0; b < nroad; ++b)
-        if ((gmask >> b) & 1u) {
-            const int d = b > li ? b - li : li - b;
-            if (d < best) best = d;
-        }
-    return best;
+    (void)nroad;   // gmask has no bits at or above nroad
+    const uint32_t up = gmask >> li;
+    const uint32_t dn = gmask & (0xFFFFFFFFu >> (31 - li));
+    const int du = up ? __builtin_ctz(up) : (1 << 20);
+    const int dd = dn ? li - (31 - __builtin_clz(dn)) : (1 << 20);
+    return du < dd ? du : dd;
 }
 
 // junction lanes (local indices) toward a vehicle's next road from the lane
@@ -836,10 +866,182 @@ __device__ __forceinline__ void reset_counters(TS& S, const Hdr& h)
     S.nroad = h.nroad;
     S.nchg = 0;
     S.nmerge = 0;
+    S.ncand = 0;
     S.sumv = 0ull;
     S.cntv = 0;
     S.changes = S.transfers = S.clamps = S.fblocks = S.finished = S.errors = S.entries = 0;
     S.sum_tt = 0ull;
+}
+
+// MOBIL decision of vehicle j of tile S (Appendix B.3): the feasibility
+// checks and utilities of both sides, the randomized choice with the
+// vehicle's draw rr, and for a change the prospective acceleration and the
+// target-lane leader (a bound of the move).
+struct Mobil {
+    int dec;     // 0 keep, 1 left, 2 right
+    float ta;    // acceleration in the target lane
+    Lead lead;   // target-lane leader
+};
+
+template <class TS, class V>
+__device__ Mobil mobil_decide(const DevNet& D, const TS& S, const V& view, const LaneSum* rsum, int j, float rr,
+                              const KParams& P)
+{
+    const int nroad = S.nroad;
+    const int li = view.lane(j);
+    const int c = j - S.start[li];
+    const VehRec rec = view.rec(j);
+    const bool is_jl = li >= nroad;
+    const float len = S.len[li];
+    const float lim = S.lim[li];
+    const float v0 = rec.f * lim;
+    const float a_e = view.aown(j);
+    const uint32_t gmask = view.gmask(j);
+    const int jqp = view.jq(j);
+    const int my_mt = view.merge(j);
+    const bool in_g = !is_jl && ((gmask >> li) & 1u);
+    const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
+    // acceleration change of the old follower when this vehicle leaves
+    // (the same for both directions; computed on first use)
+    bool have_old = false;
+    float d_old_c = 0.0f;
+    // the vehicle's position in each side lane it may consider (both
+    // searches at once; eval_dir repeats the eligibility checks)
+    int posL = 0, posR = 0;
+    {
+        const bool okL = !is_jl && li >= 1 &&
+                         (in_g ? ((gmask >> (li - 1)) & 1u) != 0u : group_dist(gmask, li - 1, nroad) < dist_l);
+        const bool okR = !is_jl && li + 1 < nroad &&
+                         (in_g ? ((gmask >> (li + 1)) & 1u) != 0u : group_dist(gmask, li + 1, nroad) < dist_l);
+        count_ahead2(S, view, okL ? li - 1 : -1, rec.x, rec.vid, posL, okR ? li + 1 : -1, rec.x, rec.vid, posR);
+    }
+    // MOBIL for one direction: utility (or -inf), prospective
+    // acceleration, and the target-lane leader used as a bound
+    auto eval_dir = [&](int d) -> DirEval {
+        DirEval o;
+        o.u = -TS_INF;
+        o.ta = 0.0f;
+        o.lead.ex = false;
+        o.lead.a = TS_INF;
+        o.lead.b = 0.0f;
+        o.lead.v = 0.0f;
+        if (is_jl) return o;
+        const int k = li + d;
+        if (k < 0 || k >= nroad) return o;
+        if (in_g) {
+            if (!((gmask >> k) & 1u)) return o;
+        } else if (!(group_dist(gmask, k, nroad) < dist_l)) {
+            return o;
+        }
+        const int pos = d < 0 ? posL : posR;
+        const int tl = pos > 0 ? S.start[k] + pos - 1 : -1;
+        const int tf = pos < S.cnt[k] ? S.start[k] + pos : -1;
+        VehRec tlr{}, tfr{};
+        if (tl >= 0) tlr = view.rec(tl);
+        if (tf >= 0) tfr = view.rec(tf);
+        // same gap of k held by a vehicle two lanes right (rightward only)
+        if (d > 0 && k + 1 < nroad) {
+            int lo2 = 0, hi2 = S.cnt[k + 1];
+            count_ahead2(S, view, tl >= 0 ? k + 1 : -1, tlr.x, tlr.vid, lo2, tf >= 0 ? k + 1 : -1, tfr.x, tfr.vid,
+                         hi2);
+            if (lo2 < hi2) return o;
+        }
+        Lead tld;
+        if (tl >= 0) {
+            tld.ex = true;
+            tld.a = tlr.x;
+            tld.b = -tlr.len;
+            tld.v = tlr.v;
+        } else {
+            tld = lookahead(D, S, view, rsum, k, jq_get(jqp, d), rec.rp, rec.rem);
+        }
+        const float g3 = tld.ex ? lead_gap(tld, rec.x) : TS_INF;
+        if (!(g3 > 0.0f)) return o;
+        const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
+        if (tf >= 0 && !tf_yields) {
+            const float g4 = ((rec.x - tfr.x) - rec.len) - (tfr.v * P.dt + P.reach);
+            if (!(g4 >= 0.0f)) return o;
+        }
+        if (tf < 0) {
+            // no follower in the target lane: the lane's feeders must not
+            // reach past the changer's rear (largest reach decides)
+            const int fm = S.fmx[k];
+            if (fm != kNoFeeder) {
+                const float g = (rec.x - rec.len) - o2f(fm);
+                if (!(g >= 0.0f)) return o;
+            }
+        }
+        // desired speeds in lane k from k's own limit (lanes of a road may
+        // have different limits)
+        const float lim_k = S.lim[k];
+        const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false),
+                                 len, P);
+        float d_new = 0.0f, d_old = 0.0f;
+        if (tf >= 0) {
+            const float a_tf = view.aown(tf);
+            const Lead me_lead{rec.x, -rec.len, rec.v, true};
+            const float ta_tf = accel(tfr.v, tfr.f * lim_k, tfr.x, me_lead, view.stopf(tf), len, P);
+            if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
+            d_new = ta_tf - a_tf;
+        }
+        if (c + 1 < S.cnt[li]) {
+            if (!have_old) {
+                const VehRec ofr = view.rec(j + 1);
+                const float a_of = view.aown(j + 1);
+                Lead ol;
+                if (c > 0) {
+                    const VehRec z = view.rec(j - 1);
+                    ol.ex = true;
+                    ol.a = z.x;
+                    ol.b = -z.len;
+                    ol.v = z.v;
+                } else {
+                    ol = lookahead(D, S, view, rsum, li, jq_get(view.jq(j + 1), 0), ofr.rp, ofr.rem);
+                }
+                const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, view.stopf(j + 1), len, P);
+                d_old_c = ta_of - a_of;
+                have_old = true;
+            }
+            d_old = d_old_c;
+        }
+        const float da = (ta_e - a_e) + P.p * (d_new + d_old);
+        float ud = da - P.a_th;
+        if (!in_g) ud = fmaxf(ud, 1.0f);
+        o.u = ud;
+        o.ta = ta_e;
+        o.lead = tld;
+        return o;
+    };
+    DirEval eL, eR;
+#pragma unroll 1
+    for (int di = 0; di < 2; ++di) {
+        const DirEval e = eval_dir(di ? 1 : -1);
+        if (di) eR = e;
+        else eL = e;
+    }
+    // randomized decision (the draw only matters when a side is feasible)
+    const float uLp = fmaxf(0.0f, eL.u), uRp = fmaxf(0.0f, eR.u);
+    const float uT = uLp + uRp;
+    const float pLC = uT >= 1.0f ? P.p_max : (uT > 0.0f ? P.p_min + (P.p_max - P.p_min) * uT : P.p_min);
+    const bool fL = eL.u > -TS_INF, fR = eR.u > -TS_INF;
+    int dec = 0;
+    if (fL || fR) {
+        if (uT > 0.0f) {
+            const float bL = pLC * uLp / uT;
+            if (uLp > 0.0f && rr < bL) dec = 1;
+            else if (uRp > 0.0f && rr >= bL && rr < pLC) dec = 2;
+        } else if (fL && fR) {
+            if (rr < 0.5f * P.p_min) dec = 1;
+            else if (rr < P.p_min) dec = 2;
+        } else {
+            if (rr < P.p_min) dec = fL ? 1 : 2;
+        }
+    }
+    Mobil m;
+    m.dec = dec;
+    m.ta = dec == 1 ? eL.ta : eR.ta;
+    m.lead = dec == 1 ? eL.lead : eR.lead;
+    return m;
 }
 
 // passes 1 and 2 of one tile (see process_tile)
@@ -916,6 +1118,75 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
     tile_sync<GW>();
 
     // ---------------- pass 2: decision and motion ----------------
+    // A: every vehicle draws its number (Philox, counter (vehicle, step));
+    // a change needs r < p_LC <= p_max, so only vehicles with a feasible
+    // side and r below p_max (with a margin far above rounding) are MOBIL
+    // candidates; the others keep their lane whatever their utilities.
+    // B: the candidates of every tile of the wavefront are evaluated
+    // together, spread over all its lanes (one pass for up to 64), instead
+    // of each tile's group walking its own vehicles.  Tiles spread over
+    // several wavefronts evaluate in A.  C: motion, bounds and transfers.
+    const float r_cut = P.p_max * 1.001f;
+    // candidates are gathered for tiles staged in LDS (the same for every
+    // tile of a wavefront: groups only hold tiles of at most kCap vehicles)
+    bool compact = false;
+    if constexpr (GW <= kWave) compact = n <= TS::kCap;
+    for (int j = gt; j < n; j += GW) {
+        const int li = view.lane(j);
+        const VehRec rec = view.rec(j);
+        const bool is_jl = li >= nroad;
+        const uint32_t gmask = view.gmask(j);
+        const bool in_g = !is_jl && ((gmask >> li) & 1u);
+        const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
+        const bool okL = !is_jl && li >= 1 &&
+                         (in_g ? ((gmask >> (li - 1)) & 1u) != 0u : group_dist(gmask, li - 1, nroad) < dist_l);
+        const bool okR = !is_jl && li + 1 < nroad &&
+                         (in_g ? ((gmask >> (li + 1)) & 1u) != 0u : group_dist(gmask, li + 1, nroad) < dist_l);
+        const uint32_t w = philox_word0(key0, key1, (uint32_t)(rec.vid - vbase), (uint32_t)t);
+        const float rr = (float)w * 2.3283064365386963e-10f;  // 2^-32
+        const bool cand = (okL || okR) && rr < r_cut;
+        if (compact) {
+            view.set_mobil(j, 0, rr, 0.0f, 0.0f, false);
+            if (cand) {
+                const int q = atomicAdd(&S.ncand, 1);
+                ((unsigned char*)S.chg_vid)[q] = (unsigned char)j;
+            }
+        } else {
+            Mobil m{0, 0.0f, Lead{TS_INF, 0.0f, 0.0f, false}};
+            if (cand) m = mobil_decide(D, S, view, rsum, j, rr, P);
+            view.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
+        }
+    }
+    if constexpr (GW <= kWave) if (compact) {
+        static_assert(TS::kCap <= 4 * TS::kChg, "a tile's candidates fit its changer list");
+        constexpr int NG = kWave / GW;
+        wave_sync();
+        TS* const S0 = &S - (int)(__lane_id() / GW);   // the wavefront's tiles are consecutive
+        int pre[NG];
+        int tot = 0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            pre[g] = tot;
+            tot += S0[g].ncand;
+        }
+        for (int e = (int)__lane_id(); e < tot; e += kWave) {
+            if constexpr (NG == 1) {
+                const int j = ((const unsigned char*)S.chg_vid)[e];
+                const Mobil m = mobil_decide(D, S, view, rsum, j, view.mobil_ta(j), P);
+                view.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
+            } else {
+                // several tiles per wavefront: always staged in LDS
+                int g = NG - 1;
+                while (e < pre[g]) g--;
+                TS& Sg = S0[g];
+                LdsView<TS> vg{Sg};
+                const int j = ((const unsigned char*)Sg.chg_vid)[e - pre[g]];
+                const Mobil m = mobil_decide(D, Sg, vg, rsum, j, vg.mobil_ta(j), P);
+                vg.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
+            }
+        }
+        wave_sync();
+    }
     long long sv_acc = 0;   // this lane's road-lane speed sum (fixed point) and count
     int cv_acc = 0;
     for (int j = gt; j < n; j += GW) {
@@ -927,151 +1198,11 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         const float lim = S.lim[li];
         const float v0 = rec.f * lim;
         const float a_e = view.aown(j);
-        const uint32_t gmask = view.gmask(j);
         const int jqp = view.jq(j);
-        const int my_mt = view.merge(j);
-        const bool in_g = !is_jl && ((gmask >> li) & 1u);
-        const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
-        // acceleration change of the old follower when this vehicle leaves
-        // (the same for both directions; computed on first use)
-        bool have_old = false;
-        float d_old_c = 0.0f;
-        // the vehicle's position in each side lane it may consider (both
-        // searches at once; eval_dir repeats the eligibility checks)
-        int posL = 0, posR = 0;
-        {
-            const bool okL = !is_jl && li >= 1 &&
-                             (in_g ? ((gmask >> (li - 1)) & 1u) != 0u : group_dist(gmask, li - 1, nroad) < dist_l);
-            const bool okR = !is_jl && li + 1 < nroad &&
-                             (in_g ? ((gmask >> (li + 1)) & 1u) != 0u : group_dist(gmask, li + 1, nroad) < dist_l);
-            count_ahead2(S, view, okL ? li - 1 : -1, rec.x, rec.vid, posL, okR ? li + 1 : -1, rec.x, rec.vid, posR);
-        }
-        // MOBIL for one direction: utility (or -inf), prospective
-        // acceleration, and the target-lane leader used as a bound
-        auto eval_dir = [&](int d) -> DirEval {
-            DirEval o;
-            o.u = -TS_INF;
-            o.ta = 0.0f;
-            o.lead.ex = false;
-            o.lead.a = TS_INF;
-            o.lead.b = 0.0f;
-            o.lead.v = 0.0f;
-            if (is_jl) return o;
-            const int k = li + d;
-            if (k < 0 || k >= nroad) return o;
-            if (in_g) {
-                if (!((gmask >> k) & 1u)) return o;
-            } else if (!(group_dist(gmask, k, nroad) < dist_l)) {
-                return o;
-            }
-            const int pos = d < 0 ? posL : posR;
-            const int tl = pos > 0 ? S.start[k] + pos - 1 : -1;
-            const int tf = pos < S.cnt[k] ? S.start[k] + pos : -1;
-            VehRec tlr{}, tfr{};
-            if (tl >= 0) tlr = view.rec(tl);
-            if (tf >= 0) tfr = view.rec(tf);
-            // same gap of k held by a vehicle two lanes right (rightward only)
-            if (d > 0 && k + 1 < nroad) {
-                int lo2 = 0, hi2 = S.cnt[k + 1];
-                count_ahead2(S, view, tl >= 0 ? k + 1 : -1, tlr.x, tlr.vid, lo2, tf >= 0 ? k + 1 : -1, tfr.x, tfr.vid,
-                             hi2);
-                if (lo2 < hi2) return o;
-            }
-            Lead tld;
-            if (tl >= 0) {
-                tld.ex = true;
-                tld.a = tlr.x;
-                tld.b = -tlr.len;
-                tld.v = tlr.v;
-            } else {
-                tld = lookahead(D, S, view, rsum, k, jq_get(jqp, d), rec.rp, rec.rem);
-            }
-            const float g3 = tld.ex ? lead_gap(tld, rec.x) : TS_INF;
-            if (!(g3 > 0.0f)) return o;
-            const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
-            if (tf >= 0 && !tf_yields) {
-                const float g4 = ((rec.x - tfr.x) - rec.len) - (tfr.v * P.dt + P.reach);
-                if (!(g4 >= 0.0f)) return o;
-            }
-            if (tf < 0) {
-                // no follower in the target lane: the lane's feeders must not
-                // reach past the changer's rear (largest reach decides)
-                const int fm = S.fmx[k];
-                if (fm != kNoFeeder) {
-                    const float g = (rec.x - rec.len) - o2f(fm);
-                    if (!(g >= 0.0f)) return o;
-                }
-            }
-            // desired speeds in lane k from k's own limit (lanes of a road may
-            // have different limits)
-            const float lim_k = S.lim[k];
-            const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false),
-                                     len, P);
-            float d_new = 0.0f, d_old = 0.0f;
-            if (tf >= 0) {
-                const float a_tf = view.aown(tf);
-                const Lead me_lead{rec.x, -rec.len, rec.v, true};
-                const float ta_tf = accel(tfr.v, tfr.f * lim_k, tfr.x, me_lead, view.stopf(tf), len, P);
-                if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
-                d_new = ta_tf - a_tf;
-            }
-            if (c + 1 < S.cnt[li]) {
-                if (!have_old) {
-                    const VehRec ofr = view.rec(j + 1);
-                    const float a_of = view.aown(j + 1);
-                    Lead ol;
-                    if (c > 0) {
-                        const VehRec z = view.rec(j - 1);
-                        ol.ex = true;
-                        ol.a = z.x;
-                        ol.b = -z.len;
-                        ol.v = z.v;
-                    } else {
-                        ol = lookahead(D, S, view, rsum, li, jq_get(view.jq(j + 1), 0), ofr.rp, ofr.rem);
-                    }
-                    const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, view.stopf(j + 1), len, P);
-                    d_old_c = ta_of - a_of;
-                    have_old = true;
-                }
-                d_old = d_old_c;
-            }
-            const float da = (ta_e - a_e) + P.p * (d_new + d_old);
-            float ud = da - P.a_th;
-            if (!in_g) ud = fmaxf(ud, 1.0f);
-            o.u = ud;
-            o.ta = ta_e;
-            o.lead = tld;
-            return o;
-        };
-        DirEval eL, eR;
-#pragma unroll 1
-        for (int di = 0; di < 2; ++di) {
-            const DirEval e = eval_dir(di ? 1 : -1);
-            if (di) eR = e;
-            else eL = e;
-        }
-        // randomized decision (the draw only matters when a side is feasible)
-        const float uLp = fmaxf(0.0f, eL.u), uRp = fmaxf(0.0f, eR.u);
-        const float uT = uLp + uRp;
-        const float pLC = uT >= 1.0f ? P.p_max : (uT > 0.0f ? P.p_min + (P.p_max - P.p_min) * uT : P.p_min);
-        const bool fL = eL.u > -TS_INF, fR = eR.u > -TS_INF;
-        int dec = 0;
-        if (fL || fR) {
-            const uint32_t w = philox_word0(key0, key1, (uint32_t)(rec.vid - vbase), (uint32_t)t);
-            const float rr = (float)w * 2.3283064365386963e-10f;  // 2^-32
-            if (uT > 0.0f) {
-                const float bL = pLC * uLp / uT;
-                if (uLp > 0.0f && rr < bL) dec = 1;
-                else if (uRp > 0.0f && rr >= bL && rr < pLC) dec = 2;
-            } else if (fL && fR) {
-                if (rr < 0.5f * P.p_min) dec = 1;
-                else if (rr < P.p_min) dec = 2;
-            } else {
-                if (rr < P.p_min) dec = fL ? 1 : 2;
-            }
-        }
+        (void)c;
+        const int dec = view.mobil_dec(j);
         const int nli = dec == 1 ? li - 1 : (dec == 2 ? li + 1 : li);
-        float a = dec == 1 ? eL.ta : (dec == 2 ? eR.ta : a_e);
+        float a = dec ? view.mobil_ta(j) : a_e;
         // cooperative yielding of lane keepers to vehicles merging into their lane
         bool has_y = false;
         float y_rear = TS_INF, y_v = 0.0f;
@@ -1132,16 +1263,13 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             Bd = lr;
             vcap = view.lv(j);
         }
-        if (dec) {
-            const Lead l2 = dec == 1 ? eL.lead : eR.lead;
-            if (l2.ex) {
-                const float r2 = lead_rear(l2);
-                if (r2 < Bd) {
-                    Bd = r2;
-                    vcap = l2.v;
-                } else if (r2 == Bd) {
-                    vcap = fminf(vcap, l2.v);
-                }
+        if (dec && view.mobil_ex(j)) {
+            const float r2 = view.mobil_rear(j), l2v = view.mobil_lv(j);
+            if (r2 < Bd) {
+                Bd = r2;
+                vcap = l2v;
+            } else if (r2 == Bd) {
+                vcap = fminf(vcap, l2v);
             }
         }
         if (has_y) {
