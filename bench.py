@@ -440,6 +440,60 @@ def summarize_window(path, steps, out=sys.stdout):
     return res
 
 
+def traffic_report(pmc_dir, steps, window, copy_mib=1024, out=sys.stdout):
+    """Writes the counter-traffic summary read by traffic_from_profiles from
+    four rocprofv3 counter runs under pmc_dir: city_FETCH_SIZE/,
+    city_WRITE_SIZE/ (city runs of this script over the window) and
+    copy_FETCH_SIZE/, copy_WRITE_SIZE/ (--workload copy of copy_mib MiB,
+    which calibrates KiB of each counter against bytes moved)."""
+    import csv
+    import glob
+
+    def csv_of(sub):
+        f = sorted(glob.glob(os.path.join(pmc_dir, sub, "*counter_collection.csv")))
+        if not f:
+            raise SystemExit(f"no counter CSV under {os.path.join(pmc_dir, sub)}")
+        return f[0]
+
+    n = copy_mib << 20
+    factor = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        per = {}
+        for r in csv.DictReader(open(csv_of(f"copy_{c}"))):
+            if "copy" in r["Kernel_Name"].lower() and r["Counter_Name"] == c:
+                per[int(r["Dispatch_Id"])] = per.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+        if not per:
+            raise SystemExit(f"copy_{c}: no copy kernel dispatches")
+        kib = sum(per.values()) / len(per)
+        factor[c] = (n, kib)
+    res = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        import io
+        res[c] = summarize_window(csv_of(f"city_{c}"), steps, out=io.StringIO())
+    kernels = sorted({k for (k, p) in res["FETCH_SIZE"]})
+    print(f"| Kernel | Dispatches | FETCH_SIZE (KiB, mean) | WRITE_SIZE (KiB, mean) |", file=out)
+    print("|---|---|---|---|", file=out)
+    per_step = {"FETCH_SIZE": 0.0, "WRITE_SIZE": 0.0}
+    for k in kernels:
+        f = res["FETCH_SIZE"][(k, "timed")][1].get("FETCH_SIZE", 0.0)
+        w_ = res["WRITE_SIZE"][(k, "timed")][1].get("WRITE_SIZE", 0.0)
+        print(f"| `{k}` | {steps} | {f:.0f} | {w_:.0f} |", file=out)
+        per_step["FETCH_SIZE"] += f
+        per_step["WRITE_SIZE"] += w_
+    scale = {c: factor[c][0] / (factor[c][1] * 1024) for c in factor}
+    rd = per_step["FETCH_SIZE"] * 1024 * scale["FETCH_SIZE"]
+    wr = per_step["WRITE_SIZE"] * 1024 * scale["WRITE_SIZE"]
+    print(f"\nCalibration (plain {copy_mib} MiB device copy): FETCH_SIZE {factor['FETCH_SIZE'][1]:.0f} KiB and "
+          f"WRITE_SIZE {factor['WRITE_SIZE'][1]:.0f} KiB per copy, so bytes = FETCH_SIZE KiB x 1024 x "
+          f"{scale['FETCH_SIZE']:.3f} and WRITE_SIZE KiB x 1024 x {scale['WRITE_SIZE']:.3f}.", file=out)
+    print(f"\nPer step (timed pass, sum over the step's kernels): read {rd / 1e6:.1f} MB, written "
+          f"{wr / 1e6:.1f} MB, {(rd + wr) / 1e6:.1f} MB in all.\n", file=out)
+    print(f"kernel_hash: {kernel_source_hash()}", file=out)
+    print(f"window: {window}", file=out)
+    print(f"hbm_bytes_per_step: {rd + wr:.0f}", file=out)
+    return rd + wr
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -450,9 +504,22 @@ def main():
     ap.add_argument("--summarize", default=None, metavar="CSV",
                     help="print the timed window's per-kernel figures from a rocprofv3 CSV of a city run "
                          "(kernel trace or counter collection) made with the same --steps, then exit")
+    ap.add_argument("--traffic-report", default=None, metavar="DIR",
+                    help="print the counter-traffic summary from rocprofv3 counter runs under DIR "
+                         "(city_FETCH_SIZE/, city_WRITE_SIZE/, copy_FETCH_SIZE/, copy_WRITE_SIZE/) made with the "
+                         "same --steps and --from-step, then exit")
     ap.add_argument("--from-step", type=int, default=None,
                     help="city: first step of the timed window (default 5/8 of the horizon)")
     ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--gen-workers", type=int, default=None,
+                    help="city: processes that generate the routes (default: up to 16; fewer keeps a "
+                         "profiled run, whose children all hold the GPU, within the box's process limit)")
+    ap.add_argument("--workload-file", default=None, metavar="NPZ",
+                    help="city: load the generated workload from this file if it exists, else generate it "
+                         "and save it there")
+    ap.add_argument("--state-out", default=None, metavar="NPZ", help="city: save the state at --from-step")
+    ap.add_argument("--state-in", default=None, metavar="NPZ",
+                    help="city: start from a state saved by --state-out instead of stepping to --from-step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="city: skip the compact batched and served legs added to the line")
@@ -474,6 +541,11 @@ def main():
     ap.add_argument("--serve-mode", choices=["batched", "streams"], default="batched")
     ap.add_argument("--max-batches", type=int, default=3)
     args = ap.parse_args()
+    if args.traffic_report:
+        fs = args.from_step if args.from_step is not None else 4500
+        traffic_report(args.traffic_report, args.steps if args.steps is not None else 200,
+                       f"from_step={fs} steps={args.steps if args.steps is not None else 200}", args.copy_mib)
+        return
     if args.summarize:
         summarize_window(args.summarize, args.steps if args.steps is not None else 200)
         return
@@ -496,7 +568,13 @@ def run_city(args):
     from paper_2406_10661_amd import workloads as W
     from paper_2406_10661_amd.tsim import SCHEDULES
     t0 = time.time()
-    w = W.CONFIGS[args.config]()
+    if args.workload_file and os.path.exists(args.workload_file):
+        w = W.load_workload(args.workload_file)
+        log(f"[bench] loaded {args.workload_file}")
+    else:
+        w = W.CONFIGS[args.config](workers=args.gen_workers)
+        if args.workload_file:
+            W.save_workload(w, args.workload_file)
     log(f"[bench] workload {w.name}: {w.network.n_roads} roads, {w.network.n_lanes} lanes, "
         f"{w.trips.n_vehicles} vehicles, generated in {time.time() - t0:.1f} s")
     from_step = w.n_steps * 5 // 8 if args.from_step is None else args.from_step
@@ -504,6 +582,7 @@ def run_city(args):
     if from_step < 0 or steps < 1 or from_step + steps > w.n_steps:
         raise SystemExit(f"window [{from_step}, {from_step + steps}) outside the {w.n_steps}-step horizon")
 
+    import numpy as np
     import torch
     from paper_2406_10661_amd.tsim import Sim
     sim = Sim(w.network, w.trips, w.params)
@@ -511,17 +590,33 @@ def run_city(args):
     log(f"[bench] device arena {sim.arena.numel() / 2**30:.2f} GiB")
     # the loaded state: the run's own state at from_step, reached by stepping
     # from t = 0 outside the timed region (captured graphs unless disabled)
-    if args.graph_steps:
-        sim.set_graph_steps(args.graph_steps)
-    done = 0
-    while done < from_step:
-        n = min(1000, from_step - done)
-        sim.step(n)
-        torch.cuda.synchronize()
-        done += n
-        log(f"[bench] reached step {done}")
-    sim.set_graph_steps(0)
+    if args.state_in:
+        # a snapshot of the same run at from_step, written by --state-out
+        # (lets counter-collection runs, which serialise every dispatch,
+        # skip the thousands of steps that reach the loaded state)
+        with np.load(args.state_in, allow_pickle=False) as z:
+            st = {k: z[k] for k in z.files}
+        st["step"] = int(st["step"])
+        if st["step"] != from_step or st["status"].size != w.trips.n_vehicles:
+            raise SystemExit(f"{args.state_in}: snapshot of step {st['step']} with {st['status'].size} vehicles, "
+                             f"expected step {from_step} of {w.name}")
+        sim.set_state(st)
+        log(f"[bench] loaded the step-{from_step} snapshot {args.state_in}")
+    else:
+        if args.graph_steps:
+            sim.set_graph_steps(args.graph_steps)
+        done = 0
+        while done < from_step:
+            n = min(1000, from_step - done)
+            sim.step(n)
+            torch.cuda.synchronize()
+            done += n
+            log(f"[bench] reached step {done}")
+        sim.set_graph_steps(0)
     snap = sim.get_state()
+    if args.state_out:
+        np.savez(args.state_out, **snap)
+        log(f"[bench] wrote the step-{from_step} snapshot {args.state_out}")
     m_snap = sim.metrics()
     log(f"[bench] state at step {snap['step']}: {m_snap['n_active']} active, {m_snap['n_finished']} finished, "
         f"{m_snap['n_waiting']} waiting")

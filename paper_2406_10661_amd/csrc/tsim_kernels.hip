@@ -12,7 +12,7 @@
 //                     publishes the step.
 //   k_update_fused    (default) every size class in one launch, workgroup
 //                     ranges: huge tiles (a workgroup per tile, up to
-//                     kHugeCap vehicles in LDS, more on global scratch), wide
+//                     kFusedHugeCap vehicles in LDS, more on global scratch), wide
 //                     tiles (one per wavefront), medium, small and tiny tiles
 //                     (64 / W per wavefront, a group of W lanes per tile,
 //                     staged in LDS).  k_update_grouped / k_update_wide / k_update_block
@@ -574,7 +574,7 @@ struct LdsView {
     __device__ float mobil_lv(int j) const { return __int_as_float(S.pref[j]); }
 };
 
-// the same storage in global per-slot scratch, for tiles above kHugeCap
+// the same storage in global per-slot scratch, for tiles above the LDS cap
 template <class TS>
 struct GlobalView {
     TS& S;
@@ -883,143 +883,120 @@ struct Mobil {
     Lead lead;   // target-lane leader
 };
 
+// MOBIL for one side d (-1 left, +1 right) of vehicle j: utility (-inf when
+// the side is infeasible), prospective acceleration, and the target-lane
+// leader used as a bound
 template <class TS, class V>
-__device__ Mobil mobil_decide(const DevNet& D, const TS& S, const V& view, const LaneSum* rsum, int j, float rr,
+__device__ DirEval mobil_side(const DevNet& D, const TS& S, const V& view, const LaneSum* rsum, int j, int d,
                               const KParams& P)
 {
+    DirEval o;
+    o.u = -TS_INF;
+    o.ta = 0.0f;
+    o.lead.ex = false;
+    o.lead.a = TS_INF;
+    o.lead.b = 0.0f;
+    o.lead.v = 0.0f;
     const int nroad = S.nroad;
     const int li = view.lane(j);
+    if (li >= nroad) return o;
+    const int k = li + d;
+    if (k < 0 || k >= nroad) return o;
+    const uint32_t gmask = view.gmask(j);
+    const bool in_g = (gmask >> li) & 1u;
+    if (in_g) {
+        if (!((gmask >> k) & 1u)) return o;
+    } else if (!(group_dist(gmask, k, nroad) < group_dist(gmask, li, nroad))) {
+        return o;
+    }
     const int c = j - S.start[li];
     const VehRec rec = view.rec(j);
-    const bool is_jl = li >= nroad;
     const float len = S.len[li];
     const float lim = S.lim[li];
-    const float v0 = rec.f * lim;
     const float a_e = view.aown(j);
-    const uint32_t gmask = view.gmask(j);
     const int jqp = view.jq(j);
     const int my_mt = view.merge(j);
-    const bool in_g = !is_jl && ((gmask >> li) & 1u);
-    const int dist_l = (is_jl || in_g) ? 0 : group_dist(gmask, li, nroad);
-    // acceleration change of the old follower when this vehicle leaves
-    // (the same for both directions; computed on first use)
-    bool have_old = false;
-    float d_old_c = 0.0f;
-    // the vehicle's position in each side lane it may consider (both
-    // searches at once; eval_dir repeats the eligibility checks)
-    int posL = 0, posR = 0;
-    {
-        const bool okL = !is_jl && li >= 1 &&
-                         (in_g ? ((gmask >> (li - 1)) & 1u) != 0u : group_dist(gmask, li - 1, nroad) < dist_l);
-        const bool okR = !is_jl && li + 1 < nroad &&
-                         (in_g ? ((gmask >> (li + 1)) & 1u) != 0u : group_dist(gmask, li + 1, nroad) < dist_l);
-        count_ahead2(S, view, okL ? li - 1 : -1, rec.x, rec.vid, posL, okR ? li + 1 : -1, rec.x, rec.vid, posR);
+    // the vehicle's position among the target lane's vehicles
+    int pos = 0, unused = 0;
+    count_ahead2(S, view, k, rec.x, rec.vid, pos, -1, 0.0f, 0, unused);
+    const int tl = pos > 0 ? S.start[k] + pos - 1 : -1;
+    const int tf = pos < S.cnt[k] ? S.start[k] + pos : -1;
+    VehRec tlr{}, tfr{};
+    if (tl >= 0) tlr = view.rec(tl);
+    if (tf >= 0) tfr = view.rec(tf);
+    // same gap of k held by a vehicle two lanes right (rightward only)
+    if (d > 0 && k + 1 < nroad) {
+        int lo2 = 0, hi2 = S.cnt[k + 1];
+        count_ahead2(S, view, tl >= 0 ? k + 1 : -1, tlr.x, tlr.vid, lo2, tf >= 0 ? k + 1 : -1, tfr.x, tfr.vid, hi2);
+        if (lo2 < hi2) return o;
     }
-    // MOBIL for one direction: utility (or -inf), prospective
-    // acceleration, and the target-lane leader used as a bound
-    auto eval_dir = [&](int d) -> DirEval {
-        DirEval o;
-        o.u = -TS_INF;
-        o.ta = 0.0f;
-        o.lead.ex = false;
-        o.lead.a = TS_INF;
-        o.lead.b = 0.0f;
-        o.lead.v = 0.0f;
-        if (is_jl) return o;
-        const int k = li + d;
-        if (k < 0 || k >= nroad) return o;
-        if (in_g) {
-            if (!((gmask >> k) & 1u)) return o;
-        } else if (!(group_dist(gmask, k, nroad) < dist_l)) {
-            return o;
+    Lead tld;
+    if (tl >= 0) {
+        tld.ex = true;
+        tld.a = tlr.x;
+        tld.b = -tlr.len;
+        tld.v = tlr.v;
+    } else {
+        tld = lookahead(D, S, view, rsum, k, jq_get(jqp, d), rec.rp, rec.rem);
+    }
+    const float g3 = tld.ex ? lead_gap(tld, rec.x) : TS_INF;
+    if (!(g3 > 0.0f)) return o;
+    const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
+    if (tf >= 0 && !tf_yields) {
+        const float g4 = ((rec.x - tfr.x) - rec.len) - (tfr.v * P.dt + P.reach);
+        if (!(g4 >= 0.0f)) return o;
+    }
+    if (tf < 0) {
+        // no follower in the target lane: the lane's feeders must not reach
+        // past the changer's rear (largest reach decides)
+        const int fm = S.fmx[k];
+        if (fm != kNoFeeder) {
+            const float g = (rec.x - rec.len) - o2f(fm);
+            if (!(g >= 0.0f)) return o;
         }
-        const int pos = d < 0 ? posL : posR;
-        const int tl = pos > 0 ? S.start[k] + pos - 1 : -1;
-        const int tf = pos < S.cnt[k] ? S.start[k] + pos : -1;
-        VehRec tlr{}, tfr{};
-        if (tl >= 0) tlr = view.rec(tl);
-        if (tf >= 0) tfr = view.rec(tf);
-        // same gap of k held by a vehicle two lanes right (rightward only)
-        if (d > 0 && k + 1 < nroad) {
-            int lo2 = 0, hi2 = S.cnt[k + 1];
-            count_ahead2(S, view, tl >= 0 ? k + 1 : -1, tlr.x, tlr.vid, lo2, tf >= 0 ? k + 1 : -1, tfr.x, tfr.vid,
-                         hi2);
-            if (lo2 < hi2) return o;
-        }
-        Lead tld;
-        if (tl >= 0) {
-            tld.ex = true;
-            tld.a = tlr.x;
-            tld.b = -tlr.len;
-            tld.v = tlr.v;
+    }
+    // desired speeds in lane k from k's own limit (lanes of a road may have
+    // different limits)
+    const float lim_k = S.lim[k];
+    const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false), len, P);
+    float d_new = 0.0f, d_old = 0.0f;
+    if (tf >= 0) {
+        const float a_tf = view.aown(tf);
+        const Lead me_lead{rec.x, -rec.len, rec.v, true};
+        const float ta_tf = accel(tfr.v, tfr.f * lim_k, tfr.x, me_lead, view.stopf(tf), len, P);
+        if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
+        d_new = ta_tf - a_tf;
+    }
+    if (c + 1 < S.cnt[li]) {
+        // acceleration change of the old follower when this vehicle leaves
+        const VehRec ofr = view.rec(j + 1);
+        const float a_of = view.aown(j + 1);
+        Lead ol;
+        if (c > 0) {
+            const VehRec z = view.rec(j - 1);
+            ol.ex = true;
+            ol.a = z.x;
+            ol.b = -z.len;
+            ol.v = z.v;
         } else {
-            tld = lookahead(D, S, view, rsum, k, jq_get(jqp, d), rec.rp, rec.rem);
+            ol = lookahead(D, S, view, rsum, li, jq_get(view.jq(j + 1), 0), ofr.rp, ofr.rem);
         }
-        const float g3 = tld.ex ? lead_gap(tld, rec.x) : TS_INF;
-        if (!(g3 > 0.0f)) return o;
-        const bool tf_yields = tf >= 0 && my_mt == k && (rec.x - rec.len > tfr.x);
-        if (tf >= 0 && !tf_yields) {
-            const float g4 = ((rec.x - tfr.x) - rec.len) - (tfr.v * P.dt + P.reach);
-            if (!(g4 >= 0.0f)) return o;
-        }
-        if (tf < 0) {
-            // no follower in the target lane: the lane's feeders must not
-            // reach past the changer's rear (largest reach decides)
-            const int fm = S.fmx[k];
-            if (fm != kNoFeeder) {
-                const float g = (rec.x - rec.len) - o2f(fm);
-                if (!(g >= 0.0f)) return o;
-            }
-        }
-        // desired speeds in lane k from k's own limit (lanes of a road may
-        // have different limits)
-        const float lim_k = S.lim[k];
-        const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false),
-                                 len, P);
-        float d_new = 0.0f, d_old = 0.0f;
-        if (tf >= 0) {
-            const float a_tf = view.aown(tf);
-            const Lead me_lead{rec.x, -rec.len, rec.v, true};
-            const float ta_tf = accel(tfr.v, tfr.f * lim_k, tfr.x, me_lead, view.stopf(tf), len, P);
-            if (!tf_yields && !(ta_tf + P.b_safe >= 0.0f)) return o;
-            d_new = ta_tf - a_tf;
-        }
-        if (c + 1 < S.cnt[li]) {
-            if (!have_old) {
-                const VehRec ofr = view.rec(j + 1);
-                const float a_of = view.aown(j + 1);
-                Lead ol;
-                if (c > 0) {
-                    const VehRec z = view.rec(j - 1);
-                    ol.ex = true;
-                    ol.a = z.x;
-                    ol.b = -z.len;
-                    ol.v = z.v;
-                } else {
-                    ol = lookahead(D, S, view, rsum, li, jq_get(view.jq(j + 1), 0), ofr.rp, ofr.rem);
-                }
-                const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, view.stopf(j + 1), len, P);
-                d_old_c = ta_of - a_of;
-                have_old = true;
-            }
-            d_old = d_old_c;
-        }
-        const float da = (ta_e - a_e) + P.p * (d_new + d_old);
-        float ud = da - P.a_th;
-        if (!in_g) ud = fmaxf(ud, 1.0f);
-        o.u = ud;
-        o.ta = ta_e;
-        o.lead = tld;
-        return o;
-    };
-    DirEval eL, eR;
-#pragma unroll 1
-    for (int di = 0; di < 2; ++di) {
-        const DirEval e = eval_dir(di ? 1 : -1);
-        if (di) eR = e;
-        else eL = e;
+        const float ta_of = accel(ofr.v, ofr.f * lim, ofr.x, ol, view.stopf(j + 1), len, P);
+        d_old = ta_of - a_of;
     }
-    // randomized decision (the draw only matters when a side is feasible)
+    const float da = (ta_e - a_e) + P.p * (d_new + d_old);
+    float ud = da - P.a_th;
+    if (!in_g) ud = fmaxf(ud, 1.0f);
+    o.u = ud;
+    o.ta = ta_e;
+    o.lead = tld;
+    return o;
+}
+
+// randomized decision from both sides' evaluations and the draw rr (the
+// draw only matters when a side is feasible)
+__device__ __forceinline__ Mobil mobil_choose(const DirEval& eL, const DirEval& eR, float rr, const KParams& P)
+{
     const float uLp = fmaxf(0.0f, eL.u), uRp = fmaxf(0.0f, eR.u);
     const float uT = uLp + uRp;
     const float pLC = uT >= 1.0f ? P.p_max : (uT > 0.0f ? P.p_min + (P.p_max - P.p_min) * uT : P.p_min);
@@ -1042,6 +1019,20 @@ __device__ Mobil mobil_decide(const DevNet& D, const TS& S, const V& view, const
     m.ta = dec == 1 ? eL.ta : eR.ta;
     m.lead = dec == 1 ? eL.lead : eR.lead;
     return m;
+}
+
+template <class TS, class V>
+__device__ Mobil mobil_decide(const DevNet& D, const TS& S, const V& view, const LaneSum* rsum, int j, float rr,
+                              const KParams& P)
+{
+    DirEval eL, eR;
+#pragma unroll 1
+    for (int di = 0; di < 2; ++di) {
+        const DirEval e = mobil_side(D, S, view, rsum, j, di ? 1 : -1, P);
+        if (di) eR = e;
+        else eL = e;
+    }
+    return mobil_choose(eL, eR, rr, P);
 }
 
 // passes 1 and 2 of one tile (see process_tile)
@@ -1130,7 +1121,8 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
     // candidates are gathered for tiles staged in LDS (the same for every
     // tile of a wavefront: groups only hold tiles of at most kCap vehicles)
     bool compact = false;
-    if constexpr (GW <= kWave) compact = n <= TS::kCap;
+    // (candidate indices are listed as bytes in the changer list)
+    if constexpr (GW <= kWave) compact = n <= TS::kCap && n <= 4 * TS::kChg && n <= 256;
     for (int j = gt; j < n; j += GW) {
         const int li = view.lane(j);
         const VehRec rec = view.rec(j);
@@ -1158,7 +1150,6 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         }
     }
     if constexpr (GW <= kWave) if (compact) {
-        static_assert(TS::kCap <= 4 * TS::kChg, "a tile's candidates fit its changer list");
         constexpr int NG = kWave / GW;
         wave_sync();
         TS* const S0 = &S - (int)(__lane_id() / GW);   // the wavefront's tiles are consecutive
@@ -1169,20 +1160,47 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             pre[g] = tot;
             tot += S0[g].ncand;
         }
-        for (int e = (int)__lane_id(); e < tot; e += kWave) {
-            if constexpr (NG == 1) {
-                const int j = ((const unsigned char*)S.chg_vid)[e];
-                const Mobil m = mobil_decide(D, S, view, rsum, j, view.mobil_ta(j), P);
-                view.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
-            } else {
-                // several tiles per wavefront: always staged in LDS
-                int g = NG - 1;
-                while (e < pre[g]) g--;
-                TS& Sg = S0[g];
-                LdsView<TS> vg{Sg};
-                const int j = ((const unsigned char*)Sg.chg_vid)[e - pre[g]];
-                const Mobil m = mobil_decide(D, Sg, vg, rsum, j, vg.mobil_ta(j), P);
-                vg.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
+        // two lanes per candidate, one side each (lane 2e left, 2e + 1
+        // right); the left lane combines both and decides
+        for (int b2 = 0; b2 < 2 * tot; b2 += kWave) {
+            const int e2 = b2 + (int)__lane_id();
+            const bool act = e2 < 2 * tot;
+            const int e = e2 >> 1;
+            const int d = (e2 & 1) ? 1 : -1;
+            DirEval r;
+            r.u = -TS_INF;
+            r.ta = 0.0f;
+            r.lead = Lead{TS_INF, 0.0f, 0.0f, false};
+            int g = 0, j = 0;
+            if (act) {
+                if constexpr (NG == 1) {
+                    j = ((const unsigned char*)S.chg_vid)[e];
+                    r = mobil_side(D, S, view, rsum, j, d, P);
+                } else {
+                    // several tiles per wavefront: always staged in LDS
+                    g = NG - 1;
+                    while (e < pre[g]) g--;
+                    const TS& Sg = S0[g];
+                    j = ((const unsigned char*)Sg.chg_vid)[e - pre[g]];
+                    r = mobil_side(D, Sg, LdsView<TS>{S0[g]}, rsum, j, d, P);
+                }
+            }
+            DirEval q;
+            q.u = __shfl_xor(r.u, 1);
+            q.ta = __shfl_xor(r.ta, 1);
+            q.lead.a = __shfl_xor(r.lead.a, 1);
+            q.lead.b = __shfl_xor(r.lead.b, 1);
+            q.lead.v = __shfl_xor(r.lead.v, 1);
+            q.lead.ex = __shfl_xor((int)r.lead.ex, 1) != 0;
+            if (act && d < 0) {
+                if constexpr (NG == 1) {
+                    const Mobil m = mobil_choose(r, q, view.mobil_ta(j), P);
+                    view.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
+                } else {
+                    LdsView<TS> vg{S0[g]};
+                    const Mobil m = mobil_choose(r, q, vg.mobil_ta(j), P);
+                    vg.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
+                }
             }
         }
         wave_sync();
@@ -1915,68 +1933,70 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_grouped(const DevNet D, 
 
 constexpr int kWideWaves = 2;   // wavefronts per wide-pass workgroup
 
-// Wide pass: the step's wide-tile list, one tile per wavefront; up to
-// kWideCap vehicles staged in LDS, more on global scratch.  Part slots follow
-// the grouped pass's (offset a_wg).
+// Wide pass: one tile of a list per wavefront, its vehicles staged in LDS up
+// to CAP (more: global scratch); the first WPB wavefronts of the workgroup
+// work, any others only meet the final barrier.  Part slots follow the
+// grouped pass's (offset a_wg).
 template <int LANES, int CAP, int WPB, int LIST>
-__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg)
+__device__ __forceinline__ void wide_pass(const DevNet& D, int a_wg, int blk, int nblk,
+                                          TileLds<LANES, CAP, kChangerCap>* Sw, WGPartial* wacc)
 {
     using TS = TileLds<LANES, CAP, kChangerCap>;
-    __shared__ TS Sw[WPB];
-    __shared__ WGPartial wacc[WPB];
     const long long tg = *D.ustep;
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
-    TS& S = Sw[w];
     const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
 
     WGPartial acc{};
     int acc_inst = -1;
-    for (int k = (int)blockIdx.x * WPB + w; k < count; k += (int)gridDim.x * WPB) {
-        const Hdr h = load_hdr(D, B, list[k]);
-        const long long t = tg - D.inst_t0[h.inst];
-        const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
-        if (tid == 0) reset_counters(S, h);
-        wave_sync();
-        {
-            int c = tid < h.nl ? S.cnt[tid] : 0;
+    if (w < WPB) {
+        TS& S = Sw[w];
+        for (int k = blk * WPB + w; k < count; k += nblk * WPB) {
+            const Hdr h = load_hdr(D, B, list[k]);
+            const long long t = tg - D.inst_t0[h.inst];
+            const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
+            if (tid == 0) reset_counters(S, h);
+            wave_sync();
+            {
+                int c = tid < h.nl ? S.cnt[tid] : 0;
 #pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const int y = __shfl_up(c, off);
-                if (tid >= off) c += y;
-            }
-            if (tid < h.nl) S.start[tid + 1] = c;
-            if (tid == 0) S.start[0] = 0;
-            if (tid == kWave - 1) S.n = c;
-        }
-        wave_sync();
-        const int n = S.n;
-        load_lanes_b(D, B, S, h, tid, lr);
-        if (n <= CAP) {
-            for (int j = tid; j < n; j += kWave) {
-                const int li = lane_of(S, j);
-                S.vl[j] = (signed char)li;
-                S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int y = __shfl_up(c, off);
+                    if (tid >= off) c += y;
+                }
+                if (tid < h.nl) S.start[tid + 1] = c;
+                if (tid == 0) S.start[0] = 0;
+                if (tid == kWave - 1) S.n = c;
             }
             wave_sync();
-            LdsView<TS> view{S};
-            process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
-        } else {
+            const int n = S.n;
+            load_lanes_b(D, B, S, h, tid, lr);
+            if (n <= CAP) {
+                for (int j = tid; j < n; j += kWave) {
+                    const int li = lane_of(S, j);
+                    S.vl[j] = (signed char)li;
+                    S.rec[j] = B.rd[S.base[li] + (j - S.start[li])];
+                }
+                wave_sync();
+                LdsView<TS> view{S};
+                process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
+            } else {
+                wave_sync();
+                GlobalView<TS> view{S, D, B.rd};
+                process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
+            }
             wave_sync();
-            GlobalView<TS> view{S, D, B.rd};
-            process_tile<kWave>(D, S, view, B, t, h.inst, tid, 0, n);
+            if (tid == 0 && D.n_inst > 1 && h.inst != acc_inst) {
+                flush_acc(D, acc, acc_inst);
+                acc_inst = h.inst;
+            }
+            finish_tile<kWave>(D, B, S, h, tid, n, acc);
+            wave_sync();
         }
-        wave_sync();
-        if (tid == 0 && D.n_inst > 1 && h.inst != acc_inst) {
-            flush_acc(D, acc, acc_inst);
-            acc_inst = h.inst;
-        }
-        finish_tile<kWave>(D, B, S, h, tid, n, acc);
-        wave_sync();
+        if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
+        if (tid == 0) wacc[w] = acc;
     }
-    if (D.n_inst > 1 && tid == 0) flush_acc(D, acc, acc_inst);
-    if (tid == 0) wacc[w] = acc;
     __syncthreads();
     WGPartial tot{};
     if (threadIdx.x == 0) {
@@ -1986,7 +2006,16 @@ __global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int
             for (int k = 0; k < kPartWords; ++k) a[k] += b[k];
         }
     }
-    finish_step(D, tot, a_wg + (int)blockIdx.x, tg);
+    finish_step(D, tot, a_wg + blk, tg);
+}
+
+template <int LANES, int CAP, int WPB, int LIST>
+__global__ __launch_bounds__(kWave * WPB) void k_update_wide(const DevNet D, int a_wg)
+{
+    using TS = TileLds<LANES, CAP, kChangerCap>;
+    __shared__ TS Sw[WPB];
+    __shared__ WGPartial wacc[WPB];
+    wide_pass<LANES, CAP, WPB, LIST>(D, a_wg, (int)blockIdx.x, (int)gridDim.x, Sw, wacc);
 }
 
 constexpr int kHugeThreads = 256;   // threads working together on one huge tile
@@ -2069,14 +2098,20 @@ __global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
 // strides over its own list, the LDS of each range is carved from one
 // dynamic allocation, and the workgroups of later ranges start as earlier
 // ones finish (no launches or stream joins between the passes).
-using FusedHuge = TileLds<kMaxTileLanes, kHugeCap, kChangerCap>;
 using FusedWide = GroupedLds<kWave, kWideCap, kChangerCap, 4, kWideLanes>;
 using FusedMed = GroupedLds<32, kMedCap, 32, 4, kWideLanes>;
 using FusedSmall = GroupedLds<16, 32, 16, 4, 16>;
 using FusedTiny = GroupedLds<8, 16, 8, 4, 8>;
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kFusedLds =
-    cmax(cmax(cmax(sizeof(FusedHuge), sizeof(FusedWide)), cmax(sizeof(FusedSmall), sizeof(FusedTiny))), sizeof(FusedMed));
+constexpr size_t kFusedGroupedLds =
+    cmax(cmax(sizeof(FusedWide), sizeof(FusedMed)), cmax(sizeof(FusedSmall), sizeof(FusedTiny)));
+// the huge range stages up to kFusedHugeCap vehicles in LDS: the grouped
+// ranges set the launch's LDS size, and a huge tile uses all of it (a tile
+// above the cap works on global scratch, much slower)
+constexpr int kFusedHugeCap = 1024;
+using FusedHuge = TileLds<kMaxTileLanes, kFusedHugeCap, kChangerCap>;
+static_assert(sizeof(FusedHuge) <= kFusedGroupedLds, "the huge range fits the grouped ranges' LDS");
+constexpr size_t kFusedLds = cmax(sizeof(FusedHuge), kFusedGroupedLds);
 constexpr int kFusedThreads = 4 * kWave;
 static_assert(kHugeThreads == kFusedThreads, "one workgroup size for every range");
 
@@ -2085,8 +2120,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_update_fused(const DevNet D)
     extern __shared__ __align__(16) char fused_lds[];
     int b = (int)blockIdx.x;
     if (b < D.GC) {
-        block_pass<kMaxTileLanes, kHugeCap, kHugeThreads, 2>(D, D.GA + D.GB, b, D.GC,
-                                                            *reinterpret_cast<FusedHuge*>(fused_lds));
+        block_pass<kMaxTileLanes, kFusedHugeCap, kHugeThreads, 2>(D, D.GA + D.GB, b, D.GC,
+                                                                *reinterpret_cast<FusedHuge*>(fused_lds));
         return;
     }
     b -= D.GC;

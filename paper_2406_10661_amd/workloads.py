@@ -133,6 +133,31 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
 
+def save_workload(w: Workload, path):
+    """Writes a generated workload (network, trips, parameters, horizon) to
+    an .npz file of plain arrays, so that a later process can load it in
+    seconds instead of generating it again."""
+    from dataclasses import asdict, fields
+    arrs = {"name": np.array(w.name), "n_steps": np.array(w.n_steps, np.int64)}
+    for f in fields(Network):
+        arrs["network." + f.name] = getattr(w.network, f.name)
+    for f in fields(Trips):
+        arrs["trips." + f.name] = getattr(w.trips, f.name)
+    for k, v in asdict(w.params).items():
+        arrs["params." + k] = np.array(v)
+    np.savez(path, **arrs)
+
+
+def load_workload(path) -> Workload:
+    """Reads a workload written by save_workload (plain arrays only)."""
+    from dataclasses import fields
+    with np.load(path, allow_pickle=False) as z:
+        net = Network(**{f.name: z["network." + f.name] for f in fields(Network)})
+        trips = Trips(**{f.name: z["trips." + f.name] for f in fields(Trips)})
+        params = Params(**{f.name: type(f.default)(z["params." + f.name][()]) for f in fields(Params)})
+        return Workload(str(z["name"][()]), net, trips, params, int(z["n_steps"][()]))
+
+
 # --------------------------------------------------------------------------
 # network construction
 # --------------------------------------------------------------------------
@@ -432,14 +457,14 @@ def uniform_od(net, rng, n):
 # the five workloads
 # --------------------------------------------------------------------------
 
-def config1(seed=0):
+def config1(seed=0, workers=None):
     """4x4 signalised grid, 200 m roads, 2 lanes per direction, 13.9 m/s;
     1,000 vehicles, uniform O!=D roads, departures U(0,300) s; 600 steps."""
     rng = np.random.default_rng(seed)
     net = grid_network(4)
     o, d = uniform_od(net, rng, 1000)
     dep = rng.uniform(0.0, 300.0, 1000)
-    trips = _finish_trips(net, rng, o, d, dep)
+    trips = _finish_trips(net, rng, o, d, dep, workers=workers)
     return Workload("grid4x4_1k", net, trips, Params(seed=seed), 600)
 
 
@@ -448,14 +473,14 @@ def jittered_grid(n, rng, phase_range=None):
                         phase_range=phase_range)
 
 
-def config2(seed=1):
+def config2(seed=1, workers=None):
     """32x32 jittered grid (+-20 m), lengths U(150,400) m, 1-4 lanes, limits
     {11.1,13.9,16.7}; 100,000 vehicles, departures U(0,1800) s; 3,600 steps."""
     rng = np.random.default_rng(seed)
     net = jittered_grid(32, rng)
     o, d = uniform_od(net, rng, 100_000)
     dep = rng.uniform(0.0, 1800.0, 100_000)
-    trips = _finish_trips(net, rng, o, d, dep)
+    trips = _finish_trips(net, rng, o, d, dep, workers=workers)
     return Workload("grid32x32_100k", net, trips, Params(seed=seed), 3600)
 
 
@@ -481,7 +506,7 @@ def city_trips(net, rng, n, pool=1024, trip_median=6000.0, trip_sigma=0.5):
     return o, d
 
 
-def config3(seed=2, n_junctions=50_000, n_vehicles=2_464_950):
+def config3(seed=2, n_junctions=50_000, n_vehicles=2_464_950, workers=None):
     """Synthetic city at the paper's largest scale: ~50,000 junctions,
     planar Delaunay-style topology, 2,464,950 vehicles, departures
     N(3600 s, 1200 s) clipped to [0, 7200); 7,200 steps."""
@@ -489,7 +514,7 @@ def config3(seed=2, n_junctions=50_000, n_vehicles=2_464_950):
     net = city_network(n_junctions, rng)
     o, d = city_trips(net, rng, n_vehicles)
     dep = np.clip(rng.normal(3600.0, 1200.0, n_vehicles), 0.0, np.nextafter(7200.0, 0))
-    trips = _finish_trips(net, rng, o, d, dep)
+    trips = _finish_trips(net, rng, o, d, dep, workers=workers)
     return Workload("city50k_2464950", net, trips, Params(seed=seed), 7200)
 
 

@@ -14,7 +14,7 @@ import pytest
 
 from paper_2406_10661_amd import workloads as W
 from tests.parity import compare_one_step
-from tests.synthstate import synthetic_state
+from paper_2406_10661_amd.workloads import synthetic_state
 from tests import simcheck as S
 
 pytestmark = pytest.mark.gpu

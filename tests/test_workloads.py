@@ -75,3 +75,20 @@ def test_generators_deterministic():
     a, b = W.config1(), W.config1()
     assert np.array_equal(a.trips.route_roads, b.trips.route_roads)
     assert np.array_equal(a.trips.v0_factor, b.trips.v0_factor)
+
+
+def test_workload_file_roundtrip(tmp_path):
+    """A workload saved to .npz loads back field for field (plain arrays, no
+    pickles), with its parameters, name and horizon."""
+    from dataclasses import fields
+    w = W.config1()
+    p = tmp_path / "w.npz"
+    W.save_workload(w, p)
+    v = W.load_workload(p)
+    assert (v.name, v.n_steps, v.params) == (w.name, w.n_steps, w.params)
+    for f in fields(W.Network):
+        a, b = getattr(w.network, f.name), getattr(v.network, f.name)
+        assert a.dtype == b.dtype and np.array_equal(a, b), f.name
+    for f in fields(W.Trips):
+        a, b = getattr(w.trips, f.name), getattr(v.trips, f.name)
+        assert a.dtype == b.dtype and np.array_equal(a, b), f.name
