@@ -100,14 +100,14 @@ int tile_class(const Build& B, int r)
 // with few enough lanes), the wide pass over at most R; each gets no more
 // workgroups than the device keeps resident (res_a, res_b; 0 = unknown)
 struct SchedGrid {
-    int gw, nA, GA, GB, GC, GT, GM;
+    int gw, nA, GA, GB, GC, GT, GM, GL;
 };
 
 constexpr int kMaxGridA = 8192, kMaxGridB = 8192;
 
 SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, int res_c = 0, int res_t = 0)
 {
-    SchedGrid g{64, 0, 0, 0, 0, 0, 0};
+    SchedGrid g{64, 0, 0, 0, 0, 0, 0, 0};
     switch (sched) {
     case kSched8x16: g.gw = 8; g.nA = B.n_le[0]; break;
     case kSched16x32:
@@ -134,6 +134,11 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
         const int capM = res_t > 0 ? std::min(res_t, kMaxGridA) : kMaxGridA;
         g.GM = std::max(1, std::min((B.n_le[2] + 1) / 2, capM));
     }
+    // large tiles (fused schedule): one per wavefront, three per workgroup
+    if (sched == kSchedFused) {
+        const int capL = res_c > 0 ? std::min(res_c, kMaxGridB) : kMaxGridB;
+        g.GL = std::max(1, std::min((B.R + 2) / 3, capL));
+    }
     return g;
 }
 
@@ -149,7 +154,7 @@ void count_tiles(Build& B)
     B.G = 1;
     for (int s = 0; s < kNumSched; ++s) {
         const SchedGrid g = sched_grid(B, s);
-        B.G = std::max(B.G, g.GA + g.GB + g.GC + g.GT + g.GM);
+        B.G = std::max(B.G, g.GA + g.GB + g.GC + g.GT + g.GM + g.GL);
     }
 }
 
@@ -162,7 +167,7 @@ long long g_bound(int R)
     long long G = 1;
     for (int s = 0; s < kNumSched; ++s) {
         const SchedGrid g = sched_grid(f, s, 0, 0, 0, 0);
-        G = std::max<long long>(G, g.GA + g.GB + g.GC + g.GT + g.GM);
+        G = std::max<long long>(G, g.GA + g.GB + g.GC + g.GT + g.GM + g.GL);
     }
     return G;
 }
@@ -708,6 +713,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.list_huge, std::max<size_t>(R, 1) * 4);
     add(&D.list_tiny, std::max<size_t>(R, 1) * 4);
     add(&D.list_med, std::max<size_t>(R, 1) * 4);
+    add(&D.list_large, std::max<size_t>(R, 1) * 4);
     add(&D.list_cnt, 2 * kNumLists * kCntStride * 4);
     add(&D.part, (size_t)std::max<long long>(c.G, 1) * sizeof(WGPartial));
     add(&D.ustep, 8);
@@ -1045,6 +1051,7 @@ static void set_sched(tsim_handle* h, int sched)
     h->D.GC = g.GC;
     h->D.GT = g.GT;
     h->D.GM = g.GM;
+    h->D.GL = g.GL;
 }
 
 int tsim_create(const tsim_network* net, const tsim_trips* trips, const tsim_params* params, void* hip_stream,

@@ -47,8 +47,10 @@ enum Schedule {
     kNumSched = 8
 };
 constexpr int kCntStride = 32;           // work-list counters one 128-byte line apart
-constexpr int kNumLists = 5;             // small, wide, huge, tiny, medium
+constexpr int kNumLists = 6;             // small, wide, huge, tiny, medium, large
 constexpr int kMedCap = 64;              // medium tiles (fused schedule): at most kWideLanes lanes and 64 vehicles
+constexpr int kLargeCap = 256;           // large tiles (fused schedule): above the wide list, at most 256 vehicles
+constexpr int kLargeLanes = 48;          // and at most 48 lanes
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
 constexpr int kWaitSpeedFlag = 0;
@@ -277,9 +279,10 @@ struct DevNet {
     int32_t* list_huge;              // [R] the rest
     int32_t* list_tiny;              // [R] tiles for the narrowest groups (two-width schedules)
     int32_t* list_med;               // [R] tiles of at most kWideLanes lanes and kMedCap vehicles (fused schedule)
+    int32_t* list_large;             // [R] tiles above the wide list with at most kLargeLanes lanes and kLargeCap vehicles (fused schedule)
     int32_t* list_cnt;               // [2][kNumLists kCntStride] by step parity (one 128-byte line each)
     // schedule (host side; passed to the kernels as arguments)
-    int32_t sched, GA, GB, GC, GT, GM;   // GT, GM: workgroups of the tiny and medium passes
+    int32_t sched, GA, GB, GC, GT, GM, GL;   // GT, GM, GL: workgroups of the tiny, medium and large passes
     int32_t mp_any;                  // host side: some junction may use MAX_PRESSURE (k_signals is launched)
     // metrics
     float* road_speed;               // [R] mean speed of the last step, -1 empty

@@ -345,6 +345,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         else if (nl <= small_lanes && n <= small_cap) out.list = 0;
         else if (D.sched == kSchedFused && nl <= kWideLanes && n <= kMedCap) out.list = 4;
         else if (nl <= kWideLanes && n <= kWideCap) out.list = 1;
+        else if (D.sched == kSchedFused && nl <= kLargeLanes && n <= kLargeCap) out.list = 5;
         else out.list = 2;
     }
     if (n == 0 && n_w != 0) {
@@ -427,7 +428,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
                         : L == 1 ? D.list_big
                         : L == 2 ? D.list_huge
                         : L == 3 ? D.list_tiny
-                                 : D.list_med;
+                        : L == 4 ? D.list_med
+                                 : D.list_large;
         list[off] = o.r;
     }
     if (!one && o.r >= 0) {
@@ -1737,10 +1739,20 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
     // the WPB wavefronts of a workgroup work independently (each its own
     // groups and tiles); they meet only to combine their partial sums
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
+    if (w >= WPB) {
+        // a workgroup larger than the pass (fused launch): the extra
+        // wavefronts only meet the final barrier
+        __syncthreads();
+        return;
+    }
     const int g = tid / GW, gt = tid % GW, gbase = g * GW;
     TS& S = Sg[w * NG + g];
     const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
-    const int32_t* const list = LIST == 0 ? D.list_small : (LIST == 1 ? D.list_big : (LIST == 3 ? D.list_tiny : D.list_med));
+    const int32_t* const list = LIST == 0   ? D.list_small
+                                : LIST == 1 ? D.list_big
+                                : LIST == 3 ? D.list_tiny
+                                : LIST == 4 ? D.list_med
+                                            : D.list_large;
     const int first = (blk * WPB + w) * NG;
     const int stride = nblk * WPB * NG;
     const int rounds = count > first ? (count - first + stride - 1) / stride : 0;
@@ -1946,7 +1958,7 @@ __device__ __forceinline__ void wide_pass(const DevNet& D, int a_wg, int blk, in
     const StepBufs B = step_bufs(D, tg);
     const int w = (int)threadIdx.x / kWave, tid = (int)threadIdx.x % kWave;
     const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
-    const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
+    const int32_t* list = LIST == 1 ? D.list_big : (LIST == 5 ? D.list_large : D.list_huge);
 
     WGPartial acc{};
     int acc_inst = -1;
@@ -2034,7 +2046,7 @@ __device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, i
     const StepBufs B = step_bufs(D, tg);
     const int tid = (int)threadIdx.x;
     const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
-    const int32_t* list = LIST == 1 ? D.list_big : D.list_huge;
+    const int32_t* list = LIST == 1 ? D.list_big : (LIST == 5 ? D.list_large : D.list_huge);
 
     WGPartial acc{};
     int acc_inst = -1;
@@ -2092,7 +2104,8 @@ __global__ __launch_bounds__(TPB) void k_update_block(const DevNet D, int a_wg)
 }
 
 // All update passes of a step in one launch (fused schedule): workgroups
-// [0, GC) take the huge tiles, then GB the wide ones (one per wavefront, four
+// [0, GC) take the huge tiles, then GL the large ones (one per wavefront,
+// three wavefronts per workgroup), GB the wide ones (one per wavefront, four
 // wavefronts per workgroup), GM the medium ones (two per wavefront), GA the
 // small and GT the tiny ones; each range
 // strides over its own list, the LDS of each range is carved from one
@@ -2111,6 +2124,11 @@ constexpr size_t kFusedGroupedLds =
 constexpr int kFusedHugeCap = 1024;
 using FusedHuge = TileLds<kMaxTileLanes, kFusedHugeCap, kChangerCap>;
 static_assert(sizeof(FusedHuge) <= kFusedGroupedLds, "the huge range fits the grouped ranges' LDS");
+// the large range: one tile per wavefront (software-pipelined like the
+// grouped ones), three wavefronts per workgroup
+constexpr int kFusedLargeWaves = 3;
+using FusedLarge = GroupedLds<kWave, kLargeCap, kChangerCap, kFusedLargeWaves, kLargeLanes>;
+static_assert(sizeof(FusedLarge) <= kFusedGroupedLds, "the large range fits the grouped ranges' LDS");
 constexpr size_t kFusedLds = cmax(sizeof(FusedHuge), kFusedGroupedLds);
 constexpr int kFusedThreads = 4 * kWave;
 static_assert(kHugeThreads == kFusedThreads, "one workgroup size for every range");
@@ -2125,6 +2143,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_update_fused(const DevNet D)
         return;
     }
     b -= D.GC;
+    if (b < D.GL) {
+        grouped_pass<kWave, kLargeCap, kChangerCap, kFusedLargeWaves, kLargeLanes, 5>(
+            D, D.GA + D.GB + D.GC + D.GT + D.GM, b, D.GL, *reinterpret_cast<FusedLarge*>(fused_lds));
+        return;
+    }
+    b -= D.GL;
     if (b < D.GB) {
         grouped_pass<kWave, kWideCap, kChangerCap, 4, kWideLanes, 1>(D, D.GA, b, D.GB,
                                                                      *reinterpret_cast<FusedWide*>(fused_lds));
@@ -2383,13 +2407,13 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     default: break;
     }
     hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap,
-                       tl, tc, H.GT + H.GA + H.GB + H.GC + H.GM);
+                       tl, tc, H.GT + H.GA + H.GB + H.GC + H.GM + H.GL);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const DevNet* Dd, const DevNet& H, hipStream_t s, const PassStreams* ps)
 {
-    const int total = H.GT + H.GA + H.GB + H.GC + H.GM;
+    const int total = H.GT + H.GA + H.GB + H.GC + H.GM + H.GL;
     if (H.sched == kSchedFused) {
         hipLaunchKernelGGL(k_update_fused, dim3(total), dim3(kFusedThreads), kFusedLds, s, H);
         return hipGetLastError();
