@@ -126,7 +126,10 @@ SchedGrid sched_grid(const Build& B, int sched, int res_a = 0, int res_b = 0, in
     const int capC = res_c > 0 ? std::min(res_c, kMaxGridB) : kMaxGridB;
     g.GC = std::max(1, std::min(B.R, capC));
     if ((sched == kSched8and16 || sched == kSchedFused) && B.n_le[0] > 0) {
-        const int capT = res_t > 0 ? std::min(res_t, kMaxGridA) : kMaxGridA;
+        // the tiny tiles come last: twice the resident workgroups, so that
+        // each does fewer rounds and the launch's tail is shorter (measured
+        // 2% faster than once, and four times slower again)
+        const int capT = res_t > 0 ? std::min(2 * res_t, kMaxGridA) : kMaxGridA;
         g.GT = std::max(1, std::min((B.n_le[0] + 7) / 8, capT));
     }
     // medium tiles (fused schedule): at most kWideLanes lanes, two per wavefront
