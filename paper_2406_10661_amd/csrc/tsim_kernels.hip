@@ -245,18 +245,29 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
     const long long t_end = D.inst_end[inst];
     QRec qr0{};
     if (head < qe) qr0 = D.q_rec[head];
+    // inbox flags count the entrants written this step: one is taken, more
+    // (two tiles writing one inbox, which the feeder gates rule out) is an
+    // error, counted here so that the writers need not wait for an atomic
     uint32_t inb = 0u;
+    int extra = 0;
 #pragma unroll 4
-    for (int li = 0; li < nrl; ++li) inb |= (D.inbox_flag[lb + li] != 0 ? 1u : 0u) << li;
+    for (int li = 0; li < nrl; ++li) {
+        const int f = D.inbox_flag[lb + li];
+        inb |= (f != 0 ? 1u : 0u) << li;
+        extra += f > 1 ? f - 1 : 0;
+    }
     // an instance past its horizon is frozen: none of its tiles is listed
     if (t >= t_end) return;
-    long long errors = 0;
+    long long errors = extra;
     int appended = 0;
     for (int li = 0; li < nrl; ++li) {
         const int m = lb + li;
         if ((inb >> li) & 1u) {
             LaneSum s = sum[m];
-            const VehRec z = D.inbox[m];
+            VehRec z = D.inbox[m];
+            // the entrant's next road (its writer leaves it to this kernel,
+            // so that the update does not wait on the route load)
+            z.nr = z.rem > 0 ? D.route[z.rp + 1] : -1;
             if (s.cnt < D.lane_cap[m]) {
                 slab[D.lane_base[m] + s.cnt] = z;
                 if (s.cnt == 0) s.front_reach = front_reach(z.x, z.v, D.lane_len[m], P);
@@ -1367,8 +1378,8 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
                     o.f = rec.f;
                     o.rp = rec.rp + 1;
                     o.rem = rec.rem - 1;
-                    o.nr = rec.rem - 1 > 0 ? D.route[rec.rp + 2] : -1;
-                    if (atomicCAS(&D.inbox_flag[g], 0, 1) != 0) atomicAdd(&S.errors, 1);
+                    o.nr = -1;   // filled in by the prepare kernel that appends the entrant
+                    atomicAdd(&D.inbox_flag[g], 1);   // no return: the next prepare checks the count
                     D.inbox[g] = o;
                     atomicAdd(&S.transfers, 1);
                     atomicAdd(&S.entries, 1);
@@ -2336,7 +2347,8 @@ __global__ __launch_bounds__(kSignalThreads) void k_signals(const DevNet D)
         for (int k = mb; k < me; ++k) {
             const int4 mv = D.mp_mov[k];
             if (!(((uint32_t)mv.z >> p) & 1u)) continue;
-            pr += (long long)(sum[mv.x].cnt + D.inbox_flag[mv.x]) - (long long)(sum[mv.y].cnt + D.inbox_flag[mv.y]);
+            pr += (long long)(sum[mv.x].cnt + (D.inbox_flag[mv.x] != 0)) -
+                  (long long)(sum[mv.y].cnt + (D.inbox_flag[mv.y] != 0));
         }
         if (p == 0 || pr > best_p) {
             best_p = pr;
