@@ -53,6 +53,7 @@ def lib():
         L.osim_set_policy.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_set_lane_max_speed.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.osim_set_lane_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_vehicle_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
         L.osim_get_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.osim_get_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -172,6 +173,13 @@ class OracleSim:
         l = np.ascontiguousarray(lanes, np.int32)
         v = np.ascontiguousarray(speeds, np.float64)
         lib().osim_set_lane_max_speed(self.h, int(l.size), _p(l), _p(v))
+
+    def set_lane_restriction(self, lanes, flags):
+        """Lanes (global lane ids) restricted (flag != 0: no new vehicle
+        enters) or released, from the next step on."""
+        l = np.ascontiguousarray(lanes, np.int32)
+        f = np.ascontiguousarray(flags, np.int32)
+        lib().osim_set_lane_restriction(self.h, int(l.size), _p(l), _p(f))
 
     def set_vehicle_route(self, vid, route):
         """Vehicle vid follows `route` (road ids, beginning with the road it is

@@ -33,7 +33,9 @@
  * hand-derived tiny scenes for the departure rules (most room, room >= s0,
  * tau <= t dt, one per lane, blocked head, feeder reach), merge priority,
  * travelling time, mean speed and its horizon average, lane queue length
- * and cooperative yielding, each shown to fail under a named mistake.
+ * and cooperative yielding, lane restrictions (departures, lane changes,
+ * closed junction lanes and the lane group they leave), each shown to fail
+ * under a named mistake.
  */
 #include <math.h>
 #include <stdint.h>
@@ -65,6 +67,7 @@ typedef struct osim {
     int *road_from, *road_to, *road_lane_begin;
     int *lane_road;            /* [NRL] */
     double *lane_len, *lane_lim; /* [NL] */
+    unsigned char *restricted;   /* [NL] set_lane_restriction: the lane admits no new vehicle */
     int *jl_in, *jl_out;       /* [NJL] road-lane ids */
     int *jl_junction;          /* [NJL] */
     int *junc_phase_begin, *phase_green_begin, *phase_green_jl;
@@ -206,6 +209,7 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
     s->lane_road = (int *)xcalloc(NRL, sizeof(int));
     s->lane_len = (double *)xcalloc(NL, sizeof(double));
     s->lane_lim = (double *)xcalloc(NL, sizeof(double));
+    s->restricted = (unsigned char *)xcalloc(NL, 1);
     for (int r = 0; r < R; ++r)
         for (int l = road_lane_begin[r]; l < road_lane_begin[r + 1]; ++l) {
             s->lane_road[l] = r;
@@ -306,7 +310,7 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
 void osim_destroy(osim *s)
 {
     if (!s) return;
-    void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim,
+    void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim, s->restricted,
                     s->jl_in, s->jl_out, s->jl_junction, s->junc_phase_begin, s->phase_green_begin,
                     s->phase_green_jl, s->phase_dur, s->policy, s->manual_phase, s->out_begin, s->out_jl,
                     s->feed_begin, s->feed_jl, s->tau, s->f, s->L, s->route_begin, s->route, s->rstart, s->rlen, s->q_begin,
@@ -335,12 +339,21 @@ static int next_road(const osim *s, int i)
     return (s->k[i] + 1 < route_len(s, i)) ? s->route[s->rstart[i] + s->k[i] + 1] : -1;
 }
 
-/* junction lane (global id) from road lane l into road r2, or -1 */
+/* a junction lane takes new vehicles unless it or the road lane it leads
+ * into is restricted (Section 3.2 "Lane" set_lane_restriction; [reading] a
+ * restricted lane admits no new vehicle, those already on it, or on a
+ * junction lane leading into it, carry on) */
+static int jl_open(const osim *s, int g)
+{
+    return !s->restricted[g] && !s->restricted[s->jl_out[g - s->NRL]];
+}
+
+/* open junction lane (global id) from road lane l into road r2, or -1 */
 static int jl_to_road(const osim *s, int l, int r2)
 {
     for (int e = s->out_begin[l]; e < s->out_begin[l + 1]; ++e) {
         int g = s->out_jl[e];
-        if (s->lane_road[s->jl_out[g - s->NRL]] == r2) return g;
+        if (s->lane_road[s->jl_out[g - s->NRL]] == r2 && jl_open(s, g)) return g;
     }
     return -1;
 }
@@ -648,6 +661,7 @@ static void departures(osim *s)
             double near = INFINITY;
             for (int m = lb; m < le; ++m) {
                 if (used & (1u << (m - lb))) continue;
+                if (s->restricted[m]) continue;
                 s->k[i] = 0;
                 if (!in_group(s, i, m)) continue;
                 int safe = 1;
@@ -713,6 +727,7 @@ static double mobil_dir(osim *s, int i, int dir, double *m_pos, double *m_acc, i
     int kk = l + dir;
     if (kk < lb || kk >= le) return -INFINITY;
     *target_out = kk;
+    if (s->restricted[kk]) return -INFINITY; /* no change into a restricted lane */
     /* F2 */
     if (in_group(s, i, l)) {
         if (!in_group(s, i, kk)) return -INFINITY;
@@ -1109,6 +1124,13 @@ void osim_get_route(const osim *s, int i, int *start_pos, int *len, int *out, in
 void osim_set_lane_max_speed(osim *s, int n, const int *lanes, const double *speed)
 {
     for (int c = 0; c < n; ++c) s->lane_lim[lanes[c]] = speed[c];
+}
+
+/* Section 3.2 "Lane" set_lane_restriction: lanes (global ids) restricted
+ * (flag != 0) or released from the next step on */
+void osim_set_lane_restriction(osim *s, int n, const int *lanes, const int *flags)
+{
+    for (int c = 0; c < n; ++c) s->restricted[lanes[c]] = flags[c] != 0;
 }
 
 /* policy and phase of every junction (the phase is the MANUAL phase, or the
