@@ -215,6 +215,20 @@ int tsim_set_signal_policy(tsim_handle *h, const int32_t *junction_ids, const in
  * instance); nothing changes then.  Synchronises the stream. */
 int tsim_set_lane_max_speed(tsim_handle *h, const int32_t *lane_ids, const float *max_speed, int32_t n);
 
+/* Lanes lane_ids[c] (road or junction lanes, ids as in the network) are
+ * restricted (flags[c] != 0) or released (0) from the next step on
+ * (Section 3.2 "Lane" set_lane_restriction).  A restricted lane admits no
+ * new vehicle: no departure into it, no lane change into it, and no entry
+ * from a road lane into a junction lane that is restricted or leads into a
+ * restricted lane (such a junction lane is closed, and the lane group of a
+ * route is formed from the open ones).  Vehicles already on a restricted
+ * lane, or on a junction lane leading into one, carry on.  A road lane plan
+ * (Section 3.2 "Road" set_road_lane_plan: which junction lanes of a road
+ * are in use) is the restriction of the junction lanes outside the plan.
+ * TSIM_EINVAL for a bad id (nothing changes then).  Synchronises the
+ * stream; the host arrays may be reused on return. */
+int tsim_set_lane_restriction(tsim_handle *h, const int32_t *lane_ids, const int32_t *flags, int32_t n);
+
 /* Vehicle vehicle_id follows the route roads[0 .. n_roads-1] from the next
  * step on (Section 3.2 "Vehicle" set_vehicle_route, for congestion pricing
  * and rerouting).  The route must begin with the road the vehicle is on (its
@@ -377,6 +391,9 @@ int tsim_batch_set_vehicle_route(tsim_batch *b, int32_t instance, int32_t vehicl
 /* As tsim_set_lane_max_speed, for the lanes of one instance. */
 int tsim_batch_set_lane_max_speed(tsim_batch *b, int32_t instance, const int32_t *lane_ids, const float *max_speed,
                                   int32_t n);
+/* As tsim_set_lane_restriction, for the lanes of one instance. */
+int tsim_batch_set_lane_restriction(tsim_batch *b, int32_t instance, const int32_t *lane_ids, const int32_t *flags,
+                                    int32_t n);
 /* As tsim_set_signal_policy, for the junctions of one instance. */
 int tsim_batch_set_signal_policy(tsim_batch *b, int32_t instance, const int32_t *junction_ids,
                                  const int32_t *policy, int32_t n);

@@ -57,6 +57,7 @@ struct Build {
     std::vector<int32_t> route_begin, route, q_begin, q_veh;   // route_begin: CSR of the routes given at creation
     std::vector<int32_t> rstart, rlen;   // the route in force of each vehicle: route[rstart, rstart + rlen)
     std::vector<uint32_t> q_mask;    // per queue entry: origin-road lanes that lead to its next road
+    std::vector<uint8_t> restricted; // per internal lane (shorter: the rest unrestricted): no new vehicle enters
     uint64_t slots = 0;
     int G = 0;                       // partial slots: max over schedules of GT + GA + GB + GC
     // tile classes by lane count (<= 8, <= 16, <= 32, more); n_le[c] = tiles
@@ -193,6 +194,50 @@ Caps caps_of(const Build& B)
     return c;
 }
 
+
+// lane restrictions (Section 3.2 "Lane" set_lane_restriction): a restricted
+// lane admits no new vehicle; a junction lane is closed when it or the road
+// lane it leads into is restricted (vehicles already on it carry on)
+static bool lane_restricted(const Build& B, int m) { return m < (int)B.restricted.size() && B.restricted[m]; }
+static bool jl_open(const Build& B, int q) { return !lane_restricted(B, q) && !lane_restricted(B, B.jl_out[q]); }
+// the road a junction lane leads to as the device tables hold it: -2 while closed
+static int32_t jl_road_eff(const Build& B, int q) { return jl_open(B, q) ? B.jl_out_road[q] : -2; }
+
+// lanes (bits) of origin road r a departing vehicle with next road nr may
+// enter: unrestricted, and with an open junction lane toward nr (any lane
+// when the route ends on r)
+static uint32_t depart_mask(const Build& B, int r, int nr)
+{
+    const int lb = B.tile_lane_begin[r], nrl = B.tile_n_road[r];
+    uint32_t m = 0u;
+    for (int li = 0; li < nrl; ++li) {
+        if (lane_restricted(B, lb + li)) continue;
+        bool ok = nr < 0;
+        for (int e = B.out_begin[lb + li]; e < B.out_begin[lb + li + 1] && !ok; ++e)
+            ok = B.jl_out_road[B.out_jl[e]] == nr && jl_open(B, B.out_jl[e]);
+        if (ok) m |= 1u << li;
+    }
+    return m;
+}
+
+// the device's static record of lane m
+static LaneInfo lane_info_of(const Build& B, int m)
+{
+    LaneInfo L;
+    L.base = B.lane_base[m];
+    L.cap = B.lane_cap[m];
+    L.len = B.lane_len[m];
+    L.lim = B.lane_lim[m];
+    L.jl_out = B.jl_out[m];
+    L.jl_out_road = B.jl_out[m] >= 0 ? jl_road_eff(B, m) : B.jl_out_road[m];
+    L.jl_junc = B.jl_junc[m];
+    L.green_mask = B.jl_green_mask[m];
+    L.jl_ext = B.jl_ext[m];
+    L.jl_in_local = B.jl_in_local[m];
+    L.flags = B.jl_out[m] < 0 && lane_restricted(B, m) ? 1 : 0;
+    L.pad1 = 0;
+    return L;
+}
 
 int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_params* prm, Build& B, std::string* err)
 {
@@ -426,19 +471,10 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
             });
         B.q_mask.assign(N, 0u);
         for (int r = 0; r < R; ++r) {
-            const int lb = B.tile_lane_begin[r], nrl = B.tile_n_road[r];
             for (int k = B.q_begin[r]; k < B.q_begin[r + 1]; ++k) {
                 const int v = B.q_veh[k];
                 const int rb = B.route_begin[v];
-                const int nr = B.route_begin[v + 1] - rb > 1 ? B.route[rb + 1] : -1;
-                uint32_t m = 0u;
-                for (int li = 0; li < nrl; ++li) {
-                    bool ok = nr < 0;
-                    for (int e = B.out_begin[lb + li]; e < B.out_begin[lb + li + 1] && !ok; ++e)
-                        ok = B.jl_out_road[B.out_jl[e]] == nr;
-                    if (ok) m |= 1u << li;
-                }
-                B.q_mask[k] = m;
+                B.q_mask[k] = depart_mask(B, r, B.route_begin[v + 1] - rb > 1 ? B.route[rb + 1] : -1);
             }
         }
     }
@@ -1153,20 +1189,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
     e = e ? e : chk(up_range(h, (float*)D.lane_len, B.lane_len, sp.m0, sp.m1), "lanes");
     {
         std::vector<LaneInfo> li(B.NL);
-        for (int m = sp.m0; m < sp.m1; ++m) {
-            LaneInfo& L = li[m];
-            L.base = B.lane_base[m];
-            L.cap = B.lane_cap[m];
-            L.len = B.lane_len[m];
-            L.lim = B.lane_lim[m];
-            L.jl_out = B.jl_out[m];
-            L.jl_out_road = B.jl_out_road[m];
-            L.jl_junc = B.jl_junc[m];
-            L.green_mask = B.jl_green_mask[m];
-            L.jl_ext = B.jl_ext[m];
-            L.jl_in_local = B.jl_in_local[m];
-            L.pad0 = L.pad1 = 0;
-        }
+        for (int m = sp.m0; m < sp.m1; ++m) li[m] = lane_info_of(B, m);
         e = e ? e : chk(up_range(h, (LaneInfo*)D.lane_info, li, sp.m0, sp.m1), "lanes");
     }
     e = e ? e : chk(up_range(h, (float*)D.lane_lim, B.lane_lim, sp.m0, sp.m1), "lanes");
@@ -1185,7 +1208,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
     {
         std::vector<int32_t> pairs(2 * B.out_jl.size());
         for (int k = sp.q0; k < sp.q1; ++k) {
-            pairs[2 * k] = B.jl_out_road[B.out_jl[k]];
+            pairs[2 * k] = jl_road_eff(B, B.out_jl[k]);
             pairs[2 * k + 1] = B.out_jl[k];
         }
         e = e ? e : chk(up_range(h, (int32_t*)D.out_pair, pairs, 2LL * sp.q0, 2LL * sp.q1), "conn");
@@ -1800,6 +1823,91 @@ int tsim_batch_set_lane_max_speed(tsim_batch* b, int32_t instance, const int32_t
     return lane_speed_impl(b, instance, lane_ids, max_speed, n);
 }
 
+static int restriction_impl(tsim_handle* h, int k, const int32_t* lane_ids, const int32_t* flags, int32_t n)
+{
+    if (!h || n < 0 || (n && (!lane_ids || !flags)) || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = h->B;
+    DevNet& D = h->D;
+    const Ranges g = ranges_of(B, k);
+    const int nl = g.nrl + g.njl;
+    if (n == 0) return TSIM_OK;
+    std::vector<int> ids(n);
+    for (int c = 0; c < n; ++c) {
+        const int l = lane_ids[c];
+        if (l < 0 || l >= nl) return fail(&h->err, TSIM_EINVAL, "lane id out of range");
+        ids[c] = B.int_of_ext[union_lane(B, g, l)];
+    }
+    if ((int)B.restricted.size() < B.NL) B.restricted.resize(B.NL, 0);
+    // lanes whose device record changes: the given ones, and the junction
+    // lanes feeding a given road lane (they close and open with it)
+    std::vector<int> lanes;
+    for (int c = 0; c < n; ++c) {
+        const int m = ids[c];
+        B.restricted[m] = flags[c] != 0 ? 1 : 0;
+        lanes.push_back(m);
+        if (B.jl_out[m] < 0)
+            for (int e = B.feed_begin[m]; e < B.feed_begin[m + 1]; ++e) lanes.push_back(B.feed_jl[e]);
+    }
+    std::sort(lanes.begin(), lanes.end());
+    lanes.erase(std::unique(lanes.begin(), lanes.end()), lanes.end());
+    // staged copies live until the stream is synchronised below
+    std::vector<LaneInfo> recs;
+    std::vector<int32_t> pairs;
+    std::vector<long long> pair_at;
+    for (int m : lanes) {
+        recs.push_back(lane_info_of(B, m));
+        if (B.jl_out[m] >= 0) {
+            // the junction lane's entry in its in lane's out-connection table
+            const int in = B.tile_lane_begin[B.lane_tile[m]] + B.jl_in_local[m];
+            for (int e = B.out_begin[in]; e < B.out_begin[in + 1]; ++e)
+                if (B.out_jl[e] == m) {
+                    pairs.push_back(jl_road_eff(B, m));
+                    pairs.push_back(m);
+                    pair_at.push_back(e);
+                }
+        }
+    }
+    for (size_t i = 0; i < lanes.size(); ++i)
+        HIPCHK(h, hipMemcpyAsync((void*)(D.lane_info + lanes[i]), &recs[i], sizeof(LaneInfo), hipMemcpyHostToDevice,
+                                 h->stream));
+    for (size_t i = 0; i < pair_at.size(); ++i)
+        HIPCHK(h, hipMemcpyAsync((void*)(D.out_pair + pair_at[i]), &pairs[2 * i], 8, hipMemcpyHostToDevice, h->stream));
+    // departure lanes of the queues of the roads these lanes belong to
+    std::vector<int> roads;
+    for (int m : lanes) roads.push_back(B.lane_tile[m]);
+    std::sort(roads.begin(), roads.end());
+    roads.erase(std::unique(roads.begin(), roads.end()), roads.end());
+    std::vector<uint32_t> masks;
+    std::vector<int> mask_at;
+    for (int r : roads)
+        for (int q = B.q_begin[r]; q < B.q_begin[r + 1]; ++q) {
+            const int v = B.q_veh[q];
+            const uint32_t mk = depart_mask(B, r, B.rlen[v] > 1 ? B.route[B.rstart[v] + 1] : -1);
+            if (mk != B.q_mask[q]) {
+                B.q_mask[q] = mk;
+                masks.push_back(mk);
+                mask_at.push_back(q);
+            }
+        }
+    for (size_t i = 0; i < mask_at.size(); ++i)
+        HIPCHK(h, hipMemcpyAsync((void*)&D.q_rec[mask_at[i]].mask, &masks[i], 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TSIM_OK;
+}
+
+int tsim_set_lane_restriction(tsim_handle* h, const int32_t* lane_ids, const int32_t* flags, int32_t n)
+{
+    return restriction_impl(h, -1, lane_ids, flags, n);
+}
+
+int tsim_batch_set_lane_restriction(tsim_batch* b, int32_t instance, const int32_t* lane_ids, const int32_t* flags,
+                                    int32_t n)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return restriction_impl(b, instance, lane_ids, flags, n);
+}
+
 static int export_state(tsim_handle* h, std::vector<int32_t>& lane, std::vector<float>& x, std::vector<float>& v,
                         std::vector<int32_t>& rpos, std::vector<int32_t>& rank);
 
@@ -1850,14 +1958,7 @@ static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* r
         for (int e = B.q_begin[origin]; e < B.q_begin[origin + 1]; ++e)
             if (B.q_veh[e] == i) q = e;
         if (q < 0) return fail(&h->err, TSIM_ESTATE, "vehicle missing from its departure queue");
-        const int lb = B.tile_lane_begin[origin];
-        uint32_t mask = 0u;
-        for (int li = 0; li < B.tile_n_road[origin]; ++li) {
-            bool ok = nr < 0;
-            for (int e = B.out_begin[lb + li]; e < B.out_begin[lb + li + 1] && !ok; ++e)
-                ok = B.jl_out_road[B.out_jl[e]] == nr;
-            if (ok) mask |= 1u << li;
-        }
+        const uint32_t mask = depart_mask(B, origin, nr);
         B.q_mask[q] = mask;
         QRec qr;
         qr.tau = B.tau[i];
@@ -2257,6 +2358,10 @@ bool append_build(tsim_handle* h, const Build& M, uint64_t seed, Span& sp)
         B.ext_of_int[NL0 + m] = e;
         B.int_of_ext[e] = NL0 + m;
     }
+    if (!M.restricted.empty()) {
+        B.restricted.resize(NL0 + M.NL, 0);
+        std::copy(M.restricted.begin(), M.restricted.end(), B.restricted.begin() + NL0);
+    }
     for (int q : M.out_jl) B.out_jl.push_back(q + NL0);
     for (int q : M.feed_jl) B.feed_jl.push_back(q + NL0);
     for (int j = 0; j < M.NJ; ++j) {
@@ -2331,6 +2436,7 @@ void pop_build(tsim_handle* h)
         v->resize(m0);
     B.lane_len.resize(m0);
     B.lane_lim.resize(m0);
+    if ((int)B.restricted.size() > m0) B.restricted.resize(m0);
     B.lane_base.resize(m0);
     B.jl_green_mask.resize(m0);
     B.out_begin.resize(m0 + 1);

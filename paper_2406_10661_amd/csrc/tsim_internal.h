@@ -125,12 +125,13 @@ struct __align__(16) LaneInfo {
     float len;
     float lim;
     int32_t jl_out;       // junction lanes: out lane (internal), else -1
-    int32_t jl_out_road;  // its road
+    int32_t jl_out_road;  // its road; -2 while the junction lane is closed (it, or its out lane, restricted)
     int32_t jl_junc;      // junction
     uint32_t green_mask;  // phases in which it is green
     int32_t jl_ext;       // external junction-lane index (feeder priority)
     int32_t jl_in_local;  // local index of its in lane within the tile
-    int32_t pad0, pad1;
+    int32_t flags;        // road lanes: bit 0 set while the lane is restricted (no lane change into it)
+    int32_t pad1;
 };
 
 // order-preserving map of floats to ints (for atomicMax on floats)

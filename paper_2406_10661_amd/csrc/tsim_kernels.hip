@@ -506,6 +506,7 @@ struct TileLds {
     int nlanes, nroad, n;
     int nchg, nmerge;
     int ncand;             // MOBIL candidates of the tile (listed as bytes in chg_vid until the changers use it)
+    uint32_t rmask;        // restricted road lanes (bit = local lane): no lane change into them
     float chg_x[CHG];
     int chg_vid[CHG];
     int chg_lane[CHG];
@@ -825,16 +826,18 @@ struct LaneRegs {
     int g;          // out lane of a junction lane
     int junc;       // its junction
     uint32_t mask;  // its green phases
+    int restr;      // a restricted road lane
 };
 
 template <class TS>
 __device__ __forceinline__ LaneRegs load_lanes_a(const DevNet& D, const StepBufs& B, TS& S, const Hdr& h, int gt)
 {
-    LaneRegs lr{-1, 0, 0u};
+    LaneRegs lr{-1, 0, 0u, 0};
     if (gt >= h.nl) return lr;
     const int m = h.lb + gt;
     const bool jl = gt >= h.nroad;
     const LaneInfo L = D.lane_info[m];
+    lr.restr = !jl && (L.flags & 1);
     S.lane[gt] = m;
     const int c0 = B.rsum[m].cnt;
     S.cnt[gt] = c0;
@@ -916,6 +919,7 @@ __device__ DirEval mobil_side(const DevNet& D, const TS& S, const V& view, const
     if (li >= nroad) return o;
     const int k = li + d;
     if (k < 0 || k >= nroad) return o;
+    if ((S.rmask >> k) & 1u) return o;   // no change into a restricted lane
     const uint32_t gmask = view.gmask(j);
     const bool in_g = (gmask >> li) & 1u;
     if (in_g) {
@@ -1909,6 +1913,10 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
                 S.green[gt] = 1;
             }
         }
+        {
+            const unsigned long long rb = __ballot(h.r >= 0 && gt < h.nroad && (pL.flags & 1));
+            if (gt == 0) S.rmask = (uint32_t)(GW == kWave ? rb : (rb >> gbase) & ((1ull << GW) - 1ull));
+        }
         if (gt < LANES) S.start[gt + 1] = pst[gt + 1];
         if (gt == 0) {
             S.start[0] = 0;
@@ -1999,6 +2007,10 @@ __device__ __forceinline__ void wide_pass(const DevNet& D, int a_wg, int blk, in
             const Hdr h = load_hdr(D, B, list[k]);
             const long long t = tg - D.inst_t0[h.inst];
             const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
+            {
+                const unsigned long long rb = __ballot(lr.restr);
+                if (tid == 0) S.rmask = (uint32_t)rb;
+            }
             if (tid == 0) reset_counters(S, h);
             wave_sync();
             {
@@ -2085,6 +2097,11 @@ __device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, i
         const Hdr h = load_hdr(D, B, list[k]);
         const long long t = tg - D.inst_t0[h.inst];
         const LaneRegs lr = load_lanes_a(D, B, S, h, tid);
+        {
+            // lanes are held by the first wavefront
+            const unsigned long long rb = __ballot(lr.restr);
+            if (tid == 0) S.rmask = (uint32_t)rb;
+        }
         if (tid == 0) reset_counters(S, h);
         __syncthreads();
         if (tid < kWave) {

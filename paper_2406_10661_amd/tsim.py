@@ -82,7 +82,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_instance_build", "tsim_instance_free", "tsim_instance_capacity", "tsim_batch_reserve_footprint",
            "tsim_batch_reserve", "tsim_batch_add", "tsim_batch_add_member", "tsim_batch_remove",
            "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc",
-           "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed", "tsim_set_vehicle_route",
+           "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed", "tsim_set_lane_restriction",
+           "tsim_batch_set_lane_restriction", "tsim_set_vehicle_route",
            "tsim_batch_set_vehicle_route", "tsim_set_trajectory", "tsim_get_trajectory_count"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
@@ -110,11 +111,13 @@ def lib():
         L.tsim_set_signal_policy.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_signal_phases_noalloc.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_lane_max_speed.argtypes = [P, P, P, C.c_int32]
+        L.tsim_set_lane_restriction.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_vehicle_route.argtypes = [P, C.c_int32, P, C.c_int32]
         L.tsim_set_trajectory.argtypes = [P, P, C.c_int64, C.c_int32]
         L.tsim_get_trajectory_count.argtypes = [P, P]
         L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32]
         L.tsim_batch_set_lane_max_speed.argtypes = [P, C.c_int32, P, P, C.c_int32]
+        L.tsim_batch_set_lane_restriction.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_get_metrics.argtypes = [P, P]
         L.tsim_get_road_mean_speed.argtypes = [P, P, C.c_int32]
@@ -293,6 +296,19 @@ class Sim:
         v = np.ascontiguousarray(speeds, np.float32)
         _check(lib().tsim_set_lane_max_speed(self.h, _p(l), _p(v), int(l.size)), self.h)
 
+    def set_lane_restriction(self, lanes, flags):
+        """Restrict (flag != 0) or release lanes (network lane ids) from the
+        next step on: a restricted lane admits no new vehicle (departure,
+        lane change, or entry through a junction lane that is restricted or
+        leads into it); vehicles already on it carry on."""
+        l = np.ascontiguousarray(lanes, np.int32)
+        f = np.ascontiguousarray(flags, np.int32)
+        _check(lib().tsim_set_lane_restriction(self.h, _p(l), _p(f), int(l.size)), self.h)
+
+    def set_road_lane_plan(self, plans, index):
+        """Put a road's lane plan in force (see lane_plan_flags)."""
+        self.set_lane_restriction(*lane_plan_flags(plans, index))
+
     def set_signal_policy(self, junctions, policies):
         """Signal policy per junction (TSIM_POLICY_*: 0 none, 1 fixed time,
         2 manual, 3 max pressure) from the next step on."""
@@ -376,6 +392,18 @@ class Sim:
     def set_state(self, st):
         keep, s = _state_in(st, self.net)
         _check(lib().tsim_set_state(self.h, C.byref(s)), self.h)
+
+
+def lane_plan_flags(plans, index):
+    """A road lane plan (Section 3.2 "Road" set_road_lane_plan) as lane
+    restrictions.  plans: a road's alternative sets of junction lanes in use
+    (network lane ids), e.g. a dynamic lane's left-turn or straight-on
+    movement; plan `index` is put in force by restricting every junction
+    lane of the plans that it does not use and releasing those it uses.
+    Returns (lanes, flags) for set_lane_restriction."""
+    every = sorted(set().union(*[set(int(l) for l in p) for p in plans]))
+    use = set(int(l) for l in plans[index])
+    return np.asarray(every, np.int32), np.asarray([0 if l in use else 1 for l in every], np.int32)
 
 
 def _state_arrays(N, NJ):
@@ -594,6 +622,14 @@ class Batch:
         l = np.ascontiguousarray(lanes, np.int32)
         v = np.ascontiguousarray(speeds, np.float32)
         _check(lib().tsim_batch_set_lane_max_speed(self.h, int(instance), _p(l), _p(v), int(l.size)), self.h)
+
+    def set_lane_restriction(self, instance, lanes, flags):
+        l = np.ascontiguousarray(lanes, np.int32)
+        f = np.ascontiguousarray(flags, np.int32)
+        _check(lib().tsim_batch_set_lane_restriction(self.h, int(instance), _p(l), _p(f), int(l.size)), self.h)
+
+    def set_road_lane_plan(self, instance, plans, index):
+        self.set_lane_restriction(instance, *lane_plan_flags(plans, index))
 
     def set_horizon(self, instance, n_steps):
         """Freeze instance after n_steps local steps (the others go on)."""

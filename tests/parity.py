@@ -39,6 +39,8 @@ def oracle_one_step(O, net, trips, params, st):
     if "lane_limits" in st:
         ids, lim = st["lane_limits"]
         o.set_lane_max_speed(ids, np.asarray(lim, np.float32).astype(np.float64))
+    if "restrictions" in st:
+        o.set_lane_restriction(*st["restrictions"])
     for vid, roads in st.get("routes", ()):
         o.set_vehicle_route(vid, roads)
     o.step(1)
@@ -58,6 +60,8 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False
         g.set_state(st)
         if "lane_limits" in st:
             g.set_lane_max_speed(*st["lane_limits"])
+        if "restrictions" in st:
+            g.set_lane_restriction(*st["restrictions"])
         for vid, roads in st.get("routes", ()):
             g.set_vehicle_route(vid, roads)
         g.step(1)

@@ -102,3 +102,21 @@ def test_lane_max_speed_rejects_without_touching_the_gpu(L):
     v = np.ones(1, np.float32)
     assert L.tsim_set_lane_max_speed(None, ids.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p), 1) \
         == T.TSIM_EINVAL
+
+
+def test_lane_restriction_rejects_without_touching_the_gpu(L):
+    """A bad handle, a negative count or missing arrays are refused on the
+    host (TSIM_EINVAL), for the single-handle and the batch calls."""
+    ids = np.zeros(1, np.int32)
+    f = np.ones(1, np.int32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    assert L.tsim_set_lane_restriction(None, p(ids), p(f), 1) == T.TSIM_EINVAL
+    assert L.tsim_batch_set_lane_restriction(None, 0, p(ids), p(f), 1) == T.TSIM_EINVAL
+
+
+def test_lane_plan_flags():
+    """A road lane plan as restrictions: the junction lanes of the other
+    plans that the chosen plan does not use are restricted, its own are
+    released (lanes in every plan stay released)."""
+    lanes, flags = T.lane_plan_flags([[10, 11], [11, 12], [13]], 1)
+    assert lanes.tolist() == [10, 11, 12, 13] and flags.tolist() == [1, 0, 0, 1]

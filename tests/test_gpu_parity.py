@@ -210,6 +210,105 @@ def test_lane_max_speed_horizon_statistics(O, Sim):
     assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
 
 
+def _restrictions(net, rng, p_road=0.2, p_jl=0.2):
+    """Random lane restrictions: a share of the road lanes of multi-lane
+    roads and one junction lane of a share of the movements (road to road)
+    served by several, such that every movement keeps a junction lane that is
+    open (neither it nor its out lane restricted) from an unrestricted lane,
+    so that no route is cut off."""
+    NRL = net.n_road_lanes
+    rl = np.diff(net.road_lane_begin)
+    rol = net.road_of_lane()
+    restricted = np.zeros(net.n_lanes, bool)
+    restricted[:NRL] = (rl[rol[:NRL]] > 1) & (rng.random(NRL) < p_road)
+    mov = {}
+    for q in range(net.n_jlanes):
+        mov.setdefault((int(rol[net.jl_in_lane[q]]), int(rol[net.jl_out_lane[q]])), []).append(q)
+    for qs in mov.values():
+        if len(qs) > 1 and rng.random() < p_jl:
+            restricted[NRL + int(rng.choice(qs))] = True
+    for qs in mov.values():
+        usable = [q for q in qs if not (restricted[NRL + q] or restricted[net.jl_out_lane[q]]
+                                        or restricted[net.jl_in_lane[q]])]
+        if not usable:
+            q = qs[0]
+            restricted[[NRL + q, net.jl_out_lane[q], net.jl_in_lane[q]]] = False
+    ids = np.nonzero(restricted)[0].astype(np.int32)
+    return ids, np.ones(ids.size, np.int32)
+
+
+def test_lane_restriction_one_step(O, Sim):
+    """Section 3.2 set_lane_restriction: about half of the road lanes of
+    multi-lane roads and one junction lane of most movements with several
+    restricted on a loaded 4x4 grid (every route keeps an open way; vehicles
+    already on restricted lanes stay); one step from the same state on both
+    sides."""
+    w = W.config1()
+    st = synthetic_state(w.network, w.trips, 150, seed=21, p_active=0.7)
+    st["restrictions"] = _restrictions(w.network, np.random.default_rng(5), 0.5, 0.7)
+    assert st["restrictions"][0].size > 10
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st)
+    _log("c1_lane_restriction", rep)
+    assert rep["active"] > 300
+
+
+def test_lane_restriction_released_one_step(O, Sim):
+    """Restricted, then released again before the step: the same step as
+    with no restriction at all (the release reaches the lane records, the
+    connection table and the departure lanes)."""
+    w = W.config1()
+    st = synthetic_state(w.network, w.trips, 150, seed=22, p_active=0.7)
+    ids, flags = _restrictions(w.network, np.random.default_rng(6), 0.5, 0.5)
+    g = Sim(w.network, w.trips, w.params)
+    g.set_lane_restriction(ids, flags)
+    g.set_lane_restriction(ids, np.zeros_like(flags))
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st, sim=g)
+    _log("c1_lane_restriction_released", rep)
+
+
+def test_lane_restriction_horizon_statistics(O, Sim):
+    """Restrictions set from t = 0 (through the ABI on the GPU) and changed
+    at t = 300, as a lane plan changes: completed trips and mean road speed
+    over the 600-step horizon within 1% of the oracle's."""
+    w = W.config1()
+    a_ids, a_fl = _restrictions(w.network, np.random.default_rng(7), 0.3, 0.5)
+    b_ids, b_fl = _restrictions(w.network, np.random.default_rng(8), 0.3, 0.5)
+    o = O.OracleSim(w.network, w.trips, w.params)
+    g = Sim(w.network, w.trips, w.params)
+    for s in (o, g):
+        s.set_lane_restriction(a_ids, a_fl)
+        s.step(300)
+        s.set_lane_restriction(a_ids, np.zeros_like(a_fl))
+        s.set_lane_restriction(b_ids, b_fl)
+        s.step(w.n_steps - 300)
+    om, gm = o.metrics(), g.metrics()
+    _log("c1_lane_restriction_horizon", dict(oracle_finished=om["finished"], gpu_finished=gm["n_finished"],
+                                             oracle_speed=om["mean_speed_avg"], gpu_speed=gm["mean_speed_avg"]))
+    assert gm["errors"] == 0
+    assert abs(gm["n_finished"] - om["finished"]) <= 0.01 * om["finished"]
+    assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
+
+
+def test_lane_restriction_in_a_batch_matches_alone(Sim):
+    """Restrictions on one instance of a batch (through the batch ABI) leave
+    the other untouched: each instance's state after 100 steps equals that
+    of a separate handle with the same restrictions (bit for bit)."""
+    from paper_2406_10661_amd.tsim import Batch
+    w = W.config1()
+    ids, flags = _restrictions(w.network, np.random.default_rng(9), 0.3, 0.5)
+    b = Batch([w.network, w.network], [w.trips, w.trips], [w.params, w.params])
+    b.set_lane_restriction(1, ids, flags)
+    b.step(100)
+    for k, restrict in ((0, False), (1, True)):
+        g = Sim(w.network, w.trips, w.params)
+        if restrict:
+            g.set_lane_restriction(ids, flags)
+        g.step(100)
+        a, e = b.get_state(k), g.get_state()
+        for f in ("status", "lane", "route_pos", "x", "v"):
+            assert np.array_equal(a[f], e[f]), (k, f)
+
+
 def _reroutes(net, trips, st, rng, n):
     """Valid new routes for n vehicles of state st: a waiting vehicle ends
     its trip on its origin road; an active one on a road lane turns onto a
