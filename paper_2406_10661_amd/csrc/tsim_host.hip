@@ -756,7 +756,8 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.list_cnt, 2 * kNumLists * kCntStride * 4);
     add(&D.part, (size_t)std::max<long long>(c.G, 1) * sizeof(WGPartial));
     add(&D.ustep, 8);
-    add(&D.fold_flag, 8);
+    add(&D.fold_flag, 24);
+    add(&D.part2, (size_t)kFoldWGs * sizeof(WGPartial));
     add(&D.met, (size_t)std::max<long long>(c.n_inst, 1) * sizeof(DevMetrics));
     add(&D.tile_inst, std::max<size_t>(R, 1) * 4);
     add(&D.junc_inst, std::max<size_t>(NJ, 1) * 4);
@@ -1042,7 +1043,7 @@ int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, con
     if (k < 0) {
         const long long gstep = step;
         const long long ustep = step - 1;   // the last step run (none folded yet)
-        HIPCHK(h, hipMemsetAsync(D.fold_flag, 0, 8, h->stream));
+        HIPCHK(h, hipMemsetAsync(D.fold_flag, 0, 24, h->stream));
         HIPCHK(h, hipMemsetAsync(D.list_cnt, 0, 2 * kNumLists * kCntStride * 4, h->stream));
         HIPCHK(h, hipMemcpyAsync(D.gstep, &gstep, sizeof(gstep), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(D.ustep, &ustep, sizeof(ustep), hipMemcpyHostToDevice, h->stream));

@@ -48,6 +48,7 @@ enum Schedule {
 };
 constexpr int kCntStride = 32;           // work-list counters one 128-byte line apart
 constexpr int kNumLists = 6;             // small, wide, huge, tiny, medium, large
+constexpr int kFoldWGs = 16;             // prepare workgroups that sum slices of the previous step's partials
 constexpr int kMedCap = 64;              // medium tiles (fused schedule): at most kWideLanes lanes and 64 vehicles
 constexpr int kLargeCap = 256;           // large tiles (fused schedule): above the wide list, at most 256 vehicles
 constexpr int kLargeLanes = 48;          // and at most 48 lanes
@@ -291,10 +292,13 @@ struct DevNet {
     WGPartial* part;                 // [G] (G >= GA + GB for every schedule)
     // step protocol: the prepare kernel of step t publishes t in *ustep (read
     // by that step's update kernels, whose workgroups then advance *gstep to
-    // t + 1) and folds the partial sums of step t - 1 when fold_flag[0] is
-    // set; fold_flag[1] is the number of partials the last step wrote
+    // t + 1) and sums the partials of step t - 1 in slices (part2) when that
+    // step's parity p has fold_flag[2 p] set (fold_flag[2 p + 1]: the number
+    // of partials); fold_flag[4] marks slice sums that the update still has
+    // to combine into the metrics
     long long* ustep;
-    int32_t* fold_flag;
+    int32_t* fold_flag;              // [6]
+    WGPartial* part2;                // [kFoldWGs]
     DevMetrics* met;                 // [n_inst]
     KParams P;
 };

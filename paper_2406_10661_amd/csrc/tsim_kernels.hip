@@ -282,31 +282,36 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
             D.inbox_flag[m] = 0;
         }
     }
-    // departures (FIFO per origin road, one per lane per step, safe entry)
+    // departures (FIFO per origin road, one per lane per step, safe entry).
+    // Each entry's loads are issued together (its vehicle's status, the next
+    // queue entry, every lane's summary and tables) and the choice is made
+    // by selects, so that an entry costs one round of memory latency.
     const double now = (double)t * P.dt_d;
     unsigned used = 0u;
     int departed = 0;
-    bool first = true;
+    QRec qr = qr0;
     while (head < qe) {
         // departure times ascend along the queue: the first future one ends
         // the scan (entries already departed are skipped once they are due)
-        const QRec qr = first ? qr0 : D.q_rec[head];
-        first = false;
         if (!((double)qr.tau <= now)) break;
         const int v = qr.vid;
-        if (D.status[v] != 0) {
-            head++;
-            continue;
-        }
+        const int st_v = D.status[v];
+        QRec qn{};
+        if (head + 1 < qe) qn = D.q_rec[head + 1];
         const float Lv = qr.len;
         int best = -1;
         float best_room = -TS_INF;
+        int b_cnt = 0, b_cap = 0;
+        uint32_t b_base = 0u;
+        float b_len = 0.0f, b_fr = 0.0f;
         const uint32_t lanes_ok = qr.mask & ~used;
-        // every lane's summary is read (no load behind a branch), the choice
-        // is made by selects
 #pragma unroll 4
         for (int li = 0; li < nrl; ++li) {
-            const LaneSum s = sum[lb + li];
+            const int m = lb + li;
+            const LaneSum s = sum[m];
+            const int cap = D.lane_cap[m];
+            const uint32_t base = D.lane_base[m];
+            const float len = D.lane_len[m];
             // no nonempty feeder may reach past the entrant's rear (x = 0)
             const int fm = fmax_of(s.fmax, tg);
             const bool ok = ((lanes_ok >> li) & 1u) && !(fm != kNoFeeder && !(-Lv - o2f(fm) >= 0.0f));
@@ -314,11 +319,20 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
             const bool better = ok && room > best_room;
             best_room = better ? room : best_room;
             best = better ? li : best;
+            b_cnt = better ? s.cnt : b_cnt;
+            b_fr = better ? s.front_reach : b_fr;
+            b_cap = better ? cap : b_cap;
+            b_base = better ? base : b_base;
+            b_len = better ? len : b_len;
+        }
+        if (st_v != 0) {
+            head++;
+            qr = qn;
+            continue;
         }
         if (best < 0 || !(best_room >= P.s0)) break;
         const int m = lb + best;
-        LaneSum s = sum[m];
-        if (s.cnt >= D.lane_cap[m]) {
+        if (b_cnt >= b_cap) {
             errors++;
             break;
         }
@@ -331,16 +345,18 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         nrec.rp = qr.rp;
         nrec.rem = qr.rem;
         nrec.nr = qr.nr;
-        slab[D.lane_base[m] + s.cnt] = nrec;
-        if (s.cnt == 0) s.front_reach = front_reach(0.0f, 0.0f, D.lane_len[m], P);
-        s.cnt += 1;
+        slab[b_base + b_cnt] = nrec;
+        LaneSum s;
+        s.cnt = b_cnt + 1;
         s.rear = 0.0f - Lv;
         s.rear_v = 0.0f;
+        s.front_reach = b_cnt == 0 ? front_reach(0.0f, 0.0f, b_len, P) : b_fr;
         put_dyn(sum[m], s);
         D.status[v] = 1;
         used |= 1u << best;
         departed++;
         head++;
+        qr = qn;
     }
     D.q_head[r] = head;
     const int n = n_prev + appended + departed;
@@ -381,6 +397,8 @@ constexpr int kPrepThreads = 512;
 // workgroup instead of one per road or wavefront.
 template <int NT>
 __device__ void fold_step(const DevNet& D, int total_wg);
+template <int NT>
+__device__ void sum_partials(const DevNet& D, int lo, int hi, long long* a);
 
 __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int small_lanes, int small_cap,
                                                           int tiny_lanes, int tiny_cap, int total_wg)
@@ -391,9 +409,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
     __shared__ int base[NL];
     __shared__ long long bsum[2][NW];
     const long long tg = *D.gstep;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // workgroups [0, kFoldWGs) fold the previous step (below); junctions
+    // and roads are spread over the others, so that the fold is not added
+    // to a workgroup's share of them
+    const int i = ((int)blockIdx.x - kFoldWGs) * (int)blockDim.x + (int)threadIdx.x;
     PrepOut o;
-    prepare_one(D, tg, i, small_lanes, small_cap, tiny_lanes, tiny_cap, o);
+    if (blockIdx.x >= kFoldWGs) prepare_one(D, tg, i, small_lanes, small_cap, tiny_lanes, tiny_cap, o);
     const int wv = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
     unsigned long long m[NL];
 #pragma unroll
@@ -451,20 +472,40 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(const DevNet D, int sm
         }
         if (o.errors) atomicAdd((unsigned long long*)&D.met[o.inst].errors, (unsigned long long)o.errors);
     }
-    // step protocol (workgroup 0): fold the step before this one, publish
-    // this one for the update kernels (with its number of partials), clear
-    // the other parity's work-list counters for the next step
-    if (blockIdx.x == 0) {
-        const int pending = D.fold_flag[0];
-        if (pending) fold_step<kPrepThreads>(D, D.fold_flag[1]);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            D.fold_flag[0] = 1;
-            D.fold_flag[1] = total_wg;
-            *D.ustep = tg;
+    // step protocol.  The update's partials of the step before this one
+    // (pending flag and count kept by that step's parity) are summed in
+    // kFoldWGs slices here, one per fold workgroup, and the slices are
+    // combined into the metrics by the first workgroup of this step's update
+    // (fold_finish; batches fold their per-instance sums in workgroup 0 at
+    // once).  Workgroup 0 then publishes this step for the update kernels
+    // (with its number of partials, under this step's parity) and clears the
+    // other parity's work-list counters for the next step.
+    if (blockIdx.x < kFoldWGs) {
+        const int pp = (int)((tg - 1) & 1);
+        const int pending = D.fold_flag[2 * pp];
+        if (pending && D.n_inst == 1) {
+            const int total = D.fold_flag[2 * pp + 1];
+            const int b = (int)blockIdx.x;
+            long long a[kPartWords];
+            sum_partials<kPrepThreads>(D, (int)((long long)total * b / kFoldWGs),
+                                       (int)((long long)total * (b + 1) / kFoldWGs), a);
+            if (threadIdx.x == 0) {
+                long long* q = (long long*)&D.part2[b];
+                for (int k = 0; k < kPartWords; ++k) q[k] = a[k];
+            }
         }
-        if (threadIdx.x < kNumLists)
-            D.list_cnt[((int)((tg + 1) & 1) * kNumLists + (int)threadIdx.x) * kCntStride] = 0;
+        if (blockIdx.x == 0) {
+            if (pending && D.n_inst > 1) fold_step<kPrepThreads>(D, 0);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                D.fold_flag[4] = pending && D.n_inst == 1 ? 1 : 0;
+                D.fold_flag[2 * (int)(tg & 1)] = 1;
+                D.fold_flag[2 * (int)(tg & 1) + 1] = total_wg;
+                *D.ustep = tg;
+            }
+            if (threadIdx.x < kNumLists)
+                D.list_cnt[((int)((tg + 1) & 1) * kNumLists + (int)threadIdx.x) * kCntStride] = 0;
+        }
     }
 }
 
@@ -1648,10 +1689,96 @@ __device__ __forceinline__ void finish_step(const DevNet& D, const WGPartial& ac
 // whole workgroup of NT threads.  The prepare kernel's other workgroups may
 // be adding departures and errors to the same metrics, so those fields take
 // atomics here.
+// the metrics of a single-instance step from its summed partials (thread of
+// the caller; fs: the step they belong to)
+__device__ __forceinline__ void apply_sums(const DevNet& D, const long long* a, long long fs)
+{
+    DevMetrics* M = D.met;
+    M->vehicle_steps += a[2];
+    M->lane_changes += a[3];
+    M->transfers += a[4];
+    M->clamps += a[5];
+    M->feeder_blocks += a[6];
+    M->finished += a[7];
+    M->sum_tt_fx += a[8];
+    M->lane_steps += a[10];
+    M->road_entries += a[11];
+    if (a[9]) atomicAdd((unsigned long long*)&M->errors, (unsigned long long)a[9]);
+    if (a[1] > 0) {
+        M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
+        M->speed_acc += M->mean_speed_last;
+        M->speed_steps += 1;
+    } else {
+        M->mean_speed_last = 0.0;
+    }
+    M->step = fs - D.inst_t0[0] + 1;
+}
+
+// sums partials [lo, hi) over a workgroup of NT threads (result in thread 0)
+template <int NT>
+__device__ void sum_partials(const DevNet& D, int lo, int hi, long long* a)
+{
+    __shared__ long long red[NT / kWave][kPartWords];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kPartWords; ++k) a[k] = 0;
+    // partials are kPartWords / 2 16-byte words at 16-byte alignment
+#pragma unroll 4
+    for (int g = lo + tid; g < hi; g += NT) {
+        const longlong2* q = (const longlong2*)&D.part[g];
+#pragma unroll
+        for (int k = 0; k < kPartWords / 2; ++k) {
+            const longlong2 x = q[k];
+            a[2 * k] += x.x;
+            a[2 * k + 1] += x.y;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPartWords; ++k) {
+        for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
+    }
+    if (tid % kWave == 0) {
+#pragma unroll
+        for (int k = 0; k < kPartWords; ++k) red[tid / kWave][k] = a[k];
+    }
+    __syncthreads();
+    if (tid == 0)
+        for (int w = 1; w < NT / kWave; ++w)
+            for (int k = 0; k < kPartWords; ++k) a[k] += red[w][k];
+}
+
+// the second level of a single-instance fold: the kFoldWGs slice sums the
+// prepare kernel wrote, combined by the first wavefront of the calling
+// workgroup into the metrics of step *ustep - 1 (run by the update)
+__device__ __forceinline__ void fold_finish(const DevNet& D)
+{
+    if (threadIdx.x >= kWave || D.fold_flag[4] == 0) return;
+    const int l = (int)threadIdx.x;
+    long long a[kPartWords];
+#pragma unroll
+    for (int k = 0; k < kPartWords; ++k) a[k] = 0;
+    if (l < kFoldWGs) {
+        const longlong2* q = (const longlong2*)&D.part2[l];
+#pragma unroll
+        for (int k = 0; k < kPartWords / 2; ++k) {
+            const longlong2 x = q[k];
+            a[2 * k] = x.x;
+            a[2 * k + 1] = x.y;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPartWords; ++k) {
+        for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
+    }
+    if (l == 0) {
+        apply_sums(D, a, *D.ustep - 1);
+        D.fold_flag[4] = 0;
+    }
+}
+
 template <int NT>
 __device__ void fold_step(const DevNet& D, int total_wg)
 {
-    __shared__ long long red[NT / kWave][kPartWords];
     const long long fs = *D.ustep;
     const int tid = threadIdx.x;
     if (D.n_inst > 1) {
@@ -1685,50 +1812,9 @@ __device__ void fold_step(const DevNet& D, int total_wg)
             M->step = fs - D.inst_t0[i] + 1;
         }
     } else {
-        long long a[kPartWords] = {};
-        // partials are kPartWords / 2 16-byte words at 16-byte alignment
-#pragma unroll 4
-        for (int g = tid; g < total_wg; g += NT) {
-            const longlong2* q = (const longlong2*)&D.part[g];
-#pragma unroll
-            for (int k = 0; k < kPartWords / 2; ++k) {
-                const longlong2 x = q[k];
-                a[2 * k] += x.x;
-                a[2 * k + 1] += x.y;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kPartWords; ++k) {
-            for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
-        }
-        if (tid % kWave == 0) {
-#pragma unroll
-            for (int k = 0; k < kPartWords; ++k) red[tid / kWave][k] = a[k];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int w = 1; w < NT / kWave; ++w)
-                for (int k = 0; k < kPartWords; ++k) a[k] += red[w][k];
-            DevMetrics* M = D.met;
-            M->vehicle_steps += a[2];
-            M->lane_changes += a[3];
-            M->transfers += a[4];
-            M->clamps += a[5];
-            M->feeder_blocks += a[6];
-            M->finished += a[7];
-            M->sum_tt_fx += a[8];
-            M->lane_steps += a[10];
-            M->road_entries += a[11];
-            if (a[9]) atomicAdd((unsigned long long*)&M->errors, (unsigned long long)a[9]);
-            if (a[1] > 0) {
-                M->mean_speed_last = (double)a[0] / (double)kSpeedFx / (double)a[1];
-                M->speed_acc += M->mean_speed_last;
-                M->speed_steps += 1;
-            } else {
-                M->mean_speed_last = 0.0;
-            }
-            M->step = fs - D.inst_t0[0] + 1;
-        }
+        long long a[kPartWords];
+        sum_partials<NT>(D, 0, total_wg, a);
+        if (tid == 0) apply_sums(D, a, fs);
     }
 }
 
@@ -1738,10 +1824,14 @@ constexpr int kFoldThreads = 256;
 
 __global__ __launch_bounds__(kFoldThreads) void k_fold(const DevNet D)
 {
-    if (D.fold_flag[0] == 0) return;
-    fold_step<kFoldThreads>(D, D.fold_flag[1]);
+    // slice sums of the step before the last, if no update combined them
+    fold_finish(D);
+    const int p = (int)(*D.ustep & 1);
+    if (D.fold_flag[2 * p] == 0) return;
     __syncthreads();
-    if (threadIdx.x == 0) D.fold_flag[0] = 0;
+    fold_step<kFoldThreads>(D, D.fold_flag[2 * p + 1]);
+    __syncthreads();
+    if (threadIdx.x == 0) D.fold_flag[2 * p] = 0;
 }
 
 
@@ -1915,7 +2005,11 @@ __device__ __forceinline__ void grouped_pass(const DevNet& D, int a_wg, int blk,
         }
         {
             const unsigned long long rb = __ballot(h.r >= 0 && gt < h.nroad && (pL.flags & 1));
-            if (gt == 0) S.rmask = (uint32_t)(GW == kWave ? rb : (rb >> gbase) & ((1ull << GW) - 1ull));
+            if constexpr (GW == kWave) {
+                if (gt == 0) S.rmask = (uint32_t)rb;
+            } else {
+                if (gt == 0) S.rmask = (uint32_t)((rb >> gbase) & ((1ull << GW) - 1ull));
+            }
         }
         if (gt < LANES) S.start[gt + 1] = pst[gt + 1];
         if (gt == 0) {
@@ -2091,6 +2185,9 @@ __device__ __forceinline__ void block_pass(const DevNet& D, int a_wg, int blk, i
     const int count = D.list_cnt[((int)(tg & 1) * kNumLists + LIST) * kCntStride];
     const int32_t* list = LIST == 1 ? D.list_big : (LIST == 5 ? D.list_large : D.list_huge);
 
+    // the previous step's metrics (every schedule runs this pass's first
+    // workgroup; a single instance's fold ends here)
+    if (blk == 0) fold_finish(D);
     WGPartial acc{};
     int acc_inst = -1;
     for (int k = blk; k < count; k += nblk) {
@@ -2458,7 +2555,8 @@ hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s)
     case kSched8x16: lanes = 8; cap = 16; break;
     default: break;
     }
-    hipLaunchKernelGGL(k_prepare, dim3((n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H, lanes, cap,
+    hipLaunchKernelGGL(k_prepare, dim3(kFoldWGs + (n + kPrepThreads - 1) / kPrepThreads), dim3(kPrepThreads), 0, s, H,
+                       lanes, cap,
                        tl, tc, H.GT + H.GA + H.GB + H.GC + H.GM + H.GL);
     return hipGetLastError();
 }
