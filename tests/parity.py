@@ -75,13 +75,23 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False
     st_lane = np.asarray(st["lane"])
     ref_len = np.where(st_lane >= 0, lane_len[np.maximum(st_lane, 0)], 1.0)
     pe = pos_eps(ref_len)
-    near = ((m[:, 0] < EPS_ACC) | (m[:, 2] < EPS_ACC) | (m[:, 1] < pe) | (m[:, 4] < pe) | (m[:, 5] < pe)
-            | (m[:, 3] < 1e-4 * (params.p_max - params.p_min)))
+    # near-threshold categories (the oracle's margins): the MOBIL threshold
+    # |u_d|, a gap margin, the new follower's |a~ + b_safe|, the draw's
+    # distance to a decision boundary, |x' - bound| or |x' - lane end|, and a
+    # departure's room margin
+    cats = {"mobil_threshold": m[:, 0] < EPS_ACC, "gap": m[:, 1] < pe, "b_safe": m[:, 2] < EPS_ACC,
+            "draw": m[:, 3] < 1e-4 * (params.p_max - params.p_min), "bound_or_lane_end": m[:, 4] < pe,
+            "departure_room": m[:, 5] < pe}
+    near = np.zeros(len(m), bool)
+    for c in cats.values():
+        near |= c
     # departures cascade into their lane: a near departure marks its lane's road
     same = ((gst["status"] == ost["status"]) & (gst["lane"] == ost["lane"]) & (gst["route_pos"] == ost["route_pos"]))
     bad = ~same & ~near
     rep = dict(n=N, active=int((ost["status"] == 1).sum()), mismatched=int((~same).sum()),
                near=int(near.sum()), near_mismatch=int((~same & near).sum()),
+               near_by=({k: int(c.sum()) for k, c in cats.items()}),
+               near_mismatch_by=({k: int((c & ~same).sum()) for k, c in cats.items()}),
                changes=int(om["lane_changes"]), transfers=int(om["transfers"]),
                departures=int(om["departures"]))
     if bad.any():
