@@ -101,6 +101,10 @@ typedef struct tsim_trips {
     const int32_t *route_roads;      /* road ids */
     const float *v0_factor;          /* [n] desired speed = v0_factor * lane limit */
     const float *length;             /* [n] vehicle length, metres, > 0 */
+    const float *end_s;              /* [n] or NULL: where the trip ends on the last road of its route, metres
+                                      * from the road's start (the trip ends in the step the vehicle's front
+                                      * passes it; Section 3.2 set_vehicle_route end position, an AOI's
+                                      * connection as the trip's end); negative or NULL: the road's end */
 } tsim_trips;
 
 /* Model parameters (Appendix B.3; the MOBIL threshold, safe deceleration,
@@ -234,14 +238,15 @@ int tsim_set_lane_restriction(tsim_handle *h, const int32_t *lane_ids, const int
  * and rerouting).  The route must begin with the road the vehicle is on (its
  * origin road while it waits; on a junction lane, the road it left, followed
  * by the road that lane enters), and consecutive roads must be joined by a
- * junction lane; its trip ends at the end of the last road (the paper's end
- * lane and position are not modelled: trips end at a road's end).  Its
- * route position becomes 0; a vehicle outside the new next road's lane group
- * changes lanes toward it as usual.  Changed routes are kept in a route pool
- * with room for a quarter of the creation routes plus 4,096 entries
- * (TSIM_ENOMEM when it is full); TSIM_EINVAL for a finished vehicle or a bad
- * route.  Synchronises the stream. */
-int tsim_set_vehicle_route(tsim_handle *h, int32_t vehicle_id, const int32_t *roads, int32_t n_roads);
+ * junction lane; its trip ends where its front passes end_s metres along
+ * the last road (negative: that road's end; the paper's end lane is not
+ * modelled).  Its route position becomes 0; a vehicle outside the new next
+ * road's lane group changes lanes toward it as usual.  Changed routes are
+ * kept in a route pool with room for a quarter of the creation routes plus
+ * 4,096 entries (TSIM_ENOMEM when it is full); TSIM_EINVAL for a finished
+ * vehicle, a bad route or an end position beyond the last road.
+ * Synchronises the stream. */
+int tsim_set_vehicle_route(tsim_handle *h, int32_t vehicle_id, const int32_t *roads, int32_t n_roads, float end_s);
 
 /* Synchronises the stream, then fills *out. */
 int tsim_get_metrics(tsim_handle *h, tsim_metrics *out);
@@ -387,7 +392,7 @@ int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t 
                                  const int32_t *phase_index, int32_t n);
 /* As tsim_set_vehicle_route, for a vehicle of one instance (local ids). */
 int tsim_batch_set_vehicle_route(tsim_batch *b, int32_t instance, int32_t vehicle_id, const int32_t *roads,
-                                 int32_t n_roads);
+                                 int32_t n_roads, float end_s);
 /* As tsim_set_lane_max_speed, for the lanes of one instance. */
 int tsim_batch_set_lane_max_speed(tsim_batch *b, int32_t instance, const int32_t *lane_ids, const float *max_speed,
                                   int32_t n);

@@ -54,7 +54,8 @@ def lib():
         L.osim_set_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_set_lane_max_speed.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_lane_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
-        L.osim_set_vehicle_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int]
+        L.osim_set_vehicle_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double]
+        L.osim_set_trip_ends.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_get_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.osim_get_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_get_metrics.argtypes = [C.c_void_p, C.c_void_p]
@@ -118,6 +119,11 @@ class OracleSim:
                                _p(k[19]), C.c_uint64(params.seed))
         if not self.h:
             raise MemoryError("oracle create failed")
+        end_s = getattr(trips, "end_s", None)
+        if end_s is not None:
+            e = np.ascontiguousarray(end_s, np.float32).astype(np.float64)
+            ids = np.arange(self.N, dtype=np.int32)
+            L.osim_set_trip_ends(self.h, self.N, _p(ids), _p(e))
 
     def close(self):
         if self.h:
@@ -181,11 +187,13 @@ class OracleSim:
         f = np.ascontiguousarray(flags, np.int32)
         lib().osim_set_lane_restriction(self.h, int(l.size), _p(l), _p(f))
 
-    def set_vehicle_route(self, vid, route):
+    def set_vehicle_route(self, vid, route, end_s=None):
         """Vehicle vid follows `route` (road ids, beginning with the road it is
-        on) from the next step on, at route position 0."""
+        on) from the next step on, at route position 0; its trip ends at
+        end_s metres along the last road (None: that road's end)."""
         r = np.ascontiguousarray(route, np.int32)
-        lib().osim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size))
+        e = -1.0 if end_s is None else float(np.float32(end_s))
+        lib().osim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size), e)
 
     def route(self, vid, max_len=100000):
         """(route position, roads of the route in force) of vehicle vid."""

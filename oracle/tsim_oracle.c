@@ -34,8 +34,8 @@
  * tau <= t dt, one per lane, blocked head, feeder reach), merge priority,
  * travelling time, mean speed and its horizon average, lane queue length
  * and cooperative yielding, lane restrictions (departures, lane changes,
- * closed junction lanes and the lane group they leave), each shown to fail
- * under a named mistake.
+ * closed junction lanes and the lane group they leave), trip end positions,
+ * each shown to fail under a named mistake.
  */
 #include <math.h>
 #include <stdint.h>
@@ -80,6 +80,7 @@ typedef struct osim {
     double *tau, *f, *L;
     int *route_begin, *route;    /* CSR of the routes given at creation */
     int *rstart, *rlen;          /* [N] the route in force: route[rstart, rstart + rlen) */
+    double *end_s;               /* [N] trip end position on the last road, < 0: the road's end */
     long route_n, route_cap;     /* route entries used / allocated (set_vehicle_route appends) */
     int *q_begin, *q_veh;        /* [R+1] departure queue of each origin road, (tau, id) order */
     /* state */
@@ -257,6 +258,8 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
     /* trips */
     s->N = N;
     s->tau = (double *)xcalloc(N, sizeof(double));
+    s->end_s = (double *)xcalloc(N, sizeof(double));
+    for (int i = 0; i < N; ++i) s->end_s[i] = -1.0;
     s->f = (double *)xcalloc(N, sizeof(double));
     s->L = (double *)xcalloc(N, sizeof(double));
     s->route_begin = (int *)xcalloc(N + 1, sizeof(int));
@@ -310,7 +313,7 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
 void osim_destroy(osim *s)
 {
     if (!s) return;
-    void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim, s->restricted,
+    void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim, s->restricted, s->end_s,
                     s->jl_in, s->jl_out, s->jl_junction, s->junc_phase_begin, s->phase_green_begin,
                     s->phase_green_jl, s->phase_dur, s->policy, s->manual_phase, s->out_begin, s->out_jl,
                     s->feed_begin, s->feed_jl, s->tau, s->f, s->L, s->route_begin, s->route, s->rstart, s->rlen, s->q_begin,
@@ -948,12 +951,17 @@ static void step_once(osim *s)
             s->event[i] |= EV_CLAMP;
             s->n_clamps += 1;
         }
-        /* U5: lane end */
+        /* U5: lane end, or the trip's end position on its last road
+         * ([reading] Section 3.2 set_vehicle_route's end position, an AOI's
+         * connection as the trip's end: the trip ends in the step its front
+         * passes that position) */
         int nl = ln, nk = s->k[i], nst = ACTIVE;
         double len = s->lane_len[ln];
+        const int last = ln < NRL && s->k[i] == route_len(s, i) - 1;
+        if (last && s->end_s[i] >= 0.0 && s->end_s[i] < len) len = s->end_s[i];
         m_x = fmin(m_x, fabs(xn - len));
         if (xn > len) {
-            if (ln < NRL && s->k[i] == route_len(s, i) - 1) {
+            if (last) {
                 nst = FINISHED;
                 s->finish_step[i] = (int)s->t;
                 s->sum_tt += (double)(s->t + 1) * P->dt - s->tau[i];
@@ -1098,8 +1106,9 @@ void osim_set_policy(osim *s, int n, const int *junction, const int *policy)
  * road while it waits), and, on a junction lane, continues with that lane's
  * road; the vehicle's route position becomes 0.  The trip ends at the end of
  * the new route's last road.  The caller checks the route is connected. */
-void osim_set_vehicle_route(osim *s, int i, const int *route, int len)
+void osim_set_vehicle_route(osim *s, int i, const int *route, int len, double end_s)
 {
+    s->end_s[i] = end_s;
     if (s->route_n + len > s->route_cap) {
         while (s->route_n + len > s->route_cap) s->route_cap *= 2;
         s->route = (int *)realloc(s->route, (size_t)s->route_cap * sizeof(int));
@@ -1124,6 +1133,13 @@ void osim_get_route(const osim *s, int i, int *start_pos, int *len, int *out, in
 void osim_set_lane_max_speed(osim *s, int n, const int *lanes, const double *speed)
 {
     for (int c = 0; c < n; ++c) s->lane_lim[lanes[c]] = speed[c];
+}
+
+/* trip end positions (metres along the last road of the route; < 0 for
+ * its end) of vehicles vids[c], e.g. an AOI's connection on that road */
+void osim_set_trip_ends(osim *s, int n, const int *vids, const double *end_s)
+{
+    for (int c = 0; c < n; ++c) s->end_s[vids[c]] = end_s[c];
 }
 
 /* Section 3.2 "Lane" set_lane_restriction: lanes (global ids) restricted

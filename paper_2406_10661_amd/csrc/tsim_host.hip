@@ -54,6 +54,7 @@ struct Build {
     std::vector<float> phase_dur;
     std::vector<double> junc_cycle;
     std::vector<float> tau, vf, vlen;
+    std::vector<float> vend;         // per vehicle: trip end position on the last road, < 0: its end
     std::vector<int32_t> route_begin, route, q_begin, q_veh;   // route_begin: CSR of the routes given at creation
     std::vector<int32_t> rstart, rlen;   // the route in force of each vehicle: route[rstart, rstart + rlen)
     std::vector<uint32_t> q_mask;    // per queue entry: origin-road lanes that lead to its next road
@@ -220,6 +221,15 @@ static uint32_t depart_mask(const Build& B, int r, int nr)
     return m;
 }
 
+// the next-road word of vehicle v's record on route position rp with rem
+// roads after it (the trip's end position on its last road)
+static int32_t next_word(const Build& B, int v, int rp, int rem)
+{
+    if (rem > 0) return B.route[rp + 1];
+    const int r = B.route[rp];
+    return end_word(B.vend[v], B.lane_len[B.tile_lane_begin[r]]);
+}
+
 // the device's static record of lane m
 static LaneInfo lane_info_of(const Build& B, int m)
 {
@@ -296,6 +306,8 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
         }
         if (!(tr->length[i] > 0) || !(tr->v0_factor[i] > 0) || !(tr->depart_time[i] >= 0))
             return fail(err, TSIM_EINVAL, "vehicle length/factor/departure");
+        if (tr->end_s && !(tr->end_s[i] < 0.0f) && !(tr->end_s[i] > 0.0f && tr->end_s[i] <= net->road_length[tr->route_roads[e - 1]]))
+            return fail(err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": end position beyond its last road");
         Lmin = std::min(Lmin, tr->length[i]);
         fmax_ = std::max(fmax_, tr->v0_factor[i]);
     }
@@ -450,6 +462,8 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
     B.tau.assign(tr->depart_time, tr->depart_time + N);
     B.vf.assign(tr->v0_factor, tr->v0_factor + N);
     B.vlen.assign(tr->length, tr->length + N);
+    if (tr->end_s) B.vend.assign(tr->end_s, tr->end_s + N);
+    else B.vend.assign(N, -1.0f);
     B.route_begin.assign(tr->route_begin, tr->route_begin + N + 1);
     B.route.assign(tr->route_roads, tr->route_roads + tr->route_begin[N]);
     B.rstart.assign(B.route_begin.begin(), B.route_begin.begin() + N);
@@ -502,7 +516,7 @@ void single_instance(Build& B, const tsim_params* prm)
 struct Union {
     std::vector<int32_t> road_from, road_to, road_lane_begin, jl_in, jl_out, junc_phase_begin, phase_green_begin,
         phase_green_jl, junc_policy, route_begin, route_roads;
-    std::vector<float> road_length, road_limit, jl_length, jl_limit, phase_duration, depart, v0f, vlen;
+    std::vector<float> road_length, road_limit, jl_length, jl_limit, phase_duration, depart, v0f, vlen, vend;
     tsim_network net{};
     tsim_trips trips{};
     std::vector<int> road_off, junc_off, rl_off, jl_off, veh_off;
@@ -567,6 +581,7 @@ int make_union(const tsim_network* nets, const tsim_trips* trips, const tsim_par
             U.depart.push_back(T.depart_time[i]);
             U.v0f.push_back(T.v0_factor[i]);
             U.vlen.push_back(T.length[i]);
+            U.vend.push_back(T.end_s ? T.end_s[i] : -1.0f);
         }
         for (int e = 0; e < T.route_begin[T.n_vehicles]; ++e) U.route_roads.push_back(T.route_roads[e] + ro);
         U.road_off.push_back(ro + N.n_roads);
@@ -600,6 +615,7 @@ int make_union(const tsim_network* nets, const tsim_trips* trips, const tsim_par
     T.route_roads = U.route_roads.data();
     T.v0_factor = U.v0f.data();
     T.length = U.vlen.data();
+    T.end_s = U.vend.data();
     return TSIM_OK;
 }
 
@@ -721,6 +737,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.route, std::max<size_t>(c.E, 1) * 4);
     add(&D.vf, std::max<size_t>(N, 1) * 4);
     add(&D.vlen, std::max<size_t>(N, 1) * 4);
+    add(&D.vend, std::max<size_t>(N, 1) * 4);
     add(&D.status, std::max<size_t>(N, 1) * 4);
     add(&D.finish_step, std::max<size_t>(N, 1) * 4);
     add(&D.q_begin, (R + 1) * 4);
@@ -973,7 +990,7 @@ int upload_state(tsim_handle* h, int k, int64_t step, const int32_t* status, con
             o.f = B.vf[i];
             o.rp = B.rstart[i] + route_pos[i - g.v0];
             o.rem = B.rstart[i] + B.rlen[i] - o.rp - 1;
-            o.nr = o.rem > 0 ? B.route[o.rp + 1] : -1;
+            o.nr = next_word(B, i, o.rp, o.rem);
             slots.push_back(B.lane_base[m] + (uint32_t)c);
             recs.push_back(o);
         }
@@ -1226,6 +1243,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
     e = e ? e : chk(up_range(h, (int32_t*)D.route, B.route, sp.e0, sp.e1), "trips");
     e = e ? e : chk(up_range(h, (float*)D.vf, B.vf, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (float*)D.vlen, B.vlen, sp.v0, sp.v1), "trips");
+    e = e ? e : chk(up_range(h, (float*)D.vend, B.vend, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (int32_t*)D.q_begin, B.q_begin, sp.r0, sp.r1 + 1), "queues");
     {
         // queue entries of the span's roads are those of its vehicles
@@ -1242,7 +1260,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
             q.f = B.vf[v];
             q.rp = rb;
             q.rem = rl - 1;
-            q.nr = rl > 1 ? B.route[rb + 1] : -1;
+            q.nr = next_word(B, v, rb, rl - 1);
         }
         e = e ? e : chk(up_range(h, (QRec*)D.q_rec, qr, k0, k1), "queues");
     }
@@ -1922,7 +1940,7 @@ static bool roads_joined(const Build& B, int a, int b)
     return false;
 }
 
-static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* roads_local, int32_t len)
+static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* roads_local, int32_t len, float end_s)
 {
     if (!h || !roads_local || len < 1 || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
         return fail(nullptr, TSIM_EINVAL, "bad arguments");
@@ -1939,6 +1957,8 @@ static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* r
         if (c > 0 && !roads_joined(B, roads[c - 1], roads[c]))
             return fail(&h->err, TSIM_EINVAL, "consecutive roads of the route are not joined by a junction lane");
     }
+    if (!(end_s < 0.0f) && !(end_s > 0.0f && end_s <= B.lane_len[B.tile_lane_begin[roads[len - 1]]]))
+        return fail(&h->err, TSIM_EINVAL, "end position beyond the route's last road");
     if ((long long)B.route.size() + len > h->cap.E)
         return fail(&h->err, TSIM_ENOMEM, "no room left for changed routes");
     // where the vehicle is: status, and for an active vehicle its lane and
@@ -1950,7 +1970,10 @@ static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* r
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (st == TSIM_FINISHED) return fail(&h->err, TSIM_EINVAL, "the vehicle has finished its trip");
     const int32_t nst = (int32_t)B.route.size();
-    const int32_t rem = len - 1, nr = len > 1 ? roads[1] : -1;
+    const float new_end = end_s < 0.0f ? -1.0f : end_s;
+    const int32_t rem = len - 1;
+    // the record's next-road word (on a one-road route, the trip's end)
+    const int32_t nr = len > 1 ? roads[1] : end_word(new_end, B.lane_len[B.tile_lane_begin[roads[len - 1]]]);
     if (st == TSIM_WAITING) {
         const int origin = B.route[B.rstart[i]];
         if (roads[0] != origin) return fail(&h->err, TSIM_EINVAL, "a waiting vehicle's route must start at its origin road");
@@ -1959,7 +1982,7 @@ static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* r
         for (int e = B.q_begin[origin]; e < B.q_begin[origin + 1]; ++e)
             if (B.q_veh[e] == i) q = e;
         if (q < 0) return fail(&h->err, TSIM_ESTATE, "vehicle missing from its departure queue");
-        const uint32_t mask = depart_mask(B, origin, nr);
+        const uint32_t mask = depart_mask(B, origin, len > 1 ? roads[1] : -1);
         B.q_mask[q] = mask;
         QRec qr;
         qr.tau = B.tau[i];
@@ -2002,22 +2025,24 @@ static int route_impl(tsim_handle* h, int k, int32_t vid_local, const int32_t* r
     B.route.insert(B.route.end(), roads.begin(), roads.end());
     B.rstart[i] = nst;
     B.rlen[i] = len;
+    B.vend[i] = new_end;
     HIPCHK(h, up_range(h, (int32_t*)D.route, B.route, nst, nst + len));
+    HIPCHK(h, up_range(h, (float*)D.vend, B.vend, i, i + 1));
     HIPCHK(h, hipMemcpyAsync((void*)(D.route_begin + i), &B.rstart[i], 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
 }
 
-int tsim_set_vehicle_route(tsim_handle* h, int32_t vehicle_id, const int32_t* roads, int32_t n_roads)
+int tsim_set_vehicle_route(tsim_handle* h, int32_t vehicle_id, const int32_t* roads, int32_t n_roads, float end_s)
 {
-    return route_impl(h, -1, vehicle_id, roads, n_roads);
+    return route_impl(h, -1, vehicle_id, roads, n_roads, end_s);
 }
 
 int tsim_batch_set_vehicle_route(tsim_batch* b, int32_t instance, int32_t vehicle_id, const int32_t* roads,
-                                 int32_t n_roads)
+                                 int32_t n_roads, float end_s)
 {
     if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
-    return route_impl(b, instance, vehicle_id, roads, n_roads);
+    return route_impl(b, instance, vehicle_id, roads, n_roads, end_s);
 }
 
 int tsim_batch_set_horizon(tsim_batch* b, int32_t instance, int64_t n_steps)
@@ -2383,6 +2408,7 @@ bool append_build(tsim_handle* h, const Build& M, uint64_t seed, Span& sp)
         B.tau.push_back(M.tau[i]);
         B.vf.push_back(M.vf[i]);
         B.vlen.push_back(M.vlen[i]);
+        B.vend.push_back(M.vend[i]);
         B.route_begin.push_back(M.route_begin[i + 1] + (int)E0);
         B.rstart.push_back(M.rstart[i] + (int)E0);
         B.rlen.push_back(M.rlen[i]);
@@ -2454,6 +2480,7 @@ void pop_build(tsim_handle* h)
     B.tau.resize(v0);
     B.vf.resize(v0);
     B.vlen.resize(v0);
+    B.vend.resize(v0);
     B.route_begin.resize(v0 + 1);
     B.route.resize(e0);
     B.rstart.resize(v0);

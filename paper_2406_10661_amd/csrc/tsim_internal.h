@@ -135,6 +135,23 @@ struct __align__(16) LaneInfo {
     int32_t pad1;
 };
 
+// A vehicle record's next-road word: on the last road of the trip (no next
+// road) it holds the trip's end position instead, as float bits: end_s when
+// it lies before the road's end, else the road's end
+__host__ __device__ inline int32_t end_word(float end_s, float road_len)
+{
+    const float e = (end_s >= 0.0f && end_s < road_len) ? end_s : road_len;
+    int32_t w;
+    __builtin_memcpy(&w, &e, 4);
+    return w;
+}
+__host__ __device__ inline float word_end(int32_t w)
+{
+    float e;
+    __builtin_memcpy(&e, &w, 4);
+    return e;
+}
+
 // order-preserving map of floats to ints (for atomicMax on floats)
 __host__ __device__ inline int f2o(float f)
 {
@@ -248,6 +265,7 @@ struct DevNet {
     const int32_t* route;
     const float* vf;
     const float* vlen;
+    const float* vend;               // [N] trip end position on the last road, < 0: its end
     int32_t* status;
     int32_t* finish_step;
     const int32_t* q_begin;          // [R+1] departure queue of each origin road

@@ -68,6 +68,10 @@ struct Lead {
 __device__ __forceinline__ float lead_rear(const Lead& L) { return L.a + L.b; }
 __device__ __forceinline__ float lead_gap(const Lead& L, float x) { return (L.a - x) + L.b; }
 
+// a record's next road, -1 on the last road of its trip (whose next-road
+// word holds the trip's end position, end_word)
+__device__ __forceinline__ int next_road(const VehRec& r) { return r.rem > 0 ? r.nr : -1; }
+
 __device__ __forceinline__ bool ahead(float xa, int va, float xb, int vb)
 {
     return xa > xb || (xa == xb && va < vb);
@@ -267,7 +271,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
             VehRec z = D.inbox[m];
             // the entrant's next road (its writer leaves it to this kernel,
             // so that the update does not wait on the route load)
-            z.nr = z.rem > 0 ? D.route[z.rp + 1] : -1;
+            z.nr = z.rem > 0 ? D.route[z.rp + 1] : end_word(D.vend[z.vid], D.lane_len[m]);
             if (s.cnt < D.lane_cap[m]) {
                 slab[D.lane_base[m] + s.cnt] = z;
                 if (s.cnt == 0) s.front_reach = front_reach(z.x, z.v, D.lane_len[m], P);
@@ -1017,7 +1021,8 @@ __device__ DirEval mobil_side(const DevNet& D, const TS& S, const V& view, const
     // desired speeds in lane k from k's own limit (lanes of a road may have
     // different limits)
     const float lim_k = S.lim[k];
-    const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, rec.nr, jq_get(jqp, d), false), len, P);
+    const float ta_e = accel(rec.v, rec.f * lim_k, rec.x, tld, stop_at(S, k, next_road(rec), jq_get(jqp, d), false),
+                             len, P);
     float d_new = 0.0f, d_old = 0.0f;
     if (tf >= 0) {
         const float a_tf = view.aown(tf);
@@ -1115,7 +1120,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         uint32_t gmask = 0u;
         int qm = -1, q0 = -1, qp = -1;
         if (!is_jl) {
-            if (rec.nr < 0) {
+            if (rec.rem == 0) {
                 gmask = nroad >= 32 ? 0xFFFFFFFFu : ((1u << nroad) - 1u);
             } else {
                 // branch-free so that the unrolled LDS reads issue together
@@ -1141,10 +1146,10 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         } else {
             ld = lookahead(D, S, view, rsum, li, q0, rec.rp, rec.rem);
         }
-        const bool stop = stop_at(S, li, rec.nr, q0, true);
+        const bool stop = stop_at(S, li, next_road(rec), q0, true);
         const float a = accel(rec.v, rec.f * S.lim[li], rec.x, ld, stop, S.len[li], P);
         int mt = -1;
-        if (!is_jl && rec.nr >= 0 && !((gmask >> li) & 1u)) {
+        if (!is_jl && rec.rem > 0 && !((gmask >> li) & 1u)) {
             int bl = -1, bd = 1 << 20;
             for (int b = 0; b < nroad; ++b)
                 if ((gmask >> b) & 1u) {
@@ -1377,7 +1382,7 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             }
         }
         const int qn = jq_get(jqp, nli - li);   // junction lane from the lane it ends the step in
-        if (stop_at(S, nli, rec.nr, qn, true)) {
+        if (stop_at(S, nli, next_road(rec), qn, true)) {
             if (len < Bd) {
                 Bd = len;
                 vcap = 0.0f;
@@ -1392,7 +1397,9 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
         }
         int kind = dec ? 1 : 0;
         int tgt_local = nli;
-        if (xn > len) {
+        // the lane end, or on the trip's last road its end position
+        const float xend = (!is_jl && rec.rem == 0) ? word_end(rec.nr) : len;
+        if (xn > xend) {
             if (!is_jl && rec.rem == 0) {
                 kind = 4;
                 D.status[rec.vid] = 2;

@@ -38,7 +38,8 @@ class tsim_network(C.Structure):
 
 class tsim_trips(C.Structure):
     _fields_ = [("n_vehicles", C.c_int32), ("depart_time", C.c_void_p), ("route_begin", C.c_void_p),
-                ("route_roads", C.c_void_p), ("v0_factor", C.c_void_p), ("length", C.c_void_p)]
+                ("route_roads", C.c_void_p), ("v0_factor", C.c_void_p), ("length", C.c_void_p),
+                ("end_s", C.c_void_p)]
 
 
 class tsim_params(C.Structure):
@@ -112,10 +113,10 @@ def lib():
         L.tsim_set_signal_phases_noalloc.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_lane_max_speed.argtypes = [P, P, P, C.c_int32]
         L.tsim_set_lane_restriction.argtypes = [P, P, P, C.c_int32]
-        L.tsim_set_vehicle_route.argtypes = [P, C.c_int32, P, C.c_int32]
+        L.tsim_set_vehicle_route.argtypes = [P, C.c_int32, P, C.c_int32, C.c_float]
         L.tsim_set_trajectory.argtypes = [P, P, C.c_int64, C.c_int32]
         L.tsim_get_trajectory_count.argtypes = [P, P]
-        L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32]
+        L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32, C.c_float]
         L.tsim_batch_set_lane_max_speed.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_lane_restriction.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
@@ -186,12 +187,16 @@ class _Inputs:
             route_begin=i32(trips.route_begin), route_roads=i32(trips.route_roads),
             v0_factor=f32(trips.v0_factor), length=f32(trips.length))
         a = self.arrays
+        end_s = getattr(trips, "end_s", None)
+        if end_s is not None:
+            a["end_s"] = f32(end_s)
         self.net = tsim_network(net.n_junctions, net.n_roads, *[_p(a[k]) for k in (
             "road_from", "road_to", "road_lane_begin", "road_length", "road_limit")], net.n_jlanes,
             *[_p(a[k]) for k in ("jl_in_lane", "jl_out_lane", "jl_length", "jl_limit", "junc_phase_begin",
                                  "phase_duration", "phase_green_begin", "phase_green_jl", "junc_policy")])
         self.trips = tsim_trips(trips.n_vehicles, *[_p(a[k]) for k in (
-            "depart_time", "route_begin", "route_roads", "v0_factor", "length")])
+            "depart_time", "route_begin", "route_roads", "v0_factor", "length")],
+            _p(a["end_s"]) if "end_s" in a else None)
         self.params = _Inputs.params_of(params)
 
     @staticmethod
@@ -284,11 +289,13 @@ class Sim:
         rec = np.sort(rec, order=["step", "vehicle"])
         return {f: rec[f].copy() for f in rec.dtype.names}, int(n[0]) - k
 
-    def set_vehicle_route(self, vid, roads):
+    def set_vehicle_route(self, vid, roads, end_s=None):
         """Vehicle vid follows `roads` (beginning with the road it is on) from
-        the next step on."""
+        the next step on; its trip ends at end_s metres along the last road
+        (None: that road's end)."""
         r = np.ascontiguousarray(roads, np.int32)
-        _check(lib().tsim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size)), self.h)
+        e = -1.0 if end_s is None else float(end_s)
+        _check(lib().tsim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size), e), self.h)
 
     def set_lane_max_speed(self, lanes, speeds):
         """Speed limits of lanes (network lane ids) from the next step on."""
@@ -614,9 +621,10 @@ class Batch:
         p = np.ascontiguousarray(policies, np.int32)
         _check(lib().tsim_batch_set_signal_policy(self.h, int(instance), _p(j), _p(p), int(j.size)), self.h)
 
-    def set_vehicle_route(self, instance, vid, roads):
+    def set_vehicle_route(self, instance, vid, roads, end_s=None):
         r = np.ascontiguousarray(roads, np.int32)
-        _check(lib().tsim_batch_set_vehicle_route(self.h, int(instance), int(vid), _p(r), int(r.size)), self.h)
+        e = -1.0 if end_s is None else float(end_s)
+        _check(lib().tsim_batch_set_vehicle_route(self.h, int(instance), int(vid), _p(r), int(r.size), e), self.h)
 
     def set_lane_max_speed(self, instance, lanes, speeds):
         l = np.ascontiguousarray(lanes, np.int32)

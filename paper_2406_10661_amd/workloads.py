@@ -117,6 +117,7 @@ class Trips:
     route_roads: np.ndarray   # int32   [sum of route lengths]
     v0_factor: np.ndarray     # float32 [N]  desired speed = v0_factor * lane limit
     length: np.ndarray        # float32 [N]
+    end_s: np.ndarray = None  # float32 [N]  trip end position on the last road (None: its end)
 
     @property
     def n_vehicles(self):
@@ -142,7 +143,8 @@ def save_workload(w: Workload, path):
     for f in fields(Network):
         arrs["network." + f.name] = getattr(w.network, f.name)
     for f in fields(Trips):
-        arrs["trips." + f.name] = getattr(w.trips, f.name)
+        if getattr(w.trips, f.name) is not None:
+            arrs["trips." + f.name] = getattr(w.trips, f.name)
     for k, v in asdict(w.params).items():
         arrs["params." + k] = np.array(v)
     np.savez(path, **arrs)
@@ -153,7 +155,7 @@ def load_workload(path) -> Workload:
     from dataclasses import fields
     with np.load(path, allow_pickle=False) as z:
         net = Network(**{f.name: z["network." + f.name] for f in fields(Network)})
-        trips = Trips(**{f.name: z["trips." + f.name] for f in fields(Trips)})
+        trips = Trips(**{f.name: z["trips." + f.name] for f in fields(Trips) if "trips." + f.name in z.files})
         params = Params(**{f.name: type(f.default)(z["params." + f.name][()]) for f in fields(Params)})
         return Workload(str(z["name"][()]), net, trips, params, int(z["n_steps"][()]))
 

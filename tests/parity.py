@@ -41,8 +41,8 @@ def oracle_one_step(O, net, trips, params, st):
         o.set_lane_max_speed(ids, np.asarray(lim, np.float32).astype(np.float64))
     if "restrictions" in st:
         o.set_lane_restriction(*st["restrictions"])
-    for vid, roads in st.get("routes", ()):
-        o.set_vehicle_route(vid, roads)
+    for vid, roads, *end in st.get("routes", ()):
+        o.set_vehicle_route(vid, roads, *end)
     o.step(1)
     return o
 
@@ -62,8 +62,8 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False
             g.set_lane_max_speed(*st["lane_limits"])
         if "restrictions" in st:
             g.set_lane_restriction(*st["restrictions"])
-        for vid, roads in st.get("routes", ()):
-            g.set_vehicle_route(vid, roads)
+        for vid, roads, *end in st.get("routes", ()):
+            g.set_vehicle_route(vid, roads, *end)
         g.step(1)
     gst = g.get_state()
     gm = g.metrics()

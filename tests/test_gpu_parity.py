@@ -309,6 +309,58 @@ def test_lane_restriction_in_a_batch_matches_alone(Sim):
             assert np.array_equal(a[f], e[f]), (k, f)
 
 
+def _with_trip_ends(net, trips, rng, lo=0.2):
+    """The same trips with end positions U(lo, 1) of their last road's
+    length (float32, as both sides read them)."""
+    import dataclasses
+    last = trips.route_roads[trips.route_begin[1:] - 1]
+    e = (rng.uniform(lo, 1.0, trips.n_vehicles) * net.road_length[last]).astype(np.float32)
+    return dataclasses.replace(trips, end_s=e)
+
+
+def test_trip_end_positions_one_step(O, Sim):
+    """Trips ending at positions along their last road (Section 3.2
+    set_vehicle_route end position; an AOI's connection as the trip's end):
+    one step from a loaded 4x4-grid state, vehicles already past their end
+    position finishing in it."""
+    w = W.config1()
+    trips = _with_trip_ends(w.network, w.trips, np.random.default_rng(11))
+    st = synthetic_state(w.network, trips, 300, seed=23, p_active=0.7)
+    rep = compare_one_step(O, Sim, w.network, trips, w.params, st)
+    _log("c1_trip_end_positions", rep)
+    assert rep["active"] > 300
+
+
+def test_trip_end_positions_horizon_statistics(O, Sim):
+    """The 4x4 grid's 600-step horizon with trip end positions: completed
+    trips and mean road speed within 1% of the oracle's, more trips ending
+    than with trips to the road ends."""
+    w = W.config1()
+    trips = _with_trip_ends(w.network, w.trips, np.random.default_rng(12))
+    o = O.OracleSim(w.network, trips, w.params)
+    o.step(w.n_steps)
+    om = o.metrics()
+    g = Sim(w.network, trips, w.params)
+    g.step(w.n_steps)
+    gm = g.metrics()
+    _log("c1_trip_end_horizon", dict(oracle_finished=om["finished"], gpu_finished=gm["n_finished"],
+                                     oracle_speed=om["mean_speed_avg"], gpu_speed=gm["mean_speed_avg"]))
+    assert gm["errors"] == 0
+    assert abs(gm["n_finished"] - om["finished"]) <= 0.01 * om["finished"]
+    assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
+
+
+def test_reroute_with_end_positions_one_step(O, Sim):
+    """Rerouted vehicles given end positions on their new last road (half of
+    the road's length): one step from the same state on both sides."""
+    w = W.config1()
+    st = synthetic_state(w.network, w.trips, 150, seed=24, p_active=0.7)
+    routes = _reroutes(w.network, w.trips, st, np.random.default_rng(13), 150)
+    st["routes"] = [(v, r, float(np.float32(0.5 * w.network.road_length[r[-1]]))) for v, r in routes]
+    rep = compare_one_step(O, Sim, w.network, w.trips, w.params, st)
+    _log("c1_reroute_end_positions", rep)
+
+
 def _reroutes(net, trips, st, rng, n):
     """Valid new routes for n vehicles of state st: a waiting vehicle ends
     its trip on its origin road; an active one on a road lane turns onto a

@@ -91,4 +91,7 @@ def test_workload_file_roundtrip(tmp_path):
         assert a.dtype == b.dtype and np.array_equal(a, b), f.name
     for f in fields(W.Trips):
         a, b = getattr(w.trips, f.name), getattr(v.trips, f.name)
+        if a is None:   # optional field left unset
+            assert b is None, f.name
+            continue
         assert a.dtype == b.dtype and np.array_equal(a, b), f.name
