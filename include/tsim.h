@@ -104,7 +104,7 @@ typedef struct tsim_trips {
     const float *end_s;              /* [n] or NULL: where the trip ends on the last road of its route, metres
                                       * from the road's start (the trip ends in the step the vehicle's front
                                       * passes it; Section 3.2 set_vehicle_route end position, an AOI's
-                                      * connection as the trip's end); negative or NULL: the road's end */
+                                      * connection (Appendix B.1) as the trip's end); negative or NULL: the road's end */
 } tsim_trips;
 
 /* Model parameters (Appendix B.3; the MOBIL threshold, safe deceleration,

@@ -953,7 +953,7 @@ static void step_once(osim *s)
         }
         /* U5: lane end, or the trip's end position on its last road
          * ([reading] Section 3.2 set_vehicle_route's end position, an AOI's
-         * connection as the trip's end: the trip ends in the step its front
+         * connection (Appendix B.1) as the trip's end: the trip ends in the step its front
          * passes that position) */
         int nl = ln, nk = s->k[i], nst = ACTIVE;
         double len = s->lane_len[ln];

@@ -1,6 +1,6 @@
 """Pins of the oracle's trip end positions (Section 3.2 set_vehicle_route:
 the trip's end position on the last road; an AOI's connection as a trip's
-end, Section 3.3 / Appendix B.2).
+end, Appendix B.1).
 
 Reading: a trip ends in the step in which the vehicle's front passes its end
 position on the last road of its route (strictly beyond it, as at a road
