@@ -67,6 +67,8 @@ def lib():
         L.osim_idm.restype = C.c_double
         L.osim_idm.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double]
         L.osim_philox.argtypes = [C.c_uint64, C.c_void_p, C.c_void_p]
+        L.osim_shortest_routes.restype = C.c_int
+        L.osim_shortest_routes.argtypes = [C.c_void_p] + [C.c_void_p] * 2 + [C.c_int] + [C.c_void_p] * 4 + [C.c_int]
         _lib = L
     return _lib
 
@@ -202,6 +204,25 @@ class OracleSim:
         out = np.zeros(max_len, np.int32)
         lib().osim_get_route(self.h, int(vid), _p(k), _p(n), _p(out), max_len)
         return int(k[0]), out[:int(n[0])].copy()
+
+    def shortest_routes(self, origins, dests, price=None, road_time=None):
+        """Routes of least cost for (origin road, destination road) pairs
+        under the lane limits and restrictions in force, road prices and
+        road times (None: free-flow), as (begin[n+1], roads, n_unreachable):
+        route c is roads[begin[c]:begin[c+1]], empty when unreachable."""
+        o = np.ascontiguousarray(origins, np.int32)
+        d = np.ascontiguousarray(dests, np.int32)
+        n = int(o.size)
+        pr = None if price is None else np.ascontiguousarray(price, np.float32)
+        rt = None if road_time is None else np.ascontiguousarray(road_time, np.float32)
+        begin = np.zeros(n + 1, np.int32)
+        cap = max(1, n * self.R)
+        roads = np.zeros(cap, np.int32)
+        bad = lib().osim_shortest_routes(self.h, None if pr is None else _p(pr), None if rt is None else _p(rt),
+                                         n, _p(o), _p(d), _p(begin), _p(roads), cap)
+        if bad < 0:
+            raise RuntimeError("route buffer too small")
+        return begin, roads[:begin[n]].copy(), int(bad)
 
     def junctions(self):
         p = np.zeros(self.net.n_junctions, np.int32)

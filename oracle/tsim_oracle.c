@@ -23,6 +23,8 @@
  *            U5 lane-end transfer, feeder priority, trip completion
  *            U6 metrics (Section 3.3)
  *   commit   state <- next state, t <- t + 1
+ * Between steps: routes of least cost under road prices (Section 4
+ * congestion pricing), computed in FP32 (osim_shortest_routes).
  * Readings of points the paper leaves open are listed next to the code that
  * implements them (tagged [reading]).
  *
@@ -35,7 +37,9 @@
  * travelling time, mean speed and its horizon average, lane queue length
  * and cooperative yielding, lane restrictions (departures, lane changes,
  * closed junction lanes and the lane group they leave), trip end positions,
- * each shown to fail under a named mistake.
+ * each shown to fail under a named mistake; shortest routes against
+ * hand-derived routes, brute force over every simple route of small
+ * networks with exact costs, and scipy's Dijkstra on a grid.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1212,3 +1216,169 @@ void osim_last_diag(const osim *s, double *margin, double *mobil, int *decision,
 }
 
 int osim_n_vehicles(const osim *s) { return s->N; }
+
+/* ------------------------------------------------------------------------ */
+/* Shortest routes (Section 4 "Congestion Pricing": drivers move to routes  */
+/* of lower cost once roads carry prices; Appendix F congestion pricing:    */
+/* every road may carry a price; Appendix E travel demand: routes of        */
+/* shortest travel time).                                                    */
+/* [reading] The cost of a route is the sum, over every road after its      */
+/* first, of the road's movement cost: the fastest open junction lane into  */
+/* it from the road before (length / limit), plus its own travel time (its  */
+/* length over the highest limit of its lanes, or a time the caller gives), */
+/* plus its price.  The route is an integer result decided by these sums,   */
+/* so it is computed in FP32, the precision the GPU takes it in; the       */
+/* cost-to-go of a road is its movement cost plus the cost-to-go of the     */
+/* road it enters (the order a tree grown from the destination sums in),    */
+/* and of roads with equal candidate costs the smaller id is taken.  A      */
+/* route of more roads than the network has counts as unreachable.          */
+/* Distances by Dijkstra from the destination over the reversed movements,  */
+/* the minimum found by a linear scan.                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int R;
+    int *fb, *fto;     /* forward movements: [R+1], [E] (ascending target per road) */
+    float *fw;         /* [E] movement cost */
+    int *rb, *rfrom;   /* reversed: movements entering each road */
+    float *rw;
+} ograph;
+
+static void ograph_free(ograph *g)
+{
+    free(g->fb); free(g->fto); free(g->fw); free(g->rb); free(g->rfrom); free(g->rw);
+}
+
+/* road travel time: length over the highest limit of its lanes (FP32) */
+static float road_time_of(const osim *s, int r, const float *road_time)
+{
+    if (road_time) return road_time[r];
+    float vmax = 0.0f;
+    for (int l = s->road_lane_begin[r]; l < s->road_lane_begin[r + 1]; ++l)
+        if ((float)s->lane_lim[l] > vmax) vmax = (float)s->lane_lim[l];
+    return (float)s->lane_len[s->road_lane_begin[r]] / vmax;
+}
+
+static void ograph_build(const osim *s, const float *price, const float *road_time, ograph *g)
+{
+    int R = s->R;
+    g->R = R;
+    /* for the road being scanned: cmin[r2], the cheapest junction lane into
+     * r2 (seen[r2] == r once one was found), and the list of its targets */
+    float *cmin = (float *)xcalloc(R, sizeof(float));
+    int *seen = (int *)xcalloc(R, sizeof(int));
+    int *tl = (int *)xcalloc(s->NJL, sizeof(int));
+    for (int r = 0; r < R; ++r) seen[r] = -1;
+    g->fb = (int *)xcalloc(R + 1, sizeof(int));
+    int cap = 16, E = 0;
+    g->fto = (int *)xcalloc(cap, sizeof(int));
+    g->fw = (float *)xcalloc(cap, sizeof(float));
+    for (int r = 0; r < R; ++r) {
+        g->fb[r] = E;
+        int nt = 0;
+        for (int l = s->road_lane_begin[r]; l < s->road_lane_begin[r + 1]; ++l)
+            for (int e = s->out_begin[l]; e < s->out_begin[l + 1]; ++e) {
+                int q = s->out_jl[e];
+                if (!jl_open(s, q)) continue;
+                int r2 = s->lane_road[s->jl_out[q - s->NRL]];
+                float c = (float)s->lane_len[q] / (float)s->lane_lim[q];
+                if (seen[r2] != r) { seen[r2] = r; cmin[r2] = c; tl[nt++] = r2; }
+                else if (c < cmin[r2]) cmin[r2] = c;
+            }
+        /* targets of road r in ascending id (insertion sort of a short list) */
+        for (int a = 1; a < nt; ++a)
+            for (int b = a; b > 0 && tl[b - 1] > tl[b]; --b) { int t = tl[b]; tl[b] = tl[b - 1]; tl[b - 1] = t; }
+        for (int c = 0; c < nt; ++c) {
+            int r2 = tl[c];
+            if (E == cap) {
+                cap *= 2;
+                g->fto = (int *)realloc(g->fto, cap * sizeof(int));
+                g->fw = (float *)realloc(g->fw, cap * sizeof(float));
+            }
+            float w = cmin[r2] + road_time_of(s, r2, road_time);
+            w = w + (price ? price[r2] : 0.0f);
+            g->fto[E] = r2;
+            g->fw[E] = w;
+            ++E;
+        }
+    }
+    g->fb[R] = E;
+    /* reversed movements */
+    g->rb = (int *)xcalloc(R + 1, sizeof(int));
+    g->rfrom = (int *)xcalloc(E, sizeof(int));
+    g->rw = (float *)xcalloc(E, sizeof(float));
+    for (int e = 0; e < E; ++e) g->rb[g->fto[e] + 1]++;
+    for (int r = 0; r < R; ++r) g->rb[r + 1] += g->rb[r];
+    int *fill = (int *)xcalloc(R, sizeof(int));
+    for (int r = 0; r < R; ++r)
+        for (int e = g->fb[r]; e < g->fb[r + 1]; ++e) {
+            int t = g->fto[e], k = g->rb[t] + fill[t]++;
+            g->rfrom[k] = r;
+            g->rw[k] = g->fw[e];
+        }
+    free(fill); free(cmin); free(seen); free(tl);
+}
+
+/* cost-to-go of every road to road d (FP32; +inf where d cannot be reached) */
+static void cost_to_go(const ograph *g, int d, float *dist)
+{
+    int R = g->R;
+    unsigned char *done = (unsigned char *)xcalloc(R, 1);
+    for (int r = 0; r < R; ++r) dist[r] = INFINITY;
+    dist[d] = 0.0f;
+    for (;;) {
+        int u = -1;
+        for (int r = 0; r < R; ++r)
+            if (!done[r] && dist[r] < INFINITY && (u < 0 || dist[r] < dist[u])) u = r;
+        if (u < 0) break;
+        done[u] = 1;
+        for (int k = g->rb[u]; k < g->rb[u + 1]; ++k) {
+            int r = g->rfrom[k];
+            float c = g->rw[k] + dist[u];
+            if (c < dist[r]) dist[r] = c;
+        }
+    }
+    free(done);
+}
+
+/* Routes for n (origin road, destination road) pairs under the lane limits
+ * and restrictions in force, road prices price[R] (NULL: none) and road
+ * times road_time[R] (NULL: free-flow).  out_begin[n+1] is a CSR into
+ * out_roads (origin first, destination last; empty when the destination
+ * cannot be reached).  Returns the number of unreachable pairs, or -1 when
+ * more than cap roads would be written. */
+int osim_shortest_routes(const osim *s, const float *price, const float *road_time, int n, const int *origin,
+                         const int *dest, int *out_begin, int *out_roads, int cap)
+{
+    ograph g;
+    ograph_build(s, price, road_time, &g);
+    float *dist = (float *)xcalloc(s->R, sizeof(float));
+    int last = -1, bad = 0, pos = 0;
+    out_begin[0] = 0;
+    for (int p = 0; p < n; ++p) {
+        if (dest[p] != last) { cost_to_go(&g, dest[p], dist); last = dest[p]; }
+        int r = origin[p], start = pos, ok = dist[r] < INFINITY;
+        if (ok) {
+            if (pos >= cap) { pos = -1; break; }
+            out_roads[pos++] = r;
+        }
+        while (ok && r != dest[p]) {
+            int best = -1;
+            float bc = INFINITY;
+            for (int e = g.fb[r]; e < g.fb[r + 1]; ++e) {
+                float c = g.fw[e] + dist[g.fto[e]];
+                if (c < bc) { bc = c; best = g.fto[e]; }
+            }
+            if (best < 0 || pos - start >= s->R) { ok = 0; break; }
+            if (pos >= cap) { pos = -1; break; }
+            out_roads[pos++] = best;
+            r = best;
+        }
+        if (pos < 0) break;
+        if (!ok) { pos = start; ++bad; }
+        out_begin[p + 1] = pos;
+    }
+    free(dist);
+    ograph_free(&g);
+    return pos < 0 ? -1 : bad;
+}

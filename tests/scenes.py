@@ -107,3 +107,39 @@ def plus_network(length=200.0, limit=13.9, policy=W.POLICY_FIXED_TIME):
     xy = np.array([[0.0, 200.0], [400.0, 200.0], [200.0, 0.0], [200.0, 400.0], [200.0, 200.0]])
     return W._build_network(xy, np.array([[0, 4], [1, 4], [2, 4], [3, 4]]), [length] * 4, [1] * 4,
                             [limit] * 4, policy=policy)
+
+
+def diamond_network():
+    """Two ways from road 0 (O->S) to road 5 (T->Z): over A (roads 1 S->A,
+    3 A->T) or over B (roads 2 S->B, 4 B->T).  Road lanes: road 0 lanes 0-1,
+    road 1 lane 2, road 2 lanes 3-4, road 3 lane 5, road 4 lane 6, road 5
+    lane 7; junction lanes 8-15 (q0-q7): q0 0->2 and q1 1->2 (two ways into
+    road 1; q1 is 200 m long), q2 1->3, q3 2->5, q4 3->6, q5 4->6, q6 5->7,
+    q7 6->7.  Every limit is 8 m/s and every other junction lane 8 m long,
+    so a junction lane takes 1 s (q1 25 s) and roads 0-5 take 10, 20, 10,
+    20, 20 and 10 s."""
+    xy = np.array([[-100.0, 0.0], [0.0, 0.0], [100.0, 100.0], [100.0, -100.0], [200.0, 0.0], [300.0, 0.0]])
+    return W.Network(
+        junction_xy=xy,
+        road_from=np.array([0, 1, 1, 2, 3, 4], np.int32),
+        road_to=np.array([1, 2, 3, 4, 4, 5], np.int32),
+        road_lane_begin=np.array([0, 2, 3, 5, 6, 7, 8], np.int32),
+        road_length=np.array([80, 160, 80, 160, 160, 80], np.float32),
+        road_limit=np.full(6, 8.0, np.float32),
+        jl_in_lane=np.array([0, 1, 1, 2, 3, 4, 5, 6], np.int32),
+        jl_out_lane=np.array([2, 2, 3, 5, 6, 6, 7, 7], np.int32),
+        jl_length=np.array([8, 200, 8, 8, 8, 8, 8, 8], np.float32),
+        jl_limit=np.full(8, 8.0, np.float32),
+        junc_phase_begin=np.zeros(7, np.int32),
+        phase_duration=np.zeros(0, np.float32),
+        phase_green_begin=np.zeros(1, np.int32),
+        phase_green_jl=np.zeros(0, np.int32),
+        junc_policy=np.full(6, W.POLICY_NONE, np.int32),
+    )
+
+
+def empty_trips():
+    """A trip table with no vehicles (for queries of the network alone)."""
+    z = np.zeros(0, np.float32)
+    return W.Trips(depart_time=z, route_begin=np.zeros(1, np.int32), route_roads=np.zeros(0, np.int32),
+                   v0_factor=z, length=z)
