@@ -248,6 +248,55 @@ int tsim_set_lane_restriction(tsim_handle *h, const int32_t *lane_ids, const int
  * Synchronises the stream. */
 int tsim_set_vehicle_route(tsim_handle *h, int32_t vehicle_id, const int32_t *roads, int32_t n_roads, float end_s);
 
+/* ---- Shortest routes on the device (Section 4 "Congestion Pricing": once
+ * roads carry prices, drivers move to routes of lower cost; Appendix F:
+ * every road may be priced and the prices change every 20 s; Appendix E:
+ * demand routed by shortest travel time).
+ *
+ * Cost of a route: over every road after its first, the fastest open
+ * junction lane into it (length / limit) plus the road's travel time (its
+ * length over the highest limit of its lanes, or road_time[r] when given)
+ * plus its price road_price[r] (seconds; NULL: none), in FP32; the route of
+ * least cost is taken, and where candidate costs tie, the smaller next road
+ * id.  Prices and times must be >= 0 (+inf closes a road).  Networks of at
+ * most 32,768 roads (a road's cost-to-go is held in LDS per destination).
+ *
+ * Work space: a device buffer the caller allocates (workspace,
+ * workspace_bytes); min_bytes is the least a call takes, hint_bytes routes
+ * the pairs in few passes.  The call synchronises its stream; the buffer is
+ * free again on return. */
+int tsim_route_footprint(const tsim_network *net, int32_t n_pairs, size_t *min_bytes, size_t *hint_bytes);
+
+/* Routes for n (origin road, destination road) pairs of a network given as
+ * host arrays, computed on the current GPU on hip_stream (NULL: the default
+ * stream).  route_begin[n+1] (always filled on success or TSIM_ENOMEM) and
+ * route_roads[max_roads] (origin first, destination last; an unreachable
+ * pair gets an empty route and is counted in *n_unreachable, which may be
+ * NULL).  TSIM_ENOMEM when the routes need more than max_roads entries
+ * (route_begin[n] says how many) or the work space is below min_bytes;
+ * TSIM_EINVAL for a bad network, road id, price or time. */
+int tsim_shortest_routes(const tsim_network *net, const float *road_price, const float *road_time,
+                         const int32_t *origin, const int32_t *dest, int32_t n, void *hip_stream, void *workspace,
+                         size_t workspace_bytes, int32_t *route_begin, int32_t *route_roads, int64_t max_roads,
+                         int32_t *n_unreachable);
+
+/* Work space of tsim_reroute_shortest for n vehicles of handle h. */
+int tsim_reroute_footprint(tsim_handle *h, int32_t n, size_t *min_bytes, size_t *hint_bytes);
+
+/* Vehicles vehicle_ids[0..n-1] (distinct) take, from the next step on, the
+ * route of least cost from where they are to the last road of their route
+ * in force, under the lane limits and restrictions in force: a waiting
+ * vehicle from its origin road, a vehicle on a road lane from that road, a
+ * vehicle on a junction lane through the road that lane enters (as
+ * tsim_set_vehicle_route requires).  Trip end positions are kept.  The
+ * routes are computed on the handle's GPU and written into the records
+ * there.  A vehicle keeps its route when it has finished, its destination
+ * cannot be reached, or the route pool is full (a new route is written over
+ * the rest of the route in force when it fits there, else appended); those
+ * are counted in *n_kept (may be NULL).  Synchronises the stream. */
+int tsim_reroute_shortest(tsim_handle *h, const int32_t *vehicle_ids, int32_t n, const float *road_price,
+                          const float *road_time, void *workspace, size_t workspace_bytes, int32_t *n_kept);
+
 /* Synchronises the stream, then fills *out. */
 int tsim_get_metrics(tsim_handle *h, tsim_metrics *out);
 
@@ -393,6 +442,13 @@ int tsim_batch_set_signal_phases(tsim_batch *b, int32_t instance, const int32_t 
 /* As tsim_set_vehicle_route, for a vehicle of one instance (local ids). */
 int tsim_batch_set_vehicle_route(tsim_batch *b, int32_t instance, int32_t vehicle_id, const int32_t *roads,
                                  int32_t n_roads, float end_s);
+/* As tsim_reroute_footprint and tsim_reroute_shortest, for vehicles of one
+ * instance (local vehicle and road ids; the instance's roads form the
+ * network). */
+int tsim_batch_reroute_footprint(tsim_batch *b, int32_t instance, int32_t n, size_t *min_bytes, size_t *hint_bytes);
+int tsim_batch_reroute_shortest(tsim_batch *b, int32_t instance, const int32_t *vehicle_ids, int32_t n,
+                                const float *road_price, const float *road_time, void *workspace,
+                                size_t workspace_bytes, int32_t *n_kept);
 /* As tsim_set_lane_max_speed, for the lanes of one instance. */
 int tsim_batch_set_lane_max_speed(tsim_batch *b, int32_t instance, const int32_t *lane_ids, const float *max_speed,
                                   int32_t n);

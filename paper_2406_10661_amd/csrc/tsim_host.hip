@@ -3,6 +3,7 @@
 // step driver.  All device memory is carved from the caller's arena; the
 // library itself never allocates device memory.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <limits>
 #include <cstdio>
@@ -14,6 +15,7 @@
 
 #include "../../include/tsim.h"
 #include "tsim_internal.h"
+#include "tsim_route.h"
 
 namespace tsim {
 hipError_t launch_prepare(const DevNet* Dd, const DevNet& H, hipStream_t s);
@@ -31,6 +33,8 @@ hipError_t launch_set_lane_speed(const DevNet& H, const int32_t* ids, const floa
 hipError_t launch_record(const DevNet& H, const int32_t* lane_ext, TrajRec* out, long long cap,
                          unsigned long long* count, int every, hipStream_t s);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
+hipError_t launch_apply_routes(const DevNet& H, const int32_t* n_rp, const int32_t* n_rem, const int32_t* n_nr,
+                               const uint32_t* n_mask, int n_queue, hipStream_t s);
 int update_blocks_per_cu(int sched);
 }  // namespace tsim
 
@@ -2043,6 +2047,315 @@ int tsim_batch_set_vehicle_route(tsim_batch* b, int32_t instance, int32_t vehicl
 {
     if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
     return route_impl(b, instance, vehicle_id, roads, n_roads, end_s);
+}
+
+// ---------------------------------------------------------------------------
+// Shortest routes on the device (Section 4 "Congestion Pricing"; Appendix F
+// road prices; Appendix E routes of shortest time)
+
+// movement graph of a network given as host arrays (one limit per road)
+static int route_graph_of_network(const tsim_network* net, RouteGraph& G, std::string* err)
+{
+    if (!net || net->n_roads < 1 || net->n_jlanes < 0 || !net->road_lane_begin || !net->road_length ||
+        !net->road_limit || (net->n_jlanes > 0 && (!net->jl_in_lane || !net->jl_out_lane || !net->jl_length ||
+                                                   !net->jl_limit))) {
+        *err = "bad network arrays";
+        return TSIM_EINVAL;
+    }
+    const int R = net->n_roads;
+    if (net->road_lane_begin[0] != 0) {
+        *err = "road_lane_begin must start at 0";
+        return TSIM_EINVAL;
+    }
+    for (int r = 0; r < R; ++r)
+        if (net->road_lane_begin[r + 1] <= net->road_lane_begin[r]) {
+            *err = "every road needs at least one lane";
+            return TSIM_EINVAL;
+        }
+    const int NRL = net->road_lane_begin[R];
+    std::vector<int32_t> road_of(NRL);
+    for (int r = 0; r < R; ++r)
+        for (int l = net->road_lane_begin[r]; l < net->road_lane_begin[r + 1]; ++l) road_of[l] = r;
+    G = RouteGraph{};
+    G.R = R;
+    G.road_lane_begin.resize(R + 1);
+    std::iota(G.road_lane_begin.begin(), G.road_lane_begin.end(), 0);
+    G.road_len.assign(net->road_length, net->road_length + R);
+    G.lane_lim.assign(net->road_limit, net->road_limit + R);
+    std::vector<std::array<int32_t, 3>> mv;   // (from road, to road, junction lane)
+    mv.reserve(net->n_jlanes);
+    for (int q = 0; q < net->n_jlanes; ++q) {
+        const int a = net->jl_in_lane[q], b = net->jl_out_lane[q];
+        if (a < 0 || a >= NRL || b < 0 || b >= NRL) {
+            *err = "junction lane joins a lane id out of range";
+            return TSIM_EINVAL;
+        }
+        mv.push_back({road_of[a], road_of[b], q});
+    }
+    std::sort(mv.begin(), mv.end());
+    G.e_begin.assign(R + 1, 0);
+    size_t c = 0;
+    for (int r = 0; r < R; ++r) {
+        G.e_begin[r] = (int32_t)G.e_to.size();
+        while (c < mv.size() && mv[c][0] == r) {
+            const int b = mv[c][1];
+            G.e_to.push_back(b);
+            G.e_jl_begin.push_back((int32_t)G.jl_len.size());
+            for (; c < mv.size() && mv[c][0] == r && mv[c][1] == b; ++c) {
+                G.jl_len.push_back(net->jl_length[mv[c][2]]);
+                G.jl_lim.push_back(net->jl_limit[mv[c][2]]);
+            }
+        }
+    }
+    G.e_begin[R] = (int32_t)G.e_to.size();
+    G.e_jl_begin.push_back((int32_t)G.jl_len.size());
+    return TSIM_OK;
+}
+
+// movement graph of one instance of a handle as it stands: lane limits in
+// force, closed junction lanes left out; local road ids
+static void route_graph_of_build(const Build& B, const Ranges& g, RouteGraph& G)
+{
+    G = RouteGraph{};
+    G.R = g.r1 - g.r0;
+    G.e_begin.assign(G.R + 1, 0);
+    std::vector<std::pair<int32_t, int32_t>> mv;   // (to road, junction lane)
+    for (int r = 0; r < G.R; ++r) {
+        const int rr = g.r0 + r, lb = B.tile_lane_begin[rr], nrl = B.tile_n_road[rr], le = B.tile_lane_begin[rr + 1];
+        G.road_lane_begin.push_back((int32_t)G.lane_lim.size());
+        for (int m = lb; m < lb + nrl; ++m) G.lane_lim.push_back(B.lane_lim[m]);
+        G.road_len.push_back(B.lane_len[lb]);
+        mv.clear();
+        for (int m = lb + nrl; m < le; ++m)
+            if (jl_open(B, m)) mv.push_back({B.jl_out_road[m] - g.r0, m});
+        std::sort(mv.begin(), mv.end());
+        G.e_begin[r] = (int32_t)G.e_to.size();
+        for (size_t c = 0; c < mv.size();) {
+            const int b = mv[c].first;
+            G.e_to.push_back(b);
+            G.e_jl_begin.push_back((int32_t)G.jl_len.size());
+            for (; c < mv.size() && mv[c].first == b; ++c) {
+                G.jl_len.push_back(B.lane_len[mv[c].second]);
+                G.jl_lim.push_back(B.lane_lim[mv[c].second]);
+            }
+        }
+    }
+    G.road_lane_begin.push_back((int32_t)G.lane_lim.size());
+    G.e_begin[G.R] = (int32_t)G.e_to.size();
+    G.e_jl_begin.push_back((int32_t)G.jl_len.size());
+}
+
+int tsim_route_footprint(const tsim_network* net, int32_t n_pairs, size_t* min_bytes, size_t* hint_bytes)
+{
+    if (n_pairs < 0) return fail(nullptr, TSIM_EINVAL, "bad pair count");
+    RouteGraph G;
+    std::string err;
+    const int rc = route_graph_of_network(net, G, &err);
+    if (rc) return fail(nullptr, rc, err);
+    if (min_bytes) *min_bytes = route_workspace_min(G, n_pairs);
+    if (hint_bytes) *hint_bytes = route_workspace_hint(G, n_pairs);
+    return TSIM_OK;
+}
+
+int tsim_shortest_routes(const tsim_network* net, const float* road_price, const float* road_time,
+                         const int32_t* origin, const int32_t* dest, int32_t n, void* hip_stream, void* workspace,
+                         size_t workspace_bytes, int32_t* route_begin, int32_t* route_roads, int64_t max_roads,
+                         int32_t* n_unreachable)
+{
+    if (!route_begin || max_roads < 0 || (max_roads > 0 && !route_roads))
+        return fail(nullptr, TSIM_EINVAL, "bad output arrays");
+    RouteGraph G;
+    std::string err;
+    int rc = route_graph_of_network(net, G, &err);
+    if (rc) return fail(nullptr, rc, err);
+    std::vector<int64_t> begin;
+    std::vector<int32_t> roads;
+    int bad = 0;
+    rc = route_pairs(G, road_price, road_time, origin, dest, n, (hipStream_t)hip_stream, workspace, workspace_bytes,
+                     begin, roads, &bad, &err);
+    if (rc) return fail(nullptr, rc, err);
+    if (begin[n] > std::numeric_limits<int32_t>::max()) return fail(nullptr, TSIM_ENOMEM, "more than 2^31 route roads");
+    for (int p = 0; p <= n; ++p) route_begin[p] = (int32_t)begin[p];
+    if (n_unreachable) *n_unreachable = bad;
+    if (begin[n] > max_roads)
+        return fail(nullptr, TSIM_ENOMEM, "route_roads holds " + std::to_string(max_roads) + " roads, the routes need " +
+                                              std::to_string(begin[n]));
+    std::copy(roads.begin(), roads.end(), route_roads);
+    return TSIM_OK;
+}
+
+static int reroute_footprint_impl(tsim_handle* h, int k, int32_t n, size_t* min_bytes, size_t* hint_bytes)
+{
+    if (!h || n < 0 || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    RouteGraph G;
+    route_graph_of_build(h->B, ranges_of(h->B, k), G);
+    if (min_bytes) *min_bytes = route_workspace_min(G, n);
+    if (hint_bytes) *hint_bytes = route_workspace_hint(G, n);
+    return TSIM_OK;
+}
+
+int tsim_reroute_footprint(tsim_handle* h, int32_t n, size_t* min_bytes, size_t* hint_bytes)
+{
+    return reroute_footprint_impl(h, -1, n, min_bytes, hint_bytes);
+}
+
+int tsim_batch_reroute_footprint(tsim_batch* b, int32_t instance, int32_t n, size_t* min_bytes, size_t* hint_bytes)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return reroute_footprint_impl(b, instance, n, min_bytes, hint_bytes);
+}
+
+// Every listed vehicle takes the least-cost route from where it is to the
+// last road of its route in force (its trip end position kept).  A new route
+// is written over the rest of the vehicle's route in force when it fits
+// there, else appended to the route pool.
+static int reroute_impl(tsim_handle* h, int k, const int32_t* vids_local, int32_t n, const float* price,
+                        const float* road_time, void* ws, size_t ws_bytes, int32_t* n_kept)
+{
+    if (!h || n < 0 || (n > 0 && !vids_local) || k >= h->B.n_inst || (k < 0 && h->B.n_inst != 1))
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    Build& B = h->B;
+    DevNet& D = h->D;
+    const Ranges g = ranges_of(B, k);
+    const int NV = g.v1 - g.v0;
+    std::vector<char> seen(NV, 0);
+    for (int c = 0; c < n; ++c) {
+        const int v = vids_local[c];
+        if (v < 0 || v >= NV) return fail(&h->err, TSIM_EINVAL, "vehicle id out of range");
+        if (seen[v]) return fail(&h->err, TSIM_EINVAL, "a vehicle is listed twice");
+        seen[v] = 1;
+    }
+    if (n_kept) *n_kept = 0;
+    if (n == 0) return TSIM_OK;
+    std::vector<int32_t> st(NV);
+    HIPCHK(h, hipMemcpyAsync(st.data(), D.status + g.v0, (size_t)NV * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::vector<int32_t> lane, rpos, rank;
+    std::vector<float> x, v;
+    bool any_active = false;
+    for (int c = 0; c < n; ++c) any_active |= st[vids_local[c]] == TSIM_ACTIVE;
+    if (any_active) {
+        const int rc = export_state(h, lane, x, v, rpos, rank);
+        if (rc) return rc;
+    }
+    // start road, the road a vehicle on a junction lane keeps, destination
+    struct Job {
+        int i, prefix, rp0;
+        bool waiting;
+    };
+    std::vector<Job> jobs;
+    std::vector<int32_t> po, pd;
+    int kept = 0;
+    for (int c = 0; c < n; ++c) {
+        const int vl = vids_local[c], i = g.v0 + vl;
+        if (st[vl] == TSIM_FINISHED) {
+            ++kept;
+            continue;
+        }
+        const int dest = B.route[B.rstart[i] + B.rlen[i] - 1];
+        Job J{i, -1, B.rstart[i], st[vl] == TSIM_WAITING};
+        int start = B.route[B.rstart[i]];
+        if (!J.waiting && lane[i] < 0) {
+            ++kept;   // not found on any lane (cannot happen at a step boundary)
+            continue;
+        }
+        if (!J.waiting) {
+            const int m = B.int_of_ext[lane[i]];
+            const int cur = B.lane_tile[m];
+            J.rp0 = B.rstart[i] + rpos[i];
+            if (B.jl_out[m] >= 0) {
+                J.prefix = cur;
+                start = B.jl_out_road[m];
+            } else {
+                start = cur;
+            }
+        }
+        jobs.push_back(J);
+        po.push_back(start - g.r0);
+        pd.push_back(dest - g.r0);
+    }
+    RouteGraph G;
+    route_graph_of_build(B, g, G);
+    std::vector<int64_t> begin;
+    std::vector<int32_t> roads;
+    std::string err;
+    int bad = 0;
+    int rc = route_pairs(G, price, road_time, po.data(), pd.data(), (int)jobs.size(), h->stream, ws, ws_bytes, begin,
+                         roads, &bad, &err);
+    if (rc) return fail(&h->err, rc, err);
+    // install: per-vehicle route position, roads after it, next-road word
+    // and (waiting) departure lanes, applied to the records on the device
+    const int N = B.N;
+    std::vector<int32_t> n_rp(N, -1), n_rem(N, 0), n_nr(N, 0);
+    std::vector<uint32_t> n_mask(N, 0);
+    std::vector<int32_t> qidx;
+    long long lo = std::numeric_limits<long long>::max(), hi = -1;
+    std::vector<int32_t> full;
+    for (size_t c = 0; c < jobs.size(); ++c) {
+        const Job& J = jobs[c];
+        const int i = J.i;
+        if (begin[c + 1] == begin[c]) {
+            ++kept;
+            continue;
+        }
+        full.clear();
+        if (J.prefix >= 0) full.push_back(J.prefix);
+        for (int64_t e = begin[c]; e < begin[c + 1]; ++e) full.push_back(roads[e] + g.r0);
+        const int len = (int)full.size();
+        long long pos;
+        if ((long long)J.rp0 + len <= (long long)B.rstart[i] + B.rlen[i]) {
+            pos = J.rp0;
+        } else if ((long long)B.route.size() + len <= h->cap.E) {
+            pos = (long long)B.route.size();
+            B.route.resize(B.route.size() + len);
+        } else {
+            ++kept;   // the route pool is full: the vehicle keeps its route
+            continue;
+        }
+        std::copy(full.begin(), full.end(), B.route.begin() + pos);
+        lo = std::min(lo, pos);
+        hi = std::max(hi, pos + len);
+        B.rstart[i] = (int32_t)pos;
+        B.rlen[i] = len;
+        n_rp[i] = (int32_t)pos;
+        n_rem[i] = len - 1;
+        n_nr[i] = len > 1 ? full[1] : end_word(B.vend[i], B.lane_len[B.tile_lane_begin[full[len - 1]]]);
+        if (J.waiting) {
+            if (qidx.empty()) {
+                qidx.assign(NV, -1);
+                for (int e = B.q_begin[g.r0]; e < B.q_begin[g.r1]; ++e) qidx[B.q_veh[e] - g.v0] = e;
+            }
+            const uint32_t mask = depart_mask(B, full[0], len > 1 ? full[1] : -1);
+            B.q_mask[qidx[i - g.v0]] = mask;
+            n_mask[i] = mask;
+        }
+    }
+    if (hi > lo) HIPCHK(h, up_range(h, (int32_t*)D.route, B.route, lo, hi));
+    HIPCHK(h, up_range(h, (int32_t*)D.route_begin, B.rstart, g.v0, g.v1));
+    HIPCHK(h, hipMemcpyAsync(h->d_io_i0, n_rp.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_io_i1, n_rem.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_io_i2, n_nr.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_io_f0, n_mask.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_apply_routes(D, h->d_io_i0, h->d_io_i1, h->d_io_i2, (const uint32_t*)h->d_io_f0,
+                                  B.q_begin[B.R], h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (n_kept) *n_kept = kept;
+    return TSIM_OK;
+}
+
+int tsim_reroute_shortest(tsim_handle* h, const int32_t* vehicle_ids, int32_t n, const float* road_price,
+                          const float* road_time, void* workspace, size_t workspace_bytes, int32_t* n_kept)
+{
+    return reroute_impl(h, -1, vehicle_ids, n, road_price, road_time, workspace, workspace_bytes, n_kept);
+}
+
+int tsim_batch_reroute_shortest(tsim_batch* b, int32_t instance, const int32_t* vehicle_ids, int32_t n,
+                                const float* road_price, const float* road_time, void* workspace,
+                                size_t workspace_bytes, int32_t* n_kept)
+{
+    if (!b || instance < 0) return fail(nullptr, TSIM_EINVAL, "bad batch or instance");
+    return reroute_impl(b, instance, vehicle_ids, n, road_price, road_time, workspace, workspace_bytes, n_kept);
 }
 
 int tsim_batch_set_horizon(tsim_batch* b, int32_t instance, int64_t n_steps)

@@ -1,0 +1,436 @@
+// Shortest routes on the device for congestion pricing (Section 4
+// "Congestion Pricing": once roads carry prices, drivers move to routes of
+// lower cost; Appendix F: every road may be priced, prices change every
+// 20 s; Appendix E: demand routed by shortest travel time).
+//
+// Cost of a route: over every road after its first, the fastest open
+// junction lane into it (length / limit), plus the road's travel time (its
+// length over the highest limit of its lanes, or a time the caller gives),
+// plus its price, in FP32.  The cost-to-go of a road is its movement cost
+// plus the cost-to-go of the road the movement enters; of successors with
+// equal candidate cost the smaller road id is taken.
+//
+// Kernels:
+//   k_route_weights  one thread per movement: the movement's cost.
+//   k_route_tree     one workgroup per destination: the cost-to-go of every
+//                    road, held in LDS, by Bellman-Ford sweeps over the
+//                    movements (each road relaxed from its successors,
+//                    updates seen within the sweep) until a sweep changes
+//                    nothing; then each road's next road toward the
+//                    destination.  The costs are positive and the candidate
+//                    sum is monotone, so any order of relaxations from +inf
+//                    settles on the same least costs as Dijkstra's order.
+//   k_route_walk     one thread per pair: follows the next roads from the
+//                    origin, first counting, then writing the route.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "../../include/tsim.h"
+#include "tsim_internal.h"
+#include "tsim_route.h"
+
+namespace tsim {
+
+namespace {
+
+constexpr int kTreeThreads = 256;
+constexpr int kWalkThreads = 256;
+
+struct RouteDev {
+    int R, E;
+    const int32_t* road_lane_begin;
+    const float* road_len;
+    const float* lane_lim;
+    const int32_t* e_begin;
+    const int32_t* e_to;
+    const int32_t* e_jl_begin;
+    const float* jl_len;
+    const float* jl_lim;
+    const float* price;      // or null
+    const float* road_time;  // or null
+    float* w;                // [E] movement costs
+};
+
+__global__ __launch_bounds__(256) void k_route_weights(RouteDev G)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= G.E) return;
+    const int b = G.e_to[e];
+    float t;
+    if (G.road_time) {
+        t = G.road_time[b];
+    } else {
+        float vmax = 0.0f;
+        for (int l = G.road_lane_begin[b]; l < G.road_lane_begin[b + 1]; ++l) vmax = fmaxf(vmax, G.lane_lim[l]);
+        t = G.road_len[b] / vmax;
+    }
+    const int q0 = G.e_jl_begin[e], q1 = G.e_jl_begin[e + 1];
+    float c = G.jl_len[q0] / G.jl_lim[q0];
+    for (int q = q0 + 1; q < q1; ++q) c = fminf(c, G.jl_len[q] / G.jl_lim[q]);
+    float w = c + t;
+    w = w + (G.price ? G.price[b] : 0.0f);
+    G.w[e] = w;
+}
+
+__global__ __launch_bounds__(kTreeThreads) void k_route_tree(RouteDev G, const int32_t* dests, int32_t* nxt)
+{
+    extern __shared__ float dist[];
+    const int R = G.R, d = dests[blockIdx.x];
+    for (int r = threadIdx.x; r < R; r += kTreeThreads) dist[r] = r == d ? 0.0f : INFINITY;
+    __syncthreads();
+    for (;;) {
+        int changed = 0;
+        for (int r = threadIdx.x; r < R; r += kTreeThreads) {
+            if (r == d) continue;
+            const int e0 = G.e_begin[r], e1 = G.e_begin[r + 1];
+            const float cur = dist[r];
+            float best = cur;
+            for (int e = e0; e < e1; ++e) {
+                const float c = G.w[e] + dist[G.e_to[e]];
+                best = c < best ? c : best;
+            }
+            if (best < cur) {
+                dist[r] = best;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    int32_t* out = nxt + (size_t)blockIdx.x * R;
+    for (int r = threadIdx.x; r < R; r += kTreeThreads) {
+        int nx = -1;
+        if (r == d) {
+            nx = d;
+        } else if (dist[r] < INFINITY) {
+            float best = INFINITY;
+            for (int e = G.e_begin[r]; e < G.e_begin[r + 1]; ++e) {
+                const int b = G.e_to[e];
+                const float c = G.w[e] + dist[b];
+                if (c < best) {
+                    best = c;
+                    nx = b;
+                }
+            }
+        }
+        out[r] = nx;
+    }
+}
+
+// pairs p of one chunk (pointers already offset to the chunk's first pair);
+// pud[p] - c0 is the pair's destination slot in nxt.  write = 0: plen[p] =
+// roads of the route (0: unreachable, or longer than the network has
+// roads); write = 1: the route of every pair with plen[p] > 0 to
+// stage[poff[p] ..].
+__global__ __launch_bounds__(kWalkThreads) void k_route_walk(const int32_t* nxt, int R, int c0, const int32_t* porig,
+                                                              const int32_t* pdest, const int32_t* pud, int np,
+                                                              int32_t* plen, const int32_t* poff, int32_t* stage,
+                                                              int write)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    if (write && plen[p] == 0) return;
+    const int32_t* nx = nxt + (size_t)(pud[p] - c0) * R;
+    const int d = pdest[p];
+    int r = porig[p], len = 0;
+    int32_t* o = write ? stage + poff[p] : nullptr;
+    if (nx[r] >= 0) {
+        for (;;) {
+            if (len >= R || r < 0) {
+                len = 0;
+                break;
+            }
+            if (write) o[len] = r;
+            ++len;
+            if (r == d) break;
+            r = nx[r];
+        }
+    }
+    if (!write) plen[p] = len;
+}
+
+constexpr size_t kAlign = 256;
+
+size_t up_align(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t rlb, rlen, llim, eb, eto, ejb, jlen, jlim, price, time, w, porig, pdest, pud, plen, poff, dests, nxt, stage;
+    size_t fixed;   // bytes before nxt
+    int C = 0;      // destinations per pass
+    long long S = 0;  // staging entries
+};
+
+Layout fixed_layout(const RouteGraph& G, long long n)
+{
+    const size_t R = G.R, L = G.lane_lim.size(), E = G.e_to.size(), J = G.jl_len.size();
+    Layout y{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = up_align(o + std::max<size_t>(bytes, 4));
+        return at;
+    };
+    y.rlb = take((R + 1) * 4);
+    y.rlen = take(R * 4);
+    y.llim = take(L * 4);
+    y.eb = take((R + 1) * 4);
+    y.eto = take(E * 4);
+    y.ejb = take((E + 1) * 4);
+    y.jlen = take(J * 4);
+    y.jlim = take(J * 4);
+    y.price = take(R * 4);
+    y.time = take(R * 4);
+    y.w = take(E * 4);
+    y.porig = take((size_t)n * 4);
+    y.pdest = take((size_t)n * 4);
+    y.pud = take((size_t)n * 4);
+    y.plen = take((size_t)n * 4);
+    y.poff = take((size_t)n * 4);
+    y.dests = take(std::min<size_t>((size_t)std::max<long long>(n, 1), R) * 4);
+    y.fixed = o;
+    return y;
+}
+
+// nxt for C destinations, then S staging entries
+size_t tail_bytes(const RouteGraph& G, int C, long long S)
+{
+    return up_align((size_t)C * G.R * 4) + (size_t)S * 4;
+}
+
+// New routes of vehicles at a step boundary: n_rp[i] >= 0 marks vehicle i,
+// whose record (a lane resident, an inbox entrant, or, while it waits, its
+// departure queue entry) takes route position n_rp[i], n_rem[i] roads after
+// it and next-road word n_nr[i]; a waiting vehicle's queue entry also takes
+// the departure lane mask n_mask[i].  One thread per lane, then one per
+// queue entry.
+__global__ void k_apply_routes(const DevNet D, const int32_t* n_rp, const int32_t* n_rem, const int32_t* n_nr,
+                               const uint32_t* n_mask, int n_queue)
+{
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < D.NL) {
+        const int m = id;
+        const long long t = *D.gstep;
+        const int inst = D.tile_inst[D.lane_tile[m]];
+        const long long t0 = D.inst_t0[inst], loc = t - t0, end = D.inst_end[inst];
+        const int p = (int)((t0 + (loc < end ? loc : end)) & 1);
+        VehRec* slab = (p ? D.slab1 : D.slab0) + D.lane_base[m];
+        const int c = (p ? D.sum1 : D.sum0)[m].cnt;
+        for (int q = 0; q <= c; ++q) {
+            VehRec* z = q < c ? slab + q : (D.inbox_flag[m] ? D.inbox + m : nullptr);
+            if (!z) break;
+            const int i = z->vid;
+            if (n_rp[i] >= 0) {
+                z->rp = n_rp[i];
+                z->rem = n_rem[i];
+                z->nr = n_nr[i];
+            }
+        }
+        return;
+    }
+    const int e = id - D.NL;
+    if (e >= n_queue) return;
+    QRec* r = const_cast<QRec*>(D.q_rec) + e;
+    const int i = r->vid;
+    if (n_rp[i] < 0 || D.status[i] != TSIM_WAITING) return;
+    r->rp = n_rp[i];
+    r->rem = n_rem[i];
+    r->nr = n_nr[i];
+    r->mask = n_mask[i];
+}
+
+}  // namespace
+
+hipError_t launch_apply_routes(const DevNet& H, const int32_t* n_rp, const int32_t* n_rem, const int32_t* n_nr,
+                               const uint32_t* n_mask, int n_queue, hipStream_t s)
+{
+    const int n = H.NL + n_queue;
+    if (n > 0) k_apply_routes<<<(n + 255) / 256, 256, 0, s>>>(H, n_rp, n_rem, n_nr, n_mask, n_queue);
+    return hipGetLastError();
+}
+
+size_t route_workspace_min(const RouteGraph& G, long long n)
+{
+    return fixed_layout(G, n).fixed + tail_bytes(G, 1, G.R);
+}
+
+size_t route_workspace_hint(const RouteGraph& G, long long n)
+{
+    const long long R = std::max(G.R, 1);
+    const long long nd = std::max<long long>(1, std::min<long long>(n, R));
+    const int C = (int)std::min<long long>(nd, std::max<long long>(1, (64ll << 20) / (4 * R)));
+    const long long S = std::max<long long>(R, std::min<long long>({n * R, std::max<long long>(R, n * 64), 1ll << 24}));
+    return fixed_layout(G, n).fixed + tail_bytes(G, C, S);
+}
+
+#define RCHK(call)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            *err = std::string("HIP error in route kernels: ") + hipGetErrorString(e_);   \
+            return TSIM_EDEVICE;                                                          \
+        }                                                                                 \
+    } while (0)
+
+int route_pairs(const RouteGraph& G, const float* price, const float* road_time, const int32_t* origin,
+                const int32_t* dest, int n, hipStream_t stream, void* ws, size_t ws_bytes,
+                std::vector<int64_t>& begin, std::vector<int32_t>& roads, int* n_unreachable, std::string* err)
+{
+    const int R = G.R;
+    const int E = (int)G.e_to.size();
+    if (n < 0 || (n > 0 && (!origin || !dest))) {
+        *err = "bad pair arrays";
+        return TSIM_EINVAL;
+    }
+    if (R < 1 || R > kRouteMaxRoads) {
+        *err = "the network has no roads or more than the route kernels take (32768)";
+        return TSIM_EINVAL;
+    }
+    for (int p = 0; p < n; ++p)
+        if (origin[p] < 0 || origin[p] >= R || dest[p] < 0 || dest[p] >= R) {
+            *err = "road id of a pair out of range";
+            return TSIM_EINVAL;
+        }
+    for (int r = 0; r < R; ++r)
+        if ((price && !(price[r] >= 0.0f)) || (road_time && !(road_time[r] >= 0.0f))) {
+            *err = "prices and road times must be non-negative";
+            return TSIM_EINVAL;
+        }
+    begin.assign((size_t)n + 1, 0);
+    roads.clear();
+    if (n_unreachable) *n_unreachable = 0;
+    if (n == 0) return TSIM_OK;
+    Layout y = fixed_layout(G, n);
+    if (!ws || ws_bytes < y.fixed + tail_bytes(G, 1, R)) {
+        *err = "route workspace too small";
+        return TSIM_ENOMEM;
+    }
+    // pairs by destination (stable), distinct destinations in that order
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return dest[a] < dest[b]; });
+    std::vector<int32_t> so(n), sd(n), sud(n), ud;
+    for (int c = 0; c < n; ++c) {
+        const int p = order[c];
+        so[c] = origin[p];
+        sd[c] = dest[p];
+        if (ud.empty() || ud.back() != dest[p]) ud.push_back(dest[p]);
+        sud[c] = (int32_t)ud.size() - 1;
+    }
+    const int nud = (int)ud.size();
+    // destinations per pass from what is left, at least R staging entries
+    const size_t left = ws_bytes - y.fixed;
+    long long C = std::min<long long>(nud, (long long)((left - (size_t)R * 4 - kAlign) / ((size_t)R * 4)));
+    if (C < 1) C = 1;
+    y.C = (int)C;
+    y.nxt = y.fixed;
+    y.stage = y.nxt + up_align((size_t)C * R * 4);
+    y.S = (long long)((ws_bytes - y.stage) / 4);
+
+    char* base = (char*)ws;
+    auto at = [&](size_t off) { return (void*)(base + off); };
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(at(off), src, bytes, hipMemcpyHostToDevice, stream) : hipSuccess;
+    };
+    RCHK(put(y.rlb, G.road_lane_begin.data(), G.road_lane_begin.size() * 4));
+    RCHK(put(y.rlen, G.road_len.data(), G.road_len.size() * 4));
+    RCHK(put(y.llim, G.lane_lim.data(), G.lane_lim.size() * 4));
+    RCHK(put(y.eb, G.e_begin.data(), G.e_begin.size() * 4));
+    RCHK(put(y.eto, G.e_to.data(), G.e_to.size() * 4));
+    RCHK(put(y.ejb, G.e_jl_begin.data(), G.e_jl_begin.size() * 4));
+    RCHK(put(y.jlen, G.jl_len.data(), G.jl_len.size() * 4));
+    RCHK(put(y.jlim, G.jl_lim.data(), G.jl_lim.size() * 4));
+    if (price) RCHK(put(y.price, price, (size_t)R * 4));
+    if (road_time) RCHK(put(y.time, road_time, (size_t)R * 4));
+    RCHK(put(y.porig, so.data(), (size_t)n * 4));
+    RCHK(put(y.pdest, sd.data(), (size_t)n * 4));
+    RCHK(put(y.pud, sud.data(), (size_t)n * 4));
+
+    RouteDev D;
+    D.R = R;
+    D.E = E;
+    D.road_lane_begin = (const int32_t*)at(y.rlb);
+    D.road_len = (const float*)at(y.rlen);
+    D.lane_lim = (const float*)at(y.llim);
+    D.e_begin = (const int32_t*)at(y.eb);
+    D.e_to = (const int32_t*)at(y.eto);
+    D.e_jl_begin = (const int32_t*)at(y.ejb);
+    D.jl_len = (const float*)at(y.jlen);
+    D.jl_lim = (const float*)at(y.jlim);
+    D.price = price ? (const float*)at(y.price) : nullptr;
+    D.road_time = road_time ? (const float*)at(y.time) : nullptr;
+    D.w = (float*)at(y.w);
+    if (E > 0) {
+        k_route_weights<<<(E + 255) / 256, 256, 0, stream>>>(D);
+        RCHK(hipGetLastError());
+    }
+    const size_t lds = (size_t)R * 4;
+    RCHK(hipFuncSetAttribute((const void*)k_route_tree, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+
+    int32_t* nxt = (int32_t*)at(y.nxt);
+    int32_t* stage = (int32_t*)at(y.stage);
+    int32_t* d_plen = (int32_t*)at(y.plen);
+    int32_t* d_poff = (int32_t*)at(y.poff);
+    std::vector<int32_t> hlen(n), hoff(n);
+    std::vector<int64_t> hstart(n, 0);   // start of each sorted pair's route in roads_sorted
+    std::vector<int32_t> roads_sorted;
+    int bad = 0;
+    int pa = 0;
+    for (int c0 = 0; c0 < nud; c0 += (int)C) {
+        const int c1 = (int)std::min<long long>(nud, c0 + C);
+        int pb = pa;
+        while (pb < n && sud[pb] < c1) ++pb;
+        const int np = pb - pa;
+        RCHK(put(y.dests, ud.data() + c0, (size_t)(c1 - c0) * 4));
+        k_route_tree<<<c1 - c0, kTreeThreads, lds, stream>>>(D, (const int32_t*)at(y.dests), nxt);
+        RCHK(hipGetLastError());
+        const int32_t* po = (const int32_t*)at(y.porig) + pa;
+        const int32_t* pd = (const int32_t*)at(y.pdest) + pa;
+        const int32_t* pu = (const int32_t*)at(y.pud) + pa;
+        const int wg = (np + kWalkThreads - 1) / kWalkThreads;
+        k_route_walk<<<wg, kWalkThreads, 0, stream>>>(nxt, R, c0, po, pd, pu, np, d_plen + pa, d_poff + pa, stage, 0);
+        RCHK(hipGetLastError());
+        RCHK(hipMemcpyAsync(hlen.data() + pa, d_plen + pa, (size_t)np * 4, hipMemcpyDeviceToHost, stream));
+        RCHK(hipStreamSynchronize(stream));
+        // write the chunk's routes through the staging buffer, as many
+        // pairs at a time as it holds
+        int q = pa;
+        while (q < pb) {
+            long long used = 0;
+            int q2 = q;
+            while (q2 < pb && used + hlen[q2] <= y.S) {
+                hoff[q2] = (int32_t)used;
+                used += hlen[q2];
+                ++q2;
+            }
+            RCHK(put(y.poff + (size_t)q * 4, hoff.data() + q, (size_t)(q2 - q) * 4));
+            k_route_walk<<<(q2 - q + kWalkThreads - 1) / kWalkThreads, kWalkThreads, 0, stream>>>(
+                nxt, R, c0, po + (q - pa), pd + (q - pa), pu + (q - pa), q2 - q, d_plen + q, d_poff + q, stage, 1);
+            RCHK(hipGetLastError());
+            const size_t at0 = roads_sorted.size();
+            roads_sorted.resize(at0 + (size_t)used);
+            if (used)
+                RCHK(hipMemcpyAsync(roads_sorted.data() + at0, stage, (size_t)used * 4, hipMemcpyDeviceToHost, stream));
+            RCHK(hipStreamSynchronize(stream));
+            for (int c = q; c < q2; ++c) {
+                hstart[c] = (int64_t)at0 + hoff[c];
+                bad += hlen[c] == 0;
+            }
+            q = q2;
+        }
+        pa = pb;
+    }
+    // back to the callers' pair order
+    std::vector<int32_t> rank(n);
+    for (int c = 0; c < n; ++c) rank[order[c]] = c;
+    for (int p = 0; p < n; ++p) begin[p + 1] = begin[p] + hlen[rank[p]];
+    roads.resize((size_t)begin[n]);
+    for (int p = 0; p < n; ++p) {
+        const int c = rank[p];
+        std::copy(roads_sorted.begin() + hstart[c], roads_sorted.begin() + hstart[c] + hlen[c],
+                  roads.begin() + begin[p]);
+    }
+    if (n_unreachable) *n_unreachable = bad;
+    return TSIM_OK;
+}
+
+}  // namespace tsim

@@ -85,7 +85,9 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_capacity_left", "tsim_batch_num_instances", "tsim_set_signal_phases_noalloc",
            "tsim_set_lane_max_speed", "tsim_batch_set_lane_max_speed", "tsim_set_lane_restriction",
            "tsim_batch_set_lane_restriction", "tsim_set_vehicle_route",
-           "tsim_batch_set_vehicle_route", "tsim_set_trajectory", "tsim_get_trajectory_count"]
+           "tsim_batch_set_vehicle_route", "tsim_set_trajectory", "tsim_get_trajectory_count",
+           "tsim_route_footprint", "tsim_shortest_routes", "tsim_reroute_footprint", "tsim_reroute_shortest",
+           "tsim_batch_reroute_footprint", "tsim_batch_reroute_shortest"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -117,6 +119,13 @@ def lib():
         L.tsim_set_trajectory.argtypes = [P, P, C.c_int64, C.c_int32]
         L.tsim_get_trajectory_count.argtypes = [P, P]
         L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32, C.c_float]
+        SZ = C.POINTER(C.c_size_t)
+        L.tsim_route_footprint.argtypes = [P, C.c_int32, SZ, SZ]
+        L.tsim_shortest_routes.argtypes = [P, P, P, P, P, C.c_int32, P, P, C.c_size_t, P, P, C.c_int64, P]
+        L.tsim_reroute_footprint.argtypes = [P, C.c_int32, SZ, SZ]
+        L.tsim_reroute_shortest.argtypes = [P, P, C.c_int32, P, P, P, C.c_size_t, P]
+        L.tsim_batch_reroute_footprint.argtypes = [P, C.c_int32, C.c_int32, SZ, SZ]
+        L.tsim_batch_reroute_shortest.argtypes = [P, C.c_int32, P, C.c_int32, P, P, P, C.c_size_t, P]
         L.tsim_batch_set_lane_max_speed.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_lane_restriction.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_signal_policy.argtypes = [P, C.c_int32, P, P, C.c_int32]
@@ -197,7 +206,7 @@ class _Inputs:
         self.trips = tsim_trips(trips.n_vehicles, *[_p(a[k]) for k in (
             "depart_time", "route_begin", "route_roads", "v0_factor", "length")],
             _p(a["end_s"]) if "end_s" in a else None)
-        self.params = _Inputs.params_of(params)
+        self.params = None if params is None else _Inputs.params_of(params)
 
     @staticmethod
     def params_of(params):
@@ -217,6 +226,61 @@ def footprint(net, trips, params):
     n = C.c_size_t(0)
     _check(lib().tsim_footprint(C.byref(ins.net), C.byref(ins.trips), C.byref(ins.params), C.byref(n)))
     return int(n.value)
+
+
+class _NoTrips:
+    """A trip table with no vehicles (network-only calls)."""
+    n_vehicles = 0
+    depart_time = v0_factor = length = np.zeros(0, np.float32)
+    route_begin = np.zeros(1, np.int32)
+    route_roads = np.zeros(0, np.int32)
+    end_s = None
+
+
+_NO_TRIPS = _NoTrips()
+
+
+def _opt_f32(a):
+    return None if a is None else np.ascontiguousarray(a, np.float32)
+
+
+def _workspace(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def shortest_routes(net, origins, dests, price=None, road_time=None, device="cuda:0", stream=None,
+                    workspace=None):
+    """Routes of least cost for (origin road, destination road) pairs of a
+    network (Section 4 congestion pricing: road prices price[R] in seconds;
+    road_time[R] replaces the free-flow times), computed on the GPU.
+    Returns (begin[n+1], roads, n_unreachable): route c is
+    roads[begin[c]:begin[c+1]], empty when unreachable."""
+    import torch
+    ins = _Inputs(net, _NO_TRIPS, None)
+    o = np.ascontiguousarray(origins, np.int32)
+    d = np.ascontiguousarray(dests, np.int32)
+    n = int(o.size)
+    pr, rt = _opt_f32(price), _opt_f32(road_time)
+    lo, hint = C.c_size_t(0), C.c_size_t(0)
+    _check(lib().tsim_route_footprint(C.byref(ins.net), n, C.byref(lo), C.byref(hint)))
+    dev = torch.device(device)
+    ws = workspace if workspace is not None else _workspace(hint.value, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    begin = np.zeros(n + 1, np.int32)
+    bad = np.zeros(1, np.int32)
+    cap = max(64 * n, 1)
+    while True:
+        roads = np.zeros(cap, np.int32)
+        rc = lib().tsim_shortest_routes(C.byref(ins.net), None if pr is None else _p(pr),
+                                        None if rt is None else _p(rt), _p(o), _p(d), n,
+                                        C.c_void_p(st.cuda_stream), C.c_void_p(ws.data_ptr()),
+                                        C.c_size_t(ws.numel()), _p(begin), _p(roads), cap, _p(bad))
+        if rc == TSIM_ENOMEM and int(begin[n]) > cap:
+            cap = int(begin[n])
+            continue
+        _check(rc)
+        return begin, roads[:int(begin[n])].copy(), int(bad[0])
 
 
 class Sim:
@@ -296,6 +360,23 @@ class Sim:
         r = np.ascontiguousarray(roads, np.int32)
         e = -1.0 if end_s is None else float(end_s)
         _check(lib().tsim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size), e), self.h)
+
+    def reroute_shortest(self, vehicle_ids, price=None, road_time=None, workspace=None):
+        """Vehicles take, from the next step on, the route of least cost from
+        where they are to the last road of their route (road prices price[R],
+        road times road_time[R] or free-flow), computed on the GPU.  Returns
+        the number of vehicles that kept their route."""
+        v = np.ascontiguousarray(vehicle_ids, np.int32)
+        pr, rt = _opt_f32(price), _opt_f32(road_time)
+        if workspace is None:
+            lo, hint = C.c_size_t(0), C.c_size_t(0)
+            _check(lib().tsim_reroute_footprint(self.h, int(v.size), C.byref(lo), C.byref(hint)), self.h)
+            workspace = _workspace(hint.value, self.device)
+        kept = np.zeros(1, np.int32)
+        _check(lib().tsim_reroute_shortest(self.h, _p(v), int(v.size), None if pr is None else _p(pr),
+                                           None if rt is None else _p(rt), C.c_void_p(workspace.data_ptr()),
+                                           C.c_size_t(workspace.numel()), _p(kept)), self.h)
+        return int(kept[0])
 
     def set_lane_max_speed(self, lanes, speeds):
         """Speed limits of lanes (network lane ids) from the next step on."""
@@ -638,6 +719,23 @@ class Batch:
 
     def set_road_lane_plan(self, instance, plans, index):
         self.set_lane_restriction(instance, *lane_plan_flags(plans, index))
+
+    def reroute_shortest(self, instance, vehicle_ids, price=None, road_time=None, workspace=None):
+        """As Sim.reroute_shortest, for vehicles of one instance (local ids;
+        price and road_time over the instance's roads)."""
+        v = np.ascontiguousarray(vehicle_ids, np.int32)
+        pr, rt = _opt_f32(price), _opt_f32(road_time)
+        if workspace is None:
+            lo, hint = C.c_size_t(0), C.c_size_t(0)
+            _check(lib().tsim_batch_reroute_footprint(self.h, int(instance), int(v.size), C.byref(lo),
+                                                      C.byref(hint)), self.h)
+            workspace = _workspace(hint.value, self.device)
+        kept = np.zeros(1, np.int32)
+        _check(lib().tsim_batch_reroute_shortest(self.h, int(instance), _p(v), int(v.size),
+                                                 None if pr is None else _p(pr), None if rt is None else _p(rt),
+                                                 C.c_void_p(workspace.data_ptr()), C.c_size_t(workspace.numel()),
+                                                 _p(kept)), self.h)
+        return int(kept[0])
 
     def set_horizon(self, instance, n_steps):
         """Freeze instance after n_steps local steps (the others go on)."""

@@ -43,8 +43,50 @@ def oracle_one_step(O, net, trips, params, st):
         o.set_lane_restriction(*st["restrictions"])
     for vid, roads, *end in st.get("routes", ()):
         o.set_vehicle_route(vid, roads, *end)
+    if "shortest" in st:
+        oracle_reroute_shortest(o, net, trips, *st["shortest"])
     o.step(1)
     return o
+
+
+def oracle_reroute_shortest(o, net, trips, vids, price=None, road_time=None):
+    """The oracle's side of a reroute to least-cost routes: from the
+    oracle's own state, each listed vehicle that has not finished takes the
+    least-cost route from where it is (its origin road while it waits, the
+    road of its lane, or, on a junction lane, the road that lane enters,
+    kept after the road it left) to the last road of its route in force;
+    unreachable destinations leave the route as it was.  Returns the number
+    of vehicles that kept their route."""
+    s = o.get_state()
+    rol = net.road_of_lane()
+    NRL = net.n_road_lanes
+    end_s = getattr(trips, "end_s", None)
+    jobs, starts, dests = [], [], []
+    kept = 0
+    for i in vids:
+        i = int(i)
+        if s["status"][i] == 2:
+            kept += 1
+            continue
+        k, roads = o.route(i)
+        prefix, start = [], int(roads[0])
+        if s["status"][i] == 1:
+            lane = int(s["lane"][i])
+            if lane >= NRL:
+                prefix, start = [int(roads[k])], int(rol[net.jl_out_lane[lane - NRL]])
+            else:
+                start = int(rol[lane])
+        jobs.append((i, prefix))
+        starts.append(start)
+        dests.append(int(roads[-1]))
+    begin, rr, _ = o.shortest_routes(starts, dests, price, road_time)
+    for c, (i, prefix) in enumerate(jobs):
+        if begin[c + 1] == begin[c]:
+            kept += 1
+            continue
+        e = None if end_s is None or end_s[i] < 0 else float(end_s[i])
+        o.set_vehicle_route(i, prefix + rr[begin[c]:begin[c + 1]].tolist(), e)
+    return kept
 
 
 def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False):
@@ -64,6 +106,8 @@ def compare_one_step(O, sim_cls, net, trips, params, st, sim=None, stepped=False
             g.set_lane_restriction(*st["restrictions"])
         for vid, roads, *end in st.get("routes", ()):
             g.set_vehicle_route(vid, roads, *end)
+        if "shortest" in st:
+            g.reroute_shortest(*st["shortest"])
         g.step(1)
     gst = g.get_state()
     gm = g.metrics()

@@ -120,3 +120,42 @@ def test_lane_plan_flags():
     released (lanes in every plan stay released)."""
     lanes, flags = T.lane_plan_flags([[10, 11], [11, 12], [13]], 1)
     assert lanes.tolist() == [10, 11, 12, 13] and flags.tolist() == [1, 0, 0, 1]
+
+
+def test_route_footprint_and_rejections_without_gpu(L):
+    """tsim_route_footprint sizes the work space from the network and the
+    pair count (the least size never above the suggested one, both growing
+    with the pairs); tsim_shortest_routes rejects bad pairs, negative or NaN
+    prices and times, and a missing work space before any GPU call, and
+    answers an empty pair list without one."""
+    net = W.grid_network(4)
+    ins = T._Inputs(net, T._NO_TRIPS, None)
+    lo, hint = C.c_size_t(0), C.c_size_t(0)
+    assert L.tsim_route_footprint(C.byref(ins.net), 10, C.byref(lo), C.byref(hint)) == T.TSIM_OK
+    assert 0 < lo.value <= hint.value
+    lo2, hint2 = C.c_size_t(0), C.c_size_t(0)
+    assert L.tsim_route_footprint(C.byref(ins.net), 10000, C.byref(lo2), C.byref(hint2)) == T.TSIM_OK
+    assert lo2.value > lo.value and hint2.value > hint.value
+    assert L.tsim_route_footprint(C.byref(ins.net), -1, None, None) == T.TSIM_EINVAL
+    assert L.tsim_route_footprint(None, 1, None, None) == T.TSIM_EINVAL
+    R = net.n_roads
+    begin = np.zeros(3, np.int32)
+    roads = np.zeros(100, np.int32)
+
+    def call(o, d, price=None, time=None, ws=None, nbytes=0, n=None):
+        o = np.ascontiguousarray(o, np.int32)
+        d = np.ascontiguousarray(d, np.int32)
+        p = None if price is None else T._p(np.ascontiguousarray(price, np.float32))
+        t = None if time is None else T._p(np.ascontiguousarray(time, np.float32))
+        return L.tsim_shortest_routes(C.byref(ins.net), p, t, T._p(o), T._p(d), o.size if n is None else n, None,
+                                      ws, nbytes, T._p(begin), T._p(roads), roads.size, None)
+
+    assert call([0, 1], [2, R]) == T.TSIM_EINVAL
+    assert call([-1, 1], [2, 3]) == T.TSIM_EINVAL
+    bad = np.zeros(R, np.float32)
+    bad[4] = -1.0
+    assert call([0, 1], [2, 3], price=bad) == T.TSIM_EINVAL
+    bad[4] = np.nan
+    assert call([0, 1], [2, 3], time=bad) == T.TSIM_EINVAL
+    assert call([0, 1], [2, 3]) == T.TSIM_ENOMEM   # no work space
+    assert call([0], [0], n=0) == T.TSIM_OK and begin[0] == 0

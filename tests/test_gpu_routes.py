@@ -1,0 +1,259 @@
+"""GPU parity of the device shortest routes (Section 4 "Congestion Pricing":
+drivers move to routes of lower cost once roads carry prices; Appendix F:
+every road may be priced; Appendix E: routes of shortest travel time)
+against the oracle's Dijkstra.
+
+The route is an integer result decided by FP32 sums that both sides form in
+the same order, so routes must be identical (bit-exact); reroutes inside a
+running simulation are compared one step later with the one-step parity of
+the vehicle update, and over a priced horizon statistically.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2406_10661_amd import workloads as W
+from paper_2406_10661_amd.workloads import synthetic_state
+from tests.parity import compare_one_step, oracle_reroute_shortest
+from tests.scenes import diamond_network, empty_trips
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as O
+    O.build()
+    return O
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2406_10661_amd import tsim
+    return tsim
+
+
+def _split(begin, roads):
+    return [roads[begin[c]:begin[c + 1]].tolist() for c in range(len(begin) - 1)]
+
+
+def _oracle_routes(O, net, o_pairs, d_pairs, price=None, road_time=None):
+    o = O.OracleSim(net, empty_trips(), W.Params())
+    order = np.argsort(d_pairs, kind="stable")
+    b, r, bad = o.shortest_routes(np.asarray(o_pairs)[order], np.asarray(d_pairs)[order], price, road_time)
+    o.close()
+    out = [None] * len(o_pairs)
+    for c, p in enumerate(order):
+        out[p] = r[b[c]:b[c + 1]].tolist()
+    return out, bad
+
+
+def _movements(net):
+    rol = net.road_of_lane()
+    return set(zip(rol[net.jl_in_lane].tolist(), rol[net.jl_out_lane].tolist()))
+
+
+@pytest.mark.parametrize("price,road_time", [
+    (None, None), ({2: 15}, None), ({2: 10}, None), ({2: 5, 1: 3}, None),
+    (None, {4: 40.0}), ({2: np.inf}, None)])
+def test_diamond_routes_match_oracle(O, T, price, road_time):
+    """The two-way network of the oracle pins: free flow, a price that moves
+    drivers, an exact tie, a price on each way, a given road time, and a
+    closed road (+inf price)."""
+    net = diamond_network()
+    pr = None if price is None else np.array([price.get(r, 0.0) for r in range(6)], np.float32)
+    rt = None
+    if road_time is not None:
+        rt = np.array([10, 20, 10, 20, 20, 10], np.float32)
+        for r, t in road_time.items():
+            rt[r] = t
+    pairs = [(a, b) for a in range(6) for b in range(6)]
+    og, dg = [p[0] for p in pairs], [p[1] for p in pairs]
+    b, r, bad = T.shortest_routes(net, og, dg, price=pr, road_time=rt)
+    want, wbad = _oracle_routes(O, net, og, dg, pr, rt)
+    assert _split(b, r) == want
+    assert bad == wbad
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_grid_routes_match_oracle(O, T, seed):
+    """8x8 grid (224 roads), prices U(0, 60) s, 1,500 pairs over every
+    destination: identical routes."""
+    rng = np.random.default_rng(seed)
+    net = W.grid_network(8)
+    R = net.n_roads
+    price = rng.uniform(0, 60, R).astype(np.float32)
+    og = rng.integers(0, R, 1500)
+    dg = rng.integers(0, R, 1500)
+    b, r, bad = T.shortest_routes(net, og, dg, price=price)
+    want, wbad = _oracle_routes(O, net, og, dg, price)
+    got = _split(b, r)
+    assert got == want
+    assert bad == wbad
+
+
+def test_least_workspace_gives_the_same_routes(O, T):
+    """With the least work space (one destination per pass, one route's
+    worth of staging) the routes are those of a roomy call and the oracle's;
+    pairs come in an order unrelated to their destinations."""
+    import torch
+    rng = np.random.default_rng(4)
+    net = W.grid_network(6)
+    R = net.n_roads
+    price = rng.uniform(0, 30, R).astype(np.float32)
+    og = rng.integers(0, R, 700)
+    dg = rng.integers(0, R, 700)
+    ins = T._Inputs(net, T._NO_TRIPS, None)
+    import ctypes as C
+    lo, hint = C.c_size_t(0), C.c_size_t(0)
+    T._check(T.lib().tsim_route_footprint(C.byref(ins.net), 700, C.byref(lo), C.byref(hint)))
+    assert 0 < lo.value <= hint.value
+    small = torch.empty(lo.value, dtype=torch.uint8, device="cuda:0")
+    b1, r1, bad1 = T.shortest_routes(net, og, dg, price=price, workspace=small)
+    b2, r2, bad2 = T.shortest_routes(net, og, dg, price=price)
+    assert np.array_equal(b1, b2) and np.array_equal(r1, r2) and bad1 == bad2
+    want, _ = _oracle_routes(O, net, og, dg, price)
+    assert _split(b1, r1) == want
+
+
+def test_served_size_routes(O, T):
+    """A served pricing job's network at its largest (32x32 jittered grid,
+    prices U(0, 120) s) and 20,000 trips: every route starts at its origin,
+    ends at its destination and follows movements; the routes of 300 pairs
+    over 10 destinations equal the oracle's."""
+    rng = np.random.default_rng(8)
+    net = W.jittered_grid(32, rng)
+    R = net.n_roads
+    price = rng.uniform(0, 120, R).astype(np.float32)
+    og, dg = W.uniform_od(net, rng, 20000)
+    b, r, bad = T.shortest_routes(net, og, dg, price=price)
+    mv = _movements(net)
+    routes = _split(b, r)
+    for a, d, x in zip(og.tolist(), dg.tolist(), routes):
+        if not x:
+            continue
+        assert x[0] == a and x[-1] == d
+        assert all((x[k], x[k + 1]) in mv for k in range(len(x) - 1))
+    dsel = rng.choice(np.unique(dg), 10, replace=False)
+    idx = np.nonzero(np.isin(dg, dsel))[0][:300]
+    want, _ = _oracle_routes(O, net, og[idx], dg[idx], price)
+    assert [routes[i] for i in idx] == want
+    print(f"served-size routes: {R} roads, {len(routes)} pairs, {bad} unreachable, "
+          f"mean length {np.mean([len(x) for x in routes]):.1f}", flush=True)
+
+
+def test_no_pairs_and_one_road_routes(T):
+    """No pairs: an empty result; origin = destination: that one road."""
+    net = W.grid_network(3)
+    b, r, bad = T.shortest_routes(net, [], [])
+    assert b.tolist() == [0] and r.size == 0 and bad == 0
+    b, r, bad = T.shortest_routes(net, [3, 5], [3, 5])
+    assert _split(b, r) == [[3], [5]] and bad == 0
+
+
+def _closed_movements(net, rng, share):
+    """Every junction lane of a share of the movements (road to road)."""
+    rol = net.road_of_lane()
+    mov = {}
+    for q in range(net.n_jlanes):
+        mov.setdefault((int(rol[net.jl_in_lane[q]]), int(rol[net.jl_out_lane[q]])), []).append(q)
+    ids = []
+    for qs in mov.values():
+        if rng.random() < share:
+            ids += [net.n_road_lanes + q for q in qs]
+    ids = np.asarray(sorted(ids), np.int32)
+    return ids, np.ones(ids.size, np.int32)
+
+
+def test_reroute_one_step(O, T):
+    """400 vehicles of a loaded 4x4 grid (waiting, on road lanes and on
+    junction lanes) take least-cost routes under road prices, with a tenth
+    of the movements closed and some lane limits raised, on both sides from
+    the same state; one step later the states agree to the one-step
+    parity bar."""
+    w = W.config1()
+    rng = np.random.default_rng(21)
+    st = synthetic_state(w.network, w.trips, 150, seed=21, p_active=0.6)
+    lanes = rng.choice(w.network.n_road_lanes, 20, replace=False).astype(np.int32)
+    st["lane_limits"] = (lanes, np.full(lanes.size, 22.0, np.float32))
+    st["restrictions"] = _closed_movements(w.network, rng, 0.1)
+    price = rng.uniform(0, 120, w.network.n_roads).astype(np.float32)
+    vids = rng.choice(w.trips.n_vehicles, 400, replace=False).astype(np.int32)
+    st["shortest"] = (vids, price)
+    rep = compare_one_step(O, T.Sim, w.network, w.trips, w.params, st)
+    print("reroute_one_step", {k: v for k, v in rep.items() if not isinstance(v, dict)}, flush=True)
+    assert rep["active"] > 300
+
+
+def test_reroute_keeps_unreachable_and_finished(O, T):
+    """A vehicle whose destination is cut off keeps its route, as does a
+    finished one; both are counted."""
+    w = W.config1()
+    g = T.Sim(w.network, w.trips, w.params)
+    g.step(400)
+    st = g.get_state()
+    fin = np.nonzero(st["status"] == 2)[0][:5]
+    assert fin.size == 5
+    k = g.reroute_shortest(fin.astype(np.int32), np.zeros(w.network.n_roads, np.float32))
+    assert k == 5
+    # close every junction lane into the destination road of a waiting vehicle
+    wait = np.nonzero(st["status"] == 0)[0]
+    if wait.size:
+        i = int(wait[0])
+        dest = int(w.trips.route_roads[w.trips.route_begin[i + 1] - 1])
+        rol = w.network.road_of_lane()
+        q = np.nonzero(rol[w.network.jl_out_lane] == dest)[0]
+        ids = (w.network.n_road_lanes + q).astype(np.int32)
+        g.set_lane_restriction(ids, np.ones(ids.size, np.int32))
+        before = g.get_state()
+        assert g.reroute_shortest(np.array([i], np.int32)) == 1
+        after = g.get_state()
+        assert np.array_equal(before["route_pos"], after["route_pos"])
+
+
+def test_priced_horizon_statistics(O, T):
+    """Congestion pricing (Appendix F: prices change every 20 s; here every
+    150 steps): new prices U(0, 60) s, and every vehicle that has not
+    finished takes its least-cost route, on both sides from their own
+    states; completed trips and mean road speed over 600 steps within 1% of
+    the oracle's."""
+    w = W.config1()
+    o = O.OracleSim(w.network, w.trips, w.params)
+    g = T.Sim(w.network, w.trips, w.params)
+    rng = np.random.default_rng(31)
+    allv = np.arange(w.trips.n_vehicles, dtype=np.int32)
+    for t0 in range(0, w.n_steps, 150):
+        price = rng.uniform(0, 60, w.network.n_roads).astype(np.float32)
+        oracle_reroute_shortest(o, w.network, w.trips, allv, price)
+        g.reroute_shortest(allv, price)
+        o.step(150)
+        g.step(150)
+    om, gm = o.metrics(), g.metrics()
+    print("priced_horizon", dict(oracle_finished=om["finished"], gpu_finished=gm["n_finished"],
+                                 oracle_speed=om["mean_speed_avg"], gpu_speed=gm["mean_speed_avg"]), flush=True)
+    assert gm["errors"] == 0
+    assert abs(gm["n_finished"] - om["finished"]) <= 0.01 * om["finished"]
+    assert abs(gm["mean_speed_avg"] - om["mean_speed_avg"]) <= 0.01 * om["mean_speed_avg"]
+
+
+def test_batch_reroute_matches_alone(T):
+    """A reroute in one instance of a batch (through the batch ABI) equals
+    the same reroute on a handle of its own (bit for bit after 100 more
+    steps); the other instance is untouched."""
+    w = W.config1()
+    rng = np.random.default_rng(41)
+    price = rng.uniform(0, 120, w.network.n_roads).astype(np.float32)
+    vids = rng.choice(w.trips.n_vehicles, 500, replace=False).astype(np.int32)
+    b = T.Batch([w.network, w.network], [w.trips, w.trips], [w.params, w.params])
+    b.step(120)
+    b.reroute_shortest(1, vids, price)
+    b.step(100)
+    for k, reroute in ((0, False), (1, True)):
+        g = T.Sim(w.network, w.trips, w.params)
+        g.step(120)
+        if reroute:
+            g.reroute_shortest(vids, price)
+        g.step(100)
+        a, e = b.get_state(k), g.get_state()
+        for f in ("status", "lane", "route_pos", "x", "v"):
+            assert np.array_equal(a[f], e[f]), (k, f)
