@@ -24,7 +24,8 @@ sample (a synthetic state of the same city at time S).
 The same line carries, under "batched" and "served", compact forms of the
 two serving-style workloads timed in the same run (64 instances for 300
 steps; 100 jobs of at most 100,000 vehicles), each against its plain
-one-instance-at-a-time loop (--no-legs leaves them out).
+one-instance-at-a-time loop, and under "routing" the device shortest routes
+of a served pricing job (--no-legs leaves them out).
 
 --workload batch: 256 uneven jittered-grid instances (1k-150k vehicles each,
 about 15M in total) stepped together through captured 15-step HIP graphs for
@@ -32,8 +33,13 @@ about 15M in total) stepped together through captured 15-step HIP graphs for
 15 steps; the same instances stepped one at a time by the plain stepper on the
 same schedule are the baseline (ratio in "vs_plain_loop").
 
+--workload route: least-cost routes under road prices (Section 4 congestion
+pricing) for 150,000 trips of a 32x32 jittered grid computed on the GPU,
+against the host's Dijkstra and the oracle on a bounded sample.
+
 --workload serve: a Poisson stream (20 jobs/s) of pre-generated jobs (signal
-timing plans or road prices; 10k-500k vehicles; 300-3,600 steps) run by the
+timing plans or road prices; 10k-500k vehicles; 300-3,600 steps; each job's
+trips routed on the GPU under its prices before the stream starts) run by the
 continuous-batching loop of ``paper_2406_10661_amd.serve`` under an HBM
 budget (default: jobs gathered into batches, each frozen at its own
 horizon); reports jobs/s, p50/p99 latency and the plain one-job-at-a-time
@@ -286,9 +292,10 @@ def run_serve(args, emit=True):
     from paper_2406_10661_amd import serve as SV
     from paper_2406_10661_amd.tsim import Sim
     t0 = time.time()
-    ws = W.served_jobs(args.jobs, max_vehicles=getattr(args, "max_vehicles", None))
+    ws = W.served_jobs(args.jobs, max_vehicles=getattr(args, "max_vehicles", None), route=False)
     arr = W.poisson_arrivals(args.jobs, rate=args.rate)
-    log(f"[bench] {len(ws)} jobs generated in {time.time() - t0:.1f} s; "
+    t_route = SV.route_jobs_on_device(ws)
+    log(f"[bench] {len(ws)} jobs generated in {time.time() - t0:.1f} s, routed on the GPU in {t_route:.2f} s; "
         f"{sum(w.trips.n_vehicles for w in ws)} vehicles in total")
     jobs = [SV.Job(jid=k, arrival=float(arr[k]), network=w.network, trips=w.trips, params=w.params,
                    horizon=w.n_steps) for k, w in enumerate(ws)]
@@ -345,7 +352,9 @@ def run_serve(args, emit=True):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "served_poisson", "jobs": len(jobs), "measured_after": args.skip,
                    "rate_jobs_per_s": args.rate, "hbm_budget_gib": args.budget_gib, "steps_per_tick": args.tick,
-                   "streams": args.streams, "mode": args.serve_mode, "batches": res.get("batches")},
+                   "streams": args.streams, "mode": args.serve_mode, "batches": res.get("batches"),
+                   "routing": "GPU (tsim_shortest_routes)", "routing_s": t_route,
+                   "route_entries": int(sum(len(w.trips.route_roads) for w in ws))},
         "latency_p50_s": summ["latency_p50_s"], "latency_p99_s": summ["latency_p99_s"],
         "queue_wait_p99_s": summ["queue_wait_p99_s"],
         "vehicle_steps_per_s": summ["vehicle_steps_per_s"],
@@ -385,6 +394,87 @@ def run_copy(args):
     ms = e0.elapsed_time(e1) / (args.steps or 10)
     print(json.dumps({"workload": "copy", "bytes_read": n, "bytes_written": n, "ms_per_copy": ms,
                       "GBps": 2 * n / (ms / 1e3) / 1e9}), flush=True)
+
+
+def run_route(args, emit=True):
+    """Device shortest routes for a served pricing job at the largest served
+    network size: a 32x32 jittered grid with per-road prices U(0, 120) s
+    and --route-trips uniform origin-destination trips.  The whole call
+    (pairs up, routes down, work space allocated beforehand) is timed over
+    --steps calls after one warm-up, against the host routing the served
+    jobs are generated with (scipy's Dijkstra from every destination, one
+    process) and the oracle on a bounded sample of destinations."""
+    import numpy as np
+    import torch
+    from paper_2406_10661_amd import tsim
+    from paper_2406_10661_amd import workloads as W
+    rng = np.random.default_rng(12)
+    net = W.jittered_grid(32, rng)
+    R = net.n_roads
+    n = int(args.route_trips)
+    price = rng.uniform(0, 120, R).astype(np.float32)
+    og, dg = W.uniform_od(net, rng, n)
+    ins = tsim._Inputs(net, tsim._NO_TRIPS, None)
+    import ctypes as C
+    lo, hint = C.c_size_t(0), C.c_size_t(0)
+    tsim._check(tsim.lib().tsim_route_footprint(C.byref(ins.net), n, C.byref(lo), C.byref(hint)))
+    ws = torch.empty(hint.value, dtype=torch.uint8, device="cuda")
+    calls = args.steps or 5
+    b, r, bad = tsim.shortest_routes(net, og, dg, price=price, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        b, r, bad = tsim.shortest_routes(net, og, dg, price=price, workspace=ws)
+    dev_s = (time.perf_counter() - t0) / calls
+    t0 = time.perf_counter()
+    hb, hr, reach = W.shortest_routes(net, og, dg, road_price=price, workers=1)
+    host_s = time.perf_counter() - t0
+    # route costs (FP64 over the movement costs) of both: equal up to FP32 rounding
+    G = W.movement_graph(net, price).tocsr()
+    dc, hc = route_costs(G, b, r), route_costs(G, hb, hr)
+    rel = np.abs(dc - hc) / np.maximum(hc, 1.0)
+    step = max(1, n // 2000)
+    same = np.mean([np.array_equal(r[b[c]:b[c + 1]], hr[hb[c]:hb[c + 1]]) for c in range(0, n, step)])
+    out = {"workload": f"route_pricing_jittered32_{n}", "metric": "routes/s", "value": n / dev_s,
+           "unit": "routes/s", "ms_per_call": dev_s * 1e3, "calls": calls, "pairs": n, "roads": R,
+           "movements": int(G.nnz), "unreachable": bad, "mean_route_roads": float(b[-1]) / n,
+           "host_scipy": {"value": n / host_s, "unit": "routes/s", "s": host_s, "cores": 1},
+           "vs_host": host_s / dev_s, "cost_max_rel_diff_vs_host": float(rel.max(initial=0.0)),
+           "identical_routes_vs_host_sampled": float(same)}
+    if not args.no_cpu_baseline:
+        # the oracle's FP32 Dijkstra on the trips of a bounded set of destinations
+        from oracle import oracle as O
+        O.build()
+        z = np.zeros(0, np.float32)
+        empty = W.Trips(depart_time=z, route_begin=np.zeros(1, np.int32), route_roads=np.zeros(0, np.int32),
+                        v0_factor=z, length=z)
+        osim = O.OracleSim(net, empty, W.Params())
+        dsel = np.unique(dg)[:args.route_oracle_dests]
+        idx = np.nonzero(np.isin(dg, dsel))[0]
+        idx = idx[np.argsort(dg[idx], kind="stable")]
+        t0 = time.perf_counter()
+        osim.shortest_routes(og[idx], dg[idx], price)
+        el = time.perf_counter() - t0
+        osim.close()
+        out["cpu_baseline"] = {"value": idx.size / el, "unit": "routes/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the {idx.size} trips to {dsel.size} destinations, {el:.1f} s"}
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def route_costs(G, begin, roads):
+    """Cost of each route of a CSR (begin, roads): the sum of G[a, b] over
+    its consecutive roads (a sparse movement-cost matrix)."""
+    import numpy as np
+    n = len(begin) - 1
+    if len(roads) < 2:
+        return np.zeros(n)
+    k = np.arange(len(roads) - 1)
+    seg = np.searchsorted(begin, k, side="right") - 1
+    valid = (k + 1) < begin[seg + 1]
+    w = np.asarray(G[roads[:-1][valid], roads[1:][valid]]).reshape(-1)
+    return np.bincount(seg[valid], weights=w, minlength=n)
 
 
 def summarize_window(path, steps, out=sys.stdout):
@@ -497,7 +587,9 @@ def traffic_report(pmc_dir, steps, window, copy_mib=1024, out=sys.stdout):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["city", "batch", "serve", "copy"], default="city")
+    ap.add_argument("--workload", choices=["city", "batch", "serve", "copy", "route"], default="city")
+    ap.add_argument("--route-trips", type=int, default=150000, help="route: origin-destination pairs")
+    ap.add_argument("--route-oracle-dests", type=int, default=40, help="route: destinations of the oracle sample")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
@@ -560,6 +652,8 @@ def main():
         return run_serve(args)
     if args.workload == "copy":
         return run_copy(args)
+    if args.workload == "route":
+        return run_route(args)
     return run_city(args)
 
 
@@ -724,7 +818,9 @@ def compact_legs(args):
     for 300 steps with phases set every 15 steps, against the same instances
     stepped one by one; and 100 served jobs (at most 100,000 vehicles each,
     Poisson 20 jobs/s, statistics after the first 10) through the
-    continuous-batching loop, against the one-job-at-a-time loop."""
+    continuous-batching loop, against the one-job-at-a-time loop; and the
+    device routes of a served pricing job at its largest (150,000 trips on a
+    32x32 jittered grid) against the host routing."""
     import copy
     b = copy.copy(args)
     b.instances, b.steps, b.concurrent = 64, 300, "0"
@@ -742,7 +838,10 @@ def compact_legs(args):
     served["config"] = rs["config"]
     if "saturated" in rs:
         served["saturated"] = rs["saturated"]
-    return {"batched": batched, "served": served}
+    r = copy.copy(args)
+    r.steps, r.route_trips = 5, 150000
+    routing = run_route(r, emit=False)
+    return {"batched": batched, "served": served, "routing": routing}
 
 
 if __name__ == "__main__":

@@ -2168,19 +2168,28 @@ int tsim_shortest_routes(const tsim_network* net, const float* road_price, const
     std::string err;
     int rc = route_graph_of_network(net, G, &err);
     if (rc) return fail(nullptr, rc, err);
+    // the routes go straight into the caller's array when they fit
+    struct Out : RouteSink {
+        int32_t* p;
+        int64_t cap;
+        int32_t* reserve(int64_t total) override
+        {
+            return total <= cap && total <= std::numeric_limits<int32_t>::max() ? p : nullptr;
+        }
+    } out;
+    out.p = route_roads;
+    out.cap = max_roads;
     std::vector<int64_t> begin;
-    std::vector<int32_t> roads;
     int bad = 0;
     rc = route_pairs(G, road_price, road_time, origin, dest, n, (hipStream_t)hip_stream, workspace, workspace_bytes,
-                     begin, roads, &bad, &err);
+                     begin, out, &bad, &err);
+    if (!begin.empty() && begin.back() <= std::numeric_limits<int32_t>::max())
+        for (size_t p = 0; p < begin.size(); ++p) route_begin[p] = (int32_t)begin[p];
+    if (rc == TSIM_ENOMEM && !begin.empty() && begin.back() > max_roads)
+        return fail(nullptr, TSIM_ENOMEM, "route_roads holds " + std::to_string(max_roads) +
+                                              " roads, the routes need " + std::to_string(begin.back()));
     if (rc) return fail(nullptr, rc, err);
-    if (begin[n] > std::numeric_limits<int32_t>::max()) return fail(nullptr, TSIM_ENOMEM, "more than 2^31 route roads");
-    for (int p = 0; p <= n; ++p) route_begin[p] = (int32_t)begin[p];
     if (n_unreachable) *n_unreachable = bad;
-    if (begin[n] > max_roads)
-        return fail(nullptr, TSIM_ENOMEM, "route_roads holds " + std::to_string(max_roads) + " roads, the routes need " +
-                                              std::to_string(begin[n]));
-    std::copy(roads.begin(), roads.end(), route_roads);
     return TSIM_OK;
 }
 
@@ -2278,12 +2287,13 @@ static int reroute_impl(tsim_handle* h, int k, const int32_t* vids_local, int32_
     RouteGraph G;
     route_graph_of_build(B, g, G);
     std::vector<int64_t> begin;
-    std::vector<int32_t> roads;
+    VectorSink sink;
     std::string err;
     int bad = 0;
     int rc = route_pairs(G, price, road_time, po.data(), pd.data(), (int)jobs.size(), h->stream, ws, ws_bytes, begin,
-                         roads, &bad, &err);
+                         sink, &bad, &err);
     if (rc) return fail(&h->err, rc, err);
+    const std::vector<int32_t>& roads = sink.roads;
     // install: per-vehicle route position, roads after it, next-road word
     // and (waiting) departure lanes, applied to the records on the device
     const int N = B.N;

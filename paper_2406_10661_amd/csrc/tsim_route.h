@@ -36,12 +36,30 @@ struct RouteGraph {
 size_t route_workspace_min(const RouteGraph& G, long long n);
 size_t route_workspace_hint(const RouteGraph& G, long long n);
 
+// Where the routes go: room for `total` road ids, or null when the caller
+// cannot hold them.
+struct RouteSink {
+    virtual int32_t* reserve(int64_t total) = 0;
+    virtual ~RouteSink() = default;
+};
+
+struct VectorSink : RouteSink {
+    std::vector<int32_t> roads;
+    int32_t* reserve(int64_t total) override
+    {
+        roads.resize((size_t)total);
+        return roads.data();
+    }
+};
+
 // Routes for n (origin, destination) pairs of local road ids under prices
-// price[R] and road times road_time[R] (either may be null): begin[n+1] and
-// roads (CSR, origin first, destination last, empty when unreachable).
-// Returns a TSIM_* status (message in *err); synchronises the stream.
+// price[R] and road times road_time[R] (either may be null): begin[n+1] (CSR
+// in the callers' order) and the roads written to sink.reserve(begin[n])
+// (origin first, destination last, empty when unreachable).  Returns a
+// TSIM_* status (message in *err; TSIM_ENOMEM with begin filled when the
+// sink has no room); synchronises the stream.
 int route_pairs(const RouteGraph& G, const float* price, const float* road_time, const int32_t* origin,
                 const int32_t* dest, int n, hipStream_t stream, void* ws, size_t ws_bytes,
-                std::vector<int64_t>& begin, std::vector<int32_t>& roads, int* n_unreachable, std::string* err);
+                std::vector<int64_t>& begin, RouteSink& sink, int* n_unreachable, std::string* err);
 
 }  // namespace tsim

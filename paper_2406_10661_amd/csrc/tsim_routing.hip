@@ -24,6 +24,7 @@
 //                    origin, first counting, then writing the route.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 
 #include "../../include/tsim.h"
@@ -273,7 +274,7 @@ size_t route_workspace_hint(const RouteGraph& G, long long n)
 
 int route_pairs(const RouteGraph& G, const float* price, const float* road_time, const int32_t* origin,
                 const int32_t* dest, int n, hipStream_t stream, void* ws, size_t ws_bytes,
-                std::vector<int64_t>& begin, std::vector<int32_t>& roads, int* n_unreachable, std::string* err)
+                std::vector<int64_t>& begin, RouteSink& sink, int* n_unreachable, std::string* err)
 {
     const int R = G.R;
     const int E = (int)G.e_to.size();
@@ -296,7 +297,6 @@ int route_pairs(const RouteGraph& G, const float* price, const float* road_time,
             return TSIM_EINVAL;
         }
     begin.assign((size_t)n + 1, 0);
-    roads.clear();
     if (n_unreachable) *n_unreachable = 0;
     if (n == 0) return TSIM_OK;
     Layout y = fixed_layout(G, n);
@@ -304,10 +304,12 @@ int route_pairs(const RouteGraph& G, const float* price, const float* road_time,
         *err = "route workspace too small";
         return TSIM_ENOMEM;
     }
-    // pairs by destination (stable), distinct destinations in that order
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return dest[a] < dest[b]; });
+    // pairs by destination (counting sort, stable), distinct destinations
+    // in increasing id
+    std::vector<int32_t> order(n), at_d((size_t)R + 1, 0);
+    for (int p = 0; p < n; ++p) ++at_d[dest[p] + 1];
+    for (int r = 0; r < R; ++r) at_d[r + 1] += at_d[r];
+    for (int p = 0; p < n; ++p) order[at_d[dest[p]]++] = p;
     std::vector<int32_t> so(n), sd(n), sud(n), ud;
     for (int c = 0; c < n; ++c) {
         const int p = order[c];
@@ -324,7 +326,7 @@ int route_pairs(const RouteGraph& G, const float* price, const float* road_time,
     y.C = (int)C;
     y.nxt = y.fixed;
     y.stage = y.nxt + up_align((size_t)C * R * 4);
-    y.S = (long long)((ws_bytes - y.stage) / 4);
+    y.S = std::min<long long>((long long)((ws_bytes - y.stage) / 4), std::numeric_limits<int32_t>::max());
 
     char* base = (char*)ws;
     auto at = [&](size_t off) { return (void*)(base + off); };
@@ -370,66 +372,97 @@ int route_pairs(const RouteGraph& G, const float* price, const float* road_time,
     int32_t* stage = (int32_t*)at(y.stage);
     int32_t* d_plen = (int32_t*)at(y.plen);
     int32_t* d_poff = (int32_t*)at(y.poff);
-    std::vector<int32_t> hlen(n), hoff(n);
-    std::vector<int64_t> hstart(n, 0);   // start of each sorted pair's route in roads_sorted
-    std::vector<int32_t> roads_sorted;
-    int bad = 0;
-    int pa = 0;
-    for (int c0 = 0; c0 < nud; c0 += (int)C) {
-        const int c1 = (int)std::min<long long>(nud, c0 + C);
-        int pb = pa;
-        while (pb < n && sud[pb] < c1) ++pb;
-        const int np = pb - pa;
+    const int32_t* d_po = (const int32_t*)at(y.porig);
+    const int32_t* d_pd = (const int32_t*)at(y.pdest);
+    const int32_t* d_pu = (const int32_t*)at(y.pud);
+    // chunks of C destinations and their pairs (contiguous in sorted order)
+    const int n_chunks = (int)((nud + C - 1) / C);
+    std::vector<int> chunk_pa(n_chunks + 1, n);
+    for (int c = n - 1; c >= 0; --c) chunk_pa[sud[c] / C] = c;
+    for (int k = n_chunks - 1; k >= 0; --k) chunk_pa[k] = std::min(chunk_pa[k], chunk_pa[k + 1]);
+    auto tree = [&](int k) {
+        const int c0 = (int)(k * C), c1 = (int)std::min<long long>(nud, c0 + C);
         RCHK(put(y.dests, ud.data() + c0, (size_t)(c1 - c0) * 4));
         k_route_tree<<<c1 - c0, kTreeThreads, lds, stream>>>(D, (const int32_t*)at(y.dests), nxt);
         RCHK(hipGetLastError());
-        const int32_t* po = (const int32_t*)at(y.porig) + pa;
-        const int32_t* pd = (const int32_t*)at(y.pdest) + pa;
-        const int32_t* pu = (const int32_t*)at(y.pud) + pa;
-        const int wg = (np + kWalkThreads - 1) / kWalkThreads;
-        k_route_walk<<<wg, kWalkThreads, 0, stream>>>(nxt, R, c0, po, pd, pu, np, d_plen + pa, d_poff + pa, stage, 0);
+        return TSIM_OK;
+    };
+    auto walk = [&](int k, int q0, int q1, int write) {
+        const int np = q1 - q0;
+        if (np <= 0) return TSIM_OK;
+        k_route_walk<<<(np + kWalkThreads - 1) / kWalkThreads, kWalkThreads, 0, stream>>>(
+            nxt, R, (int)(k * C), d_po + q0, d_pd + q0, d_pu + q0, np, d_plen + q0, d_poff + q0, stage, write);
         RCHK(hipGetLastError());
-        RCHK(hipMemcpyAsync(hlen.data() + pa, d_plen + pa, (size_t)np * 4, hipMemcpyDeviceToHost, stream));
+        return TSIM_OK;
+    };
+    // pass 1: each chunk's cost-to-go trees, then the lengths of its routes
+    for (int k = 0; k < n_chunks; ++k) {
+        int rc = tree(k);
+        if (!rc) rc = walk(k, chunk_pa[k], chunk_pa[k + 1], 0);
+        if (rc) return rc;
+    }
+    std::vector<int32_t> hlen(n);
+    RCHK(hipMemcpyAsync(hlen.data(), d_plen, (size_t)n * 4, hipMemcpyDeviceToHost, stream));
+    RCHK(hipStreamSynchronize(stream));
+    int bad = 0;
+    for (int c = 0; c < n; ++c) {
+        begin[(size_t)order[c] + 1] = hlen[c];
+        bad += hlen[c] == 0;
+    }
+    for (int p = 0; p < n; ++p) begin[p + 1] += begin[p];
+    if (n_unreachable) *n_unreachable = bad;
+    const int64_t total = begin[n];
+    int32_t* out = sink.reserve(total);
+    if (!out && total > 0) {
+        *err = "no room for the routes (" + std::to_string(total) + " roads)";
+        return TSIM_ENOMEM;
+    }
+    if (total == 0) return TSIM_OK;
+    // pass 2: the routes, the last chunk first (its trees are still in
+    // place), every other chunk's trees computed again
+    std::vector<int32_t> hoff(n);
+    if (total <= y.S) {
+        // every route written at its place in the callers' order: one copy
+        for (int c = 0; c < n; ++c) hoff[c] = (int32_t)begin[order[c]];
+        RCHK(put(y.poff, hoff.data(), (size_t)n * 4));
+        for (int k = n_chunks - 1; k >= 0; --k) {
+            int rc = k == n_chunks - 1 ? TSIM_OK : tree(k);
+            if (!rc) rc = walk(k, chunk_pa[k], chunk_pa[k + 1], 1);
+            if (rc) return rc;
+        }
+        RCHK(hipMemcpyAsync(out, stage, (size_t)total * 4, hipMemcpyDeviceToHost, stream));
         RCHK(hipStreamSynchronize(stream));
-        // write the chunk's routes through the staging buffer, as many
-        // pairs at a time as it holds
-        int q = pa;
-        while (q < pb) {
+        return TSIM_OK;
+    }
+    // the staging buffer holds part of the routes: batches of pairs, each
+    // copied down and placed
+    std::vector<int32_t> tmp;
+    for (int k = n_chunks - 1; k >= 0; --k) {
+        if (k != n_chunks - 1) {
+            const int rc = tree(k);
+            if (rc) return rc;
+        }
+        int q = chunk_pa[k];
+        while (q < chunk_pa[k + 1]) {
             long long used = 0;
             int q2 = q;
-            while (q2 < pb && used + hlen[q2] <= y.S) {
+            while (q2 < chunk_pa[k + 1] && used + hlen[q2] <= y.S) {
                 hoff[q2] = (int32_t)used;
                 used += hlen[q2];
                 ++q2;
             }
             RCHK(put(y.poff + (size_t)q * 4, hoff.data() + q, (size_t)(q2 - q) * 4));
-            k_route_walk<<<(q2 - q + kWalkThreads - 1) / kWalkThreads, kWalkThreads, 0, stream>>>(
-                nxt, R, c0, po + (q - pa), pd + (q - pa), pu + (q - pa), q2 - q, d_plen + q, d_poff + q, stage, 1);
-            RCHK(hipGetLastError());
-            const size_t at0 = roads_sorted.size();
-            roads_sorted.resize(at0 + (size_t)used);
+            const int rc = walk(k, q, q2, 1);
+            if (rc) return rc;
+            tmp.resize((size_t)used);
             if (used)
-                RCHK(hipMemcpyAsync(roads_sorted.data() + at0, stage, (size_t)used * 4, hipMemcpyDeviceToHost, stream));
+                RCHK(hipMemcpyAsync(tmp.data(), stage, (size_t)used * 4, hipMemcpyDeviceToHost, stream));
             RCHK(hipStreamSynchronize(stream));
-            for (int c = q; c < q2; ++c) {
-                hstart[c] = (int64_t)at0 + hoff[c];
-                bad += hlen[c] == 0;
-            }
+            for (int c = q; c < q2; ++c)
+                std::copy(tmp.begin() + hoff[c], tmp.begin() + hoff[c] + hlen[c], out + begin[order[c]]);
             q = q2;
         }
-        pa = pb;
     }
-    // back to the callers' pair order
-    std::vector<int32_t> rank(n);
-    for (int c = 0; c < n; ++c) rank[order[c]] = c;
-    for (int p = 0; p < n; ++p) begin[p + 1] = begin[p] + hlen[rank[p]];
-    roads.resize((size_t)begin[n]);
-    for (int p = 0; p < n; ++p) {
-        const int c = rank[p];
-        std::copy(roads_sorted.begin() + hstart[c], roads_sorted.begin() + hstart[c] + hlen[c],
-                  roads.begin() + begin[p]);
-    }
-    if (n_unreachable) *n_unreachable = bad;
     return TSIM_OK;
 }
 

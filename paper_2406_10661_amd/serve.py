@@ -429,6 +429,35 @@ class BatchedServeLoop:
         return {"jobs": done, "wall_s": wall, "batches": len(batches), "peak_bytes": reserved, "capacity": cap}
 
 
+def route_jobs_on_device(workloads, device="cuda:0"):
+    """Routes, on the GPU, every job whose trips arrive without routes: the
+    least-cost route of each trip from its origin road to its destination
+    road (``extra['od']``) under the job's road prices (``extra['price']``,
+    none for a timing-plan job), the congestion-pricing routing of Section 4
+    done by ``tsim_shortest_routes``.  One work space serves every job.
+    Returns the seconds spent."""
+    import numpy as np
+    import torch
+    from paper_2406_10661_amd import tsim
+    t0 = time.perf_counter()
+    ws = None
+    for w in workloads:
+        if w.trips.route_roads is not None:
+            continue
+        o, d = w.extra["od"]
+        price = w.extra.get("price")
+        need = tsim.route_workspace_bytes(w.network, len(o))
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+        b, r, bad = tsim.shortest_routes(w.network, o, d, price=None if price is None else np.asarray(price, np.float32),
+                                         device=device, workspace=ws)
+        if bad:
+            raise RuntimeError(f"{w.name}: {bad} trips cannot reach their destination")
+        w.trips.route_begin, w.trips.route_roads = b, r
+    torch.cuda.synchronize(device)
+    return time.perf_counter() - t0
+
+
 def summarize(result, skip=0):
     """p50/p99 latency, jobs/s and vehicle-steps/s over the jobs after the
     first `skip` (by arrival)."""

@@ -249,6 +249,15 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
+def route_workspace_bytes(net, n_pairs, least=False):
+    """Device work space for shortest_routes over n_pairs pairs of net: the
+    suggested size (few passes), or with least=True the least one."""
+    ins = _Inputs(net, _NO_TRIPS, None)
+    lo, hint = C.c_size_t(0), C.c_size_t(0)
+    _check(lib().tsim_route_footprint(C.byref(ins.net), int(n_pairs), C.byref(lo), C.byref(hint)))
+    return int(lo.value if least else hint.value)
+
+
 def shortest_routes(net, origins, dests, price=None, road_time=None, device="cuda:0", stream=None,
                     workspace=None):
     """Routes of least cost for (origin road, destination road) pairs of a
@@ -269,9 +278,9 @@ def shortest_routes(net, origins, dests, price=None, road_time=None, device="cud
     st = stream if stream is not None else torch.cuda.current_stream(dev)
     begin = np.zeros(n + 1, np.int32)
     bad = np.zeros(1, np.int32)
-    cap = max(64 * n, 1)
+    cap = max(48 * n, 1)
     while True:
-        roads = np.zeros(cap, np.int32)
+        roads = np.empty(cap, np.int32)
         rc = lib().tsim_shortest_routes(C.byref(ins.net), None if pr is None else _p(pr),
                                         None if rt is None else _p(rt), _p(o), _p(d), n,
                                         C.c_void_p(st.cuda_stream), C.c_void_p(ws.data_ptr()),
@@ -280,7 +289,7 @@ def shortest_routes(net, origins, dests, price=None, road_time=None, device="cud
             cap = int(begin[n])
             continue
         _check(rc)
-        return begin, roads[:int(begin[n])].copy(), int(bad[0])
+        return begin, roads[:int(begin[n])], int(bad[0])
 
 
 class Sim:

@@ -432,16 +432,21 @@ def shortest_routes(net: Network, origins, dests, road_price=None, chunk=64, wor
     return begin, r, reach
 
 
-def _finish_trips(net, rng, origins, dests, depart, road_price=None, length=5.0, workers=None):
-    begin, roads, reach = shortest_routes(net, origins, dests, road_price, workers=workers)
-    if not reach.all():
-        # keep only reachable trips (the generators redraw before this point)
-        raise RuntimeError(f"{(~reach).sum()} unreachable trips")
+def _finish_trips(net, rng, origins, dests, depart, road_price=None, length=5.0, workers=None, route=True):
+    """Trip table of the given origin-destination roads; route=False leaves
+    the routes unset (None) for a router that runs elsewhere."""
+    begin = roads = None
+    if route:
+        begin, roads, reach = shortest_routes(net, origins, dests, road_price, workers=workers)
+        if not reach.all():
+            # keep only reachable trips (the generators redraw before this point)
+            raise RuntimeError(f"{(~reach).sum()} unreachable trips")
+        begin, roads = begin.astype(np.int32), roads.astype(np.int32)
     N = origins.shape[0]
     return Trips(
         depart_time=np.asarray(depart, np.float32),
-        route_begin=begin.astype(np.int32),
-        route_roads=roads.astype(np.int32),
+        route_begin=begin,
+        route_roads=roads,
         v0_factor=rng.uniform(0.8, 1.2, N).astype(np.float32),
         length=np.full(N, length, np.float32),
     )
@@ -558,13 +563,14 @@ def batch_workload(n_instances=256, steps=1800, workers=None, first=0):
     return [_instance_worker(j) for j in jobs]
 
 
-def served_jobs(n_jobs, workers=None, max_vehicles=None):
-    """Jobs 0 .. n_jobs-1 of ``config5_job``, generated in parallel processes."""
+def served_jobs(n_jobs, workers=None, max_vehicles=None, route=True):
+    """Jobs 0 .. n_jobs-1 of ``config5_job``, generated in parallel processes
+    (route=False: routes left for the server to compute)."""
     import os
     import multiprocessing as mp
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
-    jobs = [("serve", j, {"max_vehicles": max_vehicles}) for j in range(n_jobs)]
+    jobs = [("serve", j, {"max_vehicles": max_vehicles, "route": route}) for j in range(n_jobs)]
     if workers > 1 and n_jobs > 1:
         with mp.get_context("fork").Pool(workers) as pool:
             return pool.map(_instance_worker, jobs, chunksize=1)
@@ -579,12 +585,14 @@ def random_phase_schedule(net: Network, seed, n_updates):
     return np.minimum((u * nph[None, :]).astype(np.int32), np.maximum(nph - 1, 0)[None, :]).astype(np.int32)
 
 
-def config5_job(j, max_vehicles=None, workers=None):
+def config5_job(j, max_vehicles=None, workers=None, route=True):
     """Job j of the served workload: w.p. 1/2 a C1-style grid (n~U{4..16}),
     else a jittered grid (n~U{8..32}); N log-uniform in [10k, 500k] capped by
     the grid-size coupling; horizon U{300..3600}; w.p. 1/2 a signal-timing
     plan (phases U{15..60} s) else per-road prices U(0,120) s added to the
-    routing cost."""
+    routing cost.  The job's origin and destination roads and its prices are
+    kept in ``extra`` ("od", "price"); route=False leaves the routes to the
+    server (every other draw is the same)."""
     rng = np.random.default_rng(10000 + j)
     plan = rng.random() < 0.5
     c1_style = rng.random() < 0.5
@@ -603,9 +611,9 @@ def config5_job(j, max_vehicles=None, workers=None):
     price = None if plan else rng.uniform(0.0, 120.0, net.n_roads)
     o, d = uniform_od(net, rng, N)
     dep = rng.uniform(0.0, 0.5 * H, N)
-    trips = _finish_trips(net, rng, o, d, dep, road_price=price, workers=workers)
+    trips = _finish_trips(net, rng, o, d, dep, road_price=price, workers=workers, route=route)
     return Workload(f"job{j}", net, trips, Params(seed=10000 + j), H,
-                    extra={"kind": "timing_plan" if plan else "pricing"})
+                    extra={"kind": "timing_plan" if plan else "pricing", "od": (o, d), "price": price})
 
 
 def poisson_arrivals(n_jobs, rate=20.0, seed=7):

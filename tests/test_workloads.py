@@ -95,3 +95,19 @@ def test_workload_file_roundtrip(tmp_path):
             assert b is None, f.name
             continue
         assert a.dtype == b.dtype and np.array_equal(a, b), f.name
+
+
+def test_served_job_without_routes_keeps_every_other_draw():
+    """config5_job(route=False) leaves the routes to the server and draws
+    everything else as the routed job does; the origin and destination
+    roads and the prices are kept for the router."""
+    a = W.config5_job(3, max_vehicles=2000)
+    b = W.config5_job(3, max_vehicles=2000, route=False)
+    assert b.trips.route_begin is None and b.trips.route_roads is None
+    for f in ("depart_time", "v0_factor", "length"):
+        assert np.array_equal(getattr(a.trips, f), getattr(b.trips, f))
+    o, d = b.extra["od"]
+    rb = a.trips.route_begin
+    assert np.array_equal(a.trips.route_roads[rb[:-1]], o)
+    assert np.array_equal(a.trips.route_roads[rb[1:] - 1], d)
+    assert (a.extra["price"] is None) == (a.extra["kind"] == "timing_plan")
