@@ -11,17 +11,21 @@
 // equal candidate cost the smaller road id is taken.
 //
 // Kernels:
-//   k_route_weights  one thread per movement: the movement's cost.
-//   k_route_tree     one workgroup per destination: the cost-to-go of every
-//                    road, held in LDS, by Bellman-Ford sweeps over the
-//                    movements (each road relaxed from its successors,
-//                    updates seen within the sweep) until a sweep changes
-//                    nothing; then each road's next road toward the
-//                    destination.  The costs are positive and the candidate
-//                    sum is monotone, so any order of relaxations from +inf
-//                    settles on the same least costs as Dijkstra's order.
-//   k_route_walk     one thread per pair: follows the next roads from the
-//                    origin, first counting, then writing the route.
+//   k_route_weights   one thread per movement: the movement's cost.
+//   k_route_tree_reg  networks of at most 16,384 movements: one workgroup
+//                     per group of up to 16 destinations, the movements
+//                     held in registers, every destination's cost-to-go in
+//                     LDS; Bellman-Ford sweeps relax every movement with an
+//                     LDS atomic minimum until a sweep changes nothing, then
+//                     each road's next road toward each destination.
+//   k_route_tree      larger networks: one workgroup per destination, the
+//                     movements read from memory, each road relaxed from its
+//                     successors.
+//   k_route_walk      one thread per pair: follows the next roads from the
+//                     origin, first counting, then writing the route.
+// The costs are non-negative and the candidate sum is monotone, so any order
+// of relaxations from +inf settles on the same least costs as Dijkstra's
+// order, bit for bit.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -118,6 +122,90 @@ __global__ __launch_bounds__(kTreeThreads) void k_route_tree(RouteDev G, const i
     }
 }
 
+// k_route_tree for networks of at most kRegMoves movements: each of the
+// workgroup's 1024 threads holds up to EPT movements (source road, target
+// road, cost) in registers for the whole kernel, and the cost-to-go of K
+// destinations lives in LDS; a sweep relaxes every movement for every
+// destination that changed in the sweep before, lowering the source road's
+// cost with an LDS atomic minimum (non-negative floats order as their bit
+// patterns).
+constexpr int kRegThreads = 1024;
+constexpr int kRegMaxK = 16;
+constexpr int kRegMoves = 16 * kRegThreads;
+
+template <int EPT>
+__global__ __launch_bounds__(kRegThreads) void k_route_tree_reg(RouteDev G, const int32_t* e_from,
+                                                                const int32_t* dests, int nd, int K, int32_t* nxt)
+{
+    extern __shared__ float dist[];   // [K][R]
+    __shared__ int chg[2][kRegMaxK];  // destinations changed in the last sweep / this sweep
+    const int R = G.R, E = G.E, tid = threadIdx.x;
+    int fr[EPT], to[EPT];
+    float w[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int e = tid + j * kRegThreads;
+        const bool ok = e < E;
+        fr[j] = ok ? e_from[e] : -1;
+        to[j] = ok ? G.e_to[e] : 0;
+        w[j] = ok ? G.w[e] : 0.0f;
+    }
+    const int base = blockIdx.x * K;
+    const int nk = min(K, nd - base);
+    for (int i = tid; i < nk * R; i += kRegThreads) {
+        const int k = i / R, r = i - k * R;
+        dist[i] = r == dests[base + k] ? 0.0f : INFINITY;
+    }
+    if (tid < kRegMaxK) {
+        chg[0][tid] = 1;
+        chg[1][tid] = 0;
+    }
+    __syncthreads();
+    for (int sweep = 0;; ++sweep) {
+        const int cur = sweep & 1;
+        for (int k = 0; k < nk; ++k) {
+            if (!chg[cur][k]) continue;
+            float* dk = dist + (size_t)k * R;
+            int changed = 0;
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                if (fr[j] < 0) continue;
+                const float c = w[j] + dk[to[j]];
+                if (c < dk[fr[j]]) {
+                    const int old = atomicMin((int*)(dk + fr[j]), __float_as_int(c));
+                    changed |= __int_as_float(old) > c;
+                }
+            }
+            if (changed) chg[cur ^ 1][k] = 1;
+        }
+        __syncthreads();
+        if (tid < kRegMaxK) chg[cur][tid] = 0;
+        int any = 0;
+        for (int k = 0; k < nk; ++k) any |= chg[cur ^ 1][k];
+        if (!__syncthreads_or(any)) break;
+    }
+    // each road's next road toward each destination
+    for (int i = tid; i < nk * R; i += kRegThreads) {
+        const int k = i / R, r = i - k * R, d = dests[base + k];
+        const float* dk = dist + (size_t)k * R;
+        int nx = -1;
+        if (r == d) {
+            nx = d;
+        } else if (dk[r] < INFINITY) {
+            float best = INFINITY;
+            for (int e = G.e_begin[r]; e < G.e_begin[r + 1]; ++e) {
+                const int b = G.e_to[e];
+                const float c = G.w[e] + dk[b];
+                if (c < best) {
+                    best = c;
+                    nx = b;
+                }
+            }
+        }
+        nxt[(size_t)(base + k) * R + r] = nx;
+    }
+}
+
 // pairs p of one chunk (pointers already offset to the chunk's first pair);
 // pud[p] - c0 is the pair's destination slot in nxt.  write = 0: plen[p] =
 // roads of the route (0: unreachable, or longer than the network has
@@ -155,7 +243,8 @@ constexpr size_t kAlign = 256;
 size_t up_align(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rlb, rlen, llim, eb, eto, ejb, jlen, jlim, price, time, w, porig, pdest, pud, plen, poff, dests, nxt, stage;
+    size_t rlb, rlen, llim, eb, eto, efr, ejb, jlen, jlim, price, time, w, porig, pdest, pud, plen, poff, dests, nxt,
+        stage;
     size_t fixed;   // bytes before nxt
     int C = 0;      // destinations per pass
     long long S = 0;  // staging entries
@@ -176,6 +265,7 @@ Layout fixed_layout(const RouteGraph& G, long long n)
     y.llim = take(L * 4);
     y.eb = take((R + 1) * 4);
     y.eto = take(E * 4);
+    y.efr = take(E * 4);
     y.ejb = take((E + 1) * 4);
     y.jlen = take(J * 4);
     y.jlim = take(J * 4);
@@ -365,8 +455,39 @@ int route_pairs(const RouteGraph& G, const float* price, const float* road_time,
         k_route_weights<<<(E + 255) / 256, 256, 0, stream>>>(D);
         RCHK(hipGetLastError());
     }
-    const size_t lds = (size_t)R * 4;
-    RCHK(hipFuncSetAttribute((const void*)k_route_tree, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // the tree kernel: movements held in registers with up to 16
+    // destinations per workgroup (enough workgroups to cover the GPU twice)
+    // when there are at most kRegMoves of them, else read from memory with
+    // one destination per workgroup
+    int dev = 0, lds_max = 0, n_cu = 0;
+    RCHK(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || lds_max <= 0)
+        RCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    RCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int ept = (E + kRegThreads - 1) / kRegThreads;
+    int K = 0;
+    if (E <= kRegMoves) {
+        const long long fit = std::min<long long>(kRegMaxK, (long long)(lds_max - 256) / ((long long)R * 4));
+        const long long want = (std::min<long long>(C, nud) + 2LL * std::max(n_cu, 1) - 1) / (2LL * std::max(n_cu, 1));
+        K = (int)std::max<long long>(0, std::min(fit, std::max<long long>(want, 1)));
+    }
+    const size_t lds = K ? (size_t)K * R * 4 : (size_t)R * 4;
+    if (lds > (size_t)lds_max) {
+        *err = "the network's cost-to-go does not fit in LDS";
+        return TSIM_EINVAL;
+    }
+    auto reg_kernel = [&]() -> const void* {
+        if (ept <= 4) return (const void*)k_route_tree_reg<4>;
+        if (ept <= 8) return (const void*)k_route_tree_reg<8>;
+        return (const void*)k_route_tree_reg<16>;
+    };
+    RCHK(hipFuncSetAttribute(K ? reg_kernel() : (const void*)k_route_tree, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+    std::vector<int32_t> e_from(E);
+    for (int r = 0; r < R; ++r)
+        for (int e = G.e_begin[r]; e < G.e_begin[r + 1]; ++e) e_from[e] = r;
+    RCHK(put(y.efr, e_from.data(), (size_t)E * 4));
+    const int32_t* d_efr = (const int32_t*)at(y.efr);
 
     int32_t* nxt = (int32_t*)at(y.nxt);
     int32_t* stage = (int32_t*)at(y.stage);
@@ -383,7 +504,16 @@ int route_pairs(const RouteGraph& G, const float* price, const float* road_time,
     auto tree = [&](int k) {
         const int c0 = (int)(k * C), c1 = (int)std::min<long long>(nud, c0 + C);
         RCHK(put(y.dests, ud.data() + c0, (size_t)(c1 - c0) * 4));
-        k_route_tree<<<c1 - c0, kTreeThreads, lds, stream>>>(D, (const int32_t*)at(y.dests), nxt);
+        const int32_t* dd = (const int32_t*)at(y.dests);
+        const int nwg = K ? (c1 - c0 + K - 1) / K : 0;
+        if (K && ept <= 4)
+            k_route_tree_reg<4><<<nwg, kRegThreads, lds, stream>>>(D, d_efr, dd, c1 - c0, K, nxt);
+        else if (K && ept <= 8)
+            k_route_tree_reg<8><<<nwg, kRegThreads, lds, stream>>>(D, d_efr, dd, c1 - c0, K, nxt);
+        else if (K)
+            k_route_tree_reg<16><<<nwg, kRegThreads, lds, stream>>>(D, d_efr, dd, c1 - c0, K, nxt);
+        else
+            k_route_tree<<<c1 - c0, kTreeThreads, lds, stream>>>(D, (const int32_t*)at(y.dests), nxt);
         RCHK(hipGetLastError());
         return TSIM_OK;
     };

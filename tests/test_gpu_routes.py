@@ -142,6 +142,23 @@ def test_served_size_routes(O, T):
           f"mean length {np.mean([len(x) for x in routes]):.1f}", flush=True)
 
 
+def test_large_network_reads_movements_from_memory(O, T):
+    """A 75x75 grid (22,200 roads, more than 65,535 movements: the movement
+    table does not fit in LDS, so the trees read it from memory) with
+    prices: routes of 400 pairs over 4 destinations equal the oracle's."""
+    rng = np.random.default_rng(6)
+    net = W.grid_network(75)
+    R = net.n_roads
+    assert len(_movements(net)) > 65535
+    price = rng.uniform(0, 60, R).astype(np.float32)
+    dsel = rng.choice(R, 4, replace=False)
+    dg = np.repeat(dsel, 100)
+    og = rng.integers(0, R, dg.size)
+    b, r, bad = T.shortest_routes(net, og, dg, price=price)
+    want, wbad = _oracle_routes(O, net, og, dg, price)
+    assert _split(b, r) == want and bad == wbad
+
+
 def test_no_pairs_and_one_road_routes(T):
     """No pairs: an empty result; origin = destination: that one road."""
     net = W.grid_network(3)
