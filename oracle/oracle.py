@@ -56,6 +56,7 @@ def lib():
         L.osim_set_lane_restriction.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_set_vehicle_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double]
         L.osim_set_trip_ends.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.osim_set_trip_starts.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.osim_get_route.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.osim_get_junctions.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.osim_get_metrics.argtypes = [C.c_void_p, C.c_void_p]
@@ -126,6 +127,11 @@ class OracleSim:
             e = np.ascontiguousarray(end_s, np.float32).astype(np.float64)
             ids = np.arange(self.N, dtype=np.int32)
             L.osim_set_trip_ends(self.h, self.N, _p(ids), _p(e))
+        start_s = getattr(trips, "start_s", None)
+        if start_s is not None:
+            b = np.ascontiguousarray(start_s, np.float32).astype(np.float64)
+            ids = np.arange(self.N, dtype=np.int32)
+            L.osim_set_trip_starts(self.h, self.N, _p(ids), _p(b))
 
     def close(self):
         if self.h:

@@ -36,7 +36,8 @@
  * tau <= t dt, one per lane, blocked head, feeder reach), merge priority,
  * travelling time, mean speed and its horizon average, lane queue length
  * and cooperative yielding, lane restrictions (departures, lane changes,
- * closed junction lanes and the lane group they leave), trip end positions,
+ * closed junction lanes and the lane group they leave), trip end and start
+ * positions (departures from an AOI's connection partway along a lane),
  * each shown to fail under a named mistake; shortest routes against
  * hand-derived routes, brute force over every simple route of small
  * networks with exact costs, and scipy's Dijkstra on a grid.
@@ -85,6 +86,7 @@ typedef struct osim {
     int *route_begin, *route;    /* CSR of the routes given at creation */
     int *rstart, *rlen;          /* [N] the route in force: route[rstart, rstart + rlen) */
     double *end_s;               /* [N] trip end position on the last road, < 0: the road's end */
+    double *start_s;             /* [N] trip start position on the origin road, <= 0: the road's start */
     long route_n, route_cap;     /* route entries used / allocated (set_vehicle_route appends) */
     int *q_begin, *q_veh;        /* [R+1] departure queue of each origin road, (tau, id) order */
     /* state */
@@ -264,6 +266,7 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
     s->tau = (double *)xcalloc(N, sizeof(double));
     s->end_s = (double *)xcalloc(N, sizeof(double));
     for (int i = 0; i < N; ++i) s->end_s[i] = -1.0;
+    s->start_s = (double *)xcalloc(N, sizeof(double));
     s->f = (double *)xcalloc(N, sizeof(double));
     s->L = (double *)xcalloc(N, sizeof(double));
     s->route_begin = (int *)xcalloc(N + 1, sizeof(int));
@@ -317,7 +320,7 @@ osim *osim_create(int NJ, int R, const int *road_from, const int *road_to, const
 void osim_destroy(osim *s)
 {
     if (!s) return;
-    void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim, s->restricted, s->end_s,
+    void *ptrs[] = {s->road_from, s->road_to, s->road_lane_begin, s->lane_road, s->lane_len, s->lane_lim, s->restricted, s->end_s, s->start_s,
                     s->jl_in, s->jl_out, s->jl_junction, s->junc_phase_begin, s->phase_green_begin,
                     s->phase_green_jl, s->phase_dur, s->policy, s->manual_phase, s->out_begin, s->out_jl,
                     s->feed_begin, s->feed_jl, s->tau, s->f, s->L, s->route_begin, s->route, s->rstart, s->rlen, s->q_begin,
@@ -643,14 +646,43 @@ static void build_index(osim *s)
 /* P2 departures (Appendix B.2: vehicles whose departure time has come are   */
 /* put into lanes when the connection is safe)                               */
 /* [reading] per origin road, waiting vehicles leave in (tau, id) order;     */
-/* the head takes the lane of its lane group with the most room behind the   */
-/* rearmost vehicle (room = x - L of that vehicle, +inf on an empty lane;    */
-/* ties to the lower lane index), needs room >= s0, and needs every feeder   */
-/* junction lane's front vehicle h to satisfy                                */
-/* x_h + v_h dt + a_max dt^2/2 - len(feeder) <= -L_head (cannot reach its    */
-/* rear); at most one insertion per lane per step; the first head that       */
-/* cannot enter stops its road's queue for this step.  Entry at x = 0, v = 0.*/
+/* the head takes the lane of its lane group with the most room ahead of it  */
+/* (ties to the lower lane index), needs that room >= s0, and needs nothing  */
+/* behind it able to reach its rear within the step (reach = x + v dt +      */
+/* a_max dt^2/2); at most one insertion per lane per step; the first head    */
+/* that cannot enter stops its road's queue for this step.  v = 0.           */
+/*  - A trip starting at its origin road's start (start position <= 0)       */
+/*    enters at x = 0 behind every vehicle of the lane: room = x - L of the  */
+/*    rearmost vehicle (+inf on an empty lane); behind it are the front      */
+/*    vehicles h of the feeder junction lanes, whose reach beyond their lane */
+/*    end, x_h + v_h dt + a_max dt^2/2 - len(feeder), must be <= -L_head.    */
+/*  - A trip starting at an AOI's connection partway along the road          */
+/*    (start position p > 0; Appendix B.1: a start may be a position in a    */
+/*    lane; Appendix B.2: an AOI puts a due vehicle into the lane when the   */
+/*    connection is safe) enters with its front at x = p: room = x - L of    */
+/*    the nearest vehicle ahead (x > p, or x = p with a smaller id) minus p; */
+/*    behind it is the nearest vehicle of the lane behind, whose reach must  */
+/*    be <= p - L_head, or, on a lane with no vehicle behind, the feeder     */
+/*    front vehicles, whose reach beyond their lane end must be <= p - L.    */
 /* ------------------------------------------------------------------------ */
+/* reach of the front vehicles of lane m's feeders past their lane ends must
+ * stay <= rear (the entrant's rear bumper); *near collects |margin| */
+static int feeders_clear(const osim *s, int m, double rear, double *near)
+{
+    const oparams *P = &s->P;
+    double reach_extra = 0.5 * P->a_max * P->dt * P->dt;
+    int safe = 1;
+    for (int e = s->feed_begin[m]; e < s->feed_begin[m + 1]; ++e) {
+        int fl = s->feed_jl[e];
+        int h = lane_front(s, fl);
+        if (h < 0) continue;
+        double mg = rear - (s->x[h] + s->v[h] * P->dt + reach_extra - s->lane_len[fl]);
+        if (fabs(mg) < *near) *near = fabs(mg);
+        if (!(mg >= 0.0)) safe = 0;
+    }
+    return safe;
+}
+
 static void departures(osim *s)
 {
     const oparams *P = &s->P;
@@ -663,6 +695,7 @@ static void departures(osim *s)
             int i = s->q_veh[c];
             if (s->status[i] != WAITING) continue;
             if (!(s->tau[i] <= now)) break;
+            double p = s->start_s[i] > 0.0 ? s->start_s[i] : 0.0;
             int best = -1;
             double best_room = -INFINITY;
             double near = INFINITY;
@@ -671,19 +704,32 @@ static void departures(osim *s)
                 if (s->restricted[m]) continue;
                 s->k[i] = 0;
                 if (!in_group(s, i, m)) continue;
-                int safe = 1;
-                for (int e = s->feed_begin[m]; e < s->feed_begin[m + 1]; ++e) {
-                    int fl = s->feed_jl[e];
-                    int h = lane_front(s, fl);
-                    if (h < 0) continue;
-                    double mg = -s->L[i] - (s->x[h] + s->v[h] * P->dt + reach_extra - s->lane_len[fl]);
-                    if (fabs(mg) < near) near = fabs(mg);
-                    if (!(mg >= 0.0)) safe = 0;
+                double room;
+                int safe;
+                if (p == 0.0) {
+                    safe = feeders_clear(s, m, -s->L[i], &near);
+                    int z = lane_rear(s, m);
+                    room = z < 0 ? INFINITY : s->x[z] - s->L[z];
+                } else {
+                    /* the lane's vehicles front first: the leader is the last
+                     * one ahead of the entrant, the follower the first behind */
+                    int lead = -1, fol = -1;
+                    for (int q = 0; q < s->lane_cnt[m]; ++q) {
+                        int z = LANE(s, m)[q];
+                        if (s->x[z] > p || (s->x[z] == p && z < i)) lead = z;
+                        else { fol = z; break; }
+                    }
+                    room = lead < 0 ? INFINITY : s->x[lead] - s->L[lead] - p;
+                    if (fol >= 0) {
+                        double mg = (p - s->L[i]) - (s->x[fol] + s->v[fol] * P->dt + reach_extra);
+                        if (fabs(mg) < near) near = fabs(mg);
+                        safe = mg >= 0.0;
+                    } else {
+                        safe = feeders_clear(s, m, p - s->L[i], &near);
+                    }
                 }
                 if (!safe) continue;
-                int z = lane_rear(s, m);
-                double room = z < 0 ? INFINITY : s->x[z] - s->L[z];
-                if (z >= 0 && fabs(room - P->s0) < near) near = fabs(room - P->s0);
+                if (room < INFINITY && fabs(room - P->s0) < near) near = fabs(room - P->s0);
                 if (room > best_room) { best_room = room; best = m; }
             }
             s->margin[(size_t)i * NMARGIN + 5] = near;
@@ -692,7 +738,7 @@ static void departures(osim *s)
             s->status[i] = ACTIVE;
             s->lane[i] = best;
             s->k[i] = 0;
-            s->x[i] = 0.0;
+            s->x[i] = p;
             s->v[i] = 0.0;
             s->event[i] |= EV_DEPART;
             s->n_departures += 1;
@@ -1137,6 +1183,13 @@ void osim_get_route(const osim *s, int i, int *start_pos, int *len, int *out, in
 void osim_set_lane_max_speed(osim *s, int n, const int *lanes, const double *speed)
 {
     for (int c = 0; c < n; ++c) s->lane_lim[lanes[c]] = speed[c];
+}
+
+/* trip start positions (metres along the origin road; <= 0 for its start)
+ * of vehicles vids[c], e.g. an AOI's connection on that road */
+void osim_set_trip_starts(osim *s, int n, const int *vids, const double *start_s)
+{
+    for (int c = 0; c < n; ++c) s->start_s[vids[c]] = start_s[c];
 }
 
 /* trip end positions (metres along the last road of the route; < 0 for

@@ -118,6 +118,7 @@ class Trips:
     v0_factor: np.ndarray     # float32 [N]  desired speed = v0_factor * lane limit
     length: np.ndarray        # float32 [N]
     end_s: np.ndarray = None  # float32 [N]  trip end position on the last road (None: its end)
+    start_s: np.ndarray = None  # float32 [N]  trip start position on the origin road (None: its start)
 
     @property
     def n_vehicles(self):
