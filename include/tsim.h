@@ -105,6 +105,12 @@ typedef struct tsim_trips {
                                       * from the road's start (the trip ends in the step the vehicle's front
                                       * passes it; Section 3.2 set_vehicle_route end position, an AOI's
                                       * connection (Appendix B.1) as the trip's end); negative or NULL: the road's end */
+    const float *start_s;            /* [n] or NULL: where the trip starts on its origin road, metres from the road's
+                                      * start, below the road's length (an AOI's connection partway along the road,
+                                      * Appendix B.1/B.2: the vehicle enters with its front there, at rest, into the
+                                      * lane of its lane group with the most room ahead, once the nearest vehicle
+                                      * ahead leaves s0 and nothing behind can reach its rear within the step);
+                                      * 0, negative or NULL: the road's start */
 } tsim_trips;
 
 /* Model parameters (Appendix B.3; the MOBIL threshold, safe deceleration,

@@ -59,6 +59,7 @@ struct Build {
     std::vector<double> junc_cycle;
     std::vector<float> tau, vf, vlen;
     std::vector<float> vend;         // per vehicle: trip end position on the last road, < 0: its end
+    std::vector<float> vstart;       // per vehicle: trip start position on the origin road, <= 0: its start
     std::vector<int32_t> route_begin, route, q_begin, q_veh;   // route_begin: CSR of the routes given at creation
     std::vector<int32_t> rstart, rlen;   // the route in force of each vehicle: route[rstart, rstart + rlen)
     std::vector<uint32_t> q_mask;    // per queue entry: origin-road lanes that lead to its next road
@@ -312,6 +313,8 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
             return fail(err, TSIM_EINVAL, "vehicle length/factor/departure");
         if (tr->end_s && !(tr->end_s[i] < 0.0f) && !(tr->end_s[i] > 0.0f && tr->end_s[i] <= net->road_length[tr->route_roads[e - 1]]))
             return fail(err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": end position beyond its last road");
+        if (tr->start_s && !(tr->start_s[i] < net->road_length[tr->route_roads[b]]))
+            return fail(err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": start position not before its origin road's end");
         Lmin = std::min(Lmin, tr->length[i]);
         fmax_ = std::max(fmax_, tr->v0_factor[i]);
     }
@@ -468,6 +471,9 @@ int build_tables(const tsim_network* net, const tsim_trips* tr, const tsim_param
     B.vlen.assign(tr->length, tr->length + N);
     if (tr->end_s) B.vend.assign(tr->end_s, tr->end_s + N);
     else B.vend.assign(N, -1.0f);
+    B.vstart.assign(N, 0.0f);
+    if (tr->start_s)
+        for (int i = 0; i < N; ++i) B.vstart[i] = tr->start_s[i] > 0.0f ? tr->start_s[i] : 0.0f;
     B.route_begin.assign(tr->route_begin, tr->route_begin + N + 1);
     B.route.assign(tr->route_roads, tr->route_roads + tr->route_begin[N]);
     B.rstart.assign(B.route_begin.begin(), B.route_begin.begin() + N);
@@ -520,7 +526,7 @@ void single_instance(Build& B, const tsim_params* prm)
 struct Union {
     std::vector<int32_t> road_from, road_to, road_lane_begin, jl_in, jl_out, junc_phase_begin, phase_green_begin,
         phase_green_jl, junc_policy, route_begin, route_roads;
-    std::vector<float> road_length, road_limit, jl_length, jl_limit, phase_duration, depart, v0f, vlen, vend;
+    std::vector<float> road_length, road_limit, jl_length, jl_limit, phase_duration, depart, v0f, vlen, vend, vstart;
     tsim_network net{};
     tsim_trips trips{};
     std::vector<int> road_off, junc_off, rl_off, jl_off, veh_off;
@@ -586,6 +592,7 @@ int make_union(const tsim_network* nets, const tsim_trips* trips, const tsim_par
             U.v0f.push_back(T.v0_factor[i]);
             U.vlen.push_back(T.length[i]);
             U.vend.push_back(T.end_s ? T.end_s[i] : -1.0f);
+            U.vstart.push_back(T.start_s ? T.start_s[i] : 0.0f);
         }
         for (int e = 0; e < T.route_begin[T.n_vehicles]; ++e) U.route_roads.push_back(T.route_roads[e] + ro);
         U.road_off.push_back(ro + N.n_roads);
@@ -620,6 +627,7 @@ int make_union(const tsim_network* nets, const tsim_trips* trips, const tsim_par
     T.v0_factor = U.v0f.data();
     T.length = U.vlen.data();
     T.end_s = U.vend.data();
+    T.start_s = U.vstart.data();
     return TSIM_OK;
 }
 
@@ -742,6 +750,7 @@ std::vector<Region> regions(tsim_handle* h, bool assign)
     add(&D.vf, std::max<size_t>(N, 1) * 4);
     add(&D.vlen, std::max<size_t>(N, 1) * 4);
     add(&D.vend, std::max<size_t>(N, 1) * 4);
+    add(&D.vstart, std::max<size_t>(N, 1) * 4);
     add(&D.status, std::max<size_t>(N, 1) * 4);
     add(&D.finish_step, std::max<size_t>(N, 1) * 4);
     add(&D.q_begin, (R + 1) * 4);
@@ -1248,6 +1257,7 @@ int upload_tables(tsim_handle* h, const Span& sp)
     e = e ? e : chk(up_range(h, (float*)D.vf, B.vf, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (float*)D.vlen, B.vlen, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (float*)D.vend, B.vend, sp.v0, sp.v1), "trips");
+    e = e ? e : chk(up_range(h, (float*)D.vstart, B.vstart, sp.v0, sp.v1), "trips");
     e = e ? e : chk(up_range(h, (int32_t*)D.q_begin, B.q_begin, sp.r0, sp.r1 + 1), "queues");
     {
         // queue entries of the span's roads are those of its vehicles
@@ -2732,6 +2742,7 @@ bool append_build(tsim_handle* h, const Build& M, uint64_t seed, Span& sp)
         B.vf.push_back(M.vf[i]);
         B.vlen.push_back(M.vlen[i]);
         B.vend.push_back(M.vend[i]);
+        B.vstart.push_back(M.vstart[i]);
         B.route_begin.push_back(M.route_begin[i + 1] + (int)E0);
         B.rstart.push_back(M.rstart[i] + (int)E0);
         B.rlen.push_back(M.rlen[i]);
@@ -2804,6 +2815,7 @@ void pop_build(tsim_handle* h)
     B.vf.resize(v0);
     B.vlen.resize(v0);
     B.vend.resize(v0);
+    B.vstart.resize(v0);
     B.route_begin.resize(v0 + 1);
     B.route.resize(e0);
     B.rstart.resize(v0);

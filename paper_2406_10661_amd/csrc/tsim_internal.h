@@ -266,6 +266,7 @@ struct DevNet {
     const float* vf;
     const float* vlen;
     const float* vend;               // [N] trip end position on the last road, < 0: its end
+    const float* vstart;             // [N] trip start position on the origin road, 0: its start
     int32_t* status;
     int32_t* finish_step;
     const int32_t* q_begin;          // [R+1] departure queue of each origin road

@@ -300,6 +300,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         if (!((double)qr.tau <= now)) break;
         const int v = qr.vid;
         const int st_v = D.status[v];
+        const float pstart = D.vstart[v];
         QRec qn{};
         if (head + 1 < qe) qn = D.q_rec[head + 1];
         const float Lv = qr.len;
@@ -334,6 +335,52 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
             qr = qn;
             continue;
         }
+        // a start partway along the road (an AOI's connection): the entry
+        // point's place in each lane's order by binary search over the
+        // lane's records (front first); room ahead to the nearest vehicle
+        // ahead; the nearest vehicle behind, or on a lane without one its
+        // feeders, must not reach the entrant's rear within the step
+        int b_k = b_cnt;
+        float b_rear = 0.0f, b_rear_v = 0.0f;
+        if (pstart > 0.0f) {
+            best = -1;
+            best_room = -TS_INF;
+            for (int li = 0; li < nrl; ++li) {
+                if (!((lanes_ok >> li) & 1u)) continue;
+                const int m = lb + li;
+                const LaneSum s = sum[m];
+                const uint32_t base = D.lane_base[m];
+                const VehRec* rl = slab + base;
+                int lo = 0, hi = s.cnt;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const float zx = rl[mid].x;
+                    if (zx > pstart || (zx == pstart && rl[mid].vid < v)) lo = mid + 1;
+                    else hi = mid;
+                }
+                const float room = lo > 0 ? (rl[lo - 1].x - rl[lo - 1].len) - pstart : TS_INF;
+                bool safe;
+                if (lo < s.cnt) {
+                    const VehRec f = rl[lo];
+                    safe = f.x + f.v * P.dt + P.reach <= pstart - Lv;
+                } else {
+                    const int fm = fmax_of(s.fmax, tg);
+                    safe = !(fm != kNoFeeder && !((pstart - Lv) - o2f(fm) >= 0.0f));
+                }
+                if (safe && room > best_room) {
+                    best_room = room;
+                    best = li;
+                    b_k = lo;
+                    b_cnt = s.cnt;
+                    b_cap = D.lane_cap[m];
+                    b_base = base;
+                    b_len = D.lane_len[m];
+                    b_fr = s.front_reach;
+                    b_rear = s.rear;
+                    b_rear_v = s.rear_v;
+                }
+            }
+        }
         if (best < 0 || !(best_room >= P.s0)) break;
         const int m = lb + best;
         if (b_cnt >= b_cap) {
@@ -341,7 +388,7 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
             break;
         }
         VehRec nrec;
-        nrec.x = 0.0f;
+        nrec.x = pstart > 0.0f ? pstart : 0.0f;
         nrec.v = 0.0f;
         nrec.vid = v;
         nrec.len = Lv;
@@ -349,12 +396,21 @@ __device__ __forceinline__ void prepare_one(const DevNet& D, long long tg, int i
         nrec.rp = qr.rp;
         nrec.rem = qr.rem;
         nrec.nr = qr.nr;
-        slab[b_base + b_cnt] = nrec;
         LaneSum s;
         s.cnt = b_cnt + 1;
-        s.rear = 0.0f - Lv;
-        s.rear_v = 0.0f;
-        s.front_reach = b_cnt == 0 ? front_reach(0.0f, 0.0f, b_len, P) : b_fr;
+        if (pstart > 0.0f) {
+            VehRec* rl = slab + b_base;
+            for (int q = b_cnt; q > b_k; --q) rl[q] = rl[q - 1];
+            rl[b_k] = nrec;
+            s.rear = b_k == b_cnt ? pstart - Lv : b_rear;
+            s.rear_v = b_k == b_cnt ? 0.0f : b_rear_v;
+            s.front_reach = b_k == 0 ? front_reach(pstart, 0.0f, b_len, P) : b_fr;
+        } else {
+            slab[b_base + b_cnt] = nrec;
+            s.rear = 0.0f - Lv;
+            s.rear_v = 0.0f;
+            s.front_reach = b_cnt == 0 ? front_reach(0.0f, 0.0f, b_len, P) : b_fr;
+        }
         put_dyn(sum[m], s);
         D.status[v] = 1;
         used |= 1u << best;

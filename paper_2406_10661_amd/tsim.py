@@ -39,7 +39,7 @@ class tsim_network(C.Structure):
 class tsim_trips(C.Structure):
     _fields_ = [("n_vehicles", C.c_int32), ("depart_time", C.c_void_p), ("route_begin", C.c_void_p),
                 ("route_roads", C.c_void_p), ("v0_factor", C.c_void_p), ("length", C.c_void_p),
-                ("end_s", C.c_void_p)]
+                ("end_s", C.c_void_p), ("start_s", C.c_void_p)]
 
 
 class tsim_params(C.Structure):
@@ -199,13 +199,16 @@ class _Inputs:
         end_s = getattr(trips, "end_s", None)
         if end_s is not None:
             a["end_s"] = f32(end_s)
+        start_s = getattr(trips, "start_s", None)
+        if start_s is not None:
+            a["start_s"] = f32(start_s)
         self.net = tsim_network(net.n_junctions, net.n_roads, *[_p(a[k]) for k in (
             "road_from", "road_to", "road_lane_begin", "road_length", "road_limit")], net.n_jlanes,
             *[_p(a[k]) for k in ("jl_in_lane", "jl_out_lane", "jl_length", "jl_limit", "junc_phase_begin",
                                  "phase_duration", "phase_green_begin", "phase_green_jl", "junc_policy")])
         self.trips = tsim_trips(trips.n_vehicles, *[_p(a[k]) for k in (
             "depart_time", "route_begin", "route_roads", "v0_factor", "length")],
-            _p(a["end_s"]) if "end_s" in a else None)
+            _p(a["end_s"]) if "end_s" in a else None, _p(a["start_s"]) if "start_s" in a else None)
         self.params = None if params is None else _Inputs.params_of(params)
 
     @staticmethod

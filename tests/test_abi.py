@@ -159,3 +159,18 @@ def test_route_footprint_and_rejections_without_gpu(L):
     assert call([0, 1], [2, 3], time=bad) == T.TSIM_EINVAL
     assert call([0, 1], [2, 3]) == T.TSIM_ENOMEM   # no work space
     assert call([0], [0], n=0) == T.TSIM_OK and begin[0] == 0
+
+
+def test_start_position_validated_without_gpu(L):
+    """A trip start position at or beyond its origin road's end is refused
+    by tsim_footprint; one partway along is accepted."""
+    w = W.config1()
+    org = w.trips.route_roads[w.trips.route_begin[:-1]]
+    ok = (0.5 * w.network.road_length[org]).astype(np.float32)
+    w.trips.start_s = ok
+    assert T.footprint(w.network, w.trips, w.params) > 0
+    bad = ok.copy()
+    bad[3] = w.network.road_length[org[3]]
+    w.trips.start_s = bad
+    with pytest.raises(T.TsimError):
+        T.footprint(w.network, w.trips, w.params)
