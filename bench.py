@@ -797,7 +797,8 @@ def run_city(args):
         "window": {"vehicle_steps": vsteps, "nonempty_lane_steps": d["lane_steps"],
                    "road_entries": d["road_entries"], "finished": d["n_finished"], "departures": d["departures"],
                    "lane_changes": d["lane_changes"], "transfers": d["transfers"],
-                   "mean_road_speed": m1["mean_speed_avg"], "errors": m1["errors"]},
+                   "mean_road_speed": m1["mean_speed_avg"], "errors": m1["errors"],
+                   "max_stalled_steps": m1["max_stalled_steps"]},
         "roofline": rl,
         "eager_us_per_step": {"update": upd_ms / max(upd_n, 1) * 1e3, "prepare": prep_ms / max(prep_n, 1) * 1e3},
         "paper_context": {"hz": 84.09, "vehicles": 2464950, "hardware": "RTX 4090 + Xeon Platinum 8462Y",

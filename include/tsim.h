@@ -151,6 +151,11 @@ typedef struct tsim_metrics {
     int64_t errors;           /* device-detected capacity/ordering violations */
     int64_t lane_steps;       /* sum over steps of lanes holding a vehicle at the step start */
     int64_t road_entries;     /* junction-lane-to-road crossings (the vehicle moves to its next road) */
+    int64_t stalled_steps;    /* gridlock detector: the current run of steps with vehicles on the network in
+                               * which none on a road lane ended the step moving and none departed, crossed a
+                               * lane end or finished (counted as the steps are folded; a departure is seen
+                               * by the fold after its step at the latest) */
+    int64_t max_stalled_steps;/* the longest such run since create / set_state */
 } tsim_metrics;
 
 /* Vehicle state for checkpoint/resume and tests (host arrays of n_vehicles,

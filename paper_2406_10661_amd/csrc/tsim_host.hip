@@ -2433,6 +2433,8 @@ static int metrics_impl(tsim_handle* h, int inst, tsim_metrics* out)
     out->errors = M.errors;
     out->lane_steps = M.lane_steps;
     out->road_entries = M.road_entries;
+    out->stalled_steps = M.stall_steps;
+    out->max_stalled_steps = M.max_stall;
     return M.errors ? TSIM_ESTATE : TSIM_OK;
 }
 

@@ -202,6 +202,9 @@ struct DevMetrics {
     long long dep_events;    // departures since create / set_state
     long long lane_steps;    // sum over steps of lanes holding vehicles at the step start
     long long road_entries;  // junction-to-road crossings (each reads one route word)
+    long long stall_steps;   // gridlock detector: current run of steps in which nothing moved
+    long long max_stall;     // its longest run
+    long long stall_dep;     // departures counted at the last fold
     double speed_acc;
     double mean_speed_last;
 };

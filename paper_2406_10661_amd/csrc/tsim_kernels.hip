@@ -1754,9 +1754,21 @@ __device__ __forceinline__ void finish_step(const DevNet& D, const WGPartial& ac
 // atomics here.
 // the metrics of a single-instance step from its summed partials (thread of
 // the caller; fs: the step they belong to)
+// gridlock detector: a step with vehicles on the network in which none on a
+// road lane ends it moving and none departs, crosses a lane end or finishes
+// extends the run of stalled steps; any movement ends it
+__device__ __forceinline__ void note_stall(DevMetrics* M, const long long* a)
+{
+    const bool moved = a[0] > 0 || a[4] > 0 || a[7] > 0 || M->dep_events != M->stall_dep;
+    M->stall_dep = M->dep_events;
+    M->stall_steps = (a[2] > 0 && !moved) ? M->stall_steps + 1 : 0;
+    if (M->stall_steps > M->max_stall) M->max_stall = M->stall_steps;
+}
+
 __device__ __forceinline__ void apply_sums(const DevNet& D, const long long* a, long long fs)
 {
     DevMetrics* M = D.met;
+    note_stall(M, a);
     M->vehicle_steps += a[2];
     M->lane_changes += a[3];
     M->transfers += a[4];
@@ -1855,6 +1867,7 @@ __device__ void fold_step(const DevNet& D, int total_wg)
                 q[k] = 0;
             }
             DevMetrics* M = &D.met[i];
+            note_stall(M, a);
             M->vehicle_steps += a[2];
             M->lane_changes += a[3];
             M->transfers += a[4];

@@ -53,7 +53,8 @@ class tsim_metrics(C.Structure):
                 ("mean_speed_avg", C.c_double), ("vehicle_steps", C.c_int64), ("lane_changes", C.c_int64),
                 ("transfers", C.c_int64), ("clamps", C.c_int64), ("feeder_blocks", C.c_int64),
                 ("departures", C.c_int64), ("speed_steps", C.c_int64), ("errors", C.c_int64),
-                ("lane_steps", C.c_int64), ("road_entries", C.c_int64)]
+                ("lane_steps", C.c_int64), ("road_entries", C.c_int64), ("stalled_steps", C.c_int64),
+                ("max_stalled_steps", C.c_int64)]
 
 
 class tsim_state_host(C.Structure):
