@@ -64,7 +64,7 @@ struct __align__(16) VehRec {
     float f;      // desired-speed factor (v0 = f * lane limit)
     int32_t rp;   // index into the route array of the current road
     int32_t rem;  // roads of the route after the current one
-    int32_t nr;   // next road of the route, -1 on the last road
+    int32_t nr;   // next road of the route; on the last road (rem == 0) the trip end position's word (end_word)
 };
 
 // one departure queue entry with everything the prepare kernel needs to
@@ -78,7 +78,7 @@ struct __align__(16) QRec {
     float f;         // desired-speed factor
     int32_t rp;      // route position of the origin road
     int32_t rem;     // roads after the origin road
-    int32_t nr;      // next road, -1 if none
+    int32_t nr;      // next road; on a one-road route the trip end position's word (end_word)
 };
 
 // per-lane summary of one step's state, read by other tiles (lookahead,
