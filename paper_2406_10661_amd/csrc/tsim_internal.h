@@ -50,7 +50,8 @@ constexpr int kCntStride = 32;           // work-list counters one 128-byte line
 constexpr int kNumLists = 6;             // small, wide, huge, tiny, medium, large
 constexpr int kFoldWGs = 16;             // prepare workgroups that sum slices of the previous step's partials
 constexpr int kMedCap = 64;              // medium tiles (fused schedule): at most kWideLanes lanes and 64 vehicles
-constexpr int kLargeCap = 256;           // large tiles (fused schedule): above the wide list, at most 256 vehicles
+constexpr int kLargeCap = 176;           // large tiles (fused schedule): above the wide list, at most 176 vehicles
+                                         // (two images fit the fused launch's LDS; larger tiles go to the huge list)
 constexpr int kLargeLanes = 48;          // and at most 48 lanes
 constexpr float kSpeedFx = 1048576.0f;   // fixed-point scale of speed sums (2^20)
 constexpr double kTimeFx = 65536.0;      // fixed-point scale of travel times (2^16)
