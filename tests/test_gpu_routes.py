@@ -274,3 +274,24 @@ def test_batch_reroute_matches_alone(T):
         a, e = b.get_state(k), g.get_state()
         for f in ("status", "lane", "route_pos", "x", "v"):
             assert np.array_equal(a[f], e[f]), (k, f)
+
+
+def test_reroute_rejects_bad_calls(T):
+    """A vehicle listed twice, a vehicle id out of range, an instance out of
+    range and a negative price are refused (TSIM_EINVAL) and change
+    nothing."""
+    w = W.config1()
+    g = T.Sim(w.network, w.trips, w.params)
+    g.step(50)
+    before = g.get_state()
+    R = w.network.n_roads
+    for vids, price in (([3, 3], None), ([w.trips.n_vehicles], None), ([1], -np.ones(R, np.float32))):
+        with pytest.raises(T.TsimError) as e:
+            g.reroute_shortest(np.asarray(vids, np.int32), price)
+        assert e.value.code == T.TSIM_EINVAL
+    after = g.get_state()
+    for f in ("status", "lane", "route_pos", "x", "v"):
+        assert np.array_equal(before[f], after[f]), f
+    b = T.Batch([w.network], [w.trips], [w.params])
+    with pytest.raises(T.TsimError):
+        b.reroute_shortest(1, np.array([0], np.int32))
