@@ -285,10 +285,11 @@ def shortest_routes(net, origins, dests, price=None, road_time=None, device="cud
     cap = max(48 * n, 1)
     while True:
         roads = np.empty(cap, np.int32)
-        rc = lib().tsim_shortest_routes(C.byref(ins.net), None if pr is None else _p(pr),
-                                        None if rt is None else _p(rt), _p(o), _p(d), n,
-                                        C.c_void_p(st.cuda_stream), C.c_void_p(ws.data_ptr()),
-                                        C.c_size_t(ws.numel()), _p(begin), _p(roads), cap, _p(bad))
+        with torch.cuda.device(dev):   # the kernels run on the current GPU
+            rc = lib().tsim_shortest_routes(C.byref(ins.net), None if pr is None else _p(pr),
+                                            None if rt is None else _p(rt), _p(o), _p(d), n,
+                                            C.c_void_p(st.cuda_stream), C.c_void_p(ws.data_ptr()),
+                                            C.c_size_t(ws.numel()), _p(begin), _p(roads), cap, _p(bad))
         if rc == TSIM_ENOMEM and int(begin[n]) > cap:
             cap = int(begin[n])
             continue
