@@ -1286,6 +1286,10 @@ __device__ void process_pass12(const DevNet& D, TS& S, V& view, const StepBufs& 
             view.set_mobil(j, m.dec, m.ta, lead_rear(m.lead), m.lead.v, m.lead.ex);
         }
     }
+    // a tile spread over several wavefronts: the merger buckets (moff, mrg)
+    // are complete only once every wavefront has left the loop above (one
+    // wavefront needs no fence: its LDS accesses complete in order)
+    if constexpr (GW > kWave) tile_sync<GW>();
     if constexpr (GW <= kWave) if (compact) {
         constexpr int NG = kWave / GW;
         wave_sync();

@@ -624,7 +624,30 @@ def _dense_big_tile_case(seed=0):
     return net, trips, params, st
 
 
-@pytest.mark.parametrize("case", ["c1", "grid3", "big"])
+def _merge_heavy_huge_case():
+    """1 km, 4-lane roads holding 217-280 vehicles each, placed on random
+    lanes so that many must merge towards their route's lanes: every road
+    tile is worked on by a whole workgroup of several wavefronts (the huge
+    pass of every schedule), where the merger buckets one wavefront fills
+    are read by the others."""
+    rng = np.random.default_rng(7)
+    net = W.grid_network(3, spacing=1000.0, length=1000.0, lanes=4)
+    o, d = W.uniform_od(net, rng, 12000)
+    trips = W._finish_trips(net, rng, o, d, rng.uniform(0, 50, 12000))
+    st = synthetic_state(net, trips, 60, seed=7, p_active=0.95, min_gap=0.2)
+    return net, trips, W.Params(seed=7), st
+
+
+def test_merge_heavy_huge_tiles_one_step(O, Sim):
+    net, trips, params, st = _merge_heavy_huge_case()
+    lanes = st["lane"][st["status"] == 1]
+    per_road = np.bincount(net.road_of_lane()[lanes[lanes < net.n_road_lanes]], minlength=net.n_roads)
+    assert per_road.min() > 176 and per_road.max() <= 448
+    rep = compare_one_step(O, Sim, net, trips, params, st)
+    _log("merge_heavy_huge", rep)
+
+
+@pytest.mark.parametrize("case", ["c1", "grid3", "big", "merge"])
 def test_schedules_bit_identical(Sim, case):
     """Every update schedule (tiles per wavefront, LDS capacity, overflow to
     the wide pass) gives the same trajectory bit for bit."""
@@ -639,8 +662,11 @@ def test_schedules_bit_identical(Sim, case):
         trips = W._finish_trips(net, rng, o, d, rng.uniform(0, 100, 1500))
         params = W.Params(seed=5)
         st = synthetic_state(net, trips, 60, seed=55, p_active=0.6)
-    else:
+    elif case == "big":
         net, trips, params, st = _dense_big_tile_case(1)
+    else:
+        net, trips, params, st = _merge_heavy_huge_case()
+    steps = 120 if case == "merge" else 40
     from paper_2406_10661_amd.tsim import SCHEDULES
     ref = None
     for sc in sorted(SCHEDULES):
@@ -648,7 +674,7 @@ def test_schedules_bit_identical(Sim, case):
         g.set_schedule(sc)
         assert g.schedule() == sc
         g.set_state(st)
-        g.step(40)
+        g.step(steps)
         s, m = g.get_state(), g.metrics()
         assert m["errors"] == 0
         if ref is None:
