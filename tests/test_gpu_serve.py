@@ -129,3 +129,41 @@ def test_served_jobs_routed_on_the_gpu():
         sim.close()
         for key in KEYS:
             assert m[key] == j.metrics[key], (j.jid, key)
+
+
+def test_served_job_whole_horizon_schedules_and_batch_identical():
+    """One served job (57k vehicles, routed on the GPU, roads of up to ~190
+    vehicles) over its whole horizon: every update schedule, and the job as
+    the only instance of a batch, give the same trajectory bit for bit.
+    Long horizons are where a rare ordering difference between the passes
+    of a schedule would show."""
+    from paper_2406_10661_amd import serve as SV
+    from paper_2406_10661_amd.tsim import SCHEDULES, Batch, Sim
+    ws = [W.config5_job(3, max_vehicles=100000, route=False)]
+    SV.route_jobs_on_device(ws)
+    w = ws[0]
+    ref = None
+    for sc in sorted(SCHEDULES):
+        g = Sim(w.network, w.trips, w.params)
+        g.set_schedule(sc)
+        g.step(w.n_steps)
+        s, m = g.get_state(), g.metrics()
+        g.close()
+        assert m["errors"] == 0
+        if ref is None:
+            ref = (s, m)
+            continue
+        for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+            assert np.array_equal(s[key], ref[0][key]), (sc, key)
+        for key in KEYS:
+            assert m[key] == ref[1][key], (sc, key, m[key], ref[1][key])
+    b = Batch([w.network], [w.trips], [w.params])
+    b.step(w.n_steps)
+    s, m = b.get_state(0), b.metrics(0)
+    b.close()
+    for key in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+        assert np.array_equal(s[key], ref[0][key]), ("batch", key)
+    for key in KEYS:
+        assert m[key] == ref[1][key], ("batch", key, m[key], ref[1][key])
+    print("served job 3:", w.trips.n_vehicles, "vehicles,", w.n_steps, "steps, finished", ref[1]["n_finished"],
+          flush=True)
