@@ -358,6 +358,39 @@ int tsim_set_trajectory(tsim_handle *h, void *device_buffer, int64_t capacity, i
  * Synchronises the stream. */
 int tsim_get_trajectory_count(tsim_handle *h, int64_t *n);
 
+/* Areas of interest (Appendix B.1: an area with several connections to the
+ * road network where trips start and end; Appendix B.2: an AOI puts a
+ * vehicle whose departure time has come into a lane at its connection when
+ * that is safe, and takes in the vehicles whose trips end there).
+ *
+ * tsim_aoi_footprint: device bytes tsim_set_aois needs for n_aoi AOIs.
+ *
+ * tsim_set_aois: n_aoi AOIs; AOI a's connections are entries
+ * conn_begin[a] .. conn_begin[a+1]-1 (conn_begin[0] = 0, non-decreasing) of
+ * conn_road (road ids) and conn_s (metres from the road's start, within its
+ * length).  origin_aoi / dest_aoi ([n_vehicles] or NULL; -1 = none) name each
+ * vehicle's AOIs: a vehicle with an origin AOI starts at that AOI's first
+ * listed connection on the first road of its route (which must lie below the
+ * road's length), one with a destination AOI ends at the connection on its
+ * last road (which must lie beyond the road's start) — the start and end
+ * positions of tsim_trips, replacing those given there.  Every vehicle named
+ * must still be waiting.  Host arrays, copied; device_buffer (caller-owned,
+ * 256-byte aligned, at least tsim_aoi_footprint bytes, alive until the next
+ * tsim_set_aois or tsim_destroy) holds the AOI ids on the device.  Errors
+ * (TSIM_EINVAL: an AOI id, road or position out of range, an AOI without a
+ * connection on the road a vehicle needs, a vehicle that has departed)
+ * change nothing.  Synchronises the stream.  Single-instance handles.
+ *
+ * tsim_get_aoi_counts: at the current step boundary, waiting[a] = vehicles
+ * whose trip starts in AOI a and that have not departed, arrived[a] =
+ * vehicles whose trip ended in AOI a (host arrays of n_aoi, the count given
+ * to tsim_set_aois; counted on the device).  Synchronises the stream. */
+int tsim_aoi_footprint(tsim_handle *h, int32_t n_aoi, size_t *bytes_out);
+int tsim_set_aois(tsim_handle *h, int32_t n_aoi, const int32_t *conn_begin, const int32_t *conn_road,
+                  const float *conn_s, const int32_t *origin_aoi, const int32_t *dest_aoi, void *device_buffer,
+                  size_t buffer_bytes);
+int tsim_get_aoi_counts(tsim_handle *h, int32_t *waiting, int32_t *arrived, int32_t n_aoi);
+
 /* Launch mode.  chunk > 0: tsim_step captures `chunk` steps (both kernels of
  * each) into one HIP graph on its first call and replays that graph for every
  * whole chunk of a call; the remaining steps are launched one by one.  chunk

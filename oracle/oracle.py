@@ -203,6 +203,69 @@ class OracleSim:
         e = -1.0 if end_s is None else float(np.float32(end_s))
         lib().osim_set_vehicle_route(self.h, int(vid), _p(r), int(r.size), e)
 
+    def set_aois(self, conn_begin, conn_road, conn_s, origin_aoi=None, dest_aoi=None):
+        """Areas of interest (Appendix B.1: an area joined to the road network
+        by connections at positions along roads, where trips start and end).
+        Reading: a vehicle whose trip starts in AOI a enters at a's first
+        listed connection on the first road of its route; one whose trip ends
+        in AOI b ends at b's first listed connection on the last road of its
+        route.  Only vehicles still waiting may be given AOIs.  Returns the
+        (start, end) positions given to the vehicles (nan: unchanged).
+        Plain loops over the vehicles: small cases only."""
+        n_aoi = len(conn_begin) - 1
+        conn = [[(int(conn_road[c]), float(np.float32(conn_s[c]))) for c in range(conn_begin[a], conn_begin[a + 1])]
+                for a in range(n_aoi)]
+
+        def place(a, road):
+            for r, x in conn[a]:
+                if r == road:
+                    return x
+            raise ValueError(f"AOI {a} has no connection on road {road}")
+
+        st = self.get_state()["status"]
+        starts = np.full(self.N, np.nan)
+        ends = np.full(self.N, np.nan)
+        self.aoi_origin = np.full(self.N, -1, np.int64)
+        self.aoi_dest = np.full(self.N, -1, np.int64)
+        for v in range(self.N):
+            o = -1 if origin_aoi is None else int(origin_aoi[v])
+            d = -1 if dest_aoi is None else int(dest_aoi[v])
+            if o < 0 and d < 0:
+                continue
+            if st[v] != WAITING:
+                raise ValueError(f"vehicle {v} has departed")
+            _, roads = self.route(v)
+            if o >= 0:
+                starts[v] = place(o, int(roads[0]))
+                self.aoi_origin[v] = o
+            if d >= 0:
+                ends[v] = place(d, int(roads[-1]))
+                self.aoi_dest[v] = d
+        L = lib()
+        ids = np.nonzero(~np.isnan(starts))[0].astype(np.int32)
+        if ids.size:
+            b = np.ascontiguousarray(starts[ids], np.float64)
+            L.osim_set_trip_starts(self.h, int(ids.size), _p(ids), _p(b))
+        ids = np.nonzero(~np.isnan(ends))[0].astype(np.int32)
+        if ids.size:
+            e = np.ascontiguousarray(ends[ids], np.float64)
+            L.osim_set_trip_ends(self.h, int(ids.size), _p(ids), _p(e))
+        self.n_aoi = n_aoi
+        return starts, ends
+
+    def aoi_counts(self):
+        """(waiting, arrived) per AOI: vehicles of each origin AOI not yet
+        departed, vehicles whose trip ended in each destination AOI."""
+        st = self.get_state()["status"]
+        w = np.zeros(self.n_aoi, np.int64)
+        a = np.zeros(self.n_aoi, np.int64)
+        for v in range(self.N):
+            if st[v] == WAITING and self.aoi_origin[v] >= 0:
+                w[self.aoi_origin[v]] += 1
+            if st[v] == FINISHED and self.aoi_dest[v] >= 0:
+                a[self.aoi_dest[v]] += 1
+        return w, a
+
     def route(self, vid, max_len=100000):
         """(route position, roads of the route in force) of vehicle vid."""
         k = np.zeros(1, np.int32)

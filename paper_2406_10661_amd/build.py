@@ -5,7 +5,7 @@ import shutil
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("tsim_kernels.hip", "tsim_host.hip", "tsim_routing.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("tsim_kernels.hip", "tsim_host.hip", "tsim_routing.hip", "tsim_aoi.hip")]
 LIB = os.path.join(HERE, "libtsim.so")
 
 

@@ -33,6 +33,8 @@ hipError_t launch_set_lane_speed(const DevNet& H, const int32_t* ids, const floa
 hipError_t launch_record(const DevNet& H, const int32_t* lane_ext, TrajRec* out, long long cap,
                          unsigned long long* count, int every, hipStream_t s);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
+hipError_t launch_aoi_counts(const DevNet& H, const int32_t* origin, const int32_t* dest, int n_aoi, int32_t* counts,
+                             hipStream_t s);
 hipError_t launch_apply_routes(const DevNet& H, const int32_t* n_rp, const int32_t* n_rem, const int32_t* n_nr,
                                const uint32_t* n_mask, int n_queue, hipStream_t s);
 int update_blocks_per_cu(int sched);
@@ -676,6 +678,10 @@ struct tsim_handle {
     int32_t* d_io_ph = nullptr;      // staging: phase updates (2 slots of 2 x NJ)
     int32_t* d_io_lane = nullptr;    // staging: lane updates (NL ids, then NL values)
     unsigned long long* d_traj_n = nullptr;   // trajectory records appended so far
+    // areas of interest (tsim_set_aois): per-vehicle origin and destination
+    // AOI ids, then the count slots, in the caller's buffer
+    int32_t* d_aoi = nullptr;
+    int n_aoi = 0;
     TrajRec* traj = nullptr;         // caller's trajectory buffer (device), traj_cap records
     long long traj_cap = 0;
     int traj_every = 0;              // 0: not recording
@@ -1652,6 +1658,138 @@ int tsim_get_trajectory_count(tsim_handle* h, int64_t* n)
     HIPCHK(h, hipMemcpyAsync(&c, h->d_traj_n, 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     *n = (int64_t)c;
+    return TSIM_OK;
+}
+
+// layout of the AOI buffer: origin ids [N], destination ids [N], counts
+// [2 n_aoi], each part 256-byte aligned
+static size_t aoi_bytes(long long n_veh, long long n_aoi)
+{
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    return 2 * up((size_t)std::max<long long>(n_veh, 1) * 4) + up((size_t)std::max<long long>(2 * n_aoi, 1) * 4);
+}
+
+int tsim_aoi_footprint(tsim_handle* h, int32_t n_aoi, size_t* bytes_out)
+{
+    if (!h || n_aoi < 0 || !bytes_out || h->B.n_inst != 1)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments (single-instance handles only)");
+    *bytes_out = aoi_bytes(h->D.N, n_aoi);
+    return TSIM_OK;
+}
+
+int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, const int32_t* conn_road,
+                  const float* conn_s, const int32_t* origin_aoi, const int32_t* dest_aoi, void* device_buffer,
+                  size_t buffer_bytes)
+{
+    if (!h || n_aoi < 0 || (n_aoi > 0 && !conn_begin) || !device_buffer || h->B.n_inst != 1)
+        return fail(nullptr, TSIM_EINVAL, "bad arguments (single-instance handles only)");
+    Build& B = h->B;
+    DevNet& D = h->D;
+    const int N = D.N, R = D.R;
+    if ((reinterpret_cast<uintptr_t>(device_buffer) & 255u) != 0 || buffer_bytes < aoi_bytes(N, n_aoi))
+        return fail(&h->err, TSIM_EINVAL, "AOI buffer too small or not 256-byte aligned");
+    const int n_conn = n_aoi > 0 ? conn_begin[n_aoi] : 0;
+    if (n_aoi > 0 && (conn_begin[0] != 0 || (n_conn > 0 && (!conn_road || !conn_s))))
+        return fail(&h->err, TSIM_EINVAL, "bad AOI connection table");
+    for (int a = 0; a < n_aoi; ++a)
+        if (conn_begin[a + 1] < conn_begin[a]) return fail(&h->err, TSIM_EINVAL, "bad AOI connection table");
+    for (int c = 0; c < n_conn; ++c) {
+        const int r = conn_road[c];
+        if (r < 0 || r >= R) return fail(&h->err, TSIM_EINVAL, "AOI connection on a road out of range");
+        if (!(conn_s[c] >= 0.0f && conn_s[c] <= B.lane_len[B.tile_lane_begin[r]]))
+            return fail(&h->err, TSIM_EINVAL, "AOI connection beyond its road");
+    }
+    // the AOI's first listed connection on a road, -1 when it has none
+    auto conn_on = [&](int a, int r) {
+        for (int c = conn_begin[a]; c < conn_begin[a + 1]; ++c)
+            if (conn_road[c] == r) return c;
+        return -1;
+    };
+    std::vector<int32_t> st(N);
+    if (N > 0) {
+        HIPCHK(h, hipMemcpyAsync(st.data(), D.status, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    std::vector<int32_t> org(N, -1), dst(N, -1);
+    std::vector<float> vstart = B.vstart, vend = B.vend;
+    for (int i = 0; i < N; ++i) {
+        const int o = origin_aoi ? origin_aoi[i] : -1, d = dest_aoi ? dest_aoi[i] : -1;
+        if (o < 0 && d < 0) continue;
+        if (o >= n_aoi || d >= n_aoi) return fail(&h->err, TSIM_EINVAL, "AOI id out of range");
+        if (st[i] != TSIM_WAITING)
+            return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + " has already departed");
+        const int first = B.route[B.rstart[i]], last = B.route[B.rstart[i] + B.rlen[i] - 1];
+        if (o >= 0) {
+            const int c = conn_on(o, first);
+            if (c < 0)
+                return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its origin AOI has no connection on its first road");
+            if (!(conn_s[c] < B.lane_len[B.tile_lane_begin[first]]))
+                return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its start connection is at the road's end");
+            vstart[i] = conn_s[c];
+            org[i] = o;
+        }
+        if (d >= 0) {
+            const int c = conn_on(d, last);
+            if (c < 0)
+                return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its destination AOI has no connection on its last road");
+            if (!(conn_s[c] > 0.0f))
+                return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its end connection is at the road's start");
+            vend[i] = conn_s[c];
+            dst[i] = d;
+        }
+    }
+    // every vehicle concerned is still waiting: its start and end positions
+    // are read when it departs
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    int32_t* base = (int32_t*)device_buffer;
+    int32_t* d_org = base;
+    int32_t* d_dst = (int32_t*)((char*)device_buffer + up((size_t)std::max(N, 1) * 4));
+    if (N > 0) {
+        HIPCHK(h, hipMemcpyAsync(d_org, org.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(d_dst, dst.data(), (size_t)N * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    B.vstart = vstart;
+    B.vend = vend;
+    HIPCHK(h, up_range(h, (float*)D.vstart, B.vstart, 0, N));
+    HIPCHK(h, up_range(h, (float*)D.vend, B.vend, 0, N));
+    // a one-road trip's departure record carries its end position (its
+    // next-road word): the queue records are written again from the tables
+    std::vector<QRec> qr(B.q_veh.size());
+    for (size_t k = 0; k < qr.size(); ++k) {
+        const int v = B.q_veh[k];
+        const int rb = B.rstart[v], rl = B.rlen[v];
+        qr[k].tau = B.tau[v];
+        qr[k].mask = B.q_mask[k];
+        qr[k].vid = v;
+        qr[k].len = B.vlen[v];
+        qr[k].f = B.vf[v];
+        qr[k].rp = rb;
+        qr[k].rem = rl - 1;
+        qr[k].nr = next_word(B, v, rb, rl - 1);
+    }
+    HIPCHK(h, up_range(h, (QRec*)D.q_rec, qr, 0, (long long)qr.size()));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->d_aoi = base;
+    h->n_aoi = n_aoi;
+    return TSIM_OK;
+}
+
+int tsim_get_aoi_counts(tsim_handle* h, int32_t* waiting, int32_t* arrived, int32_t n_aoi)
+{
+    if (!h || !h->d_aoi || n_aoi != h->n_aoi || (n_aoi > 0 && (!waiting || !arrived)))
+        return fail(h ? &h->err : nullptr, TSIM_EINVAL, "bad arguments (no AOIs set, or another AOI count)");
+    if (n_aoi == 0) return TSIM_OK;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const DevNet& D = h->D;
+    const size_t vb = up((size_t)std::max(D.N, 1) * 4);
+    const int32_t* d_org = h->d_aoi;
+    const int32_t* d_dst = (const int32_t*)((const char*)h->d_aoi + vb);
+    int32_t* cnt = (int32_t*)((char*)h->d_aoi + 2 * vb);
+    HIPCHK(h, hipMemsetAsync(cnt, 0, (size_t)2 * n_aoi * 4, h->stream));
+    HIPCHK(h, launch_aoi_counts(D, d_org, d_dst, n_aoi, cnt, h->stream));
+    HIPCHK(h, hipMemcpyAsync(waiting, cnt, (size_t)n_aoi * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(arrived, cnt + n_aoi, (size_t)n_aoi * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
 }
 

@@ -88,7 +88,8 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_set_lane_restriction", "tsim_set_vehicle_route",
            "tsim_batch_set_vehicle_route", "tsim_set_trajectory", "tsim_get_trajectory_count",
            "tsim_route_footprint", "tsim_shortest_routes", "tsim_reroute_footprint", "tsim_reroute_shortest",
-           "tsim_batch_reroute_footprint", "tsim_batch_reroute_shortest"]
+           "tsim_batch_reroute_footprint", "tsim_batch_reroute_shortest", "tsim_aoi_footprint", "tsim_set_aois",
+           "tsim_get_aoi_counts"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -119,6 +120,9 @@ def lib():
         L.tsim_set_vehicle_route.argtypes = [P, C.c_int32, P, C.c_int32, C.c_float]
         L.tsim_set_trajectory.argtypes = [P, P, C.c_int64, C.c_int32]
         L.tsim_get_trajectory_count.argtypes = [P, P]
+        L.tsim_aoi_footprint.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+        L.tsim_set_aois.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_size_t]
+        L.tsim_get_aoi_counts.argtypes = [P, P, P, C.c_int32]
         L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32, C.c_float]
         SZ = C.POINTER(C.c_size_t)
         L.tsim_route_footprint.argtypes = [P, C.c_int32, SZ, SZ]
@@ -366,6 +370,38 @@ class Sim:
                                                            ("x", "<f4"), ("v", "<f4")]))
         rec = np.sort(rec, order=["step", "vehicle"])
         return {f: rec[f].copy() for f in rec.dtype.names}, int(n[0]) - k
+
+    def set_aois(self, conn_begin, conn_road, conn_s, origin_aoi=None, dest_aoi=None):
+        """Areas of interest: AOI a's connections are conn_road / conn_s
+        [conn_begin[a]:conn_begin[a+1]]; each waiting vehicle named in
+        origin_aoi / dest_aoi (-1: none) starts / ends at its AOI's
+        connection on the first / last road of its route."""
+        import torch
+        cb = np.ascontiguousarray(conn_begin, np.int32)
+        n_aoi = int(cb.size) - 1
+        cr = np.ascontiguousarray(conn_road, np.int32)
+        cs = np.ascontiguousarray(conn_s, np.float32)
+        o = None if origin_aoi is None else np.ascontiguousarray(origin_aoi, np.int32)
+        d = None if dest_aoi is None else np.ascontiguousarray(dest_aoi, np.int32)
+        for a in (o, d):
+            if a is not None and a.size != self.N:
+                raise ValueError("one AOI id per vehicle")
+        nb = C.c_size_t()
+        _check(lib().tsim_aoi_footprint(self.h, n_aoi, C.byref(nb)), self.h)
+        # written in full by the library on its stream (no fill here, which
+        # would run on torch's stream)
+        buf = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        _check(lib().tsim_set_aois(self.h, n_aoi, _p(cb), _p(cr), _p(cs), _p(o) if o is not None else None,
+                                   _p(d) if d is not None else None, C.c_void_p(buf.data_ptr()), int(nb.value)),
+               self.h)
+        self.aoi_buf, self.n_aoi = buf, n_aoi
+
+    def aoi_counts(self):
+        """(waiting, arrived) per AOI at the current step boundary."""
+        w = np.zeros(self.n_aoi, np.int32)
+        a = np.zeros(self.n_aoi, np.int32)
+        _check(lib().tsim_get_aoi_counts(self.h, _p(w), _p(a), int(self.n_aoi)), self.h)
+        return w, a
 
     def set_vehicle_route(self, vid, roads, end_s=None):
         """Vehicle vid follows `roads` (beginning with the road it is on) from

@@ -1,0 +1,151 @@
+"""GPU areas of interest (Appendix B.1: an area joined to the road network by
+connections at positions along roads, where trips start and end; Appendix
+B.2: the AOI puts due vehicles into the lane at its connection and takes in
+those whose trips end there) through the C ABI, against the oracle: the
+pinned line scene step for step, a grid with twenty AOIs over 80 steps, the
+device counts against counts from the state, and refused calls that change
+nothing."""
+
+import numpy as np
+import pytest
+
+from paper_2406_10661_amd import workloads as W
+from tests.scenes import line_network, trips_for
+
+pytestmark = pytest.mark.gpu
+
+CB = [0, 2, 3, 4]
+CR = [2, 0, 0, 2]
+CS = [100.0, 50.0, 60.0, 120.0]
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as O
+    O.build()
+    return O
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    from paper_2406_10661_amd.tsim import Sim
+    return Sim
+
+
+def _counts_from_state(st, origin, dest, n_aoi):
+    w = np.bincount(origin[(st["status"] == 0) & (origin >= 0)], minlength=n_aoi)
+    a = np.bincount(dest[(st["status"] == 2) & (dest >= 0)], minlength=n_aoi)
+    return w, a
+
+
+def _same_states(a, b, what, tol=1e-5):
+    """Decisions exactly; positions and speeds within tol relative."""
+    for f in ("status", "lane", "route_pos", "finish_step"):
+        assert np.array_equal(a[f], b[f]), (what, f)
+    on = a["status"] == 1
+    dx = np.abs(a["x"][on] - b["x"][on]) / np.maximum(np.abs(a["x"][on]), 1.0)
+    dv = np.abs(a["v"][on] - b["v"][on]) / np.maximum(np.abs(a["v"][on]), 1.0)
+    assert dx.size == 0 or dx.max() < tol, (what, float(dx.max()))
+    assert dv.size == 0 or dv.max() < tol, (what, float(dv.max()))
+    return float(dx.max()) if dx.size else 0.0, float(dv.max()) if dv.size else 0.0
+
+
+def test_line_scene_matches_oracle_and_hand_values(O, Sim):
+    net = line_network(lanes=1, policy=W.POLICY_NONE)
+    trips = trips_for([[0], [0], [0, 2]], depart=[0.0, 10.0, 2.0])
+    params = W.Params()
+    o = O.OracleSim(net, trips, params)
+    g = Sim(net, trips, params)
+    org, dst = [0, 0, 0], [1, 1, 2]
+    o.set_aois(CB, CR, CS, org, dst)
+    g.set_aois(CB, CR, CS, org, dst)
+    for k in range(16):
+        wg, ag = g.aoi_counts()
+        wo, ao = o.aoi_counts()
+        assert wg.tolist() == wo.tolist() and ag.tolist() == ao.tolist(), k
+        if k == 1:
+            s = g.get_state()
+            assert s["x"][0] == 51.0 and s["v"][0] == 2.0
+        _same_states(o.get_state(), g.get_state(), k)
+        o.step(1)
+        g.step(1)
+    # vehicle 0 ended in step 3, vehicle 1 in step 13; vehicle 2 is on its way
+    # to AOI 2 on road 2
+    s = g.get_state()
+    assert s["finish_step"][:2].tolist() == [3, 13]
+    assert g.aoi_counts()[1].tolist() == [0, 2, 0]
+
+
+def _grid_case(seed=11, n_aoi=20, n_trips=600):
+    rng = np.random.default_rng(seed)
+    net = W.grid_network(3, spacing=300.0, length=300.0, lanes=2)
+    R = net.n_roads
+    roads = np.stack([rng.choice(R, 3, replace=False) for _ in range(n_aoi)])
+    cb = np.arange(0, 3 * n_aoi + 1, 3, dtype=np.int32)
+    cr = roads.reshape(-1).astype(np.int32)
+    cs = rng.uniform(10.0, 290.0, 3 * n_aoi).astype(np.float32)
+    oa = rng.integers(0, n_aoi, n_trips)
+    da = rng.integers(0, n_aoi, n_trips)
+    o_road = roads[oa, rng.integers(0, 3, n_trips)]
+    d_road = roads[da, rng.integers(0, 3, n_trips)]
+    keep = o_road != d_road
+    oa, da, o_road, d_road = oa[keep], da[keep], o_road[keep], d_road[keep]
+    trips = W._finish_trips(net, rng, o_road.astype(np.int32), d_road.astype(np.int32),
+                            rng.uniform(0.0, 60.0, o_road.size))
+    return net, trips, cb, cr, cs, oa.astype(np.int32), da.astype(np.int32)
+
+
+def test_grid_with_twenty_aois_matches_oracle(O, Sim):
+    """Ten steps element by element (departures at the AOIs' connections,
+    decisions exact, positions and speeds within 2e-4: the one-step bar of
+    1e-5 compounds over the ten steps); then to step 80 the
+    device counts equal the counts of the device state exactly and the
+    oracle's within two vehicles per AOI (over tens of steps the FP32
+    trajectories drift from the FP64 oracle's, so single decisions may part)."""
+    net, trips, cb, cr, cs, oa, da = _grid_case()
+    params = W.Params(seed=3)
+    o = O.OracleSim(net, trips, params)
+    g = Sim(net, trips, params)
+    starts, ends = o.set_aois(cb, cr, cs, oa, da)
+    assert not np.isnan(starts).any() and not np.isnan(ends).any()
+    g.set_aois(cb, cr, cs, oa, da)
+    n_aoi = cb.size - 1
+    for k in range(8):
+        o.step(10)
+        g.step(10)
+        sg = g.get_state()
+        if k == 0:
+            _same_states(o.get_state(), sg, k, tol=2e-4)
+        wg, ag = g.aoi_counts()
+        w2, a2 = _counts_from_state(sg, oa, da, n_aoi)
+        assert wg.tolist() == w2.tolist() and ag.tolist() == a2.tolist(), k
+        wo, ao = o.aoi_counts()
+        assert np.abs(wg - wo).max() <= 2 and np.abs(ag - ao).max() <= 2, (k, wg, wo, ag, ao)
+    assert ag.sum() > 0
+    print("aoi grid:", trips.n_vehicles, "trips; waiting", int(wg.sum()), "oracle", int(wo.sum()),
+          "; arrived", int(ag.sum()), "oracle", int(ao.sum()), flush=True)
+
+
+def test_refused_calls_change_nothing(Sim):
+    from paper_2406_10661_amd.tsim import TSIM_EINVAL, TsimError
+    net = line_network(lanes=1, policy=W.POLICY_NONE)
+    trips = trips_for([[0], [0]], depart=[0.0, 5.0])
+    params = W.Params()
+    g = Sim(net, trips, params)
+    ref = Sim(net, trips, params)
+    with pytest.raises(TsimError) as e:
+        g.set_aois(CB, CR, CS, [2, -1], None)        # AOI 2 has no connection on road 0
+    assert e.value.code == TSIM_EINVAL
+    with pytest.raises(TsimError):
+        g.set_aois(CB, CR, CS, [0, 3], None)         # AOI id out of range
+    with pytest.raises(TsimError):
+        g.set_aois(CB, [2, 0, 0, 9], CS, None, None)   # road out of range
+    g.step(1)
+    ref.step(1)
+    with pytest.raises(TsimError):
+        g.set_aois(CB, CR, CS, [0, -1], None)        # vehicle 0 has departed
+    g.step(3)
+    ref.step(3)
+    a, b = g.get_state(), ref.get_state()
+    for f in ("status", "lane", "x", "v", "finish_step"):
+        assert np.array_equal(a[f], b[f]), f
