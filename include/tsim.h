@@ -379,7 +379,8 @@ int tsim_get_trajectory_count(tsim_handle *h, int64_t *n);
  * tsim_set_aois or tsim_destroy) holds the AOI ids on the device.  Errors
  * (TSIM_EINVAL: an AOI id, road or position out of range, an AOI without a
  * connection on the road a vehicle needs, a vehicle that has departed)
- * change nothing.  Synchronises the stream.  Single-instance handles.
+ * change nothing.  Synchronises the stream.  Single-instance handles (for
+ * batches, tsim_batch_set_aois).
  *
  * tsim_get_aoi_counts: at the current step boundary, waiting[a] = vehicles
  * whose trip starts in AOI a and that have not departed, arrived[a] =
@@ -521,6 +522,14 @@ int tsim_batch_get_state(tsim_batch *b, int32_t instance, tsim_state_host *out);
 int tsim_batch_set_state(tsim_batch *b, int32_t instance, const tsim_state_host *in);
 /* Per-instance forms of tsim_get_road_mean_speed, tsim_get_lane_waiting_counts
  * and tsim_get_lane_order (sizes and ids local to the instance). */
+/* As tsim_aoi_footprint, tsim_set_aois and tsim_get_aoi_counts, for one
+ * instance of a batch (its local road and vehicle ids; the instance's own
+ * buffer).  Removing the instance drops its AOIs. */
+int tsim_batch_aoi_footprint(tsim_batch *b, int32_t instance, int32_t n_aoi, size_t *bytes_out);
+int tsim_batch_set_aois(tsim_batch *b, int32_t instance, int32_t n_aoi, const int32_t *conn_begin,
+                        const int32_t *conn_road, const float *conn_s, const int32_t *origin_aoi,
+                        const int32_t *dest_aoi, void *device_buffer, size_t buffer_bytes);
+int tsim_batch_get_aoi_counts(tsim_batch *b, int32_t instance, int32_t *waiting, int32_t *arrived, int32_t n_aoi);
 int tsim_batch_get_road_mean_speed(tsim_batch *b, int32_t instance, float *out, int32_t n_roads);
 int tsim_batch_get_lane_waiting_counts(tsim_batch *b, int32_t instance, int32_t *out, int32_t n_lanes);
 int tsim_batch_get_lane_order(tsim_batch *b, int32_t instance, int32_t *offsets, int32_t *vehicle_ids,

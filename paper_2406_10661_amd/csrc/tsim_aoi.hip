@@ -7,24 +7,27 @@
 
 namespace tsim {
 
-// one thread per vehicle; counts[a] the waiting vehicles of origin AOI a,
-// counts[n_aoi + a] the finished ones of destination AOI a (counts cleared
-// by the caller; AOI ids < 0: none)
-__global__ void k_aoi_counts(const DevNet D, const int32_t* origin, const int32_t* dest, int n_aoi, int32_t* counts)
+// one thread per vehicle of the range [v0, v0 + nv) (an instance's);
+// counts[a] the waiting vehicles of origin AOI a, counts[n_aoi + a] the
+// finished ones of destination AOI a (counts cleared by the caller; AOI ids
+// indexed from v0, < 0: none)
+__global__ void k_aoi_counts(const DevNet D, int v0, int nv, const int32_t* origin, const int32_t* dest, int n_aoi,
+                             int32_t* counts)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= D.N) return;
-    const int st = D.status[v];
-    const int o = origin[v], d = dest[v];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const int st = D.status[v0 + i];
+    const int o = origin[i], d = dest[i];
     if (st == 0 && o >= 0) atomicAdd(&counts[o], 1);
     if (st == 2 && d >= 0) atomicAdd(&counts[n_aoi + d], 1);
 }
 
-hipError_t launch_aoi_counts(const DevNet& H, const int32_t* origin, const int32_t* dest, int n_aoi, int32_t* counts,
-                             hipStream_t s)
+hipError_t launch_aoi_counts(const DevNet& H, int v0, int nv, const int32_t* origin, const int32_t* dest, int n_aoi,
+                             int32_t* counts, hipStream_t s)
 {
-    if (H.N > 0)
-        hipLaunchKernelGGL(k_aoi_counts, dim3((H.N + 255) / 256), dim3(256), 0, s, H, origin, dest, n_aoi, counts);
+    if (nv > 0)
+        hipLaunchKernelGGL(k_aoi_counts, dim3((nv + 255) / 256), dim3(256), 0, s, H, v0, nv, origin, dest, n_aoi,
+                           counts);
     return hipGetLastError();
 }
 

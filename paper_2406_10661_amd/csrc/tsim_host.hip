@@ -33,8 +33,8 @@ hipError_t launch_set_lane_speed(const DevNet& H, const int32_t* ids, const floa
 hipError_t launch_record(const DevNet& H, const int32_t* lane_ext, TrajRec* out, long long cap,
                          unsigned long long* count, int every, hipStream_t s);
 hipError_t launch_set_end(const DevNet& H, int inst, long long end, hipStream_t s);
-hipError_t launch_aoi_counts(const DevNet& H, const int32_t* origin, const int32_t* dest, int n_aoi, int32_t* counts,
-                             hipStream_t s);
+hipError_t launch_aoi_counts(const DevNet& H, int v0, int nv, const int32_t* origin, const int32_t* dest, int n_aoi,
+                             int32_t* counts, hipStream_t s);
 hipError_t launch_apply_routes(const DevNet& H, const int32_t* n_rp, const int32_t* n_rem, const int32_t* n_nr,
                                const uint32_t* n_mask, int n_queue, hipStream_t s);
 int update_blocks_per_cu(int sched);
@@ -678,10 +678,14 @@ struct tsim_handle {
     int32_t* d_io_ph = nullptr;      // staging: phase updates (2 slots of 2 x NJ)
     int32_t* d_io_lane = nullptr;    // staging: lane updates (NL ids, then NL values)
     unsigned long long* d_traj_n = nullptr;   // trajectory records appended so far
-    // areas of interest (tsim_set_aois): per-vehicle origin and destination
-    // AOI ids, then the count slots, in the caller's buffer
-    int32_t* d_aoi = nullptr;
-    int n_aoi = 0;
+    // areas of interest (tsim_set_aois), per instance: the caller's buffer
+    // (per-vehicle origin and destination AOI ids, then the count slots) and
+    // the number of AOIs
+    struct AoiSet {
+        int32_t* d = nullptr;
+        int n = 0;
+    };
+    std::vector<AoiSet> aois;
     TrajRec* traj = nullptr;         // caller's trajectory buffer (device), traj_cap records
     long long traj_cap = 0;
     int traj_every = 0;              // 0: not recording
@@ -1669,23 +1673,31 @@ static size_t aoi_bytes(long long n_veh, long long n_aoi)
     return 2 * up((size_t)std::max<long long>(n_veh, 1) * 4) + up((size_t)std::max<long long>(2 * n_aoi, 1) * 4);
 }
 
-int tsim_aoi_footprint(tsim_handle* h, int32_t n_aoi, size_t* bytes_out)
+// instance k of a batch (k >= 0, not removed) or the single instance (k < 0)
+static bool instance_ok(const tsim_handle* h, int k)
 {
-    if (!h || n_aoi < 0 || !bytes_out || h->B.n_inst != 1)
-        return fail(nullptr, TSIM_EINVAL, "bad arguments (single-instance handles only)");
-    *bytes_out = aoi_bytes(h->D.N, n_aoi);
+    if (k < 0) return h->B.n_inst == 1;
+    return k < h->B.n_inst && !(k < (int)h->removed.size() && h->removed[k]);
+}
+
+static int aoi_footprint_impl(tsim_handle* h, int k, int32_t n_aoi, size_t* bytes_out)
+{
+    if (!h || n_aoi < 0 || !bytes_out || !instance_ok(h, k)) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const Ranges g = ranges_of(h->B, k);
+    *bytes_out = aoi_bytes(g.v1 - g.v0, n_aoi);
     return TSIM_OK;
 }
 
-int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, const int32_t* conn_road,
-                  const float* conn_s, const int32_t* origin_aoi, const int32_t* dest_aoi, void* device_buffer,
-                  size_t buffer_bytes)
+static int set_aois_impl(tsim_handle* h, int k, int32_t n_aoi, const int32_t* conn_begin, const int32_t* conn_road,
+                         const float* conn_s, const int32_t* origin_aoi, const int32_t* dest_aoi, void* device_buffer,
+                         size_t buffer_bytes)
 {
-    if (!h || n_aoi < 0 || (n_aoi > 0 && !conn_begin) || !device_buffer || h->B.n_inst != 1)
-        return fail(nullptr, TSIM_EINVAL, "bad arguments (single-instance handles only)");
+    if (!h || n_aoi < 0 || (n_aoi > 0 && !conn_begin) || !device_buffer || !instance_ok(h, k))
+        return fail(nullptr, TSIM_EINVAL, "bad arguments");
     Build& B = h->B;
     DevNet& D = h->D;
-    const int N = D.N, R = D.R;
+    const Ranges g = ranges_of(B, k);
+    const int N = g.v1 - g.v0, R = g.r1 - g.r0;
     if ((reinterpret_cast<uintptr_t>(device_buffer) & 255u) != 0 || buffer_bytes < aoi_bytes(N, n_aoi))
         return fail(&h->err, TSIM_EINVAL, "AOI buffer too small or not 256-byte aligned");
     const int n_conn = n_aoi > 0 ? conn_begin[n_aoi] : 0;
@@ -1696,18 +1708,18 @@ int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, cons
     for (int c = 0; c < n_conn; ++c) {
         const int r = conn_road[c];
         if (r < 0 || r >= R) return fail(&h->err, TSIM_EINVAL, "AOI connection on a road out of range");
-        if (!(conn_s[c] >= 0.0f && conn_s[c] <= B.lane_len[B.tile_lane_begin[r]]))
+        if (!(conn_s[c] >= 0.0f && conn_s[c] <= B.lane_len[B.tile_lane_begin[g.r0 + r]]))
             return fail(&h->err, TSIM_EINVAL, "AOI connection beyond its road");
     }
-    // the AOI's first listed connection on a road, -1 when it has none
+    // the AOI's first listed connection on (union) road r, -1 when it has none
     auto conn_on = [&](int a, int r) {
         for (int c = conn_begin[a]; c < conn_begin[a + 1]; ++c)
-            if (conn_road[c] == r) return c;
+            if (g.r0 + conn_road[c] == r) return c;
         return -1;
     };
     std::vector<int32_t> st(N);
     if (N > 0) {
-        HIPCHK(h, hipMemcpyAsync(st.data(), D.status, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(st.data(), D.status + g.v0, (size_t)N * 4, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
     }
     std::vector<int32_t> org(N, -1), dst(N, -1);
@@ -1718,14 +1730,15 @@ int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, cons
         if (o >= n_aoi || d >= n_aoi) return fail(&h->err, TSIM_EINVAL, "AOI id out of range");
         if (st[i] != TSIM_WAITING)
             return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + " has already departed");
-        const int first = B.route[B.rstart[i]], last = B.route[B.rstart[i] + B.rlen[i] - 1];
+        const int v = g.v0 + i;
+        const int first = B.route[B.rstart[v]], last = B.route[B.rstart[v] + B.rlen[v] - 1];
         if (o >= 0) {
             const int c = conn_on(o, first);
             if (c < 0)
                 return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its origin AOI has no connection on its first road");
             if (!(conn_s[c] < B.lane_len[B.tile_lane_begin[first]]))
                 return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its start connection is at the road's end");
-            vstart[i] = conn_s[c];
+            vstart[v] = conn_s[c];
             org[i] = o;
         }
         if (d >= 0) {
@@ -1734,7 +1747,7 @@ int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, cons
                 return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its destination AOI has no connection on its last road");
             if (!(conn_s[c] > 0.0f))
                 return fail(&h->err, TSIM_EINVAL, "vehicle " + std::to_string(i) + ": its end connection is at the road's start");
-            vend[i] = conn_s[c];
+            vend[v] = conn_s[c];
             dst[i] = d;
         }
     }
@@ -1750,47 +1763,92 @@ int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, cons
     }
     B.vstart = vstart;
     B.vend = vend;
-    HIPCHK(h, up_range(h, (float*)D.vstart, B.vstart, 0, N));
-    HIPCHK(h, up_range(h, (float*)D.vend, B.vend, 0, N));
+    HIPCHK(h, up_range(h, (float*)D.vstart, B.vstart, g.v0, g.v1));
+    HIPCHK(h, up_range(h, (float*)D.vend, B.vend, g.v0, g.v1));
     // a one-road trip's departure record carries its end position (its
-    // next-road word): the queue records are written again from the tables
+    // next-road word): the instance's queue records are written again from
+    // the tables
+    const int q0 = B.q_begin[g.r0], q1 = B.q_begin[g.r1];
     std::vector<QRec> qr(B.q_veh.size());
-    for (size_t k = 0; k < qr.size(); ++k) {
-        const int v = B.q_veh[k];
+    for (int q = q0; q < q1; ++q) {
+        const int v = B.q_veh[q];
         const int rb = B.rstart[v], rl = B.rlen[v];
-        qr[k].tau = B.tau[v];
-        qr[k].mask = B.q_mask[k];
-        qr[k].vid = v;
-        qr[k].len = B.vlen[v];
-        qr[k].f = B.vf[v];
-        qr[k].rp = rb;
-        qr[k].rem = rl - 1;
-        qr[k].nr = next_word(B, v, rb, rl - 1);
+        qr[q].tau = B.tau[v];
+        qr[q].mask = B.q_mask[q];
+        qr[q].vid = v;
+        qr[q].len = B.vlen[v];
+        qr[q].f = B.vf[v];
+        qr[q].rp = rb;
+        qr[q].rem = rl - 1;
+        qr[q].nr = next_word(B, v, rb, rl - 1);
     }
-    HIPCHK(h, up_range(h, (QRec*)D.q_rec, qr, 0, (long long)qr.size()));
+    HIPCHK(h, up_range(h, (QRec*)D.q_rec, qr, q0, q1));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    h->d_aoi = base;
-    h->n_aoi = n_aoi;
+    const size_t slot = k < 0 ? 0 : (size_t)k;
+    if (h->aois.size() <= slot) h->aois.resize(slot + 1);
+    h->aois[slot].d = base;
+    h->aois[slot].n = n_aoi;
     return TSIM_OK;
 }
 
-int tsim_get_aoi_counts(tsim_handle* h, int32_t* waiting, int32_t* arrived, int32_t n_aoi)
+static int get_aoi_counts_impl(tsim_handle* h, int k, int32_t* waiting, int32_t* arrived, int32_t n_aoi)
 {
-    if (!h || !h->d_aoi || n_aoi != h->n_aoi || (n_aoi > 0 && (!waiting || !arrived)))
-        return fail(h ? &h->err : nullptr, TSIM_EINVAL, "bad arguments (no AOIs set, or another AOI count)");
+    if (!h || !instance_ok(h, k)) return fail(nullptr, TSIM_EINVAL, "bad arguments");
+    const size_t slot = k < 0 ? 0 : (size_t)k;
+    if (slot >= h->aois.size() || !h->aois[slot].d || n_aoi != h->aois[slot].n || (n_aoi > 0 && (!waiting || !arrived)))
+        return fail(&h->err, TSIM_EINVAL, "no AOIs set for the instance, or another AOI count");
     if (n_aoi == 0) return TSIM_OK;
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const DevNet& D = h->D;
-    const size_t vb = up((size_t)std::max(D.N, 1) * 4);
-    const int32_t* d_org = h->d_aoi;
-    const int32_t* d_dst = (const int32_t*)((const char*)h->d_aoi + vb);
-    int32_t* cnt = (int32_t*)((char*)h->d_aoi + 2 * vb);
+    const Ranges g = ranges_of(h->B, k);
+    const int nv = g.v1 - g.v0;
+    int32_t* d = h->aois[slot].d;
+    const size_t vb = up((size_t)std::max(nv, 1) * 4);
+    const int32_t* d_org = d;
+    const int32_t* d_dst = (const int32_t*)((const char*)d + vb);
+    int32_t* cnt = (int32_t*)((char*)d + 2 * vb);
     HIPCHK(h, hipMemsetAsync(cnt, 0, (size_t)2 * n_aoi * 4, h->stream));
-    HIPCHK(h, launch_aoi_counts(D, d_org, d_dst, n_aoi, cnt, h->stream));
+    HIPCHK(h, launch_aoi_counts(D, g.v0, nv, d_org, d_dst, n_aoi, cnt, h->stream));
     HIPCHK(h, hipMemcpyAsync(waiting, cnt, (size_t)n_aoi * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(arrived, cnt + n_aoi, (size_t)n_aoi * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TSIM_OK;
+}
+
+int tsim_aoi_footprint(tsim_handle* h, int32_t n_aoi, size_t* bytes_out)
+{
+    return aoi_footprint_impl(h, -1, n_aoi, bytes_out);
+}
+
+int tsim_set_aois(tsim_handle* h, int32_t n_aoi, const int32_t* conn_begin, const int32_t* conn_road,
+                  const float* conn_s, const int32_t* origin_aoi, const int32_t* dest_aoi, void* device_buffer,
+                  size_t buffer_bytes)
+{
+    return set_aois_impl(h, -1, n_aoi, conn_begin, conn_road, conn_s, origin_aoi, dest_aoi, device_buffer,
+                         buffer_bytes);
+}
+
+int tsim_get_aoi_counts(tsim_handle* h, int32_t* waiting, int32_t* arrived, int32_t n_aoi)
+{
+    return get_aoi_counts_impl(h, -1, waiting, arrived, n_aoi);
+}
+
+int tsim_batch_aoi_footprint(tsim_batch* b, int32_t instance, int32_t n_aoi, size_t* bytes_out)
+{
+    return aoi_footprint_impl(b, instance < 0 ? INT32_MAX : instance, n_aoi, bytes_out);
+}
+
+int tsim_batch_set_aois(tsim_batch* b, int32_t instance, int32_t n_aoi, const int32_t* conn_begin,
+                        const int32_t* conn_road, const float* conn_s, const int32_t* origin_aoi,
+                        const int32_t* dest_aoi, void* device_buffer, size_t buffer_bytes)
+{
+    return set_aois_impl(b, instance < 0 ? INT32_MAX : instance, n_aoi, conn_begin, conn_road, conn_s, origin_aoi,
+                         dest_aoi, device_buffer, buffer_bytes);
+}
+
+int tsim_batch_get_aoi_counts(tsim_batch* b, int32_t instance, int32_t* waiting, int32_t* arrived, int32_t n_aoi)
+{
+    return get_aoi_counts_impl(b, instance < 0 ? INT32_MAX : instance, waiting, arrived, n_aoi);
 }
 
 int tsim_set_profiling(tsim_handle* h, int32_t enable)
@@ -3164,6 +3222,8 @@ int tsim_batch_remove(tsim_batch* b, int32_t instance)
     HIPCHK(b, launch_set_end(b->D, instance, (long long)m.step, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     b->removed[instance] = 1;
+    // its AOIs go with it (the caller's buffer is no longer referenced)
+    if ((size_t)instance < b->aois.size()) b->aois[instance] = tsim_handle::AoiSet{};
     // trailing removed instances give their space back
     bool popped = false;
     while (b->B.n_inst > 0 && b->removed.back()) {
@@ -3171,6 +3231,7 @@ int tsim_batch_remove(tsim_batch* b, int32_t instance)
         b->removed.pop_back();
         popped = true;
     }
+    if (b->aois.size() > (size_t)b->B.n_inst) b->aois.resize((size_t)b->B.n_inst);
     return popped ? batch_changed(b) : TSIM_OK;
 }
 

@@ -89,7 +89,7 @@ EXPORTS = ["tsim_footprint", "tsim_create", "tsim_step", "tsim_set_signal_phases
            "tsim_batch_set_vehicle_route", "tsim_set_trajectory", "tsim_get_trajectory_count",
            "tsim_route_footprint", "tsim_shortest_routes", "tsim_reroute_footprint", "tsim_reroute_shortest",
            "tsim_batch_reroute_footprint", "tsim_batch_reroute_shortest", "tsim_aoi_footprint", "tsim_set_aois",
-           "tsim_get_aoi_counts"]
+           "tsim_get_aoi_counts", "tsim_batch_aoi_footprint", "tsim_batch_set_aois", "tsim_batch_get_aoi_counts"]
 
 SCHEDULES = {0: "wide", 1: "16x32", 2: "16x64", 3: "32x64", 4: "8x16", 5: "16x32+pipelined wide", 6: "8x16+16x32+pipelined wide",
              7: "8x16+16x32+wide, fused launch"}
@@ -123,6 +123,9 @@ def lib():
         L.tsim_aoi_footprint.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
         L.tsim_set_aois.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_size_t]
         L.tsim_get_aoi_counts.argtypes = [P, P, P, C.c_int32]
+        L.tsim_batch_aoi_footprint.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+        L.tsim_batch_set_aois.argtypes = [P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_size_t]
+        L.tsim_batch_get_aoi_counts.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.tsim_batch_set_vehicle_route.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32, C.c_float]
         SZ = C.POINTER(C.c_size_t)
         L.tsim_route_footprint.argtypes = [P, C.c_int32, SZ, SZ]
@@ -814,6 +817,37 @@ class Batch:
         from its own step st['step']; the others are untouched)."""
         keep, s = _state_in(st, self.nets[instance])
         _check(lib().tsim_batch_set_state(self.h, int(instance), C.byref(s)), self.h)
+
+    def set_aois(self, instance, conn_begin, conn_road, conn_s, origin_aoi=None, dest_aoi=None):
+        """As Sim.set_aois, for one instance (its local road and vehicle ids)."""
+        import torch
+        cb = np.ascontiguousarray(conn_begin, np.int32)
+        n_aoi = int(cb.size) - 1
+        cr = np.ascontiguousarray(conn_road, np.int32)
+        cs = np.ascontiguousarray(conn_s, np.float32)
+        o = None if origin_aoi is None else np.ascontiguousarray(origin_aoi, np.int32)
+        d = None if dest_aoi is None else np.ascontiguousarray(dest_aoi, np.int32)
+        for a in (o, d):
+            if a is not None and a.size != self.trips[instance].n_vehicles:
+                raise ValueError("one AOI id per vehicle of the instance")
+        nb = C.c_size_t()
+        _check(lib().tsim_batch_aoi_footprint(self.h, int(instance), n_aoi, C.byref(nb)), self.h)
+        # written in full by the library on its stream
+        buf = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        _check(lib().tsim_batch_set_aois(self.h, int(instance), n_aoi, _p(cb), _p(cr), _p(cs),
+                                         _p(o) if o is not None else None, _p(d) if d is not None else None,
+                                         C.c_void_p(buf.data_ptr()), int(nb.value)), self.h)
+        if not hasattr(self, "aoi_bufs"):
+            self.aoi_bufs = {}
+        self.aoi_bufs[int(instance)] = (buf, n_aoi)
+
+    def aoi_counts(self, instance):
+        """(waiting, arrived) per AOI of one instance."""
+        n_aoi = self.aoi_bufs[int(instance)][1]
+        w = np.zeros(n_aoi, np.int32)
+        a = np.zeros(n_aoi, np.int32)
+        _check(lib().tsim_batch_get_aoi_counts(self.h, int(instance), _p(w), _p(a), n_aoi), self.h)
+        return w, a
 
     def road_mean_speed(self, instance):
         out = np.zeros(self.nets[instance].n_roads, np.float32)

@@ -149,3 +149,47 @@ def test_refused_calls_change_nothing(Sim):
     a, b = g.get_state(), ref.get_state()
     for f in ("status", "lane", "x", "v", "finish_step"):
         assert np.array_equal(a[f], b[f]), f
+
+
+def test_batch_instances_with_aois_match_alone(Sim):
+    """Three instances in one batch, AOIs on two of them (local road and
+    vehicle ids): every instance steps bit-identically to the same instance
+    alone with the same AOIs, with the same counts; a removed instance's AOIs
+    are gone."""
+    from paper_2406_10661_amd.tsim import Batch, TsimError
+    net_a, trips_a, cb, cr, cs, oa, da = _grid_case()
+    net_b = line_network(lanes=1, policy=W.POLICY_NONE)
+    trips_b = trips_for([[0], [0], [0, 2]], depart=[0.0, 10.0, 2.0])
+    net_c, trips_c, *_ = _grid_case(seed=12, n_trips=300)
+    nets, trips = [net_a, net_b, net_c], [trips_a, trips_b, trips_c]
+    params = [W.Params(seed=3), W.Params(), W.Params(seed=4)]
+    aois = {0: (cb, cr, cs, oa, da), 1: (CB, CR, CS, [0, 0, 0], [1, 1, 2])}
+    b = Batch(nets, trips, params)
+    alone = []
+    for k in range(3):
+        g = Sim(nets[k], trips[k], params[k])
+        if k in aois:
+            g.set_aois(*aois[k])
+            b.set_aois(k, *aois[k])
+        alone.append(g)
+    for rnd in range(4):
+        b.step(10)
+        for g in alone:
+            g.step(10)
+        for k in range(3):
+            sb, sa = b.get_state(k), alone[k].get_state()
+            for f in ("status", "lane", "route_pos", "x", "v", "finish_step"):
+                assert np.array_equal(sb[f], sa[f]), (rnd, k, f)
+            if k in aois:
+                wb, ab = b.aoi_counts(k)
+                wa, aa = alone[k].aoi_counts()
+                assert wb.tolist() == wa.tolist() and ab.tolist() == aa.tolist(), (rnd, k)
+    assert b.aoi_counts(1)[1][1] == 2
+    from paper_2406_10661_amd.tsim import lib
+    import ctypes as C
+    assert lib().tsim_batch_remove(b.h, 1) == 0
+    w = np.zeros(3, np.int32)
+    assert lib().tsim_batch_get_aoi_counts(b.h, 1, w.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p), 3) != 0
+    wb, ab = b.aoi_counts(0)
+    wa, aa = alone[0].aoi_counts()
+    assert wb.tolist() == wa.tolist() and ab.tolist() == aa.tolist()
